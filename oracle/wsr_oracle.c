@@ -1,0 +1,282 @@
+/*
+ * wsr_oracle.c -- CPU oracle for the proximal map of the weight-sharing penalty.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it; the GPU library
+ * never links, calls or includes anything from here, and this file includes
+ * nothing from the GPU library.
+ *
+ * What it computes (paper: "Weight-Sharing Regularization", AISTATS 2024):
+ *   R(w)        = 1/(d-1) * sum_{i>j} |w_i - w_j|                 (Sec. 1, eq. reg)
+ *   prox_{lR}(w) = argmin_u  l*R(u) + 1/2 ||u - w||^2             (Sec. 1; App. A.1)
+ * computed by the textbook sequential route the paper describes:
+ *   1. sort w ascending (x = sorted w), keeping the permutation     (Sec. 4 preamble;
+ *                                                                    Alg. prox, "sort")
+ *   2. give the particle of rank k (0-based) the velocity
+ *        v_k = l * (d-1-2k)/(d-1)  = -l * grad R at the sorted point (Sec. 2, eq. hyperplane;
+ *                                                                    Alg. prox, "v <- ...")
+ *   3. destinations y = x + v; pool adjacent violators: keep a stack of blocks and
+ *      merge the top two while avg_y(lower) >= avg_y(upper)           (Sec. 4.1: a collision
+ *      is detected when y_i >= y_{i+1}; merging is the sticky-particle collision,
+ *      Sec. 3 particle model and Alg. search_collisions PerformCollisions)
+ *   4. every rank in a block takes the block's y-average; scatter back to the
+ *      original order                                                  (Alg. prox, last
+ *                                                                    two steps)
+ * All arithmetic is FP64.  Block sums of x use Neumaier compensated summation;
+ * the block sum of v has the closed form  sum_{k=a}^{b} v_k = l*(b-a+1)*(d-1-a-b)/(d-1),
+ * so a block's y-average is  sum_x/n + l*(d-1-a-b)/(d-1).
+ *
+ * Readings of the paper taken here (each is listed with its justification in the
+ * design notes of the repository):
+ *   - rank-shift indexing: v runs from +l (rank 0) to -l (rank d-1) so that the
+ *     velocities sum to zero (conservation of momentum, Sec. 3 proposition);
+ *   - merge on ">=" (coarsest partition: equal neighbouring outputs form one cluster);
+ *   - sort ties broken by original index (any tie-break gives the same values);
+ *   - d <= 1 or l == 0: identity, every element its own cluster;
+ *   - a segment containing a non-finite weight yields NaN for the whole segment.
+ *
+ * Gradient: the prox is piecewise affine; on the piece selected by the partition
+ * its Jacobian averages within each cluster (symmetric, idempotent).  The
+ * vector-Jacobian product is therefore the per-cluster mean of the cotangent.
+ * (Not in the paper; follows from step 4 and the fact that the partition is
+ * locally constant.)
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    double v;
+    int64_t i;
+} keyed_t;
+
+static int cmp_keyed(const void* pa, const void* pb) {
+    const keyed_t* a = (const keyed_t*)pa;
+    const keyed_t* b = (const keyed_t*)pb;
+    if (a->v < b->v) return -1;
+    if (a->v > b->v) return 1;
+    if (a->i < b->i) return -1;
+    if (a->i > b->i) return 1;
+    return 0;
+}
+
+/* Neumaier compensated accumulation: (*s + *c) += x */
+static void nsum_add(double* s, double* c, double x) {
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x))
+        *c += (*s - t) + x;
+    else
+        *c += (x - t) + *s;
+    *s = t;
+}
+
+/* y-average of the block of ranks [a, a+n-1] whose x-sum is (s + c). */
+static double block_avg_y(double s, double c, int64_t a, int64_t n, int64_t d, double lam) {
+    int64_t b = a + n - 1;
+    return (s + c) / (double)n + lam * (double)(d - 1 - a - b) / (double)(d - 1);
+}
+
+/*
+ * Single segment, FP64 in and out.
+ *   w[d]      input weights (original order)
+ *   lam       prox scale (step size x penalty), must be >= 0 and finite
+ *   u[d]      output prox values (original order)
+ *   perm[d]   optional: perm[k] = original index of rank k
+ *   start[d]  optional: start[k] = 1 iff rank k begins a cluster
+ * Returns 0, or -1 on bad arguments / allocation failure.
+ */
+int wsr_oracle_prox_f64(int64_t d, const double* w, double lam, double* u, int64_t* perm,
+                        uint8_t* start) {
+    if (d < 0 || !(lam >= 0.0) || isinf(lam)) return -1;
+    if (d == 0) return 0;
+    int finite = 1;
+    for (int64_t i = 0; i < d; ++i)
+        if (!isfinite(w[i])) finite = 0;
+    if (!finite) {
+        for (int64_t i = 0; i < d; ++i) {
+            u[i] = NAN;
+            if (perm) perm[i] = i;
+            if (start) start[i] = 1;
+        }
+        return 0;
+    }
+    if (d == 1 || lam == 0.0) {
+        for (int64_t i = 0; i < d; ++i) {
+            u[i] = w[i];
+            if (perm) perm[i] = i;
+            if (start) start[i] = 1;
+        }
+        return 0;
+    }
+
+    keyed_t* xs = (keyed_t*)malloc(sizeof(keyed_t) * (size_t)d);
+    int64_t* bstart = (int64_t*)malloc(sizeof(int64_t) * (size_t)d);
+    int64_t* blen = (int64_t*)malloc(sizeof(int64_t) * (size_t)d);
+    double* bs = (double*)malloc(sizeof(double) * (size_t)d);
+    double* bc = (double*)malloc(sizeof(double) * (size_t)d);
+    if (!xs || !bstart || !blen || !bs || !bc) {
+        free(xs); free(bstart); free(blen); free(bs); free(bc);
+        return -1;
+    }
+    for (int64_t i = 0; i < d; ++i) {
+        xs[i].v = w[i];
+        xs[i].i = i;
+    }
+    /* step 1: sort by (value, original index) */
+    qsort(xs, (size_t)d, sizeof(keyed_t), cmp_keyed);
+
+    /* step 3: stack pool-adjacent-violators on y = x + v */
+    int64_t top = -1;
+    for (int64_t k = 0; k < d; ++k) {
+        ++top;
+        bstart[top] = k;
+        blen[top] = 1;
+        bs[top] = xs[k].v;
+        bc[top] = 0.0;
+        while (top >= 1) {
+            double lo = block_avg_y(bs[top - 1], bc[top - 1], bstart[top - 1], blen[top - 1], d, lam);
+            double hi = block_avg_y(bs[top], bc[top], bstart[top], blen[top], d, lam);
+            if (lo < hi) break;
+            /* collision: the upper block sticks to the lower one */
+            nsum_add(&bs[top - 1], &bc[top - 1], bs[top]);
+            bc[top - 1] += bc[top];
+            blen[top - 1] += blen[top];
+            --top;
+        }
+    }
+
+    /* step 4: every rank takes its block's y-average; scatter back */
+    for (int64_t b = 0; b <= top; ++b) {
+        double val = block_avg_y(bs[b], bc[b], bstart[b], blen[b], d, lam);
+        for (int64_t k = bstart[b]; k < bstart[b] + blen[b]; ++k) {
+            u[xs[k].i] = val;
+            if (perm) perm[k] = xs[k].i;
+            if (start) start[k] = (uint8_t)(k == bstart[b]);
+        }
+    }
+    free(xs); free(bstart); free(blen); free(bs); free(bc);
+    return 0;
+}
+
+/* ---------------- flat buffer of FP32 segments (what the GPU library consumes) ---------------- */
+
+typedef struct {
+    int64_t seg_lo, seg_hi; /* segment range handled by this worker */
+    const int64_t* offsets;
+    const float* w;
+    const float* lam;
+    int per_seg_lam;
+    double* u;
+    int32_t* perm_local;
+    uint8_t* start;
+    int rc;
+} seg_job_t;
+
+static void* seg_worker(void* arg) {
+    seg_job_t* job = (seg_job_t*)arg;
+    job->rc = 0;
+    for (int64_t s = job->seg_lo; s < job->seg_hi; ++s) {
+        int64_t o = job->offsets[s];
+        int64_t d = job->offsets[s + 1] - o;
+        double lam = (double)(job->per_seg_lam ? job->lam[s] : job->lam[0]);
+        double* w64 = (double*)malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
+        int64_t* p64 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(d > 0 ? d : 1));
+        if (!w64 || !p64) {
+            free(w64); free(p64);
+            job->rc = -1;
+            return NULL;
+        }
+        for (int64_t i = 0; i < d; ++i) w64[i] = (double)job->w[o + i]; /* exact promotion */
+        int rc = wsr_oracle_prox_f64(d, w64, lam, job->u + o, p64, job->start ? job->start + o : NULL);
+        if (rc) job->rc = rc;
+        if (job->perm_local)
+            for (int64_t k = 0; k < d; ++k) job->perm_local[o + k] = (int32_t)p64[k];
+        free(w64);
+        free(p64);
+    }
+    return NULL;
+}
+
+/*
+ * Flat FP32 buffer split into segments offsets[0..n_seg] (offsets[0] = 0, non-decreasing).
+ * Segment s gets prox_{lam_s R_{d_s}} with R normalised by its own 1/(d_s - 1).
+ *   lam: one value (per_seg_lam = 0) or n_seg values (per_seg_lam = 1), promoted exactly to FP64
+ *   u: FP64 output, original order;  perm_local: rank -> segment-local original index
+ *   start: 1 at ranks that begin a cluster.  perm_local and start may be NULL.
+ *   n_threads: segments are split across this many POSIX threads (>= 1).
+ */
+int wsr_oracle_prox_segments_f32(int64_t n_seg, const int64_t* offsets, const float* w,
+                                 const float* lam, int per_seg_lam, double* u,
+                                 int32_t* perm_local, uint8_t* start, int n_threads) {
+    if (n_seg < 0 || !offsets || offsets[0] != 0) return -1;
+    for (int64_t s = 0; s < n_seg; ++s) {
+        if (offsets[s + 1] < offsets[s]) return -1;
+        float l = per_seg_lam ? lam[s] : lam[0];
+        if (!(l >= 0.0f) || isinf(l)) return -1;
+    }
+    if (n_threads < 1) n_threads = 1;
+    if ((int64_t)n_threads > n_seg) n_threads = (int)(n_seg > 0 ? n_seg : 1);
+    seg_job_t* jobs = (seg_job_t*)calloc((size_t)n_threads, sizeof(seg_job_t));
+    pthread_t* th = (pthread_t*)calloc((size_t)n_threads, sizeof(pthread_t));
+    if (!jobs || !th) {
+        free(jobs); free(th);
+        return -1;
+    }
+    /* balance by element count, not segment count */
+    int64_t total = offsets[n_seg];
+    int64_t s = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        int64_t target = total * (t + 1) / n_threads;
+        jobs[t].seg_lo = s;
+        while (s < n_seg && (offsets[s] < target || t == n_threads - 1)) ++s;
+        jobs[t].seg_hi = s;
+        jobs[t].offsets = offsets;
+        jobs[t].w = w;
+        jobs[t].lam = lam;
+        jobs[t].per_seg_lam = per_seg_lam;
+        jobs[t].u = u;
+        jobs[t].perm_local = perm_local;
+        jobs[t].start = start;
+    }
+    int rc = 0;
+    if (n_threads == 1) {
+        seg_worker(&jobs[0]);
+        rc = jobs[0].rc;
+    } else {
+        for (int t = 0; t < n_threads; ++t) pthread_create(&th[t], NULL, seg_worker, &jobs[t]);
+        for (int t = 0; t < n_threads; ++t) {
+            pthread_join(th[t], NULL);
+            if (jobs[t].rc) rc = jobs[t].rc;
+        }
+    }
+    free(jobs);
+    free(th);
+    return rc;
+}
+
+/*
+ * Vector-Jacobian product of the prox at the point whose partition is (perm_local, start):
+ * out[i] = mean of g over the cluster containing i.  FP64, per segment, sums in rank order.
+ */
+int wsr_oracle_vjp(int64_t n_seg, const int64_t* offsets, const int32_t* perm_local,
+                   const uint8_t* start, const double* g, double* out) {
+    if (n_seg < 0 || !offsets || offsets[0] != 0) return -1;
+    for (int64_t s = 0; s < n_seg; ++s) {
+        int64_t o = offsets[s];
+        int64_t d = offsets[s + 1] - o;
+        int64_t k = 0;
+        while (k < d) {
+            int64_t e = k + 1;
+            while (e < d && !start[o + e]) ++e;
+            double acc = 0.0, comp = 0.0;
+            for (int64_t j = k; j < e; ++j) nsum_add(&acc, &comp, g[o + perm_local[o + j]]);
+            double mean = (acc + comp) / (double)(e - k);
+            for (int64_t j = k; j < e; ++j) out[o + perm_local[o + j]] = mean;
+            k = e;
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,395 @@
+"""Pins for the CPU oracle (runs without a GPU).
+
+Each test checks the oracle against something fixed outside it: values printed in the
+paper (tests/golden), brute-force minimisation of the prox objective, independent
+characterisations (convex-minorant slopes, end collisions, the neighbour-collision
+criterion, the optimality certificate), closed forms, and invariants of the flow.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import pins
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _read_golden(name):
+    rows = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            rows[key] = np.array([float(v) for v in vals])
+    return rows
+
+
+# ----------------------------------------------------------------------------- golden values
+
+def test_golden_counterexample_isotonic_link():
+    """App. C counterexample: the paper's correct answer is the isotonic regression of y,
+    and prox_R of the recast input equals it (isotonic link, Sec. 3)."""
+    g = _read_golden("kearsley_counterexample.txt")
+    y, x_star, x_wrong = g["y"], g["x_star"], g["x_wrong"]
+    slopes, _ = pins.gcm_slopes(y)
+    np.testing.assert_allclose(slopes, x_star, atol=1e-15)
+    ends, _ = pins.naive_end_collisions(y)
+    np.testing.assert_allclose(ends, x_star, atol=1e-15)
+    # recast as a prox input: d = 4, lam = 0.3 gives v = [0.3, 0.1, -0.1, -0.3]; w = y - v
+    lam = 0.3
+    v = pins.shift(4, lam)
+    np.testing.assert_allclose(v, [0.3, 0.1, -0.1, -0.3], atol=1e-16)
+    w = y - v
+    assert np.all(np.diff(w) > 0)
+    u, perm, start = oracle.prox_f64(w, lam)
+    np.testing.assert_allclose(u, x_star, atol=1e-14)
+    assert np.max(np.abs(u - x_wrong)) > 1e-2
+    assert list(start) == [1, 1, 0, 1]
+    # any input order gives the same multiset of outputs, attached to the same weights
+    rng = np.random.default_rng(0)
+    p = rng.permutation(4)
+    u2, _, _ = oracle.prox_f64(w[p], lam)
+    np.testing.assert_allclose(u2, x_star[p], atol=1e-14)
+
+
+def test_golden_d3_hyperplanes():
+    """Sec. 2 example: the six printed (signs, hyperplane) pairs are consistent, are exactly the
+    hyperplanes of eq. hyperplane, and R is their pointwise maximum."""
+    rows = []
+    with open(os.path.join(GOLDEN, "d3_hyperplanes.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                _, signs, coef = [s.strip() for s in line.split(";")]
+                rows.append((np.array([1.0 if s == "+" else -1.0 for s in signs.split()]),
+                             np.array([float(c) for c in coef.split()])))
+    assert len(rows) == 6
+    terms = np.array([[1, -1, 0], [0, 1, -1], [1, 0, -1]], dtype=float)  # w1-w2, w2-w3, w1-w3
+    for signs, coef in rows:
+        np.testing.assert_allclose(0.5 * signs @ terms, coef)
+    import itertools
+    from_eq = {tuple(pins.hyperplane_coeffs(p)) for p in itertools.permutations(range(3))}
+    assert {tuple(c) for _, c in rows} == from_eq
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        w = rng.normal(size=3)
+        assert abs(max(c @ w for _, c in rows) - pins.R_pairwise(w)) < 1e-12
+
+
+@pytest.mark.parametrize("d", [2, 3, 4, 5])
+def test_R_pairwise_equals_max_hyperplane(d):
+    rng = np.random.default_rng(d)
+    for _ in range(20):
+        w = rng.normal(size=d)
+        if rng.random() < 0.3:
+            w[rng.integers(d)] = w[0]
+        assert abs(pins.R_hyperplanes(w) - pins.R_pairwise(w)) < 1e-12
+
+
+# ----------------------------------------------------------------------------- brute force
+
+def _random_case(rng, d):
+    kind = rng.integers(4)
+    if kind == 0:
+        w = rng.normal(size=d)
+    elif kind == 1:
+        w = rng.integers(-2, 3, size=d).astype(float)  # many ties
+    elif kind == 2:
+        w = rng.laplace(size=d)
+    else:
+        w = np.sort(rng.normal(size=d)) * rng.choice([0.01, 1.0, 100.0])
+    lam = float(rng.choice([0.0, 1e-3, 0.05, 0.3, 1.0, 5.0])) * float(np.abs(w).max() + 1.0)
+    return w, lam
+
+
+def test_brute_force_small_d():
+    rng = np.random.default_rng(2)
+    n = 0
+    for d in [1, 2, 3, 4, 5, 6]:
+        for _ in range(25 if d < 6 else 12):
+            w, lam = _random_case(rng, d)
+            u, _, _ = oracle.prox_f64(w, lam)
+            ub = pins.brute_force_prox(w, lam)
+            np.testing.assert_allclose(u, ub, atol=1e-9 * (1 + np.abs(w).max()), err_msg=f"{w} {lam}")
+            n += 1
+    assert n > 100
+
+
+def test_brute_force_d7():
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        w, lam = _random_case(rng, 7)
+        u, _, _ = oracle.prox_f64(w, lam)
+        np.testing.assert_allclose(u, pins.brute_force_prox(w, lam), atol=1e-9 * (1 + np.abs(w).max()))
+
+
+# ----------------------------------------------------------------------------- other algorithms
+
+def test_gcm_and_end_collisions_agree():
+    """Sorted oracle output = slopes of the convex minorant of y's cumulative sums = end
+    collisions; cluster starts agree (coarsest partition)."""
+    rng = np.random.default_rng(4)
+    for trial in range(30):
+        d = int(rng.integers(2, 400))
+        w, lam = _random_case(rng, d)
+        if lam == 0:
+            lam = 0.1
+        u, perm, start = oracle.prox_f64(w, lam)
+        x = w[perm]
+        y = x + pins.shift(d, lam)
+        gcm, hull = pins.gcm_slopes(y)
+        eca, eca_starts = pins.naive_end_collisions(y)
+        tol = 1e-10 * (1 + np.abs(w).max())
+        np.testing.assert_allclose(u[perm], gcm, atol=tol)
+        np.testing.assert_allclose(u[perm], eca, atol=tol)
+
+
+def test_exact_arithmetic_partitions_identical():
+    """With dyadic inputs and lam/(d-1) dyadic every sum is exact in FP64, so the three
+    independent routes must give the identical (coarsest) partition, ties included."""
+    rng = np.random.default_rng(5)
+    for trial in range(60):
+        d = int(rng.integers(2, 200))
+        w = rng.integers(-8, 9, size=d).astype(float) * 0.25
+        lam = (d - 1) * 0.125 * float(rng.integers(0, 5))
+        if lam == 0:
+            continue
+        u, perm, start = oracle.prox_f64(w, lam)
+        y = w[perm] + pins.shift(d, lam)
+        _, hull = pins.gcm_slopes(y)
+        _, eca_starts = pins.naive_end_collisions(y)
+        assert list(np.nonzero(start)[0]) == hull[:-1]
+        assert list(np.nonzero(start)[0]) == eca_starts
+
+
+def test_neighbour_collision_criterion():
+    rng = np.random.default_rng(6)
+    for trial in range(20):
+        d = int(rng.integers(2, 120))
+        w, lam = _random_case(rng, d)
+        if lam == 0:
+            lam = 0.2
+        u, perm, start = oracle.prox_f64(w, lam)
+        y = w[perm] + pins.shift(d, lam)
+        # only check boundaries whose decision is not a near-tie
+        for i in range(d - 1):
+            left = np.cumsum(y[:i + 1][::-1]) / np.arange(1, i + 2)
+            right = np.cumsum(y[i + 1:]) / np.arange(1, d - i)
+            if abs(left.max() - right.min()) < 1e-9 * (1 + np.abs(w).max()):
+                continue
+            assert bool(start[i + 1]) == (not pins.neighbour_collides(y, i))
+
+
+@pytest.mark.parametrize("dist", ["normal", "laplace", "ties", "sorted_quadratic", "offset"])
+def test_kkt_certificate(dist):
+    rng = np.random.default_rng(7)
+    d = 20000
+    if dist == "normal":
+        w, lam = rng.normal(size=d), 0.1
+    elif dist == "laplace":
+        w, lam = rng.laplace(size=d), 5.0
+    elif dist == "ties":
+        w, lam = rng.integers(-50, 50, size=d).astype(float), 0.5
+    elif dist == "sorted_quadratic":
+        w, lam = (np.arange(d) / (d - 1.0)) ** 2, 0.4
+    else:
+        w, lam = 1e3 + 1e-2 * rng.normal(size=d), 1e-4
+    u, _, _ = oracle.prox_f64(w, lam)
+    ok, msg = pins.kkt_certificate(w, u, lam, tol=1e-9 * (1 + np.abs(w).max()))
+    assert ok, msg
+
+
+# ----------------------------------------------------------------------------- closed forms
+
+def test_closed_form_d2():
+    rng = np.random.default_rng(8)
+    for _ in range(200):
+        a, b = rng.normal(size=2)
+        lam = abs(rng.normal())
+        u, _, _ = oracle.prox_f64(np.array([a, b]), lam)
+        lo, hi = min(a, b), max(a, b)
+        if hi - lo <= 2 * lam:
+            exp = np.array([(a + b) / 2] * 2)
+        else:
+            exp = np.array([a + lam, b - lam]) if a < b else np.array([a - lam, b + lam])
+        np.testing.assert_allclose(u, exp, atol=1e-14)
+
+
+def test_closed_form_no_collision():
+    rng = np.random.default_rng(9)
+    d = 1000
+    x = np.cumsum(rng.uniform(1.0, 2.0, size=d))
+    lam = 0.49 * (d - 1) * 1.0 / 2  # all gaps >= 1 > 2 lam/(d-1)
+    p = rng.permutation(d)
+    w = x[p]
+    u, _, start = oracle.prox_f64(w, lam)
+    np.testing.assert_allclose(u, w + pins.shift(d, lam)[np.argsort(np.argsort(w))], atol=1e-12)
+    assert start.all()
+
+
+def test_closed_form_large_lambda_one_cluster():
+    rng = np.random.default_rng(10)
+    d = 777
+    w = rng.normal(size=d)
+    maxgap = np.diff(np.sort(w)).max()
+    lam = (d - 1) * maxgap / 2 * 1.0001
+    u, _, start = oracle.prox_f64(w, lam)
+    np.testing.assert_allclose(u, w.mean(), atol=1e-13)
+    assert start.sum() == 1
+
+
+@pytest.mark.parametrize("d", [101, 1001, 4001])
+def test_ica_worst_case_all_collide(d):
+    """Sec. 4.1 worst case: y = [1, 1-2/(d-1), ..., 0, e, 2e, ..., floor(d/2) e] -- the paper states
+    all particles eventually collide.  Recast as a prox input with lam = 1 (d odd)."""
+    eps = 1.0 / (4 * d)
+    half = (d + 1) // 2
+    j = np.arange(1, d // 2 + 1)
+    w = np.concatenate([np.zeros(half), j * (eps + 2.0 / (d - 1))])
+    y = np.sort(w) + pins.shift(d, 1.0)
+    np.testing.assert_allclose(y[:half], 1 - 2 * np.arange(half) / (d - 1), atol=1e-12)
+    np.testing.assert_allclose(y[half:], j * eps, atol=1e-12)
+    u, _, start = oracle.prox_f64(w, 1.0)
+    assert start.sum() == 1
+    np.testing.assert_allclose(u, w.mean(), atol=1e-14)
+
+
+def test_worst_case_chain_one_cluster():
+    """Sorted w_k = (k/(d-1))^2: all particles end in one cluster iff
+    lam >= (4d-5)/(6(d-1)) (prefix averages of y decrease to the end)."""
+    d = 4096
+    w = (np.arange(d) / (d - 1.0)) ** 2
+    lam_min = (4 * d - 5) / (6.0 * (d - 1))
+    u, _, start = oracle.prox_f64(w, lam_min * 1.05)
+    assert start.sum() == 1
+    np.testing.assert_allclose(u, w.mean(), atol=1e-14)
+    u, _, start = oracle.prox_f64(w, lam_min * 0.95)
+    assert start.sum() > 1
+
+
+def test_tie_groups_closed_form():
+    """Weights on a coarse grid with lam far below the grid spacing: the clusters are exactly
+    the tie groups and u = value + lam (d-1-a-b)/(d-1) for the group's rank range [a, b]."""
+    rng = np.random.default_rng(11)
+    d = 50000
+    w = np.round(rng.normal(size=d) * 20) / 16.0
+    lam = 1e-4
+    u, perm, start = oracle.prox_f64(w, lam)
+    x = w[perm]
+    assert np.array_equal(np.nonzero(start)[0], np.nonzero(np.concatenate([[True], np.diff(x) != 0]))[0])
+    starts = np.nonzero(start)[0]
+    ends = np.concatenate([starts[1:], [d]]) - 1
+    for a, b in zip(starts[:50], ends[:50]):
+        np.testing.assert_allclose(u[perm[a:b + 1]], x[a] + lam * (d - 1 - a - b) / (d - 1), atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- invariants
+
+def test_invariants():
+    rng = np.random.default_rng(12)
+    for _ in range(40):
+        d = int(rng.integers(2, 3000))
+        w, lam = _random_case(rng, d)
+        u, perm, start = oracle.prox_f64(w, lam)
+        s = 1 + np.abs(w).max()
+        assert abs(u.sum() - w.sum()) < 1e-9 * s * d ** 0.5  # momentum (Sec. 3)
+        assert np.all(np.diff(u[np.argsort(w, kind='stable')]) >= 0)  # order preserved (Sec. 4.2 fact 1)
+        assert np.all(np.abs(u - w) <= lam * (1 + 1e-12) + 1e-12 * s)
+        assert u.min() >= w.min() - 1e-12 * s and u.max() <= w.max() + 1e-12 * s
+        # weight sharing preserved: equal weights stay equal (Sec. 3 lemma)
+        for v in np.unique(w)[:5]:
+            assert np.ptp(u[w == v]) == 0
+        p = rng.permutation(d)
+        up, _, _ = oracle.prox_f64(w[p], lam)
+        np.testing.assert_allclose(up, u[p], atol=1e-12 * s)
+        c = float(rng.normal())
+        np.testing.assert_allclose(oracle.prox_f64(w + c, lam)[0], u + c, atol=1e-9 * (s + abs(c)))
+        np.testing.assert_allclose(oracle.prox_f64(-w, lam)[0], -u, atol=1e-12 * s)
+        sc = float(rng.uniform(0.1, 10))
+        np.testing.assert_allclose(oracle.prox_f64(sc * w, lam)[0], sc * oracle.prox_f64(w, lam / sc)[0],
+                                   atol=1e-9 * s * sc)
+
+
+def test_semigroup():
+    """prox_{(a+b)R} = prox_{bR} o prox_{aR}: the prox is the time-1 flow of an autonomous ODE
+    (Sec. 3, eq. prox_ode and theorem prox_R), so flows compose."""
+    rng = np.random.default_rng(13)
+    for _ in range(30):
+        d = int(rng.integers(2, 2000))
+        w, lam = _random_case(rng, d)
+        a = lam * float(rng.uniform(0, 1))
+        b = lam - a
+        u = oracle.prox_f64(w, lam)[0]
+        u2 = oracle.prox_f64(oracle.prox_f64(w, a)[0], b)[0]
+        np.testing.assert_allclose(u2, u, atol=1e-9 * (1 + np.abs(w).max()))
+
+
+# ----------------------------------------------------------------------------- gradient
+
+def test_vjp_structure_and_finite_differences():
+    rng = np.random.default_rng(14)
+    d = 2000
+    for trial in range(6):
+        w = rng.laplace(size=d)
+        lam = [0.05, 5.0][trial % 2]
+        u, perm, start = oracle.prox_f64(w, lam)
+        pl = perm.astype(np.int32)
+        g = rng.normal(size=d)
+        jg = oracle.vjp(g, pl, start)
+        np.testing.assert_allclose(oracle.vjp(jg, pl, start), jg, atol=1e-12)  # J^2 = J
+        np.testing.assert_allclose(oracle.vjp(np.ones(d), pl, start), 1.0, atol=1e-12)  # J 1 = 1
+        h = rng.normal(size=d)
+        assert abs(h @ jg - g @ oracle.vjp(h, pl, start)) < 1e-9 * d  # symmetric
+        # central finite differences along a random direction; mask elements whose cluster
+        # membership changes between w - eps v, w, w + eps v (a kink is crossed there)
+        eps = 1e-6
+        vdir = rng.normal(size=d)
+        up, pp, sp = oracle.prox_f64(w + eps * vdir, lam)
+        um, pm, sm = oracle.prox_f64(w - eps * vdir, lam)
+        ids0 = oracle.cluster_ids(pl, start)
+        idp = oracle.cluster_ids(pp.astype(np.int32), sp)
+        idm = oracle.cluster_ids(pm.astype(np.int32), sm)
+
+        def members(ids):
+            out = {}
+            for i, c in enumerate(ids):
+                out.setdefault(c, []).append(i)
+            return {i: tuple(out[c]) for i, c in enumerate(ids)}
+        m0, mp, mm = members(ids0), members(idp), members(idm)
+        keep = np.array([m0[i] == mp[i] == mm[i] for i in range(d)])
+        assert keep.mean() > 0.5
+        fd = (up - um) / (2 * eps)
+        jv = oracle.vjp(vdir, pl, start)
+        assert np.max(np.abs(fd - jv)[keep]) < 1e-6
+
+
+# ----------------------------------------------------------------------------- segments API
+
+def test_segments_match_single_and_threads():
+    rng = np.random.default_rng(15)
+    lens = [0, 1, 2, 5, 100, 3072, 4096, 7, 0, 1]
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = rng.normal(size=offsets[-1]).astype(np.float32)
+    lam = rng.uniform(0, 0.1, size=len(lens)).astype(np.float32)
+    u1, p1, s1 = oracle.prox_segments(w, lam, offsets, n_threads=1)
+    u4, p4, s4 = oracle.prox_segments(w, lam, offsets, n_threads=4)
+    assert np.array_equal(u1, u4) and np.array_equal(p1, p4) and np.array_equal(s1, s4)
+    for s, (a, b) in enumerate(zip(offsets[:-1], offsets[1:])):
+        if b == a:
+            continue
+        u, perm, start = oracle.prox_f64(w[a:b].astype(np.float64), float(lam[s]))
+        np.testing.assert_array_equal(u1[a:b], u)
+        np.testing.assert_array_equal(p1[a:b], perm)
+        np.testing.assert_array_equal(s1[a:b], start)
+
+
+def test_nonfinite_and_bad_args():
+    u, perm, start = oracle.prox_f64(np.array([1.0, np.nan, 2.0]), 0.1)
+    assert np.isnan(u).all()
+    with pytest.raises(ValueError):
+        oracle.prox_f64(np.array([1.0, 2.0]), -1.0)
+    with pytest.raises(ValueError):
+        oracle.prox_segments(np.zeros(4, np.float32), 0.1, np.array([0, 3, 2, 4]))
