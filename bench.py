@@ -1,0 +1,233 @@
+"""Benchmark of the prox_R hot path on one MI355X.
+
+A step = one full pass of the path over the workload: forward (sort, rank shift, cluster
+merge, scatter, saved permutation and cluster-start bits) then backward (cluster averages of an
+upstream gradient).  Default workload: the worst-case collision chain, one segment of
+d = 2^24 FP32 weights w_k = (k/(d-1))^2 with lam = 0.7 (every particle ends in one cluster).
+
+Prints one JSON line: elements/s, the roofline of the dominant kernel (HIP-event durations
+measured live on the library's stream), the CPU oracle on the host as a reference, and extra
+figures: a typical d = 2^24 N(0,1) vector and the batched MLP-rows workload, graph-captured
+batched launch versus per-row launches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "prox_R elements/s + % HBM roofline at d=2^24; batched vs per-row launch speedup"
+
+# Algorithmic HBM bytes per element that each kernel must move (compulsory traffic of its role
+# in the path; see the design notes).  "el" = elements of the segment(s) the launch covers.
+KERNEL_BYTES_PER_EL = {
+    "radix_scatter": 16.0,      # read key+index 8 B, write key+index 8 B
+    "radix_hist": 4.0,          # read key
+    "big_tile_hull": 4.0,       # read sorted key (hull vertices are bookkeeping)
+    "big_apply": 12.125,        # read sorted key + perm 8 B, write value 4 B, start bit
+    "big_bwd_tile": 12.0,       # read perm 4 + gradient 4, write gathered gradient 4
+    "big_bwd_apply": 12.125,    # read gathered gradient 4 + perm 4 + bit, write gradient 4
+    "prox_fwd_small_4096": 12.125,  # read w, write u + perm + bit
+    "prox_bwd_small_4096": 12.125,  # read g + perm + bit, write gradient
+    "prox_fwd_small_8192": 12.125,
+    "prox_bwd_small_8192": 12.125,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the typical and batched figures")
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Step:
+    """Buffers and the fwd+bwd step of one workload through the C ABI."""
+
+    def __init__(self, case, batched=False):
+        import torch
+        import paper_2311_03096_amd as wsr
+        self.wsr, self.torch = wsr, torch
+        self.case = case
+        self.n = case["w"].shape[0]
+        self.offsets = case["offsets"]
+        self.lam = case["lam"]
+        self.w = torch.from_numpy(case["w"]).cuda()
+        self.out = torch.empty_like(self.w)
+        self.perm = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        self.mask = torch.empty((self.n + 31) // 32, dtype=torch.int32, device="cuda")
+        g = case.get("g")
+        if g is None:
+            g = np.random.default_rng(123).standard_normal(self.n).astype(np.float32)
+        self.g = torch.from_numpy(g).cuda()
+        self.gw = torch.empty_like(self.g)
+        self.batched = batched
+        if batched:
+            self.plan = wsr.wsr_plan_create(self.offsets)
+            nb = wsr.wsr_plan_workspace_bytes(self.plan)
+        else:
+            self.plan = None
+            nb = wsr.wsr_workspace_bytes(self.offsets)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+
+    def __call__(self):
+        wsr = self.wsr
+        if self.batched:
+            wsr.wsr_prox_forward_batched(self.plan, self.w, self.out, None, self.lam, self.perm, self.mask, self.ws)
+            wsr.wsr_prox_backward_batched(self.plan, self.g, self.gw, self.perm, self.mask, self.ws)
+        else:
+            wsr.wsr_prox_forward(self.w, self.out, self.offsets, self.lam, self.perm, self.mask, self.ws)
+            wsr.wsr_prox_backward(self.g, self.gw, self.offsets, self.perm, self.mask, self.ws)
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def trace_kernels(fn, reps):
+    import torch
+    import paper_2311_03096_amd as wsr
+    torch.cuda.synchronize()
+    wsr.wsr_trace_collect()
+    wsr.wsr_trace_enable(True)
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    wsr.wsr_trace_enable(False)
+    return wsr.wsr_trace_collect()
+
+
+def roofline(trace, n_el, steps):
+    """Dominant kernel by total time; achieved = algorithmic bytes per launch / mean duration."""
+    name, (cnt, tot) = max(trace.items(), key=lambda kv: kv[1][1])
+    avg_ms = tot / cnt
+    per_launch_el = n_el * steps / cnt if name in ("radix_scatter", "radix_hist") else n_el
+    bpe = KERNEL_BYTES_PER_EL.get(name)
+    if bpe is None:
+        return dict(kernel=name, launches_per_step=cnt / steps, avg_ms=avg_ms, bound="hbm", achieved=None,
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=None, traffic=None)
+    if name in ("radix_scatter", "radix_hist"):
+        per_launch_el = n_el  # every pass covers the whole segment
+    ach = bpe * per_launch_el / (avg_ms * 1e-3) / 1e9
+    return dict(kernel=name, launches_per_step=cnt / steps, avg_ms=round(avg_ms, 5),
+                bytes_per_el=bpe, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+
+
+def cpu_baseline(case):
+    """Oracle forward + VJP over the whole workload on the host (one thread)."""
+    import oracle
+    w, off, lam = case["w"], case["offsets"], case["lam"]
+    g = np.random.default_rng(123).standard_normal(w.shape[0])
+    t0 = time.perf_counter()
+    u, perm, start = oracle.prox_segments(w, lam, off, n_threads=1)
+    oracle.vjp(g, perm, start, off)
+    dt = time.perf_counter() - t0
+    return dict(value=float(w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
+                sample="one full fwd+vjp step of %s (%d elements), FP64 sort + stack PAV, 1 thread, %.1f s"
+                % (case["name"], w.shape[0], dt))
+
+
+def batched_vs_per_row(steps, warmup):
+    """MLP rows (8202 segments, 29.4M weights): fwd+bwd, graph-captured batched launches vs
+    per-row launches of the plain entry points on the same stream."""
+    import torch
+    from paper_2311_03096_amd import workloads
+    case = workloads.mlp_rows()
+    n = case["w"].shape[0]
+    b = Step(case, batched=True)
+    p = Step(case, batched=False)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b()
+    ms_graph, _ = time_steps(graph.replay, steps, warmup)
+    ms_batched, _ = time_steps(b, steps, warmup)
+    ms_rows, _ = time_steps(p, max(2, steps // 4), 1)
+    tr = trace_kernels(b, 3)
+    roof = roofline({k: v for k, v in tr.items() if k.startswith("prox_fwd")}, n, 3)
+    return dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
+                elements=n, ms_per_step_graph=round(ms_graph, 4), ms_per_step_batched=round(ms_batched, 4),
+                ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
+                speedup_graph_vs_per_row=round(ms_rows / ms_graph, 2), fwd_kernel_roofline=roof,
+                kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()})
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: the prox path here is single-GPU (segments would "
+              "shard across GPUs with no exchange); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2311_03096_amd as wsr
+    from paper_2311_03096_amd import workloads
+    wsr.load()  # fails loudly when the HIP library is missing
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    d = 1 << 24
+    case = workloads.chain(d, 0.7)
+    log("workload", case["name"], "steps", args.steps, "warmup", args.warmup)
+    step = Step(case)
+    ms, wall = time_steps(step, args.steps, args.warmup)
+    tr = trace_kernels(step, 3)
+    roof = roofline(tr, d, 3)
+    log("ms/step", ms, "trace", tr)
+    extra = dict(kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
+                 wall_ms_per_step=round(wall, 4))
+    if not args.no_extra:
+        typ = workloads.plain(d, 0.1, seed=1)
+        st = Step(typ)
+        ms_t, _ = time_steps(st, max(3, args.steps // 2), 2)
+        extra["typical_d2p24"] = dict(workload="one N(0,1) vector d=2^24, lam=0.1", ms_per_step=round(ms_t, 4),
+                                      elements_per_s=d / (ms_t * 1e-3))
+        log("typical", ms_t)
+        extra["batched_mlp_rows"] = batched_vs_per_row(max(5, args.steps), args.warmup)
+        log("batched", extra["batched_mlp_rows"])
+    res = dict(metric=METRIC, value=d / (ms * 1e-3), unit="elements/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="worst-case collision chain: one FP32 segment d=2^24, w_k=(k/(d-1))^2, "
+                                    "lam=0.7 (one final cluster); step = forward with saved state + backward",
+                           d=d, lam=0.7, parallelism="single GPU"),
+               roofline=roof)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(case)
+        log("cpu", res["cpu_baseline"])
+    res["extra"] = extra
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * wsr.h -- C ABI of the MI355X (gfx950) library for the proximal map of the
+ * weight-sharing penalty
+ *
+ *     R_d(w) = 1/(d-1) * sum_{i>j} |w_i - w_j|                (paper Sec. 1, eq. reg)
+ *     prox_{lam R_d}(w) = argmin_u  lam*R_d(u) + 1/2 ||u - w||^2   (Sec. 1; App. A.1)
+ *
+ * computed as: sort -> rank-dependent shift -> cluster merging -> scatter back
+ * (Alg. prox without its l1 lines; Sec. 3 particle model; Sec. 4 collision
+ * algorithms).  lam is "step size x penalty" (eta * alpha in the proximal-gradient
+ * update, Sec. 1 and App. A.1 eq. pgd).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A flat FP32 buffer of N = offsets[n_seg] weights is split into n_seg segments
+ *   [offsets[s], offsets[s+1]).  Each segment is an independent prox problem with its
+ *   own normalisation 1/(d_s - 1) (the paper applies R per layer, App. E.1; rows of a
+ *   weight matrix are just shorter segments).  offsets[0] must be 0, offsets must be
+ *   non-decreasing, every segment must satisfy d_s <= WSR_MAX_SEGMENT.
+ * - Device pointers are plain device addresses (hipMalloc / torch CUDA tensors) on
+ *   the current HIP device; "stream" is a hipStream_t passed as void* (NULL = the
+ *   null stream).  Every compute call only enqueues work on that stream, returns
+ *   without synchronising, and allocates no memory: scratch comes from the caller's
+ *   workspace "ws" of "ws_bytes" bytes (device memory, any contents, 256-byte
+ *   aligned), sized with the matching *_workspace_bytes call.  Two calls that
+ *   overlap in time on different streams must not share a workspace.
+ * - Outputs may alias inputs only where stated.
+ * - Saved state for the backward pass (both pointers NULL = inference, no save):
+ *     saved_perm[N]  int32: at flat position offsets[s] + k, the segment-local index
+ *                    of the weight with rank k in segment s (ascending order).
+ *     saved_mask[ceil(N/32)] uint32: bit (p % 32) of word p / 32 is set iff flat
+ *                    position p = offsets[s] + k starts a cluster (rank k is the first
+ *                    rank of its group of equal outputs).
+ *   The forward call overwrites every word of saved_mask.
+ * - Semantics of special segments: d_s == 0 is skipped; d_s == 1 or lam == 0 gives
+ *   the identity (every weight its own cluster); a segment holding a NaN or +-Inf
+ *   weight gets NaN outputs (every weight its own cluster).  In these cases saved_perm
+ *   holds some permutation of the segment.  A lambda read from device memory that is
+ *   not > 0 (negative, zero or NaN) also gives the identity.
+ * - Clusters are the coarsest partition: neighbouring ranks whose exact outputs
+ *   are equal share a cluster (merge when avg_y(lower) >= avg_y(upper), Sec. 4.1).
+ *   Results are deterministic: the same inputs give bit-identical outputs.
+ *
+ * Errors: argument errors are detected on the host before anything is enqueued and
+ * return WSR_ERR_INVALID (bad pointer, size, offsets or lambda), WSR_ERR_WORKSPACE
+ * (workspace too small) or WSR_ERR_UNSUPPORTED (segment longer than
+ * WSR_MAX_SEGMENT).  A failing HIP launch returns WSR_ERR_HIP.  Calls never abort.
+ */
+#ifndef WSR_H
+#define WSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define WSR_API __attribute__((visibility("default")))
+#else
+#define WSR_API
+#endif
+
+#define WSR_OK 0
+#define WSR_ERR_INVALID (-1)
+#define WSR_ERR_WORKSPACE (-2)
+#define WSR_ERR_HIP (-3)
+#define WSR_ERR_UNSUPPORTED (-4)
+
+/* longest supported segment (elements) */
+#define WSR_MAX_SEGMENT ((int64_t)1 << 26)
+
+/* Library version as 10000*major + 100*minor + patch. */
+WSR_API int wsr_version(void);
+
+/* Static description of a status code; never NULL. */
+WSR_API const char* wsr_status_string(int status);
+
+/*
+ * Workspace bytes needed by wsr_prox_forward / wsr_prox_backward for these host
+ * offsets (n_seg + 1 entries).  Segments short enough to be solved inside one
+ * workgroup need none; longer ones need scratch for a device-wide sort and the
+ * cross-tile cluster merge, sized for the longest segment (segments are processed
+ * one after another).  Writes the size to *bytes.
+ */
+WSR_API int wsr_workspace_bytes(const int64_t* h_offsets, int64_t n_seg, size_t* bytes);
+
+/*
+ * Forward prox, one lambda for all segments (Alg. prox lines sort / shift /
+ * collisions / repeat_interleave / scatter; l1 lines not applied).
+ *   w[N]          device, input weights (flat, segment-major)
+ *   out[N]        device, prox values in the original order; may alias w
+ *   h_offsets     HOST array of n_seg + 1 int64 segment offsets
+ *   lambda        prox scale, finite and >= 0
+ *   saved_perm, saved_mask   device, both NULL (inference) or both non-NULL
+ *   ws, ws_bytes  device workspace, >= wsr_workspace_bytes(h_offsets, n_seg)
+ * Segments are launched one after another (one launch per short segment; this is
+ * the per-row path that the batched entry point is compared against).
+ */
+WSR_API int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg,
+                     float lambda, int32_t* saved_perm, uint32_t* saved_mask, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/*
+ * Backward of the prox: grad_w = J^T grad_out, where on the piece of the map picked
+ * by the saved partition J averages within each cluster (J is symmetric and
+ * idempotent).  Not in the paper: it follows from Alg. prox's repeat_interleave of
+ * cluster averages, with the partition held fixed.
+ *   grad_out[N]   device, upstream gradient (original order)
+ *   grad_w[N]     device, result (original order); must not alias grad_out
+ *   saved_perm, saved_mask   device, as written by the matching forward call
+ */
+WSR_API int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_offsets,
+                      int64_t n_seg, const int32_t* saved_perm, const uint32_t* saved_mask,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ batched */
+
+typedef struct wsr_plan wsr_plan; /* opaque, owned by the library */
+
+/*
+ * Plan for a fixed segmentation: validates and uploads the offsets (one hipMalloc,
+ * done here and never during compute calls), groups segments by size class and
+ * records the launch schedule used by the batched calls, so that a whole optimizer
+ * step of prox calls is a fixed sequence of launches (hipGraph-capturable).
+ *   flags: 0, or WSR_PLAN_AUTOTUNE to time the launch variants once on the current
+ *   device (synchronises the device) and keep the fastest in the plan.
+ * On success *plan receives a new plan; free it with wsr_plan_destroy.
+ */
+#define WSR_PLAN_AUTOTUNE 1
+WSR_API int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan** plan);
+WSR_API int wsr_plan_destroy(wsr_plan* plan);
+
+/* Workspace bytes needed by the batched calls of this plan. */
+WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);
+
+/*
+ * Batched forward over every segment of the plan: all short segments in one launch
+ * per size class, long segments through the device-wide path.
+ *   d_lambda      device array of n_seg FP32 lambdas, or NULL to use lambda_scalar for
+ *                 every segment (values are read by the kernels, so they may change
+ *                 between replays of a captured graph)
+ * Other arguments as in wsr_prox_forward.
+ */
+WSR_API int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out,
+                             const float* d_lambda, float lambda_scalar, int32_t* saved_perm,
+                             uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream);
+
+/* Batched backward over every segment of the plan (see wsr_prox_backward). */
+WSR_API int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,
+                              const int32_t* saved_perm, const uint32_t* saved_mask, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ tracing */
+
+/*
+ * Per-kernel timing for measurement (not used by the compute path itself).
+ * wsr_trace_enable(1) creates a pool of HIP events (allocation: call it outside graph
+ * capture); while enabled, every kernel the library launches is bracketed by two events
+ * recorded on the stream it is launched on.  wsr_trace_enable(0) stops recording.
+ * wsr_trace_collect synchronises the recorded events and writes, for up to max_entries
+ * distinct kernel names, the name (NUL-terminated, at most 63 chars, in names[i*64]),
+ * the number of launches and their summed duration in milliseconds; *n_out receives the
+ * number of entries written.  Collecting clears the recorded launches.  Launches beyond the
+ * pool size (4096 per collect) are not recorded.
+ */
+WSR_API int wsr_trace_enable(int on);
+WSR_API int wsr_trace_collect(int max_entries, char* names, int64_t* counts, double* total_ms,
+                              int* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSR_H */

@@ -1,0 +1,190 @@
+"""ctypes binding of libwsr.so (include/wsr.h): argument marshalling only.
+
+Every function takes torch tensors for device buffers (float32 / int32, contiguous, on the
+current HIP device) and host int64 offsets, and forwards raw pointers plus the current torch
+stream to the C ABI.  All computation happens in the HIP kernels of the library; there is no
+fallback: if the library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwsr.so")
+
+WSR_OK, WSR_ERR_INVALID, WSR_ERR_WORKSPACE, WSR_ERR_HIP, WSR_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
+WSR_PLAN_AUTOTUNE = 1
+WSR_MAX_SEGMENT = 1 << 26
+
+EXPORTED = (
+    "wsr_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_prox_forward",
+    "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy", "wsr_plan_workspace_bytes",
+    "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
+)
+
+
+class WsrError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        super().__init__("%s failed: %s (%d)" % (fn, _status_string(status), status))
+
+
+_lib = None
+
+
+def load():
+    """Load libwsr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libwsr.so is not built; run `python -m paper_2311_03096_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    p, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+    f32 = ctypes.c_float
+    sig = {
+        "wsr_version": ([], i32),
+        "wsr_status_string": ([i32], ctypes.c_char_p),
+        "wsr_workspace_bytes": ([p, i64, ctypes.POINTER(sz)], i32),
+        "wsr_prox_forward": ([p, p, p, i64, f32, p, p, p, sz, p], i32),
+        "wsr_prox_backward": ([p, p, p, i64, p, p, p, sz, p], i32),
+        "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
+        "wsr_plan_destroy": ([p], i32),
+        "wsr_plan_workspace_bytes": ([p, ctypes.POINTER(sz)], i32),
+        "wsr_prox_forward_batched": ([p, p, p, p, f32, p, p, p, sz, p], i32),
+        "wsr_prox_backward_batched": ([p, p, p, p, p, p, sz, p], i32),
+        "wsr_trace_enable": ([i32], i32),
+        "wsr_trace_collect": ([i32, p, p, p, ctypes.POINTER(i32)], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _status_string(status):
+    try:
+        return load().wsr_status_string(int(status)).decode()
+    except Exception:  # library not loadable: plain text
+        return "status"
+
+
+def _check(fn, rc):
+    if rc != WSR_OK:
+        raise WsrError(fn, rc)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _offsets(offsets):
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or off.shape[0] < 1:
+        raise ValueError("offsets must be a 1-D array of n_seg + 1 values")
+    return off
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ws_args(ws):
+    if ws is None:
+        return None, 0
+    return _ptr(ws), ws.numel() * ws.element_size()
+
+
+def wsr_version():
+    return load().wsr_version()
+
+
+def wsr_status_string(status):
+    return load().wsr_status_string(int(status)).decode()
+
+
+def wsr_workspace_bytes(offsets):
+    off = _offsets(offsets)
+    n = ctypes.c_size_t(0)
+    _check("wsr_workspace_bytes", load().wsr_workspace_bytes(off.ctypes.data_as(ctypes.c_void_p),
+                                                             off.shape[0] - 1, ctypes.byref(n)))
+    return n.value
+
+
+def wsr_prox_forward(w, out, offsets, lam, saved_perm=None, saved_mask=None, ws=None, stream=None):
+    off = _offsets(offsets)
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_forward", load().wsr_prox_forward(
+        _ptr(w), _ptr(out), off.ctypes.data_as(ctypes.c_void_p), off.shape[0] - 1, float(lam),
+        _ptr(saved_perm), _ptr(saved_mask), wp, wn, _stream(stream)))
+
+
+def wsr_prox_backward(grad_out, grad_w, offsets, saved_perm, saved_mask, ws=None, stream=None):
+    off = _offsets(offsets)
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_backward", load().wsr_prox_backward(
+        _ptr(grad_out), _ptr(grad_w), off.ctypes.data_as(ctypes.c_void_p), off.shape[0] - 1,
+        _ptr(saved_perm), _ptr(saved_mask), wp, wn, _stream(stream)))
+
+
+def wsr_plan_create(offsets, flags=0):
+    off = _offsets(offsets)
+    h = ctypes.c_void_p()
+    _check("wsr_plan_create", load().wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p),
+                                                     off.shape[0] - 1, int(flags), ctypes.byref(h)))
+    return h
+
+
+def wsr_plan_destroy(plan):
+    _check("wsr_plan_destroy", load().wsr_plan_destroy(plan))
+
+
+def wsr_plan_workspace_bytes(plan):
+    n = ctypes.c_size_t(0)
+    _check("wsr_plan_workspace_bytes", load().wsr_plan_workspace_bytes(plan, ctypes.byref(n)))
+    return n.value
+
+
+def wsr_prox_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, saved_perm=None, saved_mask=None,
+                             ws=None, stream=None):
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_forward_batched", load().wsr_prox_forward_batched(
+        plan, _ptr(w), _ptr(out), _ptr(lam), float(lam_scalar), _ptr(saved_perm), _ptr(saved_mask),
+        wp, wn, _stream(stream)))
+
+
+def wsr_prox_backward_batched(plan, grad_out, grad_w, saved_perm, saved_mask, ws=None, stream=None):
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_backward_batched", load().wsr_prox_backward_batched(
+        plan, _ptr(grad_out), _ptr(grad_w), _ptr(saved_perm), _ptr(saved_mask), wp, wn, _stream(stream)))
+
+
+def wsr_trace_enable(on=True):
+    _check("wsr_trace_enable", load().wsr_trace_enable(1 if on else 0))
+
+
+def wsr_trace_collect(max_entries=64):
+    """Synchronise and return {kernel name: (launches, total ms)} for the traced launches."""
+    names = ctypes.create_string_buffer(64 * max_entries)
+    counts = (ctypes.c_int64 * max_entries)()
+    total = (ctypes.c_double * max_entries)()
+    n = ctypes.c_int(0)
+    _check("wsr_trace_collect", load().wsr_trace_collect(max_entries, ctypes.cast(names, ctypes.c_void_p),
+                                                         ctypes.cast(counts, ctypes.c_void_p),
+                                                         ctypes.cast(total, ctypes.c_void_p), ctypes.byref(n)))
+    res = {}
+    for i in range(n.value):
+        nm = names.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+        res[nm] = (int(counts[i]), float(total[i]))
+    return res

@@ -1,0 +1,527 @@
+// wsr_api.hip -- host side of the C ABI declared in include/wsr.h: argument validation,
+// workspace layout, size-class routing, plans and launch sequences.  Nothing here allocates or
+// synchronises inside a compute call; plans allocate once at creation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "../../include/wsr.h"
+#include "wsr_big.h"
+#include "wsr_kernels.h"
+
+namespace wsr {
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum SizeClass { kSkip = -1, kC2048 = 0, kC4096 = 1, kC8192 = 2, kBig = 3 };
+constexpr int kNumSmall = 3;
+constexpr int kClassMax[kNumSmall] = {2048, 4096, 8192};
+
+inline int size_class(int64_t d) {
+  if (d <= 0) return kSkip;
+  for (int c = 0; c < kNumSmall; ++c)
+    if (d <= kClassMax[c]) return c;
+  return kBig;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int validate_offsets(const int64_t* h_offsets, int64_t n_seg, int64_t* max_big) {
+  if (!h_offsets || n_seg < 0) return WSR_ERR_INVALID;
+  if (h_offsets[0] != 0) return WSR_ERR_INVALID;
+  int64_t mb = 0;
+  for (int64_t s = 0; s < n_seg; ++s) {
+    const int64_t d = h_offsets[s + 1] - h_offsets[s];
+    if (d < 0) return WSR_ERR_INVALID;
+    if (d > WSR_MAX_SEGMENT) return WSR_ERR_UNSUPPORTED;
+    if (size_class(d) == kBig) mb = std::max(mb, d);
+  }
+  if (max_big) *max_big = mb;
+  return WSR_OK;
+}
+
+// Workspace of the long-segment path for segments of length <= d.
+struct BigWs {
+  uint32_t* flags;
+  uint32_t *keysA, *keysB;
+  int32_t *valsA, *valsB;
+  uint32_t *hist, *totals;
+  int32_t* vpos;
+  double* vS;
+  int32_t *hcnt, *lo, *hi, *prev_pos, *next_pos;
+  double *tsum, *tileoff, *prev_s, *next_s;
+  // backward
+  int32_t *fpos, *lpos;
+  double *fG, *lG, *prevG, *nextG;
+  size_t bytes;
+};
+
+BigWs big_layout(int64_t d, void* base) {
+  BigWs w{};
+  const int64_t nrt = ceil_div(d, kRadixTile);
+  const int64_t nt = ceil_div(d, kBigTile);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)((char*)base + off) : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  w.flags = (uint32_t*)take(256);
+  w.keysA = (uint32_t*)take(sizeof(uint32_t) * d);
+  w.keysB = (uint32_t*)take(sizeof(uint32_t) * d);
+  w.valsA = (int32_t*)take(sizeof(int32_t) * d);
+  w.valsB = (int32_t*)take(sizeof(int32_t) * d);
+  w.hist = (uint32_t*)take(sizeof(uint32_t) * 256 * nrt);
+  w.totals = (uint32_t*)take(sizeof(uint32_t) * 256);
+  w.vpos = (int32_t*)take(sizeof(int32_t) * nt * (kBigTile + 1));
+  w.vS = (double*)take(sizeof(double) * nt * (kBigTile + 1));
+  w.hcnt = (int32_t*)take(sizeof(int32_t) * nt);
+  w.lo = (int32_t*)take(sizeof(int32_t) * nt);
+  w.hi = (int32_t*)take(sizeof(int32_t) * nt);
+  w.prev_pos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.next_pos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.tsum = (double*)take(sizeof(double) * nt);
+  w.tileoff = (double*)take(sizeof(double) * nt);
+  w.prev_s = (double*)take(sizeof(double) * nt);
+  w.next_s = (double*)take(sizeof(double) * nt);
+  w.fpos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.lpos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.fG = (double*)take(sizeof(double) * nt);
+  w.lG = (double*)take(sizeof(double) * nt);
+  w.prevG = (double*)take(sizeof(double) * nt);
+  w.nextG = (double*)take(sizeof(double) * nt);
+  w.bytes = off;
+  return w;
+}
+
+size_t big_bytes(int64_t max_big) { return max_big > 0 ? big_layout(max_big, nullptr).bytes : 0; }
+
+int last_error() { return hipGetLastError() == hipSuccess ? WSR_OK : WSR_ERR_HIP; }
+
+// ---- optional per-launch HIP-event trace (wsr_trace_enable / wsr_trace_collect)
+constexpr int kTracePool = 4096;
+struct TraceRec {
+  const char* name;
+  int ev;
+};
+struct Trace {
+  std::mutex mu;
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // 2 * kTracePool
+  std::vector<TraceRec> recs;
+} g_trace;
+
+// WSR_DEBUG=1 in the environment: report the first failing launch on stderr.
+bool debug_enabled() {
+  static const bool on = [] {
+    const char* e = std::getenv("WSR_DEBUG");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
+struct TraceScope {
+  hipStream_t s;
+  const char* name;
+  int slot = -1;
+  TraceScope(const char* nm, hipStream_t st) : s(st), name(nm) {
+    std::lock_guard<std::mutex> lk(g_trace.mu);
+    if (!g_trace.on || (int)g_trace.recs.size() >= kTracePool) return;
+    slot = (int)g_trace.recs.size();
+    g_trace.recs.push_back({nm, slot});
+    (void)hipEventRecord(g_trace.ev[2 * slot], s);
+  }
+  ~TraceScope() {
+    if (slot >= 0) (void)hipEventRecord(g_trace.ev[2 * slot + 1], s);
+    if (debug_enabled()) {
+      const hipError_t e = hipPeekAtLastError();
+      if (e != hipSuccess) std::fprintf(stderr, "wsr: launch of %s failed: %s\n", name, hipGetErrorString(e));
+    }
+  }
+};
+#define WSR_TRACE(name, stream) TraceScope wsr_trace_scope_(name, stream)
+
+template <int TMAX, int NT>
+void launch_small_fwd(int nblocks, const SegArgs& a, const float* w, float* out, int32_t* perm,
+                      uint32_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL((k_prox_fwd_small<TMAX, NT>), dim3(nblocks), dim3(NT), 0, s, a, w, out, perm, mask);
+}
+template <int TMAX, int NT>
+void launch_small_bwd(int nblocks, const SegArgs& a, const float* g, float* gw, const int32_t* perm,
+                      const uint32_t* mask, hipStream_t s) {
+  hipLaunchKernelGGL((k_prox_bwd_small<TMAX, NT>), dim3(nblocks), dim3(NT), 0, s, a, g, gw, perm, mask);
+}
+
+void small_fwd(int cls, int nblocks, const SegArgs& a, const float* w, float* out, int32_t* perm,
+               uint32_t* mask, hipStream_t s) {
+  switch (cls) {
+    case kC2048: { WSR_TRACE("prox_fwd_small_2048", s); launch_small_fwd<2048, 128>(nblocks, a, w, out, perm, mask, s); } break;
+    case kC4096: { WSR_TRACE("prox_fwd_small_4096", s); launch_small_fwd<4096, 256>(nblocks, a, w, out, perm, mask, s); } break;
+    default: { WSR_TRACE("prox_fwd_small_8192", s); launch_small_fwd<8192, 512>(nblocks, a, w, out, perm, mask, s); } break;
+  }
+}
+void small_bwd(int cls, int nblocks, const SegArgs& a, const float* g, float* gw, const int32_t* perm,
+               const uint32_t* mask, hipStream_t s) {
+  switch (cls) {
+    case kC2048: { WSR_TRACE("prox_bwd_small_2048", s); launch_small_bwd<2048, 128>(nblocks, a, g, gw, perm, mask, s); } break;
+    case kC4096: { WSR_TRACE("prox_bwd_small_4096", s); launch_small_bwd<4096, 256>(nblocks, a, g, gw, perm, mask, s); } break;
+    default: { WSR_TRACE("prox_bwd_small_8192", s); launch_small_bwd<8192, 512>(nblocks, a, g, gw, perm, mask, s); } break;
+  }
+}
+
+void zero_words(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 2048);
+  WSR_TRACE("zero_words", s);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
+}
+
+// Forward of one long segment [start, start + d).
+int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
+                float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s) {
+  BigWs b = big_layout(d, ws);
+  const int nrt = (int)ceil_div(d, kRadixTile);
+  const int nt = (int)ceil_div(d, kBigTile);
+  const float* wseg = w + start;
+  zero_words(b.flags, 64, s);
+  // 4 stable LSD passes: w -> B -> A -> B -> A(keys) / perm
+  int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    const uint32_t* ksrc = pass == 0 ? nullptr : (pass % 2 == 1 ? b.keysB : b.keysA);
+    const int32_t* vsrc = pass == 0 ? nullptr : (pass % 2 == 1 ? b.valsB : b.valsA);
+    uint32_t* kdst = pass % 2 == 0 ? b.keysB : b.keysA;
+    int32_t* vdst = pass % 2 == 0 ? b.valsB : (pass == 3 ? perm_final : b.valsA);
+    { WSR_TRACE("radix_hist", s);
+    hipLaunchKernelGGL(k_radix_hist, dim3(nrt), dim3(kRadixThreads), 0, s, pass == 0 ? wseg : nullptr,
+                       ksrc, d, shift, b.hist, nrt, b.flags); }
+    { WSR_TRACE("radix_rowscan", s);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, b.hist, nrt, b.totals); }
+    { WSR_TRACE("radix_scatter", s);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nrt), dim3(kRadixThreads), 0, s, pass == 0 ? wseg : nullptr,
+                       ksrc, vsrc, kdst, vdst, d, shift, b.hist, b.totals, nrt); }
+  }
+  { WSR_TRACE("big_tile_hull", s);
+  hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, lam_arr, seg_id,
+                     lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum); }
+  { WSR_TRACE("big_tile_scan", s);
+  hipLaunchKernelGGL(k_big_tile_scan, dim3(1), dim3(1024), 0, s, b.tsum, b.tileoff, b.hcnt, b.lo, b.hi, nt, d,
+                     lam_arr, seg_id, lam_scalar); }
+  int nlev = 0;
+  while ((1 << nlev) < nt) ++nlev;
+  int lvl_lo = 1;
+  do {
+    const int lvl_hi = std::min(lvl_lo + kMergeLevelsPerLaunch - 1, nlev);
+    const int G = 1 << lvl_hi;
+    const int groups = (int)ceil_div(nt, G);
+    const int fin = lvl_hi == nlev ? 1 : 0;
+    if (G > kMergeGroupMax) return WSR_ERR_UNSUPPORTED;
+    WSR_TRACE("big_merge", s);
+    if (G <= kMergeGroupSmall)
+      hipLaunchKernelGGL((k_big_merge<kMergeGroupSmall, kMergeRecMax>), dim3(groups), dim3(kMergeThreads), 0,
+                         s, lvl_lo, lvl_hi, nt, b.vpos, b.vS, b.tileoff, b.lo, b.hi, fin, b.prev_pos, b.prev_s,
+                         b.next_pos, b.next_s);
+    else
+      hipLaunchKernelGGL((k_big_merge<kMergeGroupMax, kMergeRecMax>), dim3(groups), dim3(kMergeThreads), 0,
+                         s, lvl_lo, lvl_hi, nt, b.vpos, b.vS, b.tileoff, b.lo, b.hi, fin, b.prev_pos, b.prev_s,
+                         b.next_pos, b.next_s);
+    lvl_lo = lvl_hi + 1;
+  } while (lvl_lo <= nlev);
+  { WSR_TRACE("big_apply", s);
+  hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, perm_final, d, lam_arr, seg_id,
+                     lam_scalar, b.flags, b.vpos, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
+                     b.next_pos, b.next_s, out, saved_mask, start); }
+  return last_error();
+}
+
+int big_backward(const float* g, float* gw, int64_t start, int64_t d, const int32_t* perm,
+                 const uint32_t* mask, void* ws, hipStream_t s) {
+  BigWs b = big_layout(d, ws);
+  const int nt = (int)ceil_div(d, kBigTile);
+  float* gsorted = (float*)b.keysA;
+  { WSR_TRACE("big_bwd_tile", s);
+  hipLaunchKernelGGL(k_big_bwd_tile, dim3(nt), dim3(kBigThreads), 0, s, g, perm + start, mask, d, start,
+                     gsorted, b.tsum, b.fpos, b.fG, b.lpos, b.lG); }
+  { WSR_TRACE("big_bwd_scan", s);
+  hipLaunchKernelGGL(k_big_bwd_scan, dim3(1), dim3(1024), 0, s, b.tsum, b.fpos, b.fG, b.lpos, b.lG, nt, d,
+                     b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG); }
+  { WSR_TRACE("big_bwd_apply", s);
+  hipLaunchKernelGGL(k_big_bwd_apply, dim3(nt), dim3(kBigThreads), 0, s, gsorted, perm + start, mask, d,
+                     start, b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG, gw); }
+  return last_error();
+}
+
+}  // namespace
+}  // namespace wsr
+
+using namespace wsr;
+
+struct wsr_plan {
+  int64_t n_seg = 0;
+  int64_t total = 0;
+  int64_t max_big = 0;
+  int device = 0;
+  int64_t* d_offsets = nullptr;
+  int32_t* d_sched = nullptr;                // all small schedules back to back
+  int64_t sched_off[kNumSmall] = {0, 0, 0};  // start of class c in d_sched
+  int64_t sched_cnt[kNumSmall] = {0, 0, 0};
+  std::vector<int64_t> h_offsets;
+  std::vector<int32_t> big_segs;  // long segments, in order
+};
+
+extern "C" {
+
+int wsr_version(void) { return 100; }
+
+const char* wsr_status_string(int status) {
+  switch (status) {
+    case WSR_OK: return "ok";
+    case WSR_ERR_INVALID: return "invalid argument";
+    case WSR_ERR_WORKSPACE: return "workspace too small";
+    case WSR_ERR_HIP: return "HIP launch error";
+    case WSR_ERR_UNSUPPORTED: return "segment longer than WSR_MAX_SEGMENT";
+    default: return "unknown status";
+  }
+}
+
+int wsr_workspace_bytes(const int64_t* h_offsets, int64_t n_seg, size_t* bytes) {
+  if (!bytes) return WSR_ERR_INVALID;
+  int64_t mb = 0;
+  const int rc = validate_offsets(h_offsets, n_seg, &mb);
+  if (rc) return rc;
+  *bytes = big_bytes(mb);
+  return WSR_OK;
+}
+
+int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
+                     int32_t* saved_perm, uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!w || !out) return WSR_ERR_INVALID;
+  if ((saved_perm == nullptr) != (saved_mask == nullptr)) return WSR_ERR_INVALID;
+  if (!std::isfinite(lambda) || lambda < 0.0f) return WSR_ERR_INVALID;
+  int64_t mb = 0;
+  int rc = validate_offsets(h_offsets, n_seg, &mb);
+  if (rc) return rc;
+  const size_t need = big_bytes(mb);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t total = h_offsets[n_seg];
+  if (saved_mask) zero_words(saved_mask, ceil_div(total, 32), s);
+  for (int64_t seg = 0; seg < n_seg; ++seg) {
+    const int64_t start = h_offsets[seg];
+    const int64_t d = h_offsets[seg + 1] - start;
+    const int cls = size_class(d);
+    if (cls == kSkip) continue;
+    if (cls == kBig) {
+      rc = big_forward(w, out, start, d, nullptr, 0, lambda, saved_perm, saved_mask, ws, s);
+      if (rc) return rc;
+      continue;
+    }
+    SegArgs a{nullptr, nullptr, nullptr, lambda, start, (int)d, 0};
+    small_fwd(cls, 1, a, w, out, saved_perm, saved_mask, s);
+  }
+  return last_error();
+}
+
+int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_offsets, int64_t n_seg,
+                      const int32_t* saved_perm, const uint32_t* saved_mask, void* ws, size_t ws_bytes,
+                      void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!grad_out || !grad_w || !saved_perm || !saved_mask || grad_out == grad_w) return WSR_ERR_INVALID;
+  int64_t mb = 0;
+  int rc = validate_offsets(h_offsets, n_seg, &mb);
+  if (rc) return rc;
+  const size_t need = big_bytes(mb);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  for (int64_t seg = 0; seg < n_seg; ++seg) {
+    const int64_t start = h_offsets[seg];
+    const int64_t d = h_offsets[seg + 1] - start;
+    const int cls = size_class(d);
+    if (cls == kSkip) continue;
+    if (cls == kBig) {
+      rc = big_backward(grad_out, grad_w, start, d, saved_perm, saved_mask, ws, s);
+      if (rc) return rc;
+      continue;
+    }
+    SegArgs a{nullptr, nullptr, nullptr, 0.0f, start, (int)d, 0};
+    small_bwd(cls, 1, a, grad_out, grad_w, saved_perm, saved_mask, s);
+  }
+  return last_error();
+}
+
+int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan** plan) {
+  if (!plan || (flags & ~WSR_PLAN_AUTOTUNE)) return WSR_ERR_INVALID;
+  *plan = nullptr;
+  int64_t mb = 0;
+  int rc = validate_offsets(h_offsets, n_seg, &mb);
+  if (rc) return rc;
+  if (n_seg > INT32_MAX) return WSR_ERR_UNSUPPORTED;
+  wsr_plan* p = new wsr_plan();
+  p->n_seg = n_seg;
+  p->total = h_offsets[n_seg];
+  p->max_big = mb;
+  p->h_offsets.assign(h_offsets, h_offsets + n_seg + 1);
+  (void)hipGetDevice(&p->device);
+  // schedules: segments of each class, longest first (short tail of the launch)
+  std::vector<int32_t> cls_list[kNumSmall];
+  for (int64_t s = 0; s < n_seg; ++s) {
+    const int64_t d = h_offsets[s + 1] - h_offsets[s];
+    const int c = size_class(d);
+    if (c == kSkip) continue;
+    if (c == kBig)
+      p->big_segs.push_back((int32_t)s);
+    else
+      cls_list[c].push_back((int32_t)s);
+  }
+  std::vector<int32_t> sched;
+  for (int c = 0; c < kNumSmall; ++c) {
+    std::stable_sort(cls_list[c].begin(), cls_list[c].end(), [&](int32_t a, int32_t b) {
+      return (h_offsets[a + 1] - h_offsets[a]) > (h_offsets[b + 1] - h_offsets[b]);
+    });
+    p->sched_off[c] = (int64_t)sched.size();
+    p->sched_cnt[c] = (int64_t)cls_list[c].size();
+    sched.insert(sched.end(), cls_list[c].begin(), cls_list[c].end());
+  }
+  if (hipMalloc(&p->d_offsets, sizeof(int64_t) * (n_seg + 1)) != hipSuccess) {
+    delete p;
+    return WSR_ERR_HIP;
+  }
+  if (hipMemcpy(p->d_offsets, h_offsets, sizeof(int64_t) * (n_seg + 1), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(p->d_offsets);
+    delete p;
+    return WSR_ERR_HIP;
+  }
+  if (!sched.empty()) {
+    if (hipMalloc(&p->d_sched, sizeof(int32_t) * sched.size()) != hipSuccess ||
+        hipMemcpy(p->d_sched, sched.data(), sizeof(int32_t) * sched.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+      (void)hipFree(p->d_offsets);
+      if (p->d_sched) (void)hipFree(p->d_sched);
+      delete p;
+      return WSR_ERR_HIP;
+    }
+  }
+  *plan = p;
+  return WSR_OK;
+}
+
+int wsr_plan_destroy(wsr_plan* plan) {
+  if (!plan) return WSR_ERR_INVALID;
+  if (plan->d_offsets) (void)hipFree(plan->d_offsets);
+  if (plan->d_sched) (void)hipFree(plan->d_sched);
+  delete plan;
+  return WSR_OK;
+}
+
+int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
+  if (!plan || !bytes) return WSR_ERR_INVALID;
+  *bytes = big_bytes(plan->max_big);
+  return WSR_OK;
+}
+
+int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,
+                             float lambda_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws,
+                             size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!plan || !w || !out) return WSR_ERR_INVALID;
+  if ((saved_perm == nullptr) != (saved_mask == nullptr)) return WSR_ERR_INVALID;
+  if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
+  const size_t need = big_bytes(plan->max_big);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (saved_mask) zero_words(saved_mask, ceil_div(plan->total, 32), s);
+  for (int c = 0; c < kNumSmall; ++c) {
+    if (plan->sched_cnt[c] == 0) continue;
+    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};
+    small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
+  }
+  for (int32_t seg : plan->big_segs) {
+    const int64_t start = plan->h_offsets[seg];
+    const int64_t d = plan->h_offsets[seg + 1] - start;
+    const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s);
+    if (rc) return rc;
+  }
+  return last_error();
+}
+
+int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,
+                              const int32_t* saved_perm, const uint32_t* saved_mask, void* ws, size_t ws_bytes,
+                              void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!plan || !grad_out || !grad_w || !saved_perm || !saved_mask || grad_out == grad_w) return WSR_ERR_INVALID;
+  const size_t need = big_bytes(plan->max_big);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < kNumSmall; ++c) {
+    if (plan->sched_cnt[c] == 0) continue;
+    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], nullptr, 0.0f, 0, 0, 0};
+    small_bwd(c, (int)plan->sched_cnt[c], a, grad_out, grad_w, saved_perm, saved_mask, s);
+  }
+  for (int32_t seg : plan->big_segs) {
+    const int64_t start = plan->h_offsets[seg];
+    const int64_t d = plan->h_offsets[seg + 1] - start;
+    const int rc = big_backward(grad_out, grad_w, start, d, saved_perm, saved_mask, ws, s);
+    if (rc) return rc;
+  }
+  return last_error();
+}
+
+int wsr_trace_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  if (on && g_trace.ev.empty()) {
+    g_trace.ev.resize(2 * kTracePool);
+    for (auto& e : g_trace.ev)
+      if (hipEventCreate(&e) != hipSuccess) return WSR_ERR_HIP;
+  }
+  g_trace.on = on != 0;
+  return WSR_OK;
+}
+
+int wsr_trace_collect(int max_entries, char* names, int64_t* counts, double* total_ms, int* n_out) {
+  if (max_entries < 0 || (max_entries > 0 && (!names || !counts || !total_ms)) || !n_out) return WSR_ERR_INVALID;
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  std::vector<std::pair<const char*, std::pair<int64_t, double>>> agg;
+  int rc = WSR_OK;
+  for (const TraceRec& r : g_trace.recs) {
+    if (hipEventSynchronize(g_trace.ev[2 * r.ev + 1]) != hipSuccess) {
+      rc = WSR_ERR_HIP;
+      continue;
+    }
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, g_trace.ev[2 * r.ev], g_trace.ev[2 * r.ev + 1]) != hipSuccess) {
+      rc = WSR_ERR_HIP;
+      continue;
+    }
+    auto it = std::find_if(agg.begin(), agg.end(), [&](const auto& a) { return std::strcmp(a.first, r.name) == 0; });
+    if (it == agg.end()) {
+      agg.push_back({r.name, {1, (double)ms}});
+    } else {
+      it->second.first += 1;
+      it->second.second += ms;
+    }
+  }
+  g_trace.recs.clear();
+  int n = 0;
+  for (const auto& a : agg) {
+    if (n >= max_entries) break;
+    std::strncpy(names + 64 * n, a.first, 63);
+    names[64 * n + 63] = 0;
+    counts[n] = a.second.first;
+    total_ms[n] = a.second.second;
+    ++n;
+  }
+  *n_out = n;
+  return rc;
+}
+
+}  // extern "C"

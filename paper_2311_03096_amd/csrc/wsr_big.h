@@ -1,0 +1,57 @@
+// wsr_big.h -- geometry and kernels of the long-segment (device-wide) path.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wsr {
+
+constexpr int kRadixThreads = 256;  // one digit per thread in the scatter's digit scan
+constexpr int kRadixTile = 4096;    // keys per radix workgroup
+constexpr int kBigThreads = 256;
+constexpr int kBigE = 16;
+constexpr int kBigTile = kBigThreads * kBigE;  // ranks per hull tile
+constexpr int kMergeThreads = 256;
+constexpr int kMergeLevelsPerLaunch = 7;
+constexpr int kMergeGroupSmall = 1 << kMergeLevelsPerLaunch;  // first-stage groups
+constexpr int kMergeGroupMax = 1 << 14;                        // tiles of the longest segment
+constexpr int kMergeRecMax = 1 << (kMergeLevelsPerLaunch - 1);  // merges at a launch's first level
+static_assert((int64_t)kMergeGroupMax * kBigTile >= ((int64_t)1 << 26), "top merge group too small");
+static_assert(kRadixThreads == 256, "digit scan assumes one digit per thread");
+
+__global__ void k_radix_hist(const float* wsrc, const uint32_t* ksrc, int64_t n, int shift,
+                             uint32_t* hist, int ntiles, uint32_t* flags);
+__global__ void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals);
+__global__ void k_radix_scatter(const float* wsrc, const uint32_t* ksrc, const int32_t* vsrc,
+                                uint32_t* kdst, int32_t* vdst, int64_t n, int shift,
+                                const uint32_t* hist, const uint32_t* totals, int ntiles);
+__global__ void k_big_tile_hull(const uint32_t* skeys, int64_t d, const float* lam_arr, int seg_id,
+                                float lam_scalar, int32_t* vpos, double* vS, int32_t* hcnt,
+                                double* tsum);
+__global__ void k_big_tile_scan(const double* tsum, double* tileoff, const int32_t* hcnt,
+                                int32_t* lo, int32_t* hi, int ntiles, int64_t d,
+                                const float* lam_arr, int seg_id, float lam_scalar);
+template <int GMAX, int RMAX>
+__global__ void k_big_merge(int lvl_lo, int lvl_hi, int ntiles, const int32_t* vpos,
+                            const double* vS, const double* tileoff, int32_t* lo_g, int32_t* hi_g,
+                            int finalize, int32_t* prev_pos, double* prev_s, int32_t* next_pos,
+                            double* next_s);
+__global__ void k_big_apply(const uint32_t* skeys, const int32_t* perm, int64_t d,
+                            const float* lam_arr, int seg_id, float lam_scalar,
+                            const uint32_t* flags, const int32_t* vpos, const double* vS,
+                            const double* tileoff, const int32_t* lo_g, const int32_t* hi_g,
+                            const int32_t* prev_pos, const double* prev_s, const int32_t* next_pos,
+                            const double* next_s, float* out, uint32_t* mask_out,
+                            int64_t seg_start);
+__global__ void k_big_bwd_tile(const float* g, const int32_t* perm, const uint32_t* mask,
+                               int64_t d, int64_t seg_start, float* gsorted, double* tsum,
+                               int32_t* fpos, double* fG, int32_t* lpos, double* lG);
+__global__ void k_big_bwd_scan(const double* tsum, const int32_t* fpos, const double* fG,
+                               const int32_t* lpos, const double* lG, int ntiles, int64_t d,
+                               double* tileoff, int32_t* prevp, double* prevG, int32_t* nextp,
+                               double* nextG);
+__global__ void k_big_bwd_apply(const float* gsorted, const int32_t* perm, const uint32_t* mask,
+                                int64_t d, int64_t seg_start, const double* tileoff,
+                                const int32_t* prevp, const double* prevG, const int32_t* nextp,
+                                const double* nextG, float* gout);
+
+}  // namespace wsr

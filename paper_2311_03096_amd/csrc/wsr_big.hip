@@ -1,0 +1,846 @@
+// wsr_big.hip -- prox_{lam R} of one segment longer than a workgroup can hold (d > 8192).
+//
+// Pipeline (every step a kernel on the caller's stream, no host round trip):
+//   1. device-wide stable LSD radix sort of (u32 key, i32 index), 4 passes of 8 bits:
+//      per-tile digit histograms, per-digit scan over tiles, stable in-tile ranking + scatter
+//      (Alg. prox "sort"; the paper notes that sorting bounds the whole prox, Sec. 4);
+//   2. per tile of T ranks: centred FP64 prefix sums and the tile's lower hull in LDS
+//      (the same leaf + bridge machinery as the short-segment kernel);
+//   3. scan of tile sums (global S offsets);
+//   4. cross-tile merges: a binary tree over tiles; merging two solved neighbours changes only
+//      the chain at their junction, found with the Sec. 4.3 search (theorem search_collision,
+//      Alg. search_collisions Merge), so the tree has log2(#tiles) levels of O(log) searches.
+//      Each tile keeps the contiguous range ("own range") of its hull vertices that survives;
+//      a node's chain is its left end point followed by the own ranges of its tiles;
+//   5. per tile: previous / next surviving vertex, then values c + (S_b - S_a)/(b - a),
+//      scattered to the original order, plus cluster-start bits.
+// The backward pass gathers the upstream gradient in rank order, forms FP64 prefix sums and
+// averages over each saved cluster (clusters may span tiles).
+#include "wsr_device.h"
+#include "wsr_big.h"
+
+namespace wsr {
+
+// ------------------------------------------------------------------------------- radix sort
+
+// Per-tile histogram of one 8-bit digit.  Source is either the FP32 weights (first pass: keys
+// made on the fly, non-finite values flagged) or the u32 keys of the previous pass.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc, const uint32_t* ksrc,
+                                                             int64_t n, int shift, uint32_t* hist,
+                                                             int ntiles, uint32_t* flags) {
+  __shared__ uint32_t h[256];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < 256; j += kRadixThreads) h[j] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  int bad = 0;
+#pragma unroll 4
+  for (int r = 0; r < kRadixTile / kRadixThreads; ++r) {
+    const int64_t p = base + r * kRadixThreads + tid;
+    if (p < n) {
+      uint32_t key;
+      if (wsrc) {
+        const float f = wsrc[p];
+        bad |= !isfinite(f);
+        key = float_to_key(f);
+      } else {
+        key = ksrc[p];
+      }
+      atomicAdd(&h[(key >> shift) & 255u], 1u);
+    }
+  }
+  if (wsrc) {
+    if (__syncthreads_or(bad) && tid == 0) atomicOr(flags, 1u);
+  } else {
+    __syncthreads();
+  }
+  for (int j = tid; j < 256; j += kRadixThreads) hist[(int64_t)j * ntiles + blockIdx.x] = h[j];
+}
+
+// Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals) {
+  __shared__ int sh[256 / kWave + 1];
+  uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  const int chunk = (ntiles + 255) / 256;
+  const int lo = threadIdx.x * chunk;
+  const int hi = min(lo + chunk, ntiles);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += (int)row[i];
+  int total;
+  int run = block_excl_scan<256, int>(s, sh, &total);
+  for (int i = lo; i < hi; ++i) {
+    const int c = (int)row[i];
+    row[i] = (uint32_t)run;
+    run += c;
+  }
+  if (threadIdx.x == 0) totals[blockIdx.x] = (uint32_t)total;
+}
+
+// Stable scatter of one tile by one digit.  Items are ranked in wave-striped order
+// (p = wave*64*IPT + r*64 + lane), which is the tile's current order, so equal digits keep
+// their relative order.  Writes go out digit-run by digit-run.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const float* wsrc, const uint32_t* ksrc,
+                                                                const int32_t* vsrc, uint32_t* kdst,
+                                                                int32_t* vdst, int64_t n, int shift,
+                                                                const uint32_t* hist, const uint32_t* totals,
+                                                                int ntiles) {
+  constexpr int IPT = kRadixTile / kRadixThreads;
+  constexpr int NW = kRadixThreads / kWave;
+  __shared__ uint32_t skey[kRadixTile];
+  __shared__ int32_t sval[kRadixTile];
+  __shared__ uint32_t wcnt[NW][256];
+  __shared__ uint32_t tstart[256];
+  __shared__ uint32_t gofs[256];
+  __shared__ int ish[NW + 1];
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / kWave;
+  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const int nt = (int)min((int64_t)kRadixTile, n - base);
+  const int wbase = wv * kWave * IPT;
+  const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
+
+  uint32_t k[IPT];
+  int32_t v[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    k[r] = 0xFFFFFFFFu;
+    v[r] = 0;
+    if (r < nr && p < nt) {
+      if (wsrc) {
+        k[r] = float_to_key(wsrc[base + p]);
+        v[r] = (int32_t)(base + p);
+      } else {
+        k[r] = ksrc[base + p];
+        v[r] = vsrc[base + p];
+      }
+    }
+  }
+  for (int j = lane; j < 256; j += kWave) wcnt[wv][j] = 0u;
+  uint16_t rk[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    if (r < nr) {
+      const uint32_t dg = (k[r] >> shift) & 255u;
+      const uint64_t peers = match_digit8(dg);
+      const uint32_t b = wcnt[wv][dg];
+      const int nbelow = __popcll(peers & lanemask_lt());
+      if (nbelow == 0) wcnt[wv][dg] = b + (uint32_t)__popcll(peers);
+      rk[r] = (uint16_t)(b + nbelow);
+    }
+  }
+  __syncthreads();
+  // digit offsets inside the tile (thread tid owns digit tid; kRadixThreads == 256)
+  uint32_t run = 0;
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t c = wcnt[w][tid];
+    wcnt[w][tid] = run;
+    run += c;
+  }
+  int tot;
+  const int dstart = block_excl_scan<kRadixThreads, int>((int)run, ish, &tot);
+  for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
+  tstart[tid] = (uint32_t)dstart;
+  // global base of this digit = sum of all smaller digits' totals + this digit's tiles before us
+  int gt;
+  const int rowbase = block_excl_scan<kRadixThreads, int>((int)totals[tid], ish, &gt);
+  gofs[tid] = (uint32_t)rowbase + hist[(int64_t)tid * ntiles + blockIdx.x];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    if (r < nr) {
+      const uint32_t dg = (k[r] >> shift) & 255u;
+      const int np = (int)wcnt[wv][dg] + rk[r];
+      skey[np] = k[r];
+      sval[np] = v[r];
+    }
+  }
+  __syncthreads();
+  for (int s = tid; s < nt; s += kRadixThreads) {
+    const uint32_t key = skey[s];
+    const uint32_t dg = (key >> shift) & 255u;
+    const int64_t dst = (int64_t)gofs[dg] + (s - (int)tstart[dg]);
+    if (dst >= 0 && dst < n) {  // always true for consistent histograms; guards the scatter
+      kdst[dst] = key;
+      vdst[dst] = sval[s];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------- tile hulls
+
+struct TileSmem {
+  double S[kBigTile + 1];
+  uint16_t vert[kBigThreads * (kBigE + 1)];
+  int cnt[kBigThreads];
+  int mres[kBigThreads];
+  double dred[kBigThreads / kWave + 1];
+  double xtot;
+};
+
+__device__ __forceinline__ float seg_lambda(const float* lam_arr, int seg_id, float lam_scalar) {
+  return lam_arr ? lam_arr[seg_id] : lam_scalar;
+}
+
+// Local hull of tile t: points k0..k0+np (np = elements in the tile) with tile-relative sums
+//   S'_j = sum_{k0 <= i < k0+j} (x_i - c) + lam/(d-1) * [(k0+j)(d-k0-j) - k0(d-k0)]
+//        = X'_j + lam/(d-1) * j (d - 2 k0 - j),
+// i.e. S_{k0+j} minus the tile's offset S_{k0}.  Adding that offset back does not change the
+// hull; keeping it out keeps S' small (|S'| ~ tile size) so cluster values inside a tile are
+// differences of small numbers even when the segment's global prefix sums are ~1e7.
+__global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* skeys, int64_t d,
+                                                               const float* lam_arr, int seg_id,
+                                                               float lam_scalar, int32_t* vpos,
+                                                               double* vS, int32_t* hcnt, double* tsum) {
+  __shared__ TileSmem sm;
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  const int64_t k0 = (int64_t)t * kBigTile;
+  const int np = (int)min((int64_t)kBigTile, d - k0);
+  const double c = (double)key_to_float(skeys[d >> 1]);
+  const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
+  const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
+  const int j0 = tid * kBigE;
+  double xs[kBigE];
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    const int j = j0 + i;
+    xs[i] = j < np ? (double)key_to_float(skeys[k0 + j]) - c : 0.0;
+    lsum += xs[i];
+  }
+  double X = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    const int j = j0 + i;
+    if (j <= np) sm.S[j] = X + lamd * (double)j * ((double)(d - 2 * k0) - (double)j);
+    if (j == np) sm.xtot = X;
+    X += xs[i];
+  }
+  if (tid == kBigThreads - 1 && np == kBigTile) {
+    sm.S[kBigTile] = X + lamd * (double)kBigTile * ((double)(d - 2 * k0) - (double)kBigTile);
+    sm.xtot = X;
+  }
+  __syncthreads();
+  tile_hull<kBigThreads, kBigE>(sm.S, np, sm.vert, sm.cnt, sm.mres);
+  const int nv = sm.cnt[0];
+  const int64_t vb = (int64_t)t * (kBigTile + 1);
+  for (int i = tid; i < nv; i += kBigThreads) {
+    vpos[vb + i] = (int32_t)(k0 + sm.vert[i]);
+    vS[vb + i] = sm.S[sm.vert[i]];
+  }
+  if (tid == 0) {
+    hcnt[t] = nv;
+    tsum[t] = sm.xtot;
+  }
+}
+
+// Tile offsets S_{k0} = (exclusive scan of tile sums of x - c) + lam k0 (d-k0)/(d-1), and the
+// initial own ranges [1, hcnt-1].
+__global__ __launch_bounds__(1024) void k_big_tile_scan(const double* tsum, double* tileoff,
+                                                        const int32_t* hcnt, int32_t* lo, int32_t* hi,
+                                                        int ntiles, int64_t d, const float* lam_arr,
+                                                        int seg_id, float lam_scalar) {
+  const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
+  const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
+  __shared__ double sh[1024 / kWave + 1];
+  const int chunk = (ntiles + 1023) / 1024;
+  const int a = threadIdx.x * chunk;
+  const int b = min(a + chunk, ntiles);
+  double s = 0.0;
+  for (int i = a; i < b; ++i) s += tsum[i];
+  double run = block_excl_scan<1024, double>(s, sh, (double*)nullptr);
+  for (int i = a; i < b; ++i) {
+    const double k0 = (double)i * (double)kBigTile;
+    tileoff[i] = run + lamd * k0 * ((double)d - k0);
+    run += tsum[i];
+    lo[i] = 1;
+    hi[i] = hcnt[i] - 1;
+  }
+}
+
+// ------------------------------------------------------------------------------- cross-tile merges
+
+// Chain of a node = its left end point, then the own ranges of its tiles.  State in LDS:
+// lo16[t], cnt16[t] (own range start / length) and pre[t] (exclusive prefix of cnt16) for the
+// tiles of this workgroup's group; vertex data in global memory.
+struct MergeCtx {
+  const uint16_t* lo16;
+  const int* pre;
+  int gbase;  // first tile of the group
+  const int32_t* vpos;
+  const double* vS;
+  const double* tileoff;
+};
+
+// m-th vertex of the node covering group-relative tiles [t0, t1): tile and index in that tile.
+__device__ __forceinline__ void node_vertex(const MergeCtx& C, int t0, int t1, int m, int* tile, int* idx) {
+  if (m == 0) {
+    *tile = t0;
+    *idx = 0;
+    return;
+  }
+  const int mm = m - 1 + C.pre[t0];
+  int lo = t0, hi = t1;  // pre[lo] <= mm < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (C.pre[mid] <= mm)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  *tile = lo;
+  *idx = C.lo16[lo] + (mm - C.pre[lo]);
+}
+
+struct NodeChain {
+  const MergeCtx* C;
+  int t0, t1;
+  __device__ __forceinline__ void get(int m, int* p, double* s) const {
+    int tile, idx;
+    node_vertex(*C, t0, t1, m, &tile, &idx);
+    const int g = C->gbase + tile;
+    const int64_t at = (int64_t)g * (kBigTile + 1) + idx;
+    *p = C->vpos[at];
+    *s = C->vS[at] + C->tileoff[g];
+  }
+  __device__ __forceinline__ int pos(int m) const {
+    int p;
+    double s;
+    get(m, &p, &s);
+    return p;
+  }
+  __device__ __forceinline__ double s(int m) const {
+    int p;
+    double s_;
+    get(m, &p, &s_);
+    return s_;
+  }
+};
+
+// Levels [lvl_lo, lvl_hi] of the tile merge tree; workgroup g owns tiles [g*2^lvl_hi, ...).
+// LDS (static, sized for the largest group GMAX): pre[G+1], rec[5 * (G >> lvl_lo)], lo16[G],
+// cnt16[G] with G = 2^lvl_hi <= GMAX and G >> lvl_lo <= RMAX.
+// A merge record is {bridged, last left tile keeping vertices (t0-1: none), its last kept
+// index, first right tile keeping vertices, its first kept index}.
+// When finalize != 0 (single group holding every tile, last launch), also writes the previous
+// and next surviving vertex of every tile.
+template <int GMAX, int RMAX>
+__global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl_hi, int ntiles,
+                                                             const int32_t* vpos, const double* vS,
+                                                             const double* tileoff, int32_t* lo_g,
+                                                             int32_t* hi_g, int finalize, int32_t* prev_pos,
+                                                             double* prev_s, int32_t* next_pos,
+                                                             double* next_s) {
+  __shared__ int pre[GMAX + 1];
+  __shared__ int rec[5 * RMAX];
+  __shared__ uint16_t lo16[GMAX];
+  __shared__ uint16_t cnt16[GMAX];
+  __shared__ int ish[kMergeThreads / kWave + 1];
+  const int G = 1 << lvl_hi;
+  const int gbase = blockIdx.x * G;
+  const int gn = min(G, ntiles - gbase);
+  const int tid = threadIdx.x;
+
+  auto rebuild_prefix = [&]() {
+    const int chunk = (gn + kMergeThreads - 1) / kMergeThreads;
+    const int a = tid * chunk;
+    const int b = min(a + chunk, gn);
+    int s = 0;
+    for (int i = a; i < b; ++i) s += cnt16[i];
+    int total;
+    int run = block_excl_scan<kMergeThreads, int>(s, ish, &total);
+    for (int i = a; i < b; ++i) {
+      pre[i] = run;
+      run += cnt16[i];
+    }
+    if (tid == 0) pre[gn] = total;
+    __syncthreads();
+  };
+
+  for (int i = tid; i < gn; i += kMergeThreads) {
+    const int l = lo_g[gbase + i];
+    const int h = hi_g[gbase + i];
+    lo16[i] = (uint16_t)l;
+    cnt16[i] = (uint16_t)max(0, h - l + 1);
+  }
+  __syncthreads();
+  rebuild_prefix();
+  MergeCtx C{lo16, pre, gbase, vpos, vS, tileoff};
+
+  for (int lvl = lvl_lo; lvl <= lvl_hi; ++lvl) {
+    const int size = 1 << lvl;
+    const int half = size >> 1;
+    const int nm = (gn + size - 1) >> lvl;
+    for (int m = tid; m < nm; m += kMergeThreads) {
+      const int t0 = m << lvl;
+      const int tm = t0 + half;
+      const int t1 = min(t0 + size, gn);
+      int* r = rec + 5 * m;
+      r[0] = 0;
+      if (tm < gn) {
+        NodeChain L{&C, t0, tm};
+        NodeChain R{&C, tm, t1};
+        const int p = pre[tm] - pre[t0];  // left chain: end point + own vertices; last index p
+        const int q = pre[t1] - pre[tm];
+        int istar, jstar;
+        bridge(L, p, R, q, &istar, &jstar);
+        if (!(istar == p && jstar == 1)) {
+          int ti = t0 - 1, ii = 0, tj, jj;
+          if (istar > 0) node_vertex(C, t0, tm, istar, &ti, &ii);
+          node_vertex(C, tm, t1, jstar, &tj, &jj);
+          r[0] = 1;
+          r[1] = ti;
+          r[2] = ii;
+          r[3] = tj;
+          r[4] = jj;
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < gn; i += kMergeThreads) {
+      const int m = i >> lvl;
+      const int* r = rec + 5 * m;
+      if (!r[0]) continue;
+      const int tm = (m << lvl) + half;
+      if (i < tm) {
+        if (i > r[1])
+          cnt16[i] = 0;
+        else if (i == r[1])
+          cnt16[i] = (uint16_t)(r[2] - (int)lo16[i] + 1);
+      } else {
+        if (i < r[3]) {
+          cnt16[i] = 0;
+        } else if (i == r[3]) {
+          const int oldend = (int)lo16[i] + (int)cnt16[i];
+          lo16[i] = (uint16_t)r[4];
+          cnt16[i] = (uint16_t)(oldend - r[4]);
+        }
+      }
+    }
+    __syncthreads();
+    rebuild_prefix();
+  }
+  for (int i = tid; i < gn; i += kMergeThreads) {
+    lo_g[gbase + i] = lo16[i];
+    hi_g[gbase + i] = (int)lo16[i] + (int)cnt16[i] - 1;
+  }
+  if (!finalize) return;
+  // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t
+  const int nglob = 1 + pre[gn];
+  auto gvertex = [&](int m, int* p, double* s) {
+    int tile, idx;
+    node_vertex(C, 0, gn, m, &tile, &idx);
+    const int64_t at = (int64_t)tile * (kBigTile + 1) + idx;
+    *p = vpos[at];
+    *s = vS[at] + tileoff[tile];
+  };
+  for (int t = tid; t < gn; t += kMergeThreads) {
+    int p;
+    double s;
+    gvertex(pre[t], &p, &s);
+    prev_pos[t] = p;
+    prev_s[t] = s;
+    const int nx = pre[t + 1] + 1;
+    if (nx < nglob) {
+      gvertex(nx, &p, &s);
+      next_pos[t] = p;
+      next_s[t] = s;
+    } else {
+      next_pos[t] = -1;
+      next_s[t] = 0.0;
+    }
+  }
+}
+
+template __global__ void k_big_merge<kMergeGroupSmall, kMergeRecMax>(int, int, int, const int32_t*,
+                                                                      const double*, const double*,
+                                                                      int32_t*, int32_t*, int, int32_t*,
+                                                                      double*, int32_t*, double*);
+template __global__ void k_big_merge<kMergeGroupMax, kMergeRecMax>(int, int, int, const int32_t*,
+                                                                    const double*, const double*,
+                                                                    int32_t*, int32_t*, int, int32_t*,
+                                                                    double*, int32_t*, double*);
+
+// ------------------------------------------------------------------------------- apply
+
+struct ApplySmem {
+  int32_t lp[kBigTile + 2];
+  double ls[kBigTile + 2];   // global S at the vertex
+  double lsl[kBigTile + 2];  // tile-relative S' (valid where lloc)
+  uint8_t lloc[kBigTile + 2];
+  uint32_t lmask[kBigTile / 32 + 2];
+  int n;
+};
+
+// Values for the ranks of tile t, scattered to the original order; cluster-start bits.
+__global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys, const int32_t* perm,
+                                                           int64_t d, const float* lam_arr, int seg_id,
+                                                           float lam_scalar, const uint32_t* flags,
+                                                           const int32_t* vpos, const double* vS,
+                                                           const double* tileoff, const int32_t* lo_g,
+                                                           const int32_t* hi_g, const int32_t* prev_pos,
+                                                           const double* prev_s, const int32_t* next_pos,
+                                                           const double* next_s, float* out,
+                                                           uint32_t* mask_out, int64_t seg_start) {
+  __shared__ ApplySmem sm;
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  const int64_t k0 = (int64_t)t * kBigTile;
+  const int np = (int)min((int64_t)kBigTile, d - k0);
+  const int off = (int)((seg_start + k0) & 31);
+  const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
+  const bool nonfinite = (flags[0] & 1u) != 0;
+  const bool identity = nonfinite || !(lam > 0.0f);
+  for (int j = tid; j < kBigTile / 32 + 2; j += kBigThreads) sm.lmask[j] = 0u;
+  if (identity) {
+    __syncthreads();
+    for (int j = tid; j < np; j += kBigThreads) {
+      const float x = key_to_float(skeys[k0 + j]);
+      const int64_t pl = min((int64_t)max(perm[k0 + j], 0), d - 1);
+      out[seg_start + pl] = nonfinite ? __builtin_nanf("") : x;
+      atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
+    }
+    __syncthreads();
+    if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
+    return;
+  }
+  const double c = (double)key_to_float(skeys[d >> 1]);
+  const int lo = lo_g[t];
+  const int own = max(0, hi_g[t] - lo + 1);
+  const double toff = tileoff[t];
+  const int64_t vb = (int64_t)t * (kBigTile + 1);
+  if (tid == 0) {
+    sm.lp[0] = prev_pos[t];
+    sm.ls[0] = prev_s[t];
+    sm.lsl[0] = 0.0;  // the tile's first point has S' = 0
+    sm.lloc[0] = prev_pos[t] == k0;
+    const int nx = next_pos[t];
+    sm.n = 1 + own + (nx >= 0 ? 1 : 0);
+    if (nx >= 0) {
+      sm.lp[1 + own] = nx;
+      sm.ls[1 + own] = next_s[t];
+      sm.lsl[1 + own] = 0.0;
+      sm.lloc[1 + own] = 0;
+    }
+  }
+  for (int i = tid; i < own; i += kBigThreads) {
+    const double sl = vS[vb + lo + i];
+    sm.lp[1 + i] = vpos[vb + lo + i];
+    sm.ls[1 + i] = sl + toff;
+    sm.lsl[1 + i] = sl;
+    sm.lloc[1 + i] = 1;
+  }
+  __syncthreads();
+  const int n = sm.n;
+  // cluster starts inside the tile
+  for (int i = tid; i < n; i += kBigThreads) {
+    const int64_t p = sm.lp[i];
+    if (p >= k0 && p < k0 + np) {
+      const int j = (int)(p - k0);
+      atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
+    }
+  }
+  // values, blocked ranks
+  const int j0 = tid * kBigE;
+  if (j0 < np) {
+    const int64_t kk0 = k0 + j0;
+    int a = 0, b = n - 1;  // lp[a] <= kk0 < lp[b]
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (sm.lp[mid] <= kk0)
+        a = mid;
+      else
+        b = mid;
+    }
+    // edge value: tile-relative sums when both ends lie in this tile, global sums for bridges
+    auto edge_value = [&](int e) -> float {
+      const double len = (double)(sm.lp[e + 1] - sm.lp[e]);
+      const double dS = (sm.lloc[e] && sm.lloc[e + 1]) ? sm.lsl[e + 1] - sm.lsl[e] : sm.ls[e + 1] - sm.ls[e];
+      return (float)(c + dS / len);
+    };
+    int cur = a;
+    int64_t nxt = sm.lp[cur + 1];
+    float val = edge_value(cur);
+    const int j1 = min(j0 + kBigE, np);
+    for (int j = j0; j < j1; ++j) {
+      const int64_t kk = k0 + j;
+      while (kk >= nxt && cur + 2 < n) {
+        ++cur;
+        nxt = sm.lp[cur + 1];
+        val = edge_value(cur);
+      }
+      const int64_t pl = min((int64_t)max(perm[kk], 0), d - 1);
+      out[seg_start + pl] = val;
+    }
+  }
+  __syncthreads();
+  if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
+}
+
+// ------------------------------------------------------------------------------- backward
+
+struct BwdTileSmem {
+  double dred[kBigThreads / kWave + 1];
+  int ired[kBigThreads / kWave + 1];
+  int fmin, lmax;
+  double fG, lG;
+};
+
+// Gather the cotangent in rank order (kept for the apply pass), tile sums, first / last cluster
+// start of the tile with the local prefix at it.
+__global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, const int32_t* perm,
+                                                              const uint32_t* mask, int64_t d,
+                                                              int64_t seg_start, float* gsorted,
+                                                              double* tsum, int32_t* fpos, double* fG,
+                                                              int32_t* lpos, double* lG) {
+  __shared__ BwdTileSmem sm;
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  const int64_t k0 = (int64_t)t * kBigTile;
+  const int np = (int)min((int64_t)kBigTile, d - k0);
+  const int j0 = tid * kBigE;
+  float gk[kBigE];
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    const int j = j0 + i;
+    gk[i] = 0.0f;
+    if (j < np) {
+      int pl = perm[k0 + j];
+      pl = (int)min((int64_t)max(pl, 0), d - 1);
+      gk[i] = g[seg_start + pl];
+      gsorted[k0 + j] = gk[i];
+      lsum += (double)gk[i];
+    }
+  }
+  if (tid == 0) {
+    sm.fmin = 0x7FFFFFFF;
+    sm.lmax = -1;
+  }
+  double total;
+  double G = block_excl_scan<kBigThreads, double>(lsum, sm.dred, &total);
+  int myf = 0x7FFFFFFF, myl = -1;
+  double Gf = 0.0, Gl = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    const int j = j0 + i;
+    if (j < np) {
+      const int64_t pf = seg_start + k0 + j;
+      const bool st = (k0 + j == 0) || ((mask[pf >> 5] >> (pf & 31)) & 1u);
+      if (st) {
+        if (j < myf) {
+          myf = j;
+          Gf = G;
+        }
+        myl = j;
+        Gl = G;
+      }
+      G += (double)gk[i];
+    }
+  }
+  atomicMin(&sm.fmin, myf);
+  atomicMax(&sm.lmax, myl);
+  __syncthreads();
+  if (myf != 0x7FFFFFFF && myf == sm.fmin) sm.fG = Gf;
+  if (myl >= 0 && myl == sm.lmax) sm.lG = Gl;
+  __syncthreads();
+  if (tid == 0) {
+    tsum[t] = total;
+    fpos[t] = sm.fmin == 0x7FFFFFFF ? -1 : (int32_t)(k0 + sm.fmin);
+    fG[t] = sm.fmin == 0x7FFFFFFF ? 0.0 : sm.fG;
+    lpos[t] = sm.lmax < 0 ? -1 : (int32_t)(k0 + sm.lmax);
+    lG[t] = sm.lmax < 0 ? 0.0 : sm.lG;
+  }
+}
+
+// One workgroup: tile offsets of G, and for every tile the last cluster start before it and the
+// first cluster start after its last local start (with global G values).  Carries are a
+// "last valid entry" scan: per-thread chunk summaries, a serial pass over 1024 summaries, then
+// each thread walks its chunk.
+__global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const int32_t* fpos,
+                                                       const double* fG, const int32_t* lpos,
+                                                       const double* lG, int ntiles, int64_t d,
+                                                       double* tileoff, int32_t* prevp, double* prevG,
+                                                       int32_t* nextp, double* nextG) {
+  __shared__ double sh[1024 / kWave + 1];
+  __shared__ int cpos[1024];
+  __shared__ double cval[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (ntiles + 1023) / 1024;
+  const int a = tid * chunk;
+  const int b = min(a + chunk, ntiles);
+  double s = 0.0;
+  for (int i = a; i < b; ++i) s += tsum[i];
+  double total;
+  double run = block_excl_scan<1024, double>(s, sh, &total);
+  for (int i = a; i < b; ++i) {
+    tileoff[i] = run;
+    run += tsum[i];
+  }
+  // forward: last start in my chunk
+  int mp = -1;
+  double mg = 0.0;
+  for (int i = a; i < b; ++i)
+    if (lpos[i] >= 0) {
+      mp = lpos[i];
+      mg = tileoff[i] + lG[i];
+    }
+  cpos[tid] = mp;
+  cval[tid] = mg;
+  __syncthreads();
+  if (tid == 0) {
+    int cp = 0;  // rank 0 always starts a cluster
+    double cg = 0.0;
+    for (int i = 0; i < 1024; ++i) {
+      const int p = cpos[i];
+      const double g = cval[i];
+      cpos[i] = cp;
+      cval[i] = cg;
+      if (p >= 0) {
+        cp = p;
+        cg = g;
+      }
+    }
+  }
+  __syncthreads();
+  int cp = cpos[tid];
+  double cg = cval[tid];
+  for (int i = a; i < b; ++i) {
+    prevp[i] = cp;
+    prevG[i] = cg;
+    if (lpos[i] >= 0) {
+      cp = lpos[i];
+      cg = tileoff[i] + lG[i];
+    }
+  }
+  __syncthreads();
+  // backward: first start in my chunk
+  mp = -1;
+  mg = 0.0;
+  for (int i = b - 1; i >= a; --i)
+    if (fpos[i] >= 0) {
+      mp = fpos[i];
+      mg = tileoff[i] + fG[i];
+    }
+  cpos[tid] = mp;
+  cval[tid] = mg;
+  __syncthreads();
+  if (tid == 0) {
+    int np_ = (int)d;
+    double ng = total;
+    for (int i = 1023; i >= 0; --i) {
+      const int p = cpos[i];
+      const double g = cval[i];
+      cpos[i] = np_;
+      cval[i] = ng;
+      if (p >= 0) {
+        np_ = p;
+        ng = g;
+      }
+    }
+  }
+  __syncthreads();
+  int np_ = cpos[tid];
+  double ng = cval[tid];
+  for (int i = b - 1; i >= a; --i) {
+    nextp[i] = np_;
+    nextG[i] = ng;
+    if (fpos[i] >= 0) {
+      np_ = fpos[i];
+      ng = tileoff[i] + fG[i];
+    }
+  }
+}
+
+struct BwdApplySmem {
+  int32_t lp[kBigTile + 2];
+  double lg[kBigTile + 2];
+  double dred[kBigThreads / kWave + 1];
+  int ired[kBigThreads / kWave + 1];
+  int n;
+};
+
+__global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsorted, const int32_t* perm,
+                                                               const uint32_t* mask, int64_t d,
+                                                               int64_t seg_start, const double* tileoff,
+                                                               const int32_t* prevp, const double* prevG,
+                                                               const int32_t* nextp, const double* nextG,
+                                                               float* gout) {
+  __shared__ BwdApplySmem sm;
+  const int tid = threadIdx.x;
+  const int t = blockIdx.x;
+  const int64_t k0 = (int64_t)t * kBigTile;
+  const int np = (int)min((int64_t)kBigTile, d - k0);
+  const int j0 = tid * kBigE;
+  float gk[kBigE];
+  double lsum = 0.0;
+  int lst = 0;
+  bool st[kBigE];
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    const int j = j0 + i;
+    gk[i] = 0.0f;
+    st[i] = false;
+    if (j < np) {
+      gk[i] = gsorted[k0 + j];
+      lsum += (double)gk[i];
+      const int64_t pf = seg_start + k0 + j;
+      st[i] = (k0 + j == 0) || ((mask[pf >> 5] >> (pf & 31)) & 1u);
+      lst += st[i];
+    }
+  }
+  int nst;
+  const int cb = block_excl_scan<kBigThreads, int>(lst, sm.ired, &nst);
+  double G = tileoff[t] + block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
+  // list: [previous start] + local starts + [next start after the tile's starts]
+  int ci = 1 + cb;
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    const int j = j0 + i;
+    if (j < np && st[i]) {
+      sm.lp[ci] = (int32_t)(k0 + j);
+      sm.lg[ci] = G;
+      ++ci;
+    }
+    if (j < np) G += (double)gk[i];
+  }
+  if (tid == 0) {
+    sm.lp[0] = prevp[t];
+    sm.lg[0] = prevG[t];
+    sm.lp[1 + nst] = nextp[t];
+    sm.lg[1 + nst] = nextG[t];
+    sm.n = nst + 2;
+  }
+  __syncthreads();
+  const int n = sm.n;
+  if (j0 < np) {
+    const int64_t kk0 = k0 + j0;
+    int a = 0, b = n - 1;  // lp[a] <= kk0 < lp[b]
+    while (b - a > 1) {
+      const int mid = (a + b) >> 1;
+      if (sm.lp[mid] <= kk0)
+        a = mid;
+      else
+        b = mid;
+    }
+    int cur = a;
+    int64_t nxt = sm.lp[cur + 1];
+    float val = (float)((sm.lg[cur + 1] - sm.lg[cur]) / (double)(nxt - sm.lp[cur]));
+    const int j1 = min(j0 + kBigE, np);
+    for (int j = j0; j < j1; ++j) {
+      const int64_t kk = k0 + j;
+      while (kk >= nxt && cur + 2 < n) {
+        ++cur;
+        nxt = sm.lp[cur + 1];
+        val = (float)((sm.lg[cur + 1] - sm.lg[cur]) / (double)(nxt - sm.lp[cur]));
+      }
+      int pl = perm[kk];
+      pl = (int)min((int64_t)max(pl, 0), d - 1);
+      gout[seg_start + pl] = val;
+    }
+  }
+}
+
+}  // namespace wsr

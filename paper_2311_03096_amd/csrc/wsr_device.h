@@ -1,0 +1,301 @@
+// wsr_device.h -- device building blocks shared by the gfx950 kernels.
+//
+// Geometry used throughout.  For a segment of d weights sorted ascending (x_0 <= ... <= x_{d-1}),
+// the particle of rank k gets the velocity v_k = lam (d-1-2k)/(d-1) (Alg. prox, shift line;
+// Sec. 2 eq. hyperplane) and the destination y_k = x_k + v_k.  With the centred prefix sums
+//     S_k = sum_{j<k} (x_j - c) + sum_{j<k} v_j = X_k + lam k (d-k)/(d-1),   k = 0..d,
+// the sticky-particle collisions of Sec. 3/4 (pool adjacent violators on y, merging on >=)
+// produce exactly the edges of the lower convex hull of the points P_k = (k, S_k) with collinear
+// points dropped: the cluster of ranks [a, b) is the hull edge P_a -> P_b and its value is
+//     c + (S_b - S_a) / (b - a)                        (avg y of the cluster, Sec. 4.2 fact 3).
+// The closed form of sum v follows from the rank shift; c is any constant (the sorted median is
+// used) and only makes the FP64 sums short.
+//
+// Hull building blocks:
+//   - below(a, b, c): point b strictly below the segment a -> c.  "not below" is the paper's
+//     imminent-collision test y-avg(left) >= y-avg(right) (Sec. 4.1) on blocks [a,b) and [b,c).
+//   - leaf hulls: each thread runs the sequential stack algorithm on E consecutive ranks.
+//   - bridge(L, R): merging two solved neighbours changes one chain at their junction; the
+//     merged cluster [i*, j*] is found by searching for the first left vertex whose rightmost
+//     collision crosses the junction (Sec. 4.3 theorem search_collision; Alg. search_collisions
+//     Merge and RightmostCollision), with galloping searches so that short bridges cost O(1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wsr {
+
+constexpr int kWave = 64;
+
+// Order-preserving map FP32 -> u32 (IEEE total order on non-NaN values; -0 < +0).
+__device__ __forceinline__ uint32_t float_to_key(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_to_float(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __uint_as_float(u);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Lanes of the wave holding the same 8-bit digit (all 64 lanes must be active).
+__device__ __forceinline__ uint64_t match_digit8(uint32_t dg) {
+  uint64_t peers = ~0ull;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int bit = (dg >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    peers &= bit ? m : ~m;
+  }
+  return peers;
+}
+
+// Wave-inclusive scans (Hillis-Steele over the 64 lanes, App. A.2).
+__device__ __forceinline__ double wave_incl_scan(double v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    double t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(v, o, kWave);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Block-wide exclusive scan; sh must hold NT/64 + 1 values.  Every thread of the block must call.
+// Summation order is fixed, so results are deterministic.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  T inc = wave_incl_scan(v);
+  T exc = __shfl_up(inc, 1, kWave);
+  if (lane == 0) exc = T(0);
+  if (lane == kWave - 1) sh[wv] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = T(0);
+    for (int i = 0; i < NW; ++i) {
+      T t = sh[i];
+      sh[i] = run;
+      run += t;
+    }
+    sh[NW] = run;
+  }
+  __syncthreads();
+  T res = sh[wv] + exc;
+  if (total) *total = sh[NW];
+  __syncthreads();
+  return res;
+}
+
+// Point b strictly below the segment a -> c (a < b < c); positions are ranks, s* are S values.
+__device__ __forceinline__ bool below(int a, double sa, int b, double sb, int c, double sc) {
+  return (sb - sa) * (double)(c - b) < (sc - sb) * (double)(b - a);
+}
+
+// Sequential stack hull of points lo..hi (inclusive) of S; writes vertex ranks to st, returns count.
+__device__ __forceinline__ int leaf_hull(const double* S, int lo, int hi, uint16_t* st) {
+  int n = 0;
+  int p0 = 0, p1 = 0;  // top and second-from-top ranks
+  double s0 = 0.0, s1 = 0.0;
+  for (int k = lo; k <= hi; ++k) {
+    const double sk = S[k];
+    while (n >= 2 && !below(p1, s1, p0, s0, k, sk)) {
+      --n;  // collision: the top block sticks to the incoming one
+      p0 = p1;
+      s0 = s1;
+      if (n >= 2) {
+        p1 = st[n - 2];
+        s1 = S[p1];
+      }
+    }
+    st[n++] = (uint16_t)k;
+    p1 = p0;
+    s1 = s0;
+    p0 = k;
+    s0 = sk;
+  }
+  return n;
+}
+
+// Generic vertex accessor interface for bridge(): V.pos(i), V.s(i) for the left chain L (indices
+// 0..p) and the right chain R (0..q), with L(p) == R(0) the shared junction point.
+// Returns the merged chain as L[0..istar] ++ R[jstar..q].  No-bridge result: istar = p, jstar = 1.
+template <typename LV, typename RV>
+__device__ void bridge(const LV& L, int p, const RV& R, int q, int* istar, int* jstar) {
+  if (q <= 0) {  // right chain is a single point: nothing to merge
+    *istar = p;
+    *jstar = 1;
+    return;
+  }
+  if (p <= 0) {  // left chain is a single point
+    *istar = 0;
+    *jstar = 1;
+    return;
+  }
+  // Tangent from the point (qa, qs) to R, excluding R(0): first j >= 1 with R(j) strictly below
+  // the segment Q -> R(j+1) (j = q when none): the rightmost collision of Q inside R.
+  auto tangent = [&](int qa, double qs) -> int {
+    auto f = [&](int j) -> bool {
+      if (j >= q) return true;
+      return below(qa, qs, R.pos(j), R.s(j), R.pos(j + 1), R.s(j + 1));
+    };
+    int lo = 0, hi = 1, step = 1;
+    while (!f(hi)) {
+      lo = hi;
+      step <<= 1;
+      hi = min(lo + step, q);
+    }
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (f(mid))
+        hi = mid;
+      else
+        lo = mid;
+    }
+    return hi;
+  };
+  // g(i): the rightmost collision of left vertex i crosses the junction.
+  auto g = [&](int i, int* jout) -> bool {
+    const int li = L.pos(i);
+    const double si = L.s(i);
+    const int j = tangent(li, si);
+    *jout = j;
+    return !below(li, si, L.pos(i + 1), L.s(i + 1), R.pos(j), R.s(j));
+  };
+  // junction survives iff L(p) is strictly below L(p-1) -> R(1)
+  if (below(L.pos(p - 1), L.s(p - 1), L.pos(p), L.s(p), R.pos(1), R.s(1))) {
+    *istar = p;
+    *jstar = 1;
+    return;
+  }
+  int jhi = 1;
+  if (!g(p - 1, &jhi)) {  // only reachable through rounding: keep the junction
+    *istar = p;
+    *jstar = 1;
+    return;
+  }
+  int hi = p - 1, lo = hi - 1, step = 1;
+  while (lo >= 0) {
+    int j;
+    if (!g(lo, &j)) break;
+    hi = lo;
+    jhi = j;
+    step <<= 1;
+    lo = hi - step;
+  }
+  if (lo < 0) lo = -1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    int j;
+    if (g(mid, &j)) {
+      hi = mid;
+      jhi = j;
+    } else {
+      lo = mid;
+    }
+  }
+  *istar = hi;
+  *jstar = jhi;
+}
+
+// Chains stored as rank lists in LDS, S read from LDS.
+struct LdsChain {
+  const uint16_t* v;
+  const double* S;
+  __device__ __forceinline__ int pos(int i) const { return v[i]; }
+  __device__ __forceinline__ double s(int i) const { return S[v[i]]; }
+};
+
+// Lower hull (collinear points dropped) of the points 0..d of S, computed by NT threads with
+// E ranks per leaf.  vert must hold NT*(E+1) entries, cnt NT ints, mres NT ints.  On return
+// vert[0..cnt[0]) are the hull vertices (0 and d included).  All threads of the block must call;
+// requires 1 <= d <= NT*E.
+template <int NT, int E>
+__device__ void tile_hull(const double* S, int d, uint16_t* vert, int* cnt, int* mres) {
+  constexpr int CP = E / 2 + 1;  // copy entries per thread per level
+  const int t = threadIdx.x;
+  const int nleaf = (d + E - 1) / E;
+  if (t < nleaf) {
+    const int a = t * E;
+    const int b = min(a + E, d);
+    cnt[t] = leaf_hull(S, a, b, vert + t * (E + 1));
+  }
+  __syncthreads();
+  for (int lvl = 1; (1 << (lvl - 1)) < nleaf; ++lvl) {
+    const int half = 1 << (lvl - 1);
+    const int nmerge = (nleaf + (1 << lvl) - 1) >> lvl;
+    if (t < nmerge) {
+      const int lleaf = t << lvl;
+      const int rleaf = lleaf + half;
+      int istar = -1, jstar = -1;
+      if (rleaf < nleaf) {
+        LdsChain L{vert + lleaf * (E + 1), S};
+        LdsChain R{vert + rleaf * (E + 1), S};
+        bridge(L, cnt[lleaf] - 1, R, cnt[rleaf] - 1, &istar, &jstar);
+      }
+      mres[2 * t] = istar;
+      mres[2 * t + 1] = jstar;
+    }
+    __syncthreads();
+    // move the surviving right part next to the surviving left part (read all, then write)
+    const int m = t >> lvl;
+    const int s = t & ((1 << lvl) - 1);
+    int istar = -1, jstar = 0, len = 0;
+    if (m < nmerge) {
+      istar = mres[2 * m];
+      jstar = mres[2 * m + 1];
+      if (istar >= 0) len = cnt[(m << lvl) + half] - jstar;
+    }
+    const int lbase = (m << lvl) * (E + 1);
+    const int rbase = lbase + half * (E + 1);
+    uint16_t tmp[CP];
+#pragma unroll
+    for (int r = 0; r < CP; ++r) {
+      const int e = s + (r << lvl);
+      if (e < len) tmp[r] = vert[rbase + jstar + e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CP; ++r) {
+      const int e = s + (r << lvl);
+      if (e < len) vert[lbase + istar + 1 + e] = tmp[r];
+    }
+    if (s == 0 && istar >= 0) cnt[m << lvl] = istar + 1 + len;
+    __syncthreads();
+  }
+}
+
+// Write the local cluster-start bits of one segment (or tile) to the global bit mask.
+// lmask bit j <-> flat position (base & ~31) + j.  Words shared with a neighbour are OR-ed
+// atomically (the global mask is zeroed before the forward pass); owned words are stored.
+template <int NT>
+__device__ __forceinline__ void store_mask_words(uint32_t* mask, int64_t base, int n,
+                                                 const uint32_t* lmask) {
+  const int off = (int)(base & 31);
+  const int nwords = (off + n + 31) >> 5;
+  const int64_t g0 = base >> 5;
+  const bool first_partial = off != 0;
+  const bool last_partial = ((off + n) & 31) != 0;
+  for (int j = threadIdx.x; j < nwords; j += NT) {
+    const uint32_t v = lmask[j];
+    if ((j == 0 && first_partial) || (j == nwords - 1 && last_partial))
+      atomicOr(&mask[g0 + j], v);
+    else
+      mask[g0 + j] = v;
+  }
+}
+
+}  // namespace wsr

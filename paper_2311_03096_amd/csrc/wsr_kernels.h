@@ -1,0 +1,29 @@
+// wsr_kernels.h -- kernel entry points and launch descriptors shared by the host code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wsr {
+
+// Which segment a workgroup of the short-segment kernels solves.  Batched launches give a
+// schedule (sched[blockIdx.x] = segment id) over device offsets; single-segment launches give
+// (start, d) directly.  lambda comes from lam_arr[segment] when lam_arr != nullptr.
+struct SegArgs {
+  const int64_t* offsets;
+  const int32_t* sched;
+  const float* lam_arr;
+  float lam_scalar;
+  int64_t start;
+  int d;
+  int seg_id;
+};
+
+template <int TMAX, int NT>
+__global__ void k_prox_fwd_small(SegArgs args, const float* w, float* out, int32_t* perm_out,
+                                 uint32_t* mask_out);
+template <int TMAX, int NT>
+__global__ void k_prox_bwd_small(SegArgs args, const float* gin, float* gout, const int32_t* perm_in,
+                                 const uint32_t* mask_in);
+__global__ void k_zero_u32(uint32_t* p, int64_t n);
+
+}  // namespace wsr

@@ -1,0 +1,126 @@
+"""Torch-facing wrappers over the C ABI: autograd prox and a batched per-step prox.
+
+Torch supplies device memory and the stream; every step of the prox runs in the library's
+HIP kernels.  Buffers for the saved state and the workspace are allocated here (the library
+itself never allocates during a compute call).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _mask_words(n):
+    return (n + 31) // 32
+
+
+def _workspace(nbytes, device):
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _check_f32(t, name):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError("%s must be a contiguous float32 tensor on the GPU" % name)
+
+
+class ProxFunction(torch.autograd.Function):
+    """u = prox_{lam R}(w) per segment; backward averages the cotangent within clusters."""
+
+    @staticmethod
+    def forward(ctx, w, lam, offsets):
+        _check_f32(w, "w")
+        n = w.numel()
+        out = torch.empty_like(w)
+        perm = torch.empty(n, dtype=torch.int32, device=w.device)
+        mask = torch.empty(_mask_words(n), dtype=torch.int32, device=w.device)
+        ws = _workspace(_lib.wsr_workspace_bytes(offsets), w.device)
+        _lib.wsr_prox_forward(w, out, offsets, lam, perm, mask, ws)
+        ctx.save_for_backward(perm, mask)
+        ctx.offsets = offsets
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        perm, mask = ctx.saved_tensors
+        g = g.contiguous()
+        gw = torch.empty_like(g)
+        ws = _workspace(_lib.wsr_workspace_bytes(ctx.offsets), g.device)
+        _lib.wsr_prox_backward(g, gw, ctx.offsets, perm, mask, ws)
+        return gw, None, None
+
+
+def prox(w, lam, offsets=None):
+    """prox_{lam R} of a float32 GPU tensor; ``offsets`` (host, n_seg+1 int64) splits the
+    flattened tensor into independent segments (default: one segment)."""
+    flat = w.contiguous().view(-1)
+    if offsets is None:
+        offsets = np.array([0, flat.numel()], dtype=np.int64)
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    return ProxFunction.apply(flat, float(lam), offsets).view(w.shape)
+
+
+def row_offsets(shapes):
+    """Offsets of per-row segments for a list of 2-D weight shapes laid out back to back."""
+    offs = [0]
+    for rows, cols in shapes:
+        for _ in range(rows):
+            offs.append(offs[-1] + cols)
+    return np.array(offs, dtype=np.int64)
+
+
+class BatchedProx:
+    """All segments of a fixed segmentation in one batched call per step (plan created once).
+
+    ``forward(w, out, lam)`` runs the batched prox; with ``save=True`` the saved permutation and
+    cluster-start bits for ``backward`` are kept in this object.  ``capture()`` records one
+    forward into a HIP graph (torch.cuda.CUDAGraph) for replay with ``replay()``.
+    """
+
+    def __init__(self, offsets, device="cuda", autotune=False):
+        self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.n = int(self.offsets[-1])
+        self.device = torch.device(device)
+        self.plan = _lib.wsr_plan_create(self.offsets, _lib.WSR_PLAN_AUTOTUNE if autotune else 0)
+        self.ws = _workspace(_lib.wsr_plan_workspace_bytes(self.plan), self.device)
+        self.perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        self.mask = torch.empty(_mask_words(self.n), dtype=torch.int32, device=self.device)
+        self.graph = None
+
+    def forward(self, w, out, lam=None, lam_scalar=0.0, save=True):
+        _check_f32(w, "w")
+        _check_f32(out, "out")
+        _lib.wsr_prox_forward_batched(self.plan, w, out, lam, lam_scalar,
+                                      self.perm if save else None, self.mask if save else None, self.ws)
+
+    def backward(self, g, gw):
+        _lib.wsr_prox_backward_batched(self.plan, g, gw, self.perm, self.mask, self.ws)
+
+    def capture(self, w, out, lam=None, lam_scalar=0.0, save=True):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.forward(w, out, lam, lam_scalar, save)  # warm-up outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.forward(w, out, lam, lam_scalar, save)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def close(self):
+        if self.plan is not None:
+            _lib.wsr_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,177 @@
+"""Helpers for GPU parity tests: run the HIP library, compare with the CPU oracle.
+
+Acceptance (per segment, scale = max |w| of the segment):
+  * values: |u_gpu - u_oracle| <= 1e-5 * scale + 2 ulp(u)   (normwise relative 1e-5);
+  * saved_perm: a permutation of the segment that sorts it (ties in any order);
+  * partition: neighbours (in the oracle's rank order) are in the same cluster on both sides,
+    except at near-ties: a boundary only one side has is excused when that side's two cluster
+    values differ by less than 1e-6 * scale (the two y-averages are that close, so either
+    decision is within the FP tolerance of the other);
+  * cluster values are constant within each GPU cluster and non-decreasing in rank order.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import torch
+
+import oracle
+import paper_2311_03096_amd as wsr
+
+NTHREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def mask_to_start(mask_words, n):
+    bits = np.unpackbits(np.ascontiguousarray(mask_words).view(np.uint8), bitorder="little")
+    return bits[:n].astype(np.uint8)
+
+
+def seg_start_of_rank(offsets):
+    lens = np.diff(offsets)
+    return np.repeat(offsets[:-1], lens)
+
+
+def gpu_forward(w, offsets, lam, save=True, batched=False, lam_arr=None):
+    wt = dev(w)
+    out = torch.empty_like(wt)
+    n = w.shape[0]
+    perm = torch.full((n,), -1, dtype=torch.int32, device="cuda") if save else None
+    mask = torch.full(((n + 31) // 32,), -1, dtype=torch.int32, device="cuda") if save else None
+    if batched:
+        plan = wsr.wsr_plan_create(offsets)
+        try:
+            nb = wsr.wsr_plan_workspace_bytes(plan)
+            ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+            la = dev(np.asarray(lam_arr, np.float32)) if lam_arr is not None else None
+            wsr.wsr_prox_forward_batched(plan, wt, out, la, lam, perm, mask, ws)
+            torch.cuda.synchronize()
+        finally:
+            wsr.wsr_plan_destroy(plan)
+    else:
+        nb = wsr.wsr_workspace_bytes(offsets)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        wsr.wsr_prox_forward(wt, out, offsets, lam, perm, mask, ws)
+        torch.cuda.synchronize()
+    res = dict(out=out.cpu().numpy())
+    if save:
+        res["perm"] = perm.cpu().numpy()
+        res["start"] = mask_to_start(mask.cpu().numpy(), n)
+    return res
+
+
+def gpu_backward(g, offsets, perm, start, batched=False):
+    n = g.shape[0]
+    words = np.packbits(np.concatenate([start, np.zeros((-n) % 32, np.uint8)]), bitorder="little").view(np.int32)
+    gt, pt, mt = dev(g.astype(np.float32)), dev(perm.astype(np.int32)), dev(words)
+    gw = torch.empty_like(gt)
+    if batched:
+        plan = wsr.wsr_plan_create(offsets)
+        try:
+            nb = wsr.wsr_plan_workspace_bytes(plan)
+            ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+            wsr.wsr_prox_backward_batched(plan, gt, gw, pt, mt, ws)
+            torch.cuda.synchronize()
+        finally:
+            wsr.wsr_plan_destroy(plan)
+    else:
+        nb = wsr.wsr_workspace_bytes(offsets)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        wsr.wsr_prox_backward(gt, gw, offsets, pt, mt, ws)
+        torch.cuda.synchronize()
+    return gw.cpu().numpy()
+
+
+def oracle_forward(w, offsets, lam):
+    u, perm, start = oracle.prox_segments(w, lam, offsets, n_threads=NTHREADS)
+    return dict(u=u, perm=perm, start=start)
+
+
+def compare(w, offsets, g_res, o_res, rel_tol=1e-5, tie_rel=1e-6):
+    """Return a stats dict; raises AssertionError on a violation."""
+    w = np.asarray(w, np.float32)
+    offsets = np.asarray(offsets, np.int64)
+    n = w.shape[0]
+    out = g_res["out"].astype(np.float64)
+    u = o_res["u"]
+    lens = np.diff(offsets)
+    seg_of = np.repeat(np.arange(lens.shape[0]), lens)
+    absw = np.abs(w.astype(np.float64))
+    scale = np.ones(lens.shape[0])
+    nz = lens > 0
+    scale[nz] = np.maximum.reduceat(absw, offsets[:-1][nz])
+    scale[(scale == 0) | ~np.isfinite(scale)] = 1.0
+    sc = scale[seg_of]
+    finite = np.isfinite(u)
+    assert np.array_equal(np.isnan(out), ~finite), "NaN pattern differs"
+    err = np.abs(out - u)
+    err[~finite] = 0.0
+    ulp = np.spacing(np.abs(u).astype(np.float32)).astype(np.float64)
+    ulp[~finite] = 0.0
+    bad = err > rel_tol * sc + 2 * ulp
+    stats = dict(max_abs_err=float(err.max()) if n else 0.0,
+                 max_rel_err=float((err / sc).max()) if n else 0.0,
+                 n=n, n_seg=int(lens.shape[0]))
+    assert not bad.any(), "value mismatch at %s: gpu %r oracle %r" % (
+        np.nonzero(bad)[0][:5], out[bad][:5], u[bad][:5])
+    if "perm" not in g_res:
+        return stats
+    perm = g_res["perm"].astype(np.int64)
+    sstart = seg_start_of_rank(offsets)
+    orig = sstart + perm
+    # a permutation of each segment that sorts it
+    assert np.all((perm >= 0) & (perm < np.repeat(lens, lens))), "perm out of range"
+    cnt = np.bincount(orig, minlength=n)
+    assert np.all(cnt == 1), "perm is not a permutation"
+    first = np.zeros(n, bool)
+    first[offsets[:-1][nz]] = True
+    start = g_res["start"].astype(bool)
+    # identity segments (lam = 0, d = 1, non-finite) may keep the identity permutation
+    o_all = np.ones(lens.shape[0], bool)
+    g_all = np.ones(lens.shape[0], bool)
+    is_id = np.ones(lens.shape[0], bool)
+    if nz.any():
+        idx = offsets[:-1][nz]
+        o_all[nz] = np.minimum.reduceat(o_res["start"].astype(np.uint8), idx) == 1
+        g_all[nz] = np.minimum.reduceat(start.astype(np.uint8), idx) == 1
+        is_id[nz] = np.minimum.reduceat((perm == np.arange(n) - sstart).astype(np.uint8), idx) == 1
+    exempt = (o_all & g_all & is_id)[seg_of]
+    xs = w[orig].astype(np.float64)
+    dx = np.diff(xs)
+    assert np.all((dx >= 0) | first[1:] | ~np.isfinite(dx) | exempt[1:]), "perm does not sort its segment"
+    assert np.all(start[first]), "rank 0 of a segment must start a cluster"
+    # cluster values constant inside a GPU cluster, non-decreasing across
+    ov = out[orig]
+    same = ~start[1:] & ~first[1:]
+    fin = np.isfinite(ov[1:]) & np.isfinite(ov[:-1])
+    assert np.all(ov[1:][same & fin] == ov[:-1][same & fin]), "value not constant in a cluster"
+    # monotone along the ranks; a decrease is only allowed at a near-tie (both values within
+    # the tie threshold, where the two neighbouring y-averages are equal to FP64 noise)
+    dec = (ov[:-1] - ov[1:])
+    dec[~(~first[1:] & fin) | exempt[1:]] = 0.0
+    tau_r = tie_rel * sc[orig[1:]]
+    stats_dec = float(dec.max()) if n > 1 else 0.0
+    assert np.all(dec <= tau_r), "values decrease along the ranks by %g (max allowed %g) at %s" % (
+        stats_dec, float(tau_r.min()) if n > 1 else 0.0, np.nonzero(dec > tau_r)[0][:5])
+    # partition in the oracle's rank order
+    cid = np.empty(n, np.int64)
+    cid[orig] = np.cumsum(start)
+    o_orig = sstart + o_res["perm"].astype(np.int64)
+    o_start = o_res["start"].astype(bool)
+    same_o = ~o_start[1:]
+    same_g = cid[o_orig[1:]] == cid[o_orig[:-1]]
+    mism = (same_o != same_g) & ~first[1:]
+    tau = tie_rel * sc[o_orig[1:]]
+    marg_o = np.abs(u[o_orig[1:]] - u[o_orig[:-1]])
+    marg_g = np.abs(out[o_orig[1:]] - out[o_orig[:-1]])
+    excused = np.where(~same_o, marg_o < tau, marg_g < tau + 2 * ulp[o_orig[1:]])
+    unexcused = mism & ~excused
+    stats.update(partition_mismatches=int(mism.sum()), unexcused=int(unexcused.sum()),
+                 clusters=int(start.sum()), max_rank_decrease=stats_dec,
+                 rank_decreases=int((dec > 0).sum()))
+    assert not unexcused.any(), "partition differs at ranks %s" % (np.nonzero(unexcused)[0][:5] + 1)
+    return stats

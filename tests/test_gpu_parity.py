@@ -1,0 +1,249 @@
+"""GPU parity: the HIP library against the CPU oracle, through the C ABI.
+
+Sizes run from single elements through several LDS tiles with ragged tails, across the
+short/long segment boundary (8192/8193), up to the full sizes of the benchmark workloads.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import pins  # noqa: E402
+from gpu_util import compare, gpu_backward, gpu_forward, oracle_forward  # noqa: E402
+from paper_2311_03096_amd import workloads  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _check(case, batched=False, lam_arr=None):
+    w, off, lam = case["w"], case["offsets"], case["lam"]
+    _say("case", case.get("name"), "n", w.shape[0], "segments", off.shape[0] - 1, "batched", batched)
+    g = gpu_forward(w, off, lam, batched=batched, lam_arr=lam_arr)
+    if lam_arr is not None:
+        u, p, s = oracle.prox_segments(w, np.asarray(lam_arr, np.float32), off)
+        o = dict(u=u, perm=p, start=s)
+    else:
+        o = oracle_forward(w, off, lam)
+    st = compare(w, off, g, o)
+    _say("  stats", st)
+    return g, o, st
+
+
+def test_plain_d4096():
+    _check(workloads.plain(4096, 0.1))
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 63, 64, 65, 100, 1000, 2047, 2048, 2049, 3072, 4095, 4096, 4097,
+                               8191, 8192, 8193, 12289, 50000, 100003])
+@pytest.mark.parametrize("dist", ["normal", "ties", "sorted", "laplace"])
+def test_sizes(d, dist):
+    lam = {"normal": 0.05, "ties": 0.5, "sorted": 0.02, "laplace": 2.0}[dist]
+    _check(workloads.random_segments([d], dist, lam, seed=d))
+
+
+@pytest.mark.parametrize("lam", [1e-6, 1e-3, 1.0, 1e3])
+def test_lambda_range(lam):
+    _check(workloads.random_segments([5000], "normal", lam, seed=7))
+    _check(workloads.random_segments([20000], "normal", lam, seed=8))
+
+
+def test_uneven_segments_plain_equals_batched():
+    lens = [0, 1, 2, 3, 17, 64, 65, 1000, 2048, 2049, 3072, 4096, 4097, 8192, 8193, 20000, 0, 5, 33, 7000]
+    case = workloads.random_segments(lens, "mixed", 0.05, seed=3)
+    g1, _, _ = _check(case, batched=False)
+    g2, _, _ = _check(case, batched=True)
+    assert np.array_equal(g1["out"], g2["out"])
+    assert np.array_equal(g1["perm"], g2["perm"])
+    assert np.array_equal(g1["start"], g2["start"])
+
+
+def test_per_segment_lambda_batched():
+    lens = [3000, 4096, 100, 9000, 1, 2048]
+    case = workloads.random_segments(lens, "normal", 0.0, seed=4)
+    lam_arr = np.array([0.0, 0.1, 1.0, 0.01, 0.5, 3.0], np.float32)
+    _check(case, batched=True, lam_arr=lam_arr)
+
+
+def test_mlp_rows_batched_and_per_row():
+    case = workloads.mlp_rows()
+    gb, o, st = _check(case, batched=True)
+    gp = gpu_forward(case["w"], case["offsets"], case["lam"], batched=False)
+    assert np.array_equal(gb["out"], gp["out"])
+    assert np.array_equal(gb["perm"], gp["perm"])
+    assert np.array_equal(gb["start"], gp["start"])
+
+
+def test_chain_one_cluster():
+    for shuffle in (False, True):
+        case = workloads.chain(1 << 24, 0.7, shuffle=shuffle)
+        g = gpu_forward(case["w"], case["offsets"], case["lam"])
+        mean = case["w"].astype(np.float64).mean()
+        _say("chain shuffle", shuffle, "mean", mean, "gpu", g["out"][:3], "clusters", g["start"].sum())
+        assert g["start"].sum() == 1
+        assert np.all(g["out"] == g["out"][0])
+        assert abs(g["out"][0] - mean) <= 1e-6
+    o = oracle_forward(case["w"], case["offsets"], case["lam"])
+    compare(case["w"], case["offsets"], g, o)
+
+
+def test_chain_below_threshold():
+    d = 1 << 20
+    lam_min = (4 * d - 5) / (6.0 * (d - 1))
+    _check(workloads.chain(d, lam_min * 0.9))
+    _check(workloads.chain(d, lam_min * 0.99, shuffle=True))
+
+
+def test_typical_d2p24():
+    _check(workloads.plain(1 << 24, 0.1, seed=1))
+
+
+def test_precision_d2p26():
+    case = workloads.precision(1 << 26, 1e-4)
+    g, o, st = _check(case)
+    # clusters are the FP32 tie groups
+    x = np.sort(case["w"])
+    groups = int(np.count_nonzero(np.diff(x)) + 1)
+    _say("tie groups", groups, "gpu clusters", st["clusters"])
+    assert st["clusters"] == groups
+
+
+def test_edge_cases():
+    rng = np.random.default_rng(5)
+    # identity cases and non-finite segments mixed with regular ones
+    w = np.concatenate([rng.normal(size=100), [3.0], rng.normal(size=50), [np.nan], rng.normal(size=20),
+                        np.full(300, 2.5), np.zeros(10), -np.zeros(10), rng.normal(size=9000),
+                        [np.inf], rng.normal(size=9000)]).astype(np.float32)
+    lens = [100, 1, 51, 20, 300, 20, 9000, 9001]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    for lam in (0.0, 0.3):
+        case = dict(name="edge lam=%g" % lam, w=w, offsets=off, lam=lam)
+        for batched in (False, True):
+            g, o, st = _check(case, batched=batched)
+            if lam == 0.0:
+                seg_ok = np.repeat(np.logical_and.reduceat(np.isfinite(w), off[:-1]), lens)
+                np.testing.assert_array_equal(g["out"][seg_ok], w[seg_ok])
+                assert np.isnan(g["out"][~seg_ok]).all()
+    # huge lambda: everything one cluster per segment
+    case = workloads.random_segments([4000, 20000], "laplace", 1e4, seed=6)
+    g, o, st = _check(case)
+    assert st["clusters"] == 2
+
+
+def test_determinism():
+    case = workloads.random_segments([3000, 4096, 8192, 100000], "normal", 0.05, seed=9)
+    a = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
+    b = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
+    for k in ("out", "perm", "start"):
+        assert np.array_equal(a[k], b[k])
+
+
+def test_out_aliases_w():
+    import paper_2311_03096_amd as wsr
+    case = workloads.random_segments([4096, 20000], "normal", 0.05, seed=10)
+    o = oracle_forward(case["w"], case["offsets"], case["lam"])
+    wt = torch.from_numpy(case["w"].copy()).cuda()
+    ws = torch.empty(wsr.wsr_workspace_bytes(case["offsets"]), dtype=torch.uint8, device="cuda")
+    wsr.wsr_prox_forward(wt, wt, case["offsets"], case["lam"], None, None, ws)
+    torch.cuda.synchronize()
+    compare(case["w"], case["offsets"], dict(out=wt.cpu().numpy()), o)
+
+
+# ------------------------------------------------------------------------------- backward
+
+def _cluster_key(ids):
+    """Per element: (size, sum, sum of squares) of the member indices of its cluster."""
+    n = ids.shape[0]
+    _, inv = np.unique(ids, return_inverse=True)
+    idx = np.arange(n, dtype=np.float64)
+    size = np.bincount(inv)
+    s1 = np.bincount(inv, weights=idx)
+    s2 = np.bincount(inv, weights=idx * idx)
+    return np.stack([size[inv], s1[inv], s2[inv]], axis=1).view(np.dtype((np.void, 24))).ravel()
+
+
+def _check_backward(case, batched=False):
+    w, off, lam = case["w"], case["offsets"], case["lam"]
+    g = case.get("g")
+    if g is None:
+        g = np.random.default_rng(1).standard_normal(w.shape[0]).astype(np.float32)
+    _say("backward", case.get("name"), "n", w.shape[0], "batched", batched)
+    fw = gpu_forward(w, off, lam, batched=batched)
+    gw = gpu_backward(g, off, fw["perm"], fw["start"], batched=batched)
+    # exact structure: the oracle VJP on the GPU's own partition
+    ref_same = oracle.vjp(g.astype(np.float64), fw["perm"], fw["start"], off)
+    err = np.abs(gw - ref_same)
+    tol = 1e-6 * (1 + np.abs(ref_same))
+    _say("  max err vs oracle VJP (same partition)", float(err.max()))
+    assert np.all(err <= tol)
+    # oracle's partition: equal wherever the partitions agree
+    o = oracle_forward(w, off, lam)
+    ref = oracle.vjp(g.astype(np.float64), o["perm"], o["start"], off)
+    ids_g = oracle.cluster_ids(fw["perm"], fw["start"], off)
+    ids_o = oracle.cluster_ids(o["perm"], o["start"], off)
+    same = _cluster_key(ids_g) == _cluster_key(ids_o)
+    _say("  elements in identical clusters", float(same.mean()))
+    assert same.mean() > 0.99
+    assert np.all(np.abs(gw - ref)[same] <= 1e-6 * (1 + np.abs(ref[same])))
+    return gw
+
+
+def test_backward_rows():
+    _check_backward(workloads.backward_rows(1024, 8192, 0.05), batched=True)
+    _check_backward(workloads.backward_rows(64, 8192, 5.0, seed=2), batched=False)
+
+
+def test_backward_uneven_and_big():
+    _check_backward(workloads.random_segments([1, 5, 3000, 4096, 9000, 70000], "laplace", 0.5, seed=11))
+    _check_backward(workloads.random_segments([1 << 20], "normal", 0.1, seed=12), batched=True)
+
+
+def test_backward_chain_one_cluster():
+    case = workloads.chain(1 << 22, 0.7)
+    g = np.random.default_rng(2).standard_normal(1 << 22).astype(np.float32)
+    fw = gpu_forward(case["w"], case["offsets"], case["lam"])
+    assert fw["start"].sum() == 1
+    gw = gpu_backward(g, case["offsets"], fw["perm"], fw["start"])
+    assert np.allclose(gw, g.astype(np.float64).mean(), atol=1e-6)
+
+
+def test_autograd_prox():
+    from paper_2311_03096_amd.ops import prox
+    case = workloads.random_segments([3000, 12000], "normal", 0.05, seed=13)
+    w = torch.from_numpy(case["w"]).cuda().requires_grad_(True)
+    u = prox(w, case["lam"], case["offsets"])
+    g = torch.randn_like(u)
+    u.backward(g)
+    o = oracle_forward(case["w"], case["offsets"], case["lam"])
+    compare(case["w"], case["offsets"], dict(out=u.detach().cpu().numpy()), o)
+    ref = oracle.vjp(g.cpu().numpy().astype(np.float64), o["perm"], o["start"], case["offsets"])
+    assert np.allclose(w.grad.cpu().numpy(), ref, atol=1e-5)
+
+
+def test_graph_capture_replays():
+    from paper_2311_03096_amd.ops import BatchedProx
+    case = workloads.random_segments([3072] * 50 + [4096] * 50 + [10000], "normal", 0.01, seed=14)
+    w = torch.from_numpy(case["w"]).cuda()
+    out_eager = torch.empty_like(w)
+    bp = BatchedProx(case["offsets"])
+    bp.forward(w, out_eager, lam_scalar=case["lam"])
+    torch.cuda.synchronize()
+    ref = out_eager.clone()
+    out = torch.zeros_like(w)
+    bp.capture(w, out, lam_scalar=case["lam"])
+    for i in range(3):
+        out.zero_()
+        bp.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), "replay %d differs" % i
+        _ = (w * 2).sum().item()  # eager work between replays
+    bp.close()
