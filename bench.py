@@ -210,8 +210,10 @@ def main():
         typ = workloads.plain(d, 0.1, seed=1)
         st = Step(typ)
         ms_t, _ = time_steps(st, max(3, args.steps // 2), 2)
+        tr_t = trace_kernels(st, 3)
         extra["typical_d2p24"] = dict(workload="one N(0,1) vector d=2^24, lam=0.1", ms_per_step=round(ms_t, 4),
-                                      elements_per_s=d / (ms_t * 1e-3))
+                                      elements_per_s=d / (ms_t * 1e-3),
+                                      kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr_t.items()})
         log("typical", ms_t)
         extra["batched_mlp_rows"] = batched_vs_per_row(max(5, args.steps), args.warmup)
         log("batched", extra["batched_mlp_rows"])

@@ -226,14 +226,18 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
     const int fin = lvl_hi == nlev ? 1 : 0;
     if (G > kMergeGroupMax) return WSR_ERR_UNSUPPORTED;
     WSR_TRACE("big_merge", s);
-    if (G <= kMergeGroupSmall)
-      hipLaunchKernelGGL((k_big_merge<kMergeGroupSmall, kMergeRecMax>), dim3(groups), dim3(kMergeThreads), 0,
-                         s, lvl_lo, lvl_hi, nt, b.vpos, b.vS, b.tileoff, b.lo, b.hi, fin, b.prev_pos, b.prev_s,
-                         b.next_pos, b.next_s);
+#define WSR_LAUNCH_MERGE(GM)                                                                             \
+  hipLaunchKernelGGL((k_big_merge<GM, kMergeRecMax>), dim3(groups), dim3(kMergeThreads), 0, s, lvl_lo, lvl_hi, \
+                     nt, b.vpos, b.vS, b.tileoff, b.lo, b.hi, fin, b.prev_pos, b.prev_s, b.next_pos, b.next_s)
+    if (G <= 16)
+      WSR_LAUNCH_MERGE(16);
+    else if (G <= 256)
+      WSR_LAUNCH_MERGE(256);
+    else if (G <= 4096)
+      WSR_LAUNCH_MERGE(4096);
     else
-      hipLaunchKernelGGL((k_big_merge<kMergeGroupMax, kMergeRecMax>), dim3(groups), dim3(kMergeThreads), 0,
-                         s, lvl_lo, lvl_hi, nt, b.vpos, b.vS, b.tileoff, b.lo, b.hi, fin, b.prev_pos, b.prev_s,
-                         b.next_pos, b.next_s);
+      WSR_LAUNCH_MERGE(16384);
+#undef WSR_LAUNCH_MERGE
     lvl_lo = lvl_hi + 1;
   } while (lvl_lo <= nlev);
   { WSR_TRACE("big_apply", s);

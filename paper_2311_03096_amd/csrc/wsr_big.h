@@ -10,10 +10,9 @@ constexpr int kRadixTile = 4096;    // keys per radix workgroup
 constexpr int kBigThreads = 256;
 constexpr int kBigE = 16;
 constexpr int kBigTile = kBigThreads * kBigE;  // ranks per hull tile
-constexpr int kMergeThreads = 256;
-constexpr int kMergeLevelsPerLaunch = 7;
-constexpr int kMergeGroupSmall = 1 << kMergeLevelsPerLaunch;  // first-stage groups
-constexpr int kMergeGroupMax = 1 << 14;                        // tiles of the longest segment
+constexpr int kMergeThreads = 512;  // one wave per merge
+constexpr int kMergeLevelsPerLaunch = 4;
+constexpr int kMergeGroupMax = 1 << 14;                         // tiles of the longest segment
 constexpr int kMergeRecMax = 1 << (kMergeLevelsPerLaunch - 1);  // merges at a launch's first level
 static_assert((int64_t)kMergeGroupMax * kBigTile >= ((int64_t)1 << 26), "top merge group too small");
 static_assert(kRadixThreads == 256, "digit scan assumes one digit per thread");

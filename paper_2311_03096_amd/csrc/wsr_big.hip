@@ -171,7 +171,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const float* ws
 // ------------------------------------------------------------------------------- tile hulls
 
 struct TileSmem {
-  double S[kBigTile + 1];
+  uint32_t keys[rpad_size(kBigTile)];  // sorted keys of the tile (rank-padded)
+  double S[rpad_size(kBigTile + 1)];   // tile-relative prefix sums (rank-padded)
   uint16_t vert[kBigThreads * (kBigE + 1)];
   int cnt[kBigThreads];
   int mres[kBigThreads];
@@ -202,24 +203,26 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
   const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
   const int j0 = tid * kBigE;
+  for (int j = tid; j < np; j += kBigThreads) sm.keys[rpad(j)] = skeys[k0 + j];
+  __syncthreads();
   double xs[kBigE];
   double lsum = 0.0;
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
     const int j = j0 + i;
-    xs[i] = j < np ? (double)key_to_float(skeys[k0 + j]) - c : 0.0;
+    xs[i] = j < np ? (double)key_to_float(sm.keys[rpad(j)]) - c : 0.0;
     lsum += xs[i];
   }
   double X = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
     const int j = j0 + i;
-    if (j <= np) sm.S[j] = X + lamd * (double)j * ((double)(d - 2 * k0) - (double)j);
+    if (j <= np) sm.S[rpad(j)] = X + lamd * (double)j * ((double)(d - 2 * k0) - (double)j);
     if (j == np) sm.xtot = X;
     X += xs[i];
   }
   if (tid == kBigThreads - 1 && np == kBigTile) {
-    sm.S[kBigTile] = X + lamd * (double)kBigTile * ((double)(d - 2 * k0) - (double)kBigTile);
+    sm.S[rpad(kBigTile)] = X + lamd * (double)kBigTile * ((double)(d - 2 * k0) - (double)kBigTile);
     sm.xtot = X;
   }
   __syncthreads();
@@ -228,7 +231,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   for (int i = tid; i < nv; i += kBigThreads) {
     vpos[vb + i] = (int32_t)(k0 + sm.vert[i]);
-    vS[vb + i] = sm.S[sm.vert[i]];
+    vS[vb + i] = sm.S[rpad(sm.vert[i])];
   }
   if (tid == 0) {
     hcnt[t] = nv;
@@ -294,10 +297,11 @@ __device__ __forceinline__ void node_vertex(const MergeCtx& C, int t0, int t1, i
   *idx = C.lo16[lo] + (mm - C.pre[lo]);
 }
 
-struct NodeChain {
+// Wave-cooperative access to a node's chain: any lane may fetch any vertex.
+struct WaveNode {
   const MergeCtx* C;
   int t0, t1;
-  __device__ __forceinline__ void get(int m, int* p, double* s) const {
+  __device__ __forceinline__ void fetch(int m, int* p, double* s) const {
     int tile, idx;
     node_vertex(*C, t0, t1, m, &tile, &idx);
     const int g = C->gbase + tile;
@@ -305,23 +309,127 @@ struct NodeChain {
     *p = C->vpos[at];
     *s = C->vS[at] + C->tileoff[g];
   }
-  __device__ __forceinline__ int pos(int m) const {
-    int p;
-    double s;
-    get(m, &p, &s);
-    return p;
-  }
-  __device__ __forceinline__ double s(int m) const {
-    int p;
-    double s_;
-    get(m, &p, &s_);
-    return s_;
-  }
 };
+
+// First j in [1, q] with R(j) strictly below the segment Q -> R(j+1) (q when none): the
+// rightmost collision of the point Q inside R.  Called by all 64 lanes with uniform arguments;
+// probes run 64 at a time: one exponential round (lane l probes 2^l), then 64-way refinement.
+__device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs) {
+  const int lane = lane_id();
+  auto f = [&](int j) -> bool {
+    if (j >= q) return true;
+    int pj, pj1;
+    double sj, sj1;
+    R.fetch(j, &pj, &sj);
+    R.fetch(j + 1, &pj1, &sj1);
+    return below(qa, qs, pj, sj, pj1, sj1);
+  };
+  const int j = lane < 30 ? min(1 << lane, q) : q;
+  const uint64_t b = __ballot(f(j));  // lane 63 probes q, so b != 0
+  const int ft = __ffsll((unsigned long long)b) - 1;
+  int hi = __shfl(j, ft, kWave);
+  int lo = ft == 0 ? 0 : __shfl(j, ft - 1, kWave);
+  while (hi - lo > 1) {
+    const int span = hi - lo - 1;  // candidates lo+1 .. hi-1
+    const int stride = (span + kWave - 1) / kWave;
+    const int jj = lo + 1 + lane * stride;
+    const bool valid = jj < hi;
+    const uint64_t bb = __ballot(valid && f(jj));
+    if (bb == 0) {
+      const int nvalid = (span + stride - 1) / stride;
+      lo = lo + 1 + (nvalid - 1) * stride;
+    } else {
+      const int f2 = __ffsll((unsigned long long)bb) - 1;
+      const int nhi = __shfl(jj, f2, kWave);
+      lo = f2 == 0 ? lo : __shfl(jj, f2 - 1, kWave);
+      hi = nhi;
+    }
+  }
+  return hi;
+}
+
+// Bridge between the chains L (0..p) and R (0..q) sharing the junction L(p) == R(0); same
+// contract as bridge() but executed by one wave: vertex fetches and tangent probes in parallel.
+__device__ void wave_bridge(const WaveNode& L, int p, const WaveNode& R, int q, int* istar, int* jstar) {
+  if (q <= 0) {
+    *istar = p;
+    *jstar = 1;
+    return;
+  }
+  if (p <= 0) {
+    *istar = 0;
+    *jstar = 1;
+    return;
+  }
+  const int lane = lane_id();
+  {
+    int pv = 0;
+    double sv = 0.0;
+    if (lane == 0)
+      L.fetch(p - 1, &pv, &sv);
+    else if (lane == 1)
+      L.fetch(p, &pv, &sv);
+    else if (lane == 2)
+      R.fetch(1, &pv, &sv);
+    const int a0 = __shfl(pv, 0, kWave), a1 = __shfl(pv, 1, kWave), a2 = __shfl(pv, 2, kWave);
+    const double b0 = __shfl(sv, 0, kWave), b1 = __shfl(sv, 1, kWave), b2 = __shfl(sv, 2, kWave);
+    if (below(a0, b0, a1, b1, a2, b2)) {  // junction survives
+      *istar = p;
+      *jstar = 1;
+      return;
+    }
+  }
+  auto g = [&](int i, int* jout) -> bool {
+    int pv = 0;
+    double sv = 0.0;
+    if (lane == 0)
+      L.fetch(i, &pv, &sv);
+    else if (lane == 1)
+      L.fetch(i + 1, &pv, &sv);
+    const int li = __shfl(pv, 0, kWave), ln = __shfl(pv, 1, kWave);
+    const double si = __shfl(sv, 0, kWave), sn = __shfl(sv, 1, kWave);
+    const int j = wave_tangent(R, q, li, si);
+    int rp = 0;
+    double rs = 0.0;
+    if (lane == 0) R.fetch(j, &rp, &rs);
+    rp = __shfl(rp, 0, kWave);
+    rs = __shfl(rs, 0, kWave);
+    *jout = j;
+    return !below(li, si, ln, sn, rp, rs);
+  };
+  int jhi = 1;
+  if (!g(p - 1, &jhi)) {  // only reachable through rounding: keep the junction
+    *istar = p;
+    *jstar = 1;
+    return;
+  }
+  int hi = p - 1, lo = hi - 1, step = 1;
+  while (lo >= 0) {
+    int j;
+    if (!g(lo, &j)) break;
+    hi = lo;
+    jhi = j;
+    step <<= 1;
+    lo = hi - step;
+  }
+  if (lo < 0) lo = -1;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    int j;
+    if (g(mid, &j)) {
+      hi = mid;
+      jhi = j;
+    } else {
+      lo = mid;
+    }
+  }
+  *istar = hi;
+  *jstar = jhi;
+}
 
 // Levels [lvl_lo, lvl_hi] of the tile merge tree; workgroup g owns tiles [g*2^lvl_hi, ...).
 // LDS (static, sized for the largest group GMAX): pre[G+1], rec[5 * (G >> lvl_lo)], lo16[G],
-// cnt16[G] with G = 2^lvl_hi <= GMAX and G >> lvl_lo <= RMAX.
+// cnt16[G] with G = 2^lvl_hi <= GMAX and G >> lvl_lo <= RMAX.  One wave per merge.
 // A merge record is {bridged, last left tile keeping vertices (t0-1: none), its last kept
 // index, first right tile keeping vertices, its first kept index}.
 // When finalize != 0 (single group holding every tile, last launch), also writes the previous
@@ -333,15 +441,18 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
                                                              int32_t* hi_g, int finalize, int32_t* prev_pos,
                                                              double* prev_s, int32_t* next_pos,
                                                              double* next_s) {
+  constexpr int NWV = kMergeThreads / kWave;
   __shared__ int pre[GMAX + 1];
   __shared__ int rec[5 * RMAX];
   __shared__ uint16_t lo16[GMAX];
   __shared__ uint16_t cnt16[GMAX];
-  __shared__ int ish[kMergeThreads / kWave + 1];
+  __shared__ int ish[NWV + 1];
   const int G = 1 << lvl_hi;
   const int gbase = blockIdx.x * G;
   const int gn = min(G, ntiles - gbase);
   const int tid = threadIdx.x;
+  const int wv = tid / kWave;
+  const int lane = lane_id();
 
   auto rebuild_prefix = [&]() {
     const int chunk = (gn + kMergeThreads - 1) / kMergeThreads;
@@ -372,35 +483,43 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   for (int lvl = lvl_lo; lvl <= lvl_hi; ++lvl) {
     const int size = 1 << lvl;
     const int half = size >> 1;
-    const int nm = (gn + size - 1) >> lvl;
-    for (int m = tid; m < nm; m += kMergeThreads) {
+    const int nm = min((gn + size - 1) >> lvl, RMAX);
+    for (int m = wv; m < nm; m += NWV) {
       const int t0 = m << lvl;
       const int tm = t0 + half;
       const int t1 = min(t0 + size, gn);
-      int* r = rec + 5 * m;
-      r[0] = 0;
+      int r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
       if (tm < gn) {
-        NodeChain L{&C, t0, tm};
-        NodeChain R{&C, tm, t1};
+        WaveNode L{&C, t0, tm};
+        WaveNode R{&C, tm, t1};
         const int p = pre[tm] - pre[t0];  // left chain: end point + own vertices; last index p
         const int q = pre[t1] - pre[tm];
         int istar, jstar;
-        bridge(L, p, R, q, &istar, &jstar);
+        wave_bridge(L, p, R, q, &istar, &jstar);
         if (!(istar == p && jstar == 1)) {
           int ti = t0 - 1, ii = 0, tj, jj;
           if (istar > 0) node_vertex(C, t0, tm, istar, &ti, &ii);
           node_vertex(C, tm, t1, jstar, &tj, &jj);
-          r[0] = 1;
-          r[1] = ti;
-          r[2] = ii;
-          r[3] = tj;
-          r[4] = jj;
+          r0 = 1;
+          r1 = ti;
+          r2 = ii;
+          r3 = tj;
+          r4 = jj;
         }
+      }
+      if (lane == 0) {
+        int* r = rec + 5 * m;
+        r[0] = r0;
+        r[1] = r1;
+        r[2] = r2;
+        r[3] = r3;
+        r[4] = r4;
       }
     }
     __syncthreads();
     for (int i = tid; i < gn; i += kMergeThreads) {
       const int m = i >> lvl;
+      if (m >= nm) continue;
       const int* r = rec + 5 * m;
       if (!r[0]) continue;
       const int tm = (m << lvl) + half;
@@ -454,14 +573,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   }
 }
 
-template __global__ void k_big_merge<kMergeGroupSmall, kMergeRecMax>(int, int, int, const int32_t*,
-                                                                      const double*, const double*,
-                                                                      int32_t*, int32_t*, int, int32_t*,
-                                                                      double*, int32_t*, double*);
-template __global__ void k_big_merge<kMergeGroupMax, kMergeRecMax>(int, int, int, const int32_t*,
-                                                                    const double*, const double*,
-                                                                    int32_t*, int32_t*, int, int32_t*,
-                                                                    double*, int32_t*, double*);
+#define WSR_INSTANTIATE_MERGE(GM)                                                                    \
+  template __global__ void k_big_merge<GM, kMergeRecMax>(int, int, int, const int32_t*, const double*, \
+                                                         const double*, int32_t*, int32_t*, int,        \
+                                                         int32_t*, double*, int32_t*, double*);
+WSR_INSTANTIATE_MERGE(16)
+WSR_INSTANTIATE_MERGE(256)
+WSR_INSTANTIATE_MERGE(4096)
+WSR_INSTANTIATE_MERGE(16384)
 
 // ------------------------------------------------------------------------------- apply
 
@@ -469,6 +588,7 @@ struct ApplySmem {
   int32_t lp[kBigTile + 2];
   double ls[kBigTile + 2];   // global S at the vertex
   double lsl[kBigTile + 2];  // tile-relative S' (valid where lloc)
+  int32_t perm[kBigTile];    // the tile's saved permutation, loaded coalesced
   uint8_t lloc[kBigTile + 2];
   uint32_t lmask[kBigTile / 32 + 2];
   int n;
@@ -525,6 +645,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
       sm.lloc[1 + own] = 0;
     }
   }
+  for (int j = tid; j < np; j += kBigThreads) sm.perm[j] = perm[k0 + j];
   for (int i = tid; i < own; i += kBigThreads) {
     const double sl = vS[vb + lo + i];
     sm.lp[1 + i] = vpos[vb + lo + i];
@@ -571,7 +692,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
         nxt = sm.lp[cur + 1];
         val = edge_value(cur);
       }
-      const int64_t pl = min((int64_t)max(perm[kk], 0), d - 1);
+      const int64_t pl = min((int64_t)max(sm.perm[j], 0), d - 1);
       out[seg_start + pl] = val;
     }
   }
@@ -582,6 +703,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
 // ------------------------------------------------------------------------------- backward
 
 struct BwdTileSmem {
+  float g[kBigTile];  // gathered cotangent in rank order
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
   int fmin, lmax;
@@ -601,19 +723,21 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int j0 = tid * kBigE;
+  // coalesced perm read and gsorted write; the gather itself follows the permutation
+  for (int j = tid; j < np; j += kBigThreads) {
+    const int64_t pl = min((int64_t)max(perm[k0 + j], 0), d - 1);
+    const float gv = g[seg_start + pl];
+    sm.g[j] = gv;
+    gsorted[k0 + j] = gv;
+  }
+  __syncthreads();
   float gk[kBigE];
   double lsum = 0.0;
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
     const int j = j0 + i;
-    gk[i] = 0.0f;
-    if (j < np) {
-      int pl = perm[k0 + j];
-      pl = (int)min((int64_t)max(pl, 0), d - 1);
-      gk[i] = g[seg_start + pl];
-      gsorted[k0 + j] = gk[i];
-      lsum += (double)gk[i];
-    }
+    gk[i] = j < np ? sm.g[j] : 0.0f;
+    lsum += (double)gk[i];
   }
   if (tid == 0) {
     sm.fmin = 0x7FFFFFFF;
@@ -756,7 +880,11 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const
 
 struct BwdApplySmem {
   int32_t lp[kBigTile + 2];
-  double lg[kBigTile + 2];
+  union {
+    float g[kBigTile];       // gathered cotangent (read before the list is built)
+    double lg[kBigTile + 2];
+  } u;
+  int32_t perm[kBigTile];
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
   int n;
@@ -774,6 +902,11 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int j0 = tid * kBigE;
+  for (int j = tid; j < np; j += kBigThreads) {
+    sm.u.g[j] = gsorted[k0 + j];
+    sm.perm[j] = perm[k0 + j];
+  }
+  __syncthreads();
   float gk[kBigE];
   double lsum = 0.0;
   int lst = 0;
@@ -784,7 +917,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
     gk[i] = 0.0f;
     st[i] = false;
     if (j < np) {
-      gk[i] = gsorted[k0 + j];
+      gk[i] = sm.u.g[j];
       lsum += (double)gk[i];
       const int64_t pf = seg_start + k0 + j;
       st[i] = (k0 + j == 0) || ((mask[pf >> 5] >> (pf & 31)) & 1u);
@@ -801,16 +934,16 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
     const int j = j0 + i;
     if (j < np && st[i]) {
       sm.lp[ci] = (int32_t)(k0 + j);
-      sm.lg[ci] = G;
+      sm.u.lg[ci] = G;
       ++ci;
     }
     if (j < np) G += (double)gk[i];
   }
   if (tid == 0) {
     sm.lp[0] = prevp[t];
-    sm.lg[0] = prevG[t];
+    sm.u.lg[0] = prevG[t];
     sm.lp[1 + nst] = nextp[t];
-    sm.lg[1 + nst] = nextG[t];
+    sm.u.lg[1 + nst] = nextG[t];
     sm.n = nst + 2;
   }
   __syncthreads();
@@ -827,17 +960,16 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
     }
     int cur = a;
     int64_t nxt = sm.lp[cur + 1];
-    float val = (float)((sm.lg[cur + 1] - sm.lg[cur]) / (double)(nxt - sm.lp[cur]));
+    float val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
     const int j1 = min(j0 + kBigE, np);
     for (int j = j0; j < j1; ++j) {
       const int64_t kk = k0 + j;
       while (kk >= nxt && cur + 2 < n) {
         ++cur;
         nxt = sm.lp[cur + 1];
-        val = (float)((sm.lg[cur + 1] - sm.lg[cur]) / (double)(nxt - sm.lp[cur]));
+        val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
       }
-      int pl = perm[kk];
-      pl = (int)min((int64_t)max(pl, 0), d - 1);
+      const int64_t pl = min((int64_t)max(sm.perm[j], 0), d - 1);
       gout[seg_start + pl] = val;
     }
   }

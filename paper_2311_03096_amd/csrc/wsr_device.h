@@ -38,6 +38,12 @@ __device__ __forceinline__ float key_to_float(uint32_t k) {
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// LDS arrays indexed by rank are read in blocks of 16 consecutive ranks per thread; one pad
+// word per 16 entries spreads those blocks over the LDS banks (unpadded, all lanes of a wave
+// would hit the same one or two banks).
+__device__ __forceinline__ int rpad(int k) { return k + (k >> 4); }
+constexpr int rpad_size(int n) { return n + (n >> 4) + 1; }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
 // Lanes of the wave holding the same 8-bit digit (all 64 lanes must be active).
@@ -111,14 +117,14 @@ __device__ __forceinline__ int leaf_hull(const double* S, int lo, int hi, uint16
   int p0 = 0, p1 = 0;  // top and second-from-top ranks
   double s0 = 0.0, s1 = 0.0;
   for (int k = lo; k <= hi; ++k) {
-    const double sk = S[k];
+    const double sk = S[rpad(k)];
     while (n >= 2 && !below(p1, s1, p0, s0, k, sk)) {
       --n;  // collision: the top block sticks to the incoming one
       p0 = p1;
       s0 = s1;
       if (n >= 2) {
         p1 = st[n - 2];
-        s1 = S[p1];
+        s1 = S[rpad(p1)];
       }
     }
     st[n++] = (uint16_t)k;
@@ -211,15 +217,15 @@ __device__ void bridge(const LV& L, int p, const RV& R, int q, int* istar, int* 
   *jstar = jhi;
 }
 
-// Chains stored as rank lists in LDS, S read from LDS.
+// Chains stored as rank lists in LDS, S (rank-padded) read from LDS.
 struct LdsChain {
   const uint16_t* v;
   const double* S;
   __device__ __forceinline__ int pos(int i) const { return v[i]; }
-  __device__ __forceinline__ double s(int i) const { return S[v[i]]; }
+  __device__ __forceinline__ double s(int i) const { return S[rpad(v[i])]; }
 };
 
-// Lower hull (collinear points dropped) of the points 0..d of S, computed by NT threads with
+// Lower hull (collinear points dropped) of the points 0..d of S (indexed through rpad), computed by NT threads with
 // E ranks per leaf.  vert must hold NT*(E+1) entries, cnt NT ints, mres NT ints.  On return
 // vert[0..cnt[0]) are the hull vertices (0 and d included).  All threads of the block must call;
 // requires 1 <= d <= NT*E.
@@ -275,6 +281,148 @@ __device__ void tile_hull(const double* S, int d, uint16_t* vert, int* cnt, int*
     }
     if (s == 0 && istar >= 0) cnt[m << lvl] = istar + 1 + len;
     __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------- ImminentCollisions
+// A candidate vertex: rank position and its S value; pos < 0 means "none".
+struct Cand {
+  int pos;
+  double s;
+};
+
+// Per thread, the last candidate held by lower threads (lc) and the first candidate held by
+// higher threads (rc, default dflt).  shL / shR need NT/64 entries each.  All threads must call.
+template <int NT>
+__device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, Cand* shL, Cand* shR, Cand* lc,
+                                            Cand* rc) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  Cand a = mineL, b = mineR;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int ap = __shfl_up(a.pos, o, kWave);
+    const double as = __shfl_up(a.s, o, kWave);
+    if (lane >= o && a.pos < 0) {
+      a.pos = ap;
+      a.s = as;
+    }
+    const int bp = __shfl_down(b.pos, o, kWave);
+    const double bs = __shfl_down(b.s, o, kWave);
+    if (lane + o < kWave && b.pos < 0) {
+      b.pos = bp;
+      b.s = bs;
+    }
+  }
+  Cand l, r;
+  l.pos = __shfl_up(a.pos, 1, kWave);
+  l.s = __shfl_up(a.s, 1, kWave);
+  if (lane == 0) l.pos = -1;
+  r.pos = __shfl_down(b.pos, 1, kWave);
+  r.s = __shfl_down(b.s, 1, kWave);
+  if (lane == kWave - 1) r.pos = -1;
+  if (lane == kWave - 1) shL[wv] = a;
+  if (lane == 0) shR[wv] = b;
+  __syncthreads();
+  if (l.pos < 0)
+    for (int w = wv - 1; w >= 0; --w)
+      if (shL[w].pos >= 0) {
+        l = shL[w];
+        break;
+      }
+  if (r.pos < 0)
+    for (int w = wv + 1; w < NW; ++w)
+      if (shR[w].pos >= 0) {
+        r = shR[w];
+        break;
+      }
+  if (r.pos < 0) r = dflt;
+  __syncthreads();
+  *lc = l;
+  *rc = r;
+}
+
+// ImminentCollisions rounds (Sec. 4.1; Alg. imminent_collisions_v2) on hull candidates: thread t
+// owns points k0 = t*E .. k0+E-1 (bit i of *bm = point k0+i is a candidate), point d is the fixed
+// right end.  Every round removes, all at once, each candidate that is not strictly below the
+// segment joining its neighbouring candidates (the blocks on either side collide: avg y left >=
+// avg y right), and repeats until nothing changes.  Returns true on convergence within max_rounds
+// (candidates = hull vertices, *lc / *rc = carries of the final candidate set), false otherwise.
+// sv[0..E] are this thread's S values (sv[i] = S_{k0+i}); S is the rank-padded LDS copy.
+template <int NT, int E>
+__device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, int max_rounds, uint32_t* bm,
+                           Cand* lc, Cand* rc, Cand* shL, Cand* shR) {
+  const int k0 = threadIdx.x * E;
+  const Cand dflt{d, S[rpad(d)]};
+  uint32_t b = 0;
+#pragma unroll
+  for (int i = 0; i < E; ++i) b |= (k0 + i < d ? 1u : 0u) << i;
+  for (int round = 0; round < max_rounds; ++round) {
+    Cand mineL{-1, 0.0}, mineR{-1, 0.0};
+    if (b) {
+      const int hi = 31 - __clz(b);
+      const int lo = __ffs(b) - 1;
+      mineL.pos = k0 + hi;
+      mineL.s = S[rpad(k0 + hi)];
+      mineR.pos = k0 + lo;
+      mineR.s = S[rpad(k0 + lo)];
+    }
+    Cand l, r;
+    carry_scans<NT>(mineL, mineR, dflt, shL, shR, &l, &r);
+    uint32_t rem = 0;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const uint32_t below_i = b & ((1u << i) - 1u);
+      const uint32_t above_i = b & ~((2u << i) - 1u);
+      const int pp = below_i ? k0 + 31 - __clz(below_i) : l.pos;
+      const int np = above_i ? k0 + __ffs(above_i) - 1 : r.pos;
+      const double sp_l = S[rpad(min(max(pp, 0), d))];
+      const double sn_l = S[rpad(min(max(np, 0), d))];
+      const double sp = below_i ? sp_l : l.s;
+      const double sn = above_i ? sn_l : r.s;
+      const bool cand = (b >> i) & 1u;
+      if (cand && pp >= 0 && !below(pp, sp, k0 + i, sv[i], np, sn)) rem |= 1u << i;
+    }
+    b &= ~rem;
+    if (!__syncthreads_or(rem != 0)) {
+      *bm = b;
+      *lc = l;
+      *rc = r;
+      return true;
+    }
+  }
+  *bm = b;
+  return false;
+}
+
+// Cluster value of every rank owned by this thread from its final cluster starts: bm (bit i =
+// rank k0+i starts a cluster), sv[0..E] (S at k0..k0+E), carries lc (last start before k0) and
+// rc (first start after the thread's ranks, or the end point d).  Rank k0+i gets
+// offset + (S_b - S_a) / (b - a) for its cluster [a, b); res[idx[rpad(k)]] receives it.
+template <int E>
+__device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 1], const double* S, Cand lc,
+                                            Cand rc, int d, double offset, const uint16_t* idx, float* res) {
+  const int k0 = threadIdx.x * E;
+  if (k0 >= d) return;
+  // cluster entering the thread's range (starts before k0 unless bit 0 is set)
+  const int f0 = bm ? __ffs(bm) - 1 : -1;
+  const int e0 = f0 >= 0 ? k0 + f0 : rc.pos;
+  const double se0 = f0 >= 0 ? S[rpad(k0 + f0)] : rc.s;
+  float cur = lc.pos >= 0 ? (float)(offset + (se0 - lc.s) / (double)(e0 - lc.pos)) : 0.0f;
+  float val[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const uint32_t above_i = bm & ~((2u << i) - 1u);
+    const int np = above_i ? k0 + __ffs(above_i) - 1 : rc.pos;
+    const double sn_l = S[rpad(min(max(np, 0), d))];
+    const double sn = above_i ? sn_l : rc.s;
+    val[i] = (float)(offset + (sn - sv[i]) / (double)(np - (k0 + i)));
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    if ((bm >> i) & 1u) cur = val[i];
+    if (k0 + i < d) res[idx[rpad(k0 + i)]] = cur;
   }
 }
 

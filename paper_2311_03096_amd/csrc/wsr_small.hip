@@ -21,15 +21,21 @@ template <int TMAX, int NT>
 struct FwdSmem {
   static constexpr int E = TMAX / NT;
   static constexpr int NW = NT / kWave;
+  // arrays indexed by rank use rpad(); arrays indexed by original index or cluster do not
   union {
-    uint32_t key[TMAX];  // sort keys; sorted keys after the sort
-    float cval[TMAX];    // per-cluster values (output phase)
-    float g[TMAX];       // backward: upstream gradient by original index
+    uint32_t key[rpad_size(TMAX)];  // sort keys; sorted keys after the sort (rank-padded)
+    float cval[TMAX];               // per-cluster values (hull-merge output phase)
+    float outv[TMAX];               // results by original index (rounds output phase)
+    float g[TMAX];                  // backward: upstream gradient by original index
   } a;
-  uint16_t idx[TMAX];  // payload: segment-local original index (perm after the sort)
+  uint16_t idx[rpad_size(TMAX)];  // payload: original index of each rank (rank-padded)
   union {
-    double S[TMAX + 1];  // prefix sums (forward) / G (backward)
-    float outv[TMAX];    // results by original index (output phase)
+    double S[rpad_size(TMAX + 1)];  // prefix sums (forward) / G (backward), rank-padded
+    float outv[TMAX];               // results by original index (output phase)
+    struct {
+      uint32_t start[TMAX + 1];  // bucket sort: per-bucket counts, then starts
+      uint32_t tkey[TMAX];       // bucket sort: keys in bucket order
+    } bs;
   } c;
   union {
     uint32_t wcnt[NW][256];
@@ -38,12 +44,18 @@ struct FwdSmem {
       int cnt[NT];
       int mres[NT];
     } h;
+    uint16_t tidx[TMAX];  // bucket sort: indices in bucket order
   } d;
   uint32_t lmask[TMAX / 32 + 2];
   double dred[NW + 1];
   int ired[NW + 1];
+  uint32_t ured[2 * NW];
+  Cand shL[NW], shR[NW];
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
+
+// ImminentCollisions rounds tried before the hull merge (typical weights converge in 2-4).
+constexpr int kIcaRounds = 6;
 
 __device__ __forceinline__ void resolve_segment(const SegArgs& a, int64_t* start, int* d, float* lam) {
   if (a.sched) {
@@ -80,8 +92,8 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
   for (int r = 0; r < IPT; ++r) {
     if (r < nr) {
       const int p = wbase + r * kWave + lane;
-      sm.a.key[p] = k[r];
-      sm.idx[p] = ix[r];
+      sm.a.key[rpad(p)] = k[r];
+      sm.idx[rpad(p)] = ix[r];
     }
   }
   for (int pass = 0; pass < 4; ++pass) {
@@ -137,8 +149,8 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
       if (r < nr) {
         const uint32_t dg = (k[r] >> shift) & 255u;
         const int np = (int)sm.d.wcnt[wv][dg] + rk[r];
-        sm.a.key[np] = k[r];
-        sm.idx[np] = ix[r];
+        sm.a.key[rpad(np)] = k[r];
+        sm.idx[rpad(np)] = ix[r];
       }
     }
     __syncthreads();
@@ -146,12 +158,161 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
     for (int r = 0; r < IPT; ++r) {
       if (r < nr) {
         const int p = wbase + r * kWave + lane;
-        k[r] = sm.a.key[p];
-        ix[r] = sm.idx[p];
+        k[r] = sm.a.key[rpad(p)];
+        ix[r] = sm.idx[rpad(p)];
       }
     }
     __syncthreads();
   }
+}
+
+// Bucket-rank sort of the register-held items (any layout) into sm.a.key / sm.idx.
+// Keys are spread over NB = TMAX buckets by a monotone map of their value over [min, max].  One
+// atomic pass counts the keys per bucket and gives each key its position inside its bucket; a
+// scan turns counts into bucket starts; keys are placed in bucket order; finally each key's rank
+// is its bucket's start plus the number of keys of the bucket that precede it in (key, index)
+// order.  The result is the same total order the stable radix sort produces.  Returns false
+// (sorted arrays untouched) when some bucket holds more than kBucketMax keys, so that skewed or
+// tie-heavy segments keep a bounded cost by taking the radix sort instead.
+template <int TMAX, int NT>
+__device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMAX / NT],
+                                  const uint16_t (&ix)[TMAX / NT], int d) {
+  constexpr int IPT = TMAX / NT;
+  constexpr int NW = NT / kWave;
+  constexpr int NB = TMAX;
+  constexpr int BPT = NB / NT;  // buckets per thread in the scan
+  constexpr int kBucketMax = 48;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / kWave;
+  const int wbase = wv * kWave * IPT;
+  uint32_t* start = sm.c.bs.start;
+  uint32_t* tkey = sm.c.bs.tkey;
+  uint16_t* tidx = sm.d.tidx;
+
+  uint32_t kmn = 0xFFFFFFFFu, kmx = 0u;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    if (p < d) {
+      kmn = min(kmn, k[r]);
+      kmx = max(kmx, k[r]);
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    kmn = min(kmn, (uint32_t)__shfl_xor((int)kmn, o, kWave));
+    kmx = max(kmx, (uint32_t)__shfl_xor((int)kmx, o, kWave));
+  }
+  if (lane == 0) {
+    sm.ured[2 * wv] = kmn;
+    sm.ured[2 * wv + 1] = kmx;
+  }
+  for (int j = tid; j < NB; j += NT) start[j] = 0u;
+  __syncthreads();
+  kmn = sm.ured[0];
+  kmx = sm.ured[1];
+  for (int w = 1; w < NW; ++w) {
+    kmn = min(kmn, sm.ured[2 * w]);
+    kmx = max(kmx, sm.ured[2 * w + 1]);
+  }
+  if (kmn == kmx) {  // every key equal: index order is sorted
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const int p = wbase + r * kWave + lane;
+      if (p < d) {
+        sm.a.key[rpad(ix[r])] = k[r];
+        sm.idx[rpad(ix[r])] = ix[r];
+      }
+    }
+    __syncthreads();
+    return true;
+  }
+  const float mn = key_to_float(kmn);
+  const float scale = (float)NB / (key_to_float(kmx) - mn);
+  if (!(scale > 0.0f) || isinf(scale)) return false;  // uniform: range overflow or denormal span
+  int bk[IPT];
+  uint16_t loc[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    bk[r] = 0;
+    loc[r] = 0;
+    if (p < d) {
+      const int b = (int)((key_to_float(k[r]) - mn) * scale);
+      bk[r] = min(max(b, 0), NB - 1);
+      loc[r] = (uint16_t)atomicAdd(&start[bk[r]], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t c[BPT];
+  int sum = 0;
+  int cmax = 0;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    c[i] = start[tid * BPT + i];
+    sum += (int)c[i];
+    cmax = max(cmax, (int)c[i]);
+  }
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, kWave));
+  int total;
+  int run = block_excl_scan<NT, int>(sum, sm.ired, &total);
+  if (lane == 0) sm.ured[wv] = (uint32_t)cmax;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    start[tid * BPT + i] = (uint32_t)run;
+    run += (int)c[i];
+  }
+  if (tid == NT - 1) start[NB] = (uint32_t)total;
+  __syncthreads();
+  cmax = (int)sm.ured[0];
+  for (int w = 1; w < NW; ++w) cmax = max(cmax, (int)sm.ured[w]);
+  if (cmax > kBucketMax) return false;  // uniform
+  int lo[IPT], cnt[IPT];
+  int jmax = 0;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {  // loads unconditional (bk = 0 for padding) so they overlap
+    const int p = wbase + r * kWave + lane;
+    const int s0 = (int)start[bk[r]];
+    const int s1 = (int)start[bk[r] + 1];
+    lo[r] = p < d ? s0 : 0;
+    cnt[r] = p < d ? s1 - s0 : 0;
+    jmax = max(jmax, cnt[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    if (p < d) {
+      tkey[lo[r] + loc[r]] = k[r];
+      tidx[lo[r] + loc[r]] = ix[r];
+    }
+  }
+  __syncthreads();
+  // rank = bucket start + keys of the bucket before this one; the items advance together and
+  // every load is unconditional, so one LDS round trip serves all items of a step
+  int rank[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) rank[r] = lo[r];
+  for (int j = 0; j < jmax; ++j) {
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const int jj = min(lo[r] + j, d - 1);
+      const uint32_t kj = tkey[jj];
+      const uint16_t ij = tidx[jj];
+      rank[r] += (j < cnt[r]) & ((kj < k[r]) | ((kj == k[r]) & (ij < ix[r])));
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    if (p < d) {
+      sm.a.key[rpad(rank[r])] = k[r];
+      sm.idx[rpad(rank[r])] = ix[r];
+    }
+  }
+  __syncthreads();
+  return true;
 }
 
 // Given the cluster-start list vert[0..ncl] (ranks, vert[ncl] == d) and per-cluster values
@@ -180,7 +341,7 @@ __device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int
       next = vert[cid + 1];
       v = cval[cid];
     }
-    res[idx[k]] = v;
+    res[idx[rpad(k)]] = v;
   }
 }
 
@@ -204,17 +365,18 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
   for (int j = tid; j < TMAX / 32 + 2; j += NT) sm.lmask[j] = 0u;
   uint32_t k[IPT];
   uint16_t ix[IPT];
+  float f[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {  // all loads in flight before any use
+    const int p = wbase + r * kWave + lane;
+    f[r] = p < d ? w[start + p] : 0.0f;
+  }
   int bad = 0;
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const int p = wbase + r * kWave + lane;
-    if (p < d) {
-      const float f = w[start + p];
-      bad |= !isfinite(f);
-      k[r] = float_to_key(f);
-    } else {
-      k[r] = 0xFFFFFFFFu;
-    }
+    bad |= (p < d) & !isfinite(f[r]);
+    k[r] = p < d ? float_to_key(f[r]) : 0xFFFFFFFFu;
     ix[r] = (uint16_t)p;
   }
   const bool nonfinite = __syncthreads_or(bad) != 0;
@@ -234,10 +396,10 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
     return;
   }
 
-  block_radix_sort<TMAX, NT>(sm, k, ix, d);
+  if (!block_bucket_sort<TMAX, NT>(sm, k, ix, d)) block_radix_sort<TMAX, NT>(sm, k, ix, d);
 
   // centred FP64 prefix sums S_k (blocked: thread t owns ranks [tE, tE+E))
-  const double c = (double)key_to_float(sm.a.key[d >> 1]);
+  const double c = (double)key_to_float(sm.a.key[rpad(d >> 1)]);
   const double lamd = (double)lam / (double)(d - 1);
   const int k0 = tid * E;
   double xs[E];
@@ -245,35 +407,56 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int kk = k0 + i;
-    xs[i] = kk < d ? (double)key_to_float(sm.a.key[kk]) - c : 0.0;
+    const double xv = (double)key_to_float(sm.a.key[rpad(min(kk, d - 1))]) - c;  // unconditional load
+    xs[i] = kk < d ? xv : 0.0;
     lsum += xs[i];
   }
   double Xk = block_excl_scan<NT, double>(lsum, sm.dred, (double*)nullptr);
+  double sv[E + 1];
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
+  for (int i = 0; i <= E; ++i) {
     const int kk = k0 + i;
-    if (kk <= d) sm.c.S[kk] = Xk + lamd * (double)kk * (double)(d - kk);
-    Xk += xs[i];
+    sv[i] = Xk + lamd * (double)kk * (double)(d - kk);
+    if (i < E) {
+      if (kk <= d) sm.c.S[rpad(kk)] = sv[i];
+      Xk += xs[i];
+    }
   }
-  if (tid == NT - 1 && d == TMAX) sm.c.S[TMAX] = Xk;  // X_d (the shift term vanishes at k = d)
+  if (tid == NT - 1 && d == TMAX) sm.c.S[rpad(TMAX)] = sv[E];  // X_d (the shift term vanishes at k = d)
   __syncthreads();
 
-  tile_hull<NT, E>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
-
-  // cluster values: c + (S_b - S_a)/(b - a) for consecutive hull vertices a < b
-  const int nv = sm.d.h.cnt[0];
-  const uint16_t* vert = sm.d.h.vert;
-  for (int i = tid; i < nv - 1; i += NT) {
-    const int a = vert[i], b = vert[i + 1];
-    sm.a.cval[i] = (float)(c + (sm.c.S[b] - sm.c.S[a]) / (double)(b - a));
-    atomicOr(&sm.lmask[(a + off) >> 5], 1u << ((a + off) & 31));
+  // collisions: ImminentCollisions rounds (converge in a few rounds on typical weights), else
+  // the bounded-depth hull merge
+  uint32_t bm;
+  Cand lc, rc;
+  const float* res;
+  if (ica_rounds<NT, E>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR)) {
+    if (bm) {
+      const int b0 = k0 + off;
+      const uint64_t wide = (uint64_t)bm << (b0 & 31);
+      atomicOr(&sm.lmask[b0 >> 5], (uint32_t)wide);
+      if (wide >> 32) atomicOr(&sm.lmask[(b0 >> 5) + 1], (uint32_t)(wide >> 32));
+    }
+    walk_values<E>(bm, sv, sm.c.S, lc, rc, d, c, sm.idx, sm.a.outv);
+    res = sm.a.outv;
+  } else {
+    tile_hull<NT, E>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
+    // cluster values: c + (S_b - S_a)/(b - a) for consecutive hull vertices a < b
+    const int nv = sm.d.h.cnt[0];
+    const uint16_t* vert = sm.d.h.vert;
+    for (int i = tid; i < nv - 1; i += NT) {
+      const int a = vert[i], b = vert[i + 1];
+      sm.a.cval[i] = (float)(c + (sm.c.S[rpad(b)] - sm.c.S[rpad(a)]) / (double)(b - a));
+      atomicOr(&sm.lmask[(a + off) >> 5], 1u << ((a + off) & 31));
+    }
+    __syncthreads();
+    scatter_cluster_values<NT, E>(vert, nv - 1, sm.a.cval, sm.idx, sm.c.outv, d);
+    res = sm.c.outv;
   }
   __syncthreads();
-  scatter_cluster_values<NT, E>(vert, nv - 1, sm.a.cval, sm.idx, sm.c.outv, d);
-  __syncthreads();
-  for (int i = tid; i < d; i += NT) out[start + i] = sm.c.outv[i];
+  for (int i = tid; i < d; i += NT) out[start + i] = res[i];
   if (perm_out)
-    for (int i = tid; i < d; i += NT) perm_out[start + i] = sm.idx[i];
+    for (int i = tid; i < d; i += NT) perm_out[start + i] = sm.idx[rpad(i)];
   if (mask_out) store_mask_words<NT>(mask_out, start, d, sm.lmask);
 }
 
@@ -293,52 +476,51 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   const int64_t g0 = start >> 5;
   for (int i = tid; i < d; i += NT) {
     sm.a.g[i] = gin[start + i];
-    int p = perm_in[start + i];
-    sm.idx[i] = (uint16_t)min(max(p, 0), d - 1);
+    const int p = perm_in[start + i];
+    sm.idx[rpad(i)] = (uint16_t)min(max(p, 0), d - 1);
   }
   for (int j = tid; j < nwords; j += NT) sm.lmask[j] = mask_in[g0 + j];
   __syncthreads();
-  // gathered cotangent in rank order, cluster starts, FP64 prefix sums
+  // cotangent in rank order, cluster starts of the thread's ranks, FP64 prefix sums G
   const int k0 = tid * E;
   float gk[E];
   double lsum = 0.0;
-  int lst = 0;
+  uint32_t bm = 0;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int kk = k0 + i;
-    gk[i] = 0.0f;
-    if (kk < d) {
-      gk[i] = sm.a.g[sm.idx[kk]];
-      lsum += (double)gk[i];
-      const int b = kk + off;
-      lst += (kk == 0) || ((sm.lmask[b >> 5] >> (b & 31)) & 1u);
-    }
+    const int kc = min(kk, d - 1);
+    const float gv = sm.a.g[sm.idx[rpad(kc)]];  // unconditional gather
+    const int b = kc + off;
+    const uint32_t st = (kk == 0) | ((sm.lmask[b >> 5] >> (b & 31)) & 1u);
+    gk[i] = kk < d ? gv : 0.0f;
+    lsum += (double)gk[i];
+    bm |= (kk < d ? st : 0u) << i;
   }
-  int ncl;
-  const int cbase = block_excl_scan<NT, int>(lst, sm.ired, &ncl);
   double G = block_excl_scan<NT, double>(lsum, sm.dred, (double*)nullptr);
-  int ci = cbase;
+  double sv[E + 1];
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int kk = k0 + i;
-    if (kk <= d) sm.c.S[kk] = G;
-    if (kk < d) {
-      const int b = kk + off;
-      if ((kk == 0) || ((sm.lmask[b >> 5] >> (b & 31)) & 1u)) sm.d.h.vert[ci++] = (uint16_t)kk;
+  for (int i = 0; i <= E; ++i) {
+    sv[i] = G;
+    if (i < E) {
+      if (k0 + i <= d) sm.c.S[rpad(k0 + i)] = G;
       G += (double)gk[i];
     }
   }
-  if (tid == NT - 1 && d == TMAX) sm.c.S[TMAX] = G;
-  if (tid == 0) sm.d.h.vert[ncl] = (uint16_t)d;
+  if (tid == NT - 1 && d == TMAX) sm.c.S[rpad(TMAX)] = sv[E];
   __syncthreads();
-  for (int i = tid; i < ncl; i += NT) {
-    const int a = sm.d.h.vert[i], b = sm.d.h.vert[i + 1];
-    sm.a.cval[i] = (float)((sm.c.S[b] - sm.c.S[a]) / (double)(b - a));
+  Cand mineL{-1, 0.0}, mineR{-1, 0.0};
+  if (bm) {
+    const int hi = 31 - __clz(bm);
+    const int lo = __ffs(bm) - 1;
+    mineL = Cand{k0 + hi, sm.c.S[rpad(k0 + hi)]};
+    mineR = Cand{k0 + lo, sm.c.S[rpad(k0 + lo)]};
   }
+  Cand lc, rc;
+  carry_scans<NT>(mineL, mineR, Cand{d, sm.c.S[rpad(d)]}, sm.shL, sm.shR, &lc, &rc);
+  walk_values<E>(bm, sv, sm.c.S, lc, rc, d, 0.0, sm.idx, sm.a.outv);
   __syncthreads();
-  scatter_cluster_values<NT, E>(sm.d.h.vert, ncl, sm.a.cval, sm.idx, sm.c.outv, d);
-  __syncthreads();
-  for (int i = tid; i < d; i += NT) gout[start + i] = sm.c.outv[i];
+  for (int i = tid; i < d; i += NT) gout[start + i] = sm.a.outv[i];
 }
 
 // Zero a word array (used for the saved cluster-start mask before OR-ing boundary words).
