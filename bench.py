@@ -25,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "prox_R elements/s + % HBM roofline at d=2^24; batched vs per-row launch speedup"
+WORKLOAD_TEXT = {
+    "chain": "worst-case collision chain: one FP32 segment d=2^24, w_k=(k/(d-1))^2, lam=0.7 "
+             "(one final cluster); step = forward with saved state + backward",
+    "typical": "one N(0,1) FP32 segment d=2^24, lam=0.1; step = forward with saved state + backward",
+}
 
 # Algorithmic HBM bytes per element that each kernel must move (compulsory traffic of its role
 # in the path; see the design notes).  "el" = elements of the segment(s) the launch covers.
@@ -49,6 +54,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the typical and batched figures")
+    ap.add_argument("--workload", choices=["chain", "typical", "mlp"], default="chain",
+                    help="chain (default, the headline), or run only the typical d=2^24 vector or the "
+                         "batched MLP rows (for profiling one workload)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="first run one plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -155,7 +165,7 @@ def cpu_baseline(case):
                 % (case["name"], w.shape[0], dt))
 
 
-def batched_vs_per_row(steps, warmup):
+def batched_vs_per_row(steps, warmup, per_row=True):
     """MLP rows (8202 segments, 29.4M weights): fwd+bwd, graph-captured batched launches vs
     per-row launches of the plain entry points on the same stream."""
     import torch
@@ -163,7 +173,7 @@ def batched_vs_per_row(steps, warmup):
     case = workloads.mlp_rows()
     n = case["w"].shape[0]
     b = Step(case, batched=True)
-    p = Step(case, batched=False)
+    p = Step(case, batched=False) if per_row else None
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -174,7 +184,7 @@ def batched_vs_per_row(steps, warmup):
         b()
     ms_graph, _ = time_steps(graph.replay, steps, warmup)
     ms_batched, _ = time_steps(b, steps, warmup)
-    ms_rows, _ = time_steps(p, max(2, steps // 4), 1)
+    ms_rows = time_steps(p, max(2, steps // 4), 1)[0] if per_row else float("nan")
     tr = trace_kernels(b, 3)
     roof = roofline({k: v for k, v in tr.items() if k.startswith("prox_fwd")}, n, 3)
     return dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
@@ -195,9 +205,22 @@ def main():
     from paper_2311_03096_amd import workloads
     wsr.load()  # fails loudly when the HIP library is missing
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calib > 0:
+        n = args.copy_calib // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (4 * n, 4 * n))
+        del src, dst
 
     d = 1 << 24
-    case = workloads.chain(d, 0.7)
+    if args.workload == "mlp":
+        res = batched_vs_per_row(max(5, args.steps), args.warmup, per_row=not args.no_extra)
+        print(json.dumps(res), flush=True)
+        return
+    case = workloads.chain(d, 0.7) if args.workload == "chain" else workloads.plain(d, 0.1, seed=1)
     log("workload", case["name"], "steps", args.steps, "warmup", args.warmup)
     step = Step(case)
     ms, wall = time_steps(step, args.steps, args.warmup)
@@ -220,9 +243,8 @@ def main():
     res = dict(metric=METRIC, value=d / (ms * 1e-3), unit="elements/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",
-               config=dict(workload="worst-case collision chain: one FP32 segment d=2^24, w_k=(k/(d-1))^2, "
-                                    "lam=0.7 (one final cluster); step = forward with saved state + backward",
-                           d=d, lam=0.7, parallelism="single GPU"),
+               config=dict(workload=WORKLOAD_TEXT[args.workload], d=d, lam=float(case["lam"]),
+                           parallelism="single GPU"),
                roofline=roof)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(case)

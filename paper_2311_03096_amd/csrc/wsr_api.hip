@@ -35,6 +35,14 @@ inline int size_class(int64_t d) {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// True when every segment starts at a multiple of 32: then no cluster-start mask word is shared
+// by two segments and every word is written with a plain store, so no zero fill is needed.
+bool offsets_word_aligned(const int64_t* h_offsets, int64_t n_seg) {
+  for (int64_t s = 0; s <= n_seg; ++s)
+    if (h_offsets[s] & 31) return false;
+  return true;
+}
+
 int validate_offsets(const int64_t* h_offsets, int64_t n_seg, int64_t* max_big) {
   if (!h_offsets || n_seg < 0) return WSR_ERR_INVALID;
   if (h_offsets[0] != 0) return WSR_ERR_INVALID;
@@ -280,6 +288,7 @@ struct wsr_plan {
   int64_t sched_cnt[kNumSmall] = {0, 0, 0};
   std::vector<int64_t> h_offsets;
   std::vector<int32_t> big_segs;  // long segments, in order
+  bool word_aligned = false;      // every offset a multiple of 32 (no mask zero fill needed)
 };
 
 extern "C" {
@@ -319,7 +328,7 @@ int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   const int64_t total = h_offsets[n_seg];
-  if (saved_mask) zero_words(saved_mask, ceil_div(total, 32), s);
+  if (saved_mask && !offsets_word_aligned(h_offsets, n_seg)) zero_words(saved_mask, ceil_div(total, 32), s);
   for (int64_t seg = 0; seg < n_seg; ++seg) {
     const int64_t start = h_offsets[seg];
     const int64_t d = h_offsets[seg + 1] - start;
@@ -375,6 +384,7 @@ int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan
   p->total = h_offsets[n_seg];
   p->max_big = mb;
   p->h_offsets.assign(h_offsets, h_offsets + n_seg + 1);
+  p->word_aligned = offsets_word_aligned(h_offsets, n_seg);
   (void)hipGetDevice(&p->device);
   // schedules: segments of each class, longest first (short tail of the launch)
   std::vector<int32_t> cls_list[kNumSmall];
@@ -443,7 +453,7 @@ int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out, c
   const size_t need = big_bytes(plan->max_big);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  if (saved_mask) zero_words(saved_mask, ceil_div(plan->total, 32), s);
+  if (saved_mask && !plan->word_aligned) zero_words(saved_mask, ceil_div(plan->total, 32), s);
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};

@@ -46,7 +46,17 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
       } else {
         key = ksrc[p];
       }
-      atomicAdd(&h[(key >> shift) & 255u], 1u);
+      const uint32_t dg = (key >> shift) & 255u;
+      // a wave whose lanes all hold the same digit (long runs in sorted or clustered data)
+      // adds once instead of 64 serialised atomics on one LDS address
+      // (the active mask is taken before the leader branch, where only one lane is active)
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+      const unsigned long long act = __ballot(1);
+      if (__ballot(dg == d0) == act) {
+        if (lane_id() == __ffsll(act) - 1) atomicAdd(&h[d0], (uint32_t)__popcll(act));
+      } else {
+        atomicAdd(&h[dg], 1u);
+      }
     }
   }
   if (wsrc) {
@@ -58,21 +68,28 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
 }
 
 // Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
+// The row goes through LDS so global reads and writes are coalesced.
 __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals) {
+  constexpr int kMaxRow = 16384;  // tiles of the longest segment (2^26 / kRadixTile)
+  __shared__ uint32_t row_s[kMaxRow];
   __shared__ int sh[256 / kWave + 1];
   uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  for (int i = threadIdx.x; i < ntiles; i += 256) row_s[i] = row[i];
+  __syncthreads();
   const int chunk = (ntiles + 255) / 256;
   const int lo = threadIdx.x * chunk;
   const int hi = min(lo + chunk, ntiles);
   int s = 0;
-  for (int i = lo; i < hi; ++i) s += (int)row[i];
+  for (int i = lo; i < hi; ++i) s += (int)row_s[i];
   int total;
   int run = block_excl_scan<256, int>(s, sh, &total);
   for (int i = lo; i < hi; ++i) {
-    const int c = (int)row[i];
-    row[i] = (uint32_t)run;
+    const int c = (int)row_s[i];
+    row_s[i] = (uint32_t)run;
     run += c;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ntiles; i += 256) row[i] = row_s[i];
   if (threadIdx.x == 0) totals[blockIdx.x] = (uint32_t)total;
 }
 
@@ -100,6 +117,9 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const float* ws
   const int wbase = wv * kWave * IPT;
   const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
 
+  // global offsets of this tile's digit runs, fetched first so their latency overlaps the ranking
+  const uint32_t tot_digit = totals[tid];
+  const uint32_t tile_pre = hist[(int64_t)tid * ntiles + blockIdx.x];
   uint32_t k[IPT];
   int32_t v[IPT];
 #pragma unroll
@@ -144,8 +164,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const float* ws
   tstart[tid] = (uint32_t)dstart;
   // global base of this digit = sum of all smaller digits' totals + this digit's tiles before us
   int gt;
-  const int rowbase = block_excl_scan<kRadixThreads, int>((int)totals[tid], ish, &gt);
-  gofs[tid] = (uint32_t)rowbase + hist[(int64_t)tid * ntiles + blockIdx.x];
+  const int rowbase = block_excl_scan<kRadixThreads, int>((int)tot_digit, ish, &gt);
+  gofs[tid] = (uint32_t)rowbase + tile_pre;
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
@@ -177,6 +197,8 @@ struct TileSmem {
   int cnt[kBigThreads];
   int mres[kBigThreads];
   double dred[kBigThreads / kWave + 1];
+  int ired[kBigThreads / kWave + 1];
+  Cand shL[kBigThreads / kWave], shR[kBigThreads / kWave];
   double xtot;
 };
 
@@ -210,25 +232,52 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
     const int j = j0 + i;
-    xs[i] = j < np ? (double)key_to_float(sm.keys[rpad(j)]) - c : 0.0;
+    const double xv = (double)key_to_float(sm.keys[rpad(min(j, np - 1))]) - c;  // unconditional load
+    xs[i] = j < np ? xv : 0.0;
     lsum += xs[i];
   }
   double X = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
+  double sv[kBigE + 1];
 #pragma unroll
-  for (int i = 0; i < kBigE; ++i) {
+  for (int i = 0; i <= kBigE; ++i) {
     const int j = j0 + i;
-    if (j <= np) sm.S[rpad(j)] = X + lamd * (double)j * ((double)(d - 2 * k0) - (double)j);
-    if (j == np) sm.xtot = X;
-    X += xs[i];
+    sv[i] = X + lamd * (double)j * ((double)(d - 2 * k0) - (double)j);
+    if (i < kBigE) {
+      if (j <= np) sm.S[rpad(j)] = sv[i];
+      if (j == np) sm.xtot = X;
+      X += xs[i];
+    }
   }
   if (tid == kBigThreads - 1 && np == kBigTile) {
-    sm.S[rpad(kBigTile)] = X + lamd * (double)kBigTile * ((double)(d - 2 * k0) - (double)kBigTile);
+    sm.S[rpad(kBigTile)] = sv[kBigE];
     sm.xtot = X;
   }
   __syncthreads();
+  const int64_t vb = (int64_t)t * (kBigTile + 1);
+  uint32_t bm;
+  Cand lc, rc;
+  if (ica_rounds<kBigThreads, kBigE>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR)) {
+    // hull vertices = surviving candidates in rank order, then the tile's end point
+    int nv;
+    int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i) {
+      if ((bm >> i) & 1u) {
+        vpos[vb + at] = (int32_t)(k0 + j0 + i);
+        vS[vb + at] = sv[i];
+        ++at;
+      }
+    }
+    if (tid == 0) {
+      vpos[vb + nv] = (int32_t)(k0 + np);
+      vS[vb + nv] = sm.S[rpad(np)];
+      hcnt[t] = nv + 1;
+      tsum[t] = sm.xtot;
+    }
+    return;
+  }
   tile_hull<kBigThreads, kBigE>(sm.S, np, sm.vert, sm.cnt, sm.mres);
   const int nv = sm.cnt[0];
-  const int64_t vb = (int64_t)t * (kBigTile + 1);
   for (int i = tid; i < nv; i += kBigThreads) {
     vpos[vb + i] = (int32_t)(k0 + sm.vert[i]);
     vS[vb + i] = sm.S[rpad(sm.vert[i])];
@@ -585,11 +634,9 @@ WSR_INSTANTIATE_MERGE(16384)
 // ------------------------------------------------------------------------------- apply
 
 struct ApplySmem {
-  int32_t lp[kBigTile + 2];
-  double ls[kBigTile + 2];   // global S at the vertex
-  double lsl[kBigTile + 2];  // tile-relative S' (valid where lloc)
-  int32_t perm[kBigTile];    // the tile's saved permutation, loaded coalesced
-  uint8_t lloc[kBigTile + 2];
+  int32_t lp[kBigTile + 2];        // [prev] + own vertices + [next]: ranks
+  double ls[kBigTile + 2];         // S' = S - S_{k0} for points of this tile, global S otherwise
+  float val[rpad_size(kBigTile)];  // value of each rank of the tile (rank-padded)
   uint32_t lmask[kBigTile / 32 + 2];
   int n;
 };
@@ -604,6 +651,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
                                                            const double* prev_s, const int32_t* next_pos,
                                                            const double* next_s, float* out,
                                                            uint32_t* mask_out, int64_t seg_start) {
+  constexpr int R = kBigTile / kBigThreads;
   __shared__ ApplySmem sm;
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -613,14 +661,24 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
   const bool nonfinite = (flags[0] & 1u) != 0;
   const bool identity = nonfinite || !(lam > 0.0f);
+  // the tile's permutation entries, lane-consecutive (stores below are coalesced when the
+  // permutation is locally ordered)
+  int64_t pl[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    pl[r] = j < np ? min((int64_t)max(perm[k0 + j], 0), d - 1) : 0;
+  }
   for (int j = tid; j < kBigTile / 32 + 2; j += kBigThreads) sm.lmask[j] = 0u;
   if (identity) {
     __syncthreads();
-    for (int j = tid; j < np; j += kBigThreads) {
-      const float x = key_to_float(skeys[k0 + j]);
-      const int64_t pl = min((int64_t)max(perm[k0 + j], 0), d - 1);
-      out[seg_start + pl] = nonfinite ? __builtin_nanf("") : x;
-      atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = tid + r * kBigThreads;
+      if (j < np) {
+        out[seg_start + pl[r]] = nonfinite ? __builtin_nanf("") : key_to_float(skeys[k0 + j]);
+        atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
+      }
     }
     __syncthreads();
     if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
@@ -633,37 +691,27 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   if (tid == 0) {
     sm.lp[0] = prev_pos[t];
-    sm.ls[0] = prev_s[t];
-    sm.lsl[0] = 0.0;  // the tile's first point has S' = 0
-    sm.lloc[0] = prev_pos[t] == k0;
+    sm.ls[0] = prev_pos[t] == k0 ? 0.0 : prev_s[t];  // the tile's first point has S' = 0
     const int nx = next_pos[t];
     sm.n = 1 + own + (nx >= 0 ? 1 : 0);
     if (nx >= 0) {
       sm.lp[1 + own] = nx;
       sm.ls[1 + own] = next_s[t];
-      sm.lsl[1 + own] = 0.0;
-      sm.lloc[1 + own] = 0;
     }
   }
-  for (int j = tid; j < np; j += kBigThreads) sm.perm[j] = perm[k0 + j];
   for (int i = tid; i < own; i += kBigThreads) {
-    const double sl = vS[vb + lo + i];
     sm.lp[1 + i] = vpos[vb + lo + i];
-    sm.ls[1 + i] = sl + toff;
-    sm.lsl[1 + i] = sl;
-    sm.lloc[1 + i] = 1;
+    sm.ls[1 + i] = vS[vb + lo + i];
   }
   __syncthreads();
   const int n = sm.n;
-  // cluster starts inside the tile
-  for (int i = tid; i < n; i += kBigThreads) {
+  for (int i = tid; i < n; i += kBigThreads) {  // cluster starts inside the tile
     const int64_t p = sm.lp[i];
     if (p >= k0 && p < k0 + np) {
       const int j = (int)(p - k0);
       atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
     }
   }
-  // values, blocked ranks
   const int j0 = tid * kBigE;
   if (j0 < np) {
     const int64_t kk0 = k0 + j0;
@@ -675,28 +723,42 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
       else
         b = mid;
     }
-    // edge value: tile-relative sums when both ends lie in this tile, global sums for bridges
+    // a cluster inside the tile uses S' (small numbers); a cluster reaching outside the tile uses
+    // global S formed exactly as the merge kernel forms it (vS + tile offset), so every tile it
+    // touches computes the identical value
     auto edge_value = [&](int e) -> float {
-      const double len = (double)(sm.lp[e + 1] - sm.lp[e]);
-      const double dS = (sm.lloc[e] && sm.lloc[e + 1]) ? sm.lsl[e + 1] - sm.lsl[e] : sm.ls[e + 1] - sm.ls[e];
-      return (float)(c + dS / len);
+      const int64_t pa = sm.lp[e], pb = sm.lp[e + 1];
+      const bool ina = pa >= k0 && pa <= k0 + np;
+      const bool inb = pb >= k0 && pb <= k0 + np;
+      double dS;
+      if (ina && inb) {
+        dS = sm.ls[e + 1] - sm.ls[e];
+      } else {
+        const double ga = ina ? (pa == k0 ? prev_s[t] : sm.ls[e] + toff) : sm.ls[e];
+        const double gb = inb ? sm.ls[e + 1] + toff : sm.ls[e + 1];
+        dS = gb - ga;
+      }
+      return (float)(c + dS / (double)(pb - pa));
     };
     int cur = a;
     int64_t nxt = sm.lp[cur + 1];
-    float val = edge_value(cur);
+    float v = edge_value(cur);
     const int j1 = min(j0 + kBigE, np);
     for (int j = j0; j < j1; ++j) {
-      const int64_t kk = k0 + j;
-      while (kk >= nxt && cur + 2 < n) {
+      while (k0 + j >= nxt && cur + 2 < n) {
         ++cur;
         nxt = sm.lp[cur + 1];
-        val = edge_value(cur);
+        v = edge_value(cur);
       }
-      const int64_t pl = min((int64_t)max(sm.perm[j], 0), d - 1);
-      out[seg_start + pl] = val;
+      sm.val[rpad(j)] = v;
     }
   }
   __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    if (j < np) out[seg_start + pl[r]] = sm.val[rpad(j)];
+  }
   if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
 }
 
@@ -780,17 +842,15 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
 }
 
 // One workgroup: tile offsets of G, and for every tile the last cluster start before it and the
-// first cluster start after its last local start (with global G values).  Carries are a
-// "last valid entry" scan: per-thread chunk summaries, a serial pass over 1024 summaries, then
-// each thread walks its chunk.
+// first cluster start after its last local start (with global G values).  The carries are
+// "last valid" / "first valid" scans over per-thread chunk summaries (wave shuffles + LDS).
 __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const int32_t* fpos,
                                                        const double* fG, const int32_t* lpos,
                                                        const double* lG, int ntiles, int64_t d,
                                                        double* tileoff, int32_t* prevp, double* prevG,
                                                        int32_t* nextp, double* nextG) {
   __shared__ double sh[1024 / kWave + 1];
-  __shared__ int cpos[1024];
-  __shared__ double cval[1024];
+  __shared__ Cand shL[1024 / kWave], shR[1024 / kWave];
   const int tid = threadIdx.x;
   const int chunk = (ntiles + 1023) / 1024;
   const int a = tid * chunk;
@@ -799,82 +859,26 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const
   for (int i = a; i < b; ++i) s += tsum[i];
   double total;
   double run = block_excl_scan<1024, double>(s, sh, &total);
+  Cand mineL{-1, 0.0}, mineR{-1, 0.0};
   for (int i = a; i < b; ++i) {
     tileoff[i] = run;
+    if (lpos[i] >= 0) mineL = Cand{lpos[i], run + lG[i]};
+    if (fpos[i] >= 0 && mineR.pos < 0) mineR = Cand{fpos[i], run + fG[i]};
     run += tsum[i];
   }
-  // forward: last start in my chunk
-  int mp = -1;
-  double mg = 0.0;
-  for (int i = a; i < b; ++i)
-    if (lpos[i] >= 0) {
-      mp = lpos[i];
-      mg = tileoff[i] + lG[i];
-    }
-  cpos[tid] = mp;
-  cval[tid] = mg;
-  __syncthreads();
-  if (tid == 0) {
-    int cp = 0;  // rank 0 always starts a cluster
-    double cg = 0.0;
-    for (int i = 0; i < 1024; ++i) {
-      const int p = cpos[i];
-      const double g = cval[i];
-      cpos[i] = cp;
-      cval[i] = cg;
-      if (p >= 0) {
-        cp = p;
-        cg = g;
-      }
-    }
-  }
-  __syncthreads();
-  int cp = cpos[tid];
-  double cg = cval[tid];
+  Cand lc, rc;
+  carry_scans<1024>(mineL, mineR, Cand{(int)d, total}, shL, shR, &lc, &rc);
+  if (lc.pos < 0) lc = Cand{0, 0.0};  // rank 0 always starts a cluster
+  // walk the chunk: previous start before each tile, next start after each tile
   for (int i = a; i < b; ++i) {
-    prevp[i] = cp;
-    prevG[i] = cg;
-    if (lpos[i] >= 0) {
-      cp = lpos[i];
-      cg = tileoff[i] + lG[i];
-    }
+    prevp[i] = lc.pos;
+    prevG[i] = lc.s;
+    if (lpos[i] >= 0) lc = Cand{lpos[i], tileoff[i] + lG[i]};
   }
-  __syncthreads();
-  // backward: first start in my chunk
-  mp = -1;
-  mg = 0.0;
-  for (int i = b - 1; i >= a; --i)
-    if (fpos[i] >= 0) {
-      mp = fpos[i];
-      mg = tileoff[i] + fG[i];
-    }
-  cpos[tid] = mp;
-  cval[tid] = mg;
-  __syncthreads();
-  if (tid == 0) {
-    int np_ = (int)d;
-    double ng = total;
-    for (int i = 1023; i >= 0; --i) {
-      const int p = cpos[i];
-      const double g = cval[i];
-      cpos[i] = np_;
-      cval[i] = ng;
-      if (p >= 0) {
-        np_ = p;
-        ng = g;
-      }
-    }
-  }
-  __syncthreads();
-  int np_ = cpos[tid];
-  double ng = cval[tid];
   for (int i = b - 1; i >= a; --i) {
-    nextp[i] = np_;
-    nextG[i] = ng;
-    if (fpos[i] >= 0) {
-      np_ = fpos[i];
-      ng = tileoff[i] + fG[i];
-    }
+    nextp[i] = rc.pos;
+    nextG[i] = rc.s;
+    if (fpos[i] >= 0) rc = Cand{fpos[i], tileoff[i] + fG[i]};
   }
 }
 
@@ -884,7 +888,7 @@ struct BwdApplySmem {
     float g[kBigTile];       // gathered cotangent (read before the list is built)
     double lg[kBigTile + 2];
   } u;
-  int32_t perm[kBigTile];
+  float val[rpad_size(kBigTile)];  // result of each rank of the tile (rank-padded)
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
   int n;
@@ -901,10 +905,14 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
   const int t = blockIdx.x;
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
+  constexpr int R = kBigTile / kBigThreads;
   const int j0 = tid * kBigE;
-  for (int j = tid; j < np; j += kBigThreads) {
-    sm.u.g[j] = gsorted[k0 + j];
-    sm.perm[j] = perm[k0 + j];
+  int64_t pl[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    pl[r] = j < np ? min((int64_t)max(perm[k0 + j], 0), d - 1) : 0;
+    if (j < np) sm.u.g[j] = gsorted[k0 + j];
   }
   __syncthreads();
   float gk[kBigE];
@@ -969,9 +977,14 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
         nxt = sm.lp[cur + 1];
         val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
       }
-      const int64_t pl = min((int64_t)max(sm.perm[j], 0), d - 1);
-      gout[seg_start + pl] = val;
+      sm.val[rpad(j)] = val;
     }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    if (j < np) gout[seg_start + pl[r]] = sm.val[rpad(j)];
   }
 }
 

@@ -285,6 +285,9 @@ __device__ void tile_hull(const double* S, int d, uint16_t* vert, int* cnt, int*
 }
 
 // ----------------------------------------------------------------------------- ImminentCollisions
+// Rounds tried before the hull merge (typical weights converge in 2-4 rounds).
+constexpr int kIcaRounds = 6;
+
 // A candidate vertex: rank position and its S value; pos < 0 means "none".
 struct Cand {
   int pos;

@@ -54,8 +54,6 @@ struct FwdSmem {
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
 
-// ImminentCollisions rounds tried before the hull merge (typical weights converge in 2-4).
-constexpr int kIcaRounds = 6;
 
 __device__ __forceinline__ void resolve_segment(const SegArgs& a, int64_t* start, int* d, float* lam) {
   if (a.sched) {
