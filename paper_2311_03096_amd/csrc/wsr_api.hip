@@ -172,17 +172,17 @@ void launch_small_bwd(int nblocks, const SegArgs& a, const float* g, float* gw, 
 void small_fwd(int cls, int nblocks, const SegArgs& a, const float* w, float* out, int32_t* perm,
                uint32_t* mask, hipStream_t s) {
   switch (cls) {
-    case kC2048: { WSR_TRACE("prox_fwd_small_2048", s); launch_small_fwd<2048, 128>(nblocks, a, w, out, perm, mask, s); } break;
-    case kC4096: { WSR_TRACE("prox_fwd_small_4096", s); launch_small_fwd<4096, 256>(nblocks, a, w, out, perm, mask, s); } break;
-    default: { WSR_TRACE("prox_fwd_small_8192", s); launch_small_fwd<8192, 512>(nblocks, a, w, out, perm, mask, s); } break;
+    case kC2048: { WSR_TRACE("prox_fwd_small_2048", s); launch_small_fwd<2048, 256>(nblocks, a, w, out, perm, mask, s); } break;
+    case kC4096: { WSR_TRACE("prox_fwd_small_4096", s); launch_small_fwd<4096, 512>(nblocks, a, w, out, perm, mask, s); } break;
+    default: { WSR_TRACE("prox_fwd_small_8192", s); launch_small_fwd<8192, 1024>(nblocks, a, w, out, perm, mask, s); } break;
   }
 }
 void small_bwd(int cls, int nblocks, const SegArgs& a, const float* g, float* gw, const int32_t* perm,
                const uint32_t* mask, hipStream_t s) {
   switch (cls) {
-    case kC2048: { WSR_TRACE("prox_bwd_small_2048", s); launch_small_bwd<2048, 128>(nblocks, a, g, gw, perm, mask, s); } break;
-    case kC4096: { WSR_TRACE("prox_bwd_small_4096", s); launch_small_bwd<4096, 256>(nblocks, a, g, gw, perm, mask, s); } break;
-    default: { WSR_TRACE("prox_bwd_small_8192", s); launch_small_bwd<8192, 512>(nblocks, a, g, gw, perm, mask, s); } break;
+    case kC2048: { WSR_TRACE("prox_bwd_small_2048", s); launch_small_bwd<2048, 256>(nblocks, a, g, gw, perm, mask, s); } break;
+    case kC4096: { WSR_TRACE("prox_bwd_small_4096", s); launch_small_bwd<4096, 512>(nblocks, a, g, gw, perm, mask, s); } break;
+    default: { WSR_TRACE("prox_bwd_small_8192", s); launch_small_bwd<8192, 1024>(nblocks, a, g, gw, perm, mask, s); } break;
   }
 }
 

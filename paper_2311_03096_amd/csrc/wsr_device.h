@@ -346,6 +346,22 @@ __device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, C
   *rc = r;
 }
 
+// Candidates of b next to the removed points rem (within the thread): for each removed point, the
+// nearest surviving candidate on either side.  A candidate's collision test can only change when
+// one of its neighbouring candidates changed.
+__device__ __forceinline__ uint32_t ica_neighbours(uint32_t b, uint32_t rem) {
+  uint32_t dirty = 0;
+  while (rem) {
+    const int j = __ffs(rem) - 1;
+    rem &= rem - 1u;
+    const uint32_t lo = b & ((1u << j) - 1u);
+    const uint32_t hi = b & ~((2u << j) - 1u);
+    if (lo) dirty |= 1u << (31 - __clz(lo));
+    dirty |= hi & (0u - hi);
+  }
+  return dirty;
+}
+
 // ImminentCollisions rounds (Sec. 4.1; Alg. imminent_collisions_v2) on hull candidates: thread t
 // owns points k0 = t*E .. k0+E-1 (bit i of *bm = point k0+i is a candidate), point d is the fixed
 // right end.  Every round removes, all at once, each candidate that is not strictly below the
@@ -353,15 +369,36 @@ __device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, C
 // avg y right), and repeats until nothing changes.  Returns true on convergence within max_rounds
 // (candidates = hull vertices, *lc / *rc = carries of the final candidate set), false otherwise.
 // sv[0..E] are this thread's S values (sv[i] = S_{k0+i}); S is the rank-padded LDS copy.
+// The first round has every point as a candidate, so its neighbours are the adjacent ranks and
+// the test is y_{k-1} >= y_k (S_k - S_{k-1} >= S_{k+1} - S_k), done in registers.  Later rounds
+// test only the candidates whose neighbouring candidates changed in the round before (within the
+// thread, or a changed carry from another thread); every other candidate keeps its last outcome,
+// so the removal sets are those of the full rounds.
 template <int NT, int E>
 __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, int max_rounds, uint32_t* bm,
                            Cand* lc, Cand* rc, Cand* shL, Cand* shR) {
   const int k0 = threadIdx.x * E;
   const Cand dflt{d, S[rpad(d)]};
-  uint32_t b = 0;
+  uint32_t valid = 0;
 #pragma unroll
-  for (int i = 0; i < E; ++i) b |= (k0 + i < d ? 1u : 0u) << i;
-  for (int round = 0; round < max_rounds; ++round) {
+  for (int i = 0; i < E; ++i) valid |= (k0 + i < d ? 1u : 0u) << i;
+  // round 1: adjacent neighbours
+  uint32_t rem = 0;
+  {
+    double dl = sv[0] - S[rpad(max(k0 - 1, 0))];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const double dr = sv[i + 1] - sv[i];
+      if (((valid >> i) & 1u) && (k0 + i > 0) && !(dl < dr)) rem |= 1u << i;
+      dl = dr;
+    }
+  }
+  uint32_t b = valid & ~rem;
+  bool any = __syncthreads_or(rem != 0) != 0;
+  uint32_t dirty = rem ? ica_neighbours(b, rem) : 0u;
+  int lprev = k0 - 1;          // neighbours the first round used outside the thread
+  int rprev = min(k0 + E, d);
+  for (int round = 1;; ++round) {
     Cand mineL{-1, 0.0}, mineR{-1, 0.0};
     if (b) {
       const int hi = 31 - __clz(b);
@@ -373,27 +410,35 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
     }
     Cand l, r;
     carry_scans<NT>(mineL, mineR, dflt, shL, shR, &l, &r);
-    uint32_t rem = 0;
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const uint32_t below_i = b & ((1u << i) - 1u);
-      const uint32_t above_i = b & ~((2u << i) - 1u);
-      const int pp = below_i ? k0 + 31 - __clz(below_i) : l.pos;
-      const int np = above_i ? k0 + __ffs(above_i) - 1 : r.pos;
-      const double sp_l = S[rpad(min(max(pp, 0), d))];
-      const double sn_l = S[rpad(min(max(np, 0), d))];
-      const double sp = below_i ? sp_l : l.s;
-      const double sn = above_i ? sn_l : r.s;
-      const bool cand = (b >> i) & 1u;
-      if (cand && pp >= 0 && !below(pp, sp, k0 + i, sv[i], np, sn)) rem |= 1u << i;
-    }
-    b &= ~rem;
-    if (!__syncthreads_or(rem != 0)) {
+    if (!any) {
       *bm = b;
       *lc = l;
       *rc = r;
       return true;
     }
+    if (round >= max_rounds) break;
+    if (b) {
+      if (l.pos != lprev) dirty |= b & (0u - b);
+      if (r.pos != rprev) dirty |= 1u << (31 - __clz(b));
+    }
+    lprev = l.pos;
+    rprev = r.pos;
+    uint32_t todo = dirty & b;
+    rem = 0;
+    while (todo) {
+      const int i = __ffs(todo) - 1;
+      todo &= todo - 1u;
+      const uint32_t below_i = b & ((1u << i) - 1u);
+      const uint32_t above_i = b & ~((2u << i) - 1u);
+      const int pp = below_i ? k0 + 31 - __clz(below_i) : l.pos;
+      const int np = above_i ? k0 + __ffs(above_i) - 1 : r.pos;
+      const double sp = below_i ? S[rpad(pp)] : l.s;
+      const double sn = above_i ? S[rpad(np)] : r.s;
+      if (pp >= 0 && !below(pp, sp, k0 + i, S[rpad(k0 + i)], np, sn)) rem |= 1u << i;
+    }
+    b &= ~rem;
+    any = __syncthreads_or(rem != 0) != 0;
+    dirty = rem ? ica_neighbours(b, rem) : 0u;
   }
   *bm = b;
   return false;
@@ -402,26 +447,26 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
 // Cluster value of every rank owned by this thread from its final cluster starts: bm (bit i =
 // rank k0+i starts a cluster), sv[0..E] (S at k0..k0+E), carries lc (last start before k0) and
 // rc (first start after the thread's ranks, or the end point d).  Rank k0+i gets
-// offset + (S_b - S_a) / (b - a) for its cluster [a, b); res[idx[rpad(k)]] receives it.
+// offset + (S_b - S_a) / (b - a) for its cluster [a, b); res[idx[rpad(k)]] receives it.  The next
+// cluster start is carried down a register sweep, so no S value is read from LDS.
 template <int E>
-__device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 1], const double* S, Cand lc,
-                                            Cand rc, int d, double offset, const uint16_t* idx, float* res) {
+__device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 1], Cand lc, Cand rc, int d,
+                                            double offset, const uint16_t* idx, float* res) {
   const int k0 = threadIdx.x * E;
   if (k0 >= d) return;
-  // cluster entering the thread's range (starts before k0 unless bit 0 is set)
-  const int f0 = bm ? __ffs(bm) - 1 : -1;
-  const int e0 = f0 >= 0 ? k0 + f0 : rc.pos;
-  const double se0 = f0 >= 0 ? S[rpad(k0 + f0)] : rc.s;
-  float cur = lc.pos >= 0 ? (float)(offset + (se0 - lc.s) / (double)(e0 - lc.pos)) : 0.0f;
   float val[E];
+  int np = rc.pos;
+  double sn = rc.s;
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const uint32_t above_i = bm & ~((2u << i) - 1u);
-    const int np = above_i ? k0 + __ffs(above_i) - 1 : rc.pos;
-    const double sn_l = S[rpad(min(max(np, 0), d))];
-    const double sn = above_i ? sn_l : rc.s;
+  for (int i = E - 1; i >= 0; --i) {
     val[i] = (float)(offset + (sn - sv[i]) / (double)(np - (k0 + i)));
+    if ((bm >> i) & 1u) {
+      np = k0 + i;
+      sn = sv[i];
+    }
   }
+  // (np, sn) is now the first start in the thread's ranks (or rc): it closes the entering cluster
+  float cur = lc.pos >= 0 ? (float)(offset + (sn - lc.s) / (double)(np - lc.pos)) : 0.0f;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     if ((bm >> i) & 1u) cur = val[i];

@@ -17,6 +17,11 @@
 
 namespace wsr {
 
+// Bucket sort: longest bucket handled (longer ones take the radix sort), and the sentinel padding
+// after the bucket-ordered keys that lets a rank scan run past its bucket's end.
+constexpr int kBucketMax = 48;
+constexpr int kRankPad = 64;
+
 template <int TMAX, int NT>
 struct FwdSmem {
   static constexpr int E = TMAX / NT;
@@ -26,15 +31,14 @@ struct FwdSmem {
     uint32_t key[rpad_size(TMAX)];  // sort keys; sorted keys after the sort (rank-padded)
     float cval[TMAX];               // per-cluster values (hull-merge output phase)
     float outv[TMAX];               // results by original index (rounds output phase)
-    float g[TMAX];                  // backward: upstream gradient by original index
   } a;
   uint16_t idx[rpad_size(TMAX)];  // payload: original index of each rank (rank-padded)
   union {
     double S[rpad_size(TMAX + 1)];  // prefix sums (forward) / G (backward), rank-padded
     float outv[TMAX];               // results by original index (output phase)
     struct {
-      uint32_t start[TMAX + 1];  // bucket sort: per-bucket counts, then starts
-      uint32_t tkey[TMAX];       // bucket sort: keys in bucket order
+      uint32_t cnt2[TMAX + 1];          // bucket sort: 2*TMAX 16-bit counters in pairs, then starts
+      uint32_t tkey[TMAX + kRankPad];  // bucket sort: keys in bucket order, sentinel-padded
     } bs;
   } c;
   union {
@@ -47,6 +51,7 @@ struct FwdSmem {
     uint16_t tidx[TMAX];  // bucket sort: indices in bucket order
   } d;
   uint32_t lmask[TMAX / 32 + 2];
+  uint32_t occ[TMAX / 32];  // bucket sort: ranks taken (tie detection)
   double dred[NW + 1];
   int ired[NW + 1];
   uint32_t ured[2 * NW];
@@ -165,26 +170,30 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
 }
 
 // Bucket-rank sort of the register-held items (any layout) into sm.a.key / sm.idx.
-// Keys are spread over NB = TMAX buckets by a monotone map of their value over [min, max].  One
-// atomic pass counts the keys per bucket and gives each key its position inside its bucket; a
-// scan turns counts into bucket starts; keys are placed in bucket order; finally each key's rank
-// is its bucket's start plus the number of keys of the bucket that precede it in (key, index)
-// order.  The result is the same total order the stable radix sort produces.  Returns false
-// (sorted arrays untouched) when some bucket holds more than kBucketMax keys, so that skewed or
-// tie-heavy segments keep a bounded cost by taking the radix sort instead.
+// Keys are spread over NB = 2*TMAX buckets by a monotone map of their value over [min, max].  One
+// atomic pass counts the keys per bucket (16-bit counters, two to a word) and gives each key a
+// slot inside its bucket; a scan turns counts into bucket starts; keys are placed in bucket
+// order.  A key's rank is its bucket's start plus the number of keys of its bucket that are
+// smaller: since buckets are monotone in value, every key past the end of the bucket (and the
+// sentinel padding) is larger, so the count scans a fixed number of slots with no bound checks.
+// Equal keys would share a rank; that is detected with an occupancy bit per rank, and then all
+// ranks are recomputed in (key, index) order.  The result is the same total order the stable
+// radix sort produces.  Returns false (sorted arrays untouched) when some bucket holds more than
+// kBucketMax keys, so that skewed or tie-heavy segments keep a bounded cost by taking the radix
+// sort instead.
 template <int TMAX, int NT>
 __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMAX / NT],
                                   const uint16_t (&ix)[TMAX / NT], int d) {
   constexpr int IPT = TMAX / NT;
   constexpr int NW = NT / kWave;
-  constexpr int NB = TMAX;
-  constexpr int BPT = NB / NT;  // buckets per thread in the scan
-  constexpr int kBucketMax = 48;
+  constexpr int NB = 2 * TMAX;
+  constexpr int WPT = TMAX / NT;  // counter words (bucket pairs) per thread in the scan
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int wbase = wv * kWave * IPT;
-  uint32_t* start = sm.c.bs.start;
+  uint32_t* cnt2 = sm.c.bs.cnt2;
+  const uint16_t* st16 = reinterpret_cast<const uint16_t*>(sm.c.bs.cnt2);
   uint32_t* tkey = sm.c.bs.tkey;
   uint16_t* tidx = sm.d.tidx;
 
@@ -206,7 +215,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     sm.ured[2 * wv] = kmn;
     sm.ured[2 * wv + 1] = kmx;
   }
-  for (int j = tid; j < NB; j += NT) start[j] = 0u;
+  for (int j = tid; j < TMAX + 1; j += NT) cnt2[j] = 0u;
+  for (int j = tid; j < TMAX / 32; j += NT) sm.occ[j] = 0u;
   __syncthreads();
   kmn = sm.ured[0];
   kmx = sm.ured[1];
@@ -239,18 +249,21 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     if (p < d) {
       const int b = (int)((key_to_float(k[r]) - mn) * scale);
       bk[r] = min(max(b, 0), NB - 1);
-      loc[r] = (uint16_t)atomicAdd(&start[bk[r]], 1u);
+      const int sh = (bk[r] & 1) * 16;
+      loc[r] = (uint16_t)(atomicAdd(&cnt2[bk[r] >> 1], 1u << sh) >> sh);
     }
   }
   __syncthreads();
-  uint32_t c[BPT];
+  // counts -> bucket starts; thread t owns counter words [t*WPT, (t+1)*WPT)
+  uint32_t c[WPT];
   int sum = 0;
   int cmax = 0;
 #pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    c[i] = start[tid * BPT + i];
-    sum += (int)c[i];
-    cmax = max(cmax, (int)c[i]);
+  for (int i = 0; i < WPT; ++i) {
+    c[i] = cnt2[tid * WPT + i];
+    const int c0 = (int)(c[i] & 0xFFFFu), c1 = (int)(c[i] >> 16);
+    sum += c0 + c1;
+    cmax = max(cmax, max(c0, c1));
   }
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, kWave));
@@ -258,25 +271,27 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   int run = block_excl_scan<NT, int>(sum, sm.ired, &total);
   if (lane == 0) sm.ured[wv] = (uint32_t)cmax;
 #pragma unroll
-  for (int i = 0; i < BPT; ++i) {
-    start[tid * BPT + i] = (uint32_t)run;
-    run += (int)c[i];
+  for (int i = 0; i < WPT; ++i) {
+    const int s0 = run;
+    run += (int)(c[i] & 0xFFFFu);
+    cnt2[tid * WPT + i] = (uint32_t)s0 | ((uint32_t)run << 16);
+    run += (int)(c[i] >> 16);
   }
-  if (tid == NT - 1) start[NB] = (uint32_t)total;
+  if (tid == NT - 1) cnt2[TMAX] = (uint32_t)total;  // start of the (empty) bucket NB
+  for (int j = tid; j < kRankPad; j += NT) tkey[d + j] = 0xFFFFFFFFu;  // above every finite key
   __syncthreads();
   cmax = (int)sm.ured[0];
   for (int w = 1; w < NW; ++w) cmax = max(cmax, (int)sm.ured[w]);
   if (cmax > kBucketMax) return false;  // uniform
-  int lo[IPT], cnt[IPT];
+  int lo[IPT];
   int jmax = 0;
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {  // loads unconditional (bk = 0 for padding) so they overlap
     const int p = wbase + r * kWave + lane;
-    const int s0 = (int)start[bk[r]];
-    const int s1 = (int)start[bk[r] + 1];
+    const int s0 = (int)st16[bk[r]];
+    const int s1 = (int)st16[bk[r] + 1];
     lo[r] = p < d ? s0 : 0;
-    cnt[r] = p < d ? s1 - s0 : 0;
-    jmax = max(jmax, cnt[r]);
+    jmax = max(jmax, p < d ? s1 - s0 : 0);
   }
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
@@ -287,18 +302,36 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     }
   }
   __syncthreads();
-  // rank = bucket start + keys of the bucket before this one; the items advance together and
-  // every load is unconditional, so one LDS round trip serves all items of a step
+  // rank = bucket start + smaller keys of the bucket; the items advance together, so one LDS
+  // round trip serves all items of a step
   int rank[IPT];
 #pragma unroll
   for (int r = 0; r < IPT; ++r) rank[r] = lo[r];
   for (int j = 0; j < jmax; ++j) {
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      const int jj = min(lo[r] + j, d - 1);
-      const uint32_t kj = tkey[jj];
-      const uint16_t ij = tidx[jj];
-      rank[r] += (j < cnt[r]) & ((kj < k[r]) | ((kj == k[r]) & (ij < ix[r])));
+    for (int r = 0; r < IPT; ++r) rank[r] += tkey[lo[r] + j] < k[r] ? 1 : 0;
+  }
+  int tie = 0;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    if (p < d) {
+      const uint32_t bit = 1u << (rank[r] & 31);
+      tie |= (atomicOr(&sm.occ[rank[r] >> 5], bit) & bit) != 0u;
+    }
+  }
+  if (__syncthreads_or(tie)) {
+    // equal keys: order each bucket by (key, index) instead; an equal key is always in the same
+    // bucket, and the padding never equals a finite key
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) rank[r] = lo[r];
+    for (int j = 0; j < jmax; ++j) {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t kj = tkey[lo[r] + j];
+        const uint16_t ij = tidx[min(lo[r] + j, TMAX - 1)];
+        rank[r] += (kj < k[r]) | ((kj == k[r]) & (ij < ix[r]));
+      }
     }
   }
 #pragma unroll
@@ -435,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
       atomicOr(&sm.lmask[b0 >> 5], (uint32_t)wide);
       if (wide >> 32) atomicOr(&sm.lmask[(b0 >> 5) + 1], (uint32_t)(wide >> 32));
     }
-    walk_values<E>(bm, sv, sm.c.S, lc, rc, d, c, sm.idx, sm.a.outv);
+    walk_values<E>(bm, sv, lc, rc, d, c, sm.idx, sm.a.outv);
     res = sm.a.outv;
   } else {
     tile_hull<NT, E>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
@@ -459,10 +492,20 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
 }
 
 template <int TMAX, int NT>
+struct BwdSmem {
+  static constexpr int NW = NT / kWave;
+  float g[TMAX];                  // upstream gradient by original index, then results
+  uint16_t idx[rpad_size(TMAX)];  // saved permutation (rank -> original index), rank-padded
+  uint32_t lmask[TMAX / 32 + 2];
+  double dred[NW + 1];
+  Cand shL[NW], shR[NW];
+};
+
+template <int TMAX, int NT>
 __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float* gin, float* gout,
                                                        const int32_t* perm_in, const uint32_t* mask_in) {
   constexpr int E = TMAX / NT;
-  __shared__ FwdSmem<TMAX, NT> sm;
+  __shared__ BwdSmem<TMAX, NT> sm;
   int64_t start;
   int d;
   float lam;
@@ -473,13 +516,13 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   const int nwords = (off + d + 31) >> 5;
   const int64_t g0 = start >> 5;
   for (int i = tid; i < d; i += NT) {
-    sm.a.g[i] = gin[start + i];
+    sm.g[i] = gin[start + i];
     const int p = perm_in[start + i];
     sm.idx[rpad(i)] = (uint16_t)min(max(p, 0), d - 1);
   }
   for (int j = tid; j < nwords; j += NT) sm.lmask[j] = mask_in[g0 + j];
   __syncthreads();
-  // cotangent in rank order, cluster starts of the thread's ranks, FP64 prefix sums G
+  // cotangent in rank order, cluster starts of the thread's ranks, FP64 prefix sums G (registers)
   const int k0 = tid * E;
   float gk[E];
   double lsum = 0.0;
@@ -488,37 +531,33 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   for (int i = 0; i < E; ++i) {
     const int kk = k0 + i;
     const int kc = min(kk, d - 1);
-    const float gv = sm.a.g[sm.idx[rpad(kc)]];  // unconditional gather
+    const float gv = sm.g[sm.idx[rpad(kc)]];  // unconditional gather
     const int b = kc + off;
     const uint32_t st = (kk == 0) | ((sm.lmask[b >> 5] >> (b & 31)) & 1u);
     gk[i] = kk < d ? gv : 0.0f;
     lsum += (double)gk[i];
     bm |= (kk < d ? st : 0u) << i;
   }
-  double G = block_excl_scan<NT, double>(lsum, sm.dred, (double*)nullptr);
+  double total;
+  double G = block_excl_scan<NT, double>(lsum, sm.dred, &total);
   double sv[E + 1];
+  Cand mineL{-1, 0.0}, mineR{-1, 0.0};
 #pragma unroll
   for (int i = 0; i <= E; ++i) {
     sv[i] = G;
     if (i < E) {
-      if (k0 + i <= d) sm.c.S[rpad(k0 + i)] = G;
+      if ((bm >> i) & 1u) {
+        if (mineR.pos < 0) mineR = Cand{k0 + i, G};
+        mineL = Cand{k0 + i, G};
+      }
       G += (double)gk[i];
     }
   }
-  if (tid == NT - 1 && d == TMAX) sm.c.S[rpad(TMAX)] = sv[E];
-  __syncthreads();
-  Cand mineL{-1, 0.0}, mineR{-1, 0.0};
-  if (bm) {
-    const int hi = 31 - __clz(bm);
-    const int lo = __ffs(bm) - 1;
-    mineL = Cand{k0 + hi, sm.c.S[rpad(k0 + hi)]};
-    mineR = Cand{k0 + lo, sm.c.S[rpad(k0 + lo)]};
-  }
   Cand lc, rc;
-  carry_scans<NT>(mineL, mineR, Cand{d, sm.c.S[rpad(d)]}, sm.shL, sm.shR, &lc, &rc);
-  walk_values<E>(bm, sv, sm.c.S, lc, rc, d, 0.0, sm.idx, sm.a.outv);
+  carry_scans<NT>(mineL, mineR, Cand{d, total}, sm.shL, sm.shR, &lc, &rc);
+  walk_values<E>(bm, sv, lc, rc, d, 0.0, sm.idx, sm.g);  // every gather above is done (block scan)
   __syncthreads();
-  for (int i = tid; i < d; i += NT) gout[start + i] = sm.a.outv[i];
+  for (int i = tid; i < d; i += NT) gout[start + i] = sm.g[i];
 }
 
 // Zero a word array (used for the saved cluster-start mask before OR-ing boundary words).
@@ -534,8 +573,8 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
   template __global__ void k_prox_bwd_small<TM, NTH>(SegArgs, const float*, float*,             \
                                                       const int32_t*, const uint32_t*);
 
-WSR_INSTANTIATE_SMALL(2048, 128)
-WSR_INSTANTIATE_SMALL(4096, 256)
-WSR_INSTANTIATE_SMALL(8192, 512)
+WSR_INSTANTIATE_SMALL(2048, 256)
+WSR_INSTANTIATE_SMALL(4096, 512)
+WSR_INSTANTIATE_SMALL(8192, 1024)
 
 }  // namespace wsr
