@@ -58,24 +58,46 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t dg) {
   return peers;
 }
 
-// Wave-inclusive scans (Hillis-Steele over the 64 lanes, App. A.2).
-__device__ __forceinline__ double wave_incl_scan(double v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    double t = __shfl_up(v, o, kWave);
-    if (lane >= o) v += t;
-  }
+// Cross-lane moves through DPP (data-parallel primitives: a VALU operand modifier, no LDS round
+// trip).  A lane whose source lane is out of range keeps `old`.  Every lane of the wave must be
+// active.  CTRL: 0x110+n row_shr:n (within 16-lane rows), 0x142 row_bcast:15 (lane 15 of a row to
+// the next row), 0x143 row_bcast:31 (lane 31 to rows 2 and 3), 0x138 wave_shr:1.
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp(T v, T old) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Wave-inclusive scan with an associative op and its identity (Hillis-Steele inside each row of
+// 16 lanes, then the row totals; App. A.2).
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_incl_scan_op(T v, T id, Op op) {
+  v = op(v, dpp<0x111, 0xF>(v, id));
+  v = op(v, dpp<0x112, 0xF>(v, id));
+  v = op(v, dpp<0x114, 0xF>(v, id));
+  v = op(v, dpp<0x118, 0xF>(v, id));
+  v = op(v, dpp<0x142, 0xA>(v, id));
+  v = op(v, dpp<0x143, 0xC>(v, id));
   return v;
 }
+__device__ __forceinline__ double wave_incl_scan(double v) {
+  return wave_incl_scan_op(v, 0.0, [](double a, double b) { return a + b; });
+}
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    int t = __shfl_up(v, o, kWave);
-    if (lane >= o) v += t;
-  }
-  return v;
+  return wave_incl_scan_op(v, 0, [](int a, int b) { return a + b; });
+}
+// The exclusive form: each lane gets the inclusive value of the lane below (lane 0: id).
+template <typename T>
+__device__ __forceinline__ T wave_shift_up(T v, T id) {
+  return dpp<0x138, 0xF>(v, id);
+}
+// Wave-uniform min / max (the scan's last lane, read into a scalar register).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  const uint32_t m = wave_incl_scan_op(v, 0u, [](uint32_t a, uint32_t b) { return a > b ? a : b; });
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, kWave - 1);
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  const uint32_t m = wave_incl_scan_op(v, 0xFFFFFFFFu, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, kWave - 1);
 }
 
 // Block-wide exclusive scan; sh must hold NT/64 + 1 values.  Every thread of the block must call.
@@ -86,8 +108,7 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   const int lane = lane_id();
   const int wv = threadIdx.x / kWave;
   T inc = wave_incl_scan(v);
-  T exc = __shfl_up(inc, 1, kWave);
-  if (lane == 0) exc = T(0);
+  T exc = wave_shift_up(inc, T(0));
   if (lane == kWave - 1) sh[wv] = inc;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -295,38 +316,36 @@ struct Cand {
 };
 
 // Per thread, the last candidate held by lower threads (lc) and the first candidate held by
-// higher threads (rc, default dflt).  shL / shR need NT/64 entries each.  All threads must call.
+// higher threads (rc, default dflt).  mineL / mineR are the thread's own last / first candidate
+// (pos < 0: none; both or neither).  Inside a wave the nearest lanes holding one are found from a
+// ballot and read directly; across waves through shL / shR (NT/64 entries each).  All threads
+// must call.
 template <int NT>
 __device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, Cand* shL, Cand* shR, Cand* lc,
                                             Cand* rc) {
   constexpr int NW = NT / kWave;
   const int lane = lane_id();
   const int wv = threadIdx.x / kWave;
-  Cand a = mineL, b = mineR;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int ap = __shfl_up(a.pos, o, kWave);
-    const double as = __shfl_up(a.s, o, kWave);
-    if (lane >= o && a.pos < 0) {
-      a.pos = ap;
-      a.s = as;
-    }
-    const int bp = __shfl_down(b.pos, o, kWave);
-    const double bs = __shfl_down(b.s, o, kWave);
-    if (lane + o < kWave && b.pos < 0) {
-      b.pos = bp;
-      b.s = bs;
-    }
-  }
+  const uint64_t has = __ballot(mineL.pos >= 0);
+  const uint64_t lower = has & lanemask_lt();
+  const uint64_t upper = lane == kWave - 1 ? 0ull : has & (~0ull << (lane + 1));
+  const int src_l = lower ? 63 - __clzll((long long)lower) : lane;
+  const int src_r = upper ? __ffsll((unsigned long long)upper) - 1 : lane;
   Cand l, r;
-  l.pos = __shfl_up(a.pos, 1, kWave);
-  l.s = __shfl_up(a.s, 1, kWave);
-  if (lane == 0) l.pos = -1;
-  r.pos = __shfl_down(b.pos, 1, kWave);
-  r.s = __shfl_down(b.s, 1, kWave);
-  if (lane == kWave - 1) r.pos = -1;
-  if (lane == kWave - 1) shL[wv] = a;
-  if (lane == 0) shR[wv] = b;
+  l.pos = __shfl(mineL.pos, src_l, kWave);
+  l.s = __shfl(mineL.s, src_l, kWave);
+  r.pos = __shfl(mineR.pos, src_r, kWave);
+  r.s = __shfl(mineR.s, src_r, kWave);
+  if (!lower) l.pos = -1;
+  if (!upper) r.pos = -1;
+  // the wave's last and first candidates, for the other waves
+  if (has) {
+    if (lane == 63 - __clzll((long long)has)) shL[wv] = mineL;
+    if (lane == __ffsll((unsigned long long)has) - 1) shR[wv] = mineR;
+  } else if (lane == 0) {
+    shL[wv] = Cand{-1, 0.0};
+    shR[wv] = Cand{-1, 0.0};
+  }
   __syncthreads();
   if (l.pos < 0)
     for (int w = wv - 1; w >= 0; --w)

@@ -206,11 +206,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
       kmx = max(kmx, k[r]);
     }
   }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) {
-    kmn = min(kmn, (uint32_t)__shfl_xor((int)kmn, o, kWave));
-    kmx = max(kmx, (uint32_t)__shfl_xor((int)kmx, o, kWave));
-  }
+  kmn = wave_min_u32(kmn);
+  kmx = wave_max_u32(kmx);
   if (lane == 0) {
     sm.ured[2 * wv] = kmn;
     sm.ured[2 * wv + 1] = kmx;
@@ -265,8 +262,7 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     sum += c0 + c1;
     cmax = max(cmax, max(c0, c1));
   }
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, kWave));
+  cmax = (int)wave_max_u32((uint32_t)cmax);
   int total;
   int run = block_excl_scan<NT, int>(sum, sm.ired, &total);
   if (lane == 0) sm.ured[wv] = (uint32_t)cmax;
