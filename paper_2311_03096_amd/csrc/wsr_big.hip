@@ -198,7 +198,8 @@ struct TileSmem {
   int mres[kBigThreads];
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
-  Cand shL[kBigThreads / kWave], shR[kBigThreads / kWave];
+  Cand shL[2 * (kBigThreads / kWave)], shR[2 * (kBigThreads / kWave)];
+  int shF[2 * (kBigThreads / kWave)];
   double xtot;
 };
 
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   uint32_t bm;
   Cand lc, rc;
-  if (ica_rounds<kBigThreads, kBigE>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR)) {
+  if (ica_rounds<kBigThreads, kBigE>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
     // hull vertices = surviving candidates in rank order, then the tile's end point
     int nv;
     int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);
@@ -851,6 +852,7 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const
                                                        int32_t* nextp, double* nextG) {
   __shared__ double sh[1024 / kWave + 1];
   __shared__ Cand shL[1024 / kWave], shR[1024 / kWave];
+  __shared__ int shF[1024 / kWave];
   const int tid = threadIdx.x;
   const int chunk = (ntiles + 1023) / 1024;
   const int a = tid * chunk;
@@ -867,7 +869,7 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const
     run += tsum[i];
   }
   Cand lc, rc;
-  carry_scans<1024>(mineL, mineR, Cand{(int)d, total}, shL, shR, &lc, &rc);
+  carry_exchange<1024>(mineL, mineR, false, Cand{(int)d, total}, shL, shR, shF, &lc, &rc);
   if (lc.pos < 0) lc = Cand{0, 0.0};  // rank 0 always starts a cluster
   // walk the chunk: previous start before each tile, next start after each tile
   for (int i = a; i < b; ++i) {

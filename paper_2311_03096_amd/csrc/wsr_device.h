@@ -85,6 +85,13 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
 __device__ __forceinline__ int wave_incl_scan(int v) {
   return wave_incl_scan_op(v, 0, [](int a, int b) { return a + b; });
 }
+__device__ __forceinline__ long long wave_incl_scan(long long v) {
+  return wave_incl_scan_op(v, 0ll, [](long long a, long long b) { return a + b; });
+}
+// Wave-uniform sum (the scan's last lane, read into scalar registers).
+__device__ __forceinline__ int wave_sum(int v) {
+  return __builtin_amdgcn_readlane(wave_incl_scan(v), kWave - 1);
+}
 // The exclusive form: each lane gets the inclusive value of the lane below (lane 0: id).
 template <typename T>
 __device__ __forceinline__ T wave_shift_up(T v, T id) {
@@ -316,13 +323,15 @@ struct Cand {
 };
 
 // Per thread, the last candidate held by lower threads (lc) and the first candidate held by
-// higher threads (rc, default dflt).  mineL / mineR are the thread's own last / first candidate
-// (pos < 0: none; both or neither).  Inside a wave the nearest lanes holding one are found from a
-// ballot and read directly; across waves through shL / shR (NT/64 entries each).  All threads
-// must call.
+// higher threads (rc, default dflt), and the OR of `flag` over the block (returned).  mineL /
+// mineR are the thread's own last / first candidate (pos < 0: none; both or neither).  Inside a
+// wave the nearest lanes holding one are found from a ballot and read directly; across waves
+// through shL / shR / shF (NT/64 entries each).  One barrier; the caller alternates between two
+// sets of exchange slots on consecutive calls (a wave may write the next call's slots while
+// others still read this call's).  All threads must call.
 template <int NT>
-__device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, Cand* shL, Cand* shR, Cand* lc,
-                                            Cand* rc) {
+__device__ __forceinline__ bool carry_exchange(Cand mineL, Cand mineR, bool flag, Cand dflt, Cand* shL, Cand* shR,
+                                               int* shF, Cand* lc, Cand* rc) {
   constexpr int NW = NT / kWave;
   const int lane = lane_id();
   const int wv = threadIdx.x / kWave;
@@ -338,7 +347,8 @@ __device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, C
   r.s = __shfl(mineR.s, src_r, kWave);
   if (!lower) l.pos = -1;
   if (!upper) r.pos = -1;
-  // the wave's last and first candidates, for the other waves
+  // the wave's last and first candidates and its flag, for the other waves
+  const bool wflag = __ballot(flag) != 0ull;
   if (has) {
     if (lane == 63 - __clzll((long long)has)) shL[wv] = mineL;
     if (lane == __ffsll((unsigned long long)has) - 1) shR[wv] = mineR;
@@ -346,6 +356,7 @@ __device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, C
     shL[wv] = Cand{-1, 0.0};
     shR[wv] = Cand{-1, 0.0};
   }
+  if (lane == 0) shF[wv] = wflag ? 1 : 0;
   __syncthreads();
   if (l.pos < 0)
     for (int w = wv - 1; w >= 0; --w)
@@ -360,9 +371,12 @@ __device__ __forceinline__ void carry_scans(Cand mineL, Cand mineR, Cand dflt, C
         break;
       }
   if (r.pos < 0) r = dflt;
-  __syncthreads();
+  int any = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) any |= shF[w];
   *lc = l;
   *rc = r;
+  return any != 0;
 }
 
 // Candidates of b next to the removed points rem (within the thread): for each removed point, the
@@ -395,7 +409,8 @@ __device__ __forceinline__ uint32_t ica_neighbours(uint32_t b, uint32_t rem) {
 // so the removal sets are those of the full rounds.
 template <int NT, int E>
 __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, int max_rounds, uint32_t* bm,
-                           Cand* lc, Cand* rc, Cand* shL, Cand* shR) {
+                           Cand* lc, Cand* rc, Cand* shL, Cand* shR, int* shF) {
+  constexpr int NW = NT / kWave;
   const int k0 = threadIdx.x * E;
   const Cand dflt{d, S[rpad(d)]};
   uint32_t valid = 0;
@@ -413,9 +428,8 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
     }
   }
   uint32_t b = valid & ~rem;
-  bool any = __syncthreads_or(rem != 0) != 0;
   uint32_t dirty = rem ? ica_neighbours(b, rem) : 0u;
-  int lprev = k0 - 1;          // neighbours the first round used outside the thread
+  int lprev = k0 - 1;  // neighbours the first round used outside the thread
   int rprev = min(k0 + E, d);
   for (int round = 1;; ++round) {
     Cand mineL{-1, 0.0}, mineR{-1, 0.0};
@@ -427,8 +441,10 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
       mineR.pos = k0 + lo;
       mineR.s = S[rpad(k0 + lo)];
     }
+    // carries of the current candidates, and whether the last round removed anything
+    const int slot = (round & 1) * NW;
     Cand l, r;
-    carry_scans<NT>(mineL, mineR, dflt, shL, shR, &l, &r);
+    const bool any = carry_exchange<NT>(mineL, mineR, rem != 0, dflt, shL + slot, shR + slot, shF + slot, &l, &r);
     if (!any) {
       *bm = b;
       *lc = l;
@@ -456,7 +472,6 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
       if (pp >= 0 && !below(pp, sp, k0 + i, S[rpad(k0 + i)], np, sn)) rem |= 1u << i;
     }
     b &= ~rem;
-    any = __syncthreads_or(rem != 0) != 0;
     dirty = rem ? ica_neighbours(b, rem) : 0u;
   }
   *bm = b;

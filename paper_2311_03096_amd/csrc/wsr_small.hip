@@ -51,11 +51,13 @@ struct FwdSmem {
     uint16_t tidx[TMAX];  // bucket sort: indices in bucket order
   } d;
   uint32_t lmask[TMAX / 32 + 2];
-  uint32_t occ[TMAX / 32];  // bucket sort: ranks taken (tie detection)
+  long long lred[NW + 1];
+  int tiecnt;  // bucket sort: sum over keys of the smaller keys in their bucket
   double dred[NW + 1];
   int ired[NW + 1];
   uint32_t ured[2 * NW];
-  Cand shL[NW], shR[NW];
+  Cand shL[2 * NW], shR[2 * NW];  // carry exchange slots, two sets
+  int shF[2 * NW];
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
 
@@ -176,8 +178,8 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
 // order.  A key's rank is its bucket's start plus the number of keys of its bucket that are
 // smaller: since buckets are monotone in value, every key past the end of the bucket (and the
 // sentinel padding) is larger, so the count scans a fixed number of slots with no bound checks.
-// Equal keys would share a rank; that is detected with an occupancy bit per rank, and then all
-// ranks are recomputed in (key, index) order.  The result is the same total order the stable
+// Equal keys would share a rank; that shows as fewer smaller-key counts than key pairs sharing a
+// bucket, and then all ranks are recomputed in (key, index) order.  The result is the same total order the stable
 // radix sort produces.  Returns false (sorted arrays untouched) when some bucket holds more than
 // kBucketMax keys, so that skewed or tie-heavy segments keep a bounded cost by taking the radix
 // sort instead.
@@ -213,7 +215,7 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     sm.ured[2 * wv + 1] = kmx;
   }
   for (int j = tid; j < TMAX + 1; j += NT) cnt2[j] = 0u;
-  for (int j = tid; j < TMAX / 32; j += NT) sm.occ[j] = 0u;
+  if (tid == 0) sm.tiecnt = 0;
   __syncthreads();
   kmn = sm.ured[0];
   kmx = sm.ured[1];
@@ -252,19 +254,26 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   }
   __syncthreads();
   // counts -> bucket starts; thread t owns counter words [t*WPT, (t+1)*WPT)
+  // (the high half of the scanned word counts the key pairs sharing a bucket, sum c(c-1)/2: with
+  // distinct keys exactly one key of each pair is the smaller)
   uint32_t c[WPT];
   int sum = 0;
+  int pairs = 0;
   int cmax = 0;
 #pragma unroll
   for (int i = 0; i < WPT; ++i) {
     c[i] = cnt2[tid * WPT + i];
     const int c0 = (int)(c[i] & 0xFFFFu), c1 = (int)(c[i] >> 16);
     sum += c0 + c1;
+    pairs += ((c0 * (c0 - 1)) >> 1) + ((c1 * (c1 - 1)) >> 1);
     cmax = max(cmax, max(c0, c1));
   }
   cmax = (int)wave_max_u32((uint32_t)cmax);
-  int total;
-  int run = block_excl_scan<NT, int>(sum, sm.ired, &total);
+  long long tot2;
+  const long long run2 = block_excl_scan<NT, long long>((long long)sum | ((long long)pairs << 32), sm.lred, &tot2);
+  int run = (int)(run2 & 0xFFFFFFFFll);
+  const int total = (int)(tot2 & 0xFFFFFFFFll);
+  const int pairs_total = (int)(tot2 >> 32);
   if (lane == 0) sm.ured[wv] = (uint32_t)cmax;
 #pragma unroll
   for (int i = 0; i < WPT; ++i) {
@@ -307,18 +316,22 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
 #pragma unroll
     for (int r = 0; r < IPT; ++r) rank[r] += tkey[lo[r] + j] < k[r] ? 1 : 0;
   }
-  int tie = 0;
+  int below = 0;
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const int p = wbase + r * kWave + lane;
     if (p < d) {
-      const uint32_t bit = 1u << (rank[r] & 31);
-      tie |= (atomicOr(&sm.occ[rank[r] >> 5], bit) & bit) != 0u;
+      below += rank[r] - lo[r];
+      sm.a.key[rpad(rank[r])] = k[r];
+      sm.idx[rpad(rank[r])] = ix[r];
     }
   }
-  if (__syncthreads_or(tie)) {
-    // equal keys: order each bucket by (key, index) instead; an equal key is always in the same
-    // bucket, and the padding never equals a finite key
+  below = wave_sum(below);
+  if (lane == 0) atomicAdd(&sm.tiecnt, below);
+  __syncthreads();
+  if (sm.tiecnt != pairs_total) {
+    // equal keys (they shared ranks above): order each bucket by (key, index) instead; an equal
+    // key is always in the same bucket, and the padding never equals a finite key
 #pragma unroll
     for (int r = 0; r < IPT; ++r) rank[r] = lo[r];
     for (int j = 0; j < jmax; ++j) {
@@ -329,16 +342,16 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
         rank[r] += (kj < k[r]) | ((kj == k[r]) & (ij < ix[r]));
       }
     }
-  }
 #pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    const int p = wbase + r * kWave + lane;
-    if (p < d) {
-      sm.a.key[rpad(rank[r])] = k[r];
-      sm.idx[rpad(rank[r])] = ix[r];
+    for (int r = 0; r < IPT; ++r) {
+      const int p = wbase + r * kWave + lane;
+      if (p < d) {
+        sm.a.key[rpad(rank[r])] = k[r];
+        sm.idx[rpad(rank[r])] = ix[r];
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   return true;
 }
 
@@ -457,7 +470,7 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
   uint32_t bm;
   Cand lc, rc;
   const float* res;
-  if (ica_rounds<NT, E>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR)) {
+  if (ica_rounds<NT, E>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
     if (bm) {
       const int b0 = k0 + off;
       const uint64_t wide = (uint64_t)bm << (b0 & 31);
@@ -495,6 +508,7 @@ struct BwdSmem {
   uint32_t lmask[TMAX / 32 + 2];
   double dred[NW + 1];
   Cand shL[NW], shR[NW];
+  int shF[NW];
 };
 
 template <int TMAX, int NT>
@@ -550,7 +564,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
     }
   }
   Cand lc, rc;
-  carry_scans<NT>(mineL, mineR, Cand{d, total}, sm.shL, sm.shR, &lc, &rc);
+  carry_exchange<NT>(mineL, mineR, false, Cand{d, total}, sm.shL, sm.shR, sm.shF, &lc, &rc);
   walk_values<E>(bm, sv, lc, rc, d, 0.0, sm.idx, sm.g);  // every gather above is done (block scan)
   __syncthreads();
   for (int i = tid; i < d; i += NT) gout[start + i] = sm.g[i];
