@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   uint32_t bm;
   Cand lc, rc;
-  if (ica_rounds<kBigThreads, kBigE>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
+  if (ica_rounds<kBigThreads, kBigE, RankPadded>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
     // hull vertices = surviving candidates in rank order, then the tile's end point
     int nv;
     int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
     }
     return;
   }
-  tile_hull<kBigThreads, kBigE>(sm.S, np, sm.vert, sm.cnt, sm.mres);
+  tile_hull<kBigThreads, kBigE, RankPadded, int>(sm.S, np, sm.vert, sm.cnt, sm.mres);
   const int nv = sm.cnt[0];
   for (int i = tid; i < nv; i += kBigThreads) {
     vpos[vb + i] = (int32_t)(k0 + sm.vert[i]);

@@ -134,25 +134,44 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   return res;
 }
 
+// Layouts of LDS arrays indexed by rank (prefix sums S, rank -> index maps): rank-padded (blocks
+// of 16 ranks per thread spread over the banks) or flat.
+struct RankPadded {
+  __device__ static __forceinline__ int at(int k) { return rpad(k); }
+};
+struct RankFlat {
+  __device__ static __forceinline__ int at(int k) { return k; }
+};
+// Transposed: the E ranks of thread t sit E rows apart, rank k at (k mod E)(NT+1) + k/E, so the
+// lanes of a wave touching their i-th rank hit consecutive words.  Holds ranks 0..NT*E
+// (E*(NT+1) entries).
+template <int NT, int E>
+struct RankT {
+  static_assert((E & (E - 1)) == 0, "E must be a power of two");
+  static constexpr int kSize = E * (NT + 1);
+  __device__ static __forceinline__ int at(int k) { return (k & (E - 1)) * (NT + 1) + k / E; }
+};
+
 // Point b strictly below the segment a -> c (a < b < c); positions are ranks, s* are S values.
 __device__ __forceinline__ bool below(int a, double sa, int b, double sb, int c, double sc) {
   return (sb - sa) * (double)(c - b) < (sc - sb) * (double)(b - a);
 }
 
 // Sequential stack hull of points lo..hi (inclusive) of S; writes vertex ranks to st, returns count.
+template <typename SI>
 __device__ __forceinline__ int leaf_hull(const double* S, int lo, int hi, uint16_t* st) {
   int n = 0;
   int p0 = 0, p1 = 0;  // top and second-from-top ranks
   double s0 = 0.0, s1 = 0.0;
   for (int k = lo; k <= hi; ++k) {
-    const double sk = S[rpad(k)];
+    const double sk = S[SI::at(k)];
     while (n >= 2 && !below(p1, s1, p0, s0, k, sk)) {
       --n;  // collision: the top block sticks to the incoming one
       p0 = p1;
       s0 = s1;
       if (n >= 2) {
         p1 = st[n - 2];
-        s1 = S[rpad(p1)];
+        s1 = S[SI::at(p1)];
       }
     }
     st[n++] = (uint16_t)k;
@@ -245,27 +264,28 @@ __device__ void bridge(const LV& L, int p, const RV& R, int q, int* istar, int* 
   *jstar = jhi;
 }
 
-// Chains stored as rank lists in LDS, S (rank-padded) read from LDS.
+// Chains stored as rank lists in LDS, S read from LDS.
+template <typename SI>
 struct LdsChain {
   const uint16_t* v;
   const double* S;
   __device__ __forceinline__ int pos(int i) const { return v[i]; }
-  __device__ __forceinline__ double s(int i) const { return S[rpad(v[i])]; }
+  __device__ __forceinline__ double s(int i) const { return S[SI::at(v[i])]; }
 };
 
-// Lower hull (collinear points dropped) of the points 0..d of S (indexed through rpad), computed by NT threads with
-// E ranks per leaf.  vert must hold NT*(E+1) entries, cnt NT ints, mres NT ints.  On return
-// vert[0..cnt[0]) are the hull vertices (0 and d included).  All threads of the block must call;
-// requires 1 <= d <= NT*E.
-template <int NT, int E>
-__device__ void tile_hull(const double* S, int d, uint16_t* vert, int* cnt, int* mres) {
+// Lower hull (collinear points dropped) of the points 0..d of S (layout SI), computed by NT
+// threads with E ranks per leaf.  vert must hold NT*(E+1) entries, cnt and mres NT counts each
+// (CT: a signed type holding -1..NT*E+1).  On return vert[0..cnt[0]) are the hull vertices (0
+// and d included).  All threads of the block must call; requires 1 <= d <= NT*E.
+template <int NT, int E, typename SI, typename CT>
+__device__ void tile_hull(const double* S, int d, uint16_t* vert, CT* cnt, CT* mres) {
   constexpr int CP = E / 2 + 1;  // copy entries per thread per level
   const int t = threadIdx.x;
   const int nleaf = (d + E - 1) / E;
   if (t < nleaf) {
     const int a = t * E;
     const int b = min(a + E, d);
-    cnt[t] = leaf_hull(S, a, b, vert + t * (E + 1));
+    cnt[t] = (CT)leaf_hull<SI>(S, a, b, vert + t * (E + 1));
   }
   __syncthreads();
   for (int lvl = 1; (1 << (lvl - 1)) < nleaf; ++lvl) {
@@ -276,12 +296,12 @@ __device__ void tile_hull(const double* S, int d, uint16_t* vert, int* cnt, int*
       const int rleaf = lleaf + half;
       int istar = -1, jstar = -1;
       if (rleaf < nleaf) {
-        LdsChain L{vert + lleaf * (E + 1), S};
-        LdsChain R{vert + rleaf * (E + 1), S};
+        LdsChain<SI> L{vert + lleaf * (E + 1), S};
+        LdsChain<SI> R{vert + rleaf * (E + 1), S};
         bridge(L, cnt[lleaf] - 1, R, cnt[rleaf] - 1, &istar, &jstar);
       }
-      mres[2 * t] = istar;
-      mres[2 * t + 1] = jstar;
+      mres[2 * t] = (CT)istar;
+      mres[2 * t + 1] = (CT)jstar;
     }
     __syncthreads();
     // move the surviving right part next to the surviving left part (read all, then write)
@@ -307,7 +327,7 @@ __device__ void tile_hull(const double* S, int d, uint16_t* vert, int* cnt, int*
       const int e = s + (r << lvl);
       if (e < len) vert[lbase + istar + 1 + e] = tmp[r];
     }
-    if (s == 0 && istar >= 0) cnt[m << lvl] = istar + 1 + len;
+    if (s == 0 && istar >= 0) cnt[m << lvl] = (CT)(istar + 1 + len);
     __syncthreads();
   }
 }
@@ -401,25 +421,25 @@ __device__ __forceinline__ uint32_t ica_neighbours(uint32_t b, uint32_t rem) {
 // segment joining its neighbouring candidates (the blocks on either side collide: avg y left >=
 // avg y right), and repeats until nothing changes.  Returns true on convergence within max_rounds
 // (candidates = hull vertices, *lc / *rc = carries of the final candidate set), false otherwise.
-// sv[0..E] are this thread's S values (sv[i] = S_{k0+i}); S is the rank-padded LDS copy.
+// sv[0..E] are this thread's S values (sv[i] = S_{k0+i}); S is the LDS copy (layout SI).
 // The first round has every point as a candidate, so its neighbours are the adjacent ranks and
 // the test is y_{k-1} >= y_k (S_k - S_{k-1} >= S_{k+1} - S_k), done in registers.  Later rounds
 // test only the candidates whose neighbouring candidates changed in the round before (within the
 // thread, or a changed carry from another thread); every other candidate keeps its last outcome,
 // so the removal sets are those of the full rounds.
-template <int NT, int E>
+template <int NT, int E, typename SI>
 __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, int max_rounds, uint32_t* bm,
                            Cand* lc, Cand* rc, Cand* shL, Cand* shR, int* shF) {
   constexpr int NW = NT / kWave;
   const int k0 = threadIdx.x * E;
-  const Cand dflt{d, S[rpad(d)]};
+  const Cand dflt{d, S[SI::at(d)]};
   uint32_t valid = 0;
 #pragma unroll
   for (int i = 0; i < E; ++i) valid |= (k0 + i < d ? 1u : 0u) << i;
   // round 1: adjacent neighbours
   uint32_t rem = 0;
   {
-    double dl = sv[0] - S[rpad(max(k0 - 1, 0))];
+    double dl = sv[0] - S[SI::at(max(k0 - 1, 0))];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const double dr = sv[i + 1] - sv[i];
@@ -437,9 +457,9 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
       const int hi = 31 - __clz(b);
       const int lo = __ffs(b) - 1;
       mineL.pos = k0 + hi;
-      mineL.s = S[rpad(k0 + hi)];
+      mineL.s = S[SI::at(k0 + hi)];
       mineR.pos = k0 + lo;
-      mineR.s = S[rpad(k0 + lo)];
+      mineR.s = S[SI::at(k0 + lo)];
     }
     // carries of the current candidates, and whether the last round removed anything
     const int slot = (round & 1) * NW;
@@ -467,9 +487,9 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
       const uint32_t above_i = b & ~((2u << i) - 1u);
       const int pp = below_i ? k0 + 31 - __clz(below_i) : l.pos;
       const int np = above_i ? k0 + __ffs(above_i) - 1 : r.pos;
-      const double sp = below_i ? S[rpad(pp)] : l.s;
-      const double sn = above_i ? S[rpad(np)] : r.s;
-      if (pp >= 0 && !below(pp, sp, k0 + i, S[rpad(k0 + i)], np, sn)) rem |= 1u << i;
+      const double sp = below_i ? S[SI::at(pp)] : l.s;
+      const double sn = above_i ? S[SI::at(np)] : r.s;
+      if (pp >= 0 && !below(pp, sp, k0 + i, S[SI::at(k0 + i)], np, sn)) rem |= 1u << i;
     }
     b &= ~rem;
     dirty = rem ? ica_neighbours(b, rem) : 0u;
@@ -478,14 +498,45 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
   return false;
 }
 
+// The E entries a[k0 .. k0+E) of a flat u16 array (k0 a multiple of 8), read as 16-byte words.
+template <int E>
+__device__ __forceinline__ void load_u16_block(const uint16_t* a, int k0, uint16_t (&v)[E]) {
+  static_assert(E % 8 == 0, "E must be a multiple of 8");
+#pragma unroll
+  for (int q = 0; q < E / 8; ++q) {
+    const uint4 w = *reinterpret_cast<const uint4*>(a + k0 + 8 * q);
+    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      v[8 * q + 2 * j] = (uint16_t)(u[j] & 0xFFFFu);
+      v[8 * q + 2 * j + 1] = (uint16_t)(u[j] >> 16);
+    }
+  }
+}
+
+// The E entries a[k0 .. k0+E) of a flat u32 array (k0 a multiple of 4), read as 16-byte words.
+template <int E>
+__device__ __forceinline__ void load_u32_block(const uint32_t* a, int k0, uint32_t (&v)[E]) {
+  static_assert(E % 4 == 0, "E must be a multiple of 4");
+#pragma unroll
+  for (int q = 0; q < E / 4; ++q) {
+    const uint4 w = *reinterpret_cast<const uint4*>(a + k0 + 4 * q);
+    v[4 * q] = w.x;
+    v[4 * q + 1] = w.y;
+    v[4 * q + 2] = w.z;
+    v[4 * q + 3] = w.w;
+  }
+}
+
 // Cluster value of every rank owned by this thread from its final cluster starts: bm (bit i =
 // rank k0+i starts a cluster), sv[0..E] (S at k0..k0+E), carries lc (last start before k0) and
 // rc (first start after the thread's ranks, or the end point d).  Rank k0+i gets
-// offset + (S_b - S_a) / (b - a) for its cluster [a, b); res[idx[rpad(k)]] receives it.  The next
-// cluster start is carried down a register sweep, so no S value is read from LDS.
+// offset + (S_b - S_a) / (b - a) for its cluster [a, b); res[ix[i]] receives it (ix: the original
+// indices of the thread's ranks).  The next cluster start is carried down a register sweep, so
+// no S value is read from LDS.
 template <int E>
 __device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 1], Cand lc, Cand rc, int d,
-                                            double offset, const uint16_t* idx, float* res) {
+                                            double offset, const uint16_t (&ix)[E], float* res) {
   const int k0 = threadIdx.x * E;
   if (k0 >= d) return;
   float val[E];
@@ -504,7 +555,7 @@ __device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     if ((bm >> i) & 1u) cur = val[i];
-    if (k0 + i < d) res[idx[rpad(k0 + i)]] = cur;
+    if (k0 + i < d) res[ix[i]] = cur;
   }
 }
 

@@ -22,32 +22,35 @@ namespace wsr {
 constexpr int kBucketMax = 48;
 constexpr int kRankPad = 64;
 
+// LDS of the forward kernel, sized so that three workgroups of the 4096 class share a CU.  The
+// prefix sums use the transposed rank layout; the other arrays indexed by rank are flat (a
+// thread's E = 8 consecutive ranks are read as 16-byte words).
 template <int TMAX, int NT>
 struct FwdSmem {
   static constexpr int E = TMAX / NT;
   static constexpr int NW = NT / kWave;
-  // arrays indexed by rank use rpad(); arrays indexed by original index or cluster do not
-  union {
-    uint32_t key[rpad_size(TMAX)];  // sort keys; sorted keys after the sort (rank-padded)
-    float cval[TMAX];               // per-cluster values (hull-merge output phase)
-    float outv[TMAX];               // results by original index (rounds output phase)
-  } a;
-  uint16_t idx[rpad_size(TMAX)];  // payload: original index of each rank (rank-padded)
-  union {
-    double S[rpad_size(TMAX + 1)];  // prefix sums (forward) / G (backward), rank-padded
-    float outv[TMAX];               // results by original index (output phase)
+  using SL = RankT<NT, E>;
+  // (16-byte aligned: blocks of ranks are read and written as 16-byte words)
+  union alignas(16) {
+    double S[SL::kSize];  // prefix sums S_0..S_d (layout SL)
+    float outv[TMAX];    // results by original index (after the collision rounds)
     struct {
-      uint32_t cnt2[TMAX + 1];          // bucket sort: 2*TMAX 16-bit counters in pairs, then starts
-      uint32_t tkey[TMAX + kRankPad];  // bucket sort: keys in bucket order, sentinel-padded
+      uint32_t key[TMAX + 1];          // 2*TMAX 16-bit bucket counters in pairs, then starts;
+                                       // the sorted keys once the starts are read
+      uint32_t tkey[TMAX + kRankPad];  // keys in bucket order, sentinel-padded
     } bs;
+    struct {
+      uint32_t key[TMAX + 1];  // keys by position; the sorted keys after the last pass
+      uint32_t wcnt[NW][256];
+    } rs;
   } c;
+  alignas(16) uint16_t idx[TMAX];  // original index of each rank
   union {
-    uint32_t wcnt[NW][256];
     struct {
       uint16_t vert[NT * (E + 1)];
-      int cnt[NT];
-      int mres[NT];
-    } h;
+      int16_t cnt[NT];
+      int16_t mres[NT];
+    } h;                  // hull merge (collision rounds not converged)
     uint16_t tidx[TMAX];  // bucket sort: indices in bucket order
   } d;
   uint32_t lmask[TMAX / 32 + 2];
@@ -61,23 +64,27 @@ struct FwdSmem {
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
 
+struct SegView {
+  int64_t start;
+  int d;
+  float lam;
+};
 
-__device__ __forceinline__ void resolve_segment(const SegArgs& a, int64_t* start, int* d, float* lam) {
+__device__ __forceinline__ SegView resolve_segment(const SegArgs& a) {
   if (a.sched) {
     const int s = a.sched[blockIdx.x];
     const int64_t o = a.offsets[s];
-    *start = o;
-    *d = (int)(a.offsets[s + 1] - o);
-    *lam = a.lam_arr ? a.lam_arr[s] : a.lam_scalar;
-  } else {
-    *start = a.start;
-    *d = a.d;
-    *lam = a.lam_arr ? a.lam_arr[a.seg_id] : a.lam_scalar;
+    return SegView{o, (int)(a.offsets[s + 1] - o), a.lam_arr ? a.lam_arr[s] : a.lam_scalar};
   }
+  return SegView{a.start, a.d, a.lam_arr ? a.lam_arr[a.seg_id] : a.lam_scalar};
 }
 
+// Waves per SIMD the forward kernel is compiled for (register budget): the 4096 class fits
+// three workgroups of 8 waves per CU by LDS, so it keeps its registers to 6 waves per SIMD.
+constexpr int fwd_waves_per_simd(int tmax) { return tmax == 4096 ? 6 : 1; }
+
 // Stable block radix sort of the register-held items (wave-striped layout:
-// position p = wave*64*IPT + r*64 + lane).  On return sm.a.key / sm.idx hold the sorted items.
+// position p = wave*64*IPT + r*64 + lane).  On return sm.c.rs.key / sm.idx hold the sorted items.
 template <int TMAX, int NT>
 __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT],
                                  uint16_t (&ix)[TMAX / NT], int d) {
@@ -97,22 +104,22 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
   for (int r = 0; r < IPT; ++r) {
     if (r < nr) {
       const int p = wbase + r * kWave + lane;
-      sm.a.key[rpad(p)] = k[r];
-      sm.idx[rpad(p)] = ix[r];
+      sm.c.rs.key[p] = k[r];
+      sm.idx[p] = ix[r];
     }
   }
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = pass * 8;
-    for (int j = lane; j < 256; j += kWave) sm.d.wcnt[wv][j] = 0u;
+    for (int j = lane; j < 256; j += kWave) sm.c.rs.wcnt[wv][j] = 0u;
     uint16_t rk[IPT];
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       if (r < nr) {
         const uint32_t dg = (k[r] >> shift) & 255u;
         const uint64_t peers = match_digit8(dg);
-        const uint32_t base = sm.d.wcnt[wv][dg];
+        const uint32_t base = sm.c.rs.wcnt[wv][dg];
         const int nbelow = __popcll(peers & lanemask_lt());
-        if (nbelow == 0) sm.d.wcnt[wv][dg] = base + (uint32_t)__popcll(peers);
+        if (nbelow == 0) sm.c.rs.wcnt[wv][dg] = base + (uint32_t)__popcll(peers);
         rk[r] = (uint16_t)(base + nbelow);
       }
     }
@@ -127,8 +134,8 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
       uint32_t run = 0;
       if (dg < 256) {
         for (int w = 0; w < NW; ++w) {
-          const uint32_t c = sm.d.wcnt[w][dg];
-          sm.d.wcnt[w][dg] = run;
+          const uint32_t c = sm.c.rs.wcnt[w][dg];
+          sm.c.rs.wcnt[w][dg] = run;
           run += c;
         }
       }
@@ -143,7 +150,7 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
       const int dg = tid * DPT + q;
       if (dg < 256) {
         if ((int)tot[q] == counted) sm.flag[pass] = 1;  // every key has this digit: identity pass
-        for (int w = 0; w < NW; ++w) sm.d.wcnt[w][dg] += acc;
+        for (int w = 0; w < NW; ++w) sm.c.rs.wcnt[w][dg] += acc;
       }
       acc += tot[q];
     }
@@ -153,9 +160,9 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
     for (int r = 0; r < IPT; ++r) {
       if (r < nr) {
         const uint32_t dg = (k[r] >> shift) & 255u;
-        const int np = (int)sm.d.wcnt[wv][dg] + rk[r];
-        sm.a.key[rpad(np)] = k[r];
-        sm.idx[rpad(np)] = ix[r];
+        const int np = (int)sm.c.rs.wcnt[wv][dg] + rk[r];
+        sm.c.rs.key[np] = k[r];
+        sm.idx[np] = ix[r];
       }
     }
     __syncthreads();
@@ -163,15 +170,15 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
     for (int r = 0; r < IPT; ++r) {
       if (r < nr) {
         const int p = wbase + r * kWave + lane;
-        k[r] = sm.a.key[rpad(p)];
-        ix[r] = sm.idx[rpad(p)];
+        k[r] = sm.c.rs.key[p];
+        ix[r] = sm.idx[p];
       }
     }
     __syncthreads();
   }
 }
 
-// Bucket-rank sort of the register-held items (any layout) into sm.a.key / sm.idx.
+// Bucket-rank sort of the register-held items (any layout) into sm.c.bs.key / sm.idx.
 // Keys are spread over NB = 2*TMAX buckets by a monotone map of their value over [min, max].  One
 // atomic pass counts the keys per bucket (16-bit counters, two to a word) and gives each key a
 // slot inside its bucket; a scan turns counts into bucket starts; keys are placed in bucket
@@ -194,8 +201,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int wbase = wv * kWave * IPT;
-  uint32_t* cnt2 = sm.c.bs.cnt2;
-  const uint16_t* st16 = reinterpret_cast<const uint16_t*>(sm.c.bs.cnt2);
+  uint32_t* cnt2 = sm.c.bs.key;
+  const uint16_t* st16 = reinterpret_cast<const uint16_t*>(sm.c.bs.key);
   uint32_t* tkey = sm.c.bs.tkey;
   uint16_t* tidx = sm.d.tidx;
 
@@ -228,8 +235,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     for (int r = 0; r < IPT; ++r) {
       const int p = wbase + r * kWave + lane;
       if (p < d) {
-        sm.a.key[rpad(ix[r])] = k[r];
-        sm.idx[rpad(ix[r])] = ix[r];
+        cnt2[ix[r]] = k[r];
+        sm.idx[ix[r]] = ix[r];
       }
     }
     __syncthreads();
@@ -257,12 +264,12 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   // (the high half of the scanned word counts the key pairs sharing a bucket, sum c(c-1)/2: with
   // distinct keys exactly one key of each pair is the smaller)
   uint32_t c[WPT];
+  load_u32_block<WPT>(cnt2, tid * WPT, c);
   int sum = 0;
   int pairs = 0;
   int cmax = 0;
 #pragma unroll
   for (int i = 0; i < WPT; ++i) {
-    c[i] = cnt2[tid * WPT + i];
     const int c0 = (int)(c[i] & 0xFFFFu), c1 = (int)(c[i] >> 16);
     sum += c0 + c1;
     pairs += ((c0 * (c0 - 1)) >> 1) + ((c1 * (c1 - 1)) >> 1);
@@ -277,11 +284,13 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   if (lane == 0) sm.ured[wv] = (uint32_t)cmax;
 #pragma unroll
   for (int i = 0; i < WPT; ++i) {
-    const int s0 = run;
-    run += (int)(c[i] & 0xFFFFu);
-    cnt2[tid * WPT + i] = (uint32_t)s0 | ((uint32_t)run << 16);
-    run += (int)(c[i] >> 16);
+    const int c0 = (int)(c[i] & 0xFFFFu), c1 = (int)(c[i] >> 16);
+    c[i] = (uint32_t)run | ((uint32_t)(run + c0) << 16);
+    run += c0 + c1;
   }
+#pragma unroll
+  for (int q = 0; q < WPT / 4; ++q)
+    *reinterpret_cast<uint4*>(cnt2 + tid * WPT + 4 * q) = make_uint4(c[4 * q], c[4 * q + 1], c[4 * q + 2], c[4 * q + 3]);
   if (tid == NT - 1) cnt2[TMAX] = (uint32_t)total;  // start of the (empty) bucket NB
   for (int j = tid; j < kRankPad; j += NT) tkey[d + j] = 0xFFFFFFFFu;  // above every finite key
   __syncthreads();
@@ -322,8 +331,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     const int p = wbase + r * kWave + lane;
     if (p < d) {
       below += rank[r] - lo[r];
-      sm.a.key[rpad(rank[r])] = k[r];
-      sm.idx[rpad(rank[r])] = ix[r];
+      cnt2[rank[r]] = k[r];
+      sm.idx[rank[r]] = ix[r];
     }
   }
   below = wave_sum(below);
@@ -346,8 +355,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
     for (int r = 0; r < IPT; ++r) {
       const int p = wbase + r * kWave + lane;
       if (p < d) {
-        sm.a.key[rpad(rank[r])] = k[r];
-        sm.idx[rpad(rank[r])] = ix[r];
+        cnt2[rank[r]] = k[r];
+        sm.idx[rank[r]] = ix[r];
       }
     }
     __syncthreads();
@@ -355,11 +364,11 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   return true;
 }
 
-// Given the cluster-start list vert[0..ncl] (ranks, vert[ncl] == d) and per-cluster values
-// cval[0..ncl), write res[idx[k]] = cval[cluster of k] for all ranks k < d (blocked ranges).
-template <int NT, int E>
-__device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int ncl, const float* cval,
-                                                       const uint16_t* idx, float* res, int d) {
+// Given the hull vertices vert[0..ncl] (ranks, vert[ncl] == d) of S, write every rank k < d of
+// the thread's blocked range its cluster value offset + (S_b - S_a)/(b - a) at out[idx[k]].
+template <int NT, int E, typename SL>
+__device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int ncl, const double* S,
+                                                       double offset, const uint16_t* idx, float* out, int d) {
   const int k0 = threadIdx.x * E;
   if (k0 >= d) return;
   // cluster of k0: last i with vert[i] <= k0
@@ -371,30 +380,31 @@ __device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int
     else
       hi = mid;
   }
-  int cid = lo;
-  int next = vert[cid + 1];
-  float v = cval[cid];
+  int a = vert[lo];
+  int b = vert[lo + 1];
+  float v = (float)(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a));
   const int k1 = min(k0 + E, d);
   for (int k = k0; k < k1; ++k) {
-    while (k >= next) {
-      ++cid;
-      next = vert[cid + 1];
-      v = cval[cid];
+    while (k >= b) {
+      ++lo;
+      a = b;
+      b = vert[lo + 1];
+      v = (float)(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a));
     }
-    res[idx[rpad(k)]] = v;
+    out[idx[k]] = v;
   }
 }
 
 template <int TMAX, int NT>
-__global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float* w, float* out,
+__global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small(SegArgs args, const float* w, float* out,
                                                        int32_t* perm_out, uint32_t* mask_out) {
   constexpr int IPT = TMAX / NT;
   constexpr int E = IPT;
   __shared__ FwdSmem<TMAX, NT> sm;
-  int64_t start;
-  int d;
-  float lam;
-  resolve_segment(args, &start, &d, &lam);
+  const SegView seg = resolve_segment(args);
+  const int64_t start = seg.start;
+  const int d = seg.d;
+  const float lam = seg.lam;
   if (d <= 0) return;
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -438,17 +448,20 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
 
   if (!block_bucket_sort<TMAX, NT>(sm, k, ix, d)) block_radix_sort<TMAX, NT>(sm, k, ix, d);
 
-  // centred FP64 prefix sums S_k (blocked: thread t owns ranks [tE, tE+E))
-  const double c = (double)key_to_float(sm.a.key[rpad(d >> 1)]);
+  // centred FP64 prefix sums S_k (blocked: thread t owns ranks [tE, tE+E)); S overwrites the
+  // sorted keys, so every key is read before the block scan's barriers
+  using SL = typename FwdSmem<TMAX, NT>::SL;
+  const uint32_t* skey = sm.c.bs.key;
+  const double c = (double)key_to_float(skey[d >> 1]);
   const double lamd = (double)lam / (double)(d - 1);
   const int k0 = tid * E;
+  uint32_t kv[E];
+  load_u32_block<E>(skey, k0, kv);  // ranks past d hold stale words, masked below
   double xs[E];
   double lsum = 0.0;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
-    const int kk = k0 + i;
-    const double xv = (double)key_to_float(sm.a.key[rpad(min(kk, d - 1))]) - c;  // unconditional load
-    xs[i] = kk < d ? xv : 0.0;
+    xs[i] = k0 + i < d ? (double)key_to_float(kv[i]) - c : 0.0;
     lsum += xs[i];
   }
   double Xk = block_excl_scan<NT, double>(lsum, sm.dred, (double*)nullptr);
@@ -458,53 +471,54 @@ __global__ __launch_bounds__(NT) void k_prox_fwd_small(SegArgs args, const float
     const int kk = k0 + i;
     sv[i] = Xk + lamd * (double)kk * (double)(d - kk);
     if (i < E) {
-      if (kk <= d) sm.c.S[rpad(kk)] = sv[i];
+      if (kk <= d) sm.c.S[SL::at(kk)] = sv[i];
       Xk += xs[i];
     }
   }
-  if (tid == NT - 1 && d == TMAX) sm.c.S[rpad(TMAX)] = sv[E];  // X_d (the shift term vanishes at k = d)
+  if (tid == NT - 1 && d == TMAX) sm.c.S[SL::at(TMAX)] = sv[E];  // X_d (the shift term vanishes at k = d)
   __syncthreads();
 
   // collisions: ImminentCollisions rounds (converge in a few rounds on typical weights), else
   // the bounded-depth hull merge
   uint32_t bm;
   Cand lc, rc;
-  const float* res;
-  if (ica_rounds<NT, E>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
+  bool staged = true;
+  if (ica_rounds<NT, E, SL>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
     if (bm) {
       const int b0 = k0 + off;
       const uint64_t wide = (uint64_t)bm << (b0 & 31);
       atomicOr(&sm.lmask[b0 >> 5], (uint32_t)wide);
       if (wide >> 32) atomicOr(&sm.lmask[(b0 >> 5) + 1], (uint32_t)(wide >> 32));
     }
-    walk_values<E>(bm, sv, lc, rc, d, c, sm.idx, sm.a.outv);
-    res = sm.a.outv;
+    // S is no longer read once the rounds have converged: the results take its place
+    uint16_t ixr[E];
+    load_u16_block<E>(sm.idx, k0, ixr);
+    walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv);
   } else {
-    tile_hull<NT, E>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
-    // cluster values: c + (S_b - S_a)/(b - a) for consecutive hull vertices a < b
+    tile_hull<NT, E, SL, int16_t>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
     const int nv = sm.d.h.cnt[0];
     const uint16_t* vert = sm.d.h.vert;
     for (int i = tid; i < nv - 1; i += NT) {
-      const int a = vert[i], b = vert[i + 1];
-      sm.a.cval[i] = (float)(c + (sm.c.S[rpad(b)] - sm.c.S[rpad(a)]) / (double)(b - a));
+      const int a = vert[i];
       atomicOr(&sm.lmask[(a + off) >> 5], 1u << ((a + off) & 31));
     }
-    __syncthreads();
-    scatter_cluster_values<NT, E>(vert, nv - 1, sm.a.cval, sm.idx, sm.c.outv, d);
-    res = sm.c.outv;
+    // values straight to their original positions (S still holds the sums)
+    scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d);
+    staged = false;
   }
   __syncthreads();
-  for (int i = tid; i < d; i += NT) out[start + i] = res[i];
+  if (staged)
+    for (int i = tid; i < d; i += NT) out[start + i] = sm.c.outv[i];
   if (perm_out)
-    for (int i = tid; i < d; i += NT) perm_out[start + i] = sm.idx[rpad(i)];
+    for (int i = tid; i < d; i += NT) perm_out[start + i] = sm.idx[i];
   if (mask_out) store_mask_words<NT>(mask_out, start, d, sm.lmask);
 }
 
 template <int TMAX, int NT>
 struct BwdSmem {
   static constexpr int NW = NT / kWave;
-  float g[TMAX];                  // upstream gradient by original index, then results
-  uint16_t idx[rpad_size(TMAX)];  // saved permutation (rank -> original index), rank-padded
+  float g[TMAX];                   // upstream gradient by original index, then results
+  alignas(16) uint16_t idx[TMAX];  // saved permutation (rank -> original index)
   uint32_t lmask[TMAX / 32 + 2];
   double dred[NW + 1];
   Cand shL[NW], shR[NW];
@@ -516,10 +530,10 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
                                                        const int32_t* perm_in, const uint32_t* mask_in) {
   constexpr int E = TMAX / NT;
   __shared__ BwdSmem<TMAX, NT> sm;
-  int64_t start;
-  int d;
-  float lam;
-  resolve_segment(args, &start, &d, &lam);
+  const SegView seg = resolve_segment(args);
+  const int64_t start = seg.start;
+  const int d = seg.d;
+  const float lam = seg.lam;
   if (d <= 0) return;
   const int tid = threadIdx.x;
   const int off = (int)(start & 31);
@@ -528,12 +542,14 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   for (int i = tid; i < d; i += NT) {
     sm.g[i] = gin[start + i];
     const int p = perm_in[start + i];
-    sm.idx[rpad(i)] = (uint16_t)min(max(p, 0), d - 1);
+    sm.idx[i] = (uint16_t)min(max(p, 0), d - 1);
   }
   for (int j = tid; j < nwords; j += NT) sm.lmask[j] = mask_in[g0 + j];
   __syncthreads();
   // cotangent in rank order, cluster starts of the thread's ranks, FP64 prefix sums G (registers)
   const int k0 = tid * E;
+  uint16_t ixr[E];
+  load_u16_block<E>(sm.idx, k0, ixr);  // ranks past d hold stale entries, not used
   float gk[E];
   double lsum = 0.0;
   uint32_t bm = 0;
@@ -541,7 +557,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   for (int i = 0; i < E; ++i) {
     const int kk = k0 + i;
     const int kc = min(kk, d - 1);
-    const float gv = sm.g[sm.idx[rpad(kc)]];  // unconditional gather
+    const float gv = sm.g[kk < d ? ixr[i] : 0];  // unconditional gather
     const int b = kc + off;
     const uint32_t st = (kk == 0) | ((sm.lmask[b >> 5] >> (b & 31)) & 1u);
     gk[i] = kk < d ? gv : 0.0f;
@@ -565,7 +581,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   }
   Cand lc, rc;
   carry_exchange<NT>(mineL, mineR, false, Cand{d, total}, sm.shL, sm.shR, sm.shF, &lc, &rc);
-  walk_values<E>(bm, sv, lc, rc, d, 0.0, sm.idx, sm.g);  // every gather above is done (block scan)
+  walk_values<E>(bm, sv, lc, rc, d, 0.0, ixr, sm.g);  // every gather above is done (block scan)
   __syncthreads();
   for (int i = tid; i < d; i += NT) gout[start + i] = sm.g[i];
 }
