@@ -134,7 +134,15 @@ def trace_kernels(fn, reps):
     return wsr.wsr_trace_collect()
 
 
-def roofline(trace, n_el, steps):
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary of this
+    workload (calibrated against a plain copy kernel); None when there is none or the kernel
+    sources changed since it was taken."""
+    from paper_2311_03096_amd.prof_summary import read_traffic
+    return read_traffic(os.path.join(ROOT, "profiles", "traffic_%s.md" % workload), workload, kernel)
+
+
+def roofline(trace, n_el, steps, workload):
     """Dominant kernel by total time; achieved = algorithmic bytes per launch / mean duration."""
     name, (cnt, tot) = max(trace.items(), key=lambda kv: kv[1][1])
     avg_ms = tot / cnt
@@ -146,9 +154,15 @@ def roofline(trace, n_el, steps):
     if name in ("radix_scatter", "radix_hist"):
         per_launch_el = n_el  # every pass covers the whole segment
     ach = bpe * per_launch_el / (avg_ms * 1e-3) / 1e9
-    return dict(kernel=name, launches_per_step=cnt / steps, avg_ms=round(avg_ms, 5),
-                bytes_per_el=bpe, bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(ach / HBM_PEAK_GBS, 4), traffic=None)
+    tr = measured_traffic(workload, name)
+    res = dict(kernel=name, launches_per_step=cnt / steps, avg_ms=round(avg_ms, 5),
+               bytes_per_el=bpe, algorithmic_bytes_per_launch=bpe * per_launch_el, bound="hbm",
+               achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
+               traffic=None if tr is None else round(tr))
+    if tr is not None:
+        res["traffic_unit"] = "HBM bytes per launch"
+        res["traffic_over_algorithmic"] = round(tr / (bpe * per_launch_el), 3)
+    return res
 
 
 def cpu_baseline(case):
@@ -156,13 +170,17 @@ def cpu_baseline(case):
     import oracle
     w, off, lam = case["w"], case["offsets"], case["lam"]
     g = np.random.default_rng(123).standard_normal(w.shape[0])
-    t0 = time.perf_counter()
-    u, perm, start = oracle.prox_segments(w, lam, off, n_threads=1)
-    oracle.vjp(g, perm, start, off)
-    dt = time.perf_counter() - t0
-    return dict(value=float(w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
-                sample="one full fwd+vjp step of %s (%d elements), FP64 sort + stack PAV, 1 thread, %.1f s"
-                % (case["name"], w.shape[0], dt))
+    reps, t0 = 0, time.perf_counter()
+    while True:  # whole steps until about 10 s of CPU work
+        u, perm, start = oracle.prox_segments(w, lam, off, n_threads=1)
+        oracle.vjp(g, perm, start, off)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= 10.0:
+            break
+    return dict(value=float(reps * w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
+                sample="%d full fwd+vjp steps of %s (%d elements each), FP64 sort + stack PAV, 1 thread, "
+                "%.1f s" % (reps, case["name"], w.shape[0], dt))
 
 
 def batched_vs_per_row(steps, warmup, per_row=True):
@@ -186,7 +204,7 @@ def batched_vs_per_row(steps, warmup, per_row=True):
     ms_batched, _ = time_steps(b, steps, warmup)
     ms_rows = time_steps(p, max(2, steps // 4), 1)[0] if per_row else float("nan")
     tr = trace_kernels(b, 3)
-    roof = roofline({k: v for k, v in tr.items() if k.startswith("prox_fwd")}, n, 3)
+    roof = roofline({k: v for k, v in tr.items() if k.startswith("prox_fwd")}, n, 3, "mlp_rows")
     return dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
                 elements=n, ms_per_step_graph=round(ms_graph, 4), ms_per_step_batched=round(ms_batched, 4),
                 ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
@@ -225,7 +243,7 @@ def main():
     step = Step(case)
     ms, wall = time_steps(step, args.steps, args.warmup)
     tr = trace_kernels(step, 3)
-    roof = roofline(tr, d, 3)
+    roof = roofline(tr, d, 3, {"chain": "chain_d2p24", "typical": "typical_d2p24"}[args.workload])
     log("ms/step", ms, "trace", tr)
     extra = dict(kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
                  wall_ms_per_step=round(wall, 4))
