@@ -198,8 +198,7 @@ struct TileSmem {
   int mres[kBigThreads];
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
-  Cand shL[2 * (kBigThreads / kWave)], shR[2 * (kBigThreads / kWave)];
-  int shF[2 * (kBigThreads / kWave)];
+  WaveBound wb[2 * (kBigThreads / kWave)];
   double xtot;
 };
 
@@ -257,7 +256,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   uint32_t bm;
   Cand lc, rc;
-  if (ica_rounds<kBigThreads, kBigE, RankPadded>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
+  if (ica_rounds<kBigThreads, kBigE, RankPadded>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.wb)) {
     // hull vertices = surviving candidates in rank order, then the tile's end point
     int nv;
     int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);

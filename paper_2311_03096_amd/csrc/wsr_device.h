@@ -108,8 +108,9 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
 }
 
 // Block-wide exclusive scan; sh must hold NT/64 + 1 values.  Every thread of the block must call.
-// Summation order is fixed, so results are deterministic.
-template <int NT, typename T>
+// Summation order is fixed (waves in order), so results are deterministic.  TRAIL = false leaves
+// out the closing barrier: the caller must then not write sh again before another barrier.
+template <int NT, typename T, bool TRAIL = true>
 __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   constexpr int NW = NT / kWave;
   const int lane = lane_id();
@@ -118,20 +119,16 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   T exc = wave_shift_up(inc, T(0));
   if (lane == kWave - 1) sh[wv] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    T run = T(0);
-    for (int i = 0; i < NW; ++i) {
-      T t = sh[i];
-      sh[i] = run;
-      run += t;
-    }
-    sh[NW] = run;
+  T base = T(0), tot = T(0);
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const T t = sh[w];
+    if (w < wv) base += t;
+    tot += t;
   }
-  __syncthreads();
-  T res = sh[wv] + exc;
-  if (total) *total = sh[NW];
-  __syncthreads();
-  return res;
+  if (total) *total = tot;
+  if (TRAIL) __syncthreads();
+  return base + exc;
 }
 
 // Layouts of LDS arrays indexed by rank (prefix sums S, rank -> index maps): rank-padded (blocks
@@ -415,28 +412,50 @@ __device__ __forceinline__ uint32_t ica_neighbours(uint32_t b, uint32_t rem) {
   return dirty;
 }
 
-// ImminentCollisions rounds (Sec. 4.1; Alg. imminent_collisions_v2) on hull candidates: thread t
-// owns points k0 = t*E .. k0+E-1 (bit i of *bm = point k0+i is a candidate), point d is the fixed
-// right end.  Every round removes, all at once, each candidate that is not strictly below the
-// segment joining its neighbouring candidates (the blocks on either side collide: avg y left >=
-// avg y right), and repeats until nothing changes.  Returns true on convergence within max_rounds
-// (candidates = hull vertices, *lc / *rc = carries of the final candidate set), false otherwise.
-// sv[0..E] are this thread's S values (sv[i] = S_{k0+i}); S is the LDS copy (layout SI).
-// The first round has every point as a candidate, so its neighbours are the adjacent ranks and
-// the test is y_{k-1} >= y_k (S_k - S_{k-1} >= S_{k+1} - S_k), done in registers.  Later rounds
-// test only the candidates whose neighbouring candidates changed in the round before (within the
-// thread, or a changed carry from another thread); every other candidate keeps its last outcome,
-// so the removal sets are those of the full rounds.
+// One wave's boundary in the collision exchange: its first and last candidates, the neighbours
+// outside the wave its last sweeps assumed, and whether its sweeps overflowed.
+struct WaveBound {
+  Cand first, last;
+  int lassume, rassume;
+  int overflow;
+};
+
+// ImminentCollisions (Sec. 4.1; Alg. imminent_collisions_v2) on hull candidates: thread t owns
+// points k0 = t*E .. k0+E-1 (bit i of *bm = point k0+i is a candidate), point d is the fixed
+// right end.  A candidate is removed when it is not strictly below the segment joining its
+// neighbouring candidates (the blocks on either side collide: avg y left >= avg y right).
+//
+// The order of removals does not change the result: a point that is not strictly below the
+// segment joining any point on its left and any point on its right is no vertex of the lower
+// hull, so it may be removed whatever the other candidates are, and the process stops at the
+// hull (collinear points dropped) whatever the order.  Only the final check needs the exact
+// neighbours.  Hence:
+//   1. a first round with every point a candidate (neighbours = adjacent ranks, the test is
+//      y_{k-1} >= y_k), in registers;
+//   2. sweeps inside each wave, without barriers, with the neighbours outside the wave taken as
+//      last known; a removal re-tests the thread's neighbouring candidates at once, a changed
+//      carry re-tests the thread's first / last candidate, until a sweep removes nothing;
+//   3. one block exchange of the waves' first and last candidates: when no wave assumed wrong
+//      outside neighbours, every candidate was tested against its exact neighbours and the
+//      candidates are the hull; otherwise the waves sweep again with the exact neighbours.
+// Returns true on convergence within max_rounds exchanges (*lc / *rc = the thread's carries:
+// last candidate before k0, first candidate after its ranks or the end point d), false when the
+// rounds or the sweeps run out (the caller merges hulls instead).  sv[0..E] are this thread's S
+// values; S is the LDS copy (layout SI); xs holds 2*NT/64 entries.  All threads must call.
 template <int NT, int E, typename SI>
 __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, int max_rounds, uint32_t* bm,
-                           Cand* lc, Cand* rc, Cand* shL, Cand* shR, int* shF) {
+                           Cand* lc, Cand* rc, WaveBound* xs) {
   constexpr int NW = NT / kWave;
+  constexpr int kSweepMax = 32;
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
   const int k0 = threadIdx.x * E;
+  const int wk0 = wv * kWave * E;
   const Cand dflt{d, S[SI::at(d)]};
   uint32_t valid = 0;
 #pragma unroll
   for (int i = 0; i < E; ++i) valid |= (k0 + i < d ? 1u : 0u) << i;
-  // round 1: adjacent neighbours
+  // 1. adjacent neighbours
   uint32_t rem = 0;
   {
     double dl = sv[0] - S[SI::at(max(k0 - 1, 0))];
@@ -448,51 +467,108 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
     }
   }
   uint32_t b = valid & ~rem;
-  uint32_t dirty = rem ? ica_neighbours(b, rem) : 0u;
+  uint32_t todo = rem ? ica_neighbours(b, rem) : 0u;
   int lprev = k0 - 1;  // neighbours the first round used outside the thread
   int rprev = min(k0 + E, d);
-  for (int round = 1;; ++round) {
-    Cand mineL{-1, 0.0}, mineR{-1, 0.0};
-    if (b) {
-      const int hi = 31 - __clz(b);
-      const int lo = __ffs(b) - 1;
-      mineL.pos = k0 + hi;
-      mineL.s = S[SI::at(k0 + hi)];
-      mineR.pos = k0 + lo;
-      mineR.s = S[SI::at(k0 + lo)];
+  // outside neighbours of the wave: the adjacent ranks to begin with (any point is a valid
+  // test point for removals)
+  Cand wl{-1, 0.0}, wr = dflt;
+  if (wk0 > 0 && wk0 <= d) wl = Cand{wk0 - 1, S[SI::at(wk0 - 1)]};
+  if (wk0 + kWave * E < d) wr = Cand{wk0 + kWave * E, S[SI::at(wk0 + kWave * E)]};
+  Cand l{-1, 0.0}, r = dflt, mineL{-1, 0.0}, mineR{-1, 0.0};
+  for (int round = 0; round < max_rounds; ++round) {
+    // 2. sweeps inside the wave
+    int overflow = 0;
+    for (int sweep = 0;; ++sweep) {
+      mineL = Cand{-1, 0.0};
+      mineR = Cand{-1, 0.0};
+      if (b) {
+        const int hi = 31 - __clz(b);
+        const int lo = __ffs(b) - 1;
+        mineL = Cand{k0 + hi, S[SI::at(k0 + hi)]};
+        mineR = Cand{k0 + lo, S[SI::at(k0 + lo)]};
+      }
+      const uint64_t has = __ballot(mineL.pos >= 0);
+      const uint64_t lower = has & lanemask_lt();
+      const uint64_t upper = lane == kWave - 1 ? 0ull : has & (~0ull << (lane + 1));
+      const int src_l = lower ? 63 - __clzll((long long)lower) : lane;
+      const int src_r = upper ? __ffsll((unsigned long long)upper) - 1 : lane;
+      l.pos = __shfl(mineL.pos, src_l, kWave);
+      l.s = __shfl(mineL.s, src_l, kWave);
+      r.pos = __shfl(mineR.pos, src_r, kWave);
+      r.s = __shfl(mineR.s, src_r, kWave);
+      if (!lower) l = wl;
+      if (!upper) r = wr;
+      if (b) {
+        if (l.pos != lprev) todo |= b & (0u - b);
+        if (r.pos != rprev) todo |= 1u << (31 - __clz(b));
+      }
+      lprev = l.pos;
+      rprev = r.pos;
+      todo &= b;
+      rem = 0;
+      while (todo) {
+        const int i = __ffs(todo) - 1;
+        todo &= todo - 1u;
+        const uint32_t below_i = b & ((1u << i) - 1u);
+        const uint32_t above_i = b & ~((2u << i) - 1u);
+        const int pp = below_i ? k0 + 31 - __clz(below_i) : l.pos;
+        const int np = above_i ? k0 + __ffs(above_i) - 1 : r.pos;
+        const double sp = below_i ? S[SI::at(pp)] : l.s;
+        const double sn = above_i ? S[SI::at(np)] : r.s;
+        if (pp >= 0 && !below(pp, sp, k0 + i, S[SI::at(k0 + i)], np, sn)) {
+          b &= ~(1u << i);
+          rem |= 1u << i;
+          todo |= ica_neighbours(b, 1u << i);  // cascade inside the thread at once
+        }
+      }
+      if (__ballot(rem != 0) == 0ull) break;  // nothing moved in this wave
+      if (sweep >= kSweepMax) {
+        overflow = 1;
+        break;
+      }
     }
-    // carries of the current candidates, and whether the last round removed anything
-    const int slot = (round & 1) * NW;
-    Cand l, r;
-    const bool any = carry_exchange<NT>(mineL, mineR, rem != 0, dflt, shL + slot, shR + slot, shF + slot, &l, &r);
-    if (!any) {
+    // 3. exchange of wave boundaries (mineL / mineR are those of the final candidates)
+    WaveBound* x = xs + (round & 1) * NW;
+    const uint64_t has = __ballot(mineL.pos >= 0);
+    if (has) {
+      if (lane == 63 - __clzll((long long)has)) x[wv].last = mineL;
+      if (lane == __ffsll((unsigned long long)has) - 1) x[wv].first = mineR;
+    } else if (lane == 0) {
+      x[wv].last = Cand{-1, 0.0};
+      x[wv].first = Cand{-1, 0.0};
+    }
+    if (lane == 0) {
+      x[wv].lassume = wl.pos;
+      x[wv].rassume = wr.pos;
+      x[wv].overflow = overflow;
+    }
+    __syncthreads();
+    // lane j < NW takes wave j: its exact outside neighbours are the last candidate of the
+    // nearest lower wave holding any and the first of the nearest higher one (else d)
+    const bool in = lane < NW;
+    const WaveBound e = x[in ? lane : 0];
+    const bool holds = in && e.last.pos >= 0;
+    const uint64_t hm = __ballot(holds);
+    const uint64_t lw = hm & lanemask_lt();
+    const uint64_t uw = lane == kWave - 1 ? 0ull : hm & (~0ull << (lane + 1));
+    const int sl = lw ? 63 - __clzll((long long)lw) : lane;
+    const int sr = uw ? __ffsll((unsigned long long)uw) - 1 : lane;
+    Cand exl{__shfl(e.last.pos, sl, kWave), __shfl(e.last.s, sl, kWave)};
+    Cand exr{__shfl(e.first.pos, sr, kWave), __shfl(e.first.s, sr, kWave)};
+    if (!lw) exl = Cand{-1, 0.0};
+    if (!uw) exr = dflt;
+    const bool wrong = __ballot(holds && (e.lassume != exl.pos || e.rassume != exr.pos)) != 0ull;
+    const bool ovf = __ballot(in && e.overflow != 0) != 0ull;
+    wl = Cand{__shfl(exl.pos, wv, kWave), __shfl(exl.s, wv, kWave)};
+    wr = Cand{__shfl(exr.pos, wv, kWave), __shfl(exr.s, wv, kWave)};
+    if (ovf) break;
+    if (!wrong) {
       *bm = b;
       *lc = l;
       *rc = r;
       return true;
     }
-    if (round >= max_rounds) break;
-    if (b) {
-      if (l.pos != lprev) dirty |= b & (0u - b);
-      if (r.pos != rprev) dirty |= 1u << (31 - __clz(b));
-    }
-    lprev = l.pos;
-    rprev = r.pos;
-    uint32_t todo = dirty & b;
-    rem = 0;
-    while (todo) {
-      const int i = __ffs(todo) - 1;
-      todo &= todo - 1u;
-      const uint32_t below_i = b & ((1u << i) - 1u);
-      const uint32_t above_i = b & ~((2u << i) - 1u);
-      const int pp = below_i ? k0 + 31 - __clz(below_i) : l.pos;
-      const int np = above_i ? k0 + __ffs(above_i) - 1 : r.pos;
-      const double sp = below_i ? S[SI::at(pp)] : l.s;
-      const double sn = above_i ? S[SI::at(np)] : r.s;
-      if (pp >= 0 && !below(pp, sp, k0 + i, S[SI::at(k0 + i)], np, sn)) rem |= 1u << i;
-    }
-    b &= ~rem;
-    dirty = rem ? ica_neighbours(b, rem) : 0u;
   }
   *bm = b;
   return false;

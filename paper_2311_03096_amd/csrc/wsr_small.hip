@@ -59,8 +59,7 @@ struct FwdSmem {
   double dred[NW + 1];
   int ired[NW + 1];
   uint32_t ured[2 * NW];
-  Cand shL[2 * NW], shR[2 * NW];  // carry exchange slots, two sets
-  int shF[2 * NW];
+  WaveBound wb[2 * NW];  // collision exchange slots, two sets
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
 
@@ -178,7 +177,35 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
   }
 }
 
-// Bucket-rank sort of the register-held items (any layout) into sm.c.bs.key / sm.idx.
+// Before the sort (and a barrier): per-wave key range in sm.ured, zeroed counters and tie count.
+template <int TMAX, int NT>
+__device__ __forceinline__ void bucket_sort_prologue(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMAX / NT], int d) {
+  constexpr int IPT = TMAX / NT;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / kWave;
+  const int wbase = wv * kWave * IPT;
+  uint32_t kmn = 0xFFFFFFFFu, kmx = 0u;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    if (p < d) {
+      kmn = min(kmn, k[r]);
+      kmx = max(kmx, k[r]);
+    }
+  }
+  kmn = wave_min_u32(kmn);
+  kmx = wave_max_u32(kmx);
+  if (lane == 0) {
+    sm.ured[2 * wv] = kmn;
+    sm.ured[2 * wv + 1] = kmx;
+  }
+  for (int j = tid; j < TMAX + 1; j += NT) sm.c.bs.key[j] = 0u;
+  if (tid == 0) sm.tiecnt = 0;
+}
+
+// Bucket-rank sort of the register-held items (any layout) into sm.c.bs.key / sm.idx; requires
+// bucket_sort_prologue and a barrier before it.
 // Keys are spread over NB = 2*TMAX buckets by a monotone map of their value over [min, max].  One
 // atomic pass counts the keys per bucket (16-bit counters, two to a word) and gives each key a
 // slot inside its bucket; a scan turns counts into bucket starts; keys are placed in bucket
@@ -186,8 +213,8 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
 // smaller: since buckets are monotone in value, every key past the end of the bucket (and the
 // sentinel padding) is larger, so the count scans a fixed number of slots with no bound checks.
 // Equal keys would share a rank; that shows as fewer smaller-key counts than key pairs sharing a
-// bucket, and then all ranks are recomputed in (key, index) order.  The result is the same total order the stable
-// radix sort produces.  Returns false (sorted arrays untouched) when some bucket holds more than
+// bucket, and then all ranks are recomputed in (key, index) order.  The result is the same total
+// order the stable radix sort produces.  Returns false (sorted arrays untouched) when some bucket holds more than
 // kBucketMax keys, so that skewed or tie-heavy segments keep a bounded cost by taking the radix
 // sort instead.
 template <int TMAX, int NT>
@@ -206,26 +233,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   uint32_t* tkey = sm.c.bs.tkey;
   uint16_t* tidx = sm.d.tidx;
 
-  uint32_t kmn = 0xFFFFFFFFu, kmx = 0u;
-#pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    const int p = wbase + r * kWave + lane;
-    if (p < d) {
-      kmn = min(kmn, k[r]);
-      kmx = max(kmx, k[r]);
-    }
-  }
-  kmn = wave_min_u32(kmn);
-  kmx = wave_max_u32(kmx);
-  if (lane == 0) {
-    sm.ured[2 * wv] = kmn;
-    sm.ured[2 * wv + 1] = kmx;
-  }
-  for (int j = tid; j < TMAX + 1; j += NT) cnt2[j] = 0u;
-  if (tid == 0) sm.tiecnt = 0;
-  __syncthreads();
-  kmn = sm.ured[0];
-  kmx = sm.ured[1];
+  uint32_t kmn = sm.ured[0];
+  uint32_t kmx = sm.ured[1];
   for (int w = 1; w < NW; ++w) {
     kmn = min(kmn, sm.ured[2 * w]);
     kmx = max(kmx, sm.ured[2 * w + 1]);
@@ -277,7 +286,8 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   }
   cmax = (int)wave_max_u32((uint32_t)cmax);
   long long tot2;
-  const long long run2 = block_excl_scan<NT, long long>((long long)sum | ((long long)pairs << 32), sm.lred, &tot2);
+  const long long run2 =
+      block_excl_scan<NT, long long, false>((long long)sum | ((long long)pairs << 32), sm.lred, &tot2);
   int run = (int)(run2 & 0xFFFFFFFFll);
   const int total = (int)(tot2 & 0xFFFFFFFFll);
   const int pairs_total = (int)(tot2 >> 32);
@@ -429,6 +439,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     k[r] = p < d ? float_to_key(f[r]) : 0xFFFFFFFFu;
     ix[r] = (uint16_t)p;
   }
+  bucket_sort_prologue<TMAX, NT>(sm, k, d);  // shares the barrier below
   const bool nonfinite = __syncthreads_or(bad) != 0;
   if (nonfinite || d == 1 || !(lam > 0.0f)) {
     // identity (or NaN) segment: every weight its own cluster, perm = identity
@@ -464,7 +475,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     xs[i] = k0 + i < d ? (double)key_to_float(kv[i]) - c : 0.0;
     lsum += xs[i];
   }
-  double Xk = block_excl_scan<NT, double>(lsum, sm.dred, (double*)nullptr);
+  double Xk = block_excl_scan<NT, double, false>(lsum, sm.dred, (double*)nullptr);
   double sv[E + 1];
 #pragma unroll
   for (int i = 0; i <= E; ++i) {
@@ -483,7 +494,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   uint32_t bm;
   Cand lc, rc;
   bool staged = true;
-  if (ica_rounds<NT, E, SL>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.shL, sm.shR, sm.shF)) {
+  if (ica_rounds<NT, E, SL>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.wb)) {
     if (bm) {
       const int b0 = k0 + off;
       const uint64_t wide = (uint64_t)bm << (b0 & 31);
@@ -565,7 +576,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
     bm |= (kk < d ? st : 0u) << i;
   }
   double total;
-  double G = block_excl_scan<NT, double>(lsum, sm.dred, &total);
+  double G = block_excl_scan<NT, double, false>(lsum, sm.dred, &total);
   double sv[E + 1];
   Cand mineL{-1, 0.0}, mineR{-1, 0.0};
 #pragma unroll
