@@ -434,7 +434,8 @@ struct WaveBound {
 //      y_{k-1} >= y_k), in registers;
 //   2. sweeps inside each wave, without barriers, with the neighbours outside the wave taken as
 //      last known; a removal re-tests the thread's neighbouring candidates at once, a changed
-//      carry re-tests the thread's first / last candidate, until a sweep removes nothing;
+//      carry re-tests the thread's first / last candidate, until a sweep removes no thread's
+//      first or last candidate (then no carry changes);
 //   3. one block exchange of the waves' first and last candidates: when no wave assumed wrong
 //      outside neighbours, every candidate was tested against its exact neighbours and the
 //      candidates are the hull; otherwise the waves sweep again with the exact neighbours.
@@ -507,6 +508,7 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
       rprev = r.pos;
       todo &= b;
       rem = 0;
+      const uint32_t edges = b ? ((b & (0u - b)) | (1u << (31 - __clz(b)))) : 0u;
       while (todo) {
         const int i = __ffs(todo) - 1;
         todo &= todo - 1u;
@@ -522,7 +524,8 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
           todo |= ica_neighbours(b, 1u << i);  // cascade inside the thread at once
         }
       }
-      if (__ballot(rem != 0) == 0ull) break;  // nothing moved in this wave
+      // no thread lost its first or last candidate: no carry changed, nothing left to test
+      if (__ballot((rem & edges) != 0) == 0ull) break;
       if (sweep >= kSweepMax) {
         overflow = 1;
         break;

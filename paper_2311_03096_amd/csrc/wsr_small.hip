@@ -308,7 +308,7 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   for (int w = 1; w < NW; ++w) cmax = max(cmax, (int)sm.ured[w]);
   if (cmax > kBucketMax) return false;  // uniform
   int lo[IPT];
-  int jmax = 0;
+  int jmax = 0;  // longest bucket among the thread's items
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {  // loads unconditional (bk = 0 for padding) so they overlap
     const int p = wbase + r * kWave + lane;
@@ -320,20 +320,28 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
     const int p = wbase + r * kWave + lane;
-    if (p < d) {
-      tkey[lo[r] + loc[r]] = k[r];
-      tidx[lo[r] + loc[r]] = ix[r];
-    }
+    if (p < d) tkey[lo[r] + loc[r]] = k[r];
   }
   __syncthreads();
-  // rank = bucket start + smaller keys of the bucket; the items advance together, so one LDS
-  // round trip serves all items of a step
+  // rank = bucket start + smaller keys of the bucket; the items advance together, two slots a
+  // step (one paired read per item, all issued before the compares), and the sentinel padding
+  // covers the overrun of the last step
   int rank[IPT];
+  const uint32_t* kp[IPT];
 #pragma unroll
-  for (int r = 0; r < IPT; ++r) rank[r] = lo[r];
-  for (int j = 0; j < jmax; ++j) {
+  for (int r = 0; r < IPT; ++r) {
+    rank[r] = lo[r];
+    kp[r] = tkey + lo[r];
+  }
+  for (int j = 0; j < jmax; j += 2) {
+    uint32_t q0[IPT], q1[IPT];  // every item's pair in flight before any compare
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) rank[r] += tkey[lo[r] + j] < k[r] ? 1 : 0;
+    for (int r = 0; r < IPT; ++r) {
+      q0[r] = kp[r][j];
+      q1[r] = kp[r][j + 1];
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) rank[r] += (q0[r] < k[r] ? 1 : 0) + (q1[r] < k[r] ? 1 : 0);
   }
   int below = 0;
 #pragma unroll
@@ -351,6 +359,12 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   if (sm.tiecnt != pairs_total) {
     // equal keys (they shared ranks above): order each bucket by (key, index) instead; an equal
     // key is always in the same bucket, and the padding never equals a finite key
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const int p = wbase + r * kWave + lane;
+      if (p < d) tidx[lo[r] + loc[r]] = ix[r];
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r) rank[r] = lo[r];
     for (int j = 0; j < jmax; ++j) {
