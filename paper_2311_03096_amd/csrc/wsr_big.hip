@@ -28,35 +28,49 @@ namespace wsr {
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc, const uint32_t* ksrc,
                                                              int64_t n, int shift, uint32_t* hist,
                                                              int ntiles, uint32_t* flags) {
-  __shared__ uint32_t h[256];
+  constexpr int IPT = kRadixTile / kRadixThreads;
+  constexpr int NW = kRadixThreads / kWave;
+  __shared__ uint32_t h[NW][256];  // one sub-histogram per wave (less contention on hot digits)
   const int tid = threadIdx.x;
-  for (int j = tid; j < 256; j += kRadixThreads) h[j] = 0u;
-  __syncthreads();
+  const int lane = lane_id();
+  const int wv = tid / kWave;
+  for (int j = lane; j < 256; j += kWave) h[wv][j] = 0u;
   const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+  const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
+  // all of the thread's keys in flight at once (uniform tile base, 32-bit offsets)
+  uint32_t key[IPT];
   int bad = 0;
-#pragma unroll 4
-  for (int r = 0; r < kRadixTile / kRadixThreads; ++r) {
-    const int64_t p = base + r * kRadixThreads + tid;
-    if (p < n) {
-      uint32_t key;
-      if (wsrc) {
-        const float f = wsrc[p];
-        bad |= !isfinite(f);
-        key = float_to_key(f);
-      } else {
-        key = ksrc[p];
-      }
-      const uint32_t dg = (key >> shift) & 255u;
-      // a wave whose lanes all hold the same digit (long runs in sorted or clustered data)
-      // adds once instead of 64 serialised atomics on one LDS address
-      // (the active mask is taken before the leader branch, where only one lane is active)
-      const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
-      const unsigned long long act = __ballot(1);
-      if (__ballot(dg == d0) == act) {
-        if (lane_id() == __ffsll(act) - 1) atomicAdd(&h[d0], (uint32_t)__popcll(act));
-      } else {
-        atomicAdd(&h[dg], 1u);
-      }
+  if (wsrc) {
+    const float* wt = wsrc + base;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+      const float f = p < nt ? wt[p] : 0.0f;
+      bad |= !isfinite(f);
+      key[r] = float_to_key(f);
+    }
+  } else {
+    const uint32_t* kt = ksrc + base;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+      key[r] = p < nt ? kt[p] : 0u;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+    const uint32_t dg = (key[r] >> shift) & 255u;
+    const bool in = p < nt;
+    // a wave whose lanes all hold the same digit (long runs in sorted or clustered data) adds
+    // once instead of 64 serialised atomics on one LDS address (the active mask is taken before
+    // the leader branch, where only one lane is active)
+    const unsigned long long act = __ballot(in);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+    if (act == ~0ull && __ballot(dg == d0) == act) {
+      if (lane == 0) atomicAdd(&h[wv][d0], (uint32_t)kWave);
+    } else if (in) {
+      atomicAdd(&h[wv][dg], 1u);
     }
   }
   if (wsrc) {
@@ -64,7 +78,12 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
   } else {
     __syncthreads();
   }
-  for (int j = tid; j < 256; j += kRadixThreads) hist[(int64_t)j * ntiles + blockIdx.x] = h[j];
+  for (int j = tid; j < 256; j += kRadixThreads) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) c += h[w][j];
+    hist[(int64_t)j * ntiles + blockIdx.x] = c;
+  }
 }
 
 // Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
@@ -93,10 +112,40 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntile
   if (threadIdx.x == 0) totals[blockIdx.x] = (uint32_t)total;
 }
 
-// Stable scatter of one tile by one digit.  Items are ranked in wave-striped order
-// (p = wave*64*IPT + r*64 + lane), which is the tile's current order, so equal digits keep
+// Items of one tile in wave-striped order (p = wave*64*IPT + r*64 + lane); keys past the end
+// of the segment are 0xFFFFFFFF (they sort last and are never written).
+template <int IPT>
+__device__ __forceinline__ void radix_load_tile(const float* wsrc, const uint32_t* ksrc, const int32_t* vsrc,
+                                                int64_t n, int tile, uint32_t (&k)[IPT], int32_t (&v)[IPT]) {
+  const uint32_t p0 = (threadIdx.x / kWave) * kWave * IPT + lane_id();
+  const int64_t base = (int64_t)tile * kRadixTile;
+  const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
+  // tile base pointers are uniform; per-item offsets are 32-bit
+  if (wsrc) {
+    const float* wt = wsrc + base;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t p = p0 + r * kWave;
+      k[r] = p < nt ? float_to_key(wt[p]) : 0xFFFFFFFFu;
+      v[r] = (int32_t)(base + p);
+    }
+  } else {
+    const uint32_t* kt = ksrc + base;
+    const int32_t* vt = vsrc + base;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t p = p0 + r * kWave;
+      k[r] = p < nt ? kt[p] : 0xFFFFFFFFu;
+      v[r] = p < nt ? vt[p] : 0;
+    }
+  }
+}
+
+// Stable scatter by one digit, persistent: workgroup b takes tiles b, b + G, b + 2G, ... (G =
+// gridDim.x) and loads the next tile's items while it ranks and writes the current one.  Items
+// are ranked in wave-striped order, which is the tile's current order, so equal digits keep
 // their relative order.  Writes go out digit-run by digit-run.
-__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const float* wsrc, const uint32_t* ksrc,
+__global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float* wsrc, const uint32_t* ksrc,
                                                                 const int32_t* vsrc, uint32_t* kdst,
                                                                 int32_t* vdst, int64_t n, int shift,
                                                                 const uint32_t* hist, const uint32_t* totals,
@@ -112,78 +161,76 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const float* ws
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  const int nt = (int)min((int64_t)kRadixTile, n - base);
   const int wbase = wv * kWave * IPT;
-  const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
-
-  // global offsets of this tile's digit runs, fetched first so their latency overlaps the ranking
-  const uint32_t tot_digit = totals[tid];
-  const uint32_t tile_pre = hist[(int64_t)tid * ntiles + blockIdx.x];
+  // digit bases over the whole segment (the same for every tile)
+  int gt;
+  const int rowbase = block_excl_scan<kRadixThreads, int>((int)totals[tid], ish, &gt);
   uint32_t k[IPT];
   int32_t v[IPT];
+  int tile = blockIdx.x;
+  if (tile < ntiles) radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, tile, k, v);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t base = (int64_t)tile * kRadixTile;
+    const int nt = (int)min((int64_t)kRadixTile, n - base);
+    const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
+    const uint32_t tile_pre = hist[(int64_t)tid * ntiles + tile];
+    // the next tile's items are in flight while this one is ranked and written
+    uint32_t kn[IPT];
+    int32_t vn[IPT];
+    const int next = tile + (int)gridDim.x;
+    if (next < ntiles) radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, next, kn, vn);
+    for (int j = lane; j < 256; j += kWave) wcnt[wv][j] = 0u;
+    uint16_t rk[IPT];
 #pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    const int p = wbase + r * kWave + lane;
-    k[r] = 0xFFFFFFFFu;
-    v[r] = 0;
-    if (r < nr && p < nt) {
-      if (wsrc) {
-        k[r] = float_to_key(wsrc[base + p]);
-        v[r] = (int32_t)(base + p);
-      } else {
-        k[r] = ksrc[base + p];
-        v[r] = vsrc[base + p];
+    for (int r = 0; r < IPT; ++r) {
+      if (r < nr) {
+        const uint32_t dg = (k[r] >> shift) & 255u;
+        const uint64_t peers = match_digit8(dg);
+        const uint32_t b = wcnt[wv][dg];
+        const int nbelow = __popcll(peers & lanemask_lt());
+        if (nbelow == 0) wcnt[wv][dg] = b + (uint32_t)__popcll(peers);
+        rk[r] = (uint16_t)(b + nbelow);
       }
     }
-  }
-  for (int j = lane; j < 256; j += kWave) wcnt[wv][j] = 0u;
-  uint16_t rk[IPT];
-#pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    if (r < nr) {
-      const uint32_t dg = (k[r] >> shift) & 255u;
-      const uint64_t peers = match_digit8(dg);
-      const uint32_t b = wcnt[wv][dg];
-      const int nbelow = __popcll(peers & lanemask_lt());
-      if (nbelow == 0) wcnt[wv][dg] = b + (uint32_t)__popcll(peers);
-      rk[r] = (uint16_t)(b + nbelow);
+    __syncthreads();
+    // digit offsets inside the tile (thread tid owns digit tid; kRadixThreads == 256)
+    uint32_t run = 0;
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t c = wcnt[w][tid];
+      wcnt[w][tid] = run;
+      run += c;
     }
-  }
-  __syncthreads();
-  // digit offsets inside the tile (thread tid owns digit tid; kRadixThreads == 256)
-  uint32_t run = 0;
-  for (int w = 0; w < NW; ++w) {
-    const uint32_t c = wcnt[w][tid];
-    wcnt[w][tid] = run;
-    run += c;
-  }
-  int tot;
-  const int dstart = block_excl_scan<kRadixThreads, int>((int)run, ish, &tot);
-  for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
-  tstart[tid] = (uint32_t)dstart;
-  // global base of this digit = sum of all smaller digits' totals + this digit's tiles before us
-  int gt;
-  const int rowbase = block_excl_scan<kRadixThreads, int>((int)tot_digit, ish, &gt);
-  gofs[tid] = (uint32_t)rowbase + tile_pre;
-  __syncthreads();
+    int tot;
+    const int dstart = block_excl_scan<kRadixThreads, int>((int)run, ish, &tot);
+    for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
+    tstart[tid] = (uint32_t)dstart;
+    // global base of this digit = all smaller digits + this digit in the tiles before this one
+    gofs[tid] = (uint32_t)rowbase + tile_pre;
+    __syncthreads();
 #pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    if (r < nr) {
-      const uint32_t dg = (k[r] >> shift) & 255u;
-      const int np = (int)wcnt[wv][dg] + rk[r];
-      skey[np] = k[r];
-      sval[np] = v[r];
+    for (int r = 0; r < IPT; ++r) {
+      if (r < nr) {
+        const uint32_t dg = (k[r] >> shift) & 255u;
+        const int np = (int)wcnt[wv][dg] + rk[r];
+        skey[np] = k[r];
+        sval[np] = v[r];
+      }
     }
-  }
-  __syncthreads();
-  for (int s = tid; s < nt; s += kRadixThreads) {
-    const uint32_t key = skey[s];
-    const uint32_t dg = (key >> shift) & 255u;
-    const int64_t dst = (int64_t)gofs[dg] + (s - (int)tstart[dg]);
-    if (dst >= 0 && dst < n) {  // always true for consistent histograms; guards the scatter
-      kdst[dst] = key;
-      vdst[dst] = sval[s];
+    __syncthreads();
+    for (int s = tid; s < nt; s += kRadixThreads) {
+      const uint32_t key = skey[s];
+      const uint32_t dg = (key >> shift) & 255u;
+      const int64_t dst = (int64_t)gofs[dg] + (s - (int)tstart[dg]);
+      if (dst >= 0 && dst < n) {  // always true for consistent histograms; guards the scatter
+        kdst[dst] = key;
+        vdst[dst] = sval[s];
+      }
+    }
+    __syncthreads();  // LDS is reused by the next tile
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      k[r] = kn[r];
+      v[r] = vn[r];
     }
   }
 }
