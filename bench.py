@@ -121,6 +121,32 @@ def time_steps(fn, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def copy_bandwidth(nbytes=1 << 28, reps=10):
+    """Device-copy bandwidth (read + write bytes per second) of one plain elementwise kernel over
+    nbytes, the practical ceiling next to the 8 TB/s HBM peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms, _ = time_steps(lambda: torch.mul(src, 1.0, out=dst), reps, 2)
+    del src, dst
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def step_fractions(n_el, ms, copy_gbs, extra_bpe=None):
+    """Whole-step HBM fractions: algorithmic bytes (forward with saved state 12.125 B/el +
+    backward 12.125 B/el) over the step time, against the HBM peak and the measured copy rate;
+    extra_bpe adds a model with more bytes per element (the out-of-core sort round trip)."""
+    res = {}
+    models = {"algorithmic_24.25B": 24.25}
+    if extra_bpe:
+        models["with_sort_roundtrip_%gB" % (24.25 + extra_bpe)] = 24.25 + extra_bpe
+    for k, bpe in models.items():
+        gbs = bpe * n_el / (ms * 1e-3) / 1e9
+        res[k] = dict(GBps=round(gbs, 1), frac_peak=round(gbs / HBM_PEAK_GBS, 4),
+                      frac_copy=round(gbs / copy_gbs, 4))
+    return res
+
+
 def trace_kernels(fn, reps):
     import torch
     import paper_2311_03096_amd as wsr
@@ -205,10 +231,13 @@ def batched_vs_per_row(steps, warmup, per_row=True):
     ms_rows = time_steps(p, max(2, steps // 4), 1)[0] if per_row else float("nan")
     tr = trace_kernels(b, 3)
     roof = roofline({k: v for k, v in tr.items() if k.startswith("prox_fwd")}, n, 3, "mlp_rows")
+    copy_gbs = copy_bandwidth()
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4) if roof.get("achieved") else None
     return dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
                 elements=n, ms_per_step_graph=round(ms_graph, 4), ms_per_step_batched=round(ms_batched, 4),
                 ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
                 speedup_graph_vs_per_row=round(ms_rows / ms_graph, 2), fwd_kernel_roofline=roof,
+                copy_GBps=round(copy_gbs, 1), step_fractions_graph=step_fractions(n, ms_graph, copy_gbs),
                 kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()})
 
 
@@ -245,8 +274,11 @@ def main():
     tr = trace_kernels(step, 3)
     roof = roofline(tr, d, 3, {"chain": "chain_d2p24", "typical": "typical_d2p24"}[args.workload])
     log("ms/step", ms, "trace", tr)
+    copy_gbs = copy_bandwidth()
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4) if roof.get("achieved") else None
     extra = dict(kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
-                 wall_ms_per_step=round(wall, 4))
+                 wall_ms_per_step=round(wall, 4), copy_GBps=round(copy_gbs, 1),
+                 step_fractions=step_fractions(d, ms, copy_gbs, extra_bpe=16.0))
     if not args.no_extra:
         typ = workloads.plain(d, 0.1, seed=1)
         st = Step(typ)

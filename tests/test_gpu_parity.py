@@ -103,6 +103,20 @@ def test_chain_below_threshold():
     _check(workloads.chain(d, lam_min * 0.99, shuffle=True))
 
 
+@pytest.mark.parametrize("d", [100, 2048, 4096, 6000, 8192])
+def test_chain_short_segments(d):
+    """The collision chain inside one workgroup: the merges cascade from one end over thousands
+    of ImminentCollisions rounds (one final cluster above the threshold, hundreds to thousands
+    of clusters below it), so the short-segment kernel takes its hull-merge fallback."""
+    lam_min = (4 * d - 5) / (6.0 * (d - 1))
+    case = workloads.chain(d, 0.7)
+    g, _, _ = _check(case)
+    assert g["start"].sum() == 1
+    _check(workloads.chain(d, lam_min * 0.9))
+    _check(workloads.chain(d, lam_min * 0.9, shuffle=True, seed=d))
+    _check(workloads.chain(d, lam_min * 0.5), batched=True)
+
+
 def test_typical_d2p24():
     _check(workloads.plain(1 << 24, 0.1, seed=1))
 
