@@ -593,6 +593,15 @@ __device__ __forceinline__ void load_u16_block(const uint16_t* a, int k0, uint16
   }
 }
 
+// num / n for a rank count 1 <= n <= 2^26: the hardware FP64 reciprocal refined by one
+// Newton-Raphson step (relative error ~1e-16, far below the FP32 rounding of the results).
+__device__ __forceinline__ double div_count(double num, int n) {
+  const double dn = (double)n;
+  double r = __builtin_amdgcn_rcp(dn);
+  r = r * __builtin_fma(-dn, r, 2.0);
+  return num * r;
+}
+
 // The E entries a[k0 .. k0+E) of a flat u32 array (k0 a multiple of 4), read as 16-byte words.
 template <int E>
 __device__ __forceinline__ void load_u32_block(const uint32_t* a, int k0, uint32_t (&v)[E]) {
@@ -623,14 +632,14 @@ __device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 
   double sn = rc.s;
 #pragma unroll
   for (int i = E - 1; i >= 0; --i) {
-    val[i] = (float)(offset + (sn - sv[i]) / (double)(np - (k0 + i)));
+    val[i] = (float)(offset + div_count(sn - sv[i], np - (k0 + i)));
     if ((bm >> i) & 1u) {
       np = k0 + i;
       sn = sv[i];
     }
   }
   // (np, sn) is now the first start in the thread's ranks (or rc): it closes the entering cluster
-  float cur = lc.pos >= 0 ? (float)(offset + (sn - lc.s) / (double)(np - lc.pos)) : 0.0f;
+  float cur = lc.pos >= 0 ? (float)(offset + div_count(sn - lc.s, np - lc.pos)) : 0.0f;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     if ((bm >> i) & 1u) cur = val[i];
