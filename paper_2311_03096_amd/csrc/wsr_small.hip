@@ -532,10 +532,23 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     staged = false;
   }
   __syncthreads();
-  if (staged)
-    for (int i = tid; i < d; i += NT) out[start + i] = sm.c.outv[i];
-  if (perm_out)
-    for (int i = tid; i < d; i += NT) perm_out[start + i] = sm.idx[i];
+  // fixed trip count (TMAX / NT) so every LDS read is issued before the stores wait on them
+  float* const og = out + start;
+  if (staged) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = tid + r * NT;
+      if (i < d) og[i] = sm.c.outv[i];
+    }
+  }
+  if (perm_out) {
+    int32_t* const pg = perm_out + start;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = tid + r * NT;
+      if (i < d) pg[i] = sm.idx[i];
+    }
+  }
   if (mask_out) store_mask_words<NT>(mask_out, start, d, sm.lmask);
 }
 
@@ -564,10 +577,26 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   const int off = (int)(start & 31);
   const int nwords = (off + d + 31) >> 5;
   const int64_t g0 = start >> 5;
-  for (int i = tid; i < d; i += NT) {
-    sm.g[i] = gin[start + i];
-    const int p = perm_in[start + i];
-    sm.idx[i] = (uint16_t)min(max(p, 0), d - 1);
+  // every load of the thread in flight before the LDS stores (fixed trip count TMAX / NT)
+  {
+    const float* const gg = gin + start;
+    const int32_t* const pg = perm_in + start;
+    float gv[E];
+    int32_t pv[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = tid + r * NT;
+      gv[r] = i < d ? gg[i] : 0.0f;
+      pv[r] = i < d ? pg[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = tid + r * NT;
+      if (i < d) {
+        sm.g[i] = gv[r];
+        sm.idx[i] = (uint16_t)min(max(pv[r], 0), d - 1);
+      }
+    }
   }
   for (int j = tid; j < nwords; j += NT) sm.lmask[j] = mask_in[g0 + j];
   __syncthreads();
@@ -608,7 +637,12 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   carry_exchange<NT>(mineL, mineR, false, Cand{d, total}, sm.shL, sm.shR, sm.shF, &lc, &rc);
   walk_values<E>(bm, sv, lc, rc, d, 0.0, ixr, sm.g);  // every gather above is done (block scan)
   __syncthreads();
-  for (int i = tid; i < d; i += NT) gout[start + i] = sm.g[i];
+  float* const og = gout + start;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = tid + r * NT;
+    if (i < d) og[i] = sm.g[i];
+  }
 }
 
 // Zero a word array (used for the saved cluster-start mask before OR-ing boundary words).
