@@ -238,8 +238,7 @@ __global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float*
 // ------------------------------------------------------------------------------- tile hulls
 
 struct TileSmem {
-  uint32_t keys[rpad_size(kBigTile)];  // sorted keys of the tile (rank-padded)
-  double S[rpad_size(kBigTile + 1)];   // tile-relative prefix sums (rank-padded)
+  double S[rpad_size(kBigTile + 1)];  // tile-relative prefix sums (rank-padded)
   uint16_t vert[kBigThreads * (kBigE + 1)];
   int cnt[kBigThreads];
   int mres[kBigThreads];
@@ -272,15 +271,28 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
   const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
   const int j0 = tid * kBigE;
-  for (int j = tid; j < np; j += kBigThreads) sm.keys[rpad(j)] = skeys[k0 + j];
-  __syncthreads();
+  // the thread's kBigE consecutive sorted keys, straight from global memory as 16-byte words
+  // (64-byte aligned: tiles and thread blocks are multiples of 16 keys)
+  uint32_t kv[kBigE];
+  const uint32_t* kt = skeys + k0;
+  if (j0 + kBigE <= np) {
+#pragma unroll
+    for (int q = 0; q < kBigE / 4; ++q) {
+      const uint4 w = *reinterpret_cast<const uint4*>(kt + j0 + 4 * q);
+      kv[4 * q] = w.x;
+      kv[4 * q + 1] = w.y;
+      kv[4 * q + 2] = w.z;
+      kv[4 * q + 3] = w.w;
+    }
+  } else {  // last, partial tile
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i) kv[i] = j0 + i < np ? kt[j0 + i] : 0u;
+  }
   double xs[kBigE];
   double lsum = 0.0;
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
-    const int j = j0 + i;
-    const double xv = (double)key_to_float(sm.keys[rpad(min(j, np - 1))]) - c;  // unconditional load
-    xs[i] = j < np ? xv : 0.0;
+    xs[i] = j0 + i < np ? (double)key_to_float(kv[i]) - c : 0.0;
     lsum += xs[i];
   }
   double X = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
@@ -681,9 +693,11 @@ WSR_INSTANTIATE_MERGE(16384)
 // ------------------------------------------------------------------------------- apply
 
 struct ApplySmem {
-  int32_t lp[kBigTile + 2];        // [prev] + own vertices + [next]: ranks
-  double ls[kBigTile + 2];         // S' = S - S_{k0} for points of this tile, global S otherwise
-  float val[rpad_size(kBigTile)];  // value of each rank of the tile (rank-padded)
+  int32_t lp[kBigTile + 2];  // [prev] + own vertices + [next]: ranks
+  union {
+    double ls[kBigTile + 2];         // S' = S - S_{k0} for points of this tile, global S otherwise
+    float val[rpad_size(kBigTile)];  // then: value of each rank of the tile (rank-padded)
+  } u;
   uint32_t lmask[kBigTile / 32 + 2];
   int n;
 };
@@ -710,11 +724,14 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const bool identity = nonfinite || !(lam > 0.0f);
   // the tile's permutation entries, lane-consecutive (stores below are coalesced when the
   // permutation is locally ordered)
-  int64_t pl[R];
+  // segment-relative 32-bit offsets (d <= 2^26) from a uniform base
+  float* const og = out + seg_start;
+  const int32_t* const pt = perm + k0;
+  int32_t pl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    pl[r] = j < np ? min((int64_t)max(perm[k0 + j], 0), d - 1) : 0;
+    pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
   }
   for (int j = tid; j < kBigTile / 32 + 2; j += kBigThreads) sm.lmask[j] = 0u;
   if (identity) {
@@ -723,7 +740,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
     for (int r = 0; r < R; ++r) {
       const int j = tid + r * kBigThreads;
       if (j < np) {
-        out[seg_start + pl[r]] = nonfinite ? __builtin_nanf("") : key_to_float(skeys[k0 + j]);
+        og[pl[r]] = nonfinite ? __builtin_nanf("") : key_to_float(skeys[k0 + j]);
         atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
       }
     }
@@ -738,17 +755,17 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   if (tid == 0) {
     sm.lp[0] = prev_pos[t];
-    sm.ls[0] = prev_pos[t] == k0 ? 0.0 : prev_s[t];  // the tile's first point has S' = 0
+    sm.u.ls[0] = prev_pos[t] == k0 ? 0.0 : prev_s[t];  // the tile's first point has S' = 0
     const int nx = next_pos[t];
     sm.n = 1 + own + (nx >= 0 ? 1 : 0);
     if (nx >= 0) {
       sm.lp[1 + own] = nx;
-      sm.ls[1 + own] = next_s[t];
+      sm.u.ls[1 + own] = next_s[t];
     }
   }
   for (int i = tid; i < own; i += kBigThreads) {
     sm.lp[1 + i] = vpos[vb + lo + i];
-    sm.ls[1 + i] = vS[vb + lo + i];
+    sm.u.ls[1 + i] = vS[vb + lo + i];
   }
   __syncthreads();
   const int n = sm.n;
@@ -760,6 +777,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
     }
   }
   const int j0 = tid * kBigE;
+  float vr[kBigE];  // values of the thread's ranks
   if (j0 < np) {
     const int64_t kk0 = k0 + j0;
     int a = 0, b = n - 1;  // lp[a] <= kk0 < lp[b]
@@ -779,10 +797,10 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
       const bool inb = pb >= k0 && pb <= k0 + np;
       double dS;
       if (ina && inb) {
-        dS = sm.ls[e + 1] - sm.ls[e];
+        dS = sm.u.ls[e + 1] - sm.u.ls[e];
       } else {
-        const double ga = ina ? (pa == k0 ? prev_s[t] : sm.ls[e] + toff) : sm.ls[e];
-        const double gb = inb ? sm.ls[e + 1] + toff : sm.ls[e + 1];
+        const double ga = ina ? (pa == k0 ? prev_s[t] : sm.u.ls[e] + toff) : sm.u.ls[e];
+        const double gb = inb ? sm.u.ls[e + 1] + toff : sm.u.ls[e + 1];
         dS = gb - ga;
       }
       return (float)(c + dS / (double)(pb - pa));
@@ -790,21 +808,29 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
     int cur = a;
     int64_t nxt = sm.lp[cur + 1];
     float v = edge_value(cur);
-    const int j1 = min(j0 + kBigE, np);
-    for (int j = j0; j < j1; ++j) {
-      while (k0 + j >= nxt && cur + 2 < n) {
-        ++cur;
-        nxt = sm.lp[cur + 1];
-        v = edge_value(cur);
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i) {
+      if (j0 + i < np) {
+        while (k0 + j0 + i >= nxt && cur + 2 < n) {
+          ++cur;
+          nxt = sm.lp[cur + 1];
+          v = edge_value(cur);
+        }
       }
-      sm.val[rpad(j)] = v;
+      vr[i] = v;
     }
+  }
+  __syncthreads();  // every read of the vertex list is done: the values take the place of S'
+  if (j0 < np) {
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i)
+      if (j0 + i < np) sm.u.val[rpad(j0 + i)] = vr[i];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    if (j < np) out[seg_start + pl[r]] = sm.val[rpad(j)];
+    if (j < np) og[pl[r]] = sm.u.val[rpad(j)];
   }
   if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
 }
@@ -931,12 +957,11 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const
 }
 
 struct BwdApplySmem {
-  int32_t lp[kBigTile + 2];
+  int32_t lp[kBigTile + 2];  // [previous start] + local cluster starts + [next start]: ranks
   union {
-    float g[kBigTile];       // gathered cotangent (read before the list is built)
-    double lg[kBigTile + 2];
+    double lg[kBigTile + 2];         // global prefix G at those starts
+    float val[rpad_size(kBigTile)];  // then: result of each rank of the tile (rank-padded)
   } u;
-  float val[rpad_size(kBigTile)];  // result of each rank of the tile (rank-padded)
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
   int n;
@@ -955,25 +980,39 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
   const int np = (int)min((int64_t)kBigTile, d - k0);
   constexpr int R = kBigTile / kBigThreads;
   const int j0 = tid * kBigE;
-  int64_t pl[R];
+  // segment-relative 32-bit offsets (d <= 2^26) from a uniform base
+  float* const og = gout + seg_start;
+  const int32_t* const pt = perm + k0;
+  int32_t pl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    pl[r] = j < np ? min((int64_t)max(perm[k0 + j], 0), d - 1) : 0;
-    if (j < np) sm.u.g[j] = gsorted[k0 + j];
+    pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
   }
-  __syncthreads();
+  // the thread's kBigE consecutive gathered cotangents as 16-byte words (64-byte aligned)
   float gk[kBigE];
+  const float* const gt = gsorted + k0;
+  if (j0 + kBigE <= np) {
+#pragma unroll
+    for (int q = 0; q < kBigE / 4; ++q) {
+      const float4 w = *reinterpret_cast<const float4*>(gt + j0 + 4 * q);
+      gk[4 * q] = w.x;
+      gk[4 * q + 1] = w.y;
+      gk[4 * q + 2] = w.z;
+      gk[4 * q + 3] = w.w;
+    }
+  } else {  // last, partial tile
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i) gk[i] = j0 + i < np ? gt[j0 + i] : 0.0f;
+  }
   double lsum = 0.0;
   int lst = 0;
   bool st[kBigE];
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
     const int j = j0 + i;
-    gk[i] = 0.0f;
     st[i] = false;
     if (j < np) {
-      gk[i] = sm.u.g[j];
       lsum += (double)gk[i];
       const int64_t pf = seg_start + k0 + j;
       st[i] = (k0 + j == 0) || ((mask[pf >> 5] >> (pf & 31)) & 1u);
@@ -1004,6 +1043,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
   }
   __syncthreads();
   const int n = sm.n;
+  float vr[kBigE];  // results of the thread's ranks
   if (j0 < np) {
     const int64_t kk0 = k0 + j0;
     int a = 0, b = n - 1;  // lp[a] <= kk0 < lp[b]
@@ -1017,22 +1057,29 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
     int cur = a;
     int64_t nxt = sm.lp[cur + 1];
     float val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
-    const int j1 = min(j0 + kBigE, np);
-    for (int j = j0; j < j1; ++j) {
-      const int64_t kk = k0 + j;
-      while (kk >= nxt && cur + 2 < n) {
-        ++cur;
-        nxt = sm.lp[cur + 1];
-        val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i) {
+      if (j0 + i < np) {
+        while (k0 + j0 + i >= nxt && cur + 2 < n) {
+          ++cur;
+          nxt = sm.lp[cur + 1];
+          val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
+        }
       }
-      sm.val[rpad(j)] = val;
+      vr[i] = val;
     }
+  }
+  __syncthreads();  // every read of the start list is done: the results take the place of G
+  if (j0 < np) {
+#pragma unroll
+    for (int i = 0; i < kBigE; ++i)
+      if (j0 + i < np) sm.u.val[rpad(j0 + i)] = vr[i];
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    if (j < np) gout[seg_start + pl[r]] = sm.val[rpad(j)];
+    if (j < np) og[pl[r]] = sm.u.val[rpad(j)];
   }
 }
 
