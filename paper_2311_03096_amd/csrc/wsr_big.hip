@@ -858,12 +858,28 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int j0 = tid * kBigE;
-  // coalesced perm read and gsorted write; the gather itself follows the permutation
-  for (int j = tid; j < np; j += kBigThreads) {
-    const int64_t pl = min((int64_t)max(perm[k0 + j], 0), d - 1);
-    const float gv = g[seg_start + pl];
-    sm.g[j] = gv;
-    gsorted[k0 + j] = gv;
+  // coalesced perm read and gsorted write; the gather itself follows the permutation.  All the
+  // thread's perm loads, then all its gathers, are in flight at once (fixed trip count).
+  constexpr int R = kBigTile / kBigThreads;
+  const int32_t* const pt = perm + k0;
+  const float* const gs = g + seg_start;
+  float* const go = gsorted + k0;
+  int32_t pl[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
+  }
+  float gv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) gv[r] = gs[pl[r]];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    if (j < np) {
+      sm.g[j] = gv[r];
+      go[j] = gv[r];
+    }
   }
   __syncthreads();
   float gk[kBigE];
