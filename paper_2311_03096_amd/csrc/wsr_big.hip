@@ -409,13 +409,26 @@ __device__ __forceinline__ void node_vertex(const MergeCtx& C, int t0, int t1, i
 struct WaveNode {
   const MergeCtx* C;
   int t0, t1;
-  __device__ __forceinline__ void fetch(int m, int* p, double* s) const {
-    int tile, idx;
-    node_vertex(*C, t0, t1, m, &tile, &idx);
+  __device__ __forceinline__ void load(int tile, int idx, int* p, double* s) const {
     const int g = C->gbase + tile;
     const int64_t at = (int64_t)g * (kBigTile + 1) + idx;
     *p = C->vpos[at];
     *s = C->vS[at] + C->tileoff[g];
+  }
+  __device__ __forceinline__ void fetch(int m, int* p, double* s) const {
+    int tile, idx;
+    node_vertex(*C, t0, t1, m, &tile, &idx);
+    load(tile, idx, p, s);
+  }
+  // vertices m and m+1 with one search when m+1 is the next vertex of the same tile
+  __device__ __forceinline__ void fetch2(int m, int* p0, double* s0, int* p1, double* s1) const {
+    int tile, idx;
+    node_vertex(*C, t0, t1, m, &tile, &idx);
+    const bool same = m > 0 && idx + 1 < (int)C->lo16[tile] + (C->pre[tile + 1] - C->pre[tile]);
+    int tile1 = tile, idx1 = idx + 1;
+    if (!same) node_vertex(*C, t0, t1, m + 1, &tile1, &idx1);
+    load(tile, idx, p0, s0);
+    load(tile1, idx1, p1, s1);
   }
 };
 
@@ -428,8 +441,7 @@ __device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs) {
     if (j >= q) return true;
     int pj, pj1;
     double sj, sj1;
-    R.fetch(j, &pj, &sj);
-    R.fetch(j + 1, &pj1, &sj1);
+    R.fetch2(j, &pj, &sj, &pj1, &sj1);
     return below(qa, qs, pj, sj, pj1, sj1);
   };
   const int j = lane < 30 ? min(1 << lane, q) : q;
