@@ -193,7 +193,7 @@ void zero_words(uint32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
 }
 
-// Workgroups of the persistent radix scatter: as many as are resident at once (4 per CU).
+// Workgroups of the persistent radix scatter: as many as are resident at once (2 per CU).
 int scatter_grid() {
   static int g = 0;
   if (g == 0) {
@@ -201,7 +201,7 @@ int scatter_grid() {
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
       cus = 256;
-    g = 4 * cus;
+    g = 2 * cus;
   }
   return g;
 }
@@ -228,7 +228,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
     { WSR_TRACE("radix_rowscan", s);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, b.hist, nrt, b.totals); }
     { WSR_TRACE("radix_scatter", s);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(std::min(nrt, scatter_grid())), dim3(kRadixThreads), 0, s,
+    hipLaunchKernelGGL(k_radix_scatter, dim3(std::min(nrt, scatter_grid())), dim3(kScatterThreads), 0, s,
                        pass == 0 ? wseg : nullptr,
                        ksrc, vsrc, kdst, vdst, d, shift, b.hist, b.totals, nrt); }
   }

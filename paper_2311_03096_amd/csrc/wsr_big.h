@@ -5,8 +5,10 @@
 
 namespace wsr {
 
-constexpr int kRadixThreads = 256;  // one digit per thread in the scatter's digit scan
-constexpr int kRadixTile = 4096;    // keys per radix workgroup
+constexpr int kRadixThreads = 256;   // histogram workgroup; the scatter's digit scan uses
+                                     // one thread per digit
+constexpr int kRadixTile = 8192;     // keys per radix tile (digit runs average 32 keys)
+constexpr int kScatterThreads = 512;  // scatter workgroup (16 keys per thread)
 constexpr int kBigThreads = 256;
 constexpr int kBigE = 16;
 constexpr int kBigTile = kBigThreads * kBigE;  // ranks per hull tile
@@ -15,7 +17,8 @@ constexpr int kMergeLevelsPerLaunch = 4;
 constexpr int kMergeGroupMax = 1 << 14;                         // tiles of the longest segment
 constexpr int kMergeRecMax = 1 << (kMergeLevelsPerLaunch - 1);  // merges at a launch's first level
 static_assert((int64_t)kMergeGroupMax * kBigTile >= ((int64_t)1 << 26), "top merge group too small");
-static_assert(kRadixThreads == 256, "digit scan assumes one digit per thread");
+static_assert(kRadixThreads == 256, "one histogram bin per thread");
+static_assert(kScatterThreads >= 256, "digit scan assumes one digit per thread");
 
 __global__ void k_radix_hist(const float* wsrc, const uint32_t* ksrc, int64_t n, int shift,
                              uint32_t* hist, int ntiles, uint32_t* flags);

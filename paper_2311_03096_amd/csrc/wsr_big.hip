@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
 // Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
 // The row goes through LDS so global reads and writes are coalesced.
 __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals) {
-  constexpr int kMaxRow = 16384;  // tiles of the longest segment (2^26 / kRadixTile)
+  constexpr int kMaxRow = (1 << 26) / kRadixTile;  // tiles of the longest segment
   __shared__ uint32_t row_s[kMaxRow];
   __shared__ int sh[256 / kWave + 1];
   uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
@@ -145,13 +145,13 @@ __device__ __forceinline__ void radix_load_tile(const float* wsrc, const uint32_
 // gridDim.x) and loads the next tile's items while it ranks and writes the current one.  Items
 // are ranked in wave-striped order, which is the tile's current order, so equal digits keep
 // their relative order.  Writes go out digit-run by digit-run.
-__global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float* wsrc, const uint32_t* ksrc,
+__global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const float* wsrc, const uint32_t* ksrc,
                                                                 const int32_t* vsrc, uint32_t* kdst,
                                                                 int32_t* vdst, int64_t n, int shift,
                                                                 const uint32_t* hist, const uint32_t* totals,
                                                                 int ntiles) {
-  constexpr int IPT = kRadixTile / kRadixThreads;
-  constexpr int NW = kRadixThreads / kWave;
+  constexpr int IPT = kRadixTile / kScatterThreads;
+  constexpr int NW = kScatterThreads / kWave;
   __shared__ uint32_t skey[kRadixTile];
   __shared__ int32_t sval[kRadixTile];
   __shared__ uint32_t wcnt[NW][256];
@@ -162,9 +162,10 @@ __global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float*
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int wbase = wv * kWave * IPT;
-  // digit bases over the whole segment (the same for every tile)
+  // digit bases over the whole segment (the same for every tile); thread tid < 256 owns digit tid
+  const bool owner = tid < 256;
   int gt;
-  const int rowbase = block_excl_scan<kRadixThreads, int>((int)totals[tid], ish, &gt);
+  const int rowbase = block_excl_scan<kScatterThreads, int>(owner ? (int)totals[tid] : 0, ish, &gt);
   uint32_t k[IPT];
   int32_t v[IPT];
   int tile = blockIdx.x;
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float*
     const int64_t base = (int64_t)tile * kRadixTile;
     const int nt = (int)min((int64_t)kRadixTile, n - base);
     const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
-    const uint32_t tile_pre = hist[(int64_t)tid * ntiles + tile];
+    const uint32_t tile_pre = owner ? hist[(int64_t)tid * ntiles + tile] : 0u;
     // the next tile's items are in flight while this one is ranked and written
     uint32_t kn[IPT];
     int32_t vn[IPT];
@@ -193,19 +194,23 @@ __global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float*
       }
     }
     __syncthreads();
-    // digit offsets inside the tile (thread tid owns digit tid; kRadixThreads == 256)
+    // digit offsets inside the tile (thread tid < 256 owns digit tid)
     uint32_t run = 0;
-    for (int w = 0; w < NW; ++w) {
-      const uint32_t c = wcnt[w][tid];
-      wcnt[w][tid] = run;
-      run += c;
+    if (owner) {
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t c = wcnt[w][tid];
+        wcnt[w][tid] = run;
+        run += c;
+      }
     }
     int tot;
-    const int dstart = block_excl_scan<kRadixThreads, int>((int)run, ish, &tot);
-    for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
-    tstart[tid] = (uint32_t)dstart;
-    // global base of this digit = all smaller digits + this digit in the tiles before this one
-    gofs[tid] = (uint32_t)rowbase + tile_pre;
+    const int dstart = block_excl_scan<kScatterThreads, int>((int)run, ish, &tot);
+    if (owner) {
+      for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
+      tstart[tid] = (uint32_t)dstart;
+      // global base of this digit = all smaller digits + this digit in the tiles before this one
+      gofs[tid] = (uint32_t)rowbase + tile_pre;
+    }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
@@ -217,7 +222,7 @@ __global__ __launch_bounds__(kRadixThreads, 4) void k_radix_scatter(const float*
       }
     }
     __syncthreads();
-    for (int s = tid; s < nt; s += kRadixThreads) {
+    for (int s = tid; s < nt; s += kScatterThreads) {
       const uint32_t key = skey[s];
       const uint32_t dg = (key >> shift) & 255u;
       const int64_t dst = (int64_t)gofs[dg] + (s - (int)tstart[dg]);
