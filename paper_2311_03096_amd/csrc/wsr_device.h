@@ -131,13 +131,10 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   return base + exc;
 }
 
-// Layouts of LDS arrays indexed by rank (prefix sums S, rank -> index maps): rank-padded (blocks
-// of 16 ranks per thread spread over the banks) or flat.
+// Layouts of LDS arrays indexed by rank (prefix sums S): rank-padded (blocks of 16 ranks per
+// thread spread over the banks) or transposed.
 struct RankPadded {
   __device__ static __forceinline__ int at(int k) { return rpad(k); }
-};
-struct RankFlat {
-  __device__ static __forceinline__ int at(int k) { return k; }
 };
 // Transposed: the E ranks of thread t sit E rows apart, rank k at (k mod E)(NT+1) + k/E, so the
 // lanes of a wave touching their i-th rank hit consecutive words.  Holds ranks 0..NT*E

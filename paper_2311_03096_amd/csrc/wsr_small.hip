@@ -1,15 +1,16 @@
 // wsr_small.hip -- prox_{lam R} of segments that fit one workgroup (d <= TMAX), everything in LDS.
 //
-// One workgroup solves one segment end to end (Alg. prox without its l1 lines):
+// One workgroup solves one segment end to end (Alg. prox without its l1 lines), E = TMAX/NT = 8
+// ranks per thread:
 //   1. coalesced load of the FP32 weights, order-preserving u32 keys, non-finite check;
-//   2. stable LSD radix sort in LDS (4 passes of 8 bits; wave-level digit matching with
-//      ballots, per-wave counters, block scan), index payload; a pass whose digit is the same
-//      for every key is skipped;
+//   2. sort with index payload: bucket-rank sort (value buckets, LDS atomics, rank = bucket start
+//      + smaller keys of the bucket), or a stable LSD radix sort in LDS (4 passes of 8 bits,
+//      ballot digit matching) when buckets are too full;
 //   3. centred FP64 prefix sums S_k = sum_{j<k}(x_j - c) + lam k(d-k)/(d-1)  (rank shift of
 //      Alg. prox; sum v in closed form);
-//   4. collisions = lower hull of (k, S_k): per-thread stack hulls then bridge merges
-//      (Sec. 4.1 pool adjacent violators, Sec. 4.3 search collisions);
-//   5. cluster values, scatter back to original order in LDS (Alg. prox repeat_interleave +
+//   4. collisions = lower hull of (k, S_k): ImminentCollisions rounds (Sec. 4.1), else per-thread
+//      stack hulls and bridge merges (Sec. 4.3 search collisions);
+//   5. cluster values, written to the original order in LDS (Alg. prox repeat_interleave +
 //      scatter), coalesced stores of out / saved perm / cluster-start bits.
 // The backward kernel averages the upstream gradient within each saved cluster.
 #include "wsr_device.h"
