@@ -193,18 +193,22 @@ void zero_words(uint32_t* p, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, s, p, n);
 }
 
-// Workgroups of the persistent radix scatter: as many as are resident at once (2 per CU).
-int scatter_grid() {
-  static int g = 0;
-  if (g == 0) {
-    int dev = 0, cus = 0;
+int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, c = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-    g = 2 * cus;
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    cus = c;
   }
-  return g;
+  return cus;
 }
+
+// Workgroups of the persistent radix scatter: as many as are resident at once (2 per CU).
+int scatter_grid() { return 2 * cu_count(); }
+// Workgroups of the persistent radix histogram.
+int hist_grid() { return kHistPerCu * cu_count(); }
 
 // Forward of one long segment [start, start + d).
 int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
@@ -223,7 +227,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
     uint32_t* kdst = pass % 2 == 0 ? b.keysB : b.keysA;
     int32_t* vdst = pass % 2 == 0 ? b.valsB : (pass == 3 ? perm_final : b.valsA);
     { WSR_TRACE("radix_hist", s);
-    hipLaunchKernelGGL(k_radix_hist, dim3(nrt), dim3(kRadixThreads), 0, s, pass == 0 ? wseg : nullptr,
+    hipLaunchKernelGGL(k_radix_hist, dim3(std::min(nrt, hist_grid())), dim3(kRadixThreads), 0, s, pass == 0 ? wseg : nullptr,
                        ksrc, d, shift, b.hist, nrt, b.flags); }
     { WSR_TRACE("radix_rowscan", s);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, b.hist, nrt, b.totals); }

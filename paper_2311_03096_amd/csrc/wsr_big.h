@@ -9,6 +9,7 @@ constexpr int kRadixThreads = 256;   // histogram workgroup; the scatter's digit
                                      // one thread per digit
 constexpr int kRadixTile = 8192;     // keys per radix tile (digit runs average 32 keys)
 constexpr int kScatterThreads = 512;  // scatter workgroup (16 keys per thread)
+constexpr int kHistPerCu = 4;         // resident workgroups per CU of the persistent histogram
 constexpr int kBigThreads = 256;
 constexpr int kBigE = 16;
 constexpr int kBigTile = kBigThreads * kBigE;  // ranks per hull tile

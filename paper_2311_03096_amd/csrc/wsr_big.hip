@@ -24,66 +24,83 @@ namespace wsr {
 // ------------------------------------------------------------------------------- radix sort
 
 // Per-tile histogram of one 8-bit digit.  Source is either the FP32 weights (first pass: keys
-// made on the fly, non-finite values flagged) or the u32 keys of the previous pass.
+// made on the fly, non-finite values flagged) or the u32 keys of the previous pass.  Persistent:
+// workgroup b counts tiles b, b + G, ... (G = gridDim.x) and has the next tile's keys in flight
+// while it counts the current one, so the loads of one tile overlap the LDS atomics of another.
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc, const uint32_t* ksrc,
                                                              int64_t n, int shift, uint32_t* hist,
                                                              int ntiles, uint32_t* flags) {
   constexpr int IPT = kRadixTile / kRadixThreads;
   constexpr int NW = kRadixThreads / kWave;
-  __shared__ uint32_t h[NW][256];  // one sub-histogram per wave (less contention on hot digits)
+  constexpr int kHistLanes = 16;
+  constexpr int kSub = kWave / kHistLanes;  // sub-histograms per wave
+  __shared__ uint32_t h[NW * kSub][256];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
-  for (int j = lane; j < 256; j += kWave) h[wv][j] = 0u;
-  const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-  const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
-  // all of the thread's keys in flight at once (uniform tile base, 32-bit offsets)
-  uint32_t key[IPT];
+  for (int j = lane; j < 256 * kSub; j += kWave) h[wv * kSub + j / 256][j % 256] = 0u;
+  // raw 32-bit words of a tile (weights or keys), all in flight at once: uniform tile base,
+  // 32-bit offsets; words past the end of the segment are never counted
+  const uint32_t* src = wsrc ? reinterpret_cast<const uint32_t*>(wsrc) : ksrc;
+  auto load = [&](int tile, uint32_t (&w)[IPT]) {
+    const int64_t base = (int64_t)tile * kRadixTile;
+    const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
+    const uint32_t* st = src + base;
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+      w[r] = p < nt ? st[p] : 0u;
+    }
+  };
   int bad = 0;
-  if (wsrc) {
-    const float* wt = wsrc + base;
+  uint32_t word[IPT];
+  int tile = blockIdx.x;
+  if (tile < ntiles) load(tile, word);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t base = (int64_t)tile * kRadixTile;
+    const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
+    uint32_t wn[IPT];
+    const int next = tile + (int)gridDim.x;
+    if (next < ntiles) load(next, wn);
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
-      const float f = p < nt ? wt[p] : 0.0f;
-      bad |= !isfinite(f);
-      key[r] = float_to_key(f);
+      const bool in = p < nt;
+      uint32_t key = word[r];
+      if (wsrc) {
+        const float f = __uint_as_float(key);
+        bad |= in && !isfinite(f);
+        key = float_to_key(f);
+      }
+      const uint32_t dg = (key >> shift) & 255u;
+      // a wave whose lanes all hold the same digit (long runs in sorted or clustered data) adds
+      // once instead of 64 serialised atomics on one LDS address (the active mask is taken
+      // before the leader branch, where only one lane is active); otherwise each group of
+      // kHistLanes lanes counts into its own sub-histogram, so a skewed digit (the top byte of
+      // most inputs) puts at most kHistLanes lanes on one address
+      const unsigned long long act = __ballot(in);
+      const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+      if (act == ~0ull && __ballot(dg == d0) == act) {
+        if (lane == 0) atomicAdd(&h[wv * kSub][d0], (uint32_t)kWave);
+      } else if (in) {
+        atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
+      }
     }
-  } else {
-    const uint32_t* kt = ksrc + base;
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
-      key[r] = p < nt ? kt[p] : 0u;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < IPT; ++r) {
-    const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
-    const uint32_t dg = (key[r] >> shift) & 255u;
-    const bool in = p < nt;
-    // a wave whose lanes all hold the same digit (long runs in sorted or clustered data) adds
-    // once instead of 64 serialised atomics on one LDS address (the active mask is taken before
-    // the leader branch, where only one lane is active)
-    const unsigned long long act = __ballot(in);
-    const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
-    if (act == ~0ull && __ballot(dg == d0) == act) {
-      if (lane == 0) atomicAdd(&h[wv][d0], (uint32_t)kWave);
-    } else if (in) {
-      atomicAdd(&h[wv][dg], 1u);
-    }
-  }
-  if (wsrc) {
-    if (__syncthreads_or(bad) && tid == 0) atomicOr(flags, 1u);
-  } else {
     __syncthreads();
-  }
-  for (int j = tid; j < 256; j += kRadixThreads) {
-    uint32_t c = 0;
+    for (int j = tid; j < 256; j += kRadixThreads) {
+      uint32_t c = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w) c += h[w][j];
-    hist[(int64_t)j * ntiles + blockIdx.x] = c;
+      for (int w = 0; w < NW * kSub; ++w) {
+        c += h[w][j];
+        h[w][j] = 0u;
+      }
+      hist[(int64_t)j * ntiles + tile] = c;
+    }
+    __syncthreads();  // the sub-histograms are clear for the next tile
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) word[r] = wn[r];
   }
+  if (wsrc && __syncthreads_or(bad) && tid == 0) atomicOr(flags, 1u);
 }
 
 // Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
@@ -854,12 +871,38 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
 
 // ------------------------------------------------------------------------------- backward
 
+// Cluster-start bits of one thread's n (1..kBigE) ranks starting at tile-relative rank j0 of a
+// tile starting at segment rank k0 (bit i <-> rank k0 + j0 + i); rank 0 of the segment always
+// starts a cluster.  At most two mask words are read.
+__device__ __forceinline__ uint32_t thread_start_bits(const uint32_t* mask, int64_t seg_start, int64_t kk0,
+                                                      int n) {
+  const int64_t pf0 = seg_start + kk0;
+  const int64_t pfl = pf0 + n - 1;
+  uint64_t w = mask[pf0 >> 5];
+  if ((pfl >> 5) != (pf0 >> 5)) w |= (uint64_t)mask[pfl >> 5] << 32;
+  uint32_t b = (uint32_t)(w >> (pf0 & 31)) & ((1u << n) - 1u);
+  if (kk0 == 0) b |= 1u;
+  return b;
+}
+
+// One thread's kBigE consecutive cotangents (rank order) read back from the rank-padded LDS copy,
+// and their FP64 sum.  The tile and apply kernels share it, so the prefix G at a cluster start is
+// formed by the same additions in both.
+__device__ __forceinline__ double thread_cotangents(const float* lds, int j0, int nmine, float (&gk)[kBigE]) {
+  double lsum = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    gk[i] = i < nmine ? lds[rpad(j0 + i)] : 0.0f;
+    lsum += (double)gk[i];
+  }
+  return lsum;
+}
+
 struct BwdTileSmem {
-  float g[kBigTile];  // gathered cotangent in rank order
+  float g[rpad_size(kBigTile)];  // gathered cotangent in rank order (rank-padded)
   double dred[kBigThreads / kWave + 1];
-  int ired[kBigThreads / kWave + 1];
-  int fmin, lmax;
-  double fG, lG;
+  int wf[kBigThreads / kWave], wl[kBigThreads / kWave];
+  double wfG[kBigThreads / kWave], wlG[kBigThreads / kWave];
 };
 
 // Gather the cotangent in rank order (kept for the apply pass), tile sums, first / last cluster
@@ -869,15 +912,19 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
                                                               int64_t seg_start, float* gsorted,
                                                               double* tsum, int32_t* fpos, double* fG,
                                                               int32_t* lpos, double* lG) {
+  constexpr int R = kBigTile / kBigThreads;
+  constexpr int NW = kBigThreads / kWave;
   __shared__ BwdTileSmem sm;
   const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / kWave;
   const int t = blockIdx.x;
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int j0 = tid * kBigE;
-  // coalesced perm read and gsorted write; the gather itself follows the permutation.  All the
-  // thread's perm loads, then all its gathers, are in flight at once (fixed trip count).
-  constexpr int R = kBigTile / kBigThreads;
+  const int nmine = max(0, min(kBigE, np - j0));
+  // lane-consecutive perm reads and gsorted writes; the gather itself follows the permutation.
+  // All perm loads, the thread's start bits, then all gathers, are in flight at once.
   const int32_t* const pt = perm + k0;
   const float* const gs = g + seg_start;
   float* const go = gsorted + k0;
@@ -887,6 +934,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
     const int j = tid + r * kBigThreads;
     pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
   }
+  const uint32_t bm = nmine > 0 ? thread_start_bits(mask, seg_start, k0 + j0, nmine) : 0u;
   float gv[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) gv[r] = gs[pl[r]];
@@ -894,56 +942,66 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
     if (j < np) {
-      sm.g[j] = gv[r];
+      sm.g[rpad(j)] = gv[r];
       go[j] = gv[r];
     }
   }
   __syncthreads();
   float gk[kBigE];
-  double lsum = 0.0;
-#pragma unroll
-  for (int i = 0; i < kBigE; ++i) {
-    const int j = j0 + i;
-    gk[i] = j < np ? sm.g[j] : 0.0f;
-    lsum += (double)gk[i];
-  }
-  if (tid == 0) {
-    sm.fmin = 0x7FFFFFFF;
-    sm.lmax = -1;
-  }
+  const double lsum = thread_cotangents(sm.g, j0, nmine, gk);
   double total;
-  double G = block_excl_scan<kBigThreads, double>(lsum, sm.dred, &total);
-  int myf = 0x7FFFFFFF, myl = -1;
-  double Gf = 0.0, Gl = 0.0;
+  const double P = block_excl_scan<kBigThreads, double>(lsum, sm.dred, &total);
+  // local prefix at the thread's first and last start
+  double run = P, Gf = 0.0, Gl = 0.0;
+  int f = -1, l = -1;
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
-    const int j = j0 + i;
-    if (j < np) {
-      const int64_t pf = seg_start + k0 + j;
-      const bool st = (k0 + j == 0) || ((mask[pf >> 5] >> (pf & 31)) & 1u);
-      if (st) {
-        if (j < myf) {
-          myf = j;
-          Gf = G;
-        }
-        myl = j;
-        Gl = G;
+    if ((bm >> i) & 1u) {
+      if (f < 0) {
+        f = i;
+        Gf = run;
       }
-      G += (double)gk[i];
+      l = i;
+      Gl = run;
     }
+    run += (double)gk[i];
   }
-  atomicMin(&sm.fmin, myf);
-  atomicMax(&sm.lmax, myl);
-  __syncthreads();
-  if (myf != 0x7FFFFFFF && myf == sm.fmin) sm.fG = Gf;
-  if (myl >= 0 && myl == sm.lmax) sm.lG = Gl;
+  // the wave's first and last start, then the block's (no shared-address atomics)
+  const uint64_t has = __ballot(bm != 0u);
+  if (has) {
+    if (lane == __ffsll((unsigned long long)has) - 1) {
+      sm.wf[wv] = (int)(k0 + j0 + f);
+      sm.wfG[wv] = Gf;
+    }
+    if (lane == 63 - __clzll((long long)has)) {
+      sm.wl[wv] = (int)(k0 + j0 + l);
+      sm.wlG[wv] = Gl;
+    }
+  } else if (lane == 0) {
+    sm.wf[wv] = -1;
+    sm.wl[wv] = -1;
+  }
   __syncthreads();
   if (tid == 0) {
+    int fp = -1, lp = -1;
+    double fg = 0.0, lg = 0.0;
+    for (int w = 0; w < NW; ++w)
+      if (sm.wf[w] >= 0) {
+        fp = sm.wf[w];
+        fg = sm.wfG[w];
+        break;
+      }
+    for (int w = NW - 1; w >= 0; --w)
+      if (sm.wl[w] >= 0) {
+        lp = sm.wl[w];
+        lg = sm.wlG[w];
+        break;
+      }
     tsum[t] = total;
-    fpos[t] = sm.fmin == 0x7FFFFFFF ? -1 : (int32_t)(k0 + sm.fmin);
-    fG[t] = sm.fmin == 0x7FFFFFFF ? 0.0 : sm.fG;
-    lpos[t] = sm.lmax < 0 ? -1 : (int32_t)(k0 + sm.lmax);
-    lG[t] = sm.lmax < 0 ? 0.0 : sm.lG;
+    fpos[t] = fp;
+    fG[t] = fg;
+    lpos[t] = lp;
+    lG[t] = lg;
   }
 }
 
@@ -990,129 +1048,99 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const
 }
 
 struct BwdApplySmem {
-  int32_t lp[kBigTile + 2];  // [previous start] + local cluster starts + [next start]: ranks
-  union {
-    double lg[kBigTile + 2];         // global prefix G at those starts
-    float val[rpad_size(kBigTile)];  // then: result of each rank of the tile (rank-padded)
-  } u;
+  float v[rpad_size(kBigTile)];  // cotangent in rank order, then the results (rank-padded)
   double dred[kBigThreads / kWave + 1];
-  int ired[kBigThreads / kWave + 1];
-  int n;
+  Cand shL[kBigThreads / kWave], shR[kBigThreads / kWave];
+  int shF[kBigThreads / kWave];
 };
 
+// Per rank: the mean cotangent of its cluster, scattered to the original order.  Each thread
+// holds G (global prefix) at its kBigE ranks; the start before its first start and after its last
+// one come from the other threads (carry exchange) or, at the tile ends, from the tile scan.
 __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsorted, const int32_t* perm,
                                                                const uint32_t* mask, int64_t d,
                                                                int64_t seg_start, const double* tileoff,
                                                                const int32_t* prevp, const double* prevG,
                                                                const int32_t* nextp, const double* nextG,
                                                                float* gout) {
+  constexpr int R = kBigTile / kBigThreads;
   __shared__ BwdApplySmem sm;
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
-  constexpr int R = kBigTile / kBigThreads;
   const int j0 = tid * kBigE;
-  // segment-relative 32-bit offsets (d <= 2^26) from a uniform base
+  const int nmine = max(0, min(kBigE, np - j0));
+  // segment-relative 32-bit offsets (d <= 2^26) from a uniform base; every load is issued first
   float* const og = gout + seg_start;
   const int32_t* const pt = perm + k0;
+  const float* const gt = gsorted + k0;
   int32_t pl[R];
+  float gl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
     pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
+    gl[r] = j < np ? gt[j] : 0.0f;
   }
-  // the thread's kBigE consecutive gathered cotangents as 16-byte words (64-byte aligned)
-  float gk[kBigE];
-  const float* const gt = gsorted + k0;
-  if (j0 + kBigE <= np) {
+  const uint32_t bm = nmine > 0 ? thread_start_bits(mask, seg_start, k0 + j0, nmine) : 0u;
+  const double toff = tileoff[t];
+  const Cand after{nextp[t], nextG[t]};
+  const Cand before{prevp[t], prevG[t]};
 #pragma unroll
-    for (int q = 0; q < kBigE / 4; ++q) {
-      const float4 w = *reinterpret_cast<const float4*>(gt + j0 + 4 * q);
-      gk[4 * q] = w.x;
-      gk[4 * q + 1] = w.y;
-      gk[4 * q + 2] = w.z;
-      gk[4 * q + 3] = w.w;
-    }
-  } else {  // last, partial tile
-#pragma unroll
-    for (int i = 0; i < kBigE; ++i) gk[i] = j0 + i < np ? gt[j0 + i] : 0.0f;
-  }
-  double lsum = 0.0;
-  int lst = 0;
-  bool st[kBigE];
-#pragma unroll
-  for (int i = 0; i < kBigE; ++i) {
-    const int j = j0 + i;
-    st[i] = false;
-    if (j < np) {
-      lsum += (double)gk[i];
-      const int64_t pf = seg_start + k0 + j;
-      st[i] = (k0 + j == 0) || ((mask[pf >> 5] >> (pf & 31)) & 1u);
-      lst += st[i];
-    }
-  }
-  int nst;
-  const int cb = block_excl_scan<kBigThreads, int>(lst, sm.ired, &nst);
-  double G = tileoff[t] + block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
-  // list: [previous start] + local starts + [next start after the tile's starts]
-  int ci = 1 + cb;
-#pragma unroll
-  for (int i = 0; i < kBigE; ++i) {
-    const int j = j0 + i;
-    if (j < np && st[i]) {
-      sm.lp[ci] = (int32_t)(k0 + j);
-      sm.u.lg[ci] = G;
-      ++ci;
-    }
-    if (j < np) G += (double)gk[i];
-  }
-  if (tid == 0) {
-    sm.lp[0] = prevp[t];
-    sm.u.lg[0] = prevG[t];
-    sm.lp[1 + nst] = nextp[t];
-    sm.u.lg[1 + nst] = nextG[t];
-    sm.n = nst + 2;
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    if (j < np) sm.v[rpad(j)] = gl[r];
   }
   __syncthreads();
-  const int n = sm.n;
-  float vr[kBigE];  // results of the thread's ranks
-  if (j0 < np) {
-    const int64_t kk0 = k0 + j0;
-    int a = 0, b = n - 1;  // lp[a] <= kk0 < lp[b]
-    while (b - a > 1) {
-      const int mid = (a + b) >> 1;
-      if (sm.lp[mid] <= kk0)
-        a = mid;
-      else
-        b = mid;
-    }
-    int cur = a;
-    int64_t nxt = sm.lp[cur + 1];
-    float val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
+  float gk[kBigE];
+  const double lsum = thread_cotangents(sm.v, j0, nmine, gk);
+  const double P = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
+  // G at each of the thread's ranks, formed as the tile kernel forms it for the tile scan
+  double sv[kBigE];
+  double run = P;
+  Cand mineL{-1, 0.0}, mineR{-1, 0.0};
 #pragma unroll
-    for (int i = 0; i < kBigE; ++i) {
-      if (j0 + i < np) {
-        while (k0 + j0 + i >= nxt && cur + 2 < n) {
-          ++cur;
-          nxt = sm.lp[cur + 1];
-          val = (float)((sm.u.lg[cur + 1] - sm.u.lg[cur]) / (double)(nxt - sm.lp[cur]));
-        }
-      }
-      vr[i] = val;
+  for (int i = 0; i < kBigE; ++i) {
+    sv[i] = toff + run;
+    run += (double)gk[i];
+    if ((bm >> i) & 1u) {
+      const Cand c{(int)(k0 + j0 + i), sv[i]};
+      if (mineR.pos < 0) mineR = c;
+      mineL = c;
     }
   }
-  __syncthreads();  // every read of the start list is done: the results take the place of G
-  if (j0 < np) {
+  Cand lc, rc;
+  carry_exchange<kBigThreads>(mineL, mineR, false, after, sm.shL, sm.shR, sm.shF, &lc, &rc);
+  if (lc.pos < 0) lc = before;
+  // backward sweep: each start's cluster ends at the next start (or rc); the ranks before the
+  // thread's first start belong to the cluster entered from lc.  Every tile a cluster touches
+  // forms its value from the same two G values and the same division.
+  float val[kBigE];
+  int npos = rc.pos;
+  double sn = rc.s;
 #pragma unroll
-    for (int i = 0; i < kBigE; ++i)
-      if (j0 + i < np) sm.u.val[rpad(j0 + i)] = vr[i];
+  for (int i = kBigE - 1; i >= 0; --i) {
+    val[i] = 0.0f;
+    if ((bm >> i) & 1u) {
+      const int a = (int)(k0 + j0 + i);
+      val[i] = (float)div_count(sn - sv[i], npos - a);
+      npos = a;
+      sn = sv[i];
+    }
+  }
+  float cur = nmine > 0 ? (float)div_count(sn - lc.s, max(1, npos - lc.pos)) : 0.0f;
+  // the scan and exchange barriers passed after every read of the cotangents: reuse the array
+#pragma unroll
+  for (int i = 0; i < kBigE; ++i) {
+    if ((bm >> i) & 1u) cur = val[i];
+    if (i < nmine) sm.v[rpad(j0 + i)] = cur;
   }
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    if (j < np) og[pl[r]] = sm.u.val[rpad(j)];
+    if (j < np) og[pl[r]] = sm.v[rpad(j)];
   }
 }
 
