@@ -65,6 +65,7 @@ struct BigWs {
   uint32_t *hist, *totals;
   int32_t* vpos;
   double* vS;
+  uint16_t* hbits;  // per tile and thread: hull-vertex bits of the thread's ranks
   int32_t *hcnt, *lo, *hi, *prev_pos, *next_pos;
   double *tsum, *tileoff, *prev_s, *next_s;
   // backward
@@ -92,6 +93,7 @@ BigWs big_layout(int64_t d, void* base) {
   w.totals = (uint32_t*)take(sizeof(uint32_t) * 256);
   w.vpos = (int32_t*)take(sizeof(int32_t) * nt * (kBigTile + 1));
   w.vS = (double*)take(sizeof(double) * nt * (kBigTile + 1));
+  w.hbits = (uint16_t*)take(sizeof(uint16_t) * nt * kBigThreads);
   w.hcnt = (int32_t*)take(sizeof(int32_t) * nt);
   w.lo = (int32_t*)take(sizeof(int32_t) * nt);
   w.hi = (int32_t*)take(sizeof(int32_t) * nt);
@@ -238,7 +240,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   }
   { WSR_TRACE("big_tile_hull", s);
   hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, lam_arr, seg_id,
-                     lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum); }
+                     lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum, b.hbits); }
   { WSR_TRACE("big_tile_scan", s);
   hipLaunchKernelGGL(k_big_tile_scan, dim3(1), dim3(1024), 0, s, b.tsum, b.tileoff, b.hcnt, b.lo, b.hi, nt, d,
                      lam_arr, seg_id, lam_scalar); }
@@ -268,7 +270,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   } while (lvl_lo <= nlev);
   { WSR_TRACE("big_apply", s);
   hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, perm_final, d, lam_arr, seg_id,
-                     lam_scalar, b.flags, b.vpos, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
+                     lam_scalar, b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
                      b.next_pos, b.next_s, out, saved_mask, start); }
   return last_error();
 }

@@ -13,6 +13,8 @@ constexpr int kHistPerCu = 4;         // resident workgroups per CU of the persi
 constexpr int kBigThreads = 256;
 constexpr int kBigE = 16;
 constexpr int kBigTile = kBigThreads * kBigE;  // ranks per hull tile
+constexpr int kApplySparseMax = 256;  // surviving hull vertices up to which a tile's S' values
+                                      // are read from the hull rather than recomputed
 constexpr int kMergeThreads = 512;  // one wave per merge
 constexpr int kMergeLevelsPerLaunch = 4;
 constexpr int kMergeGroupMax = 1 << 14;                         // tiles of the longest segment
@@ -29,7 +31,7 @@ __global__ void k_radix_scatter(const float* wsrc, const uint32_t* ksrc, const i
                                 const uint32_t* hist, const uint32_t* totals, int ntiles);
 __global__ void k_big_tile_hull(const uint32_t* skeys, int64_t d, const float* lam_arr, int seg_id,
                                 float lam_scalar, int32_t* vpos, double* vS, int32_t* hcnt,
-                                double* tsum);
+                                double* tsum, uint16_t* hbits);
 __global__ void k_big_tile_scan(const double* tsum, double* tileoff, const int32_t* hcnt,
                                 int32_t* lo, int32_t* hi, int ntiles, int64_t d,
                                 const float* lam_arr, int seg_id, float lam_scalar);
@@ -40,8 +42,9 @@ __global__ void k_big_merge(int lvl_lo, int lvl_hi, int ntiles, const int32_t* v
                             double* next_s);
 __global__ void k_big_apply(const uint32_t* skeys, const int32_t* perm, int64_t d,
                             const float* lam_arr, int seg_id, float lam_scalar,
-                            const uint32_t* flags, const int32_t* vpos, const double* vS,
-                            const double* tileoff, const int32_t* lo_g, const int32_t* hi_g,
+                            const uint32_t* flags, const uint16_t* hbits, const int32_t* hcnt,
+                            const double* vS, const double* tileoff, const int32_t* lo_g,
+                            const int32_t* hi_g,
                             const int32_t* prev_pos, const double* prev_s, const int32_t* next_pos,
                             const double* next_s, float* out, uint32_t* mask_out,
                             int64_t seg_start);

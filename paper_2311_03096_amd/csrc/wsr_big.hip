@@ -267,6 +267,7 @@ struct TileSmem {
   double dred[kBigThreads / kWave + 1];
   int ired[kBigThreads / kWave + 1];
   WaveBound wb[2 * (kBigThreads / kWave)];
+  uint32_t hb[kBigThreads];  // fallback path: hull-vertex bits of each thread's ranks
   double xtot;
 };
 
@@ -283,7 +284,8 @@ __device__ __forceinline__ float seg_lambda(const float* lam_arr, int seg_id, fl
 __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* skeys, int64_t d,
                                                                const float* lam_arr, int seg_id,
                                                                float lam_scalar, int32_t* vpos,
-                                                               double* vS, int32_t* hcnt, double* tsum) {
+                                                               double* vS, int32_t* hcnt, double* tsum,
+                                                               uint16_t* hbits) {
   __shared__ TileSmem sm;
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -341,6 +343,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
     // hull vertices = surviving candidates in rank order, then the tile's end point
     int nv;
     int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);
+    hbits[(int64_t)t * kBigThreads + tid] = (uint16_t)bm;
 #pragma unroll
     for (int i = 0; i < kBigE; ++i) {
       if ((bm >> i) & 1u) {
@@ -357,12 +360,17 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
     }
     return;
   }
+  sm.hb[tid] = 0u;
   tile_hull<kBigThreads, kBigE, RankPadded, int>(sm.S, np, sm.vert, sm.cnt, sm.mres);
   const int nv = sm.cnt[0];
   for (int i = tid; i < nv; i += kBigThreads) {
-    vpos[vb + i] = (int32_t)(k0 + sm.vert[i]);
-    vS[vb + i] = sm.S[rpad(sm.vert[i])];
+    const int r = sm.vert[i];
+    vpos[vb + i] = (int32_t)(k0 + r);
+    vS[vb + i] = sm.S[rpad(r)];
+    if (r < np) atomicOr(&sm.hb[r / kBigE], 1u << (r % kBigE));
   }
+  __syncthreads();
+  hbits[(int64_t)t * kBigThreads + tid] = (uint16_t)sm.hb[tid];
   if (tid == 0) {
     hcnt[t] = nv;
     tsum[t] = sm.xtot;
@@ -727,21 +735,27 @@ WSR_INSTANTIATE_MERGE(16384)
 // ------------------------------------------------------------------------------- apply
 
 struct ApplySmem {
-  int32_t lp[kBigTile + 2];  // [prev] + own vertices + [next]: ranks
-  union {
-    double ls[kBigTile + 2];         // S' = S - S_{k0} for points of this tile, global S otherwise
-    float val[rpad_size(kBigTile)];  // then: value of each rank of the tile (rank-padded)
-  } u;
+  uint32_t kv[rpad_size(kBigTile)];  // sorted keys in rank order, then the values (rank-padded)
   uint32_t lmask[kBigTile / 32 + 2];
-  int n;
+  double dred[kBigThreads / kWave + 1];
+  int ired[kBigThreads / kWave + 1];
+  Cand shL[kBigThreads / kWave], shR[kBigThreads / kWave];
+  int shF[kBigThreads / kWave];
 };
 
-// Values for the ranks of tile t, scattered to the original order; cluster-start bits.
+// Values for the ranks of tile t, scattered to the original order; cluster-start bits.  The
+// starts inside the tile are its surviving hull vertices: the tile's hull-vertex bits whose
+// vertex index lies in the own range [lo, hi], plus rank k0 when the previous tile's end point
+// survives.  S' at a start is the hull's stored value (tiles with few surviving vertices) or is
+// recomputed from the sorted keys by the tile kernel's own operations (dense tiles); each thread
+// then sweeps its ranks with the neighbouring starts from the other threads (carry exchange) or
+// from the merge (tile ends).
 __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys, const int32_t* perm,
                                                            int64_t d, const float* lam_arr, int seg_id,
                                                            float lam_scalar, const uint32_t* flags,
-                                                           const int32_t* vpos, const double* vS,
-                                                           const double* tileoff, const int32_t* lo_g,
+                                                           const uint16_t* hbits, const int32_t* hcnt,
+                                                           const double* vS, const double* tileoff,
+                                                           const int32_t* lo_g,
                                                            const int32_t* hi_g, const int32_t* prev_pos,
                                                            const double* prev_s, const int32_t* next_pos,
                                                            const double* next_s, float* out,
@@ -753,118 +767,179 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const int64_t k0 = (int64_t)t * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int off = (int)((seg_start + k0) & 31);
+  const int j0 = tid * kBigE;
+  const int nmine = max(0, min(kBigE, np - j0));
   const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
   const bool nonfinite = (flags[0] & 1u) != 0;
   const bool identity = nonfinite || !(lam > 0.0f);
-  // the tile's permutation entries, lane-consecutive (stores below are coalesced when the
-  // permutation is locally ordered)
   // segment-relative 32-bit offsets (d <= 2^26) from a uniform base
   float* const og = out + seg_start;
   const int32_t* const pt = perm + k0;
+  const uint32_t* const kt = skeys + k0;
+  // the permutation entries are needed only for the final scatter: loaded late (their latency
+  // overlaps the last barrier), so they do not hold registers through the scans and passes
   int32_t pl[R];
+  auto load_perm = [&]() {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int j = tid + r * kBigThreads;
-    pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
-  }
+    for (int r = 0; r < R; ++r) {
+      const int j = tid + r * kBigThreads;
+      pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
+    }
+  };
   for (int j = tid; j < kBigTile / 32 + 2; j += kBigThreads) sm.lmask[j] = 0u;
+  // the thread's cluster-start bits go to the tile's mask words (at most two words per thread)
+  auto mark = [&](uint32_t bits) {
+    if (bits == 0u) return;
+    const int q = j0 + off;
+    const uint64_t b = (uint64_t)bits << (q & 31);
+    atomicOr(&sm.lmask[q >> 5], (uint32_t)b);
+    if (b >> 32) atomicOr(&sm.lmask[(q >> 5) + 1], (uint32_t)(b >> 32));
+  };
   if (identity) {
+    load_perm();
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = tid + r * kBigThreads;
-      if (j < np) {
-        og[pl[r]] = nonfinite ? __builtin_nanf("") : key_to_float(skeys[k0 + j]);
-        atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
-      }
+      if (j < np) og[pl[r]] = nonfinite ? __builtin_nanf("") : key_to_float(kt[j]);
     }
+    mark(nmine > 0 ? (1u << nmine) - 1u : 0u);
     __syncthreads();
     if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
     return;
   }
-  const double c = (double)key_to_float(skeys[d >> 1]);
-  const int lo = lo_g[t];
-  const int own = max(0, hi_g[t] - lo + 1);
-  const double toff = tileoff[t];
+  const uint32_t hb = hbits[(int64_t)t * kBigThreads + tid];
+  const int lo = lo_g[t], hi = hi_g[t], hc = hcnt[t];
   const int64_t vb = (int64_t)t * (kBigTile + 1);
-  if (tid == 0) {
-    sm.lp[0] = prev_pos[t];
-    sm.u.ls[0] = prev_pos[t] == k0 ? 0.0 : prev_s[t];  // the tile's first point has S' = 0
-    const int nx = next_pos[t];
-    sm.n = 1 + own + (nx >= 0 ? 1 : 0);
-    if (nx >= 0) {
-      sm.lp[1 + own] = nx;
-      sm.u.ls[1 + own] = next_s[t];
+  // S' at a start: read from the tile's hull vertices while the tile has few surviving ones, else
+  // recomputed for the whole tile from its sorted keys (lane-consecutive reads), by the same
+  // operations as the tile kernel, which make the same S'
+  const bool dense = hi - lo + 1 > kApplySparseMax;
+  if (dense) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = tid + r * kBigThreads;
+      if (j < np) sm.kv[rpad(j)] = kt[j];
     }
   }
-  for (int i = tid; i < own; i += kBigThreads) {
-    sm.lp[1 + i] = vpos[vb + lo + i];
-    sm.u.ls[1 + i] = vS[vb + lo + i];
-  }
-  __syncthreads();
-  const int n = sm.n;
-  for (int i = tid; i < n; i += kBigThreads) {  // cluster starts inside the tile
-    const int64_t p = sm.lp[i];
-    if (p >= k0 && p < k0 + np) {
-      const int j = (int)(p - k0);
-      atomicOr(&sm.lmask[(j + off) >> 5], 1u << ((j + off) & 31));
-    }
-  }
-  const int j0 = tid * kBigE;
-  float vr[kBigE];  // values of the thread's ranks
-  if (j0 < np) {
-    const int64_t kk0 = k0 + j0;
-    int a = 0, b = n - 1;  // lp[a] <= kk0 < lp[b]
-    while (b - a > 1) {
-      const int mid = (a + b) >> 1;
-      if (sm.lp[mid] <= kk0)
-        a = mid;
-      else
-        b = mid;
-    }
-    // a cluster inside the tile uses S' (small numbers); a cluster reaching outside the tile uses
-    // global S formed exactly as the merge kernel forms it (vS + tile offset), so every tile it
-    // touches computes the identical value
-    auto edge_value = [&](int e) -> float {
-      const int64_t pa = sm.lp[e], pb = sm.lp[e + 1];
-      const bool ina = pa >= k0 && pa <= k0 + np;
-      const bool inb = pb >= k0 && pb <= k0 + np;
-      double dS;
-      if (ina && inb) {
-        dS = sm.u.ls[e + 1] - sm.u.ls[e];
-      } else {
-        const double ga = ina ? (pa == k0 ? prev_s[t] : sm.u.ls[e] + toff) : sm.u.ls[e];
-        const double gb = inb ? sm.u.ls[e + 1] + toff : sm.u.ls[e + 1];
-        dS = gb - ga;
-      }
-      return (float)(c + dS / (double)(pb - pa));
-    };
-    int cur = a;
-    int64_t nxt = sm.lp[cur + 1];
-    float v = edge_value(cur);
+  const double c = (double)key_to_float(skeys[d >> 1]);
+  const double lamd = (double)lam / (double)(d - 1);
+  const double toff = tileoff[t];
+  const int ppos = prev_pos[t];
+  const double ps = prev_s[t];
+  const int npn = next_pos[t];
+  const double nsn = next_s[t];
+  const double endS = vS[vb + hc - 1];  // the tile's end point, as the tile kernel stored it
+  // surviving starts among the thread's ranks: hull-vertex bits whose vertex index is own (the
+  // scan's barriers also order the key writes above before the reads below)
+  const int vbase = block_excl_scan<kBigThreads, int>(__popc(hb), sm.ired, (int*)nullptr);
+  uint32_t bm = 0u;
+  {
+    int vi = vbase;
 #pragma unroll
     for (int i = 0; i < kBigE; ++i) {
-      if (j0 + i < np) {
-        while (k0 + j0 + i >= nxt && cur + 2 < n) {
-          ++cur;
-          nxt = sm.lp[cur + 1];
-          v = edge_value(cur);
-        }
+      if ((hb >> i) & 1u) {
+        if (vi >= lo && vi <= hi) bm |= 1u << i;
+        ++vi;
       }
-      vr[i] = v;
     }
   }
-  __syncthreads();  // every read of the vertex list is done: the values take the place of S'
-  if (j0 < np) {
+  const bool k0start = tid == 0 && ppos == k0;  // the previous tile's end point survives
+  if (k0start) bm |= 1u;
+  auto xc = [&](int i) -> double {
+    return j0 + i < np ? (double)key_to_float(sm.kv[rpad(j0 + i)]) - c : 0.0;
+  };
+  auto sprime = [&](int i, double Xi) -> double {
+    const int j = j0 + i;
+    return Xi + lamd * (double)j * ((double)(d - 2 * k0) - (double)j);
+  };
+  double X0 = 0.0;
+  if (dense) {
+    double lsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < kBigE; ++i)
-      if (j0 + i < np) sm.u.val[rpad(j0 + i)] = vr[i];
+    for (int i = 0; i < kBigE; ++i) lsum += xc(i);
+    X0 = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
   }
+  // S' of rank j0 + i, a start; X is the prefix before it (dense), vi its vertex index (sparse)
+  auto start_s = [&](int i, double X, int vi) -> double {
+    if (dense) return sprime(i, X);
+    return (k0start && i == 0) ? 0.0 : vS[vb + vi];
+  };
+  // first pass: the thread's first and last start
+  Cand mineL{-1, 0.0}, mineR{-1, 0.0};
+  {
+    double X = X0;
+    int vi = vbase;
+#pragma unroll 1
+    for (int i = 0; i < kBigE; ++i) {
+      if ((bm >> i) & 1u) {
+        const Cand cd{(int)(k0 + j0 + i), start_s(i, X, vi)};
+        if (mineR.pos < 0) mineR = cd;
+        mineL = cd;
+      }
+      if (dense) X += xc(i);
+      vi += (hb >> i) & 1u;
+    }
+  }
+  Cand lc, rc;
+  carry_exchange<kBigThreads>(mineL, mineR, false, Cand{-1, 0.0}, sm.shL, sm.shR, sm.shF, &lc, &rc);
+  if (lc.pos < 0) lc = Cand{ppos, ps};
+  // after the tile's last start: its end point when that survives (S'), else the merge's next
+  // surviving vertex (global S)
+  if (rc.pos < 0) rc = hi == hc - 1 ? Cand{(int)(k0 + np), endS} : Cand{npn, nsn};
+  // a cluster inside the tile uses S' (small numbers); a cluster reaching outside the tile uses
+  // global S formed exactly as the merge kernel forms it (S' + tile offset), so every tile it
+  // touches computes the identical value.  Candidates inside [k0, k0 + np] carry S', others S.
+  auto cval = [&](int pa, double sa, int pb, double sb) -> float {
+    const bool ina = pa >= k0 && pa <= k0 + np;
+    const bool inb = pb >= k0 && pb <= k0 + np;
+    double dS;
+    if (ina && inb) {
+      dS = sb - sa;
+    } else {
+      const double ga = ina ? (pa == k0 ? ps : sa + toff) : sa;
+      const double gb = inb ? sb + toff : sb;
+      dS = gb - ga;
+    }
+    return (float)(c + dS / (double)(pb - pa));
+  };
+  // second pass, left to right: each start closes the open cluster, whose value then goes to its
+  // ranks in this thread.  Rank i's key is read before any value lands on it; the exchange
+  // barrier passed after every other thread's reads of these keys.  (The sparse path uses the
+  // array only for the values.)
+  int pa = lc.pos, a = 0;
+  double sa = lc.s;
+  {
+    double X = X0;
+    int vi = vbase;
+#pragma unroll 1
+    for (int i = 0; i < kBigE; ++i) {
+      if ((bm >> i) & 1u) {
+        const int p = (int)(k0 + j0 + i);
+        const double si = start_s(i, X, vi);
+        if (i > a) {
+          const uint32_t v = __float_as_uint(cval(pa, sa, p, si));
+          for (int m = a; m < i; ++m) sm.kv[rpad(j0 + m)] = v;
+        }
+        pa = p;
+        sa = si;
+        a = i;
+      }
+      if (dense) X += xc(i);
+      vi += (hb >> i) & 1u;
+    }
+  }
+  if (a < nmine) {
+    const uint32_t v = __float_as_uint(cval(pa, sa, rc.pos, rc.s));
+    for (int m = a; m < nmine; ++m) sm.kv[rpad(j0 + m)] = v;
+  }
+  load_perm();
+  mark(bm);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    if (j < np) og[pl[r]] = sm.u.val[rpad(j)];
+    if (j < np) og[pl[r]] = __uint_as_float(sm.kv[rpad(j)]);
   }
   if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
 }
@@ -885,16 +960,16 @@ __device__ __forceinline__ uint32_t thread_start_bits(const uint32_t* mask, int6
   return b;
 }
 
-// One thread's kBigE consecutive cotangents (rank order) read back from the rank-padded LDS copy,
-// and their FP64 sum.  The tile and apply kernels share it, so the prefix G at a cluster start is
-// formed by the same additions in both.
-__device__ __forceinline__ double thread_cotangents(const float* lds, int j0, int nmine, float (&gk)[kBigE]) {
+// Cotangent i of one thread's kBigE consecutive ranks (rank order) from the rank-padded LDS copy.
+// The tile and apply kernels read it the same way and add in the same order, so the prefix G at a
+// cluster start is formed by the same additions in both.
+__device__ __forceinline__ double thread_cotangent(const float* lds, int j0, int nmine, int i) {
+  return i < nmine ? (double)lds[rpad(j0 + i)] : 0.0;
+}
+__device__ __forceinline__ double thread_cotangent_sum(const float* lds, int j0, int nmine) {
   double lsum = 0.0;
 #pragma unroll
-  for (int i = 0; i < kBigE; ++i) {
-    gk[i] = i < nmine ? lds[rpad(j0 + i)] : 0.0f;
-    lsum += (double)gk[i];
-  }
+  for (int i = 0; i < kBigE; ++i) lsum += thread_cotangent(lds, j0, nmine, i);
   return lsum;
 }
 
@@ -947,8 +1022,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
     }
   }
   __syncthreads();
-  float gk[kBigE];
-  const double lsum = thread_cotangents(sm.g, j0, nmine, gk);
+  const double lsum = thread_cotangent_sum(sm.g, j0, nmine);
   double total;
   const double P = block_excl_scan<kBigThreads, double>(lsum, sm.dred, &total);
   // local prefix at the thread's first and last start
@@ -964,7 +1038,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
       l = i;
       Gl = run;
     }
-    run += (double)gk[i];
+    run += thread_cotangent(sm.g, j0, nmine, i);
   }
   // the wave's first and last start, then the block's (no shared-address atomics)
   const uint64_t has = __ballot(bm != 0u);
@@ -1075,12 +1149,10 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
   float* const og = gout + seg_start;
   const int32_t* const pt = perm + k0;
   const float* const gt = gsorted + k0;
-  int32_t pl[R];
   float gl[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
     gl[r] = j < np ? gt[j] : 0.0f;
   }
   const uint32_t bm = nmine > 0 ? thread_start_bits(mask, seg_start, k0 + j0, nmine) : 0u;
@@ -1093,48 +1165,57 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
     if (j < np) sm.v[rpad(j)] = gl[r];
   }
   __syncthreads();
-  float gk[kBigE];
-  const double lsum = thread_cotangents(sm.v, j0, nmine, gk);
+  const double lsum = thread_cotangent_sum(sm.v, j0, nmine);
   const double P = block_excl_scan<kBigThreads, double>(lsum, sm.dred, (double*)nullptr);
-  // G at each of the thread's ranks, formed as the tile kernel forms it for the tile scan
-  double sv[kBigE];
-  double run = P;
+  // G at a rank = tile offset + local prefix, formed as the tile kernel forms it for the tile
+  // scan; first pass: the thread's first and last start
   Cand mineL{-1, 0.0}, mineR{-1, 0.0};
+  double run = P;
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
-    sv[i] = toff + run;
-    run += (double)gk[i];
     if ((bm >> i) & 1u) {
-      const Cand c{(int)(k0 + j0 + i), sv[i]};
+      const Cand c{(int)(k0 + j0 + i), toff + run};
       if (mineR.pos < 0) mineR = c;
       mineL = c;
     }
+    run += thread_cotangent(sm.v, j0, nmine, i);
   }
   Cand lc, rc;
   carry_exchange<kBigThreads>(mineL, mineR, false, after, sm.shL, sm.shR, sm.shF, &lc, &rc);
   if (lc.pos < 0) lc = before;
-  // backward sweep: each start's cluster ends at the next start (or rc); the ranks before the
-  // thread's first start belong to the cluster entered from lc.  Every tile a cluster touches
-  // forms its value from the same two G values and the same division.
-  float val[kBigE];
-  int npos = rc.pos;
-  double sn = rc.s;
-#pragma unroll
-  for (int i = kBigE - 1; i >= 0; --i) {
-    val[i] = 0.0f;
-    if ((bm >> i) & 1u) {
-      const int a = (int)(k0 + j0 + i);
-      val[i] = (float)div_count(sn - sv[i], npos - a);
-      npos = a;
-      sn = sv[i];
-    }
-  }
-  float cur = nmine > 0 ? (float)div_count(sn - lc.s, max(1, npos - lc.pos)) : 0.0f;
-  // the scan and exchange barriers passed after every read of the cotangents: reuse the array
+  // second pass, left to right: each start closes the open cluster, whose mean then goes to its
+  // ranks in this thread (rank i's cotangent is read before any result lands on it; the exchange
+  // barrier passed after every other thread's reads).  Every tile a cluster touches forms its
+  // mean from the same two G values and the same division.
+  int pa = lc.pos, a = 0;
+  double sa = lc.s;
+  run = P;
 #pragma unroll
   for (int i = 0; i < kBigE; ++i) {
-    if ((bm >> i) & 1u) cur = val[i];
-    if (i < nmine) sm.v[rpad(j0 + i)] = cur;
+    if ((bm >> i) & 1u) {
+      const int p = (int)(k0 + j0 + i);
+      const double gi = toff + run;
+      if (i > a) {
+        const float v = (float)div_count(gi - sa, p - pa);
+        for (int m = a; m < i; ++m) sm.v[rpad(j0 + m)] = v;
+      }
+      pa = p;
+      sa = gi;
+      a = i;
+    }
+    run += thread_cotangent(sm.v, j0, nmine, i);
+  }
+  if (a < nmine) {
+    const float v = (float)div_count(rc.s - sa, max(1, rc.pos - pa));
+    for (int m = a; m < nmine; ++m) sm.v[rpad(j0 + m)] = v;
+  }
+  // the permutation entries are needed only for the final scatter: loaded late (their latency
+  // overlaps the last barrier), so they do not hold registers through the scan and passes
+  int32_t pl[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = tid + r * kBigThreads;
+    pl[r] = j < np ? min(max(pt[j], 0), (int32_t)(d - 1)) : 0;
   }
   __syncthreads();
 #pragma unroll

@@ -117,6 +117,36 @@ def test_chain_short_segments(d):
     _check(workloads.chain(d, lam_min * 0.5), batched=True)
 
 
+def _mixed_runs(d, lam, seed):
+    """One segment whose sorted order alternates long runs of equal values (one cluster each,
+    thousands of ranks, crossing tile boundaries) with stretches of well-separated values (every
+    rank its own cluster), so tiles with few and with thousands of cluster starts neighbour each
+    other and clusters span both kinds."""
+    rng = np.random.default_rng(seed)
+    gap = 1e-4  # far above 2 lam / (d - 1) and above the FP32 spacing of the values
+    assert gap > 2.0 * lam / (d - 1)
+    vals, x = [], 0.0
+    while sum(v.shape[0] for v in vals) < d:
+        n1 = int(rng.integers(500, 12000))
+        vals.append(x + gap * np.arange(1, n1 + 1))
+        x = float(vals[-1][-1])
+        n2 = int(rng.integers(500, 12000))
+        x += 1.0
+        vals.append(np.full(n2, x))
+        x += 1.0
+    w = np.concatenate(vals)[:d].astype(np.float32)
+    rng.shuffle(w)
+    return dict(w=w, offsets=np.array([0, d], np.int64), lam=np.float32(lam), name="mixed runs")
+
+
+def test_mixed_sparse_dense_tiles():
+    for d, seed in ((300000, 3), (1 << 20, 4)):
+        case = _mixed_runs(d, 0.05, seed)
+        _, _, st = _check(case)
+        assert st["clusters"] > 1000
+        _check_backward(case)
+
+
 def test_typical_d2p24():
     _check(workloads.plain(1 << 24, 0.1, seed=1))
 
