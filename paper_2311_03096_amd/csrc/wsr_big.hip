@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
         const uint32_t dg = (k[r] >> shift) & 255u;
         const uint64_t peers = match_digit8(dg);
         const uint32_t b = wcnt[wv][dg];
-        const int nbelow = __popcll(peers & lanemask_lt());
+        const int nbelow = popc_below(peers);
         if (nbelow == 0) wcnt[wv][dg] = b + (uint32_t)__popcll(peers);
         rk[r] = (uint16_t)(b + nbelow);
       }

@@ -46,16 +46,26 @@ __device__ __forceinline__ int rpad(int k) { return k + (k >> 4); }
 constexpr int rpad_size(int n) { return n + (n >> 4) + 1; }
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
 
-// Lanes of the wave holding the same 8-bit digit (all 64 lanes must be active).
+// Lanes of the wave holding the same 8-bit digit (all 64 lanes must be active).  Per bit b the
+// lanes whose bit differs from this lane's are ballot(b) ^ B, with B = 0 or all ones from this
+// lane's bit; the peers are the lanes that differ in no bit.  Each bit costs a sign-extending bit
+// extract, a compare for the ballot and one three-input bit operation per mask half.
 __device__ __forceinline__ uint64_t match_digit8(uint32_t dg) {
-  uint64_t peers = ~0ull;
+  uint32_t dlo = 0u, dhi = 0u;  // lanes that differ in some bit so far
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const int bit = (dg >> b) & 1u;
-    const uint64_t m = __ballot(bit);
-    peers &= bit ? m : ~m;
+    const uint32_t B = (uint32_t)(-(int32_t)((dg >> b) & 1u));
+    const uint64_t m = __builtin_amdgcn_uicmp(B, 0u, 33);  // ballot(B != 0): one compare
+    dlo |= (uint32_t)m ^ B;
+    dhi |= (uint32_t)(m >> 32) ^ B;
   }
-  return peers;
+  return ~(((uint64_t)dhi << 32) | dlo);
+}
+
+// Number of set bits of m at lanes below this one (the mbcnt instructions, which take the mask
+// per lane).
+__device__ __forceinline__ int popc_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Cross-lane moves through DPP (data-parallel primitives: a VALU operand modifier, no LDS round

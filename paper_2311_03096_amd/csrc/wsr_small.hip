@@ -118,7 +118,7 @@ __device__ void block_radix_sort(FwdSmem<TMAX, NT>& sm, uint32_t (&k)[TMAX / NT]
         const uint32_t dg = (k[r] >> shift) & 255u;
         const uint64_t peers = match_digit8(dg);
         const uint32_t base = sm.c.rs.wcnt[wv][dg];
-        const int nbelow = __popcll(peers & lanemask_lt());
+        const int nbelow = popc_below(peers);
         if (nbelow == 0) sm.c.rs.wcnt[wv][dg] = base + (uint32_t)__popcll(peers);
         rk[r] = (uint16_t)(base + nbelow);
       }
