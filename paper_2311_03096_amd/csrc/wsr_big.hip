@@ -465,12 +465,18 @@ struct WaveNode {
 // First j in [1, q] with R(j) strictly below the segment Q -> R(j+1) (q when none): the
 // rightmost collision of the point Q inside R.  Called by all 64 lanes with uniform arguments;
 // probes run 64 at a time: one exponential round (lane l probes 2^l), then 64-way refinement.
-__device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs) {
+// The point R(j) comes back in (*rp, *rs): the lane whose probe decided j has already read it.
+__device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs, int* rp, double* rs) {
   const int lane = lane_id();
+  int pj = 0;
+  double sj = 0.0;
   auto f = [&](int j) -> bool {
-    if (j >= q) return true;
-    int pj, pj1;
-    double sj, sj1;
+    if (j >= q) {
+      R.fetch(q, &pj, &sj);
+      return true;
+    }
+    int pj1;
+    double sj1;
     R.fetch2(j, &pj, &sj, &pj1, &sj1);
     return below(qa, qs, pj, sj, pj1, sj1);
   };
@@ -479,6 +485,8 @@ __device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs) {
   const int ft = __ffsll((unsigned long long)b) - 1;
   int hi = __shfl(j, ft, kWave);
   int lo = ft == 0 ? 0 : __shfl(j, ft - 1, kWave);
+  int hp = __shfl(pj, ft, kWave);
+  double hs = __shfl(sj, ft, kWave);
   while (hi - lo > 1) {
     const int span = hi - lo - 1;  // candidates lo+1 .. hi-1
     const int stride = (span + kWave - 1) / kWave;
@@ -491,10 +499,14 @@ __device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs) {
     } else {
       const int f2 = __ffsll((unsigned long long)bb) - 1;
       const int nhi = __shfl(jj, f2, kWave);
+      hp = __shfl(pj, f2, kWave);
+      hs = __shfl(sj, f2, kWave);
       lo = f2 == 0 ? lo : __shfl(jj, f2 - 1, kWave);
       hi = nhi;
     }
   }
+  *rp = hp;
+  *rs = hs;
   return hi;
 }
 
@@ -512,6 +524,35 @@ __device__ void wave_bridge(const WaveNode& L, int p, const WaveNode& R, int q, 
     return;
   }
   const int lane = lane_id();
+  // L(i) and L(i+1), one fetch round (lanes 0 and 1)
+  auto fetch_left = [&](int i, int* li, double* si, int* ln, double* sn) {
+    int pv = 0;
+    double sv = 0.0;
+    if (lane == 0)
+      L.fetch(i, &pv, &sv);
+    else if (lane == 1)
+      L.fetch(i + 1, &pv, &sv);
+    *li = __shfl(pv, 0, kWave);
+    *ln = __shfl(pv, 1, kWave);
+    *si = __shfl(sv, 0, kWave);
+    *sn = __shfl(sv, 1, kWave);
+  };
+  // does L(i) collide inside R (L(i+1) not below L(i) -> its tangent point in R)?
+  auto g_at = [&](int li, double si, int ln, double sn, int* jout) -> bool {
+    int rp;
+    double rs;
+    const int j = wave_tangent(R, q, li, si, &rp, &rs);
+    *jout = j;
+    return !below(li, si, ln, sn, rp, rs);
+  };
+  auto g = [&](int i, int* jout) -> bool {
+    int li, ln;
+    double si, sn;
+    fetch_left(i, &li, &si, &ln, &sn);
+    return g_at(li, si, ln, sn, jout);
+  };
+  int lp1, lp;
+  double sp1, sp;
   {
     int pv = 0;
     double sv = 0.0;
@@ -521,34 +562,20 @@ __device__ void wave_bridge(const WaveNode& L, int p, const WaveNode& R, int q, 
       L.fetch(p, &pv, &sv);
     else if (lane == 2)
       R.fetch(1, &pv, &sv);
-    const int a0 = __shfl(pv, 0, kWave), a1 = __shfl(pv, 1, kWave), a2 = __shfl(pv, 2, kWave);
-    const double b0 = __shfl(sv, 0, kWave), b1 = __shfl(sv, 1, kWave), b2 = __shfl(sv, 2, kWave);
-    if (below(a0, b0, a1, b1, a2, b2)) {  // junction survives
+    lp1 = __shfl(pv, 0, kWave);
+    lp = __shfl(pv, 1, kWave);
+    const int a2 = __shfl(pv, 2, kWave);
+    sp1 = __shfl(sv, 0, kWave);
+    sp = __shfl(sv, 1, kWave);
+    const double b2 = __shfl(sv, 2, kWave);
+    if (below(lp1, sp1, lp, sp, a2, b2)) {  // junction survives
       *istar = p;
       *jstar = 1;
       return;
     }
   }
-  auto g = [&](int i, int* jout) -> bool {
-    int pv = 0;
-    double sv = 0.0;
-    if (lane == 0)
-      L.fetch(i, &pv, &sv);
-    else if (lane == 1)
-      L.fetch(i + 1, &pv, &sv);
-    const int li = __shfl(pv, 0, kWave), ln = __shfl(pv, 1, kWave);
-    const double si = __shfl(sv, 0, kWave), sn = __shfl(sv, 1, kWave);
-    const int j = wave_tangent(R, q, li, si);
-    int rp = 0;
-    double rs = 0.0;
-    if (lane == 0) R.fetch(j, &rp, &rs);
-    rp = __shfl(rp, 0, kWave);
-    rs = __shfl(rs, 0, kWave);
-    *jout = j;
-    return !below(li, si, ln, sn, rp, rs);
-  };
   int jhi = 1;
-  if (!g(p - 1, &jhi)) {  // only reachable through rounding: keep the junction
+  if (!g_at(lp1, sp1, lp, sp, &jhi)) {  // only reachable through rounding: keep the junction
     *istar = p;
     *jstar = 1;
     return;
