@@ -242,8 +242,17 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, lam_arr, seg_id,
                      lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum, b.hbits); }
   { WSR_TRACE("big_tile_scan", s);
-  hipLaunchKernelGGL(k_big_tile_scan, dim3(1), dim3(1024), 0, s, b.tsum, b.tileoff, b.hcnt, b.lo, b.hi, nt, d,
-                     lam_arr, seg_id, lam_scalar); }
+#define WSR_LAUNCH_TILE_SCAN(CM)                                                                         \
+  hipLaunchKernelGGL(k_big_tile_scan<CM>, dim3(1), dim3(1024), 0, s, b.tsum, b.tileoff, b.hcnt, b.lo, b.hi, nt, \
+                     d, lam_arr, seg_id, lam_scalar)
+  if (nt <= 4 * 1024)
+    WSR_LAUNCH_TILE_SCAN(4);
+  else if (nt <= 8 * 1024)
+    WSR_LAUNCH_TILE_SCAN(8);
+  else
+    WSR_LAUNCH_TILE_SCAN(16);
+#undef WSR_LAUNCH_TILE_SCAN
+  }
   int nlev = 0;
   while ((1 << nlev) < nt) ++nlev;
   int lvl_lo = 1;
@@ -284,8 +293,17 @@ int big_backward(const float* g, float* gw, int64_t start, int64_t d, const int3
   hipLaunchKernelGGL(k_big_bwd_tile, dim3(nt), dim3(kBigThreads), 0, s, g, perm + start, mask, d, start,
                      gsorted, b.tsum, b.fpos, b.fG, b.lpos, b.lG); }
   { WSR_TRACE("big_bwd_scan", s);
-  hipLaunchKernelGGL(k_big_bwd_scan, dim3(1), dim3(1024), 0, s, b.tsum, b.fpos, b.fG, b.lpos, b.lG, nt, d,
-                     b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG); }
+#define WSR_LAUNCH_BWD_SCAN(CM)                                                                          \
+  hipLaunchKernelGGL(k_big_bwd_scan<CM>, dim3(1), dim3(1024), 0, s, b.tsum, b.fpos, b.fG, b.lpos, b.lG, nt, d, \
+                     b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG)
+  if (nt <= 4 * 1024)
+    WSR_LAUNCH_BWD_SCAN(4);
+  else if (nt <= 8 * 1024)
+    WSR_LAUNCH_BWD_SCAN(8);
+  else
+    WSR_LAUNCH_BWD_SCAN(16);
+#undef WSR_LAUNCH_BWD_SCAN
+  }
   { WSR_TRACE("big_bwd_apply", s);
   hipLaunchKernelGGL(k_big_bwd_apply, dim3(nt), dim3(kBigThreads), 0, s, gsorted, perm + start, mask, d,
                      start, b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG, gw); }

@@ -21,6 +21,7 @@ constexpr int kMergeGroupMax = 1 << 14;                         // tiles of the 
 constexpr int kMergeRecMax = 1 << (kMergeLevelsPerLaunch - 1);  // merges at a launch's first level
 static_assert((int64_t)kMergeGroupMax * kBigTile >= ((int64_t)1 << 26), "top merge group too small");
 static_assert(kRadixThreads == 256, "one histogram bin per thread");
+static_assert(kMergeGroupMax / 1024 <= 16, "tile scans hold at most 16 tiles per thread");
 static_assert(kScatterThreads >= 256, "digit scan assumes one digit per thread");
 
 __global__ void k_radix_hist(const float* wsrc, const uint32_t* ksrc, int64_t n, int shift,
@@ -32,6 +33,7 @@ __global__ void k_radix_scatter(const float* wsrc, const uint32_t* ksrc, const i
 __global__ void k_big_tile_hull(const uint32_t* skeys, int64_t d, const float* lam_arr, int seg_id,
                                 float lam_scalar, int32_t* vpos, double* vS, int32_t* hcnt,
                                 double* tsum, uint16_t* hbits);
+template <int CM>
 __global__ void k_big_tile_scan(const double* tsum, double* tileoff, const int32_t* hcnt,
                                 int32_t* lo, int32_t* hi, int ntiles, int64_t d,
                                 const float* lam_arr, int seg_id, float lam_scalar);
@@ -51,6 +53,7 @@ __global__ void k_big_apply(const uint32_t* skeys, const int32_t* perm, int64_t 
 __global__ void k_big_bwd_tile(const float* g, const int32_t* perm, const uint32_t* mask,
                                int64_t d, int64_t seg_start, float* gsorted, double* tsum,
                                int32_t* fpos, double* fG, int32_t* lpos, double* lG);
+template <int CM>
 __global__ void k_big_bwd_scan(const double* tsum, const int32_t* fpos, const double* fG,
                                const int32_t* lpos, const double* lG, int ntiles, int64_t d,
                                double* tileoff, int32_t* prevp, double* prevG, int32_t* nextp,

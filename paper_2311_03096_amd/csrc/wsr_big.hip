@@ -34,7 +34,9 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
   constexpr int NW = kRadixThreads / kWave;
   constexpr int kHistLanes = 16;
   constexpr int kSub = kWave / kHistLanes;  // sub-histograms per wave
-  __shared__ uint32_t h[NW * kSub][256];
+  // one pad word per sub-histogram: the same digit in different lane groups falls on different
+  // LDS banks
+  __shared__ uint32_t h[NW * kSub][257];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
@@ -379,25 +381,43 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
 
 // Tile offsets S_{k0} = (exclusive scan of tile sums of x - c) + lam k0 (d-k0)/(d-1), and the
 // initial own ranges [1, hcnt-1].
-__global__ __launch_bounds__(1024) void k_big_tile_scan(const double* tsum, double* tileoff,
-                                                        const int32_t* hcnt, int32_t* lo, int32_t* hi,
+template <int CM>
+__global__ __launch_bounds__(1024) void k_big_tile_scan(const double* __restrict__ tsum,
+                                                        double* __restrict__ tileoff,
+                                                        const int32_t* __restrict__ hcnt,
+                                                        int32_t* __restrict__ lo, int32_t* __restrict__ hi,
                                                         int ntiles, int64_t d, const float* lam_arr,
                                                         int seg_id, float lam_scalar) {
+  // CM >= tiles per thread (ceil(ntiles / 1024)), chosen by the host
   const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
   const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
   __shared__ double sh[1024 / kWave + 1];
   const int chunk = (ntiles + 1023) / 1024;
   const int a = threadIdx.x * chunk;
-  const int b = min(a + chunk, ntiles);
+  // every load of the thread's chunk first (one round trip), then the scan
+  double ts[CM];
+  int hc[CM];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) {
+    const int i = a + c;
+    const bool ok = c < chunk && i < ntiles;
+    ts[c] = ok ? tsum[i] : 0.0;
+    hc[c] = ok ? hcnt[i] : 0;
+  }
   double s = 0.0;
-  for (int i = a; i < b; ++i) s += tsum[i];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) s += ts[c];
   double run = block_excl_scan<1024, double>(s, sh, (double*)nullptr);
-  for (int i = a; i < b; ++i) {
-    const double k0 = (double)i * (double)kBigTile;
-    tileoff[i] = run + lamd * k0 * ((double)d - k0);
-    run += tsum[i];
-    lo[i] = 1;
-    hi[i] = hcnt[i] - 1;
+#pragma unroll
+  for (int c = 0; c < CM; ++c) {
+    const int i = a + c;
+    if (c < chunk && i < ntiles) {
+      const double k0 = (double)i * (double)kBigTile;
+      tileoff[i] = run + lamd * k0 * ((double)d - k0);
+      run += ts[c];
+      lo[i] = 1;
+      hi[i] = hc[c] - 1;
+    }
   }
 }
 
@@ -1109,44 +1129,85 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
 // One workgroup: tile offsets of G, and for every tile the last cluster start before it and the
 // first cluster start after its last local start (with global G values).  The carries are
 // "last valid" / "first valid" scans over per-thread chunk summaries (wave shuffles + LDS).
-__global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* tsum, const int32_t* fpos,
-                                                       const double* fG, const int32_t* lpos,
-                                                       const double* lG, int ntiles, int64_t d,
-                                                       double* tileoff, int32_t* prevp, double* prevG,
-                                                       int32_t* nextp, double* nextG) {
+template <int CM>
+__global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* __restrict__ tsum,
+                                                       const int32_t* __restrict__ fpos,
+                                                       const double* __restrict__ fG,
+                                                       const int32_t* __restrict__ lpos,
+                                                       const double* __restrict__ lG, int ntiles, int64_t d,
+                                                       double* __restrict__ tileoff, int32_t* __restrict__ prevp,
+                                                       double* __restrict__ prevG, int32_t* __restrict__ nextp,
+                                                       double* __restrict__ nextG) {
+  // CM >= tiles per thread (ceil(ntiles / 1024)), chosen by the host
   __shared__ double sh[1024 / kWave + 1];
   __shared__ Cand shL[1024 / kWave], shR[1024 / kWave];
   __shared__ int shF[1024 / kWave];
   const int tid = threadIdx.x;
   const int chunk = (ntiles + 1023) / 1024;
   const int a = tid * chunk;
-  const int b = min(a + chunk, ntiles);
+  // every load of the thread's chunk first (one round trip), then scan and walks
+  double ts[CM], lg[CM], fg[CM];
+  int lp[CM], fp[CM];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) {
+    const int i = a + c;
+    const bool ok = c < chunk && i < ntiles;
+    ts[c] = ok ? tsum[i] : 0.0;
+    lp[c] = ok ? lpos[i] : -1;
+    fp[c] = ok ? fpos[i] : -1;
+    lg[c] = ok ? lG[i] : 0.0;
+    fg[c] = ok ? fG[i] : 0.0;
+  }
   double s = 0.0;
-  for (int i = a; i < b; ++i) s += tsum[i];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) s += ts[c];
   double total;
   double run = block_excl_scan<1024, double>(s, sh, &total);
   Cand mineL{-1, 0.0}, mineR{-1, 0.0};
-  for (int i = a; i < b; ++i) {
-    tileoff[i] = run;
-    if (lpos[i] >= 0) mineL = Cand{lpos[i], run + lG[i]};
-    if (fpos[i] >= 0 && mineR.pos < 0) mineR = Cand{fpos[i], run + fG[i]};
-    run += tsum[i];
+  const double run0 = run;
+#pragma unroll
+  for (int c = 0; c < CM; ++c) {
+    if (c < chunk && a + c < ntiles) tileoff[a + c] = run;
+    if (lp[c] >= 0) mineL = Cand{lp[c], run + lg[c]};
+    if (fp[c] >= 0 && mineR.pos < 0) mineR = Cand{fp[c], run + fg[c]};
+    run += ts[c];
   }
   Cand lc, rc;
   carry_exchange<1024>(mineL, mineR, false, Cand{(int)d, total}, shL, shR, shF, &lc, &rc);
   if (lc.pos < 0) lc = Cand{0, 0.0};  // rank 0 always starts a cluster
-  // walk the chunk: previous start before each tile, next start after each tile
-  for (int i = a; i < b; ++i) {
-    prevp[i] = lc.pos;
-    prevG[i] = lc.s;
-    if (lpos[i] >= 0) lc = Cand{lpos[i], tileoff[i] + lG[i]};
+  // walk the chunk: previous start before each tile, next start after each tile (the tile
+  // offsets are formed again by the same additions, not held)
+  run = run0;
+  Cand firsts[CM];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) {
+    if (c < chunk && a + c < ntiles) {
+      prevp[a + c] = lc.pos;
+      prevG[a + c] = lc.s;
+    }
+    if (lp[c] >= 0) lc = Cand{lp[c], run + lg[c]};
+    firsts[c] = Cand{fp[c], run + fg[c]};
+    run += ts[c];
   }
-  for (int i = b - 1; i >= a; --i) {
-    nextp[i] = rc.pos;
-    nextG[i] = rc.s;
-    if (fpos[i] >= 0) rc = Cand{fpos[i], tileoff[i] + fG[i]};
+#pragma unroll
+  for (int c = CM - 1; c >= 0; --c) {
+    if (c < chunk && a + c < ntiles) {
+      nextp[a + c] = rc.pos;
+      nextG[a + c] = rc.s;
+    }
+    if (firsts[c].pos >= 0) rc = firsts[c];
   }
 }
+
+#define WSR_INSTANTIATE_SCANS(CM)                                                                   \
+  template __global__ void k_big_tile_scan<CM>(const double*, double*, const int32_t*, int32_t*,      \
+                                               int32_t*, int, int64_t, const float*, int, float);     \
+  template __global__ void k_big_bwd_scan<CM>(const double*, const int32_t*, const double*,          \
+                                              const int32_t*, const double*, int, int64_t, double*,  \
+                                              int32_t*, double*, int32_t*, double*);
+WSR_INSTANTIATE_SCANS(4)
+WSR_INSTANTIATE_SCANS(8)
+WSR_INSTANTIATE_SCANS(16)
 
 struct BwdApplySmem {
   float v[rpad_size(kBigTile)];  // cotangent in rank order, then the results (rank-padded)

@@ -251,6 +251,22 @@ def test_backward_uneven_and_big():
     _check_backward(workloads.random_segments([1 << 20], "normal", 0.1, seed=12), batched=True)
 
 
+def test_backward_many_tiles():
+    """More than 8192 rank tiles in one segment (the widest tile-scan variant); clusters are
+    FP32 tie groups spanning many tiles.  Checked against the oracle VJP on the GPU's own
+    partition."""
+    d = (1 << 25) + 12345
+    case = workloads.precision(d, 1e-4, seed=3)
+    g = np.random.default_rng(4).standard_normal(d).astype(np.float32)
+    fw = gpu_forward(case["w"], case["offsets"], case["lam"])
+    _say("many tiles: clusters", int(fw["start"].sum()))
+    gw = gpu_backward(g, case["offsets"], fw["perm"], fw["start"])
+    ref = oracle.vjp(g.astype(np.float64), fw["perm"], fw["start"], case["offsets"])
+    err = np.abs(gw - ref)
+    _say("  max err vs oracle VJP (same partition)", float(err.max()))
+    assert np.all(err <= 1e-6 * (1 + np.abs(ref)))
+
+
 def test_backward_chain_one_cluster():
     case = workloads.chain(1 << 22, 0.7)
     g = np.random.default_rng(2).standard_normal(1 << 22).astype(np.float32)
