@@ -55,14 +55,21 @@ struct FwdSmem {
     uint16_t tidx[TMAX];  // bucket sort: indices in bucket order
   } d;
   uint32_t lmask[TMAX / 32 + 2];
-  long long lred[NW + 1];
+  union {
+    long long lred[NW + 1];  // bucket sort: counter scan
+    double dred[NW + 1];     // prefix sums (barriers separate the two scans)
+  } sc;
   int tiecnt;  // bucket sort: sum over keys of the smaller keys in their bucket
-  double dred[NW + 1];
   int ired[NW + 1];
   uint32_t ured[2 * NW];
   WaveBound wb[2 * NW];  // collision exchange slots, two sets
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
+
+// LDS is allocated in 512-byte granules: three 4096-key forward workgroups share a CU (160 KB)
+// only while the rounded size stays at or below a third of it.
+static_assert(3 * ((sizeof(FwdSmem<4096, 512>) + 511) / 512 * 512) <= 160 * 1024,
+              "three 4096-key forward workgroups per CU");
 
 struct SegView {
   int64_t start;
@@ -288,7 +295,7 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   cmax = (int)wave_max_u32((uint32_t)cmax);
   long long tot2;
   const long long run2 =
-      block_excl_scan<NT, long long, false>((long long)sum | ((long long)pairs << 32), sm.lred, &tot2);
+      block_excl_scan<NT, long long, false>((long long)sum | ((long long)pairs << 32), sm.sc.lred, &tot2);
   int run = (int)(run2 & 0xFFFFFFFFll);
   const int total = (int)(tot2 & 0xFFFFFFFFll);
   const int pairs_total = (int)(tot2 >> 32);
@@ -490,7 +497,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     xs[i] = k0 + i < d ? (double)key_to_float(kv[i]) - c : 0.0;
     lsum += xs[i];
   }
-  double Xk = block_excl_scan<NT, double, false>(lsum, sm.dred, (double*)nullptr);
+  double Xk = block_excl_scan<NT, double, false>(lsum, sm.sc.dred, (double*)nullptr);
   double sv[E + 1];
 #pragma unroll
   for (int i = 0; i <= E; ++i) {
