@@ -174,8 +174,8 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
   __shared__ uint32_t skey[kRadixTile];
   __shared__ int32_t sval[kRadixTile];
   __shared__ uint32_t wcnt[NW][256];
-  __shared__ uint32_t tstart[256];
-  __shared__ uint32_t gofs[256];
+  __shared__ int delta[256];  // per digit: global position of the tile's first key of the digit
+                              // minus its position in the tile
   __shared__ int ish[NW + 1];
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -226,9 +226,8 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
     const int dstart = block_excl_scan<kScatterThreads, int>((int)run, ish, &tot);
     if (owner) {
       for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
-      tstart[tid] = (uint32_t)dstart;
       // global base of this digit = all smaller digits + this digit in the tiles before this one
-      gofs[tid] = (uint32_t)rowbase + tile_pre;
+      delta[tid] = rowbase + (int)tile_pre - dstart;
     }
     __syncthreads();
 #pragma unroll
@@ -241,13 +240,30 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
       }
     }
     __syncthreads();
-    for (int s = tid; s < nt; s += kScatterThreads) {
-      const uint32_t key = skey[s];
-      const uint32_t dg = (key >> shift) & 255u;
-      const int64_t dst = (int64_t)gofs[dg] + (s - (int)tstart[dg]);
-      if (dst >= 0 && dst < n) {  // always true for consistent histograms; guards the scatter
-        kdst[dst] = key;
-        vdst[dst] = sval[s];
+    // write-out by digit runs, four ranks of the thread at a time (their LDS reads issued
+    // together); 32-bit byte offsets (n <= 2^26) from the uniform array bases
+    constexpr int WB = 4;
+    static_assert(IPT % WB == 0, "write-out batches");
+#pragma unroll 1
+    for (int h = 0; h < IPT; h += WB) {
+      uint32_t ko[WB], dso[WB];
+      int32_t vo[WB];
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        const int sp = tid + (h + q) * kScatterThreads;
+        ko[q] = skey[sp];
+        vo[q] = sval[sp];
+      }
+#pragma unroll
+      for (int q = 0; q < WB; ++q)
+        dso[q] = (uint32_t)(delta[(ko[q] >> shift) & 255u] + tid + (h + q) * kScatterThreads);
+#pragma unroll
+      for (int q = 0; q < WB; ++q) {
+        // dso < n always holds for consistent histograms; it guards the scatter
+        if (tid + (h + q) * kScatterThreads < nt && dso[q] < (uint32_t)n) {
+          *at_u32(kdst, dso[q]) = ko[q];
+          *at_u32(vdst, dso[q]) = vo[q];
+        }
       }
     }
     __syncthreads();  // LDS is reused by the next tile
@@ -848,7 +864,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = tid + r * kBigThreads;
-      if (j < np) og[pl[r]] = nonfinite ? __builtin_nanf("") : key_to_float(kt[j]);
+      if (j < np) *at_u32(og, (uint32_t)pl[r]) = nonfinite ? __builtin_nanf("") : key_to_float(kt[j]);
     }
     mark(nmine > 0 ? (1u << nmine) - 1u : 0u);
     __syncthreads();
@@ -986,7 +1002,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    if (j < np) og[pl[r]] = __uint_as_float(sm.kv[rpad(j)]);
+    if (j < np) *at_u32(og, (uint32_t)pl[r]) = __uint_as_float(sm.kv[rpad(j)]);
   }
   if (mask_out) store_mask_words<kBigThreads>(mask_out, seg_start + k0, np, sm.lmask);
 }
@@ -1059,7 +1075,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
   const uint32_t bm = nmine > 0 ? thread_start_bits(mask, seg_start, k0 + j0, nmine) : 0u;
   float gv[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) gv[r] = gs[pl[r]];
+  for (int r = 0; r < R; ++r) gv[r] = *at_u32(gs, (uint32_t)pl[r]);
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
@@ -1309,7 +1325,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int j = tid + r * kBigThreads;
-    if (j < np) og[pl[r]] = sm.v[rpad(j)];
+    if (j < np) *at_u32(og, (uint32_t)pl[r]) = sm.v[rpad(j)];
   }
 }
 

@@ -62,6 +62,17 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t dg) {
   return ~(((uint64_t)dhi << 32) | dlo);
 }
 
+// base + i for an index below 2^30 / sizeof(T), formed as a 32-bit byte offset so a uniform base
+// stays in scalar registers (one vector address register, no 64-bit vector arithmetic).
+template <typename T>
+__device__ __forceinline__ T* at_u32(T* base, uint32_t i) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T* at_u32(const T* base, uint32_t i) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+}
+
 // Number of set bits of m at lanes below this one (the mbcnt instructions, which take the mask
 // per lane).
 __device__ __forceinline__ int popc_below(uint64_t m) {
