@@ -471,23 +471,43 @@ __device__ __forceinline__ void node_vertex(const MergeCtx& C, int t0, int t1, i
   *idx = C.lo16[lo] + (mm - C.pre[lo]);
 }
 
-// Wave-cooperative access to a node's chain: any lane may fetch any vertex.
+// Wave-cooperative access to a node's chain: any lane may fetch any vertex.  Chain indices
+// [wlo, whi] are also held in an LDS window (loaded once per merge, the vertices next to the
+// junction, where most bridge probes land); other indices come from global memory.
 struct WaveNode {
   const MergeCtx* C;
   int t0, t1;
+  const int* wp = nullptr;
+  const double* ws = nullptr;
+  int wlo = 0, whi = -1;
   __device__ __forceinline__ void load(int tile, int idx, int* p, double* s) const {
     const int g = C->gbase + tile;
     const int64_t at = (int64_t)g * (kBigTile + 1) + idx;
     *p = C->vpos[at];
     *s = C->vS[at] + C->tileoff[g];
   }
-  __device__ __forceinline__ void fetch(int m, int* p, double* s) const {
+  __device__ __forceinline__ void fetch_global(int m, int* p, double* s) const {
     int tile, idx;
     node_vertex(*C, t0, t1, m, &tile, &idx);
     load(tile, idx, p, s);
   }
-  // vertices m and m+1 with one search when m+1 is the next vertex of the same tile
+  __device__ __forceinline__ void fetch(int m, int* p, double* s) const {
+    if (m >= wlo && m <= whi) {
+      *p = wp[m - wlo];
+      *s = ws[m - wlo];
+    } else {
+      fetch_global(m, p, s);
+    }
+  }
+  // vertices m and m+1 (window, or one search when m+1 is the next vertex of the same tile)
   __device__ __forceinline__ void fetch2(int m, int* p0, double* s0, int* p1, double* s1) const {
+    if (m >= wlo && m + 1 <= whi) {
+      *p0 = wp[m - wlo];
+      *s0 = ws[m - wlo];
+      *p1 = wp[m + 1 - wlo];
+      *s1 = ws[m + 1 - wlo];
+      return;
+    }
     int tile, idx;
     node_vertex(*C, t0, t1, m, &tile, &idx);
     const bool same = m > 0 && idx + 1 < (int)C->lo16[tile] + (C->pre[tile + 1] - C->pre[tile]);
@@ -516,11 +536,27 @@ __device__ int wave_tangent(const WaveNode& R, int q, int qa, double qs, int* rp
     R.fetch2(j, &pj, &sj, &pj1, &sj1);
     return below(qa, qs, pj, sj, pj1, sj1);
   };
-  const int j = lane < 30 ? min(1 << lane, q) : q;
+  int lo = 0;
+  // the probes R's window can answer first: j = 1 + lane for j <= J (f(j) reads R(j) and
+  // R(j+1), f(q) only R(q)); one LDS round instead of a global one when the tangent is near
+  const int J = q <= R.whi ? q : R.whi - 1;
+  if (R.wlo == 0 && J >= 1) {
+    const int jw = 1 + lane;
+    const bool tw = jw <= J && f(jw);
+    const uint64_t bw = __ballot(tw);
+    if (bw) {
+      const int fw = __ffsll((unsigned long long)bw) - 1;
+      *rp = __shfl(pj, fw, kWave);
+      *rs = __shfl(sj, fw, kWave);
+      return __shfl(jw, fw, kWave);
+    }
+    lo = min(J, kWave);  // every j <= J is false (J < q here)
+  }
+  const int j = lane < 30 ? min(lo + (1 << lane), q) : q;
   const uint64_t b = __ballot(f(j));  // lane 63 probes q, so b != 0
   const int ft = __ffsll((unsigned long long)b) - 1;
   int hi = __shfl(j, ft, kWave);
-  int lo = ft == 0 ? 0 : __shfl(j, ft - 1, kWave);
+  lo = ft == 0 ? lo : __shfl(j, ft - 1, kWave);
   int hp = __shfl(pj, ft, kWave);
   double hs = __shfl(sj, ft, kWave);
   while (hi - lo > 1) {
@@ -660,6 +696,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   __shared__ uint16_t lo16[GMAX];
   __shared__ uint16_t cnt16[GMAX];
   __shared__ int ish[NWV + 1];
+  __shared__ int win_p[NWV][2][kWave];  // per wave: the junction windows of L and R
+  __shared__ double win_s[NWV][2][kWave];
   const int G = 1 << lvl_hi;
   const int gbase = blockIdx.x * G;
   const int gn = min(G, ntiles - gbase);
@@ -703,10 +741,34 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
       const int t1 = min(t0 + size, gn);
       int r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
       if (tm < gn) {
-        WaveNode L{&C, t0, tm};
-        WaveNode R{&C, tm, t1};
         const int p = pre[tm] - pre[t0];  // left chain: end point + own vertices; last index p
         const int q = pre[t1] - pre[tm];
+        // the 64 vertices of each chain nearest the junction, one fetch round for the wave
+        const int wlo = max(0, p - (kWave - 1));
+        const int rhi = min(q, kWave - 1);
+        {
+          WaveNode Lg{&C, t0, tm};
+          WaveNode Rg{&C, tm, t1};
+          int vp;
+          double vs;
+          if (wlo + lane <= p) {
+            Lg.fetch_global(wlo + lane, &vp, &vs);
+            win_p[wv][0][lane] = vp;
+            win_s[wv][0][lane] = vs;
+          }
+          if (lane <= rhi) {
+            Rg.fetch_global(lane, &vp, &vs);
+            win_p[wv][1][lane] = vp;
+            win_s[wv][1][lane] = vs;
+          }
+        }
+        // the wave reads its own window writes (LDS is in order within a wave; this keeps the
+        // compiler from moving the reads above the writes)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        WaveNode L{&C, t0, tm, win_p[wv][0], win_s[wv][0], wlo, p};
+        WaveNode R{&C, tm, t1, win_p[wv][1], win_s[wv][1], 0, rhi};
         int istar, jstar;
         wave_bridge(L, p, R, q, &istar, &jstar);
         if (!(istar == p && jstar == 1)) {
