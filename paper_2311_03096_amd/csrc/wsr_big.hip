@@ -48,10 +48,15 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
     const int64_t base = (int64_t)tile * kRadixTile;
     const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
     const uint32_t* st = src + base;
+    if (nt == (uint32_t)kRadixTile) {  // full tile: no bounds checks
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
-      w[r] = p < nt ? st[p] : 0u;
+      for (int r = 0; r < IPT; ++r) w[r] = st[r * kRadixThreads + tid];
+    } else {
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+        w[r] = p < nt ? st[p] : 0u;
+      }
     }
   };
   int bad = 0;
@@ -74,19 +79,12 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
         bad |= in && !isfinite(f);
         key = float_to_key(f);
       }
-      const uint32_t dg = (key >> shift) & 255u;
-      // a wave whose lanes all hold the same digit (long runs in sorted or clustered data) adds
-      // once instead of 64 serialised atomics on one LDS address (the active mask is taken
-      // before the leader branch, where only one lane is active); otherwise each group of
-      // kHistLanes lanes counts into its own sub-histogram, so a skewed digit (the top byte of
-      // most inputs) puts at most kHistLanes lanes on one address
-      const unsigned long long act = __ballot(in);
-      const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
-      if (act == ~0ull && __ballot(dg == d0) == act) {
-        if (lane == 0) atomicAdd(&h[wv * kSub][d0], (uint32_t)kWave);
-      } else if (in) {
-        atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
-      }
+      // each group of kHistLanes lanes counts into its own sub-histogram, so a skewed digit
+      // (the top byte of most inputs, long runs in sorted data) puts at most kHistLanes lanes on
+      // one address; keys past the end of the segment count into the pad word (never read).
+      // No branch per key.
+      const uint32_t dg = in ? (key >> shift) & 255u : 256u;
+      atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
     }
     __syncthreads();
     for (int j = tid; j < 256; j += kRadixThreads) {
