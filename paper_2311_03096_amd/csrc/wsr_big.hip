@@ -130,20 +130,23 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntile
 }
 
 // Items of one tile in wave-striped order (p = wave*64*IPT + r*64 + lane); keys past the end
-// of the segment are 0xFFFFFFFF (they sort last and are never written).
+// of the segment are 0xFFFFFFFF (they sort last and are never written).  From FP32 weights the
+// raw bits are loaded (past the end: 0x7FFFFFFF, whose key is 0xFFFFFFFF) and made keys by
+// radix_raw_to_key when the tile is used, so a prefetch does not wait for its loads.
 template <int IPT>
 __device__ __forceinline__ void radix_load_tile(const float* wsrc, const uint32_t* ksrc, const int32_t* vsrc,
                                                 int64_t n, int tile, uint32_t (&k)[IPT], int32_t (&v)[IPT]) {
   const uint32_t p0 = (threadIdx.x / kWave) * kWave * IPT + lane_id();
   const int64_t base = (int64_t)tile * kRadixTile;
   const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
+  const bool full = nt == (uint32_t)kRadixTile;
   // tile base pointers are uniform; per-item offsets are 32-bit
   if (wsrc) {
-    const float* wt = wsrc + base;
+    const uint32_t* wt = reinterpret_cast<const uint32_t*>(wsrc) + base;
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       const uint32_t p = p0 + r * kWave;
-      k[r] = p < nt ? float_to_key(wt[p]) : 0xFFFFFFFFu;
+      k[r] = (full || p < nt) ? wt[p] : 0x7FFFFFFFu;
       v[r] = (int32_t)(base + p);
     }
   } else {
@@ -152,9 +155,17 @@ __device__ __forceinline__ void radix_load_tile(const float* wsrc, const uint32_
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       const uint32_t p = p0 + r * kWave;
-      k[r] = p < nt ? kt[p] : 0xFFFFFFFFu;
-      v[r] = p < nt ? vt[p] : 0;
+      k[r] = (full || p < nt) ? kt[p] : 0xFFFFFFFFu;
+      v[r] = (full || p < nt) ? vt[p] : 0;
     }
+  }
+}
+
+template <int IPT>
+__device__ __forceinline__ void radix_raw_to_key(const float* wsrc, uint32_t (&k)[IPT]) {
+  if (wsrc) {
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) k[r] = float_to_key(__uint_as_float(k[r]));
   }
 }
 
@@ -186,7 +197,10 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
   uint32_t k[IPT];
   int32_t v[IPT];
   int tile = blockIdx.x;
-  if (tile < ntiles) radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, tile, k, v);
+  if (tile < ntiles) {
+    radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, tile, k, v);
+    radix_raw_to_key<IPT>(wsrc, k);
+  }
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t base = (int64_t)tile * kRadixTile;
     const int nt = (int)min((int64_t)kRadixTile, n - base);
@@ -270,6 +284,7 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
       k[r] = kn[r];
       v[r] = vn[r];
     }
+    radix_raw_to_key<IPT>(wsrc, k);
   }
 }
 
