@@ -60,6 +60,7 @@ int validate_offsets(const int64_t* h_offsets, int64_t n_seg, int64_t* max_big) 
 // Workspace of the long-segment path for segments of length <= d.
 struct BigWs {
   uint32_t* flags;
+  uint32_t* tbad;  // per radix tile: non-finite weight seen (first pass)
   uint32_t *keysA, *keysB;
   int32_t *valsA, *valsB;
   uint32_t *hist, *totals;
@@ -85,6 +86,7 @@ BigWs big_layout(int64_t d, void* base) {
     return p;
   };
   w.flags = (uint32_t*)take(256);
+  w.tbad = (uint32_t*)take(sizeof(uint32_t) * nrt);
   w.keysA = (uint32_t*)take(sizeof(uint32_t) * d);
   w.keysB = (uint32_t*)take(sizeof(uint32_t) * d);
   w.valsA = (int32_t*)take(sizeof(int32_t) * d);
@@ -219,7 +221,6 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   const int nrt = (int)ceil_div(d, kRadixTile);
   const int nt = (int)ceil_div(d, kBigTile);
   const float* wseg = w + start;
-  zero_words(b.flags, 64, s);
   // 4 stable LSD passes: w -> B -> A -> B -> A(keys) / perm
   int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
   for (int pass = 0; pass < 4; ++pass) {
@@ -230,9 +231,10 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
     int32_t* vdst = pass % 2 == 0 ? b.valsB : (pass == 3 ? perm_final : b.valsA);
     { WSR_TRACE("radix_hist", s);
     hipLaunchKernelGGL(k_radix_hist, dim3(std::min(nrt, hist_grid())), dim3(kRadixThreads), 0, s, pass == 0 ? wseg : nullptr,
-                       ksrc, d, shift, b.hist, nrt, b.flags); }
+                       ksrc, d, shift, b.hist, nrt, b.tbad); }
     { WSR_TRACE("radix_rowscan", s);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, b.hist, nrt, b.totals); }
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, b.hist, nrt, b.totals,
+                       pass == 0 ? b.tbad : nullptr, b.flags); }
     { WSR_TRACE("radix_scatter", s);
     hipLaunchKernelGGL(k_radix_scatter, dim3(std::min(nrt, scatter_grid())), dim3(kScatterThreads), 0, s,
                        pass == 0 ? wseg : nullptr,

@@ -25,8 +25,9 @@ static_assert(kMergeGroupMax / 1024 <= 16, "tile scans hold at most 16 tiles per
 static_assert(kScatterThreads >= 256, "digit scan assumes one digit per thread");
 
 __global__ void k_radix_hist(const float* wsrc, const uint32_t* ksrc, int64_t n, int shift,
-                             uint32_t* hist, int ntiles, uint32_t* flags);
-__global__ void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals);
+                             uint32_t* hist, int ntiles, uint32_t* tbad);
+__global__ void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals, const uint32_t* tbad,
+                                uint32_t* flags);
 __global__ void k_radix_scatter(const float* wsrc, const uint32_t* ksrc, const int32_t* vsrc,
                                 uint32_t* kdst, int32_t* vdst, int64_t n, int shift,
                                 const uint32_t* hist, const uint32_t* totals, int ntiles);

@@ -29,7 +29,7 @@ namespace wsr {
 // while it counts the current one, so the loads of one tile overlap the LDS atomics of another.
 __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc, const uint32_t* ksrc,
                                                              int64_t n, int shift, uint32_t* hist,
-                                                             int ntiles, uint32_t* flags) {
+                                                             int ntiles, uint32_t* tbad) {
   constexpr int IPT = kRadixTile / kRadixThreads;
   constexpr int NW = kRadixThreads / kWave;
   constexpr int kHistLanes = 16;
@@ -86,7 +86,14 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
       const uint32_t dg = in ? (key >> shift) & 255u : 256u;
       atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
     }
-    __syncthreads();
+    if (wsrc) {
+      // first pass: every tile's non-finite flag is written each call (no clearing launch)
+      const int any = __syncthreads_or(bad);
+      if (tid == 0) tbad[tile] = any ? 1u : 0u;
+      bad = 0;
+    } else {
+      __syncthreads();
+    }
     for (int j = tid; j < 256; j += kRadixThreads) {
       uint32_t c = 0;
 #pragma unroll
@@ -100,15 +107,23 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
 #pragma unroll
     for (int r = 0; r < IPT; ++r) word[r] = wn[r];
   }
-  if (wsrc && __syncthreads_or(bad) && tid == 0) atomicOr(flags, 1u);
 }
 
 // Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
 // The row goes through LDS so global reads and writes are coalesced.
-__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals) {
+// For the first pass (tbad != null) workgroup 0 also folds the tiles' non-finite flags into
+// flags[0] (a plain store: every call writes it).
+__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals,
+                                                       const uint32_t* tbad, uint32_t* flags) {
   constexpr int kMaxRow = (1 << 26) / kRadixTile;  // tiles of the longest segment
   __shared__ uint32_t row_s[kMaxRow];
   __shared__ int sh[256 / kWave + 1];
+  if (tbad && blockIdx.x == 0) {
+    uint32_t any = 0u;
+    for (int i = threadIdx.x; i < ntiles; i += 256) any |= tbad[i];
+    any = __syncthreads_or(any != 0u);
+    if (threadIdx.x == 0) flags[0] = any ? 1u : 0u;
+  }
   uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
   for (int i = threadIdx.x; i < ntiles; i += 256) row_s[i] = row[i];
   __syncthreads();
