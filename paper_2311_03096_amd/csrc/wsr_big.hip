@@ -502,11 +502,17 @@ __device__ __forceinline__ void node_vertex(const MergeCtx& C, int t0, int t1, i
 // Wave-cooperative access to a node's chain: any lane may fetch any vertex.  Chain indices
 // [wlo, whi] are also held in an LDS window (loaded once per merge, the vertices next to the
 // junction, where most bridge probes land); other indices come from global memory.
+// LDS-qualified pointers: window reads compile to LDS instructions, which a wave executes in
+// order with its own window writes (a generic pointer would read through the flat path, which is
+// not ordered with pending LDS writes).
+typedef __attribute__((address_space(3))) int lds_int;
+typedef __attribute__((address_space(3))) double lds_double;
+
 struct WaveNode {
   const MergeCtx* C;
   int t0, t1;
-  const int* wp = nullptr;
-  const double* ws = nullptr;
+  const lds_int* wp = nullptr;
+  const lds_double* ws = nullptr;
   int wlo = 0, whi = -1;
   __device__ __forceinline__ void load(int tile, int idx, int* p, double* s) const {
     const int g = C->gbase + tile;
@@ -795,8 +801,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        WaveNode L{&C, t0, tm, win_p[wv][0], win_s[wv][0], wlo, p};
-        WaveNode R{&C, tm, t1, win_p[wv][1], win_s[wv][1], 0, rhi};
+        WaveNode L{&C, t0, tm, (const lds_int*)win_p[wv][0], (const lds_double*)win_s[wv][0], wlo, p};
+        WaveNode R{&C, tm, t1, (const lds_int*)win_p[wv][1], (const lds_double*)win_s[wv][1], 0, rhi};
         int istar, jstar;
         wave_bridge(L, p, R, q, &istar, &jstar);
         if (!(istar == p && jstar == 1)) {

@@ -183,6 +183,20 @@ def test_edge_cases():
     assert st["clusters"] == 2
 
 
+def test_long_segment_repeatable():
+    """Tie-group clusters spanning many tiles: cross-tile merges decide every cluster's ends,
+    so repeated runs must agree bit for bit and every cluster be constant."""
+    case = workloads.precision(1 << 22, 1e-4, seed=5)
+    first = None
+    for run in range(3):
+        g, _, st = _check(case)
+        if first is None:
+            first = g
+        else:
+            for k in ("out", "perm", "start"):
+                assert np.array_equal(first[k], g[k]), "run %d differs in %s" % (run, k)
+
+
 def test_determinism():
     case = workloads.random_segments([3000, 4096, 8192, 100000], "normal", 0.05, seed=9)
     a = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
