@@ -147,6 +147,21 @@ def test_mixed_sparse_dense_tiles():
         _check_backward(case)
 
 
+@pytest.mark.parametrize("d", [12289, 40961])
+def test_ica_worst_case_long(d):
+    """Sec. 4.1 worst case recast as a prox input (lam = 1, d odd): a long run of equal weights
+    then a slow ramp; the left cluster absorbs the ramp one rank at a time (about d/2 rounds of
+    the paper's ImminentCollisions).  One final cluster."""
+    eps = 1.0 / (4 * d)
+    half = (d + 1) // 2
+    j = np.arange(1, d // 2 + 1)
+    w = np.concatenate([np.zeros(half), j * (eps + 2.0 / (d - 1))]).astype(np.float32)
+    w = w[np.random.default_rng(d).permutation(d)]
+    case = dict(name="ica worst d=%d" % d, w=w, offsets=np.array([0, d], np.int64), lam=np.float32(1.0))
+    g, _, st = _check(case)
+    assert st["clusters"] == 1
+
+
 def test_typical_d2p24():
     _check(workloads.plain(1 << 24, 0.1, seed=1))
 
