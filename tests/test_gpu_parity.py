@@ -212,6 +212,23 @@ def test_long_segment_repeatable():
                 assert np.array_equal(first[k], g[k]), "run %d differs in %s" % (run, k)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_layouts(seed):
+    """Seeded random layouts: 1-40 segments with lengths from 1 to ~150k (both size classes and
+    the long path, ragged tails), every weight distribution, lambda over five decades; plain and
+    batched entry points, forward against the oracle and backward against the oracle VJP."""
+    rng = np.random.default_rng(1000 + seed)
+    nseg = int(rng.integers(1, 41))
+    kinds = rng.choice(["tiny", "short", "long"], nseg, p=[0.3, 0.5, 0.2])
+    lens = [int(rng.integers(0, 40)) if k == "tiny" else int(rng.integers(40, 8193)) if k == "short"
+            else int(rng.integers(8193, 150000)) for k in kinds]
+    dist = ["normal", "laplace", "ties", "sorted", "mixed"][seed % 5]
+    lam = float(10.0 ** rng.uniform(-4, 1))
+    case = workloads.random_segments(lens, dist, lam, seed=seed)
+    _check(case, batched=bool(seed % 2))
+    _check_backward(case, batched=bool(seed % 2))
+
+
 def test_determinism():
     case = workloads.random_segments([3000, 4096, 8192, 100000], "normal", 0.05, seed=9)
     a = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
