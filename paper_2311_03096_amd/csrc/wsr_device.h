@@ -414,20 +414,19 @@ __device__ __forceinline__ bool carry_exchange(Cand mineL, Cand mineR, bool flag
   return any != 0;
 }
 
-// Candidates of b next to the removed points rem (within the thread): for each removed point, the
-// nearest surviving candidate on either side.  A candidate's collision test can only change when
-// one of its neighbouring candidates changed.
+// Candidates of b next to the removed points rem (within the thread; b and rem disjoint): for
+// each removed point, the nearest surviving candidate on either side.  A candidate's collision
+// test can only change when one of its neighbouring candidates changed.  No loop: adding rem to
+// ~b starts a carry at every removed bit that runs through the non-candidate bits and enters
+// the next candidate above (the carry-in bits are sum ^ a ^ b); the same on the bit-reversed
+// masks gives the next candidate below.
 __device__ __forceinline__ uint32_t ica_neighbours(uint32_t b, uint32_t rem) {
-  uint32_t dirty = 0;
-  while (rem) {
-    const int j = __ffs(rem) - 1;
-    rem &= rem - 1u;
-    const uint32_t lo = b & ((1u << j) - 1u);
-    const uint32_t hi = b & ~((2u << j) - 1u);
-    if (lo) dirty |= 1u << (31 - __clz(lo));
-    dirty |= hi & (0u - hi);
-  }
-  return dirty;
+  const uint32_t m = ~b;
+  const uint32_t up = ((m + rem) ^ m ^ rem) & b;
+  const uint32_t rb = __builtin_bitreverse32(b), rr = __builtin_bitreverse32(rem);
+  const uint32_t mr = ~rb;
+  const uint32_t dn = __builtin_bitreverse32(((mr + rr) ^ mr ^ rr) & rb);
+  return up | dn;
 }
 
 // One wave's boundary in the collision exchange: its first and last candidates, the neighbours
