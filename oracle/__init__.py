@@ -6,7 +6,8 @@ shares no code with it.
 
 The arithmetic lives in ``wsr_oracle.c`` (plain C, FP64): sort, rank-dependent
 shift, stack pool-adjacent-violators, scatter back (paper Sec. 4.1 and
-Alg. prox).  This module only builds that file with gcc and marshals arguments.
+Alg. prox), and Alg. prox's l1 and rewinding lines per cluster.  This module
+only builds that file with gcc and marshals arguments.
 """
 from __future__ import annotations
 
@@ -44,6 +45,11 @@ def _load():
         lib.wsr_oracle_prox_f64.restype = ctypes.c_int
         lib.wsr_oracle_prox_segments_f32.argtypes = [i64, p, p, p, ctypes.c_int, p, p, p, ctypes.c_int]
         lib.wsr_oracle_prox_segments_f32.restype = ctypes.c_int
+        lib.wsr_oracle_prox_l1_f64.argtypes = [i64, p, ctypes.c_double, ctypes.c_double, ctypes.c_double, p]
+        lib.wsr_oracle_prox_l1_f64.restype = ctypes.c_int
+        lib.wsr_oracle_prox_l1_segments_f32.argtypes = [i64, p, p, p, ctypes.c_int, ctypes.c_float,
+                                                        ctypes.c_float, p, ctypes.c_int]
+        lib.wsr_oracle_prox_l1_segments_f32.restype = ctypes.c_int
         lib.wsr_oracle_vjp.argtypes = [i64, p, p, p, p, p]
         lib.wsr_oracle_vjp.restype = ctypes.c_int
         _lib = lib
@@ -90,6 +96,37 @@ def prox_segments(w, lam, offsets=None, n_threads: int = 1):
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return u, perm, start
+
+
+def prox_l1_f64(w, lam: float, beta: float, rho: float):
+    """One segment in FP64, Alg. prox in full: prox of lam*R + beta*l1 with rewinding rho."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    out = np.empty(w.shape[0], np.float64)
+    rc = _load().wsr_oracle_prox_l1_f64(w.shape[0], _ptr(w), float(lam), float(beta), float(rho), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
+    return out
+
+
+def prox_l1_segments(w, lam, beta: float, rho: float, offsets=None, n_threads: int = 1):
+    """Flat FP32 buffer with segment offsets, Alg. prox in full on every segment (lam scalar or
+    per segment; beta and rho FP32 scalars).  Returns the FP64 output in the original order."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    n = w.shape[0]
+    if offsets is None:
+        offsets = np.array([0, n], np.int64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_seg = offsets.shape[0] - 1
+    lam_arr = np.ascontiguousarray(np.atleast_1d(np.asarray(lam, dtype=np.float32)))
+    per_seg = 1 if lam_arr.shape[0] == n_seg and n_seg != 1 else 0
+    if per_seg == 0 and lam_arr.shape[0] != 1:
+        raise ValueError("lam must be a scalar or have one value per segment")
+    out = np.empty(n, np.float64)
+    rc = _load().wsr_oracle_prox_l1_segments_f32(n_seg, _ptr(offsets), _ptr(w), _ptr(lam_arr), per_seg,
+                                                 float(beta), float(rho), _ptr(out), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
+    return out
 
 
 def vjp(g, perm_local, start, offsets=None):

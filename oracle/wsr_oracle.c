@@ -36,6 +36,9 @@
  *   - d <= 1 or l == 0: identity, every element its own cluster;
  *   - a segment containing a non-finite weight yields NaN for the whole segment.
  *
+ * Full Alg. prox (wsr_oracle_prox_l1_*): the same collisions, then the algorithm's
+ * l1 and rewinding lines applied per cluster (prox of lam*R + beta*l1, rewinding rho).
+ *
  * Gradient: the prox is piecewise affine; on the piece selected by the partition
  * its Jacobian averages within each cluster (symmetric, idempotent).  The
  * vector-Jacobian product is therefore the per-cluster mean of the cotangent.
@@ -161,6 +164,76 @@ int wsr_oracle_prox_f64(int64_t d, const double* w, double lam, double* u, int64
     return 0;
 }
 
+/*
+ * Alg. prox in full: the proximal map of  lam*R + beta*l1  with rewinding rho
+ * (Sec. 1, prox of the combined penalty; App. "combining weight-sharing and
+ * sparsity"; Sec. "rewinding").  The collisions give the clusters of prox_{lam R};
+ * the algorithm then works per cluster C with
+ *     x_C = mean of the weights of C        (what the collisions leave in x),
+ *     v_C = mean velocity of C = lam*(d-1-a-b)/(d-1) for C = ranks [a, b],
+ * and, in this order:
+ *     zero  = |x_C + v_C| < beta           (x_C + v_C is the prox_{lam R} value)
+ *     v_C  -= beta * sign(x_C + v_C)
+ *     x_C = v_C = 0 where zero
+ *     x_C  += (1 - rho) * v_C               (rewinding scales the remaining displacement)
+ * and every rank of C takes x_C.  rho = 0 is prox_{lam R + beta l1}, which equals the
+ * soft-thresholding of prox_{lam R} (the decomposition proposition); rho = 1 keeps the
+ * cluster means of the surviving clusters.  The strict "<" of the zero test is the
+ * algorithm's.  d <= 1 or lam == 0: every weight its own cluster with v_C = 0.
+ * A segment containing a non-finite weight yields NaN for the whole segment.
+ *   lam, beta >= 0 and finite; 0 <= rho <= 1.   out[d]: original order.
+ * Returns 0, or -1 on bad arguments / allocation failure.
+ */
+int wsr_oracle_prox_l1_f64(int64_t d, const double* w, double lam, double beta, double rho,
+                           double* out) {
+    if (d < 0 || !(lam >= 0.0) || isinf(lam) || !(beta >= 0.0) || isinf(beta) ||
+        !(rho >= 0.0) || !(rho <= 1.0))
+        return -1;
+    if (d == 0) return 0;
+    double* u = (double*)malloc(sizeof(double) * (size_t)d);
+    int64_t* perm = (int64_t*)malloc(sizeof(int64_t) * (size_t)d);
+    uint8_t* start = (uint8_t*)malloc((size_t)d);
+    if (!u || !perm || !start) {
+        free(u); free(perm); free(start);
+        return -1;
+    }
+    int rc = wsr_oracle_prox_f64(d, w, lam, u, perm, start);
+    if (rc == 0) {
+        int finite = 1;
+        for (int64_t i = 0; i < d; ++i)
+            if (!isfinite(w[i])) finite = 0;
+        if (!finite) {
+            for (int64_t i = 0; i < d; ++i) out[i] = NAN;
+        } else {
+            int64_t k = 0;
+            while (k < d) {
+                int64_t e = k + 1;
+                while (e < d && !start[e]) ++e;
+                /* cluster C = ranks [k, e-1] */
+                double acc = 0.0, comp = 0.0;
+                for (int64_t j = k; j < e; ++j) nsum_add(&acc, &comp, w[perm[j]]);
+                double x = (acc + comp) / (double)(e - k);
+                double v = (d <= 1 || lam == 0.0)
+                               ? 0.0
+                               : lam * (double)(d - 1 - k - (e - 1)) / (double)(d - 1);
+                double y = x + v;
+                int zero = fabs(y) < beta;
+                double sgn = (double)((y > 0.0) - (y < 0.0));
+                v = v - beta * sgn;
+                if (zero) {
+                    x = 0.0;
+                    v = 0.0;
+                }
+                x = x + (1.0 - rho) * v;
+                for (int64_t j = k; j < e; ++j) out[perm[j]] = x;
+                k = e;
+            }
+        }
+    }
+    free(u); free(perm); free(start);
+    return rc;
+}
+
 /* ---------------- flat buffer of FP32 segments (what the GPU library consumes) ---------------- */
 
 typedef struct {
@@ -172,6 +245,8 @@ typedef struct {
     double* u;
     int32_t* perm_local;
     uint8_t* start;
+    int l1;            /* 1: Alg. prox with its l1 and rewinding lines (u receives its output) */
+    double beta, rho;
     int rc;
 } seg_job_t;
 
@@ -190,9 +265,11 @@ static void* seg_worker(void* arg) {
             return NULL;
         }
         for (int64_t i = 0; i < d; ++i) w64[i] = (double)job->w[o + i]; /* exact promotion */
-        int rc = wsr_oracle_prox_f64(d, w64, lam, job->u + o, p64, job->start ? job->start + o : NULL);
+        int rc = job->l1 ? wsr_oracle_prox_l1_f64(d, w64, lam, job->beta, job->rho, job->u + o)
+                         : wsr_oracle_prox_f64(d, w64, lam, job->u + o, p64,
+                                               job->start ? job->start + o : NULL);
         if (rc) job->rc = rc;
-        if (job->perm_local)
+        if (job->perm_local && !job->l1)
             for (int64_t k = 0; k < d; ++k) job->perm_local[o + k] = (int32_t)p64[k];
         free(w64);
         free(p64);
@@ -208,9 +285,9 @@ static void* seg_worker(void* arg) {
  *   start: 1 at ranks that begin a cluster.  perm_local and start may be NULL.
  *   n_threads: segments are split across this many POSIX threads (>= 1).
  */
-int wsr_oracle_prox_segments_f32(int64_t n_seg, const int64_t* offsets, const float* w,
-                                 const float* lam, int per_seg_lam, double* u,
-                                 int32_t* perm_local, uint8_t* start, int n_threads) {
+static int run_segments(int64_t n_seg, const int64_t* offsets, const float* w, const float* lam,
+                        int per_seg_lam, double* u, int32_t* perm_local, uint8_t* start,
+                        int n_threads, int l1, double beta, double rho) {
     if (n_seg < 0 || !offsets || offsets[0] != 0) return -1;
     for (int64_t s = 0; s < n_seg; ++s) {
         if (offsets[s + 1] < offsets[s]) return -1;
@@ -240,6 +317,9 @@ int wsr_oracle_prox_segments_f32(int64_t n_seg, const int64_t* offsets, const fl
         jobs[t].u = u;
         jobs[t].perm_local = perm_local;
         jobs[t].start = start;
+        jobs[t].l1 = l1;
+        jobs[t].beta = beta;
+        jobs[t].rho = rho;
     }
     int rc = 0;
     if (n_threads == 1) {
@@ -255,6 +335,26 @@ int wsr_oracle_prox_segments_f32(int64_t n_seg, const int64_t* offsets, const fl
     free(jobs);
     free(th);
     return rc;
+}
+
+int wsr_oracle_prox_segments_f32(int64_t n_seg, const int64_t* offsets, const float* w,
+                                 const float* lam, int per_seg_lam, double* u,
+                                 int32_t* perm_local, uint8_t* start, int n_threads) {
+    return run_segments(n_seg, offsets, w, lam, per_seg_lam, u, perm_local, start, n_threads, 0,
+                        0.0, 0.0);
+}
+
+/*
+ * Alg. prox in full (wsr_oracle_prox_l1_f64) on every segment of a flat FP32 buffer, with the
+ * segment's lam (as in wsr_oracle_prox_segments_f32) and one beta and rho for all segments,
+ * promoted exactly to FP64.  out: FP64, original order.
+ */
+int wsr_oracle_prox_l1_segments_f32(int64_t n_seg, const int64_t* offsets, const float* w,
+                                    const float* lam, int per_seg_lam, float beta, float rho,
+                                    double* out, int n_threads) {
+    if (!(beta >= 0.0f) || isinf(beta) || !(rho >= 0.0f) || !(rho <= 1.0f)) return -1;
+    return run_segments(n_seg, offsets, w, lam, per_seg_lam, out, NULL, NULL, n_threads, 1,
+                        (double)beta, (double)rho);
 }
 
 /*

@@ -10,6 +10,8 @@ shares nothing with the oracle's sort + pool-adjacent-violators code:
                            weak ordering of the output (ordered set partitions); on each
                            piece R is linear, so the restricted minimiser is closed form
                            (definition of prox, App. A.1; piecewise-linear R, Sec. 2).
+* ``brute_force_prox_l1`` -- the same enumeration for alpha*R + beta*l1 (sign pattern and
+                           zero block of the output enumerated as well).
 * ``gcm_slopes``        -- isotonic regression of y as the slopes of the greatest convex
                            minorant of its cumulative-sum diagram, by a monotone-chain
                            lower hull with cross products (isotonic link, Sec. 1.2 and Sec. 3).
@@ -92,6 +94,49 @@ def brute_force_prox(w, lam):
         obj = lam * R_pairwise(u) + 0.5 * float(((u - w) ** 2).sum())
         if obj < best:
             best, best_u = obj, u
+    return best_u
+
+
+def brute_force_prox_l1(w, alpha, beta):
+    """Exact minimiser of alpha*R(u) + beta*||u||_1 + 1/2||u-w||^2 by enumeration; 2 <= d <= 6.
+
+    A piece of the objective is fixed by a weak ordering of the output and by which of its
+    blocks sit below zero, at zero, above zero: either one block is pinned at 0 (blocks before
+    it negative, after it positive) or none is and a split point separates negative from
+    positive blocks.  On a piece R and l1 are linear, so each free block's restricted
+    minimiser is mean(w_g) - alpha*mean(coef over its ranks) - beta*sign_g.  The objective is
+    strictly convex, so the best candidate that lies on its own piece is the minimiser
+    (definition of prox, Sec. 1; the l1 prox as soft-thresholding, App. A.1 example)."""
+    w = np.asarray(w, dtype=np.float64)
+    d = w.shape[0]
+    coef = (2.0 * np.arange(d) + 1.0 - d) / (d - 1)
+    best, best_u = np.inf, None
+    for blocks in weak_orderings(d):
+        nb = len(blocks)
+        pieces = [(z, z) for z in range(nb)] + [(None, s) for s in range(nb + 1)]
+        for zero, split in pieces:
+            r = 0
+            vals = []
+            ok = True
+            for gi, b in enumerate(blocks):
+                n = len(b)
+                if zero is not None and gi == zero:
+                    vals.append(0.0)
+                else:
+                    sgn = -1.0 if gi < split else 1.0
+                    val = w[list(b)].mean() - alpha * coef[r:r + n].mean() - beta * sgn
+                    if not (val * sgn > 0.0):
+                        ok = False
+                    vals.append(val)
+                r += n
+            if not ok or any(vals[i] >= vals[i + 1] for i in range(nb - 1)):
+                continue
+            u = np.empty(d)
+            for b, val in zip(blocks, vals):
+                u[list(b)] = val
+            obj = alpha * R_pairwise(u) + beta * float(np.abs(u).sum()) + 0.5 * float(((u - w) ** 2).sum())
+            if obj < best:
+                best, best_u = obj, u
     return best_u
 
 

@@ -393,3 +393,116 @@ def test_nonfinite_and_bad_args():
         oracle.prox_f64(np.array([1.0, 2.0]), -1.0)
     with pytest.raises(ValueError):
         oracle.prox_segments(np.zeros(4, np.float32), 0.1, np.array([0, 3, 2, 4]))
+
+
+# ----------------------------------------------------------------------------- l1 and rewinding
+# Alg. prox in full: the clusters of prox_{lam R}, then its l1 and rewinding lines per cluster.
+
+def _l1_case(rng, d):
+    w, lam = _random_case(rng, d)
+    beta = float(rng.choice([0.0, 0.05, 0.2, 0.6])) * float(np.abs(w).max() + 1e-3) * float(rng.uniform(0.5, 1.5))
+    return w, lam, beta
+
+
+def test_l1_brute_force_small_d():
+    """rho = 0: the output is the exact minimiser of lam*R + beta*l1 + 1/2||u - w||^2, found by
+    enumeration (pins the decomposition proposition and the soft-threshold lines)."""
+    rng = np.random.default_rng(21)
+    n = 0
+    for d in [2, 3, 4, 5]:
+        for _ in range(20):
+            w, lam, beta = _l1_case(rng, d)
+            out = oracle.prox_l1_f64(w, lam, beta, 0.0)
+            ub = pins.brute_force_prox_l1(w, lam, beta)
+            np.testing.assert_allclose(out, ub, atol=1e-9 * (1 + np.abs(w).max()), err_msg=f"{w} {lam} {beta}")
+            n += 1
+    w, lam, beta = _l1_case(rng, 6)
+    np.testing.assert_allclose(oracle.prox_l1_f64(w, lam, beta, 0.0), pins.brute_force_prox_l1(w, lam, beta),
+                               atol=1e-9 * (1 + np.abs(w).max()))
+    assert n == 80
+
+
+def test_l1_rewinding_from_brute_force():
+    """rho in (0, 1]: before the rewinding line the output splits as x + v, x the mean weight of
+    each surviving cluster, zero on zeroed ones; rewinding returns x + (1 - rho) v.  x is taken
+    from the groups of the brute-force minimiser, so nothing here comes from the oracle."""
+    rng = np.random.default_rng(22)
+    for d in [3, 4, 5]:
+        for _ in range(12):
+            w, lam, beta = _l1_case(rng, d)
+            P = pins.brute_force_prox_l1(w, lam, beta)
+            vals, inv = np.unique(P, return_inverse=True)
+            for rho in [0.25, 0.98, 1.0]:
+                exp = np.empty(d)
+                for gi, val in enumerate(vals):
+                    m = inv == gi
+                    xbar = w[m].mean()
+                    exp[m] = 0.0 if val == 0.0 else xbar + (1.0 - rho) * (val - xbar)
+                np.testing.assert_allclose(oracle.prox_l1_f64(w, lam, beta, rho), exp,
+                                           atol=1e-9 * (1 + np.abs(w).max()), err_msg=f"{w} {lam} {beta} {rho}")
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.5, 0.98, 1.0])
+def test_l1_closed_form_without_weight_sharing(rho):
+    """lam = 0 (and d = 1 for any lam): the rewound l1 prox of the rewinding section's example,
+    sign(w) (|w| - (1 - rho) beta) where |w| > beta, else 0; rho = 0 is soft-thresholding
+    (App. A.1 example)."""
+    rng = np.random.default_rng(23)
+    w = rng.normal(size=2000)
+    beta = 0.5
+    exp = np.where(np.abs(w) > beta, w - (1.0 - rho) * beta * np.sign(w), 0.0)
+    np.testing.assert_allclose(oracle.prox_l1_f64(w, 0.0, beta, rho), exp, atol=1e-15)
+    for x in [-2.0, -0.3, 0.0, 0.4, 1.7]:
+        got = oracle.prox_l1_f64(np.array([x]), 0.7, beta, rho)[0]
+        assert got == (0.0 if abs(x) < beta else x - (1.0 - rho) * beta * np.sign(x))
+    if rho == 0.0:
+        np.testing.assert_allclose(exp, np.sign(w) * np.maximum(np.abs(w) - beta, 0.0), atol=1e-15)
+
+
+def test_l1_reductions_and_invariants():
+    rng = np.random.default_rng(24)
+    for _ in range(30):
+        d = int(rng.integers(2, 3000))
+        w, lam, beta = _l1_case(rng, d)
+        s = 1 + np.abs(w).max()
+        u = oracle.prox_f64(w, lam)[0]
+        # beta = 0, rho = 0: prox_{lam R} itself
+        np.testing.assert_allclose(oracle.prox_l1_f64(w, lam, 0.0, 0.0), u, atol=1e-12 * s)
+        rho = float(rng.uniform())
+        # beta = 0: the velocities of a cluster sum to its displacement and all of them to zero
+        # (momentum, Sec. 3), so every rho keeps the sum of the weights
+        assert abs(oracle.prox_l1_f64(w, lam, 0.0, rho).sum() - w.sum()) < 1e-9 * s * d ** 0.5
+        out = oracle.prox_l1_f64(w, lam, beta, rho)
+        # the zeroed weights are exactly those whose prox_{lam R} value is below beta in size
+        np.testing.assert_array_equal(out == 0.0, np.abs(u) < beta)
+        # odd symmetry and positive homogeneity of lam*R + beta*l1
+        np.testing.assert_allclose(oracle.prox_l1_f64(-w, lam, beta, rho), -out, atol=1e-12 * s)
+        np.testing.assert_allclose(oracle.prox_l1_f64(2.0 * w, 2.0 * lam, 2.0 * beta, rho), 2.0 * out,
+                                   atol=1e-12 * s)
+        # rho = 0 equals soft-thresholding of prox_{lam R} (decomposition proposition)
+        np.testing.assert_allclose(oracle.prox_l1_f64(w, lam, beta, 0.0),
+                                   np.sign(u) * np.maximum(np.abs(u) - beta, 0.0), atol=1e-12 * s)
+
+
+def test_l1_segments_match_single_and_threads():
+    rng = np.random.default_rng(25)
+    lens = [0, 1, 2, 5, 100, 3072, 4096, 7, 0, 1]
+    offsets = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = rng.normal(size=offsets[-1]).astype(np.float32)
+    lam = rng.uniform(0, 0.1, size=len(lens)).astype(np.float32)
+    beta, rho = np.float32(0.3), np.float32(0.75)
+    o1 = oracle.prox_l1_segments(w, lam, beta, rho, offsets, n_threads=1)
+    o4 = oracle.prox_l1_segments(w, lam, beta, rho, offsets, n_threads=4)
+    assert np.array_equal(o1, o4)
+    for s, (a, b) in enumerate(zip(offsets[:-1], offsets[1:])):
+        if b > a:
+            np.testing.assert_array_equal(
+                o1[a:b], oracle.prox_l1_f64(w[a:b].astype(np.float64), float(lam[s]), float(beta), float(rho)))
+
+
+def test_l1_nonfinite_and_bad_args():
+    assert np.isnan(oracle.prox_l1_f64(np.array([1.0, np.inf, 2.0]), 0.1, 0.5, 0.5)).all()
+    for lam, beta, rho in [(-1.0, 0.1, 0.0), (0.1, -0.1, 0.0), (0.1, 0.1, 1.5), (0.1, 0.1, -0.5),
+                           (0.1, np.nan, 0.0), (0.1, 0.1, np.nan), (0.1, np.inf, 0.0)]:
+        with pytest.raises(ValueError):
+            oracle.prox_l1_f64(np.array([1.0, 2.0]), lam, beta, rho)
