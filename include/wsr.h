@@ -103,6 +103,27 @@ WSR_API int wsr_prox_forward(const float* w, float* out, const int64_t* h_offset
                      size_t ws_bytes, void* stream);
 
 /*
+ * Forward of Alg. prox in full: the proximal map of lambda*R_d + beta*l1 with rewinding rho
+ * (Sec. 1, prox of the combined penalty; App. "combining weight-sharing and sparsity" for its
+ * decomposition; Sec. "rewinding" and Alg. prox, l1 and rewinding lines).  The collisions are
+ * those of wsr_prox_forward; then every cluster C = ranks [a, b) of prox_{lambda R} with value
+ * u_C, mean weight x_C and mean velocity v_C = lambda (d - a - b)/(d - 1) (u_C = x_C + v_C) gets
+ *     0                                          if |u_C| < beta
+ *     x_C + (1 - rho) (v_C - beta sign(u_C))     otherwise,
+ * decided and evaluated in FP64, rounded once to FP32.  rho = 0 gives prox_{lambda R + beta l1}
+ * (soft-thresholding of prox_{lambda R}); beta = rho = 0 gives prox_{lambda R}; rho = 1 keeps
+ * the mean weight of every surviving cluster.  Segments that wsr_prox_forward leaves unchanged
+ * (d_s == 1, lambda == 0) get the elementwise rule with v = 0; non-finite segments get NaN.
+ *   beta          finite, >= 0
+ *   rho           in [0, 1]
+ * Other arguments as in wsr_prox_forward.  No state is saved: this is the update of a
+ * proximal-gradient step, not a differentiable layer.
+ */
+WSR_API int wsr_prox_l1_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg,
+                                float lambda, float beta, float rho, void* ws, size_t ws_bytes,
+                                void* stream);
+
+/*
  * Backward of the prox: grad_w = J^T grad_out, where on the piece of the map picked
  * by the saved partition J averages within each cluster (J is symmetric and
  * idempotent).  Not in the paper: it follows from Alg. prox's repeat_interleave of
@@ -146,6 +167,12 @@ WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);
 WSR_API int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out,
                              const float* d_lambda, float lambda_scalar, int32_t* saved_perm,
                              uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream);
+
+/* Batched form of wsr_prox_l1_forward: lambdas as in wsr_prox_forward_batched, one beta and one
+ * rho for every segment. */
+WSR_API int wsr_prox_l1_forward_batched(const wsr_plan* plan, const float* w, float* out,
+                                        const float* d_lambda, float lambda_scalar, float beta,
+                                        float rho, void* ws, size_t ws_bytes, void* stream);
 
 /* Batched backward over every segment of the plan (see wsr_prox_backward). */
 WSR_API int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,

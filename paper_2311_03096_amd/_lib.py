@@ -23,6 +23,7 @@ EXPORTED = (
     "wsr_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_prox_forward",
     "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy", "wsr_plan_workspace_bytes",
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
+    "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched",
 )
 
 
@@ -52,6 +53,8 @@ def load():
         "wsr_workspace_bytes": ([p, i64, ctypes.POINTER(sz)], i32),
         "wsr_prox_forward": ([p, p, p, i64, f32, p, p, p, sz, p], i32),
         "wsr_prox_backward": ([p, p, p, i64, p, p, p, sz, p], i32),
+        "wsr_prox_l1_forward": ([p, p, p, i64, f32, f32, f32, p, sz, p], i32),
+        "wsr_prox_l1_forward_batched": ([p, p, p, p, f32, f32, f32, p, sz, p], i32),
         "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
         "wsr_plan_destroy": ([p], i32),
         "wsr_plan_workspace_bytes": ([p, ctypes.POINTER(sz)], i32),
@@ -130,6 +133,14 @@ def wsr_prox_forward(w, out, offsets, lam, saved_perm=None, saved_mask=None, ws=
         _ptr(saved_perm), _ptr(saved_mask), wp, wn, _stream(stream)))
 
 
+def wsr_prox_l1_forward(w, out, offsets, lam, beta, rho, ws=None, stream=None):
+    off = _offsets(offsets)
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_l1_forward", load().wsr_prox_l1_forward(
+        _ptr(w), _ptr(out), off.ctypes.data_as(ctypes.c_void_p), off.shape[0] - 1, float(lam),
+        float(beta), float(rho), wp, wn, _stream(stream)))
+
+
 def wsr_prox_backward(grad_out, grad_w, offsets, saved_perm, saved_mask, ws=None, stream=None):
     off = _offsets(offsets)
     wp, wn = _ws_args(ws)
@@ -162,6 +173,14 @@ def wsr_prox_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, saved_perm=
     _check("wsr_prox_forward_batched", load().wsr_prox_forward_batched(
         plan, _ptr(w), _ptr(out), _ptr(lam), float(lam_scalar), _ptr(saved_perm), _ptr(saved_mask),
         wp, wn, _stream(stream)))
+
+
+def wsr_prox_l1_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, beta=0.0, rho=0.0, ws=None,
+                                stream=None):
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_l1_forward_batched", load().wsr_prox_l1_forward_batched(
+        plan, _ptr(w), _ptr(out), _ptr(lam), float(lam_scalar), float(beta), float(rho), wp, wn,
+        _stream(stream)))
 
 
 def wsr_prox_backward_batched(plan, grad_out, grad_w, saved_perm, saved_mask, ws=None, stream=None):

@@ -214,9 +214,21 @@ int scatter_grid() { return 2 * cu_count(); }
 // Workgroups of the persistent radix histogram.
 int hist_grid() { return kHistPerCu * cu_count(); }
 
+// Alg. prox's l1 and rewinding lines, applied to every cluster when on != 0.
+struct L1Opt {
+  float beta = 0.0f;
+  float rho = 0.0f;
+  int on = 0;
+};
+
+bool l1_args_ok(float beta, float rho) {
+  return std::isfinite(beta) && beta >= 0.0f && rho >= 0.0f && rho <= 1.0f;
+}
+
 // Forward of one long segment [start, start + d).
 int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
-                float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s) {
+                float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s,
+                const L1Opt& l1) {
   BigWs b = big_layout(d, ws);
   const int nrt = (int)ceil_div(d, kRadixTile);
   const int nt = (int)ceil_div(d, kBigTile);
@@ -282,7 +294,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   { WSR_TRACE("big_apply", s);
   hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, perm_final, d, lam_arr, seg_id,
                      lam_scalar, b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
-                     b.next_pos, b.next_s, out, saved_mask, start); }
+                     b.next_pos, b.next_s, out, saved_mask, start, l1.beta, l1.rho, l1.on); }
   return last_error();
 }
 
@@ -333,7 +345,7 @@ struct wsr_plan {
 
 extern "C" {
 
-int wsr_version(void) { return 100; }
+int wsr_version(void) { return 200; }
 
 const char* wsr_status_string(int status) {
   switch (status) {
@@ -355,8 +367,13 @@ int wsr_workspace_bytes(const int64_t* h_offsets, int64_t n_seg, size_t* bytes) 
   return WSR_OK;
 }
 
-int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
-                     int32_t* saved_perm, uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int forward_impl(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
+                 int32_t* saved_perm, uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream,
+                 const L1Opt& l1) {
   (void)hipGetLastError();  // report only errors of this call
   if (!w || !out) return WSR_ERR_INVALID;
   if ((saved_perm == nullptr) != (saved_mask == nullptr)) return WSR_ERR_INVALID;
@@ -375,14 +392,56 @@ int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64
     const int cls = size_class(d);
     if (cls == kSkip) continue;
     if (cls == kBig) {
-      rc = big_forward(w, out, start, d, nullptr, 0, lambda, saved_perm, saved_mask, ws, s);
+      rc = big_forward(w, out, start, d, nullptr, 0, lambda, saved_perm, saved_mask, ws, s, l1);
       if (rc) return rc;
       continue;
     }
-    SegArgs a{nullptr, nullptr, nullptr, lambda, start, (int)d, 0};
+    SegArgs a{nullptr, nullptr, nullptr, lambda, start, (int)d, 0, l1.beta, l1.rho, l1.on};
     small_fwd(cls, 1, a, w, out, saved_perm, saved_mask, s);
   }
   return last_error();
+}
+
+int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,
+                         float lambda_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws,
+                         size_t ws_bytes, void* stream, const L1Opt& l1) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!plan || !w || !out) return WSR_ERR_INVALID;
+  if ((saved_perm == nullptr) != (saved_mask == nullptr)) return WSR_ERR_INVALID;
+  if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
+  const size_t need = big_bytes(plan->max_big);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (saved_mask && !plan->word_aligned) zero_words(saved_mask, ceil_div(plan->total, 32), s);
+  for (int c = 0; c < kNumSmall; ++c) {
+    if (plan->sched_cnt[c] == 0) continue;
+    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0,
+              l1.beta, l1.rho, l1.on};
+    small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
+  }
+  for (int32_t seg : plan->big_segs) {
+    const int64_t start = plan->h_offsets[seg];
+    const int64_t d = plan->h_offsets[seg + 1] - start;
+    const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s, l1);
+    if (rc) return rc;
+  }
+  return last_error();
+}
+
+}  // namespace
+
+extern "C" {
+
+int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
+                     int32_t* saved_perm, uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream) {
+  return forward_impl(w, out, h_offsets, n_seg, lambda, saved_perm, saved_mask, ws, ws_bytes, stream, L1Opt{});
+}
+
+int wsr_prox_l1_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
+                        float beta, float rho, void* ws, size_t ws_bytes, void* stream) {
+  if (!l1_args_ok(beta, rho)) return WSR_ERR_INVALID;
+  return forward_impl(w, out, h_offsets, n_seg, lambda, nullptr, nullptr, ws, ws_bytes, stream,
+                      L1Opt{beta, rho, 1});
 }
 
 int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_offsets, int64_t n_seg,
@@ -486,26 +545,16 @@ int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
 int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,
                              float lambda_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws,
                              size_t ws_bytes, void* stream) {
-  (void)hipGetLastError();  // report only errors of this call
-  if (!plan || !w || !out) return WSR_ERR_INVALID;
-  if ((saved_perm == nullptr) != (saved_mask == nullptr)) return WSR_ERR_INVALID;
-  if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
-  const size_t need = big_bytes(plan->max_big);
-  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
-  hipStream_t s = (hipStream_t)stream;
-  if (saved_mask && !plan->word_aligned) zero_words(saved_mask, ceil_div(plan->total, 32), s);
-  for (int c = 0; c < kNumSmall; ++c) {
-    if (plan->sched_cnt[c] == 0) continue;
-    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};
-    small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
-  }
-  for (int32_t seg : plan->big_segs) {
-    const int64_t start = plan->h_offsets[seg];
-    const int64_t d = plan->h_offsets[seg + 1] - start;
-    const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s);
-    if (rc) return rc;
-  }
-  return last_error();
+  return forward_batched_impl(plan, w, out, d_lambda, lambda_scalar, saved_perm, saved_mask, ws, ws_bytes,
+                              stream, L1Opt{});
+}
+
+int wsr_prox_l1_forward_batched(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,
+                                float lambda_scalar, float beta, float rho, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (!l1_args_ok(beta, rho)) return WSR_ERR_INVALID;
+  return forward_batched_impl(plan, w, out, d_lambda, lambda_scalar, nullptr, nullptr, ws, ws_bytes, stream,
+                              L1Opt{beta, rho, 1});
 }
 
 int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,

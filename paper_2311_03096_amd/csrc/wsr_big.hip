@@ -908,7 +908,8 @@ struct ApplySmem {
 // survives.  S' at a start is the hull's stored value (tiles with few surviving vertices) or is
 // recomputed from the sorted keys by the tile kernel's own operations (dense tiles); each thread
 // then sweeps its ranks with the neighbouring starts from the other threads (carry exchange) or
-// from the merge (tile ends).
+// from the merge (tile ends).  l1 != 0: each cluster's output goes through Alg. prox's l1 and
+// rewinding lines (beta, rho).
 __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys, const int32_t* perm,
                                                            int64_t d, const float* lam_arr, int seg_id,
                                                            float lam_scalar, const uint32_t* flags,
@@ -918,7 +919,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
                                                            const int32_t* hi_g, const int32_t* prev_pos,
                                                            const double* prev_s, const int32_t* next_pos,
                                                            const double* next_s, float* out,
-                                                           uint32_t* mask_out, int64_t seg_start) {
+                                                           uint32_t* mask_out, int64_t seg_start,
+                                                           float beta, float rho, int l1) {
   constexpr int R = kBigTile / kBigThreads;
   __shared__ ApplySmem sm;
   const int tid = threadIdx.x;
@@ -960,7 +962,11 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = tid + r * kBigThreads;
-      if (j < np) *at_u32(og, (uint32_t)pl[r]) = nonfinite ? __builtin_nanf("") : key_to_float(kt[j]);
+      if (j < np) {
+        const float x = key_to_float(kt[j]);
+        *at_u32(og, (uint32_t)pl[r]) =
+            nonfinite ? __builtin_nanf("") : (l1 ? l1_rewind((double)x, 0.0, beta, rho) : x);
+      }
     }
     mark(nmine > 0 ? (1u << nmine) - 1u : 0u);
     __syncthreads();
@@ -1060,7 +1066,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
       const double gb = inb ? sb + toff : sb;
       dS = gb - ga;
     }
-    return (float)(c + dS / (double)(pb - pa));
+    const double u = c + dS / (double)(pb - pa);
+    return l1 ? l1_rewind(u, lamd * (double)(d - pa - pb), beta, rho) : (float)u;
   };
   // second pass, left to right: each start closes the open cluster, whose value then goes to its
   // ranks in this thread.  Rank i's key is read before any value lands on it; the exchange

@@ -633,15 +633,39 @@ __device__ __forceinline__ void load_u32_block(const uint32_t* a, int k0, uint32
   }
 }
 
+// Output of a cluster: its FP64 value rounded to FP32 (prox_{lam R}).
+struct PlainValue {
+  __device__ __forceinline__ float operator()(double u, int, int) const { return (float)u; }
+};
+
+// Output of a cluster of ranks [a, b) under Alg. prox's l1 and rewinding lines (prox of
+// lam*R + beta*l1, rewinding rho): u is the cluster's prox_{lam R} value, its mean velocity is
+// v = lam (d - a - b)/(d - 1) (lamd = lam/(d - 1)) and its mean weight x = u - v.  The cluster
+// is zeroed when |u| < beta, else it gets x + (1 - rho)(v - beta sign(u)).  FP64, one rounding.
+__device__ __forceinline__ float l1_rewind(double u, double v, double beta, double rho) {
+  if (fabs(u) < beta) return 0.0f;
+  const double sgn = u > 0.0 ? 1.0 : (u < 0.0 ? -1.0 : 0.0);
+  const double x = u - v;
+  return (float)(x + (1.0 - rho) * (v - beta * sgn));
+}
+struct L1Value {
+  double lamd, beta, rho;
+  int d;
+  __device__ __forceinline__ float operator()(double u, int a, int b) const {
+    return l1_rewind(u, lamd * (double)(d - a - b), beta, rho);
+  }
+};
+
 // Cluster value of every rank owned by this thread from its final cluster starts: bm (bit i =
 // rank k0+i starts a cluster), sv[0..E] (S at k0..k0+E), carries lc (last start before k0) and
 // rc (first start after the thread's ranks, or the end point d).  Rank k0+i gets
-// offset + (S_b - S_a) / (b - a) for its cluster [a, b); res[ix[i]] receives it (ix: the original
-// indices of the thread's ranks).  The next cluster start is carried down a register sweep, so
-// no S value is read from LDS.
-template <int E>
+// fin(offset + (S_b - S_a) / (b - a), a, b) for its cluster [a, b); res[ix[i]] receives it (ix:
+// the original indices of the thread's ranks).  The next cluster start is carried down a register
+// sweep, so no S value is read from LDS.
+template <int E, typename Fin = PlainValue>
 __device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 1], Cand lc, Cand rc, int d,
-                                            double offset, const uint16_t (&ix)[E], float* res) {
+                                            double offset, const uint16_t (&ix)[E], float* res,
+                                            Fin fin = Fin()) {
   const int k0 = threadIdx.x * E;
   if (k0 >= d) return;
   float val[E];
@@ -649,14 +673,14 @@ __device__ __forceinline__ void walk_values(uint32_t bm, const double (&sv)[E + 
   double sn = rc.s;
 #pragma unroll
   for (int i = E - 1; i >= 0; --i) {
-    val[i] = (float)(offset + div_count(sn - sv[i], np - (k0 + i)));
+    val[i] = fin(offset + div_count(sn - sv[i], np - (k0 + i)), k0 + i, np);
     if ((bm >> i) & 1u) {
       np = k0 + i;
       sn = sv[i];
     }
   }
   // (np, sn) is now the first start in the thread's ranks (or rc): it closes the entering cluster
-  float cur = lc.pos >= 0 ? (float)(offset + div_count(sn - lc.s, np - lc.pos)) : 0.0f;
+  float cur = lc.pos >= 0 ? fin(offset + div_count(sn - lc.s, np - lc.pos), lc.pos, np) : 0.0f;
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     if ((bm >> i) & 1u) cur = val[i];

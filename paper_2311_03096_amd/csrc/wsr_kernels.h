@@ -8,6 +8,7 @@ namespace wsr {
 // Which segment a workgroup of the short-segment kernels solves.  Batched launches give a
 // schedule (sched[blockIdx.x] = segment id) over device offsets; single-segment launches give
 // (start, d) directly.  lambda comes from lam_arr[segment] when lam_arr != nullptr.
+// l1 = 1: the forward applies Alg. prox's l1 and rewinding lines (beta, rho) to every cluster.
 struct SegArgs {
   const int64_t* offsets;
   const int32_t* sched;
@@ -16,6 +17,9 @@ struct SegArgs {
   int64_t start;
   int d;
   int seg_id;
+  float beta = 0.0f;
+  float rho = 0.0f;
+  int l1 = 0;
 };
 
 template <int TMAX, int NT>

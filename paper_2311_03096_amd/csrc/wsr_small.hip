@@ -1,7 +1,7 @@
 // wsr_small.hip -- prox_{lam R} of segments that fit one workgroup (d <= TMAX), everything in LDS.
 //
-// One workgroup solves one segment end to end (Alg. prox without its l1 lines), E = TMAX/NT = 8
-// ranks per thread:
+// One workgroup solves one segment end to end (Alg. prox; its l1 and rewinding lines when
+// SegArgs::l1 is set), E = TMAX/NT = 8 ranks per thread:
 //   1. coalesced load of the FP32 weights, order-preserving u32 keys, non-finite check;
 //   2. sort with index payload: bucket-rank sort (value buckets, LDS atomics, rank = bucket start
 //      + smaller keys of the bucket), or a stable LSD radix sort in LDS (4 passes of 8 bits,
@@ -397,10 +397,12 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
 }
 
 // Given the hull vertices vert[0..ncl] (ranks, vert[ncl] == d) of S, write every rank k < d of
-// the thread's blocked range its cluster value offset + (S_b - S_a)/(b - a) at out[idx[k]].
-template <int NT, int E, typename SL>
+// the thread's blocked range the output fin(offset + (S_b - S_a)/(b - a), a, b) of its cluster
+// [a, b) at out[idx[k]].
+template <int NT, int E, typename SL, typename Fin>
 __device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int ncl, const double* S,
-                                                       double offset, const uint16_t* idx, float* out, int d) {
+                                                       double offset, const uint16_t* idx, float* out, int d,
+                                                       Fin fin) {
   const int k0 = threadIdx.x * E;
   if (k0 >= d) return;
   // cluster of k0: last i with vert[i] <= k0
@@ -414,14 +416,14 @@ __device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int
   }
   int a = vert[lo];
   int b = vert[lo + 1];
-  float v = (float)(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a));
+  float v = fin(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a), a, b);
   const int k1 = min(k0 + E, d);
   for (int k = k0; k < k1; ++k) {
     while (k >= b) {
       ++lo;
       a = b;
       b = vert[lo + 1];
-      v = (float)(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a));
+      v = fin(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a), a, b);
     }
     out[idx[k]] = v;
   }
@@ -469,7 +471,9 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     for (int r = 0; r < IPT; ++r) {
       const int p = wbase + r * kWave + lane;
       if (p < d) {
-        out[start + p] = nonfinite ? __builtin_nanf("") : key_to_float(k[r]);
+        const float x = key_to_float(k[r]);
+        out[start + p] = nonfinite ? __builtin_nanf("")
+                                   : (args.l1 ? l1_rewind((double)x, 0.0, args.beta, args.rho) : x);
         if (perm_out) perm_out[start + p] = p;
         atomicOr(&sm.lmask[(p + off) >> 5], 1u << ((p + off) & 31));
       }
@@ -526,7 +530,10 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     // S is no longer read once the rounds have converged: the results take its place
     uint16_t ixr[E];
     load_u16_block<E>(sm.idx, k0, ixr);
-    walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv);
+    if (args.l1)
+      walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv, L1Value{lamd, args.beta, args.rho, d});
+    else
+      walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv);
   } else {
     tile_hull<NT, E, SL, int16_t>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
     const int nv = sm.d.h.cnt[0];
@@ -536,7 +543,11 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
       atomicOr(&sm.lmask[(a + off) >> 5], 1u << ((a + off) & 31));
     }
     // values straight to their original positions (S still holds the sums)
-    scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d);
+    if (args.l1)
+      scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d,
+                                        L1Value{lamd, args.beta, args.rho, d});
+    else
+      scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d, PlainValue());
     staged = false;
   }
   __syncthreads();

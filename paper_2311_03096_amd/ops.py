@@ -63,6 +63,20 @@ def prox(w, lam, offsets=None):
     return ProxFunction.apply(flat, float(lam), offsets).view(w.shape)
 
 
+def prox_l1(w, lam, beta, rho=0.0, offsets=None):
+    """Alg. prox in full on a float32 GPU tensor: prox of lam*R + beta*l1 with rewinding rho,
+    per segment (the update of a proximal-gradient step; not differentiable here)."""
+    _check_f32(w.contiguous(), "w")
+    flat = w.contiguous().view(-1)
+    if offsets is None:
+        offsets = np.array([0, flat.numel()], dtype=np.int64)
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    out = torch.empty_like(flat)
+    ws = _workspace(_lib.wsr_workspace_bytes(offsets), flat.device)
+    _lib.wsr_prox_l1_forward(flat, out, offsets, lam, beta, rho, ws)
+    return out.view(w.shape)
+
+
 def row_offsets(shapes):
     """Offsets of per-row segments for a list of 2-D weight shapes laid out back to back."""
     offs = [0]
@@ -95,6 +109,12 @@ class BatchedProx:
         _check_f32(out, "out")
         _lib.wsr_prox_forward_batched(self.plan, w, out, lam, lam_scalar,
                                       self.perm if save else None, self.mask if save else None, self.ws)
+
+    def forward_l1(self, w, out, lam=None, lam_scalar=0.0, beta=0.0, rho=0.0):
+        """Alg. prox in full (l1 and rewinding lines) over every segment; saves nothing."""
+        _check_f32(w, "w")
+        _check_f32(out, "out")
+        _lib.wsr_prox_l1_forward_batched(self.plan, w, out, lam, lam_scalar, beta, rho, self.ws)
 
     def backward(self, g, gw):
         _lib.wsr_prox_backward_batched(self.plan, g, gw, self.perm, self.mask, self.ws)

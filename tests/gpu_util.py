@@ -175,3 +175,83 @@ def compare(w, offsets, g_res, o_res, rel_tol=1e-5, tie_rel=1e-6):
                  rank_decreases=int((dec > 0).sum()))
     assert not unexcused.any(), "partition differs at ranks %s" % (np.nonzero(unexcused)[0][:5] + 1)
     return stats
+
+
+def gpu_forward_l1(w, offsets, lam, beta, rho, batched=False, lam_arr=None):
+    """Alg. prox in full on the GPU (wsr_prox_l1_forward / _batched); returns the output."""
+    wt = dev(w)
+    out = torch.empty_like(wt)
+    if batched:
+        plan = wsr.wsr_plan_create(offsets)
+        try:
+            nb = wsr.wsr_plan_workspace_bytes(plan)
+            ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+            la = dev(np.asarray(lam_arr, np.float32)) if lam_arr is not None else None
+            wsr.wsr_prox_l1_forward_batched(plan, wt, out, la, lam, beta, rho, ws)
+            torch.cuda.synchronize()
+        finally:
+            wsr.wsr_plan_destroy(plan)
+    else:
+        nb = wsr.wsr_workspace_bytes(offsets)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        wsr.wsr_prox_l1_forward(wt, out, offsets, lam, beta, rho, ws)
+        torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def compare_l1(w, offsets, out, o_l1, o_plain, g_plain, beta, rho, rel_tol=1e-5, tie_rel=1e-6):
+    """Check the GPU output of Alg. prox in full against the oracle's.
+
+    o_plain / g_plain: the oracle's and the GPU's prox_{lam R} results with their partitions
+    (the l1 call makes the same collisions as the plain forward).  Two kinds of element are left
+    out of the value check, and counted: those whose prox_{lam R} value lies within
+    tie_rel * scale of +-beta (the zero test is decided in FP64 on either side, and at the
+    threshold both outcomes are within rounding of the exact value), and, when rho > 0, those
+    whose cluster is not the same set of ranks on both sides (near-ties that the compare of the
+    plain forward excuses; rewinding moves the output by rho times the mean velocity, which
+    depends on the cluster's extent, so there the outputs differ by more than rounding)."""
+    w = np.asarray(w, np.float32)
+    offsets = np.asarray(offsets, np.int64)
+    n = w.shape[0]
+    out = np.asarray(out, np.float64)
+    lens = np.diff(offsets)
+    seg_of = np.repeat(np.arange(lens.shape[0]), lens)
+    absw = np.abs(w.astype(np.float64))
+    scale = np.ones(lens.shape[0])
+    nz = lens > 0
+    scale[nz] = np.maximum.reduceat(absw, offsets[:-1][nz])
+    scale[(scale == 0) | ~np.isfinite(scale)] = 1.0
+    sc = scale[seg_of]
+    finite = np.isfinite(o_l1)
+    assert np.array_equal(np.isnan(out), ~finite), "NaN pattern differs"
+    u = o_plain["u"]
+    near_zero_test = finite & (np.abs(np.abs(u) - float(np.float32(beta))) < tie_rel * sc)
+    other_cluster = np.zeros(n, bool)
+    if rho > 0 and n:
+        sstart = seg_start_of_rank(offsets)
+        o_orig = sstart + o_plain["perm"].astype(np.int64)
+        g_orig = sstart + g_plain["perm"].astype(np.int64)
+        gid = np.empty(n, np.int64)
+        gid[g_orig] = np.cumsum(g_plain["start"].astype(np.int64))
+        o_first = np.nonzero(o_plain["start"])[0]
+        g_seq = gid[o_orig]  # GPU cluster id of each rank, in the oracle's rank order
+        lo = np.minimum.reduceat(g_seq, o_first)
+        hi = np.maximum.reduceat(g_seq, o_first)
+        o_size = np.diff(np.concatenate([o_first, [n]]))
+        g_size = np.bincount(gid)[lo]
+        same = (lo == hi) & (g_size == o_size)
+        other_cluster[o_orig] = np.repeat(~same, o_size)
+    skip = near_zero_test | other_cluster
+    err = np.abs(out - o_l1)
+    err[~finite | skip] = 0.0
+    ulp = np.spacing(np.abs(o_l1).astype(np.float32)).astype(np.float64)
+    ulp[~finite] = 0.0
+    bad = err > rel_tol * sc + 2 * ulp
+    assert not bad.any(), "value mismatch at %s: gpu %r oracle %r" % (
+        np.nonzero(bad)[0][:5], out[bad][:5], o_l1[bad][:5])
+    zeros_g = (out == 0.0) & finite & ~skip
+    zeros_o = (o_l1 == 0.0) & finite & ~skip
+    assert np.array_equal(zeros_g, zeros_o), "zeroed weights differ"
+    return dict(n=n, max_abs_err=float(err.max()) if n else 0.0,
+                max_rel_err=float((err / sc).max()) if n else 0.0, zeroed=int(zeros_o.sum()),
+                skipped_zero_test=int(near_zero_test.sum()), skipped_partition=int(other_cluster.sum()))

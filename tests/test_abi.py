@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 12
+    assert len(declared) == 14
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -75,6 +75,28 @@ def test_forward_argument_errors():
                                        None) == E
     assert wsr.load().wsr_prox_forward(FAKE, FAKE, off.ctypes.data_as(ctypes.c_void_p), -1,
                                        ctypes.c_float(0.1), None, None, None, 0, None) == E
+
+
+def test_l1_forward_argument_errors():
+    lib = wsr.load()
+    off = np.array([0, 4], np.int64)
+    po = off.ctypes.data_as(ctypes.c_void_p)
+    E = wsr.WSR_ERR_INVALID
+    f = ctypes.c_float
+
+    def l1(beta, rho, lam=0.1, w=FAKE):
+        return lib.wsr_prox_l1_forward(w, FAKE, po, 1, f(lam), f(beta), f(rho), None, 0, None)
+
+    for beta, rho in [(-0.1, 0.0), (float("nan"), 0.0), (float("inf"), 0.0), (0.1, -0.01), (0.1, 1.01),
+                      (0.1, float("nan"))]:
+        assert l1(beta, rho) == E
+    assert l1(0.1, 0.5, lam=-1.0) == E
+    assert l1(0.1, 0.5, w=None) == E
+    big = np.array([0, 1 << 20], np.int64)
+    assert lib.wsr_prox_l1_forward(FAKE, FAKE, big.ctypes.data_as(ctypes.c_void_p), 1, f(0.1), f(0.1), f(0.5),
+                                   None, 0, None) == wsr.WSR_ERR_WORKSPACE
+    assert lib.wsr_prox_l1_forward_batched(None, FAKE, FAKE, None, f(0.1), f(0.1), f(0.5), None, 0, None) == E
+    assert lib.wsr_prox_l1_forward_batched(FAKE, FAKE, FAKE, None, f(0.1), f(-1.0), f(0.5), None, 0, None) == E
 
 
 def test_backward_argument_errors():

@@ -1,0 +1,113 @@
+"""GPU parity of Alg. prox in full (l1 and rewinding lines) through the C ABI, against the
+oracle's wsr_oracle_prox_l1_* on the same seeded inputs.
+
+The collisions are those of the plain forward; the cases cover both kernel paths (one
+workgroup per segment, device-wide for long segments), the batched entry point with
+per-segment lambdas, the identity segments (lambda = 0, d = 1) where only the l1 rule acts,
+non-finite segments, and the paper's rewinding value rho = 0.98.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import NTHREADS, compare_l1, gpu_forward, gpu_forward_l1  # noqa: E402
+from paper_2311_03096_amd import workloads  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _check_l1(case, beta, rho, batched=False, lam_arr=None):
+    w, off, lam = case["w"], case["offsets"], case["lam"]
+    beta, rho = float(np.float32(beta)), float(np.float32(rho))
+    _say("l1 case", case.get("name"), "n", w.shape[0], "segments", off.shape[0] - 1, "beta", beta,
+         "rho", rho, "batched", batched)
+    lam_o = np.asarray(lam_arr, np.float32) if lam_arr is not None else lam
+    out = gpu_forward_l1(w, off, lam, beta, rho, batched=batched, lam_arr=lam_arr)
+    g_plain = gpu_forward(w, off, lam, batched=batched, lam_arr=lam_arr)
+    u, p, s = oracle.prox_segments(w, lam_o, off, n_threads=NTHREADS)
+    o_l1 = oracle.prox_l1_segments(w, lam_o, beta, rho, off, n_threads=NTHREADS)
+    st = compare_l1(w, off, out, o_l1, dict(u=u, perm=p, start=s), g_plain, beta, rho)
+    _say("  stats", st)
+    assert st["skipped_zero_test"] + st["skipped_partition"] <= max(8, w.shape[0] // 1000)
+    return out, st
+
+
+@pytest.mark.parametrize("beta,rho", [(0.0, 0.0), (0.3, 0.0), (0.3, 0.5), (0.05, 0.98), (0.0, 1.0), (2.5, 0.5)])
+def test_l1_d4096(beta, rho):
+    _check_l1(workloads.plain(4096, 0.1), beta, rho)
+
+
+@pytest.mark.parametrize("d", [1, 2, 65, 2049, 4097, 8192, 8193, 50000, 100003])
+@pytest.mark.parametrize("dist", ["normal", "ties", "laplace"])
+def test_l1_sizes(d, dist):
+    lam = {"normal": 0.05, "ties": 0.5, "laplace": 2.0}[dist]
+    case = workloads.random_segments([d], dist, lam, seed=d + 1)
+    beta = 0.2 * float(np.abs(case["w"]).max())
+    _check_l1(case, beta, 0.98)
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.98])
+def test_l1_long_typical(rho):
+    case = workloads.random_segments([(1 << 20) + 777], "normal", 0.1, seed=31)
+    _, st = _check_l1(case, 0.5, rho)
+    assert st["zeroed"] > 0
+
+
+def test_l1_chain_one_cluster():
+    case = workloads.chain(d=1 << 20)
+    out, _ = _check_l1(case, 0.1, 0.5)
+    assert np.ptp(out) == 0.0  # one cluster: one value
+
+
+def test_l1_batched_equals_plain_and_per_segment_lambda():
+    lens = [0, 1, 2, 3, 17, 64, 65, 1000, 2048, 2049, 3072, 4096, 4097, 8192, 8193, 20000, 0, 5, 33, 7000]
+    case = workloads.random_segments(lens, "mixed", 0.05, seed=5)
+    beta = 0.1 * float(np.abs(case["w"]).max())
+    o1, _ = _check_l1(case, beta, 0.98, batched=False)
+    o2, _ = _check_l1(case, beta, 0.98, batched=True)
+    assert np.array_equal(o1, o2)
+    lam_arr = np.linspace(0.0, 2.0, len(lens)).astype(np.float32)
+    _check_l1(case, beta, 0.25, batched=True, lam_arr=lam_arr)
+
+
+def test_l1_identity_and_nonfinite_segments():
+    lens = [1, 3000, 1, 9000, 50, 20000]
+    case = workloads.random_segments(lens, "normal", 0.0, seed=6)
+    w = case["w"].copy()
+    off = case["offsets"]
+    w[off[4] + 7] = np.nan  # the fifth segment holds a NaN
+    w[off[5] + 19999] = np.inf  # the last one an infinity (long segment)
+    case = dict(case, w=w)
+    for rho in (0.0, 0.6):
+        # lambda = 0 on every segment: the elementwise rule of the rewinding section's example
+        out, _ = _check_l1(case, 0.4, rho)
+        ok = np.isfinite(w)
+        seg_bad = np.zeros(w.shape[0], bool)
+        for s in (4, 5):
+            seg_bad[off[s]:off[s + 1]] = True
+        x = w.astype(np.float64)
+        b, r = float(np.float32(0.4)), float(np.float32(rho))  # the library takes FP32 arguments
+        exp = np.where(np.abs(x) < b, 0.0, x - (1 - r) * b * np.sign(x))
+        m = ok & ~seg_bad
+        ulp = np.spacing(np.abs(exp[m]).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(out[m] - exp[m]) <= ulp)  # one FP32 rounding of the FP64 value
+        assert np.isnan(out[seg_bad]).all()
+    lam_arr = np.array([0.3, 0.0, 1.0, 0.0, 0.2, 0.05], np.float32)
+    _check_l1(case, 0.4, 0.6, batched=True, lam_arr=lam_arr)
+
+
+def test_l1_mlp_rows_batched():
+    case = workloads.mlp_rows()
+    _, st = _check_l1(case, 0.01, 0.98, batched=True)
+    assert st["zeroed"] > 0
