@@ -50,6 +50,10 @@ def _load():
         lib.wsr_oracle_prox_l1_segments_f32.argtypes = [i64, p, p, p, ctypes.c_int, ctypes.c_float,
                                                         ctypes.c_float, p, ctypes.c_int]
         lib.wsr_oracle_prox_l1_segments_f32.restype = ctypes.c_int
+        lib.wsr_oracle_prox_step_segments_f32.argtypes = [i64, p, p, p, ctypes.c_float, p, ctypes.c_int,
+                                                          ctypes.c_float, ctypes.c_float, ctypes.c_int, p,
+                                                          ctypes.c_int]
+        lib.wsr_oracle_prox_step_segments_f32.restype = ctypes.c_int
         lib.wsr_oracle_vjp.argtypes = [i64, p, p, p, p, p]
         lib.wsr_oracle_vjp.restype = ctypes.c_int
         _lib = lib
@@ -124,6 +128,32 @@ def prox_l1_segments(w, lam, beta: float, rho: float, offsets=None, n_threads: i
     out = np.empty(n, np.float64)
     rc = _load().wsr_oracle_prox_l1_segments_f32(n_seg, _ptr(offsets), _ptr(w), _ptr(lam_arr), per_seg,
                                                  float(beta), float(rho), _ptr(out), int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
+    return out
+
+
+def prox_step_segments(w, grad, eta, alpha, beta, rho, offsets=None, eta_in_displacement=False,
+                       n_threads: int = 1):
+    """One proximal-gradient step per segment: z = fmaf(-eta, grad, w) in FP32, then Alg. prox in
+    full with lambda = eta*alpha, beta' = eta*beta (FP32 products), or, with
+    ``eta_in_displacement``, with alpha and beta unscaled and eta on the rewinding line.
+    Returns the FP64 output in the original order."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    grad = np.ascontiguousarray(grad, dtype=np.float32)
+    n = w.shape[0]
+    if offsets is None:
+        offsets = np.array([0, n], np.int64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_seg = offsets.shape[0] - 1
+    a = np.ascontiguousarray(np.atleast_1d(np.asarray(alpha, dtype=np.float32)))
+    per_seg = 1 if a.shape[0] == n_seg and n_seg != 1 else 0
+    if per_seg == 0 and a.shape[0] != 1:
+        raise ValueError("alpha must be a scalar or have one value per segment")
+    out = np.empty(n, np.float64)
+    rc = _load().wsr_oracle_prox_step_segments_f32(n_seg, _ptr(offsets), _ptr(w), _ptr(grad), float(eta),
+                                                   _ptr(a), per_seg, float(beta), float(rho),
+                                                   1 if eta_in_displacement else 0, _ptr(out), int(n_threads))
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return out

@@ -38,6 +38,8 @@
  *
  * Full Alg. prox (wsr_oracle_prox_l1_*): the same collisions, then the algorithm's
  * l1 and rewinding lines applied per cluster (prox of lam*R + beta*l1, rewinding rho).
+ * Proximal-gradient step (wsr_oracle_prox_step_*): the gradient step in FP32, then the full
+ * Alg. prox with eta in the coefficients or, as a variant, on the rewinding line.
  *
  * Gradient: the prox is piecewise affine; on the piece selected by the partition
  * its Jacobian averages within each cluster (symmetric, idempotent).  The
@@ -184,10 +186,23 @@ int wsr_oracle_prox_f64(int64_t d, const double* w, double lam, double* u, int64
  *   lam, beta >= 0 and finite; 0 <= rho <= 1.   out[d]: original order.
  * Returns 0, or -1 on bad arguments / allocation failure.
  */
+static int prox_l1_kappa(int64_t d, const double* w, double lam, double beta, double rho,
+                         double kappa, double* out);
+
 int wsr_oracle_prox_l1_f64(int64_t d, const double* w, double lam, double beta, double rho,
                            double* out) {
+    return prox_l1_kappa(d, w, lam, beta, rho, 1.0, out);
+}
+
+/*
+ * The same with the rewinding line scaled by kappa:  x_C += kappa * (1 - rho) * v_C.  kappa = 1
+ * is Alg. prox; kappa = eta is the variant of the experiments appendix (MNIST on a torus) that
+ * multiplies the learning rate into v on that line instead of into alpha and beta.
+ */
+static int prox_l1_kappa(int64_t d, const double* w, double lam, double beta, double rho,
+                         double kappa, double* out) {
     if (d < 0 || !(lam >= 0.0) || isinf(lam) || !(beta >= 0.0) || isinf(beta) ||
-        !(rho >= 0.0) || !(rho <= 1.0))
+        !(rho >= 0.0) || !(rho <= 1.0) || !(kappa >= 0.0) || isinf(kappa))
         return -1;
     if (d == 0) return 0;
     double* u = (double*)malloc(sizeof(double) * (size_t)d);
@@ -224,7 +239,7 @@ int wsr_oracle_prox_l1_f64(int64_t d, const double* w, double lam, double beta, 
                     x = 0.0;
                     v = 0.0;
                 }
-                x = x + (1.0 - rho) * v;
+                x = x + kappa * (1.0 - rho) * v;
                 for (int64_t j = k; j < e; ++j) out[perm[j]] = x;
                 k = e;
             }
@@ -247,6 +262,10 @@ typedef struct {
     uint8_t* start;
     int l1;            /* 1: Alg. prox with its l1 and rewinding lines (u receives its output) */
     double beta, rho;
+    double kappa;      /* rewinding-line scale (1, or eta in the eta-in-displacement step) */
+    const float* grad; /* non-NULL: the input is the gradient step fmaf(-eta, grad, w) */
+    float eta;
+    int lam_times_eta; /* the segment's lambda is the FP32 product eta * lambda */
     int rc;
 } seg_job_t;
 
@@ -256,7 +275,9 @@ static void* seg_worker(void* arg) {
     for (int64_t s = job->seg_lo; s < job->seg_hi; ++s) {
         int64_t o = job->offsets[s];
         int64_t d = job->offsets[s + 1] - o;
-        double lam = (double)(job->per_seg_lam ? job->lam[s] : job->lam[0]);
+        float lam32 = job->per_seg_lam ? job->lam[s] : job->lam[0];
+        if (job->lam_times_eta) lam32 = job->eta * lam32; /* one FP32 rounding */
+        double lam = (double)lam32;
         double* w64 = (double*)malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
         int64_t* p64 = (int64_t*)malloc(sizeof(int64_t) * (size_t)(d > 0 ? d : 1));
         if (!w64 || !p64) {
@@ -264,8 +285,12 @@ static void* seg_worker(void* arg) {
             job->rc = -1;
             return NULL;
         }
-        for (int64_t i = 0; i < d; ++i) w64[i] = (double)job->w[o + i]; /* exact promotion */
-        int rc = job->l1 ? wsr_oracle_prox_l1_f64(d, w64, lam, job->beta, job->rho, job->u + o)
+        for (int64_t i = 0; i < d; ++i) {
+            float x = job->w[o + i];
+            if (job->grad) x = fmaf(-job->eta, job->grad[o + i], x); /* gradient step, one rounding */
+            w64[i] = (double)x; /* exact promotion */
+        }
+        int rc = job->l1 ? prox_l1_kappa(d, w64, lam, job->beta, job->rho, job->kappa, job->u + o)
                          : wsr_oracle_prox_f64(d, w64, lam, job->u + o, p64,
                                                job->start ? job->start + o : NULL);
         if (rc) job->rc = rc;
@@ -285,9 +310,17 @@ static void* seg_worker(void* arg) {
  *   start: 1 at ranks that begin a cluster.  perm_local and start may be NULL.
  *   n_threads: segments are split across this many POSIX threads (>= 1).
  */
+typedef struct {
+    int l1;
+    double beta, rho, kappa;
+    const float* grad;
+    float eta;
+    int lam_times_eta;
+} seg_opts_t;
+
 static int run_segments(int64_t n_seg, const int64_t* offsets, const float* w, const float* lam,
                         int per_seg_lam, double* u, int32_t* perm_local, uint8_t* start,
-                        int n_threads, int l1, double beta, double rho) {
+                        int n_threads, seg_opts_t opt) {
     if (n_seg < 0 || !offsets || offsets[0] != 0) return -1;
     for (int64_t s = 0; s < n_seg; ++s) {
         if (offsets[s + 1] < offsets[s]) return -1;
@@ -317,9 +350,13 @@ static int run_segments(int64_t n_seg, const int64_t* offsets, const float* w, c
         jobs[t].u = u;
         jobs[t].perm_local = perm_local;
         jobs[t].start = start;
-        jobs[t].l1 = l1;
-        jobs[t].beta = beta;
-        jobs[t].rho = rho;
+        jobs[t].l1 = opt.l1;
+        jobs[t].beta = opt.beta;
+        jobs[t].rho = opt.rho;
+        jobs[t].kappa = opt.kappa;
+        jobs[t].grad = opt.grad;
+        jobs[t].eta = opt.eta;
+        jobs[t].lam_times_eta = opt.lam_times_eta;
     }
     int rc = 0;
     if (n_threads == 1) {
@@ -340,8 +377,8 @@ static int run_segments(int64_t n_seg, const int64_t* offsets, const float* w, c
 int wsr_oracle_prox_segments_f32(int64_t n_seg, const int64_t* offsets, const float* w,
                                  const float* lam, int per_seg_lam, double* u,
                                  int32_t* perm_local, uint8_t* start, int n_threads) {
-    return run_segments(n_seg, offsets, w, lam, per_seg_lam, u, perm_local, start, n_threads, 0,
-                        0.0, 0.0);
+    seg_opts_t opt = {0, 0.0, 0.0, 1.0, NULL, 0.0f, 0};
+    return run_segments(n_seg, offsets, w, lam, per_seg_lam, u, perm_local, start, n_threads, opt);
 }
 
 /*
@@ -353,8 +390,42 @@ int wsr_oracle_prox_l1_segments_f32(int64_t n_seg, const int64_t* offsets, const
                                     const float* lam, int per_seg_lam, float beta, float rho,
                                     double* out, int n_threads) {
     if (!(beta >= 0.0f) || isinf(beta) || !(rho >= 0.0f) || !(rho <= 1.0f)) return -1;
-    return run_segments(n_seg, offsets, w, lam, per_seg_lam, out, NULL, NULL, n_threads, 1,
-                        (double)beta, (double)rho);
+    seg_opts_t opt = {1, (double)beta, (double)rho, 1.0, NULL, 0.0f, 0};
+    return run_segments(n_seg, offsets, w, lam, per_seg_lam, out, NULL, NULL, n_threads, opt);
+}
+
+/*
+ * One proximal-gradient step (Sec. 1 update with Alg. prox in full): every weight first takes
+ * the gradient step z = fmaf(-eta, grad, w) in FP32 (one rounding), then each segment gets
+ *   eta_in_displacement == 0:  Alg. prox of z with lambda = eta*alpha_s (FP32 product),
+ *                              beta' = eta*beta (FP32 product) and rho, i.e. the prox of
+ *                              eta*(alpha R + beta l1) with rewinding;
+ *   eta_in_displacement == 1:  Alg. prox of z with alpha_s and beta unscaled and the rewinding
+ *                              line x += eta (1 - rho) v (experiments appendix, MNIST on a torus).
+ * alpha: one value or n_seg values (per_seg_alpha).  out: FP64, original order.
+ */
+int wsr_oracle_prox_step_segments_f32(int64_t n_seg, const int64_t* offsets, const float* w,
+                                      const float* grad, float eta, const float* alpha,
+                                      int per_seg_alpha, float beta, float rho,
+                                      int eta_in_displacement, double* out, int n_threads) {
+    if (!grad || !(eta >= 0.0f) || isinf(eta)) return -1;
+    if (!(beta >= 0.0f) || isinf(beta) || !(rho >= 0.0f) || !(rho <= 1.0f)) return -1;
+    seg_opts_t opt;
+    opt.l1 = 1;
+    opt.rho = (double)rho;
+    opt.grad = grad;
+    opt.eta = eta;
+    if (eta_in_displacement) {
+        opt.beta = (double)beta;
+        opt.kappa = (double)eta;
+        opt.lam_times_eta = 0;
+    } else {
+        float b = eta * beta; /* one FP32 rounding */
+        opt.beta = (double)b;
+        opt.kappa = 1.0;
+        opt.lam_times_eta = 1;
+    }
+    return run_segments(n_seg, offsets, w, alpha, per_seg_alpha, out, NULL, NULL, n_threads, opt);
 }
 
 /*

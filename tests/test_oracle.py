@@ -506,3 +506,61 @@ def test_l1_nonfinite_and_bad_args():
                            (0.1, np.nan, 0.0), (0.1, 0.1, np.nan), (0.1, np.inf, 0.0)]:
         with pytest.raises(ValueError):
             oracle.prox_l1_f64(np.array([1.0, 2.0]), lam, beta, rho)
+
+
+# ----------------------------------------------------------------------------- proximal-gradient step
+
+def _rewound(P, w, kappa_one_minus_rho):
+    """x + k (P - x) per group of equal entries of the brute-force minimiser P, zero on its zero
+    group (x = mean weight of the group): the rewinding split of Alg. prox."""
+    vals, inv = np.unique(P, return_inverse=True)
+    exp = np.empty(P.shape[0])
+    for gi, val in enumerate(vals):
+        m = inv == gi
+        xbar = w[m].mean()
+        exp[m] = 0.0 if val == 0.0 else xbar + kappa_one_minus_rho * (val - xbar)
+    return exp
+
+
+def test_step_against_brute_force():
+    """z = w - eta*g (exact here: eta = 1/2 or 1/4 and weights and gradients of similar size,
+    so the FP32 gradient step has one rounding on both routes); the step is the prox of
+    eta*(alpha R + beta l1) at z with rewinding, or, with eta on the rewinding line, the prox of
+    alpha R + beta l1 at z with x + eta (1 - rho) v."""
+    rng = np.random.default_rng(26)
+    for d in [2, 3, 4, 5]:
+        for _ in range(10):
+            w = rng.normal(size=d).astype(np.float32)
+            g = rng.normal(size=d).astype(np.float32)
+            eta = float(rng.choice([0.5, 0.25]))
+            alpha = np.float32(rng.choice([0.0, 0.1, 0.5, 2.0]))
+            beta = np.float32(rng.choice([0.0, 0.1, 0.4]))
+            rho = float(np.float32(rng.choice([0.0, 0.5, 0.98])))
+            z = (w.astype(np.float64) - eta * g.astype(np.float64)).astype(np.float32).astype(np.float64)
+            off = np.array([0, d], np.int64)
+            tol = 1e-9 * (1 + np.abs(z).max())
+            got = oracle.prox_step_segments(w, g, eta, alpha, beta, rho, off)
+            P = pins.brute_force_prox_l1(z, float(np.float32(eta * alpha)), float(np.float32(eta * beta)))
+            np.testing.assert_allclose(got, _rewound(P, z, 1.0 - rho), atol=tol)
+            got = oracle.prox_step_segments(w, g, eta, alpha, beta, rho, off, eta_in_displacement=True)
+            P = pins.brute_force_prox_l1(z, float(alpha), float(beta))
+            np.testing.assert_allclose(got, _rewound(P, z, eta * (1.0 - rho)), atol=tol)
+
+
+def test_step_modes_agree_at_unit_eta_and_per_segment_alpha():
+    rng = np.random.default_rng(27)
+    lens = [0, 1, 5, 300, 4096, 7]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = rng.normal(size=off[-1]).astype(np.float32)
+    g = rng.normal(size=off[-1]).astype(np.float32)
+    alpha = rng.uniform(0, 0.2, size=len(lens)).astype(np.float32)
+    a = oracle.prox_step_segments(w, g, 1.0, alpha, 0.2, 0.5, off)
+    b = oracle.prox_step_segments(w, g, 1.0, alpha, 0.2, 0.5, off, eta_in_displacement=True, n_threads=3)
+    np.testing.assert_array_equal(a, b)
+    # with a zero gradient the standard step is Alg. prox with eta folded into the coefficients
+    eta = np.float32(0.3)
+    c = oracle.prox_step_segments(w, np.zeros_like(g), eta, alpha, 0.2, 0.5, off)
+    np.testing.assert_array_equal(c, oracle.prox_l1_segments(w, (eta * alpha).astype(np.float32),
+                                                             np.float32(eta * np.float32(0.2)), 0.5, off))
+    with pytest.raises(ValueError):
+        oracle.prox_step_segments(w, g, -1.0, alpha, 0.2, 0.5, off)
