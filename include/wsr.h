@@ -174,6 +174,30 @@ WSR_API int wsr_prox_l1_forward_batched(const wsr_plan* plan, const float* w, fl
                                         const float* d_lambda, float lambda_scalar, float beta,
                                         float rho, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * One proximal-gradient step over every segment of the plan (Sec. 1 update of w with step size
+ * eta and the prox of alpha*R + beta*l1; App. A.1 eq. pgd), with Alg. prox in full:
+ *     z   = fmaf(-eta, grad, w)               elementwise, FP32, one rounding
+ *     out = Alg. prox of z, per segment
+ * flags = 0: the prox of eta*(alpha_s R + beta l1) with rewinding rho, i.e. wsr_prox_l1_forward
+ *            with lambda = eta*alpha_s and beta' = eta*beta (both FP32 products);
+ * flags = WSR_STEP_ETA_IN_DISPLACEMENT: the variant of the experiments appendix (MNIST on a
+ *            torus) that multiplies the learning rate into the remaining displacement instead of
+ *            into alpha and beta: collisions and the zero test use alpha_s and beta, and the
+ *            rewinding line becomes x_C += eta (1 - rho) v_C.
+ *   w[N], grad[N] device inputs;  out[N] device output, may alias w or grad (in-place update)
+ *   eta           finite, >= 0
+ *   d_alpha       device array of n_seg FP32 alphas, or NULL to use alpha_scalar everywhere
+ *   beta, rho     as in wsr_prox_l1_forward
+ * Short segments take the gradient step inside the prox kernel's load; long segments write z
+ * to out first (one extra elementwise pass) and run the device-wide path in place.  No state
+ * is saved.  Other arguments as in wsr_prox_forward_batched.
+ */
+#define WSR_STEP_ETA_IN_DISPLACEMENT 1
+WSR_API int wsr_prox_step_batched(const wsr_plan* plan, const float* w, const float* grad, float eta,
+                                  float* out, const float* d_alpha, float alpha_scalar, float beta,
+                                  float rho, int flags, void* ws, size_t ws_bytes, void* stream);
+
 /* Batched backward over every segment of the plan (see wsr_prox_backward). */
 WSR_API int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,
                               const int32_t* saved_perm, const uint32_t* saved_mask, void* ws,

@@ -54,6 +54,8 @@ def _load():
                                                           ctypes.c_float, ctypes.c_float, ctypes.c_int, p,
                                                           ctypes.c_int]
         lib.wsr_oracle_prox_step_segments_f32.restype = ctypes.c_int
+        lib.wsr_oracle_grad_step_f32.argtypes = [i64, p, p, ctypes.c_float, p]
+        lib.wsr_oracle_grad_step_f32.restype = ctypes.c_int
         lib.wsr_oracle_vjp.argtypes = [i64, p, p, p, p, p]
         lib.wsr_oracle_vjp.restype = ctypes.c_int
         _lib = lib
@@ -157,6 +159,17 @@ def prox_step_segments(w, grad, eta, alpha, beta, rho, offsets=None, eta_in_disp
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return out
+
+
+def grad_step(w, grad, eta):
+    """z = fmaf(-eta, grad, w) in FP32 (one rounding per element)."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    grad = np.ascontiguousarray(grad, dtype=np.float32)
+    z = np.empty_like(w)
+    rc = _load().wsr_oracle_grad_step_f32(w.shape[0], _ptr(w), _ptr(grad), float(eta), _ptr(z))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
+    return z
 
 
 def vjp(g, perm_local, start, offsets=None):

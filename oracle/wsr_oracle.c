@@ -394,6 +394,13 @@ int wsr_oracle_prox_l1_segments_f32(int64_t n_seg, const int64_t* offsets, const
     return run_segments(n_seg, offsets, w, lam, per_seg_lam, out, NULL, NULL, n_threads, opt);
 }
 
+/* The gradient step alone: z[i] = fmaf(-eta, grad[i], w[i]) in FP32 (one rounding). */
+int wsr_oracle_grad_step_f32(int64_t n, const float* w, const float* grad, float eta, float* z) {
+    if (n < 0 || (n > 0 && (!w || !grad || !z))) return -1;
+    for (int64_t i = 0; i < n; ++i) z[i] = fmaf(-eta, grad[i], w[i]);
+    return 0;
+}
+
 /*
  * One proximal-gradient step (Sec. 1 update with Alg. prox in full): every weight first takes
  * the gradient step z = fmaf(-eta, grad, w) in FP32 (one rounding), then each segment gets

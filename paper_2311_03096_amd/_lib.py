@@ -17,13 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libwsr.so")
 
 WSR_OK, WSR_ERR_INVALID, WSR_ERR_WORKSPACE, WSR_ERR_HIP, WSR_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 WSR_PLAN_AUTOTUNE = 1
+WSR_STEP_ETA_IN_DISPLACEMENT = 1
 WSR_MAX_SEGMENT = 1 << 26
 
 EXPORTED = (
     "wsr_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_prox_forward",
     "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy", "wsr_plan_workspace_bytes",
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
-    "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched",
+    "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
 )
 
 
@@ -55,6 +56,7 @@ def load():
         "wsr_prox_backward": ([p, p, p, i64, p, p, p, sz, p], i32),
         "wsr_prox_l1_forward": ([p, p, p, i64, f32, f32, f32, p, sz, p], i32),
         "wsr_prox_l1_forward_batched": ([p, p, p, p, f32, f32, f32, p, sz, p], i32),
+        "wsr_prox_step_batched": ([p, p, p, f32, p, p, f32, f32, f32, i32, p, sz, p], i32),
         "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
         "wsr_plan_destroy": ([p], i32),
         "wsr_plan_workspace_bytes": ([p, ctypes.POINTER(sz)], i32),
@@ -181,6 +183,14 @@ def wsr_prox_l1_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, beta=0.0
     _check("wsr_prox_l1_forward_batched", load().wsr_prox_l1_forward_batched(
         plan, _ptr(w), _ptr(out), _ptr(lam), float(lam_scalar), float(beta), float(rho), wp, wn,
         _stream(stream)))
+
+
+def wsr_prox_step_batched(plan, w, grad, eta, out, alpha=None, alpha_scalar=0.0, beta=0.0, rho=0.0, flags=0,
+                          ws=None, stream=None):
+    wp, wn = _ws_args(ws)
+    _check("wsr_prox_step_batched", load().wsr_prox_step_batched(
+        plan, _ptr(w), _ptr(grad), float(eta), _ptr(out), _ptr(alpha), float(alpha_scalar), float(beta),
+        float(rho), int(flags), wp, wn, _stream(stream)))
 
 
 def wsr_prox_backward_batched(plan, grad_out, grad_w, saved_perm, saved_mask, ws=None, stream=None):

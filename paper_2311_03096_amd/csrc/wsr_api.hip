@@ -60,6 +60,7 @@ int validate_offsets(const int64_t* h_offsets, int64_t n_seg, int64_t* max_big) 
 // Workspace of the long-segment path for segments of length <= d.
 struct BigWs {
   uint32_t* flags;
+  float* lamtmp;   // a segment's lambda formed on the device (proximal-gradient step)
   uint32_t* tbad;  // per radix tile: non-finite weight seen (first pass)
   uint32_t *keysA, *keysB;
   int32_t *valsA, *valsB;
@@ -86,6 +87,7 @@ BigWs big_layout(int64_t d, void* base) {
     return p;
   };
   w.flags = (uint32_t*)take(256);
+  w.lamtmp = (float*)take(256);
   w.tbad = (uint32_t*)take(sizeof(uint32_t) * nrt);
   w.keysA = (uint32_t*)take(sizeof(uint32_t) * d);
   w.keysB = (uint32_t*)take(sizeof(uint32_t) * d);
@@ -219,6 +221,7 @@ struct L1Opt {
   float beta = 0.0f;
   float rho = 0.0f;
   int on = 0;
+  float kappa = 1.0f;  // scale of the rewinding line
 };
 
 bool l1_args_ok(float beta, float rho) {
@@ -294,7 +297,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   { WSR_TRACE("big_apply", s);
   hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, perm_final, d, lam_arr, seg_id,
                      lam_scalar, b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
-                     b.next_pos, b.next_s, out, saved_mask, start, l1.beta, l1.rho, l1.on); }
+                     b.next_pos, b.next_s, out, saved_mask, start, l1.beta, l1.rho, l1.kappa, l1.on); }
   return last_error();
 }
 
@@ -396,7 +399,7 @@ int forward_impl(const float* w, float* out, const int64_t* h_offsets, int64_t n
       if (rc) return rc;
       continue;
     }
-    SegArgs a{nullptr, nullptr, nullptr, lambda, start, (int)d, 0, l1.beta, l1.rho, l1.on};
+    SegArgs a{nullptr, nullptr, nullptr, lambda, start, (int)d, 0, l1.beta, l1.rho, l1.on, l1.kappa};
     small_fwd(cls, 1, a, w, out, saved_perm, saved_mask, s);
   }
   return last_error();
@@ -416,13 +419,60 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0,
-              l1.beta, l1.rho, l1.on};
+              l1.beta, l1.rho, l1.on, l1.kappa};
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
   for (int32_t seg : plan->big_segs) {
     const int64_t start = plan->h_offsets[seg];
     const int64_t d = plan->h_offsets[seg + 1] - start;
     const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s, l1);
+    if (rc) return rc;
+  }
+  return last_error();
+}
+
+int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, float eta, float* out,
+                      const float* d_alpha, float alpha_scalar, float beta, float rho, int flags, void* ws,
+                      size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!plan || !w || !grad || !out) return WSR_ERR_INVALID;
+  if (flags & ~WSR_STEP_ETA_IN_DISPLACEMENT) return WSR_ERR_INVALID;
+  if (!std::isfinite(eta) || eta < 0.0f || !l1_args_ok(beta, rho)) return WSR_ERR_INVALID;
+  if (!d_alpha && (!std::isfinite(alpha_scalar) || alpha_scalar < 0.0f)) return WSR_ERR_INVALID;
+  const size_t need = big_bytes(plan->max_big);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  const bool variant = (flags & WSR_STEP_ETA_IN_DISPLACEMENT) != 0;
+  // standard: the prox of eta*(alpha R + beta l1): lambda = eta*alpha, beta' = eta*beta (FP32);
+  // variant: alpha and beta unscaled, eta on the rewinding line
+  const float lam_mul = variant ? 1.0f : eta;
+  L1Opt l1{variant ? beta : eta * beta, rho, 1, variant ? eta : 1.0f};
+  hipStream_t s = (hipStream_t)stream;
+  for (int c = 0; c < kNumSmall; ++c) {
+    if (plan->sched_cnt[c] == 0) continue;
+    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
+              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul};
+    small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s);
+  }
+  for (int32_t seg : plan->big_segs) {
+    const int64_t start = plan->h_offsets[seg];
+    const int64_t d = plan->h_offsets[seg + 1] - start;
+    {
+      WSR_TRACE("grad_step", s);
+      const int64_t blocks = std::min<int64_t>(ceil_div(d, 256), 4 * (int64_t)cu_count());
+      hipLaunchKernelGGL(k_grad_step, dim3((unsigned)blocks), dim3(256), 0, s, out + start, w + start,
+                         grad + start, eta, d);
+    }
+    const float* lam_arr = d_alpha;
+    int lam_seg = seg;
+    float lam_scalar = alpha_scalar * lam_mul;
+    if (d_alpha && !variant) {
+      BigWs b = big_layout(d, ws);
+      WSR_TRACE("scale_lambda", s);
+      hipLaunchKernelGGL(k_scale_lambda, dim3(1), dim3(64), 0, s, b.lamtmp, d_alpha, seg, alpha_scalar, lam_mul);
+      lam_arr = b.lamtmp;
+      lam_seg = 0;
+    }
+    const int rc = big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, l1);
     if (rc) return rc;
   }
   return last_error();
@@ -555,6 +605,13 @@ int wsr_prox_l1_forward_batched(const wsr_plan* plan, const float* w, float* out
   if (!l1_args_ok(beta, rho)) return WSR_ERR_INVALID;
   return forward_batched_impl(plan, w, out, d_lambda, lambda_scalar, nullptr, nullptr, ws, ws_bytes, stream,
                               L1Opt{beta, rho, 1});
+}
+
+int wsr_prox_step_batched(const wsr_plan* plan, const float* w, const float* grad, float eta, float* out,
+                          const float* d_alpha, float alpha_scalar, float beta, float rho, int flags, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return step_batched_impl(plan, w, grad, eta, out, d_alpha, alpha_scalar, beta, rho, flags, ws, ws_bytes,
+                           stream);
 }
 
 int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,

@@ -909,7 +909,7 @@ struct ApplySmem {
 // recomputed from the sorted keys by the tile kernel's own operations (dense tiles); each thread
 // then sweeps its ranks with the neighbouring starts from the other threads (carry exchange) or
 // from the merge (tile ends).  l1 != 0: each cluster's output goes through Alg. prox's l1 and
-// rewinding lines (beta, rho).
+// rewinding lines (beta, rho, rewinding-line scale kappa).
 __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys, const int32_t* perm,
                                                            int64_t d, const float* lam_arr, int seg_id,
                                                            float lam_scalar, const uint32_t* flags,
@@ -920,7 +920,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
                                                            const double* prev_s, const int32_t* next_pos,
                                                            const double* next_s, float* out,
                                                            uint32_t* mask_out, int64_t seg_start,
-                                                           float beta, float rho, int l1) {
+                                                           float beta, float rho, float kappa, int l1) {
   constexpr int R = kBigTile / kBigThreads;
   __shared__ ApplySmem sm;
   const int tid = threadIdx.x;
@@ -965,7 +965,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
       if (j < np) {
         const float x = key_to_float(kt[j]);
         *at_u32(og, (uint32_t)pl[r]) =
-            nonfinite ? __builtin_nanf("") : (l1 ? l1_rewind((double)x, 0.0, beta, rho) : x);
+            nonfinite ? __builtin_nanf("") : (l1 ? L1Rewind(beta, rho, kappa)((double)x, 0.0) : x);
       }
     }
     mark(nmine > 0 ? (1u << nmine) - 1u : 0u);
@@ -989,6 +989,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   }
   const double c = (double)key_to_float(skeys[d >> 1]);
   const double lamd = (double)lam / (double)(d - 1);
+  const L1Rewind l1f(beta, rho, kappa);
   const double toff = tileoff[t];
   const int ppos = prev_pos[t];
   const double ps = prev_s[t];
@@ -1067,7 +1068,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
       dS = gb - ga;
     }
     const double u = c + dS / (double)(pb - pa);
-    return l1 ? l1_rewind(u, lamd * (double)(d - pa - pb), beta, rho) : (float)u;
+    return l1 ? l1f(u, lamd * (double)(d - pa - pb)) : (float)u;
   };
   // second pass, left to right: each start closes the open cluster, whose value then goes to its
   // ranks in this thread.  Rank i's key is read before any value lands on it; the exchange

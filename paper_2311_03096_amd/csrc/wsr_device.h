@@ -639,20 +639,28 @@ struct PlainValue {
 };
 
 // Output of a cluster of ranks [a, b) under Alg. prox's l1 and rewinding lines (prox of
-// lam*R + beta*l1, rewinding rho): u is the cluster's prox_{lam R} value, its mean velocity is
-// v = lam (d - a - b)/(d - 1) (lamd = lam/(d - 1)) and its mean weight x = u - v.  The cluster
-// is zeroed when |u| < beta, else it gets x + (1 - rho)(v - beta sign(u)).  FP64, one rounding.
-__device__ __forceinline__ float l1_rewind(double u, double v, double beta, double rho) {
-  if (fabs(u) < beta) return 0.0f;
-  const double sgn = u > 0.0 ? 1.0 : (u < 0.0 ? -1.0 : 0.0);
-  const double x = u - v;
-  return (float)(x + (1.0 - rho) * (v - beta * sgn));
-}
+// lam*R + beta*l1, rewinding rho, rewinding line scaled by kappa): u is the cluster's
+// prox_{lam R} value, its mean velocity is v = lam (d - a - b)/(d - 1) and its mean weight
+// x = u - v.  The cluster is zeroed when |u| < beta, else it gets
+//   x + kappa (1 - rho)(v - beta sign(u)) = u - q v - kappa (1 - rho) beta sign(u),
+// q = 1 - kappa (1 - rho), evaluated in the second form (at u == 0 the sign term matters only
+// when beta == 0, where it vanishes).  kappa = 1 is Alg. prox; kappa = eta is the variant with
+// the learning rate on the rewinding line.  FP64, one rounding.
+struct L1Rewind {
+  double beta, q, omb;
+  __host__ __device__ L1Rewind(float b, float r, float k)
+      : beta(b), q(1.0 - (double)k * (1.0 - (double)r)), omb((double)k * (1.0 - (double)r) * (double)b) {}
+  __device__ __forceinline__ float operator()(double u, double v) const {
+    const double r = fma(-q, v, u) - (u > 0.0 ? omb : -omb);
+    return fabs(u) < beta ? 0.0f : (float)r;
+  }
+};
 struct L1Value {
-  double lamd, beta, rho;
+  L1Rewind f;
+  double lamd;  // lam / (d - 1)
   int d;
   __device__ __forceinline__ float operator()(double u, int a, int b) const {
-    return l1_rewind(u, lamd * (double)(d - a - b), beta, rho);
+    return f(u, lamd * (double)(d - a - b));
   }
 };
 

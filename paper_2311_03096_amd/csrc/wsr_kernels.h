@@ -8,7 +8,9 @@ namespace wsr {
 // Which segment a workgroup of the short-segment kernels solves.  Batched launches give a
 // schedule (sched[blockIdx.x] = segment id) over device offsets; single-segment launches give
 // (start, d) directly.  lambda comes from lam_arr[segment] when lam_arr != nullptr.
-// l1 = 1: the forward applies Alg. prox's l1 and rewinding lines (beta, rho) to every cluster.
+// l1 = 1: the forward applies Alg. prox's l1 and rewinding lines (beta, rho, rewinding-line
+// scale kappa) to every cluster.  grad != nullptr: the forward's input is the gradient step
+// fmaf(-eta, grad, w), and the segment's lambda is multiplied by lam_mul (FP32).
 struct SegArgs {
   const int64_t* offsets;
   const int32_t* sched;
@@ -20,6 +22,10 @@ struct SegArgs {
   float beta = 0.0f;
   float rho = 0.0f;
   int l1 = 0;
+  float kappa = 1.0f;
+  const float* grad = nullptr;
+  float eta = 0.0f;
+  float lam_mul = 1.0f;
 };
 
 template <int TMAX, int NT>
@@ -29,5 +35,7 @@ template <int TMAX, int NT>
 __global__ void k_prox_bwd_small(SegArgs args, const float* gin, float* gout, const int32_t* perm_in,
                                  const uint32_t* mask_in);
 __global__ void k_zero_u32(uint32_t* p, int64_t n);
+__global__ void k_grad_step(float* out, const float* w, const float* grad, float eta, int64_t n);
+__global__ void k_scale_lambda(float* dst, const float* lam_arr, int seg_id, float lam_scalar, float mul);
 
 }  // namespace wsr

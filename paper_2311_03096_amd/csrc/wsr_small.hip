@@ -81,9 +81,9 @@ __device__ __forceinline__ SegView resolve_segment(const SegArgs& a) {
   if (a.sched) {
     const int s = a.sched[blockIdx.x];
     const int64_t o = a.offsets[s];
-    return SegView{o, (int)(a.offsets[s + 1] - o), a.lam_arr ? a.lam_arr[s] : a.lam_scalar};
+    return SegView{o, (int)(a.offsets[s + 1] - o), (a.lam_arr ? a.lam_arr[s] : a.lam_scalar) * a.lam_mul};
   }
-  return SegView{a.start, a.d, a.lam_arr ? a.lam_arr[a.seg_id] : a.lam_scalar};
+  return SegView{a.start, a.d, (a.lam_arr ? a.lam_arr[a.seg_id] : a.lam_scalar) * a.lam_mul};
 }
 
 // Waves per SIMD the forward kernel is compiled for (register budget): the 4096 class fits
@@ -455,6 +455,16 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     const int p = wbase + r * kWave + lane;
     f[r] = p < d ? w[start + p] : 0.0f;
   }
+  if (args.grad) {  // proximal-gradient step: the input is w - eta * grad, one FP32 rounding
+    float gv[IPT];
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) {
+      const int p = wbase + r * kWave + lane;
+      gv[r] = p < d ? args.grad[start + p] : 0.0f;
+    }
+#pragma unroll
+    for (int r = 0; r < IPT; ++r) f[r] = __builtin_fmaf(-args.eta, gv[r], f[r]);
+  }
   int bad = 0;
 #pragma unroll
   for (int r = 0; r < IPT; ++r) {
@@ -473,7 +483,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
       if (p < d) {
         const float x = key_to_float(k[r]);
         out[start + p] = nonfinite ? __builtin_nanf("")
-                                   : (args.l1 ? l1_rewind((double)x, 0.0, args.beta, args.rho) : x);
+                                   : (args.l1 ? L1Rewind(args.beta, args.rho, args.kappa)((double)x, 0.0) : x);
         if (perm_out) perm_out[start + p] = p;
         atomicOr(&sm.lmask[(p + off) >> 5], 1u << ((p + off) & 31));
       }
@@ -531,7 +541,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     uint16_t ixr[E];
     load_u16_block<E>(sm.idx, k0, ixr);
     if (args.l1)
-      walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv, L1Value{lamd, args.beta, args.rho, d});
+      walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv, L1Value{L1Rewind(args.beta, args.rho, args.kappa), lamd, d});
     else
       walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv);
   } else {
@@ -545,7 +555,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     // values straight to their original positions (S still holds the sums)
     if (args.l1)
       scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d,
-                                        L1Value{lamd, args.beta, args.rho, d});
+                                        L1Value{L1Rewind(args.beta, args.rho, args.kappa), lamd, d});
     else
       scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d, PlainValue());
     staged = false;
@@ -669,6 +679,19 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = i; j < n; j += stride) p[j] = 0u;
+}
+
+// Gradient step of a proximal-gradient update: out = fmaf(-eta, grad, w), one FP32 rounding
+// (out may alias w or grad).
+__global__ void k_grad_step(float* out, const float* w, const float* grad, float eta, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = i; j < n; j += stride) out[j] = __builtin_fmaf(-eta, grad[j], w[j]);
+}
+
+// dst[0] = (lam_arr ? lam_arr[seg_id] : lam_scalar) * mul, one FP32 rounding (one thread).
+__global__ void k_scale_lambda(float* dst, const float* lam_arr, int seg_id, float lam_scalar, float mul) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) dst[0] = (lam_arr ? lam_arr[seg_id] : lam_scalar) * mul;
 }
 
 #define WSR_INSTANTIATE_SMALL(TM, NTH)                                                          \

@@ -116,6 +116,17 @@ class BatchedProx:
         _check_f32(out, "out")
         _lib.wsr_prox_l1_forward_batched(self.plan, w, out, lam, lam_scalar, beta, rho, self.ws)
 
+    def step(self, w, grad, eta, alpha=None, alpha_scalar=0.0, beta=0.0, rho=0.0, eta_in_displacement=False,
+             out=None):
+        """One proximal-gradient step w <- Prox(w - eta*grad) over every segment (in place unless
+        ``out`` is given); ``alpha`` is a device tensor of per-segment coefficients or None."""
+        _check_f32(w, "w")
+        _check_f32(grad, "grad")
+        out = w if out is None else out
+        _lib.wsr_prox_step_batched(self.plan, w, grad, eta, out, alpha, alpha_scalar, beta, rho,
+                                   _lib.WSR_STEP_ETA_IN_DISPLACEMENT if eta_in_displacement else 0, self.ws)
+        return out
+
     def backward(self, g, gw):
         _lib.wsr_prox_backward_batched(self.plan, g, gw, self.perm, self.mask, self.ws)
 

@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 14
+    assert len(declared) == 15
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -97,6 +97,28 @@ def test_l1_forward_argument_errors():
                                    None, 0, None) == wsr.WSR_ERR_WORKSPACE
     assert lib.wsr_prox_l1_forward_batched(None, FAKE, FAKE, None, f(0.1), f(0.1), f(0.5), None, 0, None) == E
     assert lib.wsr_prox_l1_forward_batched(FAKE, FAKE, FAKE, None, f(0.1), f(-1.0), f(0.5), None, 0, None) == E
+
+
+def test_step_argument_errors():
+    lib = wsr.load()
+    E = wsr.WSR_ERR_INVALID
+    f = ctypes.c_float
+
+    def step(plan=FAKE, w=FAKE, g=FAKE, eta=0.1, out=FAKE, alpha=None, a=0.1, beta=0.1, rho=0.5, flags=0):
+        return lib.wsr_prox_step_batched(plan, w, g, f(eta), out, alpha, f(a), f(beta), f(rho), flags, None, 0,
+                                         None)
+
+    assert step(plan=None) == E
+    assert step(w=None) == E
+    assert step(g=None) == E
+    assert step(out=None) == E
+    assert step(flags=2) == E
+    assert step(eta=-1.0) == E
+    assert step(eta=float("nan")) == E
+    assert step(beta=-0.5) == E
+    assert step(rho=1.5) == E
+    assert step(a=-1.0) == E
+    assert step(a=float("inf")) == E
 
 
 def test_backward_argument_errors():

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():  # pragma: no cover - collected only where a G
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
-from gpu_util import NTHREADS, compare_l1, gpu_forward, gpu_forward_l1  # noqa: E402
+from gpu_util import NTHREADS, compare_l1, gpu_forward, gpu_forward_l1, gpu_step  # noqa: E402
 from paper_2311_03096_amd import workloads  # noqa: E402
 
 
@@ -111,3 +111,63 @@ def test_l1_mlp_rows_batched():
     case = workloads.mlp_rows()
     _, st = _check_l1(case, 0.01, 0.98, batched=True)
     assert st["zeroed"] > 0
+
+
+# ----------------------------------------------------------------------------- proximal-gradient step
+
+def _check_step(case, eta, alpha, beta, rho, variant, inplace=True, alpha_arr=None, seed=0):
+    w, off = case["w"], case["offsets"]
+    f32 = np.float32
+    eta, alpha, beta, rho = float(f32(eta)), float(f32(alpha)), float(f32(beta)), float(f32(rho))
+    _say("step case", case.get("name"), "n", w.shape[0], "segments", off.shape[0] - 1, "eta", eta, "alpha",
+         alpha, "beta", beta, "rho", rho, "variant", variant, "inplace", inplace)
+    grad = np.random.default_rng(seed).standard_normal(w.shape[0]).astype(np.float32)
+    out, w_after = gpu_step(w, grad, off, eta, alpha, beta, rho, variant, inplace, alpha_arr)
+    if not inplace:
+        assert np.array_equal(w_after, w)
+    a = np.asarray(alpha_arr, np.float32) if alpha_arr is not None else f32(alpha)
+    o = oracle.prox_step_segments(w, grad, eta, a, beta, rho, off, eta_in_displacement=variant,
+                                  n_threads=NTHREADS)
+    # the collisions run on z = fmaf(-eta, grad, w) with lambda_eff; the plain forward of z gives
+    # both sides' partitions for the near-tie excuses
+    z = oracle.grad_step(w, grad, eta)
+    lam_eff = a if variant else (f32(eta) * a).astype(np.float32)
+    beta_eff = beta if variant else float(f32(eta) * f32(beta))
+    q = 1.0 - (eta if variant else 1.0) * (1.0 - rho)  # coefficient of v in u - q v
+    lam_s = float(np.atleast_1d(lam_eff)[0])
+    g_plain = gpu_forward(z, off, lam_s, batched=True, lam_arr=lam_eff if alpha_arr is not None else None)
+    u, p, s = oracle.prox_segments(z, lam_eff, off, n_threads=NTHREADS)
+    st = compare_l1(z, off, out, o, dict(u=u, perm=p, start=s), g_plain, beta_eff, q)
+    _say("  stats", st)
+    assert st["skipped_zero_test"] + st["skipped_partition"] <= max(8, w.shape[0] // 1000)
+    return out, st
+
+
+@pytest.mark.parametrize("variant", [False, True])
+def test_step_mlp_rows_in_place(variant):
+    case = workloads.mlp_rows()
+    # the paper's CIFAR10 setting has learning rate 0.1 and rho = 0.98
+    _check_step(case, 0.1, 1e-2 if not variant else 1e-3, 0.1 if not variant else 0.01, 0.98, variant)
+
+
+@pytest.mark.parametrize("variant", [False, True])
+def test_step_mixed_segments_per_segment_alpha(variant):
+    lens = [0, 1, 2, 65, 2049, 4096, 8192, 8193, 20000, 3, 100003]
+    case = workloads.random_segments(lens, "mixed", 0.05, seed=9)
+    alpha_arr = np.linspace(0.0, 0.5, len(lens)).astype(np.float32)
+    _check_step(case, 0.25, 0.0, 0.05, 0.5, variant, inplace=False, alpha_arr=alpha_arr, seed=1)
+    _check_step(case, 0.25, 0.2, 0.05, 0.5, variant, inplace=True, seed=2)
+
+
+@pytest.mark.parametrize("eta", [0.0, 1.0, 3.0])
+def test_step_eta_edges(eta):
+    """eta = 0: the standard step is the identity (lambda = beta' = 0), the variant keeps the
+    cluster means; eta = 1: both forms coincide; eta = 3 > 1/(1 - rho): the variant moves the
+    clusters past their prox values."""
+    case = workloads.random_segments([3000, 9000], "normal", 0.1, seed=10)
+    o1, _ = _check_step(case, eta, 0.3, 0.2, 0.5, False, seed=3)
+    o2, _ = _check_step(case, eta, 0.3, 0.2, 0.5, True, seed=3)
+    if eta == 0.0:
+        assert np.array_equal(o1, case["w"])
+    if eta == 1.0:
+        np.testing.assert_allclose(o1, o2, rtol=0, atol=1e-6)

@@ -564,3 +564,14 @@ def test_step_modes_agree_at_unit_eta_and_per_segment_alpha():
                                                              np.float32(eta * np.float32(0.2)), 0.5, off))
     with pytest.raises(ValueError):
         oracle.prox_step_segments(w, g, -1.0, alpha, 0.2, 0.5, off)
+    # the gradient step alone: one rounding of w - eta*g.  eta*g is exact in FP64; rounding the
+    # FP64 difference to FP32 gives the correctly rounded result unless that difference is itself
+    # halfway between two FP32 values (FP32 midpoints are FP64 numbers, so the exact value lies
+    # on the same side of every midpoint as its FP64 rounding)
+    z = oracle.grad_step(w, g, eta)
+    r64 = w.astype(np.float64) - np.float64(eta) * g.astype(np.float64)
+    r32 = r64.astype(np.float32)
+    nb = np.where(r64 > r32, np.nextafter(r32, np.float32(np.inf)), np.nextafter(r32, np.float32(-np.inf)))
+    ok = r64 != (r32.astype(np.float64) + nb.astype(np.float64)) / 2
+    assert ok.mean() > 0.99
+    np.testing.assert_array_equal(z[ok], r32[ok])
