@@ -7,8 +7,9 @@ d = 2^24 FP32 weights w_k = (k/(d-1))^2 with lam = 0.7 (every particle ends in o
 
 Prints one JSON line: elements/s, the roofline of the dominant kernel (HIP-event durations
 measured live on the library's stream), the CPU oracle on the host as a reference, and extra
-figures: a typical d = 2^24 N(0,1) vector and the batched MLP-rows workload, graph-captured
-batched launch versus per-row launches.
+figures: a typical d = 2^24 N(0,1) vector, the batched MLP-rows workload (graph-captured
+batched launch versus per-row launches), and Alg. prox in full (l1 and rewinding lines) on both
+next to the plain forward.
 """
 from __future__ import annotations
 
@@ -241,6 +242,77 @@ def batched_vs_per_row(steps, warmup, per_row=True):
                 kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()})
 
 
+def l1_figures(steps, warmup):
+    """Alg. prox in full (l1 and rewinding lines, the update of a proximal-gradient step) next
+    to the plain inference forward on the same inputs: MLP rows batched and graph-captured, and
+    one N(0,1) vector of 2^24 weights."""
+    import torch
+    import paper_2311_03096_amd as wsr
+    from paper_2311_03096_amd import workloads
+    res = {}
+    case = workloads.mlp_rows()
+    off = case["offsets"]
+    w = torch.from_numpy(case["w"]).cuda()
+    out = torch.empty_like(w)
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        beta, rho = 0.01, 0.98
+        fns = dict(
+            l1=lambda: wsr.wsr_prox_l1_forward_batched(plan, w, out, None, case["lam"], beta, rho, ws),
+            plain=lambda: wsr.wsr_prox_forward_batched(plan, w, out, None, case["lam"], None, None, ws))
+        ms = {}
+        for k, fn in fns.items():
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                fn()
+            torch.cuda.current_stream().wait_stream(s)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            ms[k] = time_steps(g.replay, steps, warmup)[0]
+        n = w.numel()
+        res["mlp_rows"] = dict(workload="mlp_rows, lam=1e-3, beta=0.01, rho=0.98, batched + hipGraph, no saved state",
+                               ms_l1=round(ms["l1"], 4), ms_plain_forward=round(ms["plain"], 4),
+                               elements_per_s_l1=n / (ms["l1"] * 1e-3))
+        # one proximal-gradient step of every row (out of place, so every timed step sees the
+        # same weights): gradient step fused into the prox kernels' loads
+        grad = torch.from_numpy(np.random.default_rng(7).standard_normal(n).astype(np.float32)).cuda()
+        fn = lambda: wsr.wsr_prox_step_batched(plan, w, grad, 0.1, out, None, 1e-2, 0.1, 0.98, 0, ws)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            fn()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        ms_step = time_steps(g.replay, steps, warmup)[0]
+        res["mlp_rows_step"] = dict(
+            workload="mlp_rows: w <- Prox(w - 0.1 grad), alpha=1e-2, beta=0.1, rho=0.98, batched + hipGraph",
+            ms=round(ms_step, 4), elements_per_s=n / (ms_step * 1e-3),
+            hbm_frac_12B=round(12.0 * n / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    finally:
+        wsr.wsr_plan_destroy(plan)
+    d = 1 << 24
+    case = workloads.plain(d, 0.1, seed=1)
+    off = case["offsets"]
+    w = torch.from_numpy(case["w"]).cuda()
+    out = torch.empty_like(w)
+    nb = wsr.wsr_workspace_bytes(off)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ms_l1 = time_steps(lambda: wsr.wsr_prox_l1_forward(w, out, off, case["lam"], 0.5, 0.98, ws),
+                       max(3, steps // 2), 2)[0]
+    ms_pl = time_steps(lambda: wsr.wsr_prox_forward(w, out, off, case["lam"], None, None, ws),
+                       max(3, steps // 2), 2)[0]
+    res["typical_d2p24"] = dict(workload="one N(0,1) vector d=2^24, lam=0.1, beta=0.5, rho=0.98",
+                                ms_l1=round(ms_l1, 4), ms_plain_forward=round(ms_pl, 4),
+                                elements_per_s_l1=d / (ms_l1 * 1e-3))
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -290,6 +362,15 @@ def main():
         log("typical", ms_t)
         extra["batched_mlp_rows"] = batched_vs_per_row(max(5, args.steps), args.warmup)
         log("batched", extra["batched_mlp_rows"])
+        extra["prox_l1_rewinding"] = l1_figures(max(5, args.steps), args.warmup)
+        log("l1", extra["prox_l1_rewinding"])
+        lay = workloads.mlp_layers()
+        st = Step(lay, batched=True)
+        ms_l, _ = time_steps(st, max(3, args.steps // 2), 2)
+        extra["mlp_per_layer"] = dict(workload="the MLP's weights, one segment per layer (12.6M, 16.8M, 41K), "
+                                      "lam=1e-3, fwd+bwd, batched", ms_per_step=round(ms_l, 4),
+                                      elements_per_s=lay["w"].shape[0] / (ms_l * 1e-3))
+        log("per-layer", extra["mlp_per_layer"])
     res = dict(metric=METRIC, value=d / (ms * 1e-3), unit="elements/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f32", data="synthetic",

@@ -42,6 +42,16 @@ def mlp_rows(lam=1e-3, seed=0, shapes=((4096, 3072), (4096, 4096), (10, 4096))):
     return _pack("mlp_rows_%d" % offs[-1], np.concatenate(parts), offs, lam)
 
 
+def mlp_layers(lam=1e-3, seed=0, shapes=((4096, 3072), (4096, 4096), (10, 4096))):
+    """The weights of ``mlp_rows`` (same draw) with one segment per weight matrix, the paper's
+    per-layer application of R (App. E.1): segments of 12,582,912, 16,777,216 and 40,960."""
+    case = mlp_rows(lam, seed, shapes)
+    offs = [0]
+    for rows, cols in shapes:
+        offs.append(offs[-1] + rows * cols)
+    return _pack("mlp_layers_%d" % offs[-1], case["w"], offs, lam)
+
+
 def chain(d=1 << 24, lam=0.7, shuffle=False, seed=0):
     """Worst-case collision chain: sorted w_k = (k/(d-1))^2 (gaps grow, so clusters merge one at
     a time from one end).  All particles end in one cluster once

@@ -297,6 +297,14 @@ def test_backward_uneven_and_big():
     _check_backward(workloads.random_segments([1 << 20], "normal", 0.1, seed=12), batched=True)
 
 
+def test_mlp_per_layer_batched():
+    """The MLP's weights with one segment per weight matrix (the paper applies R per layer):
+    two long segments through the device-wide path and one short, forward and backward."""
+    case = workloads.mlp_layers()
+    _check(case, batched=True)
+    _check_backward(case, batched=True)
+
+
 def test_backward_many_tiles():
     """More than 8192 rank tiles in one segment (the widest tile-scan variant); clusters are
     FP32 tie groups spanning many tiles.  Checked against the oracle VJP on the GPU's own
