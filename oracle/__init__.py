@@ -56,6 +56,8 @@ def _load():
         lib.wsr_oracle_prox_step_segments_f32.restype = ctypes.c_int
         lib.wsr_oracle_grad_step_f32.argtypes = [i64, p, p, ctypes.c_float, p]
         lib.wsr_oracle_grad_step_f32.restype = ctypes.c_int
+        lib.wsr_oracle_segment_stats.argtypes = [i64, p, p, p, p, p]
+        lib.wsr_oracle_segment_stats.restype = ctypes.c_int
         lib.wsr_oracle_vjp.argtypes = [i64, p, p, p, p, p]
         lib.wsr_oracle_vjp.restype = ctypes.c_int
         _lib = lib
@@ -170,6 +172,22 @@ def grad_step(w, grad, eta):
     if rc != 0:
         raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
     return z
+
+
+def segment_stats(w, offsets=None):
+    """Per segment: (R(w) FP64, distinct non-zero values, non-zero weights) as three arrays."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    if offsets is None:
+        offsets = np.array([0, w.shape[0]], np.int64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    n_seg = offsets.shape[0] - 1
+    pen = np.empty(n_seg, np.float64)
+    nd = np.empty(n_seg, np.int64)
+    nz = np.empty(n_seg, np.int64)
+    rc = _load().wsr_oracle_segment_stats(n_seg, _ptr(offsets), _ptr(w), _ptr(pen), _ptr(nd), _ptr(nz))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments (rc=%d)" % rc)
+    return pen, nd, nz
 
 
 def vjp(g, perm_local, start, offsets=None):

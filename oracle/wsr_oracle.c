@@ -40,6 +40,8 @@
  * l1 and rewinding lines applied per cluster (prox of lam*R + beta*l1, rewinding rho).
  * Proximal-gradient step (wsr_oracle_prox_step_*): the gradient step in FP32, then the full
  * Alg. prox with eta in the coefficients or, as a variant, on the rewinding line.
+ * Segment statistics (wsr_oracle_segment_stats): R(w) from the sorted order and the counts of
+ * the weight-sharing measure.
  *
  * Gradient: the prox is piecewise affine; on the piece selected by the partition
  * its Jacobian averages within each cluster (symmetric, idempotent).  The
@@ -433,6 +435,60 @@ int wsr_oracle_prox_step_segments_f32(int64_t n_seg, const int64_t* offsets, con
         opt.lam_times_eta = 1;
     }
     return run_segments(n_seg, offsets, w, alpha, per_seg_alpha, out, NULL, NULL, n_threads, opt);
+}
+
+static int cmp_double(const void* pa, const void* pb) {
+    double a = *(const double*)pa, b = *(const double*)pb;
+    return (a > b) - (a < b);
+}
+
+/*
+ * Per-segment statistics of a flat FP32 buffer, each from the sorted segment x_0 <= ... <= x_{d-1}:
+ *   penalty[s]  = R(w_s) = 1/(d-1) * sum_k (2k - d + 1) x_k      (App. B: R in O(d log d) from the
+ *                 sorted order, each pair counted once with the larger element positive); 0 for d <= 1
+ *   distinct[s] = number of distinct non-zero values               (numerator of the weight-sharing
+ *   nonzero[s]  = number of non-zero weights                        measure of the CIFAR10 table)
+ * -0 counts as zero.  A segment with a non-finite weight gets penalty NaN and counts -1.
+ * FP64, Neumaier summation.
+ */
+int wsr_oracle_segment_stats(int64_t n_seg, const int64_t* offsets, const float* w, double* penalty,
+                             int64_t* distinct, int64_t* nonzero) {
+    if (n_seg < 0 || !offsets || offsets[0] != 0) return -1;
+    for (int64_t s = 0; s < n_seg; ++s)
+        if (offsets[s + 1] < offsets[s]) return -1;
+    for (int64_t s = 0; s < n_seg; ++s) {
+        int64_t o = offsets[s];
+        int64_t d = offsets[s + 1] - o;
+        double* x = (double*)malloc(sizeof(double) * (size_t)(d > 0 ? d : 1));
+        if (!x) return -1;
+        int finite = 1;
+        for (int64_t i = 0; i < d; ++i) {
+            x[i] = (double)w[o + i];
+            if (!isfinite(x[i])) finite = 0;
+        }
+        if (!finite) {
+            penalty[s] = NAN;
+            distinct[s] = -1;
+            nonzero[s] = -1;
+            free(x);
+            continue;
+        }
+        qsort(x, (size_t)d, sizeof(double), cmp_double);
+        double acc = 0.0, comp = 0.0;
+        int64_t nd = 0, nz = 0;
+        for (int64_t k = 0; k < d; ++k) {
+            nsum_add(&acc, &comp, (double)(2 * k - d + 1) * x[k]);
+            if (x[k] != 0.0) {
+                ++nz;
+                if (k == 0 || x[k] != x[k - 1]) ++nd;
+            }
+        }
+        penalty[s] = d > 1 ? (acc + comp) / (double)(d - 1) : 0.0;
+        distinct[s] = nd;
+        nonzero[s] = nz;
+        free(x);
+    }
+    return 0;
 }
 
 /*

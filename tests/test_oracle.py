@@ -575,3 +575,48 @@ def test_step_modes_agree_at_unit_eta_and_per_segment_alpha():
     ok = r64 != (r32.astype(np.float64) + nb.astype(np.float64)) / 2
     assert ok.mean() > 0.99
     np.testing.assert_array_equal(z[ok], r32[ok])
+
+
+# ----------------------------------------------------------------------------- segment statistics
+
+def test_segment_penalty_against_definitions():
+    """R from the sorted order (App. B) against the O(d^2) pairwise definition (Sec. 1, eq. reg)
+    and, for d <= 6, the maximum over all orderings of the hyperplanes (Sec. 2)."""
+    rng = np.random.default_rng(30)
+    lens = [0, 1, 2, 3, 5, 6, 40, 1000, 1999]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = np.concatenate([rng.normal(size=n) if i % 2 else rng.integers(-3, 4, size=n)
+                        for i, n in enumerate(lens)]).astype(np.float32)
+    pen, _, _ = oracle.segment_stats(w, off)
+    for s, (a, b) in enumerate(zip(off[:-1], off[1:])):
+        x = w[a:b].astype(np.float64)
+        ref = pins.R_pairwise(x) if b - a >= 2 else 0.0
+        np.testing.assert_allclose(pen[s], ref, rtol=1e-12, atol=1e-12)
+        if 2 <= b - a <= 6:
+            np.testing.assert_allclose(pen[s], pins.R_hyperplanes(x), rtol=1e-12, atol=1e-12)
+
+
+def test_segment_counts_and_invariants():
+    rng = np.random.default_rng(31)
+    w = np.round(rng.normal(size=5000) * 4) / 4  # many ties and exact zeros
+    w[:7] = -0.0
+    w = w.astype(np.float32)
+    pen, nd, nz = oracle.segment_stats(w)
+    v = w[w != 0]
+    assert nz[0] == v.size and nd[0] == np.unique(v).size
+    # translation and permutation invariance, positive homogeneity, R = 0 on a constant vector
+    c = np.float32(0.5)
+    np.testing.assert_allclose(oracle.segment_stats(w + c)[0], pen, rtol=1e-12)
+    np.testing.assert_allclose(oracle.segment_stats(w[rng.permutation(w.size)])[0], pen, rtol=1e-12)
+    np.testing.assert_allclose(oracle.segment_stats(np.float32(-2) * w)[0], 2 * pen, rtol=1e-12)
+    assert oracle.segment_stats(np.full(10, 3.0, np.float32))[0][0] == 0.0
+    # chain w_k = (k/(d-1))^2: R = 1/(d-1) sum_{i>j} (w_i - w_j) in exact rationals, from the
+    # FP32 inputs themselves (every float is a rational)
+    from fractions import Fraction
+    d = 64
+    x = np.array([(k / (d - 1)) ** 2 for k in range(d)], np.float32)
+    wk = [Fraction(float(v)) for v in x]
+    exact = sum(wk[i] - wk[j] for i in range(d) for j in range(i)) / (d - 1)
+    np.testing.assert_allclose(oracle.segment_stats(x)[0][0], float(exact), rtol=1e-14)
+    pen, nd, nz = oracle.segment_stats(np.array([1.0, np.nan, 2.0], np.float32))
+    assert np.isnan(pen[0]) and nd[0] == -1 and nz[0] == -1
