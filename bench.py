@@ -313,6 +313,37 @@ def l1_figures(steps, warmup):
     return res
 
 
+def stats_figures(steps, warmup):
+    """Per-segment R(w) and the weight-sharing counts: MLP rows batched, one 2^24 vector."""
+    import torch
+    import paper_2311_03096_amd as wsr
+    from paper_2311_03096_amd import workloads
+    res = {}
+    case = workloads.mlp_rows()
+    off = case["offsets"]
+    w = torch.from_numpy(case["w"]).cuda()
+    st = torch.empty((off.shape[0] - 1, 3), dtype=torch.int64, device="cuda")
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        ms = time_steps(lambda: wsr.wsr_segment_stats_batched(plan, w, st, ws), steps, warmup)[0]
+    finally:
+        wsr.wsr_plan_destroy(plan)
+    res["mlp_rows"] = dict(workload="R(w) and counts of each of the 8202 MLP rows, batched", ms=round(ms, 4),
+                           elements_per_s=w.numel() / (ms * 1e-3))
+    d = 1 << 24
+    case = workloads.plain(d, 0.1, seed=1)
+    off = case["offsets"]
+    w = torch.from_numpy(case["w"]).cuda()
+    st = torch.empty((1, 3), dtype=torch.int64, device="cuda")
+    ws = torch.empty(wsr.wsr_workspace_bytes(off), dtype=torch.uint8, device="cuda")
+    ms = time_steps(lambda: wsr.wsr_segment_stats(w, off, st, ws), max(3, steps // 2), 2)[0]
+    res["typical_d2p24"] = dict(workload="R(w) and counts of one N(0,1) vector d=2^24", ms=round(ms, 4),
+                                elements_per_s=d / (ms * 1e-3))
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -364,6 +395,8 @@ def main():
         log("batched", extra["batched_mlp_rows"])
         extra["prox_l1_rewinding"] = l1_figures(max(5, args.steps), args.warmup)
         log("l1", extra["prox_l1_rewinding"])
+        extra["segment_stats"] = stats_figures(max(5, args.steps), args.warmup)
+        log("stats", extra["segment_stats"])
         lay = workloads.mlp_layers()
         st = Step(lay, batched=True)
         ms_l, _ = time_steps(st, max(3, args.steps // 2), 2)

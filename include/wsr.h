@@ -203,6 +203,37 @@ WSR_API int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_ou
                               const int32_t* saved_perm, const uint32_t* saved_mask, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ statistics */
+
+/*
+ * Per-segment statistics of a weight buffer, each from the segment's sorted order:
+ *   penalty           R_d(w_s) = 1/(d-1) sum_k (2k - d + 1) x_k for the sorted x (App. B: R in
+ *                     O(d log d); Sec. 1 eq. reg), FP64 (centred FP64 sums); 0 for d <= 1
+ *   distinct_nonzero  number of distinct non-zero values   } the weight-sharing measure of the
+ *   nonzero           number of non-zero weights           } CIFAR10 table is their ratio
+ * -0 counts as zero.  A segment holding a NaN or +-Inf weight gets penalty NaN and counts -1;
+ * an empty segment gets zeros.
+ */
+typedef struct {
+  double penalty;
+  int64_t distinct_nonzero;
+  int64_t nonzero;
+} wsr_segment_stats_t;
+
+/*
+ *   w[N]          device, weights (flat, segment-major)
+ *   d_stats       device array of n_seg wsr_segment_stats_t, every entry written
+ *   ws, ws_bytes  as for wsr_prox_forward (same size: wsr_workspace_bytes)
+ * Segments are processed one after another (one launch per short segment).
+ */
+WSR_API int wsr_segment_stats(const float* w, const int64_t* h_offsets, int64_t n_seg,
+                              wsr_segment_stats_t* d_stats, void* ws, size_t ws_bytes, void* stream);
+
+/* Batched form over the plan's segments (one launch per size class; workspace as
+ * wsr_plan_workspace_bytes). */
+WSR_API int wsr_segment_stats_batched(const wsr_plan* plan, const float* w, wsr_segment_stats_t* d_stats,
+                                      void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ tracing */
 
 /*

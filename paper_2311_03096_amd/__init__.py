@@ -9,7 +9,8 @@ from ._lib import (WSR_ERR_HIP, WSR_ERR_INVALID, WSR_ERR_UNSUPPORTED, WSR_ERR_WO
                    wsr_plan_create, wsr_plan_destroy, wsr_plan_workspace_bytes,
                    wsr_prox_backward, wsr_prox_backward_batched, wsr_prox_forward,
                    wsr_prox_forward_batched, wsr_prox_l1_forward, wsr_prox_l1_forward_batched,
-                   wsr_prox_step_batched, WSR_STEP_ETA_IN_DISPLACEMENT,
+                   wsr_prox_step_batched, WSR_STEP_ETA_IN_DISPLACEMENT, wsr_segment_stats,
+                   wsr_segment_stats_batched, stats_to_numpy,
                    wsr_status_string, wsr_trace_collect,
                    wsr_trace_enable, wsr_version, wsr_workspace_bytes)
 
@@ -18,7 +19,8 @@ __all__ = [
     "wsr_prox_forward", "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy",
     "wsr_plan_workspace_bytes", "wsr_prox_forward_batched", "wsr_prox_backward_batched",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
-    "WSR_STEP_ETA_IN_DISPLACEMENT", "wsr_trace_enable", "wsr_trace_collect",
+    "WSR_STEP_ETA_IN_DISPLACEMENT", "wsr_segment_stats", "wsr_segment_stats_batched", "stats_to_numpy",
+    "wsr_trace_enable", "wsr_trace_collect",
     "WSR_OK", "WSR_ERR_INVALID", "WSR_ERR_WORKSPACE", "WSR_ERR_HIP", "WSR_ERR_UNSUPPORTED",
     "WSR_PLAN_AUTOTUNE", "WSR_MAX_SEGMENT",
 ]

@@ -25,6 +25,7 @@ EXPORTED = (
     "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy", "wsr_plan_workspace_bytes",
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
+    "wsr_segment_stats", "wsr_segment_stats_batched",
 )
 
 
@@ -57,6 +58,8 @@ def load():
         "wsr_prox_l1_forward": ([p, p, p, i64, f32, f32, f32, p, sz, p], i32),
         "wsr_prox_l1_forward_batched": ([p, p, p, p, f32, f32, f32, p, sz, p], i32),
         "wsr_prox_step_batched": ([p, p, p, f32, p, p, f32, f32, f32, i32, p, sz, p], i32),
+        "wsr_segment_stats": ([p, p, i64, p, p, sz, p], i32),
+        "wsr_segment_stats_batched": ([p, p, p, p, sz, p], i32),
         "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
         "wsr_plan_destroy": ([p], i32),
         "wsr_plan_workspace_bytes": ([p, ctypes.POINTER(sz)], i32),
@@ -191,6 +194,29 @@ def wsr_prox_step_batched(plan, w, grad, eta, out, alpha=None, alpha_scalar=0.0,
     _check("wsr_prox_step_batched", load().wsr_prox_step_batched(
         plan, _ptr(w), _ptr(grad), float(eta), _ptr(out), _ptr(alpha), float(alpha_scalar), float(beta),
         float(rho), int(flags), wp, wn, _stream(stream)))
+
+
+def wsr_segment_stats(w, offsets, stats, ws=None, stream=None):
+    """stats: a device buffer of n_seg records of (float64 penalty, int64 distinct non-zero,
+    int64 non-zero), e.g. an int64 tensor of shape (n_seg, 3) viewed as needed."""
+    off = _offsets(offsets)
+    wp, wn = _ws_args(ws)
+    _check("wsr_segment_stats", load().wsr_segment_stats(
+        _ptr(w), off.ctypes.data_as(ctypes.c_void_p), off.shape[0] - 1, _ptr(stats), wp, wn, _stream(stream)))
+
+
+def wsr_segment_stats_batched(plan, w, stats, ws=None, stream=None):
+    wp, wn = _ws_args(ws)
+    _check("wsr_segment_stats_batched", load().wsr_segment_stats_batched(
+        plan, _ptr(w), _ptr(stats), wp, wn, _stream(stream)))
+
+
+def stats_to_numpy(stats_host_bytes, n_seg):
+    """Split the raw records (bytes or a uint8/int64 array on the host) into (penalty float64,
+    distinct int64, nonzero int64) arrays."""
+    rec = np.frombuffer(np.ascontiguousarray(stats_host_bytes).tobytes(), dtype=np.dtype(
+        [("penalty", "<f8"), ("distinct", "<i8"), ("nonzero", "<i8")]), count=n_seg)
+    return rec["penalty"].copy(), rec["distinct"].copy(), rec["nonzero"].copy()
 
 
 def wsr_prox_backward_batched(plan, grad_out, grad_w, saved_perm, saved_mask, ws=None, stream=None):

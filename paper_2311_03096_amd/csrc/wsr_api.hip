@@ -228,16 +228,10 @@ bool l1_args_ok(float beta, float rho) {
   return std::isfinite(beta) && beta >= 0.0f && rho >= 0.0f && rho <= 1.0f;
 }
 
-// Forward of one long segment [start, start + d).
-int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
-                float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s,
-                const L1Opt& l1) {
-  BigWs b = big_layout(d, ws);
+// Stable LSD radix sort of one long segment (4 passes of 8 bits: w -> B -> A -> B -> A): sorted
+// keys end in b.keysA, the permutation in perm_final; b.flags[0] gets the non-finite bit.
+void big_sort(const float* wseg, int64_t d, const BigWs& b, int32_t* perm_final, hipStream_t s) {
   const int nrt = (int)ceil_div(d, kRadixTile);
-  const int nt = (int)ceil_div(d, kBigTile);
-  const float* wseg = w + start;
-  // 4 stable LSD passes: w -> B -> A -> B -> A(keys) / perm
-  int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 8 * pass;
     const uint32_t* ksrc = pass == 0 ? nullptr : (pass % 2 == 1 ? b.keysB : b.keysA);
@@ -255,6 +249,16 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
                        pass == 0 ? wseg : nullptr,
                        ksrc, vsrc, kdst, vdst, d, shift, b.hist, b.totals, nrt); }
   }
+}
+
+// Forward of one long segment [start, start + d).
+int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
+                float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s,
+                const L1Opt& l1) {
+  BigWs b = big_layout(d, ws);
+  const int nt = (int)ceil_div(d, kBigTile);
+  int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
+  big_sort(w + start, d, b, perm_final, s);
   { WSR_TRACE("big_tile_hull", s);
   hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, lam_arr, seg_id,
                      lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum, b.hbits); }
@@ -327,10 +331,34 @@ int big_backward(const float* g, float* gw, int64_t start, int64_t d, const int3
   return last_error();
 }
 
+// Statistics of one long segment: the sort, then the tile partials and their fixed-order sum.
+int big_stats(const float* w, int64_t start, int64_t d, SegStats* out, void* ws, hipStream_t s) {
+  BigWs b = big_layout(d, ws);
+  const int nt = (int)ceil_div(d, kBigTile);
+  big_sort(w + start, d, b, b.valsA, s);
+  { WSR_TRACE("big_stats_tile", s);
+  hipLaunchKernelGGL(k_big_stats_tile, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, b.tsum, b.hcnt, b.lo); }
+  { WSR_TRACE("big_stats_final", s);
+  hipLaunchKernelGGL(k_big_stats_final, dim3(1), dim3(1024), 0, s, b.tsum, b.hcnt, b.lo, nt, d, b.flags, out); }
+  return last_error();
+}
+
+void small_stats(int cls, int nblocks, const SegArgs& a, const float* w, SegStats* st, hipStream_t s) {
+  switch (cls) {
+    case kC2048: { WSR_TRACE("seg_stats_small_2048", s);
+      hipLaunchKernelGGL((k_seg_stats_small<2048, 256>), dim3(nblocks), dim3(256), 0, s, a, w, st); } break;
+    case kC4096: { WSR_TRACE("seg_stats_small_4096", s);
+      hipLaunchKernelGGL((k_seg_stats_small<4096, 512>), dim3(nblocks), dim3(512), 0, s, a, w, st); } break;
+    default: { WSR_TRACE("seg_stats_small_8192", s);
+      hipLaunchKernelGGL((k_seg_stats_small<8192, 1024>), dim3(nblocks), dim3(1024), 0, s, a, w, st); } break;
+  }
+}
+
 }  // namespace
 }  // namespace wsr
 
 using namespace wsr;
+static_assert(sizeof(SegStats) == sizeof(wsr_segment_stats_t), "stats layout");
 
 struct wsr_plan {
   int64_t n_seg = 0;
@@ -494,6 +522,35 @@ int wsr_prox_l1_forward(const float* w, float* out, const int64_t* h_offsets, in
                       L1Opt{beta, rho, 1});
 }
 
+int wsr_segment_stats(const float* w, const int64_t* h_offsets, int64_t n_seg, wsr_segment_stats_t* d_stats,
+                      void* ws, size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!w || !d_stats) return WSR_ERR_INVALID;
+  int64_t mb = 0;
+  int rc = validate_offsets(h_offsets, n_seg, &mb);
+  if (rc) return rc;
+  if (n_seg > INT32_MAX) return WSR_ERR_UNSUPPORTED;
+  const size_t need = big_bytes(mb);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  SegStats* st = reinterpret_cast<SegStats*>(d_stats);
+  zero_words(reinterpret_cast<uint32_t*>(st), n_seg * (int64_t)(sizeof(SegStats) / 4), s);  // empty segments
+  for (int64_t seg = 0; seg < n_seg; ++seg) {
+    const int64_t start = h_offsets[seg];
+    const int64_t d = h_offsets[seg + 1] - start;
+    const int cls = size_class(d);
+    if (cls == kSkip) continue;
+    if (cls == kBig) {
+      rc = big_stats(w, start, d, st + seg, ws, s);
+      if (rc) return rc;
+      continue;
+    }
+    SegArgs a{nullptr, nullptr, nullptr, 0.0f, start, (int)d, (int)seg};
+    small_stats(cls, 1, a, w, st, s);
+  }
+  return last_error();
+}
+
 int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_offsets, int64_t n_seg,
                       const int32_t* saved_perm, const uint32_t* saved_mask, void* ws, size_t ws_bytes,
                       void* stream) {
@@ -612,6 +669,29 @@ int wsr_prox_step_batched(const wsr_plan* plan, const float* w, const float* gra
                           size_t ws_bytes, void* stream) {
   return step_batched_impl(plan, w, grad, eta, out, d_alpha, alpha_scalar, beta, rho, flags, ws, ws_bytes,
                            stream);
+}
+
+int wsr_segment_stats_batched(const wsr_plan* plan, const float* w, wsr_segment_stats_t* d_stats, void* ws,
+                              size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!plan || !w || !d_stats) return WSR_ERR_INVALID;
+  const size_t need = big_bytes(plan->max_big);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  SegStats* st = reinterpret_cast<SegStats*>(d_stats);
+  zero_words(reinterpret_cast<uint32_t*>(st), plan->n_seg * (int64_t)(sizeof(SegStats) / 4), s);
+  for (int c = 0; c < kNumSmall; ++c) {
+    if (plan->sched_cnt[c] == 0) continue;
+    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], nullptr, 0.0f, 0, 0, 0};
+    small_stats(c, (int)plan->sched_cnt[c], a, w, st, s);
+  }
+  for (int32_t seg : plan->big_segs) {
+    const int64_t start = plan->h_offsets[seg];
+    const int64_t d = plan->h_offsets[seg + 1] - start;
+    const int rc = big_stats(w, start, d, st + seg, ws, s);
+    if (rc) return rc;
+  }
+  return last_error();
 }
 
 int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float* grad_w,

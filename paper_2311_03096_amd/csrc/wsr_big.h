@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "wsr_kernels.h"
+
 namespace wsr {
 
 constexpr int kRadixThreads = 256;   // histogram workgroup; the scatter's digit scan uses
@@ -63,5 +65,9 @@ __global__ void k_big_bwd_apply(const float* gsorted, const int32_t* perm, const
                                 int64_t d, int64_t seg_start, const double* tileoff,
                                 const int32_t* prevp, const double* prevG, const int32_t* nextp,
                                 const double* nextG, float* gout);
+
+__global__ void k_big_stats_tile(const uint32_t* skeys, int64_t d, double* tsum, int32_t* tnz, int32_t* tnd);
+__global__ void k_big_stats_final(const double* tsum, const int32_t* tnz, const int32_t* tnd, int ntiles,
+                                  int64_t d, const uint32_t* flags, SegStats* out);
 
 }  // namespace wsr

@@ -1433,4 +1433,67 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
   }
 }
 
+// Statistics of a long segment from its sorted keys (App. B: R(w) from the sorted order).
+// k_big_stats_tile: per rank tile, the centred weighted sum sum_k (2k-d+1)(x_k - c) in FP64 and
+// the counts of non-zero weights and of distinct non-zero values (a rank counts when its value
+// differs from the previous rank's, read across the tile edge); k_big_stats_final adds the
+// tiles in a fixed order.  Deterministic.
+__global__ __launch_bounds__(kBigThreads) void k_big_stats_tile(const uint32_t* skeys, int64_t d, double* tsum,
+                                                                int32_t* tnz, int32_t* tnd) {
+  __shared__ double dred[kBigThreads / kWave + 1];
+  __shared__ long long lred[kBigThreads / kWave + 1];
+  const int tid = threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.x * kBigTile;
+  const int np = (int)min((int64_t)kBigTile, d - k0);
+  const double c = (double)key_to_float(skeys[d >> 1]);
+  double lsum = 0.0;
+  long long cnt = 0;  // non-zero weights in the high half, distinct non-zero values in the low
+#pragma unroll 4
+  for (int r = 0; r < kBigE; ++r) {
+    const int j = tid + r * kBigThreads;
+    if (j < np) {
+      const int64_t kk = k0 + j;
+      const float x = key_to_float(skeys[kk]);
+      const float xp = kk > 0 ? key_to_float(skeys[kk - 1]) : 0.0f;
+      lsum += (double)(2 * kk - d + 1) * ((double)x - c);
+      if (x != 0.0f) cnt += (1ll << 32) + ((kk == 0 || x != xp) ? 1 : 0);
+    }
+  }
+  double total;
+  long long ctot;
+  (void)block_excl_scan<kBigThreads, double, false>(lsum, dred, &total);
+  (void)block_excl_scan<kBigThreads, long long, false>(cnt, lred, &ctot);
+  if (tid == 0) {
+    tsum[blockIdx.x] = total;
+    tnz[blockIdx.x] = (int32_t)(ctot >> 32);
+    tnd[blockIdx.x] = (int32_t)(ctot & 0xFFFFFFFFll);
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_big_stats_final(const double* tsum, const int32_t* tnz,
+                                                          const int32_t* tnd, int ntiles, int64_t d,
+                                                          const uint32_t* flags, SegStats* out) {
+  __shared__ double dred[1024 / kWave + 1];
+  __shared__ long long zred[1024 / kWave + 1], nred[1024 / kWave + 1];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  long long nz = 0, nd = 0;
+  for (int t = tid; t < ntiles; t += 1024) {
+    s += tsum[t];
+    nz += tnz[t];
+    nd += tnd[t];
+  }
+  double total;
+  long long ztot, ntot;
+  (void)block_excl_scan<1024, double, false>(s, dred, &total);
+  (void)block_excl_scan<1024, long long, false>(nz, zred, &ztot);
+  (void)block_excl_scan<1024, long long, false>(nd, nred, &ntot);
+  if (tid == 0) {
+    if (flags[0] & 1u)
+      out[0] = SegStats{__builtin_nan(""), -1, -1};
+    else
+      out[0] = SegStats{total / (double)(d - 1), ntot, ztot};
+  }
+}
+
 }  // namespace wsr

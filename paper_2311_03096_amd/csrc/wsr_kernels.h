@@ -28,6 +28,16 @@ struct SegArgs {
   float lam_mul = 1.0f;
 };
 
+// Per-segment statistics (layout of wsr_segment_stats_t): R(w), the number of distinct non-zero
+// values and the number of non-zero weights.
+struct SegStats {
+  double penalty;
+  long long distinct;
+  long long nonzero;
+};
+
+template <int TMAX, int NT>
+__global__ void k_seg_stats_small(SegArgs args, const float* w, SegStats* stats);
 template <int TMAX, int NT>
 __global__ void k_prox_fwd_small(SegArgs args, const float* w, float* out, int32_t* perm_out,
                                  uint32_t* mask_out);

@@ -581,6 +581,76 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   if (mask_out) store_mask_words<NT>(mask_out, start, d, sm.lmask);
 }
 
+// Statistics of one segment from its sorted order (App. B): R(w) = 1/(d-1) sum_k (2k-d+1) x_k,
+// summed in FP64 over the centred values x_k - c (the weights 2k-d+1 sum to zero, so centring
+// changes nothing but the rounding), and the counts of non-zero weights and of distinct non-zero
+// values (a rank counts when its value differs from the previous rank's).  The sort is the
+// forward kernel's.  Non-finite segment: penalty NaN, counts -1.
+template <int TMAX, int NT>
+__global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_seg_stats_small(SegArgs args, const float* w,
+                                                                                  SegStats* stats) {
+  constexpr int IPT = TMAX / NT;
+  constexpr int E = IPT;
+  __shared__ FwdSmem<TMAX, NT> sm;
+  const SegView seg = resolve_segment(args);
+  const int sid = args.sched ? args.sched[blockIdx.x] : args.seg_id;
+  const int64_t start = seg.start;
+  const int d = seg.d;
+  if (d <= 0) return;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int wv = tid / kWave;
+  const int wbase = wv * kWave * IPT;
+  uint32_t k[IPT];
+  uint16_t ix[IPT];
+  float f[IPT];
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    f[r] = p < d ? w[start + p] : 0.0f;
+  }
+  int bad = 0;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const int p = wbase + r * kWave + lane;
+    bad |= (p < d) & !isfinite(f[r]);
+    k[r] = p < d ? float_to_key(f[r]) : 0xFFFFFFFFu;
+    ix[r] = (uint16_t)p;
+  }
+  bucket_sort_prologue<TMAX, NT>(sm, k, d);  // shares the barrier below
+  const bool nonfinite = __syncthreads_or(bad) != 0;
+  if (nonfinite) {
+    if (tid == 0) stats[sid] = SegStats{__builtin_nan(""), -1, -1};
+    return;
+  }
+  if (!block_bucket_sort<TMAX, NT>(sm, k, ix, d)) block_radix_sort<TMAX, NT>(sm, k, ix, d);
+  const uint32_t* skey = sm.c.bs.key;
+  const double c = (double)key_to_float(skey[d >> 1]);
+  const int k0 = tid * E;
+  uint32_t kv[E];
+  load_u32_block<E>(skey, k0, kv);  // ranks past d hold stale words, masked below
+  float prev = (k0 > 0 && k0 <= d) ? key_to_float(skey[k0 - 1]) : 0.0f;
+  double lsum = 0.0;
+  long long cnt = 0;  // non-zero weights in the high half, distinct non-zero values in the low
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int kk = k0 + i;
+    if (kk < d) {
+      const float x = key_to_float(kv[i]);
+      lsum += (double)(2 * kk - d + 1) * ((double)x - c);
+      if (x != 0.0f) cnt += (1ll << 32) + ((kk == 0 || x != prev) ? 1 : 0);
+      prev = x;
+    }
+  }
+  double total;
+  (void)block_excl_scan<NT, double, false>(lsum, sm.sc.dred, &total);
+  __syncthreads();  // the counter scan below reuses the same LDS slots
+  long long ctot;
+  (void)block_excl_scan<NT, long long, false>(cnt, sm.sc.lred, &ctot);
+  if (tid == 0)
+    stats[sid] = SegStats{d > 1 ? total / (double)(d - 1) : 0.0, ctot & 0xFFFFFFFFll, ctot >> 32};
+}
+
 template <int TMAX, int NT>
 struct BwdSmem {
   static constexpr int NW = NT / kWave;
@@ -695,6 +765,7 @@ __global__ void k_scale_lambda(float* dst, const float* lam_arr, int seg_id, flo
 }
 
 #define WSR_INSTANTIATE_SMALL(TM, NTH)                                                          \
+  template __global__ void k_seg_stats_small<TM, NTH>(SegArgs, const float*, SegStats*);         \
   template __global__ void k_prox_fwd_small<TM, NTH>(SegArgs, const float*, float*, int32_t*,   \
                                                       uint32_t*);                               \
   template __global__ void k_prox_bwd_small<TM, NTH>(SegArgs, const float*, float*,             \

@@ -77,6 +77,21 @@ def prox_l1(w, lam, beta, rho=0.0, offsets=None):
     return out.view(w.shape)
 
 
+def segment_stats(w, offsets=None):
+    """Per segment of a float32 GPU tensor: (R(w), distinct non-zero values, non-zero weights)
+    as host numpy arrays (the ratio of the last two is the weight-sharing measure)."""
+    _check_f32(w.contiguous(), "w")
+    flat = w.contiguous().view(-1)
+    if offsets is None:
+        offsets = np.array([0, flat.numel()], dtype=np.int64)
+    offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    n_seg = offsets.shape[0] - 1
+    st = torch.empty((n_seg, 3), dtype=torch.int64, device=flat.device)
+    ws = _workspace(_lib.wsr_workspace_bytes(offsets), flat.device)
+    _lib.wsr_segment_stats(flat, offsets, st, ws)
+    return _lib.stats_to_numpy(st.cpu().numpy(), n_seg)
+
+
 def row_offsets(shapes):
     """Offsets of per-row segments for a list of 2-D weight shapes laid out back to back."""
     offs = [0]

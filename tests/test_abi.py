@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 15
+    assert len(declared) == 17
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -119,6 +119,21 @@ def test_step_argument_errors():
     assert step(rho=1.5) == E
     assert step(a=-1.0) == E
     assert step(a=float("inf")) == E
+
+
+def test_stats_argument_errors():
+    lib = wsr.load()
+    E = wsr.WSR_ERR_INVALID
+    off = np.array([0, 4], np.int64)
+    po = off.ctypes.data_as(ctypes.c_void_p)
+    assert lib.wsr_segment_stats(None, po, 1, FAKE, None, 0, None) == E
+    assert lib.wsr_segment_stats(FAKE, po, 1, None, None, 0, None) == E
+    bad = np.array([0, 5, 3], np.int64)
+    assert lib.wsr_segment_stats(FAKE, bad.ctypes.data_as(ctypes.c_void_p), 2, FAKE, None, 0, None) == E
+    big = np.array([0, 1 << 20], np.int64)
+    assert lib.wsr_segment_stats(FAKE, big.ctypes.data_as(ctypes.c_void_p), 1, FAKE, None, 0,
+                                 None) == wsr.WSR_ERR_WORKSPACE
+    assert lib.wsr_segment_stats_batched(None, FAKE, FAKE, None, 0, None) == E
 
 
 def test_backward_argument_errors():
