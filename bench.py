@@ -344,6 +344,37 @@ def stats_figures(steps, warmup):
     return res
 
 
+def merge_route_figures(steps, warmup):
+    """The merge routes side by side (inference forward, batched): ImminentCollisions rounds with
+    the hull merge as fallback (default), the hull merge alone, and the autotuned choice, on
+    training-like rows, on rows of the collision worst case, and on one long N(0,1) vector."""
+    import torch
+    import paper_2311_03096_amd as wsr
+    from paper_2311_03096_amd import workloads
+    res = {}
+    cases = [("mlp_rows", workloads.mlp_rows()), ("ica_worst_rows_1024x4095", workloads.ica_worst_rows(1024, 4095)),
+             ("typical_d2p24", workloads.plain(1 << 24, 0.1, seed=1))]
+    for name, case in cases:
+        off = case["offsets"]
+        w = torch.from_numpy(case["w"]).cuda()
+        out = torch.empty_like(w)
+        row = {}
+        for route in ("default", "hull_only", "autotuned"):
+            plan = wsr.wsr_plan_create(off, wsr.WSR_PLAN_MERGE_HULL if route == "hull_only" else 0)
+            try:
+                nb = wsr.wsr_plan_workspace_bytes(plan)
+                ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+                if route == "autotuned":
+                    wsr.wsr_plan_autotune(plan, w, out, None, case["lam"], ws)
+                    row["autotuned_rounds"] = wsr.wsr_plan_merge_rounds(plan)
+                fn = lambda: wsr.wsr_prox_forward_batched(plan, w, out, None, case["lam"], None, None, ws)
+                row["ms_" + route] = round(time_steps(fn, max(3, steps // 2), 2)[0], 4)
+            finally:
+                wsr.wsr_plan_destroy(plan)
+        res[name] = row
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -397,6 +428,8 @@ def main():
         log("l1", extra["prox_l1_rewinding"])
         extra["segment_stats"] = stats_figures(max(5, args.steps), args.warmup)
         log("stats", extra["segment_stats"])
+        extra["merge_routes"] = merge_route_figures(max(5, args.steps), args.warmup)
+        log("merge routes", extra["merge_routes"])
         lay = workloads.mlp_layers()
         st = Step(lay, batched=True)
         ms_l, _ = time_steps(st, max(3, args.steps // 2), 2)

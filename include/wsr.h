@@ -20,7 +20,8 @@
  * - Device pointers are plain device addresses (hipMalloc / torch CUDA tensors) on
  *   the current HIP device; "stream" is a hipStream_t passed as void* (NULL = the
  *   null stream).  Every compute call only enqueues work on that stream, returns
- *   without synchronising, and allocates no memory: scratch comes from the caller's
+ *   without synchronising (the exceptions, wsr_plan_autotune and wsr_trace_collect, say
+ *   so), and allocates no memory: scratch comes from the caller's
  *   workspace "ws" of "ws_bytes" bytes (device memory, any contents, 256-byte
  *   aligned), sized with the matching *_workspace_bytes call.  Two calls that
  *   overlap in time on different streams must not share a workspace.
@@ -145,13 +146,32 @@ typedef struct wsr_plan wsr_plan; /* opaque, owned by the library */
  * done here and never during compute calls), groups segments by size class and
  * records the launch schedule used by the batched calls, so that a whole optimizer
  * step of prox calls is a fixed sequence of launches (hipGraph-capturable).
- *   flags: 0, or WSR_PLAN_AUTOTUNE to time the launch variants once on the current
- *   device (synchronises the device) and keep the fastest in the plan.
+ *   flags: 0, or WSR_PLAN_MERGE_HULL to merge clusters by the bounded-depth hull merge
+ *   only (Sec. 4.3 search collisions on hulls), without the ImminentCollisions rounds
+ *   (Sec. 4.1) that the default route tries first; results are identical, only the time
+ *   differs (for comparing the two routes).
  * On success *plan receives a new plan; free it with wsr_plan_destroy.
  */
-#define WSR_PLAN_AUTOTUNE 1
+#define WSR_PLAN_MERGE_HULL 2
 WSR_API int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan** plan);
 WSR_API int wsr_plan_destroy(wsr_plan* plan);
+
+/*
+ * Autotuner: times the merge routes of every size class of the plan on the caller's weights
+ * (the batched forward of that class alone, without saved state: a warm-up launch and three
+ * timed ones per route; routes = a cap of 0 (hull merge only), 2, 6 or 16 ImminentCollisions
+ * rounds before the hull merge; long segments: 0 or 6, timed on the longest one) and keeps the
+ * fastest route of each class in the plan for every later batched call.  Synchronises the
+ * stream; not for use under graph capture.
+ *   w[N]      device weights of the plan's layout; out[N] device scratch (overwritten)
+ *   d_lambda, lambda_scalar, ws, ws_bytes, stream   as in wsr_prox_forward_batched
+ */
+WSR_API int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d_lambda,
+                              float lambda_scalar, void* ws, size_t ws_bytes, void* stream);
+
+/* The plan's collision-round cap per size class (2048, 4096, 8192, long), 0 = hull merge only:
+ * writes 4 values. */
+WSR_API int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds);
 
 /* Workspace bytes needed by the batched calls of this plan. */
 WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);

@@ -5,8 +5,9 @@ The C ABI (include/wsr.h, libwsr.so) does the work in hand-written HIP kernels; 
 is its ctypes binding (same names) plus torch wrappers for autograd and batched steps.
 """
 from ._lib import (WSR_ERR_HIP, WSR_ERR_INVALID, WSR_ERR_UNSUPPORTED, WSR_ERR_WORKSPACE,
-                   WSR_MAX_SEGMENT, WSR_OK, WSR_PLAN_AUTOTUNE, WsrError, load,
-                   wsr_plan_create, wsr_plan_destroy, wsr_plan_workspace_bytes,
+                   WSR_MAX_SEGMENT, WSR_OK, WSR_PLAN_MERGE_HULL, WsrError, load,
+                   wsr_plan_autotune, wsr_plan_create, wsr_plan_destroy, wsr_plan_merge_rounds,
+                   wsr_plan_workspace_bytes,
                    wsr_prox_backward, wsr_prox_backward_batched, wsr_prox_forward,
                    wsr_prox_forward_batched, wsr_prox_l1_forward, wsr_prox_l1_forward_batched,
                    wsr_prox_step_batched, WSR_STEP_ETA_IN_DISPLACEMENT, wsr_segment_stats,
@@ -22,5 +23,5 @@ __all__ = [
     "WSR_STEP_ETA_IN_DISPLACEMENT", "wsr_segment_stats", "wsr_segment_stats_batched", "stats_to_numpy",
     "wsr_trace_enable", "wsr_trace_collect",
     "WSR_OK", "WSR_ERR_INVALID", "WSR_ERR_WORKSPACE", "WSR_ERR_HIP", "WSR_ERR_UNSUPPORTED",
-    "WSR_PLAN_AUTOTUNE", "WSR_MAX_SEGMENT",
+    "WSR_PLAN_MERGE_HULL", "WSR_MAX_SEGMENT", "wsr_plan_autotune", "wsr_plan_merge_rounds",
 ]

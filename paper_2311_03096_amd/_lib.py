@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwsr.so")
 
 WSR_OK, WSR_ERR_INVALID, WSR_ERR_WORKSPACE, WSR_ERR_HIP, WSR_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
-WSR_PLAN_AUTOTUNE = 1
+WSR_PLAN_MERGE_HULL = 2
 WSR_STEP_ETA_IN_DISPLACEMENT = 1
 WSR_MAX_SEGMENT = 1 << 26
 
@@ -25,7 +25,7 @@ EXPORTED = (
     "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy", "wsr_plan_workspace_bytes",
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
-    "wsr_segment_stats", "wsr_segment_stats_batched",
+    "wsr_segment_stats", "wsr_segment_stats_batched", "wsr_plan_autotune", "wsr_plan_merge_rounds",
 )
 
 
@@ -59,6 +59,8 @@ def load():
         "wsr_prox_l1_forward_batched": ([p, p, p, p, f32, f32, f32, p, sz, p], i32),
         "wsr_prox_step_batched": ([p, p, p, f32, p, p, f32, f32, f32, i32, p, sz, p], i32),
         "wsr_segment_stats": ([p, p, i64, p, p, sz, p], i32),
+        "wsr_plan_autotune": ([p, p, p, p, f32, p, sz, p], i32),
+        "wsr_plan_merge_rounds": ([p, p], i32),
         "wsr_segment_stats_batched": ([p, p, p, p, sz, p], i32),
         "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
         "wsr_plan_destroy": ([p], i32),
@@ -170,6 +172,19 @@ def wsr_plan_workspace_bytes(plan):
     n = ctypes.c_size_t(0)
     _check("wsr_plan_workspace_bytes", load().wsr_plan_workspace_bytes(plan, ctypes.byref(n)))
     return n.value
+
+
+def wsr_plan_autotune(plan, w, out, lam=None, lam_scalar=0.0, ws=None, stream=None):
+    wp, wn = _ws_args(ws)
+    _check("wsr_plan_autotune", load().wsr_plan_autotune(plan, _ptr(w), _ptr(out), _ptr(lam), float(lam_scalar),
+                                                         wp, wn, _stream(stream)))
+
+
+def wsr_plan_merge_rounds(plan):
+    """The plan's collision-round cap per size class (2048, 4096, 8192, long); 0 = hull merge only."""
+    r = (ctypes.c_int32 * 4)()
+    _check("wsr_plan_merge_rounds", load().wsr_plan_merge_rounds(plan, ctypes.cast(r, ctypes.c_void_p)))
+    return list(r)
 
 
 def wsr_prox_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, saved_perm=None, saved_mask=None,

@@ -254,14 +254,14 @@ void big_sort(const float* wseg, int64_t d, const BigWs& b, int32_t* perm_final,
 // Forward of one long segment [start, start + d).
 int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
                 float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s,
-                const L1Opt& l1) {
+                const L1Opt& l1, int rounds = -1) {
   BigWs b = big_layout(d, ws);
   const int nt = (int)ceil_div(d, kBigTile);
   int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
   big_sort(w + start, d, b, perm_final, s);
   { WSR_TRACE("big_tile_hull", s);
   hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, lam_arr, seg_id,
-                     lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum, b.hbits); }
+                     lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum, b.hbits, rounds); }
   { WSR_TRACE("big_tile_scan", s);
 #define WSR_LAUNCH_TILE_SCAN(CM)                                                                         \
   hipLaunchKernelGGL(k_big_tile_scan<CM>, dim3(1), dim3(1024), 0, s, b.tsum, b.tileoff, b.hcnt, b.lo, b.hi, nt, \
@@ -372,6 +372,9 @@ struct wsr_plan {
   std::vector<int64_t> h_offsets;
   std::vector<int32_t> big_segs;  // long segments, in order
   bool word_aligned = false;      // every offset a multiple of 32 (no mask zero fill needed)
+  // merge route per size class (short classes, then long segments): cap on ImminentCollisions
+  // rounds before the bounded-depth hull merge; -1 = the library default, 0 = hull merge only
+  int rounds[kNumSmall + 1] = {-1, -1, -1, -1};
 };
 
 extern "C" {
@@ -448,12 +451,14 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0,
               l1.beta, l1.rho, l1.on, l1.kappa};
+    a.merge_rounds = plan->rounds[c];
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
   for (int32_t seg : plan->big_segs) {
     const int64_t start = plan->h_offsets[seg];
     const int64_t d = plan->h_offsets[seg + 1] - start;
-    const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s, l1);
+    const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s, l1,
+                               plan->rounds[kNumSmall]);
     if (rc) return rc;
   }
   return last_error();
@@ -478,7 +483,7 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
-              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul};
+              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul, plan->rounds[c]};
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s);
   }
   for (int32_t seg : plan->big_segs) {
@@ -500,7 +505,8 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
       lam_arr = b.lamtmp;
       lam_seg = 0;
     }
-    const int rc = big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, l1);
+    const int rc = big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, l1,
+                               plan->rounds[kNumSmall]);
     if (rc) return rc;
   }
   return last_error();
@@ -579,7 +585,7 @@ int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_off
 }
 
 int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan** plan) {
-  if (!plan || (flags & ~WSR_PLAN_AUTOTUNE)) return WSR_ERR_INVALID;
+  if (!plan || (flags & ~WSR_PLAN_MERGE_HULL)) return WSR_ERR_INVALID;
   *plan = nullptr;
   int64_t mb = 0;
   int rc = validate_offsets(h_offsets, n_seg, &mb);
@@ -591,6 +597,8 @@ int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan
   p->max_big = mb;
   p->h_offsets.assign(h_offsets, h_offsets + n_seg + 1);
   p->word_aligned = offsets_word_aligned(h_offsets, n_seg);
+  if (flags & WSR_PLAN_MERGE_HULL)
+    for (int c = 0; c <= kNumSmall; ++c) p->rounds[c] = 0;
   (void)hipGetDevice(&p->device);
   // schedules: segments of each class, longest first (short tail of the launch)
   std::vector<int32_t> cls_list[kNumSmall];
@@ -647,6 +655,81 @@ int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return WSR_ERR_INVALID;
   *bytes = big_bytes(plan->max_big);
   return WSR_OK;
+}
+
+int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds) {
+  if (!plan || !rounds) return WSR_ERR_INVALID;
+  for (int c = 0; c <= kNumSmall; ++c) rounds[c] = plan->rounds[c] < 0 ? kIcaRounds : plan->rounds[c];
+  return WSR_OK;
+}
+
+int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d_lambda, float lambda_scalar,
+                      void* ws, size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  if (!plan || !w || !out) return WSR_ERR_INVALID;
+  if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
+  const size_t need = big_bytes(plan->max_big);
+  if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return WSR_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return WSR_ERR_HIP;
+  }
+  constexpr int kCand[] = {0, 2, kIcaRounds, 16};  // 0: hull merge only
+  constexpr int kReps = 3;
+  int rc = WSR_OK;
+  // one route at a time: a warm-up launch, then kReps timed launches of the class alone
+  auto time_route = [&](auto&& launch, float* ms) -> int {
+    launch();
+    if (hipEventRecord(e0, s) != hipSuccess) return WSR_ERR_HIP;
+    for (int r = 0; r < kReps; ++r) launch();
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return WSR_ERR_HIP;
+    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return WSR_ERR_HIP;
+    return last_error();
+  };
+  for (int c = 0; c < kNumSmall && rc == WSR_OK; ++c) {
+    if (plan->sched_cnt[c] == 0) continue;
+    float best = 0.0f;
+    for (int r : kCand) {
+      SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};
+      a.merge_rounds = r;
+      float ms = 0.0f;
+      rc = time_route([&] { small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s); }, &ms);
+      if (rc) break;
+      if (r == kCand[0] || ms < best) {
+        best = ms;
+        plan->rounds[c] = r;
+      }
+    }
+  }
+  if (rc == WSR_OK && !plan->big_segs.empty()) {
+    // long segments: timed on the longest one
+    int32_t seg = plan->big_segs[0];
+    for (int32_t q : plan->big_segs)
+      if (plan->h_offsets[q + 1] - plan->h_offsets[q] > plan->h_offsets[seg + 1] - plan->h_offsets[seg]) seg = q;
+    const int64_t start = plan->h_offsets[seg];
+    const int64_t d = plan->h_offsets[seg + 1] - start;
+    float best = 0.0f;
+    for (int r : {0, kIcaRounds}) {
+      float ms = 0.0f;
+      int lrc = WSR_OK;
+      rc = time_route([&] {
+        const int e = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, nullptr, nullptr, ws, s, L1Opt{}, r);
+        if (e) lrc = e;
+      }, &ms);
+      if (!rc) rc = lrc;
+      if (rc) break;
+      if (r == 0 || ms < best) {
+        best = ms;
+        plan->rounds[kNumSmall] = r;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,

@@ -35,7 +35,7 @@ __global__ void k_radix_scatter(const float* wsrc, const uint32_t* ksrc, const i
                                 const uint32_t* hist, const uint32_t* totals, int ntiles);
 __global__ void k_big_tile_hull(const uint32_t* skeys, int64_t d, const float* lam_arr, int seg_id,
                                 float lam_scalar, int32_t* vpos, double* vS, int32_t* hcnt,
-                                double* tsum, uint16_t* hbits);
+                                double* tsum, uint16_t* hbits, int rounds);
 template <int CM>
 __global__ void k_big_tile_scan(const double* tsum, double* tileoff, const int32_t* hcnt,
                                 int32_t* lo, int32_t* hi, int ntiles, int64_t d,

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
                                                                const float* lam_arr, int seg_id,
                                                                float lam_scalar, int32_t* vpos,
                                                                double* vS, int32_t* hcnt, double* tsum,
-                                                               uint16_t* hbits) {
+                                                               uint16_t* hbits, int rounds) {
   __shared__ TileSmem sm;
   const int tid = threadIdx.x;
   const int t = blockIdx.x;
@@ -385,7 +385,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
   const int64_t vb = (int64_t)t * (kBigTile + 1);
   uint32_t bm;
   Cand lc, rc;
-  if (ica_rounds<kBigThreads, kBigE, RankPadded>(sm.S, sv, np, kIcaRounds, &bm, &lc, &rc, sm.wb)) {
+  if (ica_rounds<kBigThreads, kBigE, RankPadded>(sm.S, sv, np, rounds < 0 ? kIcaRounds : rounds, &bm, &lc, &rc,
+                                                  sm.wb)) {
     // hull vertices = surviving candidates in rank order, then the tile's end point
     int nv;
     int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);

@@ -348,8 +348,7 @@ __device__ void tile_hull(const double* S, int d, uint16_t* vert, CT* cnt, CT* m
 }
 
 // ----------------------------------------------------------------------------- ImminentCollisions
-// Rounds tried before the hull merge (typical weights converge in 2-4 rounds).
-constexpr int kIcaRounds = 6;
+// (kIcaRounds, the default number of rounds tried before the hull merge, is in wsr_kernels.h.)
 
 // A candidate vertex: rank position and its S value; pos < 0 means "none".
 struct Cand {

@@ -5,6 +5,10 @@
 
 namespace wsr {
 
+// ImminentCollisions rounds tried before the hull merge by default (typical weights converge
+// in 2-4 rounds).
+constexpr int kIcaRounds = 6;
+
 // Which segment a workgroup of the short-segment kernels solves.  Batched launches give a
 // schedule (sched[blockIdx.x] = segment id) over device offsets; single-segment launches give
 // (start, d) directly.  lambda comes from lam_arr[segment] when lam_arr != nullptr.
@@ -26,6 +30,8 @@ struct SegArgs {
   const float* grad = nullptr;
   float eta = 0.0f;
   float lam_mul = 1.0f;
+  int merge_rounds = -1;  // cap on ImminentCollisions rounds before the hull merge (-1: default,
+                          // 0: hull merge only)
 };
 
 // Per-segment statistics (layout of wsr_segment_stats_t): R(w), the number of distinct non-zero

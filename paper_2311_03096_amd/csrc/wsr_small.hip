@@ -530,7 +530,8 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   uint32_t bm;
   Cand lc, rc;
   bool staged = true;
-  if (ica_rounds<NT, E, SL>(sm.c.S, sv, d, kIcaRounds, &bm, &lc, &rc, sm.wb)) {
+  if (ica_rounds<NT, E, SL>(sm.c.S, sv, d, args.merge_rounds < 0 ? kIcaRounds : args.merge_rounds, &bm, &lc, &rc,
+                            sm.wb)) {
     if (bm) {
       const int b0 = k0 + off;
       const uint64_t wide = (uint64_t)bm << (b0 & 31);

@@ -107,13 +107,16 @@ class BatchedProx:
     ``forward(w, out, lam)`` runs the batched prox; with ``save=True`` the saved permutation and
     cluster-start bits for ``backward`` are kept in this object.  ``capture()`` records one
     forward into a HIP graph (torch.cuda.CUDAGraph) for replay with ``replay()``.
+    ``autotune=True`` times the merge routes on the first forward's weights (wsr_plan_autotune);
+    ``hull_only=True`` merges by the hull merge alone (for comparing routes).
     """
 
-    def __init__(self, offsets, device="cuda", autotune=False):
+    def __init__(self, offsets, device="cuda", autotune=False, hull_only=False):
         self.offsets = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
         self.n = int(self.offsets[-1])
         self.device = torch.device(device)
-        self.plan = _lib.wsr_plan_create(self.offsets, _lib.WSR_PLAN_AUTOTUNE if autotune else 0)
+        self.plan = _lib.wsr_plan_create(self.offsets, _lib.WSR_PLAN_MERGE_HULL if hull_only else 0)
+        self.tune_pending = bool(autotune)  # tuned on the first forward's weights
         self.ws = _workspace(_lib.wsr_plan_workspace_bytes(self.plan), self.device)
         self.perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
         self.mask = torch.empty(_mask_words(self.n), dtype=torch.int32, device=self.device)
@@ -122,6 +125,9 @@ class BatchedProx:
     def forward(self, w, out, lam=None, lam_scalar=0.0, save=True):
         _check_f32(w, "w")
         _check_f32(out, "out")
+        if self.tune_pending:  # synchronising: done before any graph capture
+            _lib.wsr_plan_autotune(self.plan, w, out, lam, lam_scalar, self.ws)
+            self.tune_pending = False
         _lib.wsr_prox_forward_batched(self.plan, w, out, lam, lam_scalar,
                                       self.perm if save else None, self.mask if save else None, self.ws)
 

@@ -52,6 +52,18 @@ def mlp_layers(lam=1e-3, seed=0, shapes=((4096, 3072), (4096, 4096), (10, 4096))
     return _pack("mlp_layers_%d" % offs[-1], case["w"], offs, lam)
 
 
+def ica_worst_rows(rows=1024, d=4095, seed=0):
+    """Rows holding the Sec. 4.1 worst case of ImminentCollisions recast as a prox input
+    (lam = 1, d odd): (d+1)/2 equal weights and a slow ramp j(eps + 2/(d-1)), j = 1..d//2, with
+    eps = 1/(4d), each row in its own random order.  Every row ends in one cluster after about
+    d/2 collision rounds, the case the bounded-depth hull merge is for."""
+    rng = np.random.default_rng(seed)
+    eps = 1.0 / (4 * d)
+    base = np.concatenate([np.zeros((d + 1) // 2), np.arange(1, d // 2 + 1) * (eps + 2.0 / (d - 1))])
+    w = np.concatenate([base[rng.permutation(d)] for _ in range(rows)])
+    return _pack("ica_worst_rows_%dx%d" % (rows, d), w, np.arange(rows + 1, dtype=np.int64) * d, 1.0)
+
+
 def chain(d=1 << 24, lam=0.7, shuffle=False, seed=0):
     """Worst-case collision chain: sorted w_k = (k/(d-1))^2 (gaps grow, so clusters merge one at
     a time from one end).  All particles end in one cluster once

@@ -36,18 +36,20 @@ def seg_start_of_rank(offsets):
     return np.repeat(offsets[:-1], lens)
 
 
-def gpu_forward(w, offsets, lam, save=True, batched=False, lam_arr=None):
+def gpu_forward(w, offsets, lam, save=True, batched=False, lam_arr=None, plan_flags=0, autotune=False):
     wt = dev(w)
     out = torch.empty_like(wt)
     n = w.shape[0]
     perm = torch.full((n,), -1, dtype=torch.int32, device="cuda") if save else None
     mask = torch.full(((n + 31) // 32,), -1, dtype=torch.int32, device="cuda") if save else None
     if batched:
-        plan = wsr.wsr_plan_create(offsets)
+        plan = wsr.wsr_plan_create(offsets, plan_flags)
         try:
             nb = wsr.wsr_plan_workspace_bytes(plan)
             ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
             la = dev(np.asarray(lam_arr, np.float32)) if lam_arr is not None else None
+            if autotune:
+                wsr.wsr_plan_autotune(plan, wt, out, la, lam, ws)
             wsr.wsr_prox_forward_batched(plan, wt, out, la, lam, perm, mask, ws)
             torch.cuda.synchronize()
         finally:

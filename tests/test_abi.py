@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 17
+    assert len(declared) == 19
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -158,12 +158,32 @@ def test_plan_argument_errors():
     off = np.array([0, 4], np.int64)
     assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 8, ctypes.byref(h)) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 1, ctypes.byref(h)) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_plan_autotune(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, 0, None) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_plan_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_destroy(None) == wsr.WSR_ERR_INVALID
     n = ctypes.c_size_t()
     assert lib.wsr_plan_workspace_bytes(None, ctypes.byref(n)) == wsr.WSR_ERR_INVALID
     assert lib.wsr_prox_forward_batched(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, None, None, 0,
                                         None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_prox_backward_batched(None, FAKE, FAKE, FAKE, FAKE, None, 0, None) == wsr.WSR_ERR_INVALID
+
+
+@pytest.mark.gpu
+def test_plan_merge_routes():
+    """The route a plan records: the default cap of collision rounds, or 0 (hull merge only).
+    Creating a plan uploads its offsets, so this needs a device."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("plan creation uploads offsets to a device")
+    p0 = wsr.wsr_plan_create([0, 100, 5000, 20000])
+    p1 = wsr.wsr_plan_create([0, 100, 5000, 20000], wsr.WSR_PLAN_MERGE_HULL)
+    try:
+        assert wsr.wsr_plan_merge_rounds(p0) == [6, 6, 6, 6]
+        assert wsr.wsr_plan_merge_rounds(p1) == [0, 0, 0, 0]
+    finally:
+        wsr.wsr_plan_destroy(p0)
+        wsr.wsr_plan_destroy(p1)
 
 
 def test_trace_collect_arguments():

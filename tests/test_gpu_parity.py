@@ -25,10 +25,11 @@ def _say(*a):
     sys.stdout.flush()
 
 
-def _check(case, batched=False, lam_arr=None):
+def _check(case, batched=False, lam_arr=None, plan_flags=0, autotune=False):
     w, off, lam = case["w"], case["offsets"], case["lam"]
-    _say("case", case.get("name"), "n", w.shape[0], "segments", off.shape[0] - 1, "batched", batched)
-    g = gpu_forward(w, off, lam, batched=batched, lam_arr=lam_arr)
+    _say("case", case.get("name"), "n", w.shape[0], "segments", off.shape[0] - 1, "batched", batched,
+         "plan flags", plan_flags, "autotune", autotune)
+    g = gpu_forward(w, off, lam, batched=batched, lam_arr=lam_arr, plan_flags=plan_flags, autotune=autotune)
     if lam_arr is not None:
         u, p, s = oracle.prox_segments(w, np.asarray(lam_arr, np.float32), off)
         o = dict(u=u, perm=p, start=s)
@@ -160,6 +161,21 @@ def test_ica_worst_case_long(d):
     case = dict(name="ica worst d=%d" % d, w=w, offsets=np.array([0, d], np.int64), lam=np.float32(1.0))
     g, _, st = _check(case)
     assert st["clusters"] == 1
+
+
+@pytest.mark.parametrize("route", ["hull_only", "autotuned"])
+def test_merge_routes(route):
+    """Both merge routes give the oracle's clusters: the hull merge alone (no collision rounds)
+    and whatever the autotuner keeps, on rows, long segments and the collision worst case."""
+    import paper_2311_03096_amd as wsr
+    flags = wsr.WSR_PLAN_MERGE_HULL if route == "hull_only" else 0
+    tune = route == "autotuned"
+    _check(workloads.mlp_rows(), batched=True, plan_flags=flags, autotune=tune)
+    lens = [1, 2, 65, 2049, 4096, 8192, 8193, 40000, 100003]
+    _check(workloads.random_segments(lens, "mixed", 0.05, seed=14), batched=True, plan_flags=flags,
+           autotune=tune)
+    g, _, st = _check(workloads.ica_worst_rows(64, 4095), batched=True, plan_flags=flags, autotune=tune)
+    assert st["clusters"] == 64
 
 
 def test_typical_d2p24():
