@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the typical and batched figures")
+    ap.add_argument("--rounds", default="", help="with --workload mlp: the batched plan's merge routes as four "
+                    "collision-round caps (2048,4096,8192,long classes) instead of autotuning them")
     ap.add_argument("--workload", choices=["chain", "typical", "mlp"], default="chain",
                     help="chain (default, the headline), or run only the typical d=2^24 vector or the "
                          "batched MLP rows (for profiling one workload)")
@@ -70,7 +72,7 @@ def log(*a):
 class Step:
     """Buffers and the fwd+bwd step of one workload through the C ABI."""
 
-    def __init__(self, case, batched=False):
+    def __init__(self, case, batched=False, autotune=False, rounds=None):
         import torch
         import paper_2311_03096_amd as wsr
         self.wsr, self.torch = wsr, torch
@@ -95,6 +97,13 @@ class Step:
             self.plan = None
             nb = wsr.wsr_workspace_bytes(self.offsets)
         self.ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        self.rounds = None
+        if batched and rounds is not None:  # merge routes given (e.g. an earlier run's tuning)
+            wsr.wsr_plan_set_merge_rounds(self.plan, rounds)
+            self.rounds = wsr.wsr_plan_merge_rounds(self.plan)
+        elif batched and autotune:  # merge route per size class, timed on these weights (synchronises)
+            wsr.wsr_plan_autotune(self.plan, self.w, self.out, None, self.lam, self.ws)
+            self.rounds = wsr.wsr_plan_merge_rounds(self.plan)
 
     def __call__(self):
         wsr = self.wsr
@@ -210,14 +219,15 @@ def cpu_baseline(case):
                 "%.1f s" % (reps, case["name"], w.shape[0], dt))
 
 
-def batched_vs_per_row(steps, warmup, per_row=True):
-    """MLP rows (8202 segments, 29.4M weights): fwd+bwd, graph-captured batched launches vs
-    per-row launches of the plain entry points on the same stream."""
+def batched_vs_per_row(steps, warmup, per_row=True, rounds=None):
+    """MLP rows (8202 segments, 29.4M weights): fwd+bwd, graph-captured batched launches (plan
+    autotuned once on these weights, outside the timed region) vs per-row launches of the plain
+    entry points on the same stream."""
     import torch
     from paper_2311_03096_amd import workloads
     case = workloads.mlp_rows()
     n = case["w"].shape[0]
-    b = Step(case, batched=True)
+    b = Step(case, batched=True, autotune=True, rounds=rounds)
     p = Step(case, batched=False) if per_row else None
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -239,7 +249,8 @@ def batched_vs_per_row(steps, warmup, per_row=True):
                 ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
                 speedup_graph_vs_per_row=round(ms_rows / ms_graph, 2), fwd_kernel_roofline=roof,
                 copy_GBps=round(copy_gbs, 1), step_fractions_graph=step_fractions(n, ms_graph, copy_gbs),
-                kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()})
+                kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
+                autotuned_merge_rounds=b.rounds)
 
 
 def l1_figures(steps, warmup):
@@ -398,7 +409,8 @@ def main():
 
     d = 1 << 24
     if args.workload == "mlp":
-        res = batched_vs_per_row(max(5, args.steps), args.warmup, per_row=not args.no_extra)
+        rounds = [int(x) for x in args.rounds.split(",")] if args.rounds else None
+        res = batched_vs_per_row(max(5, args.steps), args.warmup, per_row=not args.no_extra, rounds=rounds)
         print(json.dumps(res), flush=True)
         return
     case = workloads.chain(d, 0.7) if args.workload == "chain" else workloads.plain(d, 0.1, seed=1)

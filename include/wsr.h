@@ -173,6 +173,10 @@ WSR_API int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const 
  * writes 4 values. */
 WSR_API int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds);
 
+/* Sets the 4 caps (each 0..64), e.g. to reuse what wsr_plan_autotune found in an earlier run
+ * without timing again.  Host only; WSR_ERR_INVALID for a value out of range. */
+WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
+
 /* Workspace bytes needed by the batched calls of this plan. */
 WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);
 

@@ -26,6 +26,7 @@ EXPORTED = (
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
     "wsr_segment_stats", "wsr_segment_stats_batched", "wsr_plan_autotune", "wsr_plan_merge_rounds",
+    "wsr_plan_set_merge_rounds",
 )
 
 
@@ -61,6 +62,7 @@ def load():
         "wsr_segment_stats": ([p, p, i64, p, p, sz, p], i32),
         "wsr_plan_autotune": ([p, p, p, p, f32, p, sz, p], i32),
         "wsr_plan_merge_rounds": ([p, p], i32),
+        "wsr_plan_set_merge_rounds": ([p, p], i32),
         "wsr_segment_stats_batched": ([p, p, p, p, sz, p], i32),
         "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
         "wsr_plan_destroy": ([p], i32),
@@ -185,6 +187,11 @@ def wsr_plan_merge_rounds(plan):
     r = (ctypes.c_int32 * 4)()
     _check("wsr_plan_merge_rounds", load().wsr_plan_merge_rounds(plan, ctypes.cast(r, ctypes.c_void_p)))
     return list(r)
+
+
+def wsr_plan_set_merge_rounds(plan, rounds):
+    r = (ctypes.c_int32 * 4)(*[int(x) for x in rounds])
+    _check("wsr_plan_set_merge_rounds", load().wsr_plan_set_merge_rounds(plan, ctypes.cast(r, ctypes.c_void_p)))
 
 
 def wsr_prox_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, saved_perm=None, saved_mask=None,

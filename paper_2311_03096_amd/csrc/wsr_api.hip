@@ -22,6 +22,8 @@ namespace {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
+constexpr int kMaxMergeRounds = 64;  // largest collision-round cap a plan accepts
+
 enum SizeClass { kSkip = -1, kC2048 = 0, kC4096 = 1, kC8192 = 2, kBig = 3 };
 constexpr int kNumSmall = 3;
 constexpr int kClassMax[kNumSmall] = {2048, 4096, 8192};
@@ -660,6 +662,14 @@ int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
 int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds) {
   if (!plan || !rounds) return WSR_ERR_INVALID;
   for (int c = 0; c <= kNumSmall; ++c) rounds[c] = plan->rounds[c] < 0 ? kIcaRounds : plan->rounds[c];
+  return WSR_OK;
+}
+
+int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds) {
+  if (!plan || !rounds) return WSR_ERR_INVALID;
+  for (int c = 0; c <= kNumSmall; ++c)
+    if (rounds[c] < 0 || rounds[c] > kMaxMergeRounds) return WSR_ERR_INVALID;
+  for (int c = 0; c <= kNumSmall; ++c) plan->rounds[c] = rounds[c];
   return WSR_OK;
 }
 

@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 19
+    assert len(declared) == 20
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -161,6 +161,7 @@ def test_plan_argument_errors():
     assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 1, ctypes.byref(h)) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_autotune(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_plan_set_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_destroy(None) == wsr.WSR_ERR_INVALID
     n = ctypes.c_size_t()
     assert lib.wsr_plan_workspace_bytes(None, ctypes.byref(n)) == wsr.WSR_ERR_INVALID
@@ -181,6 +182,12 @@ def test_plan_merge_routes():
     try:
         assert wsr.wsr_plan_merge_rounds(p0) == [6, 6, 6, 6]
         assert wsr.wsr_plan_merge_rounds(p1) == [0, 0, 0, 0]
+        wsr.wsr_plan_set_merge_rounds(p0, [0, 16, 2, 6])
+        assert wsr.wsr_plan_merge_rounds(p0) == [0, 16, 2, 6]
+        with pytest.raises(wsr.WsrError):
+            wsr.wsr_plan_set_merge_rounds(p0, [0, 65, 2, 6])
+        with pytest.raises(wsr.WsrError):
+            wsr.wsr_plan_set_merge_rounds(p0, [-1, 6, 6, 6])
     finally:
         wsr.wsr_plan_destroy(p0)
         wsr.wsr_plan_destroy(p1)
