@@ -201,22 +201,41 @@ def roofline(trace, n_el, steps, workload):
     return res
 
 
-def cpu_baseline(case):
-    """Oracle forward + VJP over the whole workload on the host (one thread)."""
+def cpu_baseline(case, step=None):
+    """Oracle forward + VJP over the whole workload on the host (one thread), on the same upstream
+    gradient as the GPU step.  With ``step`` (the GPU step's buffers after the timed region) the
+    oracle's last results also give the accuracy of the GPU results."""
     import oracle
     w, off, lam = case["w"], case["offsets"], case["lam"]
-    g = np.random.default_rng(123).standard_normal(w.shape[0])
+    g = np.random.default_rng(123).standard_normal(w.shape[0]).astype(np.float32).astype(np.float64)
     reps, t0 = 0, time.perf_counter()
     while True:  # whole steps until about 10 s of CPU work
         u, perm, start = oracle.prox_segments(w, lam, off, n_threads=1)
-        oracle.vjp(g, perm, start, off)
+        vg = oracle.vjp(g, perm, start, off)
         reps += 1
         dt = time.perf_counter() - t0
         if dt >= 10.0:
             break
-    return dict(value=float(reps * w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
-                sample="%d full fwd+vjp steps of %s (%d elements each), FP64 sort + stack PAV, 1 thread, "
-                "%.1f s" % (reps, case["name"], w.shape[0], dt))
+    res = dict(value=float(reps * w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
+               sample="%d full fwd+vjp steps of %s (%d elements each), FP64 sort + stack PAV, 1 thread, "
+               "%.1f s" % (reps, case["name"], w.shape[0], dt))
+    acc = None
+    if step is not None:
+        out = step.out.cpu().numpy().astype(np.float64)
+        gw = step.gw.cpu().numpy().astype(np.float64)
+        words = step.mask.cpu().numpy().view(np.uint8)
+        start_g = np.unpackbits(words, bitorder="little")[:w.shape[0]]
+        scale = float(np.abs(w).max())
+        err = np.abs(out - u)
+        gerr = np.abs(gw - vg)
+        acc = dict(workload=case["name"], max_abs_err=float(err.max()), max_rel_err=float(err.max() / scale),
+                   grad_max_abs_err=float(gerr.max()),
+                   grad_max_rel_err=float(gerr.max() / max(float(np.abs(vg).max()), 1e-30)),
+                   clusters_gpu=int(start_g.sum()), clusters_oracle=int(start.sum()),
+                   permutation_equal=bool(np.array_equal(step.perm.cpu().numpy(), perm)),
+                   cluster_starts_differing=int((start_g != start).sum()),
+                   sum_w=float(w.astype(np.float64).sum()), sum_out_gpu=float(out.sum()))
+    return res, acc
 
 
 def batched_vs_per_row(steps, warmup, per_row=True, rounds=None):
@@ -456,8 +475,8 @@ def main():
                            parallelism="single GPU"),
                roofline=roof)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(case)
-        log("cpu", res["cpu_baseline"])
+        res["cpu_baseline"], res["accuracy"] = cpu_baseline(case, step)
+        log("cpu", res["cpu_baseline"], res["accuracy"])
     res["extra"] = extra
     print(json.dumps(res), flush=True)
 
