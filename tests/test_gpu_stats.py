@@ -103,3 +103,52 @@ def test_stats_of_l1_output_mlp_rows():
     _say("  weight-sharing measure (distinct / non-zero):", float(ratio), "non-zero fraction",
          float(ng.sum() / w.shape[0]))
     assert 0.0 < ratio < 1.0
+
+
+def test_graph_step_stats_replays():
+    """One optimizer step as a captured graph: the proximal-gradient step over rows and a long
+    segment (per-segment alphas on the device), then the statistics of the new weights.  Every
+    replay, with eager work and synchronisations between replays, equals the eager results."""
+    case = workloads.random_segments([3072] * 40 + [4096] * 40 + [10000], "normal", 0.01, seed=43)
+    off = case["offsets"]
+    n_seg = off.shape[0] - 1
+    w = dev(case["w"])
+    grad = dev(np.random.default_rng(44).standard_normal(w.numel()).astype(np.float32))
+    alpha = dev(np.linspace(1e-3, 2e-2, n_seg).astype(np.float32))
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        new = torch.empty_like(w)
+        st = torch.empty((n_seg, 3), dtype=torch.int64, device="cuda")
+
+        def step():
+            wsr.wsr_prox_step_batched(plan, w, grad, 0.1, new, alpha, 0.0, 0.05, 0.98, 0, ws)
+            wsr.wsr_segment_stats_batched(plan, new, st, ws)
+
+        step()
+        torch.cuda.synchronize()
+        ref_new, ref_st = new.clone(), st.clone()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for i in range(3):
+            new.zero_()
+            st.fill_(-1)
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(new, ref_new), "replay %d: weights differ" % i
+            assert torch.equal(st, ref_st), "replay %d: statistics differ" % i
+            _ = (w * 2).sum().item()  # eager work between replays
+        # and the eager result is the oracle's (a zero test decided at the threshold may differ:
+        # the step's own parity test covers those; here at most a couple are allowed)
+        o = oracle.prox_step_segments(case["w"], grad.cpu().numpy(), 0.1, alpha.cpu().numpy(), 0.05, 0.98, off)
+        bad = np.abs(ref_new.cpu().numpy() - o) > 1e-5 * np.abs(case["w"]).max() + 1e-7
+        assert bad.sum() <= 2, "step differs from the oracle at %d weights" % bad.sum()
+    finally:
+        wsr.wsr_plan_destroy(plan)
