@@ -144,6 +144,10 @@ class BatchedProx:
         _check_f32(w, "w")
         _check_f32(grad, "grad")
         out = w if out is None else out
+        if self.tune_pending:  # time the merge routes on these weights (scratch output, not w)
+            scratch = torch.empty_like(w)
+            _lib.wsr_plan_autotune(self.plan, w, scratch, alpha, float(alpha_scalar) * float(eta), self.ws)
+            self.tune_pending = False
         _lib.wsr_prox_step_batched(self.plan, w, grad, eta, out, alpha, alpha_scalar, beta, rho,
                                    _lib.WSR_STEP_ETA_IN_DISPLACEMENT if eta_in_displacement else 0, self.ws)
         return out

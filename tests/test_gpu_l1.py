@@ -171,3 +171,29 @@ def test_step_eta_edges(eta):
         assert np.array_equal(o1, case["w"])
     if eta == 1.0:
         np.testing.assert_allclose(o1, o2, rtol=0, atol=1e-6)
+
+
+def test_ops_batched_step_autotuned_in_place():
+    """The torch wrapper: a plan tuned on the first step's weights, an in-place step, the
+    statistics of the result."""
+    from paper_2311_03096_amd.ops import BatchedProx, row_offsets, segment_stats
+    off = row_offsets([(300, 3072), (2, 20000)])
+    rng = np.random.default_rng(50)
+    w0 = (rng.standard_normal(off[-1]) / 50).astype(np.float32)
+    g0 = rng.standard_normal(off[-1]).astype(np.float32)
+    w = torch.from_numpy(w0).cuda()
+    bp = BatchedProx(off, autotune=True)
+    try:
+        bp.step(w, torch.from_numpy(g0).cuda(), eta=0.1, alpha_scalar=1e-2, beta=0.1, rho=0.98)
+        torch.cuda.synchronize()
+        assert not bp.tune_pending
+    finally:
+        bp.close()
+    got = w.cpu().numpy()
+    o = oracle.prox_step_segments(w0, g0, 0.1, np.float32(1e-2), 0.1, 0.98, off, n_threads=NTHREADS)
+    bad = np.abs(got - o) > 1e-5 * float(np.abs(w0).max() + 0.1 * np.abs(g0).max()) + 1e-7
+    assert bad.sum() <= 2, "in-place step differs from the oracle at %d weights" % bad.sum()
+    R, nd, nz = segment_stats(w, off)
+    Ro, ndo, nzo = oracle.segment_stats(got, off)
+    np.testing.assert_allclose(R, Ro, rtol=1e-9)
+    assert np.array_equal(nd, ndo) and np.array_equal(nz, nzo)
