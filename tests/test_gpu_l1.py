@@ -18,7 +18,8 @@ if not torch.cuda.is_available():  # pragma: no cover - collected only where a G
     pytest.skip("no GPU", allow_module_level=True)
 
 import oracle  # noqa: E402
-from gpu_util import NTHREADS, compare_l1, gpu_forward, gpu_forward_l1, gpu_step  # noqa: E402
+import paper_2311_03096_amd as wsr  # noqa: E402
+from gpu_util import NTHREADS, compare_l1, dev, gpu_forward, gpu_forward_l1, gpu_step  # noqa: E402
 from paper_2311_03096_amd import workloads  # noqa: E402
 
 
@@ -197,3 +198,31 @@ def test_ops_batched_step_autotuned_in_place():
     Ro, ndo, nzo = oracle.segment_stats(got, off)
     np.testing.assert_allclose(R, Ro, rtol=1e-9)
     assert np.array_equal(nd, ndo) and np.array_equal(nz, nzo)
+
+
+def test_step_aliasing_and_nonfinite_gradient():
+    """out may alias the gradient; a non-finite gradient entry makes its segment NaN (the step's
+    input there is non-finite), the other segments are unaffected."""
+    lens = [3000, 9000, 4096, 20000]
+    case = workloads.random_segments(lens, "normal", 0.05, seed=51)
+    w0, off = case["w"], case["offsets"]
+    g0 = np.random.default_rng(52).standard_normal(w0.shape[0]).astype(np.float32)
+    g0[off[1] + 17] = np.nan   # second segment (long)
+    g0[off[2] + 5] = np.inf    # third segment (short)
+    o = oracle.prox_step_segments(w0, g0, 0.2, np.float32(0.05), 0.1, 0.5, off, n_threads=NTHREADS)
+    wt, gt = dev(w0), dev(g0)
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        wsr.wsr_prox_step_batched(plan, wt, gt, 0.2, gt, None, 0.05, 0.1, 0.5, 0, ws)  # out = grad
+        torch.cuda.synchronize()
+    finally:
+        wsr.wsr_plan_destroy(plan)
+    got = gt.cpu().numpy()
+    assert np.array_equal(np.isnan(got), np.isnan(o))
+    assert np.isnan(got[off[1]:off[2]]).all() and np.isnan(got[off[2]:off[3]]).all()
+    fin = ~np.isnan(o)
+    bad = np.abs(got[fin] - o[fin]) > 1e-5 * float(np.abs(w0).max() + 0.2 * np.nanmax(np.abs(g0[np.isfinite(g0)]))) + 1e-7
+    assert bad.sum() <= 2
+    assert np.array_equal(wt.cpu().numpy(), w0)  # w untouched
