@@ -376,8 +376,9 @@ def stats_figures(steps, warmup):
 
 def merge_route_figures(steps, warmup):
     """The merge routes side by side (inference forward, batched): ImminentCollisions rounds with
-    the hull merge as fallback (default), the hull merge alone, and the autotuned choice, on
-    training-like rows, on rows of the collision worst case, and on one long N(0,1) vector."""
+    the hull merge as fallback (default), the hull merge alone, EndCollisions (short segments),
+    and the autotuned choice, on training-like rows, on rows of the collision worst case, and on
+    one long N(0,1) vector."""
     import torch
     import paper_2311_03096_amd as wsr
     from paper_2311_03096_amd import workloads
@@ -389,8 +390,11 @@ def merge_route_figures(steps, warmup):
         w = torch.from_numpy(case["w"]).cuda()
         out = torch.empty_like(w)
         row = {}
-        for route in ("default", "hull_only", "autotuned"):
-            plan = wsr.wsr_plan_create(off, wsr.WSR_PLAN_MERGE_HULL if route == "hull_only" else 0)
+        for route in ("default", "hull_only", "end_collisions", "autotuned"):
+            if route == "end_collisions" and name.startswith("typical"):
+                continue  # one long segment: EndCollisions is a short-segment route
+            flags = {"hull_only": wsr.WSR_PLAN_MERGE_HULL, "end_collisions": wsr.WSR_PLAN_MERGE_END}.get(route, 0)
+            plan = wsr.wsr_plan_create(off, flags)
             try:
                 nb = wsr.wsr_plan_workspace_bytes(plan)
                 ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None

@@ -153,6 +153,11 @@ typedef struct wsr_plan wsr_plan; /* opaque, owned by the library */
  * On success *plan receives a new plan; free it with wsr_plan_destroy.
  */
 #define WSR_PLAN_MERGE_HULL 2
+/* WSR_PLAN_MERGE_END: short segments merge by EndCollisions (Sec. 4.2, Alg. end_collisions: the
+ * rightmost collision found by a block-wide reduction, one round per cluster: fast with few
+ * clusters, slow with many); long segments keep the default route.  Not combinable with
+ * WSR_PLAN_MERGE_HULL.  For comparing routes; results are identical. */
+#define WSR_PLAN_MERGE_END 4
 WSR_API int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan** plan);
 WSR_API int wsr_plan_destroy(wsr_plan* plan);
 
@@ -169,12 +174,13 @@ WSR_API int wsr_plan_destroy(wsr_plan* plan);
 WSR_API int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d_lambda,
                               float lambda_scalar, void* ws, size_t ws_bytes, void* stream);
 
-/* The plan's collision-round cap per size class (2048, 4096, 8192, long), 0 = hull merge only:
- * writes 4 values. */
+/* The plan's route per size class (2048, 4096, 8192, long): the cap on collision rounds before
+ * the hull merge (0 = hull merge only), or -1 = EndCollisions.  Writes 4 values. */
 WSR_API int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds);
 
-/* Sets the 4 caps (each 0..64), e.g. to reuse what wsr_plan_autotune found in an earlier run
- * without timing again.  Host only; WSR_ERR_INVALID for a value out of range. */
+/* Sets the 4 routes (short classes -1..64, long 0..64), e.g. to reuse what wsr_plan_autotune
+ * found in an earlier run without timing again.  Host only; WSR_ERR_INVALID for a value out of
+ * range. */
 WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
 
 /* Workspace bytes needed by the batched calls of this plan. */

@@ -5,7 +5,7 @@ The C ABI (include/wsr.h, libwsr.so) does the work in hand-written HIP kernels; 
 is its ctypes binding (same names) plus torch wrappers for autograd and batched steps.
 """
 from ._lib import (WSR_ERR_HIP, WSR_ERR_INVALID, WSR_ERR_UNSUPPORTED, WSR_ERR_WORKSPACE,
-                   WSR_MAX_SEGMENT, WSR_OK, WSR_PLAN_MERGE_HULL, WsrError, load,
+                   WSR_MAX_SEGMENT, WSR_OK, WSR_PLAN_MERGE_END, WSR_PLAN_MERGE_HULL, WsrError, load,
                    wsr_plan_autotune, wsr_plan_create, wsr_plan_destroy, wsr_plan_merge_rounds,
                    wsr_plan_set_merge_rounds,
                    wsr_plan_workspace_bytes,
@@ -24,6 +24,6 @@ __all__ = [
     "WSR_STEP_ETA_IN_DISPLACEMENT", "wsr_segment_stats", "wsr_segment_stats_batched", "stats_to_numpy",
     "wsr_trace_enable", "wsr_trace_collect",
     "WSR_OK", "WSR_ERR_INVALID", "WSR_ERR_WORKSPACE", "WSR_ERR_HIP", "WSR_ERR_UNSUPPORTED",
-    "WSR_PLAN_MERGE_HULL", "WSR_MAX_SEGMENT", "wsr_plan_autotune", "wsr_plan_merge_rounds",
+    "WSR_PLAN_MERGE_HULL", "WSR_PLAN_MERGE_END", "WSR_MAX_SEGMENT", "wsr_plan_autotune", "wsr_plan_merge_rounds",
     "wsr_plan_set_merge_rounds",
 ]

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libwsr.so")
 
 WSR_OK, WSR_ERR_INVALID, WSR_ERR_WORKSPACE, WSR_ERR_HIP, WSR_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 WSR_PLAN_MERGE_HULL = 2
+WSR_PLAN_MERGE_END = 4
 WSR_STEP_ETA_IN_DISPLACEMENT = 1
 WSR_MAX_SEGMENT = 1 << 26
 
@@ -183,7 +184,8 @@ def wsr_plan_autotune(plan, w, out, lam=None, lam_scalar=0.0, ws=None, stream=No
 
 
 def wsr_plan_merge_rounds(plan):
-    """The plan's collision-round cap per size class (2048, 4096, 8192, long); 0 = hull merge only."""
+    """The plan's route per size class (2048, 4096, 8192, long): the cap on collision rounds
+    (0 = hull merge only) or -1 = EndCollisions."""
     r = (ctypes.c_int32 * 4)()
     _check("wsr_plan_merge_rounds", load().wsr_plan_merge_rounds(plan, ctypes.cast(r, ctypes.c_void_p)))
     return list(r)

@@ -169,7 +169,10 @@ struct TraceScope {
 template <int TMAX, int NT>
 void launch_small_fwd(int nblocks, const SegArgs& a, const float* w, float* out, int32_t* perm,
                       uint32_t* mask, hipStream_t s) {
-  hipLaunchKernelGGL((k_prox_fwd_small<TMAX, NT>), dim3(nblocks), dim3(NT), 0, s, a, w, out, perm, mask);
+  if (a.merge_rounds == kRouteEnd)
+    hipLaunchKernelGGL((k_prox_fwd_small<TMAX, NT, true>), dim3(nblocks), dim3(NT), 0, s, a, w, out, perm, mask);
+  else
+    hipLaunchKernelGGL((k_prox_fwd_small<TMAX, NT, false>), dim3(nblocks), dim3(NT), 0, s, a, w, out, perm, mask);
 }
 template <int TMAX, int NT>
 void launch_small_bwd(int nblocks, const SegArgs& a, const float* g, float* gw, const int32_t* perm,
@@ -375,8 +378,10 @@ struct wsr_plan {
   std::vector<int32_t> big_segs;  // long segments, in order
   bool word_aligned = false;      // every offset a multiple of 32 (no mask zero fill needed)
   // merge route per size class (short classes, then long segments): cap on ImminentCollisions
-  // rounds before the bounded-depth hull merge; -1 = the library default, 0 = hull merge only
-  int rounds[kNumSmall + 1] = {-1, -1, -1, -1};
+  // rounds before the bounded-depth hull merge (0 = hull merge only), or -1: EndCollisions
+  // (short classes only)
+  int rounds[kNumSmall + 1] = {kIcaRounds, kIcaRounds, kIcaRounds, kIcaRounds};
+  int small_route(int c) const { return rounds[c] >= 0 ? rounds[c] : kRouteEnd; }
 };
 
 extern "C" {
@@ -453,7 +458,7 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0,
               l1.beta, l1.rho, l1.on, l1.kappa};
-    a.merge_rounds = plan->rounds[c];
+    a.merge_rounds = plan->small_route(c);
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
   for (int32_t seg : plan->big_segs) {
@@ -485,7 +490,7 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
-              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul, plan->rounds[c]};
+              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul, plan->small_route(c)};
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s);
   }
   for (int32_t seg : plan->big_segs) {
@@ -587,7 +592,8 @@ int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_off
 }
 
 int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan** plan) {
-  if (!plan || (flags & ~WSR_PLAN_MERGE_HULL)) return WSR_ERR_INVALID;
+  if (!plan || (flags & ~(WSR_PLAN_MERGE_HULL | WSR_PLAN_MERGE_END))) return WSR_ERR_INVALID;
+  if ((flags & WSR_PLAN_MERGE_HULL) && (flags & WSR_PLAN_MERGE_END)) return WSR_ERR_INVALID;
   *plan = nullptr;
   int64_t mb = 0;
   int rc = validate_offsets(h_offsets, n_seg, &mb);
@@ -601,6 +607,8 @@ int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan
   p->word_aligned = offsets_word_aligned(h_offsets, n_seg);
   if (flags & WSR_PLAN_MERGE_HULL)
     for (int c = 0; c <= kNumSmall; ++c) p->rounds[c] = 0;
+  if (flags & WSR_PLAN_MERGE_END)
+    for (int c = 0; c < kNumSmall; ++c) p->rounds[c] = -1;
   (void)hipGetDevice(&p->device);
   // schedules: segments of each class, longest first (short tail of the launch)
   std::vector<int32_t> cls_list[kNumSmall];
@@ -661,14 +669,14 @@ int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
 
 int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds) {
   if (!plan || !rounds) return WSR_ERR_INVALID;
-  for (int c = 0; c <= kNumSmall; ++c) rounds[c] = plan->rounds[c] < 0 ? kIcaRounds : plan->rounds[c];
+  for (int c = 0; c <= kNumSmall; ++c) rounds[c] = plan->rounds[c];
   return WSR_OK;
 }
 
 int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds) {
   if (!plan || !rounds) return WSR_ERR_INVALID;
   for (int c = 0; c <= kNumSmall; ++c)
-    if (rounds[c] < 0 || rounds[c] > kMaxMergeRounds) return WSR_ERR_INVALID;
+    if (rounds[c] < (c < kNumSmall ? -1 : 0) || rounds[c] > kMaxMergeRounds) return WSR_ERR_INVALID;
   for (int c = 0; c <= kNumSmall; ++c) plan->rounds[c] = rounds[c];
   return WSR_OK;
 }

@@ -8,6 +8,8 @@ namespace wsr {
 // ImminentCollisions rounds tried before the hull merge by default (typical weights converge
 // in 2-4 rounds).
 constexpr int kIcaRounds = 6;
+// SegArgs::merge_rounds value selecting the EndCollisions route (short segments only).
+constexpr int kRouteEnd = -2;
 
 // Which segment a workgroup of the short-segment kernels solves.  Batched launches give a
 // schedule (sched[blockIdx.x] = segment id) over device offsets; single-segment launches give
@@ -31,7 +33,7 @@ struct SegArgs {
   float eta = 0.0f;
   float lam_mul = 1.0f;
   int merge_rounds = -1;  // cap on ImminentCollisions rounds before the hull merge (-1: default,
-                          // 0: hull merge only)
+                          // 0: hull merge only), or kRouteEnd: EndCollisions
 };
 
 // Per-segment statistics (layout of wsr_segment_stats_t): R(w), the number of distinct non-zero
@@ -44,7 +46,7 @@ struct SegStats {
 
 template <int TMAX, int NT>
 __global__ void k_seg_stats_small(SegArgs args, const float* w, SegStats* stats);
-template <int TMAX, int NT>
+template <int TMAX, int NT, bool END>
 __global__ void k_prox_fwd_small(SegArgs args, const float* w, float* out, int32_t* perm_out,
                                  uint32_t* mask_out);
 template <int TMAX, int NT>

@@ -429,7 +429,75 @@ __device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int
   }
 }
 
-template <int TMAX, int NT>
+// EndCollisions (Sec. 4.2: the rightmost collision ends the cluster that starts at a; it is the
+// last b in (a, d] minimising the average of y over [a, b), i.e. the next vertex of the lower
+// hull of (k, S_k); Alg. end_collisions), repeated from a = 0 until b = d: one block-wide
+// reduction per cluster, so it is fast when the clusters are few and slow when they are many.
+// Later candidates win ties (rightmost), and a candidate q beats an earlier p exactly when p is
+// not strictly below the segment a -> q (the predicate of every other route).  sv[0..E] are the
+// thread's S values; red holds NT/64 ints.  Writes the hull vertices to vert (vert[0] = 0, the
+// last = d) and returns their number.  All threads must call.
+template <int NT, int E, typename SL>
+__device__ int end_collisions(const double* S, const double (&sv)[E + 1], int d, uint16_t* vert, int* red) {
+  constexpr int NW = NT / kWave;
+  const int tid = threadIdx.x;
+  const int k0 = tid * E;
+  int a = 0, nv = 0;
+  if (tid == 0) vert[0] = 0;
+  while (a < d) {
+    const double sa = S[SL::at(a)];
+    int best = -1;
+    double sbest = 0.0;
+#pragma unroll
+    for (int i = 1; i <= E; ++i) {
+      const int b = k0 + i;
+      if (b > a && b <= d && (best < 0 || !below(a, sa, best, sbest, b, sv[i]))) {
+        best = b;
+        sbest = sv[i];
+      }
+    }
+    // wave: butterfly over the lanes (both partners combine the same pair, so all agree)
+    for (int m = 1; m < kWave; m <<= 1) {
+      const int ob = __shfl_xor(best, m, kWave);
+      const double os = __shfl_xor(sbest, m, kWave);
+      if (ob >= 0) {
+        if (best < 0) {
+          best = ob;
+          sbest = os;
+        } else {
+          const bool lo_mine = best < ob;
+          const int p = lo_mine ? best : ob, q = lo_mine ? ob : best;
+          const double sp = lo_mine ? sbest : os, sq = lo_mine ? os : sbest;
+          const bool q_wins = !below(a, sa, p, sp, q, sq);
+          best = q_wins ? q : p;
+          sbest = q_wins ? sq : sp;
+        }
+      }
+    }
+    if (lane_id() == 0) red[tid / kWave] = best;
+    __syncthreads();
+    // block: the waves' winners in rank order, the same sequence in every thread
+    int w = -1;
+    double sw = 0.0;
+    for (int j = 0; j < NW; ++j) {
+      const int p = red[j];
+      if (p < 0) continue;
+      const double sp = S[SL::at(p)];
+      if (w < 0 || !below(a, sa, w, sw, p, sp)) {
+        w = p;
+        sw = sp;
+      }
+    }
+    __syncthreads();  // red is written again in the next round
+    a = w;
+    ++nv;
+    if (tid == 0) vert[nv] = (uint16_t)a;
+  }
+  __syncthreads();
+  return nv + 1;
+}
+
+template <int TMAX, int NT, bool END>
 __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small(SegArgs args, const float* w, float* out,
                                                        int32_t* perm_out, uint32_t* mask_out) {
   constexpr int IPT = TMAX / NT;
@@ -526,11 +594,13 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   __syncthreads();
 
   // collisions: ImminentCollisions rounds (converge in a few rounds on typical weights), else
-  // the bounded-depth hull merge
+  // the bounded-depth hull merge; or, in the END instantiation (a route the caller chooses),
+  // EndCollisions
   uint32_t bm;
   Cand lc, rc;
   bool staged = true;
-  if (ica_rounds<NT, E, SL>(sm.c.S, sv, d, args.merge_rounds < 0 ? kIcaRounds : args.merge_rounds, &bm, &lc, &rc,
+  if (!END &&
+      ica_rounds<NT, E, SL>(sm.c.S, sv, d, args.merge_rounds < 0 ? kIcaRounds : args.merge_rounds, &bm, &lc, &rc,
                             sm.wb)) {
     if (bm) {
       const int b0 = k0 + off;
@@ -546,8 +616,13 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     else
       walk_values<E>(bm, sv, lc, rc, d, c, ixr, sm.c.outv);
   } else {
-    tile_hull<NT, E, SL, int16_t>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
-    const int nv = sm.d.h.cnt[0];
+    int nv;
+    if constexpr (END) {
+      nv = end_collisions<NT, E, SL>(sm.c.S, sv, d, sm.d.h.vert, sm.ired);
+    } else {
+      tile_hull<NT, E, SL, int16_t>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
+      nv = sm.d.h.cnt[0];
+    }
     const uint16_t* vert = sm.d.h.vert;
     for (int i = tid; i < nv - 1; i += NT) {
       const int a = vert[i];
@@ -767,8 +842,10 @@ __global__ void k_scale_lambda(float* dst, const float* lam_arr, int seg_id, flo
 
 #define WSR_INSTANTIATE_SMALL(TM, NTH)                                                          \
   template __global__ void k_seg_stats_small<TM, NTH>(SegArgs, const float*, SegStats*);         \
-  template __global__ void k_prox_fwd_small<TM, NTH>(SegArgs, const float*, float*, int32_t*,   \
-                                                      uint32_t*);                               \
+  template __global__ void k_prox_fwd_small<TM, NTH, false>(SegArgs, const float*, float*,       \
+                                                             int32_t*, uint32_t*);              \
+  template __global__ void k_prox_fwd_small<TM, NTH, true>(SegArgs, const float*, float*,        \
+                                                            int32_t*, uint32_t*);               \
   template __global__ void k_prox_bwd_small<TM, NTH>(SegArgs, const float*, float*,             \
                                                       const int32_t*, const uint32_t*);
 

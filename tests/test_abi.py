@@ -159,6 +159,8 @@ def test_plan_argument_errors():
     assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 8, ctypes.byref(h)) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, 1, ctypes.byref(h)) == wsr.WSR_ERR_INVALID
+    both = wsr.WSR_PLAN_MERGE_HULL | wsr.WSR_PLAN_MERGE_END
+    assert lib.wsr_plan_create(off.ctypes.data_as(ctypes.c_void_p), 1, both, ctypes.byref(h)) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_autotune(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_set_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
@@ -186,8 +188,15 @@ def test_plan_merge_routes():
         assert wsr.wsr_plan_merge_rounds(p0) == [0, 16, 2, 6]
         with pytest.raises(wsr.WsrError):
             wsr.wsr_plan_set_merge_rounds(p0, [0, 65, 2, 6])
+        wsr.wsr_plan_set_merge_rounds(p0, [-1, 6, 6, 6])  # EndCollisions for the 2048 class
+        assert wsr.wsr_plan_merge_rounds(p0) == [-1, 6, 6, 6]
         with pytest.raises(wsr.WsrError):
-            wsr.wsr_plan_set_merge_rounds(p0, [-1, 6, 6, 6])
+            wsr.wsr_plan_set_merge_rounds(p0, [-2, 6, 6, 6])
+        with pytest.raises(wsr.WsrError):
+            wsr.wsr_plan_set_merge_rounds(p0, [6, 6, 6, -1])  # no EndCollisions for long segments
+        p2 = wsr.wsr_plan_create([0, 100, 5000, 20000], wsr.WSR_PLAN_MERGE_END)
+        assert wsr.wsr_plan_merge_rounds(p2) == [-1, -1, -1, 6]
+        wsr.wsr_plan_destroy(p2)
     finally:
         wsr.wsr_plan_destroy(p0)
         wsr.wsr_plan_destroy(p1)

@@ -163,12 +163,13 @@ def test_ica_worst_case_long(d):
     assert st["clusters"] == 1
 
 
-@pytest.mark.parametrize("route", ["hull_only", "autotuned"])
+@pytest.mark.parametrize("route", ["hull_only", "end_collisions", "autotuned"])
 def test_merge_routes(route):
-    """Both merge routes give the oracle's clusters: the hull merge alone (no collision rounds)
-    and whatever the autotuner keeps, on rows, long segments and the collision worst case."""
+    """Every merge route gives the oracle's clusters: the hull merge alone (no collision
+    rounds), EndCollisions on the short segments, and whatever the autotuner keeps, on rows,
+    long segments and the collision worst case."""
     import paper_2311_03096_amd as wsr
-    flags = wsr.WSR_PLAN_MERGE_HULL if route == "hull_only" else 0
+    flags = {"hull_only": wsr.WSR_PLAN_MERGE_HULL, "end_collisions": wsr.WSR_PLAN_MERGE_END}.get(route, 0)
     tune = route == "autotuned"
     _check(workloads.mlp_rows(), batched=True, plan_flags=flags, autotune=tune)
     lens = [1, 2, 65, 2049, 4096, 8192, 8193, 40000, 100003]
