@@ -20,8 +20,8 @@
  * - Device pointers are plain device addresses (hipMalloc / torch CUDA tensors) on
  *   the current HIP device; "stream" is a hipStream_t passed as void* (NULL = the
  *   null stream).  Every compute call only enqueues work on that stream, returns
- *   without synchronising (the exceptions, wsr_plan_autotune and wsr_trace_collect, say
- *   so), and allocates no memory: scratch comes from the caller's
+ *   without synchronising (the exceptions, wsr_plan_autotune, wsr_read_status and
+ *   wsr_trace_collect, say so), and allocates no memory: scratch comes from the caller's
  *   workspace "ws" of "ws_bytes" bytes (device memory, any contents, 256-byte
  *   aligned), sized with the matching *_workspace_bytes call.  Two calls that
  *   overlap in time on different streams must not share a workspace.
@@ -182,6 +182,16 @@ WSR_API int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds);
  * found in an earlier run without timing again.  Host only; WSR_ERR_INVALID for a value out of
  * range. */
 WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
+
+/*
+ * Sticky status of a plan's batched calls (forward, l1 forward, step): bit WSR_STATUS_NONFINITE
+ * is set on the device when any segment held a NaN or +-Inf input weight (that segment's
+ * outputs are NaN, as documented above) and stays set until read with clear != 0.  Synchronises
+ * the device, then copies the word to *flags (and clears it when clear != 0).  Not for use under
+ * graph capture.
+ */
+#define WSR_STATUS_NONFINITE 1u
+WSR_API int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear);
 
 /* Workspace bytes needed by the batched calls of this plan. */
 WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);

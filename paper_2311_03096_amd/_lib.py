@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libwsr.so")
 WSR_OK, WSR_ERR_INVALID, WSR_ERR_WORKSPACE, WSR_ERR_HIP, WSR_ERR_UNSUPPORTED = 0, -1, -2, -3, -4
 WSR_PLAN_MERGE_HULL = 2
 WSR_PLAN_MERGE_END = 4
+WSR_STATUS_NONFINITE = 1
 WSR_STEP_ETA_IN_DISPLACEMENT = 1
 WSR_MAX_SEGMENT = 1 << 26
 
@@ -27,7 +28,7 @@ EXPORTED = (
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
     "wsr_segment_stats", "wsr_segment_stats_batched", "wsr_plan_autotune", "wsr_plan_merge_rounds",
-    "wsr_plan_set_merge_rounds",
+    "wsr_plan_set_merge_rounds", "wsr_read_status",
 )
 
 
@@ -64,6 +65,7 @@ def load():
         "wsr_plan_autotune": ([p, p, p, p, f32, p, sz, p], i32),
         "wsr_plan_merge_rounds": ([p, p], i32),
         "wsr_plan_set_merge_rounds": ([p, p], i32),
+        "wsr_read_status": ([p, ctypes.POINTER(ctypes.c_uint32), i32], i32),
         "wsr_segment_stats_batched": ([p, p, p, p, sz, p], i32),
         "wsr_plan_create": ([p, i64, i32, ctypes.POINTER(p)], i32),
         "wsr_plan_destroy": ([p], i32),
@@ -194,6 +196,13 @@ def wsr_plan_merge_rounds(plan):
 def wsr_plan_set_merge_rounds(plan, rounds):
     r = (ctypes.c_int32 * 4)(*[int(x) for x in rounds])
     _check("wsr_plan_set_merge_rounds", load().wsr_plan_set_merge_rounds(plan, ctypes.cast(r, ctypes.c_void_p)))
+
+
+def wsr_read_status(plan, clear=True):
+    """Synchronise and return the plan's sticky status word (WSR_STATUS_NONFINITE bit)."""
+    v = ctypes.c_uint32(0)
+    _check("wsr_read_status", load().wsr_read_status(plan, ctypes.byref(v), 1 if clear else 0))
+    return v.value
 
 
 def wsr_prox_forward_batched(plan, w, out, lam=None, lam_scalar=0.0, saved_perm=None, saved_mask=None,

@@ -259,7 +259,7 @@ void big_sort(const float* wseg, int64_t d, const BigWs& b, int32_t* perm_final,
 // Forward of one long segment [start, start + d).
 int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
                 float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s,
-                const L1Opt& l1, int rounds = -1) {
+                const L1Opt& l1, int rounds = -1, uint32_t* status = nullptr) {
   BigWs b = big_layout(d, ws);
   const int nt = (int)ceil_div(d, kBigTile);
   int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
@@ -306,7 +306,7 @@ int big_forward(const float* w, float* out, int64_t start, int64_t d, const floa
   { WSR_TRACE("big_apply", s);
   hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, perm_final, d, lam_arr, seg_id,
                      lam_scalar, b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
-                     b.next_pos, b.next_s, out, saved_mask, start, l1.beta, l1.rho, l1.kappa, l1.on); }
+                     b.next_pos, b.next_s, out, saved_mask, start, l1.beta, l1.rho, l1.kappa, l1.on, status); }
   return last_error();
 }
 
@@ -382,6 +382,7 @@ struct wsr_plan {
   // (short classes only)
   int rounds[kNumSmall + 1] = {kIcaRounds, kIcaRounds, kIcaRounds, kIcaRounds};
   int small_route(int c) const { return rounds[c] >= 0 ? rounds[c] : kRouteEnd; }
+  uint32_t* d_status = nullptr;  // sticky status word (kStatusNonFinite), read by wsr_read_status
 };
 
 extern "C" {
@@ -459,13 +460,14 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0,
               l1.beta, l1.rho, l1.on, l1.kappa};
     a.merge_rounds = plan->small_route(c);
+    a.status = plan->d_status;
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
   for (int32_t seg : plan->big_segs) {
     const int64_t start = plan->h_offsets[seg];
     const int64_t d = plan->h_offsets[seg + 1] - start;
     const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s, l1,
-                               plan->rounds[kNumSmall]);
+                               plan->rounds[kNumSmall], plan->d_status);
     if (rc) return rc;
   }
   return last_error();
@@ -490,7 +492,7 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
-              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul, plan->small_route(c)};
+              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul, plan->small_route(c), plan->d_status};
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s);
   }
   for (int32_t seg : plan->big_segs) {
@@ -513,7 +515,7 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
       lam_seg = 0;
     }
     const int rc = big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, l1,
-                               plan->rounds[kNumSmall]);
+                               plan->rounds[kNumSmall], plan->d_status);
     if (rc) return rc;
   }
   return last_error();
@@ -639,11 +641,19 @@ int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan
     delete p;
     return WSR_ERR_HIP;
   }
+  if (hipMalloc(&p->d_status, sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(p->d_status, 0, sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(p->d_offsets);
+    if (p->d_status) (void)hipFree(p->d_status);
+    delete p;
+    return WSR_ERR_HIP;
+  }
   if (!sched.empty()) {
     if (hipMalloc(&p->d_sched, sizeof(int32_t) * sched.size()) != hipSuccess ||
         hipMemcpy(p->d_sched, sched.data(), sizeof(int32_t) * sched.size(), hipMemcpyHostToDevice) !=
             hipSuccess) {
       (void)hipFree(p->d_offsets);
+      (void)hipFree(p->d_status);
       if (p->d_sched) (void)hipFree(p->d_sched);
       delete p;
       return WSR_ERR_HIP;
@@ -657,7 +667,18 @@ int wsr_plan_destroy(wsr_plan* plan) {
   if (!plan) return WSR_ERR_INVALID;
   if (plan->d_offsets) (void)hipFree(plan->d_offsets);
   if (plan->d_sched) (void)hipFree(plan->d_sched);
+  if (plan->d_status) (void)hipFree(plan->d_status);
   delete plan;
+  return WSR_OK;
+}
+
+int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear) {
+  if (!plan || !flags) return WSR_ERR_INVALID;
+  if (hipDeviceSynchronize() != hipSuccess) return WSR_ERR_HIP;
+  uint32_t v = 0;
+  if (hipMemcpy(&v, plan->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return WSR_ERR_HIP;
+  if (clear && hipMemset(plan->d_status, 0, sizeof(uint32_t)) != hipSuccess) return WSR_ERR_HIP;
+  *flags = v;
   return WSR_OK;
 }
 

@@ -52,7 +52,8 @@ __global__ void k_big_apply(const uint32_t* skeys, const int32_t* perm, int64_t 
                             const int32_t* hi_g,
                             const int32_t* prev_pos, const double* prev_s, const int32_t* next_pos,
                             const double* next_s, float* out, uint32_t* mask_out,
-                            int64_t seg_start, float beta, float rho, float kappa, int l1);
+                            int64_t seg_start, float beta, float rho, float kappa, int l1,
+                            uint32_t* status);
 __global__ void k_big_bwd_tile(const float* g, const int32_t* perm, const uint32_t* mask,
                                int64_t d, int64_t seg_start, float* gsorted, double* tsum,
                                int32_t* fpos, double* fG, int32_t* lpos, double* lG);

@@ -921,7 +921,8 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
                                                            const double* prev_s, const int32_t* next_pos,
                                                            const double* next_s, float* out,
                                                            uint32_t* mask_out, int64_t seg_start,
-                                                           float beta, float rho, float kappa, int l1) {
+                                                           float beta, float rho, float kappa, int l1,
+                                                           uint32_t* status) {
   constexpr int R = kBigTile / kBigThreads;
   __shared__ ApplySmem sm;
   const int tid = threadIdx.x;
@@ -934,6 +935,7 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
   const bool nonfinite = (flags[0] & 1u) != 0;
   const bool identity = nonfinite || !(lam > 0.0f);
+  if (nonfinite && t == 0 && tid == 0 && status) atomicOr(status, kStatusNonFinite);
   // segment-relative 32-bit offsets (d <= 2^26) from a uniform base
   float* const og = out + seg_start;
   const int32_t* const pt = perm + k0;

@@ -34,7 +34,11 @@ struct SegArgs {
   float lam_mul = 1.0f;
   int merge_rounds = -1;  // cap on ImminentCollisions rounds before the hull merge (-1: default,
                           // 0: hull merge only), or kRouteEnd: EndCollisions
+  uint32_t* status = nullptr;  // sticky status word: bit 0 is OR-ed in for a non-finite segment
 };
+
+// Bits of the sticky status word of a plan.
+constexpr uint32_t kStatusNonFinite = 1u;
 
 // Per-segment statistics (layout of wsr_segment_stats_t): R(w), the number of distinct non-zero
 // values and the number of non-zero weights.

@@ -543,6 +543,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   }
   bucket_sort_prologue<TMAX, NT>(sm, k, d);  // shares the barrier below
   const bool nonfinite = __syncthreads_or(bad) != 0;
+  if (nonfinite && tid == 0 && args.status) atomicOr(args.status, kStatusNonFinite);
   if (nonfinite || d == 1 || !(lam > 0.0f)) {
     // identity (or NaN) segment: every weight its own cluster, perm = identity
 #pragma unroll

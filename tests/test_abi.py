@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 20
+    assert len(declared) == 21
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -164,6 +164,7 @@ def test_plan_argument_errors():
     assert lib.wsr_plan_autotune(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_set_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_read_status(None, None, 0) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_destroy(None) == wsr.WSR_ERR_INVALID
     n = ctypes.c_size_t()
     assert lib.wsr_plan_workspace_bytes(None, ctypes.byref(n)) == wsr.WSR_ERR_INVALID

@@ -226,3 +226,35 @@ def test_step_aliasing_and_nonfinite_gradient():
     bad = np.abs(got[fin] - o[fin]) > 1e-5 * float(np.abs(w0).max() + 0.2 * np.nanmax(np.abs(g0[np.isfinite(g0)]))) + 1e-7
     assert bad.sum() <= 2
     assert np.array_equal(wt.cpu().numpy(), w0)  # w untouched
+
+
+def test_sticky_nonfinite_status():
+    """A plan's status word records a non-finite input weight from any batched forward-type call
+    (short or long segment) until it is read and cleared."""
+    lens = [3000, 20000]
+    case = workloads.random_segments(lens, "normal", 0.05, seed=53)
+    off = case["offsets"]
+    w_ok = dev(case["w"])
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        out = torch.empty_like(w_ok)
+        wsr.wsr_prox_forward_batched(plan, w_ok, out, None, 0.05, None, None, ws)
+        assert wsr.wsr_read_status(plan) == 0
+        for where in (off[0] + 5, off[1] + 19999):  # short segment, then long segment
+            w_bad = w_ok.clone()
+            w_bad[int(where)] = float("nan")
+            wsr.wsr_prox_forward_batched(plan, w_bad, out, None, 0.05, None, None, ws)
+            wsr.wsr_prox_forward_batched(plan, w_ok, out, None, 0.05, None, None, ws)  # sticky
+            assert wsr.wsr_read_status(plan, clear=False) == wsr.WSR_STATUS_NONFINITE
+            assert wsr.wsr_read_status(plan) == wsr.WSR_STATUS_NONFINITE
+            assert wsr.wsr_read_status(plan) == 0
+        g = torch.zeros_like(w_ok)
+        g[7] = float("inf")
+        wsr.wsr_prox_step_batched(plan, w_ok, g, 0.1, out, None, 0.1, 0.0, 0.0, 0, ws)
+        assert wsr.wsr_read_status(plan) == wsr.WSR_STATUS_NONFINITE
+        wsr.wsr_prox_l1_forward_batched(plan, w_ok, out, None, 0.05, 0.1, 0.5, ws)
+        assert wsr.wsr_read_status(plan) == 0
+    finally:
+        wsr.wsr_plan_destroy(plan)
