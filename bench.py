@@ -201,6 +201,17 @@ def roofline(trace, n_el, steps, workload):
     return res
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(case, step=None):
     """Oracle forward + VJP over the whole workload on the host (one thread), on the same upstream
     gradient as the GPU step.  With ``step`` (the GPU step's buffers after the timed region) the
@@ -218,7 +229,18 @@ def cpu_baseline(case, step=None):
             break
     res = dict(value=float(reps * w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
                sample="%d full fwd+vjp steps of %s (%d elements each), FP64 sort + stack PAV, 1 thread, "
-               "%.1f s" % (reps, case["name"], w.shape[0], dt))
+               "%.1f s" % (reps, case["name"], w.shape[0], dt), host_cpu=_cpu_model())
+    # the row-batched workload on every host core (rows split across POSIX threads), one step
+    from paper_2311_03096_amd import workloads
+    rows = workloads.mlp_rows()
+    nthr = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    gr = np.random.default_rng(123).standard_normal(rows["w"].shape[0]).astype(np.float32).astype(np.float64)
+    t1 = time.perf_counter()
+    ur, pr, sr = oracle.prox_segments(rows["w"], rows["lam"], rows["offsets"], n_threads=nthr)
+    oracle.vjp(gr, pr, sr, rows["offsets"])
+    dt1 = time.perf_counter() - t1
+    res["mlp_rows_all_cores"] = dict(value=float(rows["w"].shape[0] / dt1), unit="elements/s", cores=nthr,
+                                     sample="one fwd+vjp step of the 8202 MLP rows, %.2f s" % dt1)
     acc = None
     if step is not None:
         out = step.out.cpu().numpy().astype(np.float64)
