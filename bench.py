@@ -212,6 +212,27 @@ def _cpu_model():
     return "unknown"
 
 
+VALU_PEAK_WAVE_INSTR = 256 * 2.4e9  # one wave64 VALU instruction per clock per CU (4 SIMDs x 16 lanes)
+
+
+def alu_roofline(kernel, avg_ms, workload):
+    """The issue-rate bound of a kernel that is not HBM-bound: its VALU wave-instructions per
+    launch (committed rocprofv3 counter summary, matched by kernel source hash) over its mean
+    launch time, against one wave64 VALU instruction per clock per CU; the LDS instructions
+    per launch are given beside it."""
+    if not kernel or not avg_ms:
+        return None
+    from paper_2311_03096_amd import prof_summary as ps
+    c = ps.read_counters(os.path.join(ROOT, "profiles", "counters_%s.md" % workload), workload, kernel)
+    if c is None:
+        return None
+    achieved = c["valu"] / (avg_ms * 1e-3)
+    return dict(kernel=kernel, bound="alu", unit="wave64 VALU instr/s", achieved=achieved,
+                peak=VALU_PEAK_WAVE_INSTR, frac=round(achieved / VALU_PEAK_WAVE_INSTR, 4),
+                valu_per_launch=c["valu"], lds_per_launch=c["lds"],
+                valu_floor_ms=round(c["valu"] / VALU_PEAK_WAVE_INSTR * 1e3, 4))
+
+
 def cpu_baseline(case, step=None):
     """Oracle forward + VJP over the whole workload on the host (one thread), on the same upstream
     gradient as the GPU step.  With ``step`` (the GPU step's buffers after the timed region) the
@@ -286,6 +307,7 @@ def batched_vs_per_row(steps, warmup, per_row=True, rounds=None):
     copy_gbs = copy_bandwidth()
     roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4) if roof.get("achieved") else None
     return dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
+                fwd_kernel_alu_roofline=alu_roofline(roof.get("kernel"), roof.get("avg_ms"), "mlp_rows"),
                 elements=n, ms_per_step_graph=round(ms_graph, 4), ms_per_step_batched=round(ms_batched, 4),
                 ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
                 speedup_graph_vs_per_row=round(ms_rows / ms_graph, 2), fwd_kernel_roofline=roof,
@@ -396,6 +418,32 @@ def stats_figures(steps, warmup):
     return res
 
 
+def lds_probe_figures():
+    """LDS throughput on this device (the bound of the short-segment kernels next to VALU):
+    conflict-free 4-byte reads, random 4-byte reads, random 4-byte atomics, from the probes of
+    libwsr_probe.so (measurement only)."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2311_03096_amd", "libwsr_probe.so"))
+    lib.wsr_lds_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.wsr_lds_probe_shape.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    nt, nw = ctypes.c_int(), ctypes.c_int()
+    lib.wsr_lds_probe_shape(ctypes.byref(nt), ctypes.byref(nw))
+    blocks, rounds = 4 * 256, 512  # 8 accesses per lane per round
+    out = torch.zeros(blocks, dtype=torch.int32, device="cuda")
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = dict(workgroups=blocks, threads=nt.value, accesses_per_thread=rounds * 8)
+    for kind, name, nbytes in ((0, "read4_conflict_free", 4), (1, "read4_random", 4), (2, "atomic4_random", 4)):
+        fn = lambda: lib.wsr_lds_probe(kind, rounds, blocks, ctypes.c_void_p(out.data_ptr()), stream)
+        assert fn() == 0
+        ms = time_steps(fn, 5, 1)[0]
+        accesses = blocks * nt.value * rounds * 8
+        res[name] = dict(ms=round(ms, 4), G_accesses_per_s=round(accesses / (ms * 1e-3) / 1e9, 1),
+                         TBps=round(accesses * nbytes / (ms * 1e-3) / 1e12, 2),
+                         bytes_per_clk_per_cu=round(accesses * nbytes / (ms * 1e-3) / 256 / 2.4e9, 1))
+    return res
+
+
 def merge_route_figures(steps, warmup):
     """The merge routes side by side (inference forward, batched): ImminentCollisions rounds with
     the hull merge as fallback (default), the hull merge alone, EndCollisions (short segments),
@@ -485,6 +533,8 @@ def main():
         log("l1", extra["prox_l1_rewinding"])
         extra["segment_stats"] = stats_figures(max(5, args.steps), args.warmup)
         log("stats", extra["segment_stats"])
+        extra["lds_probe"] = lds_probe_figures()
+        log("lds probe", extra["lds_probe"])
         extra["merge_routes"] = merge_route_figures(max(5, args.steps), args.warmup)
         log("merge routes", extra["merge_routes"])
         lay = workloads.mlp_layers()

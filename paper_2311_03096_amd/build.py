@@ -17,18 +17,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+PROBE_LIB = os.path.join(HERE, "libwsr_probe.so")  # LDS throughput probes (measurement only)
+PROBE_SOURCES = ["wsr_lds_probe.hip"]
+
+
+def _hipcc(sources, lib, verbose):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [hipcc] + FLAGS + [os.path.join(CSRC, s) for s in sources] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + err)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
+    return _hipcc(SOURCES, LIB, verbose)
 
 
 if __name__ == "__main__":

@@ -25,12 +25,15 @@ import re
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
+PROBE_SOURCES = ("wsr_lds_probe.hip",)  # measurement probes, not kernels of the prox path
+
+
 def source_hash() -> str:
-    """Hash of the HIP kernel sources (every file under csrc/), so a stored counter reading can
-    be matched to the code it was taken on."""
+    """Hash of the HIP kernel sources of the prox library (the files under csrc/ other than the
+    measurement probes), so a stored counter reading can be matched to the code it was taken on."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
+        if name.endswith((".hip", ".h")) and name not in PROBE_SOURCES:
             h.update(name.encode())
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(f.read())
@@ -123,6 +126,52 @@ def read_traffic(path, workload, kernel):
     return None
 
 
+INSTR_COUNTERS = ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVES")
+
+
+def instr_counters(csv_path, workload, command):
+    """Per-launch wave-instruction counts (VALU, LDS, SALU) and waves of every library kernel
+    from one rocprofv3 --pmc run, with counter records that the bench matches by source hash."""
+    per = {c: _per_kernel(csv_path, c)[0] for c in INSTR_COUNTERS}
+    src = source_hash()
+    out = ["# Instruction counters per launch: %s" % workload, "",
+           "Wave-level instruction counts per dispatch (`SQ_INSTS_*` sum over the dispatch's waves) "
+           "from one rocprofv3 --pmc run.", "", "Command:", "", "```", command, "```", "",
+           "Kernel sources hash: `%s`" % src, "",
+           "| kernel | dispatches | VALU | LDS | SALU | waves | VALU / wave | LDS / wave |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    recs = []
+    for k in sorted(per["SQ_INSTS_VALU"]):
+        n, valu = per["SQ_INSTS_VALU"][k]
+        lds = per["SQ_INSTS_LDS"].get(k, (0, 0.0))[1]
+        salu = per["SQ_INSTS_SALU"].get(k, (0, 0.0))[1]
+        waves = per["SQ_WAVES"].get(k, (0, 0.0))[1]
+        out.append("| %s | %d | %.4g | %.4g | %.4g | %.0f | %.0f | %.0f |" % (
+            k, n, valu, lds, salu, waves, valu / max(waves, 1), lds / max(waves, 1)))
+        if k.startswith(("radix_", "big_", "prox_")):
+            recs.append("counter-record: workload=%s kernel=%s src=%s valu=%.0f lds=%.0f salu=%.0f waves=%.0f" % (
+                workload, k, src, valu, lds, salu, waves))
+    out += ["", "```"] + recs + ["```"]
+    return "\n".join(out) + "\n"
+
+
+def read_counters(path, workload, kernel):
+    """{valu, lds, salu, waves} per launch of `kernel` from an instruction-counter summary, or None
+    when missing or measured on other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    src = source_hash()
+    for line in open(path):
+        if not line.startswith("counter-record:"):
+            continue
+        kv = dict(t.split("=", 1) for t in line.split()[1:])
+        if kv.get("workload") == workload and kv.get("kernel") == kernel:
+            if kv.get("src") != src:
+                return None
+            return {c: float(kv[c]) for c in ("valu", "lds", "salu", "waves")}
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -137,9 +186,15 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--command", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         print(stats(a.csv, a.title, a.command), end="")
+    elif a.cmd == "counters":
+        print(instr_counters(a.csv, a.workload, a.command), end="")
     else:
         print(traffic(a.fetch_csv, a.write_csv, a.calib_bytes, a.workload, a.command_fetch, a.command_write),
               end="")

@@ -35,3 +35,14 @@ def test_read_traffic_rejects_other_sources(tmp_path):
     p.write_text("traffic-record: workload=x kernel=k src=%s read_bytes=10 write_bytes=5\n" % ps.source_hash())
     assert ps.read_traffic(str(p), "x", "k") == 15.0
     assert ps.read_traffic(str(p), "x", "other") is None
+
+
+def test_counter_summary_parses():
+    f = os.path.join(ROOT, "profiles", "counters_mlp_rows.md")
+    recs = [l for l in open(f) if l.startswith("counter-record:")]
+    assert recs
+    for line in recs:
+        kv = dict(t.split("=", 1) for t in line.split()[1:])
+        assert kv["workload"] == "mlp_rows" and len(kv["src"]) == 16
+        assert float(kv["valu"]) > 0 and float(kv["waves"]) > 0
+    assert "rocprofv3 --pmc SQ_INSTS_VALU" in open(f).read()
