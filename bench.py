@@ -533,7 +533,10 @@ def main():
         log("l1", extra["prox_l1_rewinding"])
         extra["segment_stats"] = stats_figures(max(5, args.steps), args.warmup)
         log("stats", extra["segment_stats"])
-        extra["lds_probe"] = lds_probe_figures()
+        try:  # a measurement aside: its absence must not cost the bench line
+            extra["lds_probe"] = lds_probe_figures()
+        except Exception as e:  # noqa: BLE001
+            extra["lds_probe"] = dict(error=str(e))
         log("lds probe", extra["lds_probe"])
         extra["merge_routes"] = merge_route_figures(max(5, args.steps), args.warmup)
         log("merge routes", extra["merge_routes"])
