@@ -164,8 +164,9 @@ WSR_API int wsr_plan_destroy(wsr_plan* plan);
 /*
  * Autotuner: times the merge routes of every size class of the plan on the caller's weights
  * (the batched forward of that class alone, without saved state: a warm-up launch and three
- * timed ones per route; routes = a cap of 0 (hull merge only), 2, 6 or 16 ImminentCollisions
- * rounds before the hull merge; long segments: 0 or 6, timed on the longest one) and keeps the
+ * timed ones per route; routes = a cap of 0 (hull merge only), 2, 6, 16 or 64
+ * ImminentCollisions rounds before the hull merge; long segments: 0, 6 or 16, timed on the
+ * longest one) and keeps the
  * fastest route of each class in the plan for every later batched call.  Synchronises the
  * stream; not for use under graph capture.
  *   w[N]      device weights of the plan's layout; out[N] device scratch (overwritten)

@@ -716,7 +716,7 @@ int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d
     (void)hipEventDestroy(e0);
     return WSR_ERR_HIP;
   }
-  constexpr int kCand[] = {0, 2, kIcaRounds, 16};  // 0: hull merge only
+  constexpr int kCand[] = {0, 2, kIcaRounds, 16, 64};  // 0: hull merge only
   constexpr int kReps = 3;
   int rc = WSR_OK;
   // one route at a time: a warm-up launch, then kReps timed launches of the class alone
@@ -751,7 +751,7 @@ int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d
     const int64_t start = plan->h_offsets[seg];
     const int64_t d = plan->h_offsets[seg + 1] - start;
     float best = 0.0f;
-    for (int r : {0, kIcaRounds}) {
+    for (int r : {0, kIcaRounds, 16}) {
       float ms = 0.0f;
       int lrc = WSR_OK;
       rc = time_route([&] {
