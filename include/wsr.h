@@ -194,6 +194,10 @@ WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
 #define WSR_STATUS_NONFINITE 1u
 WSR_API int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear);
 
+/* A plan may be used by calls on any stream, but calls that overlap in time must not share a
+ * workspace; wsr_plan_autotune and wsr_plan_set_merge_rounds change the plan and must not run
+ * while other calls with the same plan are being issued from another host thread. */
+
 /* Workspace bytes needed by the batched calls of this plan. */
 WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);
 
