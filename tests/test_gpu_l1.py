@@ -258,3 +258,30 @@ def test_sticky_nonfinite_status():
         assert wsr.wsr_read_status(plan) == 0
     finally:
         wsr.wsr_plan_destroy(plan)
+
+
+def _random_layout(seed):
+    rng = np.random.default_rng(2000 + seed)
+    nseg = int(rng.integers(1, 41))
+    kinds = rng.choice(["tiny", "short", "long"], nseg, p=[0.3, 0.5, 0.2])
+    lens = [int(rng.integers(0, 40)) if k == "tiny" else int(rng.integers(40, 8193)) if k == "short"
+            else int(rng.integers(8193, 150000)) for k in kinds]
+    dist = ["normal", "laplace", "ties", "sorted", "mixed"][seed % 5]
+    lam = float(10.0 ** rng.uniform(-4, 0))
+    case = workloads.random_segments(lens, dist, lam, seed=seed)
+    scale = float(np.abs(case["w"]).max()) if case["w"].size else 1.0
+    beta = float(rng.choice([0.0, 0.01, 0.1, 0.5])) * scale
+    rho = float(rng.choice([0.0, 0.5, 0.98, 1.0]))
+    return case, beta, rho, rng
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_l1_and_step_random_layouts(seed):
+    """Seeded random layouts (1-40 segments, 1 to ~150k weights each, every distribution):
+    Alg. prox in full through the plain and batched entry points, and one proximal-gradient step
+    in both forms, against the oracle."""
+    case, beta, rho, rng = _random_layout(seed)
+    _check_l1(case, beta, rho, batched=bool(seed % 2))
+    eta = float(rng.choice([0.05, 0.1, 1.0]))
+    _check_step(case, eta, case["lam"] / eta, beta / eta, rho, variant=bool(seed % 2), inplace=bool(seed % 3),
+                seed=seed)

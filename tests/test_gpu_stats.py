@@ -152,3 +152,15 @@ def test_graph_step_stats_replays():
         assert bad.sum() <= 2, "step differs from the oracle at %d weights" % bad.sum()
     finally:
         wsr.wsr_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_stats_random_layouts(seed):
+    rng = np.random.default_rng(3000 + seed)
+    nseg = int(rng.integers(1, 41))
+    kinds = rng.choice(["tiny", "short", "long"], nseg, p=[0.3, 0.5, 0.2])
+    lens = [int(rng.integers(0, 40)) if k == "tiny" else int(rng.integers(40, 8193)) if k == "short"
+            else int(rng.integers(8193, 150000)) for k in kinds]
+    dist = ["normal", "laplace", "ties", "sorted", "mixed"][seed % 5]
+    case = workloads.random_segments(lens, dist, 0.1, seed=seed)
+    _check(case["w"], case["offsets"], case["name"], batched=bool(seed % 2))
