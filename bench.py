@@ -5,11 +5,14 @@ merge, scatter, saved permutation and cluster-start bits) then backward (cluster
 upstream gradient).  Default workload: the worst-case collision chain, one segment of
 d = 2^24 FP32 weights w_k = (k/(d-1))^2 with lam = 0.7 (every particle ends in one cluster).
 
-Prints one JSON line: elements/s, the roofline of the dominant kernel (HIP-event durations
-measured live on the library's stream), the CPU oracle on the host as a reference, and extra
-figures: a typical d = 2^24 N(0,1) vector, the batched MLP-rows workload (graph-captured
-batched launch versus per-row launches), and Alg. prox in full (l1 and rewinding lines) on both
-next to the plain forward.
+Prints one JSON line: elements/s over the timed steps, the roofline of the dominant kernel
+(HIP-event durations measured live on the library's stream; a sort pass is charged its share of
+the sort's one key + index round trip), the CPU oracle on the host as a reference, and extra
+figures, each the median of >= 50 timed reps after >= 10 warm-ups: one row per workload (plain
+d = 4096, the shuffled chain, a typical N(0,1) vector of 2^24, the 1024 x 8192 backward rows, the
+d = 2^26 precision vector with its FP32 negative control), the batched MLP rows (graph-captured
+batched launches versus per-row launches), Alg. prox in full, segment statistics, the merge
+routes and the per-layer segmentation.
 """
 from __future__ import annotations
 
@@ -33,10 +36,16 @@ WORKLOAD_TEXT = {
 }
 
 # Algorithmic HBM bytes per element that each kernel must move (compulsory traffic of its role
-# in the path; see the design notes).  "el" = elements of the segment(s) the launch covers.
+# in the path; see the design notes).  "el" = elements of the segment(s) the launch covers.  A
+# segment too long for on-chip memory needs one out-of-core key + index round trip for its sort
+# (SORT_ROUND_TRIP_B per element, once per sort): it is spread over the sort's scatter passes, so
+# each scatter launch is charged its share; the histogram passes and the extra passes of a
+# multi-pass sort are not compulsory.  The rate of one scatter pass moving key + index once is
+# reported beside it as ``achieved_per_pass``.
+SORT_ROUND_TRIP_B = 16.0
 KERNEL_BYTES_PER_EL = {
-    "radix_scatter": 16.0,      # read key+index 8 B, write key+index 8 B
-    "radix_hist": 4.0,          # read key
+    "radix_hist": 0.0,          # histogram reads: not compulsory (inside the sort's round trip)
+    "radix_rowscan": 0.0,
     "big_tile_hull": 4.0,       # read sorted key (hull vertices are bookkeeping)
     "big_apply": 12.125,        # read sorted key + perm 8 B, write value 4 B, start bit
     "big_bwd_tile": 12.0,       # read perm 4 + gradient 4, write gathered gradient 4
@@ -45,7 +54,11 @@ KERNEL_BYTES_PER_EL = {
     "prox_bwd_small_4096": 12.125,  # read g + perm + bit, write gradient
     "prox_fwd_small_8192": 12.125,
     "prox_bwd_small_8192": 12.125,
+    "prox_fwd_small_2048": 12.125,
+    "prox_bwd_small_2048": 12.125,
 }
+SORT_KERNELS = ("radix_scatter", "radix_hist", "radix_rowscan")
+MED_REPS, MED_WARMUP = 50, 10  # extra figures: median of >= 50 timed reps after >= 10 warm-ups
 
 
 def parse():
@@ -57,9 +70,11 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="skip the typical and batched figures")
     ap.add_argument("--rounds", default="", help="with --workload mlp: the batched plan's merge routes as four "
                     "collision-round caps (2048,4096,8192,long classes) instead of autotuning them")
-    ap.add_argument("--workload", choices=["chain", "typical", "mlp"], default="chain",
-                    help="chain (default, the headline), or run only the typical d=2^24 vector or the "
-                         "batched MLP rows (for profiling one workload)")
+    ap.add_argument("--workload", choices=["chain", "typical", "mlp", "shuffled", "backward", "precision"],
+                    default="chain",
+                    help="chain (default, the headline), or run one workload only (for profiling): the typical "
+                         "d=2^24 vector, the batched MLP rows, the shuffled chain, the 1024x8192 backward "
+                         "rows, the d=2^26 precision vector")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="first run one plain device copy of BYTES bytes (HBM counter calibration)")
     return ap.parse_args()
@@ -142,21 +157,6 @@ def copy_bandwidth(nbytes=1 << 28, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def step_fractions(n_el, ms, copy_gbs, extra_bpe=None):
-    """Whole-step HBM fractions: algorithmic bytes (forward with saved state 12.125 B/el +
-    backward 12.125 B/el) over the step time, against the HBM peak and the measured copy rate;
-    extra_bpe adds a model with more bytes per element (the out-of-core sort round trip)."""
-    res = {}
-    models = {"algorithmic_24.25B": 24.25}
-    if extra_bpe:
-        models["with_sort_roundtrip_%gB" % (24.25 + extra_bpe)] = 24.25 + extra_bpe
-    for k, bpe in models.items():
-        gbs = bpe * n_el / (ms * 1e-3) / 1e9
-        res[k] = dict(GBps=round(gbs, 1), frac_peak=round(gbs / HBM_PEAK_GBS, 4),
-                      frac_copy=round(gbs / copy_gbs, 4))
-    return res
-
-
 def trace_kernels(fn, reps):
     import torch
     import paper_2311_03096_amd as wsr
@@ -178,27 +178,56 @@ def measured_traffic(workload, kernel):
     return read_traffic(os.path.join(ROOT, "profiles", "traffic_%s.md" % workload), workload, kernel)
 
 
-def roofline(trace, n_el, steps, workload):
-    """Dominant kernel by total time; achieved = algorithmic bytes per launch / mean duration."""
+def roofline(trace, n_el, steps, workload, sorts_per_step=1):
+    """Dominant kernel by total time; achieved = algorithmic bytes per launch / mean duration.
+    A radix scatter launch is charged its share of the sort's one round trip
+    (SORT_ROUND_TRIP_B * n_el * sorts / scatter launches); ``achieved_per_pass`` gives the rate of
+    that pass moving key + index once (16 B/el)."""
     name, (cnt, tot) = max(trace.items(), key=lambda kv: kv[1][1])
     avg_ms = tot / cnt
-    per_launch_el = n_el * steps / cnt if name in ("radix_scatter", "radix_hist") else n_el
-    bpe = KERNEL_BYTES_PER_EL.get(name)
-    if bpe is None:
+    if name == "radix_scatter":
+        bpl = SORT_ROUND_TRIP_B * n_el * sorts_per_step * steps / cnt
+    elif name in KERNEL_BYTES_PER_EL:
+        bpl = KERNEL_BYTES_PER_EL[name] * n_el
+    else:
         return dict(kernel=name, launches_per_step=cnt / steps, avg_ms=avg_ms, bound="hbm", achieved=None,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=None, traffic=None)
-    if name in ("radix_scatter", "radix_hist"):
-        per_launch_el = n_el  # every pass covers the whole segment
-    ach = bpe * per_launch_el / (avg_ms * 1e-3) / 1e9
+    ach = bpl / (avg_ms * 1e-3) / 1e9
     tr = measured_traffic(workload, name)
     res = dict(kernel=name, launches_per_step=cnt / steps, avg_ms=round(avg_ms, 5),
-               bytes_per_el=bpe, algorithmic_bytes_per_launch=bpe * per_launch_el, bound="hbm",
+               bytes_per_el=round(bpl / n_el, 4), algorithmic_bytes_per_launch=bpl, bound="hbm",
                achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4),
                traffic=None if tr is None else round(tr))
+    if name == "radix_scatter":
+        per_pass = SORT_ROUND_TRIP_B * n_el / (avg_ms * 1e-3) / 1e9
+        res["achieved_per_pass"] = round(per_pass, 1)
+        res["frac_per_pass"] = round(per_pass / HBM_PEAK_GBS, 4)
     if tr is not None:
         res["traffic_unit"] = "HBM bytes per launch"
-        res["traffic_over_algorithmic"] = round(tr / (bpe * per_launch_el), 3)
+        res["traffic_over_algorithmic"] = round(tr / bpl, 3) if bpl else None
     return res
+
+
+def median_ms(fn, reps=MED_REPS, warmup=MED_WARMUP):
+    """Median over ``reps`` single-call timings (HIP events on the current stream, which the
+    library's calls use) after ``warmup`` untimed calls."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def step_fraction(n_el, ms, bpe, copy_gbs):
+    gbs = bpe * n_el / (ms * 1e-3) / 1e9
+    return dict(bytes_per_el=bpe, GBps=round(gbs, 1), frac_peak=round(gbs / HBM_PEAK_GBS, 4),
+                frac_copy=round(gbs / copy_gbs, 4) if copy_gbs else None)
 
 
 def _cpu_model():
@@ -251,40 +280,119 @@ def cpu_baseline(case, step=None):
     res = dict(value=float(reps * w.shape[0] / dt), unit="elements/s", cores=1, kind="oracle",
                sample="%d full fwd+vjp steps of %s (%d elements each), FP64 sort + stack PAV, 1 thread, "
                "%.1f s" % (reps, case["name"], w.shape[0], dt), host_cpu=_cpu_model())
-    # the row-batched workload on every host core (rows split across POSIX threads), one step
-    from paper_2311_03096_amd import workloads
-    rows = workloads.mlp_rows()
-    nthr = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    gr = np.random.default_rng(123).standard_normal(rows["w"].shape[0]).astype(np.float32).astype(np.float64)
-    t1 = time.perf_counter()
-    ur, pr, sr = oracle.prox_segments(rows["w"], rows["lam"], rows["offsets"], n_threads=nthr)
-    oracle.vjp(gr, pr, sr, rows["offsets"])
-    dt1 = time.perf_counter() - t1
-    res["mlp_rows_all_cores"] = dict(value=float(rows["w"].shape[0] / dt1), unit="elements/s", cores=nthr,
-                                     sample="one fwd+vjp step of the 8202 MLP rows, %.2f s" % dt1)
-    acc = None
-    if step is not None:
-        out = step.out.cpu().numpy().astype(np.float64)
-        gw = step.gw.cpu().numpy().astype(np.float64)
-        words = step.mask.cpu().numpy().view(np.uint8)
-        start_g = np.unpackbits(words, bitorder="little")[:w.shape[0]]
-        scale = float(np.abs(w).max())
-        err = np.abs(out - u)
-        gerr = np.abs(gw - vg)
-        acc = dict(workload=case["name"], max_abs_err=float(err.max()), max_rel_err=float(err.max() / scale),
-                   grad_max_abs_err=float(gerr.max()),
-                   grad_max_rel_err=float(gerr.max() / max(float(np.abs(vg).max()), 1e-30)),
-                   clusters_gpu=int(start_g.sum()), clusters_oracle=int(start.sum()),
-                   permutation_equal=bool(np.array_equal(step.perm.cpu().numpy(), perm)),
-                   cluster_starts_differing=int((start_g != start).sum()),
-                   sum_w=float(w.astype(np.float64).sum()), sum_out_gpu=float(out.sum()))
+    acc = accuracy(case, step, u, perm, start, vg) if step is not None else None
     return res, acc
 
 
-def batched_vs_per_row(steps, warmup, per_row=True, rounds=None):
+def accuracy(case, step, u, perm, start, vg=None):
+    """Errors of a GPU step's results against the FP64 oracle's (u, perm, start, and the VJP vg):
+    max abs and normwise relative error, the max elementwise relative error over |u| >= 1e-3 max|w|,
+    |sum u - sum w|, cluster counts, permutation equality, and the backward's errors."""
+    w = case["w"]
+    out = step.out.cpu().numpy().astype(np.float64)
+    words = step.mask.cpu().numpy().view(np.uint8)
+    start_g = np.unpackbits(words, bitorder="little")[:w.shape[0]]
+    scale = float(np.abs(w).max())
+    err = np.abs(out - u)
+    big = np.abs(u) >= 1e-3 * scale
+    acc = dict(workload=case["name"], max_abs_err=float(err.max()), max_rel_err=float(err.max() / scale),
+               max_elementwise_rel_err_large=float((err[big] / np.abs(u[big])).max()) if big.any() else 0.0,
+               abs_sum_diff=float(abs(out.sum() - w.astype(np.float64).sum())),
+               clusters_gpu=int(start_g.sum()), clusters_oracle=int(start.sum()),
+               permutation_equal=bool(np.array_equal(step.perm.cpu().numpy(), perm)),
+               cluster_starts_differing=int((start_g != start).sum()))
+    if vg is not None:
+        gw = step.gw.cpu().numpy().astype(np.float64)
+        gerr = np.abs(gw - vg)
+        acc.update(grad_max_abs_err=float(gerr.max()),
+                   grad_max_rel_err=float(gerr.max() / max(float(np.abs(vg).max()), 1e-30)))
+    return acc
+
+
+def config_line(name, case, copy_gbs, kind="fwd_bwd", batched=False, long_sort=False, oracle_check=False,
+                cpu_threads=0):
+    """One row of the per-workload table: the median step time (>= 50 reps after >= 10 warm-ups),
+    elements/s, the whole step's fraction of HBM peak under the algorithmic bytes (24.25 B/el for
+    forward with saved state + backward, 12.125 B/el for the backward alone; plus the sort's
+    16 B/el round trip for a segment too long for on-chip memory), and the dominant kernel with its
+    own fraction.  ``oracle_check``: errors against the FP64 oracle; ``cpu_threads`` > 0: the
+    oracle's forward + VJP timed on that many host threads (median of >= 5 runs)."""
+    import torch
+    import oracle
+    step = Step(case, batched=batched)
+    n = step.n
+    if kind == "bwd":  # the saved state of one forward, then the backward alone
+        if batched:
+            step.wsr.wsr_prox_forward_batched(step.plan, step.w, step.out, None, step.lam, step.perm, step.mask,
+                                              step.ws)
+            fn = lambda: step.wsr.wsr_prox_backward_batched(step.plan, step.g, step.gw, step.perm, step.mask,
+                                                            step.ws)
+        else:
+            step.wsr.wsr_prox_forward(step.w, step.out, step.offsets, step.lam, step.perm, step.mask, step.ws)
+            fn = lambda: step.wsr.wsr_prox_backward(step.g, step.gw, step.offsets, step.perm, step.mask, step.ws)
+        bpe = 12.125
+    else:
+        fn = step
+        bpe = 24.25
+    ms = median_ms(fn)
+    tr = trace_kernels(fn, 3)
+    roof = roofline(tr, n, 3, name, sorts_per_step=1 if (long_sort and kind != "bwd") else 0)
+    res = dict(workload=case["name"], elements=n, segments=int(case["offsets"].shape[0] - 1), lam=case["lam"],
+               step=("backward" if kind == "bwd" else "forward with saved state + backward"),
+               ms_median=round(ms, 5), elements_per_s=n / (ms * 1e-3),
+               step_fraction=step_fraction(n, ms, bpe, copy_gbs), dominant_kernel=roof,
+               kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()})
+    if long_sort and kind != "bwd":
+        res["step_fraction_with_sort_round_trip"] = step_fraction(n, ms, bpe + SORT_ROUND_TRIP_B, copy_gbs)
+    if kind == "bwd":
+        res["ms_median_forward_and_backward"] = round(median_ms(step), 5)
+    if oracle_check or cpu_threads:
+        torch.cuda.synchronize()
+        w, off, lam = case["w"], case["offsets"], case["lam"]
+        g = step.g.cpu().numpy().astype(np.float64)
+        nthr = cpu_threads or 1
+        times = []
+        for _ in range(5 if cpu_threads else 1):
+            t0 = time.perf_counter()
+            u, perm, start = oracle.prox_segments(w, lam, off, n_threads=nthr)
+            vg = oracle.vjp(g, perm, start, off)
+            times.append(time.perf_counter() - t0)
+        if cpu_threads:
+            t = float(np.median(times))
+            res["cpu_oracle"] = dict(value=n / t, unit="elements/s", cores=nthr, kind="oracle",
+                                     sample="median of 5 fwd+vjp runs over the whole workload, %.3f s each" % t)
+        if kind != "bwd":
+            step()  # results of one whole step for the accuracy check
+        torch.cuda.synchronize()
+        res["accuracy"] = accuracy(case, step, u, perm, start, vg)
+    return res
+
+
+def fp32_prefix_control(case):
+    """Negative control for the precision workload: cluster values formed from a plain sequential
+    FP32 prefix sum of the sorted weights (the clusters are the FP32 tie groups here, so each
+    value is S[b] - S[a] over its group, divided by its size, plus the group's mean velocity),
+    against the same formula in FP64 -- the error the FP64 sums of the kernels avoid."""
+    w = np.sort(case["w"])
+    d = w.shape[0]
+    lam = float(case["lam"])
+    edges = np.concatenate([[0], np.nonzero(np.diff(w))[0] + 1, [d]])
+    a, b = edges[:-1], edges[1:]
+    S32 = np.concatenate([[np.float32(0)], np.cumsum(w, dtype=np.float32)])
+    S64 = np.concatenate([[0.0], np.cumsum(w.astype(np.float64))])
+    v = lam * (d - a - b) / (d - 1.0)  # mean velocity of ranks [a, b)
+    u32 = (S32[b].astype(np.float64) - S32[a].astype(np.float64)) / (b - a) + v
+    u64 = (S64[b] - S64[a]) / (b - a) + v
+    return dict(what="cluster values of the FP32 tie groups from a sequential FP32 prefix sum vs FP64",
+                groups=int(a.shape[0]), max_abs_err=float(np.abs(u32 - u64).max()),
+                max_rel_err=float(np.abs(u32 - u64).max() / np.abs(w).max()))
+
+
+def batched_vs_per_row(steps, warmup, per_row=True, rounds=None, cpu_threads=0):
     """MLP rows (8202 segments, 29.4M weights): fwd+bwd, graph-captured batched launches (plan
     autotuned once on these weights, outside the timed region) vs per-row launches of the plain
-    entry points on the same stream."""
+    entry points on the same stream.  Medians of >= 50 reps (10 for the per-row launches, which
+    take ~0.2 s a step) after >= 10 warm-ups (2 per-row)."""
     import torch
     from paper_2311_03096_amd import workloads
     case = workloads.mlp_rows()
@@ -299,21 +407,41 @@ def batched_vs_per_row(steps, warmup, per_row=True, rounds=None):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         b()
-    ms_graph, _ = time_steps(graph.replay, steps, warmup)
-    ms_batched, _ = time_steps(b, steps, warmup)
-    ms_rows = time_steps(p, max(2, steps // 4), 1)[0] if per_row else float("nan")
+    ms_graph = median_ms(graph.replay, max(MED_REPS, steps), max(MED_WARMUP, warmup))
+    ms_batched = median_ms(b, max(MED_REPS, steps), max(MED_WARMUP, warmup))
+    ms_rows = median_ms(p, 10, 2) if per_row else float("nan")
     tr = trace_kernels(b, 3)
     roof = roofline({k: v for k, v in tr.items() if k.startswith("prox_fwd")}, n, 3, "mlp_rows")
     copy_gbs = copy_bandwidth()
     roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4) if roof.get("achieved") else None
-    return dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
-                fwd_kernel_alu_roofline=alu_roofline(roof.get("kernel"), roof.get("avg_ms"), "mlp_rows"),
-                elements=n, ms_per_step_graph=round(ms_graph, 4), ms_per_step_batched=round(ms_batched, 4),
-                ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
-                speedup_graph_vs_per_row=round(ms_rows / ms_graph, 2), fwd_kernel_roofline=roof,
-                copy_GBps=round(copy_gbs, 1), step_fractions_graph=step_fractions(n, ms_graph, copy_gbs),
-                kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
-                autotuned_merge_rounds=b.rounds)
+    bwd = {k: v for k, v in tr.items() if k.startswith("prox_bwd")}
+    roof_b = roofline(bwd, n, 3, "mlp_rows") if bwd else None
+    res = dict(workload="mlp_rows 4096x3072 + 4096x4096 + 10x4096, per-row segments, lam=1e-3",
+               fwd_kernel_alu_roofline=alu_roofline(roof.get("kernel"), roof.get("avg_ms"), "mlp_rows"),
+               elements=n, ms_per_step_graph=round(ms_graph, 4), ms_per_step_batched=round(ms_batched, 4),
+               ms_per_step_per_row=round(ms_rows, 4), elements_per_s_graph=n / (ms_graph * 1e-3),
+               speedup_graph_vs_per_row=round(ms_rows / ms_graph, 2), fwd_kernel_roofline=roof,
+               bwd_kernel_roofline=roof_b, copy_GBps=round(copy_gbs, 1),
+               step_fraction_graph=step_fraction(n, ms_graph, 24.25, copy_gbs),
+               kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
+               autotuned_merge_rounds=b.rounds, timing="median of >= 50 reps after >= 10 warm-ups")
+    if cpu_threads:
+        import oracle
+        g = b.g.cpu().numpy().astype(np.float64)
+        times = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            u, perm, start = oracle.prox_segments(case["w"], case["lam"], case["offsets"], n_threads=cpu_threads)
+            vg = oracle.vjp(g, perm, start, case["offsets"])
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
+        res["cpu_oracle"] = dict(value=n / t, unit="elements/s", cores=cpu_threads, kind="oracle",
+                                 sample="median of 5 fwd+vjp runs over the 8202 rows, rows split across "
+                                        "threads, %.3f s each" % t)
+        graph.replay()
+        torch.cuda.synchronize()
+        res["accuracy"] = accuracy(case, b, u, perm, start, vg)
+    return res
 
 
 def l1_figures(steps, warmup):
@@ -346,7 +474,7 @@ def l1_figures(steps, warmup):
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
                 fn()
-            ms[k] = time_steps(g.replay, steps, warmup)[0]
+            ms[k] = median_ms(g.replay)
         n = w.numel()
         res["mlp_rows"] = dict(workload="mlp_rows, lam=1e-3, beta=0.01, rho=0.98, batched + hipGraph, no saved state",
                                ms_l1=round(ms["l1"], 4), ms_plain_forward=round(ms["plain"], 4),
@@ -363,7 +491,7 @@ def l1_figures(steps, warmup):
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             fn()
-        ms_step = time_steps(g.replay, steps, warmup)[0]
+        ms_step = median_ms(g.replay)
         res["mlp_rows_step"] = dict(
             workload="mlp_rows: w <- Prox(w - 0.1 grad), alpha=1e-2, beta=0.1, rho=0.98, batched + hipGraph",
             ms=round(ms_step, 4), elements_per_s=n / (ms_step * 1e-3),
@@ -377,10 +505,8 @@ def l1_figures(steps, warmup):
     out = torch.empty_like(w)
     nb = wsr.wsr_workspace_bytes(off)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    ms_l1 = time_steps(lambda: wsr.wsr_prox_l1_forward(w, out, off, case["lam"], 0.5, 0.98, ws),
-                       max(3, steps // 2), 2)[0]
-    ms_pl = time_steps(lambda: wsr.wsr_prox_forward(w, out, off, case["lam"], None, None, ws),
-                       max(3, steps // 2), 2)[0]
+    ms_l1 = median_ms(lambda: wsr.wsr_prox_l1_forward(w, out, off, case["lam"], 0.5, 0.98, ws))
+    ms_pl = median_ms(lambda: wsr.wsr_prox_forward(w, out, off, case["lam"], None, None, ws))
     res["typical_d2p24"] = dict(workload="one N(0,1) vector d=2^24, lam=0.1, beta=0.5, rho=0.98",
                                 ms_l1=round(ms_l1, 4), ms_plain_forward=round(ms_pl, 4),
                                 elements_per_s_l1=d / (ms_l1 * 1e-3))
@@ -401,7 +527,7 @@ def stats_figures(steps, warmup):
     try:
         nb = wsr.wsr_plan_workspace_bytes(plan)
         ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
-        ms = time_steps(lambda: wsr.wsr_segment_stats_batched(plan, w, st, ws), steps, warmup)[0]
+        ms = median_ms(lambda: wsr.wsr_segment_stats_batched(plan, w, st, ws))
     finally:
         wsr.wsr_plan_destroy(plan)
     res["mlp_rows"] = dict(workload="R(w) and counts of each of the 8202 MLP rows, batched", ms=round(ms, 4),
@@ -412,7 +538,7 @@ def stats_figures(steps, warmup):
     w = torch.from_numpy(case["w"]).cuda()
     st = torch.empty((1, 3), dtype=torch.int64, device="cuda")
     ws = torch.empty(wsr.wsr_workspace_bytes(off), dtype=torch.uint8, device="cuda")
-    ms = time_steps(lambda: wsr.wsr_segment_stats(w, off, st, ws), max(3, steps // 2), 2)[0]
+    ms = median_ms(lambda: wsr.wsr_segment_stats(w, off, st, ws))
     res["typical_d2p24"] = dict(workload="R(w) and counts of one N(0,1) vector d=2^24", ms=round(ms, 4),
                                 elements_per_s=d / (ms * 1e-3))
     return res
@@ -472,11 +598,41 @@ def merge_route_figures(steps, warmup):
                     wsr.wsr_plan_autotune(plan, w, out, None, case["lam"], ws)
                     row["autotuned_rounds"] = wsr.wsr_plan_merge_rounds(plan)
                 fn = lambda: wsr.wsr_prox_forward_batched(plan, w, out, None, case["lam"], None, None, ws)
-                row["ms_" + route] = round(time_steps(fn, max(3, steps // 2), 2)[0], 4)
+                reps = 5 if route == "end_collisions" and name == "mlp_rows" else MED_REPS  # ~0.1 s a call
+                row["ms_" + route] = round(median_ms(fn, reps, 2 if reps < MED_REPS else MED_WARMUP), 4)
             finally:
                 wsr.wsr_plan_destroy(plan)
         res[name] = row
     return res
+
+
+def nproc():
+    return len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def config_table(copy_gbs):
+    """The per-workload rows (single-GPU workloads of the benchmark configurations and the
+    variants that exercise the sort): median timings, fractions, dominant kernels, errors."""
+    from paper_2311_03096_amd import workloads
+    d = 1 << 24
+    rows = {}
+    rows["plain_d4096"] = config_line("plain_d4096", workloads.plain(4096, 0.1), copy_gbs, oracle_check=True,
+                                      cpu_threads=1)
+    log("plain d=4096", rows["plain_d4096"])
+    rows["chain_d2p24_shuffled"] = config_line("chain_shuffled_d2p24", workloads.chain(d, 0.7, shuffle=True),
+                                               copy_gbs, long_sort=True)
+    log("shuffled chain", rows["chain_d2p24_shuffled"])
+    rows["typical_d2p24"] = config_line("typical_d2p24", workloads.plain(d, 0.1, seed=1), copy_gbs, long_sort=True)
+    log("typical", rows["typical_d2p24"])
+    rows["backward_rows_1024x8192"] = config_line("backward_rows", workloads.backward_rows(1024, 8192, 0.05),
+                                                  copy_gbs, kind="bwd", batched=True, oracle_check=True,
+                                                  cpu_threads=nproc())
+    log("backward rows", rows["backward_rows_1024x8192"])
+    prec = workloads.precision(1 << 26, 1e-4)
+    rows["precision_d2p26"] = config_line("precision_d2p26", prec, copy_gbs, long_sort=True, oracle_check=True)
+    rows["precision_d2p26"]["fp32_prefix_sum_control"] = fp32_prefix_control(prec)
+    log("precision", rows["precision_d2p26"])
+    return rows
 
 
 def main():
@@ -506,6 +662,17 @@ def main():
         res = batched_vs_per_row(max(5, args.steps), args.warmup, per_row=not args.no_extra, rounds=rounds)
         print(json.dumps(res), flush=True)
         return
+    if args.workload in ("shuffled", "backward", "precision"):  # one workload's row (for profiling)
+        copy_gbs = copy_bandwidth()
+        if args.workload == "shuffled":
+            res = config_line("chain_shuffled_d2p24", workloads.chain(d, 0.7, shuffle=True), copy_gbs, long_sort=True)
+        elif args.workload == "backward":
+            res = config_line("backward_rows", workloads.backward_rows(1024, 8192, 0.05), copy_gbs, kind="bwd",
+                              batched=True)
+        else:
+            res = config_line("precision_d2p26", workloads.precision(1 << 26, 1e-4), copy_gbs, long_sort=True)
+        print(json.dumps(res), flush=True)
+        return
     case = workloads.chain(d, 0.7) if args.workload == "chain" else workloads.plain(d, 0.1, seed=1)
     log("workload", case["name"], "steps", args.steps, "warmup", args.warmup)
     step = Step(case)
@@ -517,17 +684,12 @@ def main():
     roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4) if roof.get("achieved") else None
     extra = dict(kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr.items()},
                  wall_ms_per_step=round(wall, 4), copy_GBps=round(copy_gbs, 1),
-                 step_fractions=step_fractions(d, ms, copy_gbs, extra_bpe=16.0))
+                 step_fraction=step_fraction(d, ms, 24.25, copy_gbs),
+                 step_fraction_with_sort_round_trip=step_fraction(d, ms, 24.25 + SORT_ROUND_TRIP_B, copy_gbs),
+                 ms_median=round(median_ms(step), 5))
     if not args.no_extra:
-        typ = workloads.plain(d, 0.1, seed=1)
-        st = Step(typ)
-        ms_t, _ = time_steps(st, max(3, args.steps // 2), 2)
-        tr_t = trace_kernels(st, 3)
-        extra["typical_d2p24"] = dict(workload="one N(0,1) vector d=2^24, lam=0.1", ms_per_step=round(ms_t, 4),
-                                      elements_per_s=d / (ms_t * 1e-3),
-                                      kernel_ms_per_step={k: round(v[1] / 3, 4) for k, v in tr_t.items()})
-        log("typical", ms_t)
-        extra["batched_mlp_rows"] = batched_vs_per_row(max(5, args.steps), args.warmup)
+        extra["configs"] = config_table(copy_gbs)
+        extra["batched_mlp_rows"] = batched_vs_per_row(max(5, args.steps), args.warmup, cpu_threads=nproc())
         log("batched", extra["batched_mlp_rows"])
         extra["prox_l1_rewinding"] = l1_figures(max(5, args.steps), args.warmup)
         log("l1", extra["prox_l1_rewinding"])
@@ -542,10 +704,11 @@ def main():
         log("merge routes", extra["merge_routes"])
         lay = workloads.mlp_layers()
         st = Step(lay, batched=True)
-        ms_l, _ = time_steps(st, max(3, args.steps // 2), 2)
+        ms_l = median_ms(st)
         extra["mlp_per_layer"] = dict(workload="the MLP's weights, one segment per layer (12.6M, 16.8M, 41K), "
-                                      "lam=1e-3, fwd+bwd, batched", ms_per_step=round(ms_l, 4),
-                                      elements_per_s=lay["w"].shape[0] / (ms_l * 1e-3))
+                                      "lam=1e-3, fwd+bwd, batched", ms_median=round(ms_l, 4),
+                                      elements_per_s=lay["w"].shape[0] / (ms_l * 1e-3),
+                                      step_fraction=step_fraction(lay["w"].shape[0], ms_l, 24.25, copy_gbs))
         log("per-layer", extra["mlp_per_layer"])
     res = dict(metric=METRIC, value=d / (ms * 1e-3), unit="elements/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms, 4), higher_is_better=True, scaling="weak",

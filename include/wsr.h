@@ -164,16 +164,30 @@ WSR_API int wsr_plan_destroy(wsr_plan* plan);
 /*
  * Autotuner: times the merge routes of every size class of the plan on the caller's weights
  * (the batched forward of that class alone, without saved state: a warm-up launch and three
- * timed ones per route; routes = a cap of 0 (hull merge only), 2, 6, 16 or 64
- * ImminentCollisions rounds before the hull merge; long segments: 0, 6 or 16, timed on the
- * longest one) and keeps the
- * fastest route of each class in the plan for every later batched call.  Synchronises the
- * stream; not for use under graph capture.
- *   w[N]      device weights of the plan's layout; out[N] device scratch (overwritten)
+ * timed ones per route) and keeps the fastest route of each class in the plan for every later
+ * batched call.  Routes of the short classes: a cap of 0 (hull merge only), 2, 6, 16 or 64
+ * ImminentCollisions rounds before the hull merge, and EndCollisions (Sec. 4.2) when a probe over
+ * the class's first segments finds it no slower than 1.5x the default route there; long
+ * segments: a cap of 0, 6 or 16, timed on the longest one.  Synchronises the stream; not for use
+ * under graph capture.
+ *   w[N]      device weights of the plan's layout; out[N] device scratch (overwritten), which must
+ *             not alias w (WSR_ERR_INVALID)
  *   d_lambda, lambda_scalar, ws, ws_bytes, stream   as in wsr_prox_forward_batched
  */
 WSR_API int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d_lambda,
                               float lambda_scalar, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Autotuner for the proximal-gradient step: as wsr_plan_autotune, but each candidate route is
+ * timed on the launches of wsr_prox_step_batched itself (gradient step fused into the load, the
+ * lambda and l1 options of the chosen form), so the routes are chosen for the input the step's
+ * collisions actually see, z = fmaf(-eta, grad, w), and its lambda (eta*alpha, or alpha in the
+ * variant).  Arguments as in wsr_prox_step_batched; the result goes to scratch[N], which must
+ * alias neither w nor grad (WSR_ERR_INVALID).  Synchronises the stream.
+ */
+WSR_API int wsr_plan_autotune_step(wsr_plan* plan, const float* w, const float* grad, float eta,
+                                   float* scratch, const float* d_alpha, float alpha_scalar, float beta,
+                                   float rho, int flags, void* ws, size_t ws_bytes, void* stream);
 
 /* The plan's route per size class (2048, 4096, 8192, long): the cap on collision rounds before
  * the hull merge (0 = hull merge only), or -1 = EndCollisions.  Writes 4 values. */
@@ -187,12 +201,13 @@ WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
 /*
  * Sticky status of a plan's batched calls (forward, l1 forward, step): bit WSR_STATUS_NONFINITE
  * is set on the device when any segment held a NaN or +-Inf input weight (that segment's
- * outputs are NaN, as documented above) and stays set until read with clear != 0.  Synchronises
- * the device, then copies the word to *flags (and clears it when clear != 0).  Not for use under
- * graph capture.
+ * outputs are NaN, as documented above) and stays set until read with clear != 0.  Enqueues the
+ * read (and the clear) on `stream` and synchronises that stream only: the word covers the calls
+ * ordered before it on that stream (calls on other streams must have completed or be ordered
+ * before it by events).  Writes the word to *flags.  Not for use under graph capture.
  */
 #define WSR_STATUS_NONFINITE 1u
-WSR_API int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear);
+WSR_API int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear, void* stream);
 
 /* A plan may be used by calls on any stream, but calls that overlap in time must not share a
  * workspace; wsr_plan_autotune and wsr_plan_set_merge_rounds change the plan and must not run

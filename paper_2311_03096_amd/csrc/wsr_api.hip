@@ -473,52 +473,157 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
   return last_error();
 }
 
-int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, float eta, float* out,
-                      const float* d_alpha, float alpha_scalar, float beta, float rho, int flags, void* ws,
-                      size_t ws_bytes, void* stream) {
-  (void)hipGetLastError();  // report only errors of this call
+// The step's form: lambda multiplier of the short-segment kernels and the l1 / rewinding options.
+struct StepForm {
+  float lam_mul;
+  L1Opt l1;
+};
+StepForm step_form(float eta, float beta, float rho, int flags) {
+  const bool variant = (flags & WSR_STEP_ETA_IN_DISPLACEMENT) != 0;
+  // standard: the prox of eta*(alpha R + beta l1): lambda = eta*alpha, beta' = eta*beta (FP32);
+  // variant: alpha and beta unscaled, eta on the rewinding line
+  return StepForm{variant ? 1.0f : eta, L1Opt{variant ? beta : eta * beta, rho, 1, variant ? eta : 1.0f}};
+}
+
+int step_args_ok(const wsr_plan* plan, const float* w, const float* grad, float eta, const float* out,
+                 const float* d_alpha, float alpha_scalar, float beta, float rho, int flags, const void* ws,
+                 size_t ws_bytes) {
   if (!plan || !w || !grad || !out) return WSR_ERR_INVALID;
   if (flags & ~WSR_STEP_ETA_IN_DISPLACEMENT) return WSR_ERR_INVALID;
   if (!std::isfinite(eta) || eta < 0.0f || !l1_args_ok(beta, rho)) return WSR_ERR_INVALID;
   if (!d_alpha && (!std::isfinite(alpha_scalar) || alpha_scalar < 0.0f)) return WSR_ERR_INVALID;
   const size_t need = big_bytes(plan->max_big);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
-  const bool variant = (flags & WSR_STEP_ETA_IN_DISPLACEMENT) != 0;
-  // standard: the prox of eta*(alpha R + beta l1): lambda = eta*alpha, beta' = eta*beta (FP32);
-  // variant: alpha and beta unscaled, eta on the rewinding line
-  const float lam_mul = variant ? 1.0f : eta;
-  L1Opt l1{variant ? beta : eta * beta, rho, 1, variant ? eta : 1.0f};
+  return WSR_OK;
+}
+
+// The fused launch of size class c over its first nblocks segments with merge route `route`.
+void step_small(const wsr_plan* plan, int c, int nblocks, int route, const float* w, const float* grad, float eta,
+                float* out, const float* d_alpha, float alpha_scalar, const StepForm& f, hipStream_t s) {
+  SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
+            f.l1.beta, f.l1.rho, f.l1.on, f.l1.kappa, grad, eta, f.lam_mul, route, plan->d_status};
+  small_fwd(c, nblocks, a, w, out, nullptr, nullptr, s);
+}
+
+// One long segment of the step: z = fmaf(-eta, grad, w) into out, then the device-wide path in place.
+int step_big(const wsr_plan* plan, int32_t seg, int rounds, const float* w, const float* grad, float eta, float* out,
+             const float* d_alpha, float alpha_scalar, const StepForm& f, void* ws, hipStream_t s) {
+  const int64_t start = plan->h_offsets[seg];
+  const int64_t d = plan->h_offsets[seg + 1] - start;
+  {
+    WSR_TRACE("grad_step", s);
+    const int64_t blocks = std::min<int64_t>(ceil_div(d, 256), 4 * (int64_t)cu_count());
+    hipLaunchKernelGGL(k_grad_step, dim3((unsigned)blocks), dim3(256), 0, s, out + start, w + start,
+                       grad + start, eta, d);
+  }
+  const float* lam_arr = d_alpha;
+  int lam_seg = seg;
+  const float lam_scalar = alpha_scalar * f.lam_mul;
+  if (d_alpha && f.lam_mul != 1.0f) {
+    BigWs b = big_layout(d, ws);
+    WSR_TRACE("scale_lambda", s);
+    hipLaunchKernelGGL(k_scale_lambda, dim3(1), dim3(64), 0, s, b.lamtmp, d_alpha, seg, alpha_scalar, f.lam_mul);
+    lam_arr = b.lamtmp;
+    lam_seg = 0;
+  }
+  return big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, f.l1, rounds,
+                     plan->d_status);
+}
+
+int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, float eta, float* out,
+                      const float* d_alpha, float alpha_scalar, float beta, float rho, int flags, void* ws,
+                      size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  int rc = step_args_ok(plan, w, grad, eta, out, d_alpha, alpha_scalar, beta, rho, flags, ws, ws_bytes);
+  if (rc) return rc;
+  const StepForm f = step_form(eta, beta, rho, flags);
   hipStream_t s = (hipStream_t)stream;
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
-    SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
-              l1.beta, l1.rho, l1.on, l1.kappa, grad, eta, lam_mul, plan->small_route(c), plan->d_status};
-    small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s);
+    step_small(plan, c, (int)plan->sched_cnt[c], plan->small_route(c), w, grad, eta, out, d_alpha, alpha_scalar, f,
+               s);
   }
   for (int32_t seg : plan->big_segs) {
-    const int64_t start = plan->h_offsets[seg];
-    const int64_t d = plan->h_offsets[seg + 1] - start;
-    {
-      WSR_TRACE("grad_step", s);
-      const int64_t blocks = std::min<int64_t>(ceil_div(d, 256), 4 * (int64_t)cu_count());
-      hipLaunchKernelGGL(k_grad_step, dim3((unsigned)blocks), dim3(256), 0, s, out + start, w + start,
-                         grad + start, eta, d);
-    }
-    const float* lam_arr = d_alpha;
-    int lam_seg = seg;
-    float lam_scalar = alpha_scalar * lam_mul;
-    if (d_alpha && !variant) {
-      BigWs b = big_layout(d, ws);
-      WSR_TRACE("scale_lambda", s);
-      hipLaunchKernelGGL(k_scale_lambda, dim3(1), dim3(64), 0, s, b.lamtmp, d_alpha, seg, alpha_scalar, lam_mul);
-      lam_arr = b.lamtmp;
-      lam_seg = 0;
-    }
-    const int rc = big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, l1,
-                               plan->rounds[kNumSmall], plan->d_status);
+    rc = step_big(plan, seg, plan->rounds[kNumSmall], w, grad, eta, out, d_alpha, alpha_scalar, f, ws, s);
     if (rc) return rc;
   }
   return last_error();
+}
+
+// Autotuner core: for every short size class, times the batched launch of the class alone under
+// each candidate route and keeps the fastest; EndCollisions is a candidate only when a probe over
+// the class's first segments (one workgroup per CU pair) shows it no slower than 1.5x the default
+// route there.  Long segments: the caps {0, kIcaRounds, 16}, timed on the longest one.
+//   small(c, nblocks, route): launches class c over its first nblocks segments
+//   big(seg, rounds): runs long segment seg, returns a status
+template <class SmallFn, class BigFn>
+int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return WSR_ERR_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return WSR_ERR_HIP;
+  }
+  constexpr int kReps = 3;
+  int rc = WSR_OK;
+  // a warm-up launch, then `reps` timed launches
+  auto time_it = [&](auto&& launch, int reps, float* ms) -> int {
+    launch();
+    if (hipEventRecord(e0, s) != hipSuccess) return WSR_ERR_HIP;
+    for (int r = 0; r < reps; ++r) launch();
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return WSR_ERR_HIP;
+    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return WSR_ERR_HIP;
+    return last_error();
+  };
+  for (int c = 0; c < kNumSmall && rc == WSR_OK; ++c) {
+    const int cnt = (int)plan->sched_cnt[c];
+    if (cnt == 0) continue;
+    std::vector<int> cand = {0, 2, kIcaRounds, 16, 64};  // 0: hull merge only
+    {
+      const int np = std::min(cnt, 2 * cu_count());
+      float t_def = 0.0f, t_end = 0.0f;
+      rc = time_it([&] { small(c, np, kIcaRounds); }, 1, &t_def);
+      if (rc) break;
+      rc = time_it([&] { small(c, np, kRouteEnd); }, 1, &t_end);
+      if (rc) break;
+      if (t_end <= 1.5f * t_def) cand.push_back(kRouteEnd);
+    }
+    float best = 0.0f;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      float ms = 0.0f;
+      rc = time_it([&] { small(c, cnt, cand[i]); }, kReps, &ms);
+      if (rc) break;
+      if (i == 0 || ms < best) {
+        best = ms;
+        plan->rounds[c] = cand[i] == kRouteEnd ? -1 : cand[i];
+      }
+    }
+  }
+  if (rc == WSR_OK && !plan->big_segs.empty()) {
+    int32_t seg = plan->big_segs[0];
+    for (int32_t q : plan->big_segs)
+      if (plan->h_offsets[q + 1] - plan->h_offsets[q] > plan->h_offsets[seg + 1] - plan->h_offsets[seg]) seg = q;
+    float best = 0.0f;
+    bool first = true;
+    for (int r : {0, kIcaRounds, 16}) {
+      float ms = 0.0f;
+      int lrc = WSR_OK;
+      rc = time_it([&] {
+        const int e = big(seg, r);
+        if (e) lrc = e;
+      }, kReps, &ms);
+      if (!rc) rc = lrc;
+      if (rc) break;
+      if (first || ms < best) {
+        best = ms;
+        first = false;
+        plan->rounds[kNumSmall] = r;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 }  // namespace
@@ -672,14 +777,20 @@ int wsr_plan_destroy(wsr_plan* plan) {
   return WSR_OK;
 }
 
-int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear) {
+int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear, void* stream) {
   if (!plan || !flags) return WSR_ERR_INVALID;
-  if (hipDeviceSynchronize() != hipSuccess) return WSR_ERR_HIP;
+  (void)hipGetLastError();  // report only errors of this call
+  hipStream_t s = (hipStream_t)stream;
   uint32_t v = 0;
-  if (hipMemcpy(&v, plan->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return WSR_ERR_HIP;
-  if (clear && hipMemset(plan->d_status, 0, sizeof(uint32_t)) != hipSuccess) return WSR_ERR_HIP;
+  if (hipMemcpyAsync(&v, plan->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return WSR_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return WSR_ERR_HIP;
+  if (clear) {
+    zero_words(plan->d_status, 1, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return WSR_ERR_HIP;
+  }
   *flags = v;
-  return WSR_OK;
+  return last_error();
 }
 
 int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
@@ -705,70 +816,44 @@ int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds) {
 int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d_lambda, float lambda_scalar,
                       void* ws, size_t ws_bytes, void* stream) {
   (void)hipGetLastError();  // report only errors of this call
-  if (!plan || !w || !out) return WSR_ERR_INVALID;
+  if (!plan || !w || !out || out == w) return WSR_ERR_INVALID;
   if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
   const size_t need = big_bytes(plan->max_big);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return WSR_ERR_HIP;
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return WSR_ERR_HIP;
-  }
-  constexpr int kCand[] = {0, 2, kIcaRounds, 16, 64};  // 0: hull merge only
-  constexpr int kReps = 3;
-  int rc = WSR_OK;
-  // one route at a time: a warm-up launch, then kReps timed launches of the class alone
-  auto time_route = [&](auto&& launch, float* ms) -> int {
-    launch();
-    if (hipEventRecord(e0, s) != hipSuccess) return WSR_ERR_HIP;
-    for (int r = 0; r < kReps; ++r) launch();
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return WSR_ERR_HIP;
-    if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return WSR_ERR_HIP;
-    return last_error();
-  };
-  for (int c = 0; c < kNumSmall && rc == WSR_OK; ++c) {
-    if (plan->sched_cnt[c] == 0) continue;
-    float best = 0.0f;
-    for (int r : kCand) {
-      SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};
-      a.merge_rounds = r;
-      float ms = 0.0f;
-      rc = time_route([&] { small_fwd(c, (int)plan->sched_cnt[c], a, w, out, nullptr, nullptr, s); }, &ms);
-      if (rc) break;
-      if (r == kCand[0] || ms < best) {
-        best = ms;
-        plan->rounds[c] = r;
-      }
-    }
-  }
-  if (rc == WSR_OK && !plan->big_segs.empty()) {
-    // long segments: timed on the longest one
-    int32_t seg = plan->big_segs[0];
-    for (int32_t q : plan->big_segs)
-      if (plan->h_offsets[q + 1] - plan->h_offsets[q] > plan->h_offsets[seg + 1] - plan->h_offsets[seg]) seg = q;
-    const int64_t start = plan->h_offsets[seg];
-    const int64_t d = plan->h_offsets[seg + 1] - start;
-    float best = 0.0f;
-    for (int r : {0, kIcaRounds, 16}) {
-      float ms = 0.0f;
-      int lrc = WSR_OK;
-      rc = time_route([&] {
-        const int e = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, nullptr, nullptr, ws, s, L1Opt{}, r);
-        if (e) lrc = e;
-      }, &ms);
-      if (!rc) rc = lrc;
-      if (rc) break;
-      if (r == 0 || ms < best) {
-        best = ms;
-        plan->rounds[kNumSmall] = r;
-      }
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  return rc;
+  return autotune_impl(
+      plan,
+      [&](int c, int nblocks, int route) {
+        SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};
+        a.merge_rounds = route;
+        small_fwd(c, nblocks, a, w, out, nullptr, nullptr, s);
+      },
+      [&](int32_t seg, int rounds) {
+        const int64_t start = plan->h_offsets[seg];
+        const int64_t d = plan->h_offsets[seg + 1] - start;
+        return big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, nullptr, nullptr, ws, s, L1Opt{}, rounds);
+      },
+      s);
+}
+
+int wsr_plan_autotune_step(wsr_plan* plan, const float* w, const float* grad, float eta, float* scratch,
+                           const float* d_alpha, float alpha_scalar, float beta, float rho, int flags, void* ws,
+                           size_t ws_bytes, void* stream) {
+  (void)hipGetLastError();  // report only errors of this call
+  int rc = step_args_ok(plan, w, grad, eta, scratch, d_alpha, alpha_scalar, beta, rho, flags, ws, ws_bytes);
+  if (rc) return rc;
+  if (scratch == w || scratch == grad) return WSR_ERR_INVALID;
+  const StepForm f = step_form(eta, beta, rho, flags);
+  hipStream_t s = (hipStream_t)stream;
+  return autotune_impl(
+      plan,
+      [&](int c, int nblocks, int route) {
+        step_small(plan, c, nblocks, route, w, grad, eta, scratch, d_alpha, alpha_scalar, f, s);
+      },
+      [&](int32_t seg, int rounds) {
+        return step_big(plan, seg, rounds, w, grad, eta, scratch, d_alpha, alpha_scalar, f, ws, s);
+      },
+      s);
 }
 
 int wsr_prox_forward_batched(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,

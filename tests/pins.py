@@ -19,6 +19,8 @@ shares nothing with the oracle's sort + pool-adjacent-violators code:
                            (Sec. 4.2 proposition rightmost_collision; Alg. end_collisions).
 * ``kkt_certificate``   -- optimality check w - u in l*dR(u) (App. A.1 eq. prox_opt with the
                            subdifferential of Sec. 2 eq. subdiff_R, written as majorisation).
+* ``kkt_certificate_segments`` -- the same certificate vectorised over the segments of a flat
+                           buffer (GPU output at full size), in the GPU's own rank order.
 * ``neighbour_collides`` -- the if-and-only-if condition for neighbours i, i+1 to collide
                            (App. C corollary "Neighbour collision").
 """
@@ -228,3 +230,95 @@ def neighbour_collides(y, i):
     left = np.cumsum(y[:i + 1][::-1]) / np.arange(1, i + 2)
     right = np.cumsum(y[i + 1:]) / np.arange(1, y.shape[0] - i)
     return left.max() >= right.min()
+
+
+def kkt_certificate_segments(w, offsets, u, lam, tol_rel=1e-6, perm=None, start=None):
+    """Vectorised form of ``kkt_certificate`` over every segment of a flat buffer, usable on
+    GPU output at full size (App. A.1 eq. prox_opt with Sec. 2 eq. subdiff_R).
+
+    Per segment s with d >= 2 and lam_s > 0, in the rank order (``perm``: segment-local indices
+    in rank order, with ``start`` marking the first rank of every group; without them the order
+    of (u, w) and the maximal runs of equal u), with v_k = lam (d-1-2k)/(d-1) and y = x + v:
+      order     x non-decreasing along the ranks;
+      constant  u equal inside a group;
+      increase  group values non-decreasing along the ranks, up to tol (strictly increasing in
+                exact arithmetic; a decrease below tol is a near-tie split);
+      mean      group value = mean of y over the group, within tol;
+      prefix    every proper prefix of a group has mean y >= group value - tol (majorisation:
+                (w - u)/lam restricted to the group lies in the permutahedron of its
+                hyperplane coefficients).
+    Identity segments (d = 1 or lam = 0) must return w unchanged; segments holding a non-finite
+    weight are skipped.  tol = tol_rel * max |w| of the segment.  Returns a dict of the worst
+    slack per condition and ``ok``."""
+    w = np.asarray(w, np.float32).astype(np.float64)
+    u = np.asarray(u, np.float64)
+    offsets = np.asarray(offsets, np.int64)
+    n = w.shape[0]
+    lens = np.diff(offsets)
+    nseg = lens.shape[0]
+    lam_s = np.asarray(lam, np.float64).reshape(-1)
+    if lam_s.shape[0] != nseg:
+        lam_s = np.full(nseg, float(lam_s[0]))
+    res = dict(ok=True, order=0.0, constant=0, increase=0.0, mean=0.0, prefix=0.0, identity=0.0, groups=0)
+    if n == 0:
+        return res
+    seg_of = np.repeat(np.arange(nseg), lens)
+    seg_lo = np.repeat(offsets[:-1], lens)
+    nz = lens > 0
+    scale = np.ones(nseg)
+    finite_seg = np.ones(nseg, bool)
+    scale[nz] = np.maximum.reduceat(np.abs(w), offsets[:-1][nz])
+    finite_seg[nz] = np.logical_and.reduceat(np.isfinite(w), offsets[:-1][nz])
+    scale[~np.isfinite(scale) | (scale == 0)] = 1.0
+    tol = tol_rel * scale
+    ident_seg = (lens <= 1) | ~(lam_s > 0)
+    ident = (ident_seg & finite_seg)[seg_of]
+    if ident.any():
+        res["identity"] = float(np.abs(u[ident] - w[ident]).max())
+    if perm is not None:
+        order = seg_lo + np.asarray(perm, np.int64)
+        starts = np.asarray(start).astype(bool).copy()
+    else:
+        order = np.lexsort((w, u, seg_of))
+        uo = u[order]
+        starts = np.ones(n, bool)
+        starts[1:] = uo[1:] != uo[:-1]
+    first = np.zeros(n, bool)
+    first[offsets[:-1][nz]] = True
+    starts |= first
+    act = ((~ident_seg) & finite_seg)[seg_of]  # per rank position (segments are contiguous)
+    x = w[order]
+    ur = u[order]
+    k = (np.arange(n) - seg_lo).astype(np.float64)
+    d = lens[seg_of].astype(np.float64)
+    lam_r = lam_s[seg_of]
+    v = np.where(act, lam_r * (d - 1.0 - 2.0 * k) / np.maximum(d - 1.0, 1.0), 0.0)
+    tol_r = tol[seg_of]
+    inner = act[1:] & ~first[1:]
+    dx = np.diff(x)
+    if inner.any():
+        res["order"] = float(-np.min(np.where(inner, dx, 0.0)))
+        same = inner & ~starts[1:]
+        res["constant"] = int(np.count_nonzero(same & (ur[1:] != ur[:-1])))
+        jump = inner & starts[1:]
+        res["increase"] = float(np.max(np.where(jump, (ur[:-1] - ur[1:]) / tol_r[1:], -np.inf)))
+    gs = np.nonzero(starts)[0]
+    glen = np.diff(np.concatenate([gs, [n]]))
+    gact = act[gs]
+    res["groups"] = int(np.count_nonzero(gact))
+    c = np.where(act, x + v - ur, 0.0)  # y - u: each group sums to ~0, so the running sum stays small
+    cs = np.cumsum(c)
+    base = np.concatenate([[0.0], cs])[gs]  # running sum before each group
+    gsum = np.concatenate([cs[gs[1:] - 1], [cs[-1]]]) - base
+    if gact.any():
+        res["mean"] = float(np.max(np.abs(gsum / glen)[gact] / tol_r[gs][gact]))
+    pref = cs - np.repeat(base, glen)
+    plen = (np.arange(n) - np.repeat(gs, glen) + 1).astype(np.float64)
+    last = np.zeros(n, bool)
+    last[np.concatenate([gs[1:] - 1, [n - 1]])] = True
+    proper = act & ~last
+    if proper.any():
+        res["prefix"] = float(np.max(np.where(proper, -(pref / plen) / tol_r, -np.inf)))
+    res["ok"] = bool(res["order"] <= 0.0 and res["constant"] == 0 and res["increase"] <= 1.0
+                     and res["mean"] <= 1.0 and res["prefix"] <= 1.0 and res["identity"] == 0.0)
+    return res

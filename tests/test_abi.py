@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 21
+    assert len(declared) == 22
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -164,7 +164,10 @@ def test_plan_argument_errors():
     assert lib.wsr_plan_autotune(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_set_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
-    assert lib.wsr_read_status(None, None, 0) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_read_status(None, None, 0, None) == wsr.WSR_ERR_INVALID
+    f = ctypes.c_float
+    assert lib.wsr_plan_autotune_step(None, FAKE, FAKE, f(0.1), ctypes.c_void_p(512), None, f(0.1), f(0.0), f(0.0), 0,
+                                      None, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_destroy(None) == wsr.WSR_ERR_INVALID
     n = ctypes.c_size_t()
     assert lib.wsr_plan_workspace_bytes(None, ctypes.byref(n)) == wsr.WSR_ERR_INVALID
@@ -221,3 +224,89 @@ def test_workloads_shapes():
     assert np.all(np.diff(c["w"]) >= 0) and c["lam"] == np.float32(0.7)
     b = workloads.backward_rows(rows=4, d=16)
     assert b["g"].shape == (64,)
+
+
+# ----------------------------------------------------------------------------- binding checks
+# The ctypes binding rejects every buffer the kernels could read or write out of bounds (wrong
+# dtype, wrong length for the segment layout, non-contiguous, not on the GPU) before any call
+# into the library.  These run on CPU tensors: each mismatch must be named before the device check.
+
+def _t(n, dtype=None):
+    import torch
+    return torch.zeros(n, dtype=dtype or torch.float32)
+
+
+def test_binding_rejects_bad_buffers_plain():
+    import torch
+    off = np.array([0, 100, 300], np.int64)
+    cases = [
+        (dict(w=_t(300, torch.float64)), TypeError, "dtype"),
+        (dict(w=_t(299)), ValueError, "elements"),
+        (dict(out=_t(301)), ValueError, "elements"),
+        (dict(w=_t(600)[::2]), ValueError, "contiguous"),
+        (dict(saved_perm=_t(300, torch.int32)), ValueError, "both"),
+        (dict(saved_perm=_t(300, torch.int64), saved_mask=_t(10, torch.int32)), TypeError, "dtype"),
+        (dict(saved_perm=_t(299, torch.int32), saved_mask=_t(10, torch.int32)), ValueError, "elements"),
+        (dict(saved_perm=_t(300, torch.int32), saved_mask=_t(9, torch.int32)), ValueError, "elements"),
+        (dict(ws=_t(16, torch.float32)), TypeError, "dtype"),
+        (dict(), ValueError, "GPU"),  # right sizes, but host memory
+    ]
+    for over, exc, word in cases:
+        args = dict(w=_t(300), out=_t(300), saved_perm=None, saved_mask=None, ws=None)
+        args.update(over)
+        with pytest.raises(exc, match=word):
+            _lib.wsr_prox_forward(args["w"], args["out"], off, 0.1, args["saved_perm"], args["saved_mask"],
+                                  args["ws"])
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_backward(_t(300), _t(300), off, _t(300, torch.int32), _t(11, torch.int32))
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_l1_forward(_t(300), _t(30), off, 0.1, 0.1, 0.5)
+    with pytest.raises(ValueError, match="bytes"):
+        _lib.wsr_segment_stats(_t(300), off, _t(5, torch.int64))  # needs 2 records of 24 bytes
+
+
+def test_binding_rejects_bad_buffers_batched():
+    import torch
+    plan = _lib.Plan(ctypes.c_void_p(256), np.array([0, 100, 300], np.int64))  # never dereferenced
+    assert plan.n == 300 and plan.n_seg == 2
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_forward_batched(plan, _t(300), _t(200), None, 0.1)
+    with pytest.raises(ValueError, match="elements"):  # one lambda per segment
+        _lib.wsr_prox_forward_batched(plan, _t(300), _t(300), _t(3), 0.1)
+    with pytest.raises(TypeError, match="dtype"):
+        _lib.wsr_prox_forward_batched(plan, _t(300), _t(300), _t(2, torch.float64), 0.1)
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_backward_batched(plan, _t(300), _t(300), _t(299, torch.int32), _t(10, torch.int32))
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_step_batched(plan, _t(300), _t(301), 0.1, _t(300))
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_step_batched(plan, _t(300), _t(300), 0.1, _t(300), alpha=_t(1))
+    with pytest.raises(ValueError, match="elements"):
+        _lib.wsr_prox_l1_forward_batched(plan, _t(3), _t(300))
+    with pytest.raises(ValueError, match="bytes"):
+        _lib.wsr_segment_stats_batched(plan, _t(300), _t(47, torch.uint8))
+    w = _t(300)
+    with pytest.raises(ValueError, match="alias"):
+        _lib.wsr_plan_autotune(plan, w, w, None, 0.1)
+    with pytest.raises(ValueError, match="alias"):
+        _lib.wsr_plan_autotune_step(plan, w, _t(300), 0.1, w)
+    with pytest.raises(TypeError, match="Plan"):
+        _lib.wsr_prox_forward_batched(ctypes.c_void_p(256), _t(300), _t(300), None, 0.1)
+
+
+def test_tuning_key_and_cache(tmp_path):
+    from paper_2311_03096_amd.ops import TuningCache, tuning_key
+    off = np.concatenate([[0], np.cumsum([100, 3000, 3000, 5000, 20000, 1 << 20])]).astype(np.int64)
+    k = tuning_key(off, "gfx950", 0, "forward")
+    assert k == "gfx950|forward|0|1,2,1|32768,1048576"
+    assert tuning_key(off, "gfx950", 0, "step0") != k
+    assert tuning_key(off[:-1], "gfx950", 0, "forward") != k
+    cache = TuningCache(str(tmp_path / "sub" / "tuning.json"))
+    assert cache.get(k) is None
+    cache.put(k, [6, 64, -1, 16])
+    assert TuningCache(cache.path).get(k) == [6, 64, -1, 16]
+    cache.put("other", [0, 0, 0, 0])
+    assert cache.get(k) == [6, 64, -1, 16] and cache.get("other") == [0, 0, 0, 0]
+    with open(cache.path, "w") as f:
+        f.write("not json")
+    assert cache.get(k) is None  # a damaged file is ignored, not fatal

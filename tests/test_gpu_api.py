@@ -1,0 +1,163 @@
+"""GPU tests of the torch-facing layer and the plan API: batched autograd through a cached plan,
+an autotuned in-place forward, the step's autotuner, the persisted tuning, and the stream-local
+status read.  Results are checked against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected only where a GPU exists
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2311_03096_amd as wsr  # noqa: E402
+from gpu_util import (autograd_saved_partition, compare, compare_l1, dev, gpu_forward, oracle_forward,  # noqa: E402
+                      step_reference, vjp_check)
+from paper_2311_03096_amd import ops, workloads  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_autograd_batched_rows_and_plan_cache():
+    """prox() on a row-segmented layer runs the batched entry points over a cached plan: forward
+    and backward against the oracle, and a second call reuses the same plan."""
+    off = ops.row_offsets([(300, 3072), (40, 4096), (2, 20000)])
+    rng = np.random.default_rng(60)
+    w0 = (rng.standard_normal(off[-1]) / 50).astype(np.float32)
+    g0 = rng.standard_normal(off[-1]).astype(np.float32)
+    lam = 1e-3
+    w = torch.from_numpy(w0).cuda().requires_grad_(True)
+    u = ops.prox(w, lam, off)
+    u.backward(torch.from_numpy(g0).cuda())
+    bp = ops.cached_plan(off, w.device)
+    u2 = ops.prox(w.detach(), lam, off)
+    assert ops.cached_plan(off, w.device) is bp
+    assert torch.equal(u.detach(), u2)
+    o = oracle_forward(w0, off, lam)
+    out = u.detach().cpu().numpy()
+    _say("  forward", compare(w0, off, dict(out=out), o, lam=lam))
+    gp, gs = autograd_saved_partition(u, off)
+    _say("  with the saved partition", compare(w0, off, dict(out=out, perm=gp, start=gs), o, lam=lam))
+    vjp_check(g0, off, dict(perm=gp, start=gs), w.grad.cpu().numpy())
+
+
+def test_autotuned_forward_in_place():
+    """BatchedProx(autotune=True).forward(w, w): the routes are timed into a scratch buffer, so
+    the in-place result is the prox applied once."""
+    case = workloads.random_segments([3000] * 100 + [4096] * 50 + [30000], "normal", 0.05, seed=61)
+    off = case["offsets"]
+    w = dev(case["w"])
+    bp = ops.BatchedProx(off, autotune=True)
+    try:
+        bp.forward(w, w, lam_scalar=case["lam"], save=False)
+        torch.cuda.synchronize()
+        assert not bp.tune_pending
+        _say("  tuned routes", bp.merge_rounds())
+    finally:
+        bp.close()
+    o = oracle_forward(case["w"], off, case["lam"])
+    _say("  stats", compare(case["w"], off, dict(out=w.cpu().numpy()), o, lam=case["lam"]))
+
+
+def test_autotune_rejects_aliasing():
+    case = workloads.random_segments([3000, 20000], "normal", 0.05, seed=62)
+    w = dev(case["w"])
+    plan = wsr.wsr_plan_create(case["offsets"])
+    try:
+        lib = wsr.load()
+        import ctypes
+        p = ctypes.c_void_p(w.data_ptr())
+        rc = lib.wsr_plan_autotune(plan, p, p, None, ctypes.c_float(0.05), None, 0, None)
+        assert rc == wsr.WSR_ERR_INVALID
+    finally:
+        wsr.wsr_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("variant", [False, True])
+def test_autotune_step_then_step(variant):
+    """The step's autotuner times the step's own launches (into scratch, w and grad untouched);
+    the tuned plan's step matches the oracle."""
+    case = workloads.random_segments([3072] * 200 + [4096] * 100 + [50000], "normal", 0.05, seed=63)
+    off = case["offsets"]
+    w0 = case["w"]
+    g0 = np.random.default_rng(64).standard_normal(w0.shape[0]).astype(np.float32)
+    eta, alpha, beta, rho = 0.1, (1e-2 if not variant else 1e-3), (0.1 if not variant else 0.01), 0.98
+    w, g = dev(w0), dev(g0)
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        scratch = torch.empty_like(w)
+        flags = wsr.WSR_STEP_ETA_IN_DISPLACEMENT if variant else 0
+        wsr.wsr_plan_autotune_step(plan, w, g, eta, scratch, None, alpha, beta, rho, flags, ws)
+        _say("  tuned routes", wsr.wsr_plan_merge_rounds(plan))
+        assert np.array_equal(w.cpu().numpy(), w0) and np.array_equal(g.cpu().numpy(), g0)
+        wsr.wsr_prox_step_batched(plan, w, g, eta, w, None, alpha, beta, rho, flags, ws)
+        torch.cuda.synchronize()
+    finally:
+        wsr.wsr_plan_destroy(plan)
+    o, z, o_plain, g_plain, beta_eff, q, lam_eff = step_reference(w0, g0, off, np.float32(eta), np.float32(alpha),
+                                                                  np.float32(beta), np.float32(rho), variant)
+    _say("  stats", compare_l1(z, off, w.cpu().numpy(), o, o_plain, g_plain, beta_eff, q, lam_eff))
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """A plan tuned once stores its routes under the architecture and segment-length histogram; a
+    new plan of the same layout takes them from the cache without timing, and gives the same
+    result."""
+    case = workloads.random_segments([4096] * 64 + [20000], "normal", 0.05, seed=65)
+    off = case["offsets"]
+    path = str(tmp_path / "tuning.json")
+    w = dev(case["w"])
+    out1, out2 = torch.empty_like(w), torch.empty_like(w)
+    a = ops.BatchedProx(off, autotune=True, tuning_cache=path)
+    a.forward(w, out1, lam_scalar=case["lam"])
+    key = ops.tuning_key(off, ops.device_arch(), 0, "forward")
+    stored = ops.TuningCache(path).get(key)
+    assert stored == a.merge_rounds()
+    # a different stored tuning is applied as is, with no timing (the plan's routes become it)
+    forced = [6, 0, 16, 0]
+    ops.TuningCache(path).put(key, forced)
+    b = ops.BatchedProx(off, autotune=True, tuning_cache=path)
+    b.forward(w, out2, lam_scalar=case["lam"])
+    assert b.merge_rounds() == forced and not b.tune_pending
+    torch.cuda.synchronize()
+    assert torch.equal(out1, out2)  # every route gives the same result
+    a.close()
+    b.close()
+
+
+def test_read_status_on_its_stream():
+    """The status read synchronises only the stream it is given: work on that stream is covered."""
+    case = workloads.random_segments([3000, 20000], "normal", 0.05, seed=66)
+    off = case["offsets"]
+    w_bad = dev(case["w"])
+    w_bad[17] = float("nan")
+    plan = wsr.wsr_plan_create(off)
+    s = torch.cuda.Stream()
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+        out = torch.empty_like(w_bad)
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            wsr.wsr_prox_forward_batched(plan, w_bad, out, None, 0.05, None, None, ws)
+        assert wsr.wsr_read_status(plan, clear=True, stream=s.cuda_stream) == wsr.WSR_STATUS_NONFINITE
+        assert wsr.wsr_read_status(plan, clear=False, stream=s.cuda_stream) == 0
+    finally:
+        torch.cuda.synchronize()
+        wsr.wsr_plan_destroy(plan)
+
+
+def test_per_row_and_batched_equal_gpu_forward():
+    """The plain entry point (one launch per row) and the batched one give identical bits."""
+    case = workloads.random_segments([4096] * 32 + [3072] * 32, "laplace", 0.05, seed=67)
+    a = gpu_forward(case["w"], case["offsets"], case["lam"], batched=False)
+    b = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
+    for k in ("out", "perm", "start"):
+        assert np.array_equal(a[k], b[k])

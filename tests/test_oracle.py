@@ -202,6 +202,87 @@ def test_kkt_certificate(dist):
     assert ok, msg
 
 
+def _kkt_case(seed=21):
+    rng = np.random.default_rng(seed)
+    lens = [1, 2, 7, 300, 5000, 0, 2048, 40]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = np.concatenate([rng.normal(size=lens[0] + lens[1] + lens[2]), rng.laplace(size=lens[3]),
+                        1e3 + 1e-2 * rng.normal(size=lens[4]), rng.integers(-9, 9, lens[6]) / 4.0,
+                        rng.normal(size=lens[7])]).astype(np.float32)
+    lam = np.array([0.3, 0.2, 0.5, 1.0, 1e-4, 0.1, 0.25, 0.0], np.float32)
+    return w, off, lam
+
+
+def test_kkt_certificate_segments_accepts_oracle_output():
+    """The vectorised certificate accepts the oracle's output on a layout with identity segments
+    (d = 1, lam = 0), an empty segment, a precision-stress segment and tie groups, both in the
+    oracle's rank order and in the (u, w) order; and it agrees with the per-segment loop form."""
+    w, off, lam = _kkt_case()
+    u, perm, start = oracle.prox_segments(w, lam, off)
+    for kw in (dict(perm=perm, start=start), {}):
+        r = pins.kkt_certificate_segments(w, off, u, lam, tol_rel=1e-9, **kw)
+        assert r["ok"], r
+    for s in range(len(off) - 1):
+        a, b = off[s], off[s + 1]
+        if b - a >= 2 and lam[s] > 0:
+            ok, msg = pins.kkt_certificate(w[a:b].astype(np.float64), u[a:b], float(lam[s]), 1e-9 * 1e3)
+            assert ok, msg
+
+
+def test_kkt_certificate_segments_rejects_mistakes():
+    """Plausible mistakes in a prox output each fail one condition: a wrong lambda, a shifted
+    cluster value, two clusters merged, one cluster split, the shift v with the wrong sign, and a
+    changed identity segment."""
+    w, off, lam = _kkt_case()
+    u, perm, start = oracle.prox_segments(w, lam, off)
+    seg = 3  # the Laplace segment (many clusters of several ranks)
+    a, b = off[seg], off[seg + 1]
+    tol = 1e-9
+
+    def bad(u2, **kw):
+        r = pins.kkt_certificate_segments(w, off, u2, lam, tol_rel=tol, **kw)
+        return not r["ok"]
+
+    u_lam, _, _ = oracle.prox_segments(w, lam * np.float32(1.01), off)
+    assert bad(u_lam) and bad(u_lam, perm=perm, start=start)
+    u2 = u.copy()
+    o = a + perm[a:b].astype(np.int64)  # original indices in rank order
+    cid = np.cumsum(start[a:b]) - 1
+    big = np.bincount(cid)
+    c = int(np.argmax(big))  # the largest cluster
+    members = o[cid == c]
+    u2[members] += 1e-3
+    assert bad(u2) and bad(u2, perm=perm, start=start)
+    # merge clusters c and c+1 into one with their joint mean value
+    u3 = u.copy()
+    both = o[(cid == c) | (cid == c + 1)]
+    u3[both] = u[both].mean()
+    assert bad(u3)
+    # split the largest cluster in two at its middle rank, each half at its own mean of y
+    x = w[o].astype(np.float64)
+    d = b - a
+    v = lam[seg] * (d - 1 - 2 * np.arange(d)) / (d - 1)
+    y = x + v
+    idx = np.nonzero(cid == c)[0]
+    h = idx[: len(idx) // 2]
+    t = idx[len(idx) // 2:]
+    u4 = u.copy()
+    u4[o[h]] = y[h].mean()
+    u4[o[t]] = y[t].mean()
+    st4 = start.copy()
+    st4[a + t[0]] = 1
+    assert bad(u4) and bad(u4, perm=perm, start=st4)
+    # v with the wrong sign: isotonic regression of x - v instead of x + v
+    yw = x - v
+    u5 = u.copy()
+    u5[o] = np.maximum.accumulate(yw)  # any monotone fit of the wrong y
+    assert bad(u5)
+    # identity segment changed
+    u6 = u.copy()
+    u6[off[7]] += 1e-6
+    assert bad(u6, perm=perm, start=start)
+
+
 # ----------------------------------------------------------------------------- closed forms
 
 def test_closed_form_d2():
