@@ -33,6 +33,7 @@ def test_autograd_batched_rows_and_plan_cache():
     lam = 1e-3
     w = torch.from_numpy(w0).cuda().requires_grad_(True)
     u = ops.prox(w, lam, off)
+    gp, gs = autograd_saved_partition(u, off)  # read before backward frees it
     u.backward(torch.from_numpy(g0).cuda())
     bp = ops.cached_plan(off, w.device)
     u2 = ops.prox(w.detach(), lam, off)
@@ -41,7 +42,6 @@ def test_autograd_batched_rows_and_plan_cache():
     o = oracle_forward(w0, off, lam)
     out = u.detach().cpu().numpy()
     _say("  forward", compare(w0, off, dict(out=out), o, lam=lam))
-    gp, gs = autograd_saved_partition(u, off)
     _say("  with the saved partition", compare(w0, off, dict(out=out, perm=gp, start=gs), o, lam=lam))
     vjp_check(g0, off, dict(perm=gp, start=gs), w.grad.cpu().numpy())
 

@@ -334,13 +334,13 @@ def test_autograd_prox():
     case = workloads.random_segments([3000, 12000], "normal", 0.05, seed=13)
     w = torch.from_numpy(case["w"]).cuda().requires_grad_(True)
     u = prox(w, case["lam"], case["offsets"])
+    gp, gs = autograd_saved_partition(u, case["offsets"])  # read before backward frees it
     g = torch.randn_like(u)
     u.backward(g)
     o = oracle_forward(case["w"], case["offsets"], case["lam"])
     out = u.detach().cpu().numpy()
     compare(case["w"], case["offsets"], dict(out=out), o, lam=case["lam"])
     # backward against the oracle VJP on the partition the forward saved
-    gp, gs = autograd_saved_partition(u, case["offsets"])
     compare(case["w"], case["offsets"], dict(out=out, perm=gp, start=gs), o, lam=case["lam"])
     vjp_check(g.cpu().numpy(), case["offsets"], dict(perm=gp, start=gs), w.grad.cpu().numpy())
 
