@@ -104,6 +104,23 @@ WSR_API int wsr_prox_forward(const float* w, float* out, const int64_t* h_offset
                      size_t ws_bytes, void* stream);
 
 /*
+ * wsr_prox_forward without a workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Long
+ * segments use a fixed scratch array of WSR_NOALLOC_SCRATCH_BYTES in device memory, one per GPU,
+ * created with the library's code object and held until the process ends; the call itself
+ * allocates nothing.  Limit: a segment whose workspace (wsr_workspace_bytes) exceeds the scratch
+ * returns WSR_ERR_WORKSPACE before anything is enqueued; every segment of up to
+ * WSR_NOALLOC_MAX_SEGMENT elements fits.  All calls on one GPU share its scratch: calls that
+ * overlap in time on one GPU (other streams, other host threads) race and must be ordered by the
+ * caller.  The scratch needs no clearing (every word the kernels read is written first in the
+ * same call).  Arguments, results and errors otherwise as in wsr_prox_forward.
+ */
+#define WSR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+#define WSR_NOALLOC_MAX_SEGMENT ((int64_t)1 << 21)
+WSR_API int wsr_prox_forward_noalloc(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg,
+                                     float lambda, int32_t* saved_perm, uint32_t* saved_mask, void* stream);
+
+/*
  * Forward of Alg. prox in full: the proximal map of lambda*R_d + beta*l1 with rewinding rho
  * (Sec. 1, prox of the combined penalty; App. "combining weight-sharing and sparsity" for its
  * decomposition; Sec. "rewinding" and Alg. prox, l1 and rewinding lines).  The collisions are

@@ -9,7 +9,8 @@ from ._lib import (Plan, WSR_ERR_HIP, WSR_ERR_INVALID, WSR_ERR_UNSUPPORTED, WSR_
                    wsr_plan_autotune, wsr_plan_autotune_step, wsr_plan_create, wsr_plan_destroy, wsr_plan_merge_rounds,
                    wsr_plan_set_merge_rounds, wsr_read_status, WSR_STATUS_NONFINITE,
                    wsr_plan_workspace_bytes,
-                   wsr_prox_backward, wsr_prox_backward_batched, wsr_prox_forward,
+                   wsr_prox_backward, wsr_prox_backward_batched, wsr_prox_forward, wsr_prox_forward_noalloc,
+                   WSR_NOALLOC_MAX_SEGMENT, WSR_NOALLOC_SCRATCH_BYTES,
                    wsr_prox_forward_batched, wsr_prox_l1_forward, wsr_prox_l1_forward_batched,
                    wsr_prox_step_batched, WSR_STEP_ETA_IN_DISPLACEMENT, wsr_segment_stats,
                    wsr_segment_stats_batched, stats_to_numpy,
@@ -18,7 +19,8 @@ from ._lib import (Plan, WSR_ERR_HIP, WSR_ERR_INVALID, WSR_ERR_UNSUPPORTED, WSR_
 
 __all__ = [
     "load", "WsrError", "wsr_version", "wsr_status_string", "wsr_workspace_bytes",
-    "wsr_prox_forward", "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy",
+    "wsr_prox_forward", "wsr_prox_forward_noalloc", "WSR_NOALLOC_MAX_SEGMENT", "WSR_NOALLOC_SCRATCH_BYTES",
+    "wsr_prox_backward", "wsr_plan_create", "wsr_plan_destroy",
     "wsr_plan_workspace_bytes", "wsr_prox_forward_batched", "wsr_prox_backward_batched",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
     "WSR_STEP_ETA_IN_DISPLACEMENT", "wsr_segment_stats", "wsr_segment_stats_batched", "stats_to_numpy",

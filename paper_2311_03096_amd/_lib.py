@@ -21,6 +21,8 @@ WSR_PLAN_MERGE_END = 4
 WSR_STATUS_NONFINITE = 1
 WSR_STEP_ETA_IN_DISPLACEMENT = 1
 WSR_MAX_SEGMENT = 1 << 26
+WSR_NOALLOC_SCRATCH_BYTES = 64 << 20
+WSR_NOALLOC_MAX_SEGMENT = 1 << 21
 
 EXPORTED = (
     "wsr_version", "wsr_status_string", "wsr_workspace_bytes", "wsr_prox_forward",
@@ -28,7 +30,7 @@ EXPORTED = (
     "wsr_prox_forward_batched", "wsr_prox_backward_batched", "wsr_trace_enable", "wsr_trace_collect",
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
     "wsr_segment_stats", "wsr_segment_stats_batched", "wsr_plan_autotune", "wsr_plan_merge_rounds",
-    "wsr_plan_set_merge_rounds", "wsr_read_status", "wsr_plan_autotune_step",
+    "wsr_plan_set_merge_rounds", "wsr_read_status", "wsr_plan_autotune_step", "wsr_prox_forward_noalloc",
 )
 
 
@@ -57,6 +59,7 @@ def load():
         "wsr_status_string": ([i32], ctypes.c_char_p),
         "wsr_workspace_bytes": ([p, i64, ctypes.POINTER(sz)], i32),
         "wsr_prox_forward": ([p, p, p, i64, f32, p, p, p, sz, p], i32),
+        "wsr_prox_forward_noalloc": ([p, p, p, i64, f32, p, p, p], i32),
         "wsr_prox_backward": ([p, p, p, i64, p, p, p, sz, p], i32),
         "wsr_prox_l1_forward": ([p, p, p, i64, f32, f32, f32, p, sz, p], i32),
         "wsr_prox_l1_forward_batched": ([p, p, p, p, f32, f32, f32, p, sz, p], i32),
@@ -237,6 +240,19 @@ def wsr_prox_forward(w, out, offsets, lam, saved_perm=None, saved_mask=None, ws=
     _check("wsr_prox_forward", load().wsr_prox_forward(
         _ptr(w), _ptr(out), off.ctypes.data_as(ctypes.c_void_p), off.shape[0] - 1, float(lam),
         _ptr(saved_perm), _ptr(saved_mask), wp, wn, _stream(stream)))
+
+
+def wsr_prox_forward_noalloc(w, out, offsets, lam, saved_perm=None, saved_mask=None, stream=None):
+    """wsr_prox_forward with the library's fixed per-GPU scratch instead of a workspace (no
+    allocation in the call; segments up to WSR_NOALLOC_MAX_SEGMENT)."""
+    off = _offsets(offsets)
+    n = _n_of(off)
+    _check_values(n, w=w, out=out)
+    _check_saved(n, saved_perm, saved_mask)
+    _on_gpu(w=w, out=out, saved_perm=saved_perm, saved_mask=saved_mask)
+    _check("wsr_prox_forward_noalloc", load().wsr_prox_forward_noalloc(
+        _ptr(w), _ptr(out), off.ctypes.data_as(ctypes.c_void_p), off.shape[0] - 1, float(lam),
+        _ptr(saved_perm), _ptr(saved_mask), _stream(stream)))
 
 
 def wsr_prox_l1_forward(w, out, offsets, lam, beta, rho, ws=None, stream=None):

@@ -628,10 +628,50 @@ int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
 
 }  // namespace
 
+// ---- fixed device scratch of the allocation-free forward (wsr_prox_forward_noalloc)
+// One copy per GPU, created with the code object and held until the process ends.  In host code
+// the array's name is not a device address: the kernels get the address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static_assert(kNoAllocScratchBytes == WSR_NOALLOC_SCRATCH_BYTES, "scratch size as declared in the header");
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+int noalloc_scratch(void** out) {
+  static std::mutex mu;
+  static std::vector<void*> per_device;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return WSR_ERR_HIP;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((size_t)dev >= per_device.size()) per_device.resize((size_t)dev + 1, nullptr);
+  if (per_device[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return WSR_ERR_HIP;
+    per_device[dev] = p;
+  }
+  *out = per_device[dev];
+  return WSR_OK;
+}
+
 extern "C" {
 
 int wsr_prox_forward(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
                      int32_t* saved_perm, uint32_t* saved_mask, void* ws, size_t ws_bytes, void* stream) {
+  return forward_impl(w, out, h_offsets, n_seg, lambda, saved_perm, saved_mask, ws, ws_bytes, stream, L1Opt{});
+}
+
+int wsr_prox_forward_noalloc(const float* w, float* out, const int64_t* h_offsets, int64_t n_seg, float lambda,
+                             int32_t* saved_perm, uint32_t* saved_mask, void* stream) {
+  int64_t mb = 0;
+  int rc = validate_offsets(h_offsets, n_seg, &mb);
+  if (rc) return rc;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  if (mb > 0) {
+    if (big_bytes(mb) > kNoAllocScratchBytes) return WSR_ERR_WORKSPACE;  // beyond the fixed scratch
+    rc = noalloc_scratch(&ws);
+    if (rc) return rc;
+    ws_bytes = kNoAllocScratchBytes;
+  }
   return forward_impl(w, out, h_offsets, n_seg, lambda, saved_perm, saved_mask, ws, ws_bytes, stream, L1Opt{});
 }
 

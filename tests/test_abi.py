@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 22
+    assert len(declared) == 23
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -310,3 +310,18 @@ def test_tuning_key_and_cache(tmp_path):
     with open(cache.path, "w") as f:
         f.write("not json")
     assert cache.get(k) is None  # a damaged file is ignored, not fatal
+
+
+def test_noalloc_limits_on_host():
+    """The fixed scratch of the allocation-free forward holds the workspace of every segment up to
+    WSR_NOALLOC_MAX_SEGMENT; a longer one is rejected before any device call."""
+    assert wsr.wsr_workspace_bytes([0, wsr.WSR_NOALLOC_MAX_SEGMENT]) <= wsr.WSR_NOALLOC_SCRATCH_BYTES
+    assert wsr.wsr_workspace_bytes([0, 4 * wsr.WSR_NOALLOC_MAX_SEGMENT]) > wsr.WSR_NOALLOC_SCRATCH_BYTES
+    lib = wsr.load()
+    for d, want in ((4 * wsr.WSR_NOALLOC_MAX_SEGMENT, wsr.WSR_ERR_WORKSPACE), ((1 << 26) + 1, wsr.WSR_ERR_UNSUPPORTED)):
+        off = np.array([0, d], np.int64)
+        assert lib.wsr_prox_forward_noalloc(FAKE, FAKE, off.ctypes.data_as(ctypes.c_void_p), 1, ctypes.c_float(0.1),
+                                            None, None, None) == want
+    off = np.array([0, 5, 3], np.int64)
+    assert lib.wsr_prox_forward_noalloc(FAKE, FAKE, off.ctypes.data_as(ctypes.c_void_p), 2, ctypes.c_float(0.1),
+                                        None, None, None) == wsr.WSR_ERR_INVALID
