@@ -64,6 +64,7 @@ struct BigWs {
   uint32_t* flags;
   float* lamtmp;   // a segment's lambda formed on the device (proximal-gradient step)
   uint32_t* tbad;  // per radix tile: non-finite weight seen (first pass)
+  uint32_t *tor, *tand;  // per radix tile: OR and AND of its keys (first pass)
   uint32_t *keysA, *keysB;
   int32_t *valsA, *valsB;
   uint32_t *hist, *totals;
@@ -88,9 +89,11 @@ BigWs big_layout(int64_t d, void* base) {
     off += align_up(bytes);
     return p;
   };
-  w.flags = (uint32_t*)take(256);
+  w.flags = (uint32_t*)take(256);  // [0] non-finite weight seen, [1] key bits that vary
   w.lamtmp = (float*)take(256);
   w.tbad = (uint32_t*)take(sizeof(uint32_t) * nrt);
+  w.tor = (uint32_t*)take(sizeof(uint32_t) * nrt);
+  w.tand = (uint32_t*)take(sizeof(uint32_t) * nrt);
   w.keysA = (uint32_t*)take(sizeof(uint32_t) * d);
   w.keysB = (uint32_t*)take(sizeof(uint32_t) * d);
   w.valsA = (int32_t*)take(sizeof(int32_t) * d);
@@ -233,26 +236,26 @@ bool l1_args_ok(float beta, float rho) {
   return std::isfinite(beta) && beta >= 0.0f && rho >= 0.0f && rho <= 1.0f;
 }
 
-// Stable LSD radix sort of one long segment (4 passes of 8 bits: w -> B -> A -> B -> A): sorted
-// keys end in b.keysA, the permutation in perm_final; b.flags[0] gets the non-finite bit.
+// Grid of a persistent radix kernel: at most `maxg` workgroups, a multiple of 8 (every XCD gets a
+// contiguous share of the tiles).
+int radix_grid(int ntiles, int maxg) { return (std::min(ntiles, maxg) + 7) / 8 * 8; }
+
+// Stable LSD radix sort of one long segment (up to 4 passes of 8 bits; a later pass whose digit
+// is the same for every key is skipped on the device): sorted keys end in b.keysA, the
+// permutation in perm_final; b.flags[0] gets the non-finite bit, b.flags[1] the varying key bits.
 void big_sort(const float* wseg, int64_t d, const BigWs& b, int32_t* perm_final, hipStream_t s) {
   const int nrt = (int)ceil_div(d, kRadixTile);
   for (int pass = 0; pass < 4; ++pass) {
-    const int shift = 8 * pass;
-    const uint32_t* ksrc = pass == 0 ? nullptr : (pass % 2 == 1 ? b.keysB : b.keysA);
-    const int32_t* vsrc = pass == 0 ? nullptr : (pass % 2 == 1 ? b.valsB : b.valsA);
-    uint32_t* kdst = pass % 2 == 0 ? b.keysB : b.keysA;
-    int32_t* vdst = pass % 2 == 0 ? b.valsB : (pass == 3 ? perm_final : b.valsA);
     { WSR_TRACE("radix_hist", s);
-    hipLaunchKernelGGL(k_radix_hist, dim3(std::min(nrt, hist_grid())), dim3(kRadixThreads), 0, s, pass == 0 ? wseg : nullptr,
-                       ksrc, d, shift, b.hist, nrt, b.tbad); }
+    hipLaunchKernelGGL(k_radix_hist, dim3(radix_grid(nrt, hist_grid())), dim3(kRadixThreads), 0, s, pass, wseg,
+                       b.keysA, b.keysB, b.valsA, b.valsB, perm_final, d, b.hist, nrt, b.tbad, b.tor, b.tand,
+                       b.flags); }
     { WSR_TRACE("radix_rowscan", s);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, b.hist, nrt, b.totals,
-                       pass == 0 ? b.tbad : nullptr, b.flags); }
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, pass, b.hist, nrt, b.totals, b.tbad, b.tor,
+                       b.tand, b.flags); }
     { WSR_TRACE("radix_scatter", s);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(std::min(nrt, scatter_grid())), dim3(kScatterThreads), 0, s,
-                       pass == 0 ? wseg : nullptr,
-                       ksrc, vsrc, kdst, vdst, d, shift, b.hist, b.totals, nrt); }
+    hipLaunchKernelGGL(k_radix_scatter, dim3(radix_grid(nrt, scatter_grid())), dim3(kScatterThreads), 0, s, pass,
+                       wseg, b.keysA, b.keysB, b.valsA, b.valsB, perm_final, d, b.hist, b.totals, nrt, b.flags); }
   }
 }
 

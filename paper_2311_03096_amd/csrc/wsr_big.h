@@ -10,8 +10,9 @@ namespace wsr {
 constexpr int kRadixThreads = 256;   // histogram workgroup; the scatter's digit scan uses
                                      // one thread per digit
 constexpr int kRadixTile = 8192;     // keys per radix tile (digit runs average 32 keys)
-constexpr int kScatterThreads = 512;  // scatter workgroup (16 keys per thread)
+constexpr int kMaxRadixTiles = (1 << 26) / kRadixTile;  // radix tiles of the longest segment
 constexpr int kHistPerCu = 4;         // resident workgroups per CU of the persistent histogram
+constexpr int kScatterThreads = 512;  // scatter workgroup (16 keys per thread)
 constexpr int kBigThreads = 256;
 constexpr int kBigE = 16;
 constexpr int kBigTile = kBigThreads * kBigE;  // ranks per hull tile
@@ -26,13 +27,14 @@ static_assert(kRadixThreads == 256, "one histogram bin per thread");
 static_assert(kMergeGroupMax / 1024 <= 16, "tile scans hold at most 16 tiles per thread");
 static_assert(kScatterThreads >= 256, "digit scan assumes one digit per thread");
 
-__global__ void k_radix_hist(const float* wsrc, const uint32_t* ksrc, int64_t n, int shift,
-                             uint32_t* hist, int ntiles, uint32_t* tbad);
-__global__ void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals, const uint32_t* tbad,
-                                uint32_t* flags);
-__global__ void k_radix_scatter(const float* wsrc, const uint32_t* ksrc, const int32_t* vsrc,
-                                uint32_t* kdst, int32_t* vdst, int64_t n, int shift,
-                                const uint32_t* hist, const uint32_t* totals, int ntiles);
+__global__ void k_radix_hist(int pass, const float* wsrc, uint32_t* kA, uint32_t* kB, int32_t* vA, int32_t* vB,
+                             int32_t* vfinal, int64_t n, uint32_t* hist, int ntiles, uint32_t* tbad, uint32_t* tor,
+                             uint32_t* tand, const uint32_t* flags);
+__global__ void k_radix_rowscan(int pass, uint32_t* hist, int ntiles, uint32_t* totals, const uint32_t* tbad,
+                                const uint32_t* tor, const uint32_t* tand, uint32_t* flags);
+__global__ void k_radix_scatter(int pass, const float* w, uint32_t* kA, uint32_t* kB, int32_t* vA, int32_t* vB,
+                                int32_t* vfinal, int64_t n, const uint32_t* hist, const uint32_t* totals,
+                                int ntiles, const uint32_t* flags);
 __global__ void k_big_tile_hull(const uint32_t* skeys, int64_t d, const float* lam_arr, int seg_id,
                                 float lam_scalar, int32_t* vpos, double* vS, int32_t* hcnt,
                                 double* tsum, uint16_t* hbits, int rounds);

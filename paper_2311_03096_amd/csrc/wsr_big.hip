@@ -23,27 +23,88 @@ namespace wsr {
 
 // ------------------------------------------------------------------------------- radix sort
 
-// Per-tile histogram of one 8-bit digit.  Source is either the FP32 weights (first pass: keys
-// made on the fly, non-finite values flagged) or the u32 keys of the previous pass.  Persistent:
-// workgroup b counts tiles b, b + G, ... (G = gridDim.x) and has the next tile's keys in flight
-// while it counts the current one, so the loads of one tile overlap the LDS atomics of another.
-__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc, const uint32_t* ksrc,
-                                                             int64_t n, int shift, uint32_t* hist,
-                                                             int ntiles, uint32_t* tbad) {
+// Persistent radix kernels walk their tiles in XCD-contiguous order.  Workgroup b runs on XCD
+// b % 8 (the dispatcher deals workgroups to the eight XCDs in turn); the workgroups of one XCD
+// share one contiguous eighth of the tiles, so the tiles in flight on an XCD are neighbours and
+// the partial cache lines where their output runs meet are completed in that XCD's L2 rather than
+// written back in pieces from several XCDs.  The grid is a multiple of 8 (chosen by the host).
+__device__ __forceinline__ void xcd_tiles(int ntiles, int* first, int* end, int* step) {
+  const int x = (int)(blockIdx.x & 7u), j = (int)(blockIdx.x >> 3), gx = (int)(gridDim.x >> 3);
+  *first = (int)((int64_t)x * ntiles / 8) + j;
+  *end = (int)((int64_t)(x + 1) * ntiles / 8);
+  *step = gx;
+}
+
+// Buffers of sort pass `pass`.  The first pass's row scan stores in flags[1] the key bits that
+// vary over the segment; a later pass whose 8-bit digit is the same for every key would move
+// nothing and is skipped.  Of the passes that run, the last writes the final keys (kA) and the
+// permutation (vfinal); the others alternate so that each reads what the previous one wrote.
+struct RadixBufs {
+  const uint32_t* ksrc;  // null: the first pass reads the FP32 weights
+  const int32_t* vsrc;
+  uint32_t* kdst;
+  int32_t* vdst;
+  bool run;
+};
+__device__ __forceinline__ bool radix_pass_runs(int pass, uint32_t varying) {
+  return pass == 0 || ((varying >> (8 * pass)) & 255u) != 0u;
+}
+__device__ __forceinline__ RadixBufs radix_bufs(int pass, uint32_t varying, uint32_t* kA, uint32_t* kB, int32_t* vA,
+                                                int32_t* vB, int32_t* vfinal) {
+  int n = 0, j = 0;
+  for (int p = 0; p < 4; ++p) {
+    if (!radix_pass_runs(p, varying)) continue;
+    if (p == pass) j = n;
+    ++n;
+  }
+  RadixBufs b{nullptr, nullptr, nullptr, nullptr, radix_pass_runs(pass, varying)};
+  if (!b.run) return b;
+  // the i-th pass that runs writes the A buffers when n - 1 - i is even (so the last one writes A)
+  auto writes_a = [&](int i) { return ((n - 1 - i) & 1) == 0; };
+  if (j > 0) {
+    const bool a = writes_a(j - 1);
+    b.ksrc = a ? kA : kB;
+    b.vsrc = a ? vA : vB;
+  }
+  const bool a = writes_a(j);
+  b.kdst = a ? kA : kB;
+  b.vdst = j == n - 1 ? vfinal : (a ? vA : vB);
+  return b;
+}
+
+// Per-tile histogram of one 8-bit digit, written digit-major (hist[digit * ntiles + tile]; the
+// tiles in flight on one XCD are neighbours, so their counts of a digit fill whole cache lines).
+// Source: the FP32 weights (first pass: keys made on the fly, non-finite values flagged, and the
+// OR and AND of the tile's keys kept for the varying-bits mask) or the keys the previous pass
+// wrote.  Persistent: each workgroup has its next tile's keys in flight while it counts the
+// current one, so the loads of one tile overlap the LDS atomics of another.
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(int pass, const float* wsrc, uint32_t* kA, uint32_t* kB,
+                                                             int32_t* vA, int32_t* vB, int32_t* vfinal, int64_t n,
+                                                             uint32_t* hist, int ntiles, uint32_t* tbad,
+                                                             uint32_t* tor, uint32_t* tand, const uint32_t* flags) {
   constexpr int IPT = kRadixTile / kRadixThreads;
   constexpr int NW = kRadixThreads / kWave;
   constexpr int kHistLanes = 16;
   constexpr int kSub = kWave / kHistLanes;  // sub-histograms per wave
+  const int shift = 8 * pass;
+  const uint32_t* ksrc = nullptr;
+  if (pass > 0) {
+    const RadixBufs b = radix_bufs(pass, flags[1], kA, kB, vA, vB, vfinal);
+    if (!b.run) return;
+    ksrc = b.ksrc;
+  }
+  const bool first = pass == 0;
   // one pad word per sub-histogram: the same digit in different lane groups falls on different
   // LDS banks
   __shared__ uint32_t h[NW * kSub][257];
+  __shared__ uint32_t red[2][NW];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
   for (int j = lane; j < 256 * kSub; j += kWave) h[wv * kSub + j / 256][j % 256] = 0u;
   // raw 32-bit words of a tile (weights or keys), all in flight at once: uniform tile base,
   // 32-bit offsets; words past the end of the segment are never counted
-  const uint32_t* src = wsrc ? reinterpret_cast<const uint32_t*>(wsrc) : ksrc;
+  const uint32_t* src = first ? reinterpret_cast<const uint32_t*>(wsrc) : ksrc;
   auto load = [&](int tile, uint32_t (&w)[IPT]) {
     const int64_t base = (int64_t)tile * kRadixTile;
     const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
@@ -59,25 +120,29 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
       }
     }
   };
-  int bad = 0;
+  int tile, tend, tstep;
+  xcd_tiles(ntiles, &tile, &tend, &tstep);
   uint32_t word[IPT];
-  int tile = blockIdx.x;
-  if (tile < ntiles) load(tile, word);
-  for (; tile < ntiles; tile += gridDim.x) {
+  if (tile < tend) load(tile, word);
+  for (; tile < tend; tile += tstep) {
     const int64_t base = (int64_t)tile * kRadixTile;
     const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
     uint32_t wn[IPT];
-    const int next = tile + (int)gridDim.x;
-    if (next < ntiles) load(next, wn);
+    const int next = tile + tstep;
+    if (next < tend) load(next, wn);
+    int bad = 0;
+    uint32_t kor = 0u, kand = 0xFFFFFFFFu;
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
       const bool in = p < nt;
       uint32_t key = word[r];
-      if (wsrc) {
+      if (first) {
         const float f = __uint_as_float(key);
         bad |= in && !isfinite(f);
         key = float_to_key(f);
+        kor |= in ? key : 0u;
+        kand &= in ? key : 0xFFFFFFFFu;
       }
       // each group of kHistLanes lanes counts into its own sub-histogram, so a skewed digit
       // (the top byte of most inputs, long runs in sorted data) puts at most kHistLanes lanes on
@@ -86,11 +151,26 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
       const uint32_t dg = in ? (key >> shift) & 255u : 256u;
       atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
     }
-    if (wsrc) {
-      // first pass: every tile's non-finite flag is written each call (no clearing launch)
+    if (first) {
+      // first pass: every tile's non-finite flag and key OR / AND are written each call (no
+      // clearing launch)
+      kor = wave_or_u32(kor);
+      kand = wave_and_u32(kand);
+      if (lane == 0) {
+        red[0][wv] = kor;
+        red[1][wv] = kand;
+      }
       const int any = __syncthreads_or(bad);
-      if (tid == 0) tbad[tile] = any ? 1u : 0u;
-      bad = 0;
+      if (tid == 0) {
+        uint32_t o = 0u, a = 0xFFFFFFFFu;
+        for (int w = 0; w < NW; ++w) {
+          o |= red[0][w];
+          a &= red[1][w];
+        }
+        tbad[tile] = any ? 1u : 0u;
+        tor[tile] = o;
+        tand[tile] = a;
+      }
     } else {
       __syncthreads();
     }
@@ -103,26 +183,47 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const float* wsrc,
       }
       hist[(int64_t)j * ntiles + tile] = c;
     }
-    __syncthreads();  // the sub-histograms are clear for the next tile
+    __syncthreads();  // the sub-histograms are clear (and red is free) for the next tile
 #pragma unroll
     for (int r = 0; r < IPT; ++r) word[r] = wn[r];
   }
 }
 
 // Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
-// The row goes through LDS so global reads and writes are coalesced.
-// For the first pass (tbad != null) workgroup 0 also folds the tiles' non-finite flags into
-// flags[0] (a plain store: every call writes it).
-__global__ __launch_bounds__(256) void k_radix_rowscan(uint32_t* hist, int ntiles, uint32_t* totals,
-                                                       const uint32_t* tbad, uint32_t* flags) {
-  constexpr int kMaxRow = (1 << 26) / kRadixTile;  // tiles of the longest segment
-  __shared__ uint32_t row_s[kMaxRow];
+// The row goes through LDS so global reads and writes are coalesced.  For the first pass
+// (pass == 0) workgroup 0 also folds the tiles' non-finite flags into flags[0] and their key OR /
+// AND into the varying-bits mask flags[1] (plain stores: every call writes them); a later pass
+// whose digit does not vary returns at once.
+__global__ __launch_bounds__(256) void k_radix_rowscan(int pass, uint32_t* hist, int ntiles, uint32_t* totals,
+                                                       const uint32_t* tbad, const uint32_t* tor,
+                                                       const uint32_t* tand, uint32_t* flags) {
+  __shared__ uint32_t row_s[kMaxRadixTiles];
   __shared__ int sh[256 / kWave + 1];
-  if (tbad && blockIdx.x == 0) {
-    uint32_t any = 0u;
-    for (int i = threadIdx.x; i < ntiles; i += 256) any |= tbad[i];
+  __shared__ uint32_t ored[2][256 / kWave];
+  if (pass > 0 && !radix_pass_runs(pass, flags[1])) return;
+  if (pass == 0 && blockIdx.x == 0) {
+    uint32_t any = 0u, o = 0u, a = 0xFFFFFFFFu;
+    for (int i = threadIdx.x; i < ntiles; i += 256) {
+      any |= tbad[i];
+      o |= tor[i];
+      a &= tand[i];
+    }
+    o = wave_or_u32(o);
+    a = wave_and_u32(a);
+    if (lane_id() == 0) {
+      ored[0][threadIdx.x / kWave] = o;
+      ored[1][threadIdx.x / kWave] = a;
+    }
     any = __syncthreads_or(any != 0u);
-    if (threadIdx.x == 0) flags[0] = any ? 1u : 0u;
+    if (threadIdx.x == 0) {
+      uint32_t wo = 0u, wa = 0xFFFFFFFFu;
+      for (int w = 0; w < 256 / kWave; ++w) {
+        wo |= ored[0][w];
+        wa &= ored[1][w];
+      }
+      flags[0] = any ? 1u : 0u;
+      flags[1] = wo ^ wa;
+    }
   }
   uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
   for (int i = threadIdx.x; i < ntiles; i += 256) row_s[i] = row[i];
@@ -184,17 +285,25 @@ __device__ __forceinline__ void radix_raw_to_key(const float* wsrc, uint32_t (&k
   }
 }
 
-// Stable scatter by one digit, persistent: workgroup b takes tiles b, b + G, b + 2G, ... (G =
-// gridDim.x) and loads the next tile's items while it ranks and writes the current one.  Items
-// are ranked in wave-striped order, which is the tile's current order, so equal digits keep
-// their relative order.  Writes go out digit-run by digit-run.
-__global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const float* wsrc, const uint32_t* ksrc,
-                                                                const int32_t* vsrc, uint32_t* kdst,
-                                                                int32_t* vdst, int64_t n, int shift,
+// Stable scatter by one digit, persistent over XCD-contiguous tiles; each workgroup loads its
+// next tile's items while it ranks and writes the current one.  Items are ranked in wave-striped
+// order, which is the tile's current order, so equal digits keep their relative order.  Writes go
+// out digit-run by digit-run.
+__global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(int pass, const float* w, uint32_t* kA,
+                                                                uint32_t* kB, int32_t* vA, int32_t* vB,
+                                                                int32_t* vfinal, int64_t n,
                                                                 const uint32_t* hist, const uint32_t* totals,
-                                                                int ntiles) {
+                                                                int ntiles, const uint32_t* flags) {
   constexpr int IPT = kRadixTile / kScatterThreads;
   constexpr int NW = kScatterThreads / kWave;
+  const RadixBufs bufs = radix_bufs(pass, flags[1], kA, kB, vA, vB, vfinal);
+  if (!bufs.run) return;
+  const float* wsrc = pass == 0 ? w : nullptr;
+  const uint32_t* ksrc = bufs.ksrc;
+  const int32_t* vsrc = bufs.vsrc;
+  uint32_t* kdst = bufs.kdst;
+  int32_t* vdst = bufs.vdst;
+  const int shift = 8 * pass;
   __shared__ uint32_t skey[kRadixTile];
   __shared__ int32_t sval[kRadixTile];
   __shared__ uint32_t wcnt[NW][256];
@@ -211,12 +320,13 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
   const int rowbase = block_excl_scan<kScatterThreads, int>(owner ? (int)totals[tid] : 0, ish, &gt);
   uint32_t k[IPT];
   int32_t v[IPT];
-  int tile = blockIdx.x;
-  if (tile < ntiles) {
+  int tile, tend, tstep;
+  xcd_tiles(ntiles, &tile, &tend, &tstep);
+  if (tile < tend) {
     radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, tile, k, v);
     radix_raw_to_key<IPT>(wsrc, k);
   }
-  for (; tile < ntiles; tile += gridDim.x) {
+  for (; tile < tend; tile += tstep) {
     const int64_t base = (int64_t)tile * kRadixTile;
     const int nt = (int)min((int64_t)kRadixTile, n - base);
     const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
@@ -224,8 +334,8 @@ __global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(const floa
     // the next tile's items are in flight while this one is ranked and written
     uint32_t kn[IPT];
     int32_t vn[IPT];
-    const int next = tile + (int)gridDim.x;
-    if (next < ntiles) radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, next, kn, vn);
+    const int next = tile + tstep;
+    if (next < tend) radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, next, kn, vn);
     for (int j = lane; j < 256; j += kWave) wcnt[wv][j] = 0u;
     uint16_t rk[IPT];
 #pragma unroll

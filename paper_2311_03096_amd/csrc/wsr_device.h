@@ -127,6 +127,15 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   const uint32_t m = wave_incl_scan_op(v, 0xFFFFFFFFu, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
   return (uint32_t)__builtin_amdgcn_readlane((int)m, kWave - 1);
 }
+// Wave-uniform bitwise OR / AND.
+__device__ __forceinline__ uint32_t wave_or_u32(uint32_t v) {
+  const uint32_t m = wave_incl_scan_op(v, 0u, [](uint32_t a, uint32_t b) { return a | b; });
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, kWave - 1);
+}
+__device__ __forceinline__ uint32_t wave_and_u32(uint32_t v) {
+  const uint32_t m = wave_incl_scan_op(v, 0xFFFFFFFFu, [](uint32_t a, uint32_t b) { return a & b; });
+  return (uint32_t)__builtin_amdgcn_readlane((int)m, kWave - 1);
+}
 
 // Block-wide exclusive scan; sh must hold NT/64 + 1 values.  Every thread of the block must call.
 // Summation order is fixed (waves in order), so results are deterministic.  TRAIL = false leaves
