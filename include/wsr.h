@@ -69,8 +69,8 @@ extern "C" {
 #define WSR_ERR_HIP (-3)
 #define WSR_ERR_UNSUPPORTED (-4)
 
-/* longest supported segment (elements) */
-#define WSR_MAX_SEGMENT ((int64_t)1 << 26)
+/* longest supported segment (elements): 2^27, above the paper's largest layers (~1e8 weights) */
+#define WSR_MAX_SEGMENT ((int64_t)1 << 27)
 
 /* Library version as 10000*major + 100*minor + patch. */
 WSR_API int wsr_version(void);

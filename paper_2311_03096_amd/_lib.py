@@ -20,7 +20,7 @@ WSR_PLAN_MERGE_HULL = 2
 WSR_PLAN_MERGE_END = 4
 WSR_STATUS_NONFINITE = 1
 WSR_STEP_ETA_IN_DISPLACEMENT = 1
-WSR_MAX_SEGMENT = 1 << 26
+WSR_MAX_SEGMENT = 1 << 27
 WSR_NOALLOC_SCRATCH_BYTES = 64 << 20
 WSR_NOALLOC_MAX_SEGMENT = 1 << 21
 

@@ -59,11 +59,61 @@ int validate_offsets(const int64_t* h_offsets, int64_t n_seg, int64_t* max_big) 
   return WSR_OK;
 }
 
-// Workspace of the long-segment path for segments of length <= d.
+// Host description of a set of long segments solved by one launch sequence: the per-segment
+// records (element, radix-tile and hull-tile bases) and the set's totals.
+struct LongSetHost {
+  std::vector<LongSeg> segs;
+  int64_t elems = 0;  // workspace elements (each segment's base aligned to 64 elements)
+  int nrt = 0, nt = 0;
+  int max_nt = 0;
+  int max_nlev = 0;
+};
+
+int levels_of(int nt) {
+  int nlev = 0;
+  while ((1 << nlev) < nt) ++nlev;
+  return nlev;
+}
+
+// The set of the long segments `ids` of these offsets (ids in order).
+LongSetHost make_set(const int64_t* h_offsets, const std::vector<int32_t>& ids) {
+  LongSetHost hs;
+  for (int32_t id : ids) {
+    LongSeg g{};
+    g.start = h_offsets[id];
+    g.d = h_offsets[id + 1] - g.start;
+    g.ebase = hs.elems;
+    g.rbase = hs.nrt;
+    g.nrt = (int)ceil_div(g.d, kRadixTile);
+    g.tbase = hs.nt;
+    g.nt = (int)ceil_div(g.d, kBigTile);
+    g.seg_id = id;
+    g.nlev = levels_of(g.nt);
+    hs.elems += (g.d + 63) / 64 * 64;
+    hs.nrt += g.nrt;
+    hs.nt += g.nt;
+    hs.max_nt = std::max(hs.max_nt, g.nt);
+    hs.max_nlev = std::max(hs.max_nlev, g.nlev);
+    hs.segs.push_back(g);
+  }
+  return hs;
+}
+
+// A set passed by value: one segment, no device tables.
+LongSet single_set(const LongSetHost& hs) {
+  LongSet set{};
+  set.one = hs.segs[0];
+  set.nsegs = 1;
+  set.nrt = hs.nrt;
+  set.nt = hs.nt;
+  return set;
+}
+
+// Workspace of the long-segment path for one set: element arrays over all its segments,
+// radix-tile and hull-tile arrays over all its tiles, per-segment records.
 struct BigWs {
-  uint32_t* flags;
-  float* lamtmp;   // a segment's lambda formed on the device (proximal-gradient step)
-  uint32_t* tbad;  // per radix tile: non-finite weight seen (first pass)
+  uint32_t* flags;       // kSegFlagWords per segment: [0] non-finite weight seen, [1] varying key bits
+  uint32_t* tbad;        // per radix tile: non-finite weight seen (first pass)
   uint32_t *tor, *tand;  // per radix tile: OR and AND of its keys (first pass)
   uint32_t *keysA, *keysB;
   int32_t *valsA, *valsB;
@@ -72,34 +122,31 @@ struct BigWs {
   double* vS;
   uint16_t* hbits;  // per tile and thread: hull-vertex bits of the thread's ranks
   int32_t *hcnt, *lo, *hi, *prev_pos, *next_pos;
-  double *tsum, *tileoff, *prev_s, *next_s;
+  double *tsum, *tileoff, *prev_s, *next_s, *prev_sl, *next_sl;
   // backward
   int32_t *fpos, *lpos;
   double *fG, *lG, *prevG, *nextG;
   size_t bytes;
 };
 
-BigWs big_layout(int64_t d, void* base) {
+BigWs big_layout(int64_t elems, int64_t nrt, int64_t nt, int64_t nsegs, void* base) {
   BigWs w{};
-  const int64_t nrt = ceil_div(d, kRadixTile);
-  const int64_t nt = ceil_div(d, kBigTile);
   size_t off = 0;
   auto take = [&](size_t bytes) -> void* {
     void* p = base ? (void*)((char*)base + off) : nullptr;
     off += align_up(bytes);
     return p;
   };
-  w.flags = (uint32_t*)take(256);  // [0] non-finite weight seen, [1] key bits that vary
-  w.lamtmp = (float*)take(256);
+  w.flags = (uint32_t*)take(sizeof(uint32_t) * kSegFlagWords * nsegs);
   w.tbad = (uint32_t*)take(sizeof(uint32_t) * nrt);
   w.tor = (uint32_t*)take(sizeof(uint32_t) * nrt);
   w.tand = (uint32_t*)take(sizeof(uint32_t) * nrt);
-  w.keysA = (uint32_t*)take(sizeof(uint32_t) * d);
-  w.keysB = (uint32_t*)take(sizeof(uint32_t) * d);
-  w.valsA = (int32_t*)take(sizeof(int32_t) * d);
-  w.valsB = (int32_t*)take(sizeof(int32_t) * d);
+  w.keysA = (uint32_t*)take(sizeof(uint32_t) * elems);
+  w.keysB = (uint32_t*)take(sizeof(uint32_t) * elems);
+  w.valsA = (int32_t*)take(sizeof(int32_t) * elems);
+  w.valsB = (int32_t*)take(sizeof(int32_t) * elems);
   w.hist = (uint32_t*)take(sizeof(uint32_t) * 256 * nrt);
-  w.totals = (uint32_t*)take(sizeof(uint32_t) * 256);
+  w.totals = (uint32_t*)take(sizeof(uint32_t) * 256 * nsegs);
   w.vpos = (int32_t*)take(sizeof(int32_t) * nt * (kBigTile + 1));
   w.vS = (double*)take(sizeof(double) * nt * (kBigTile + 1));
   w.hbits = (uint16_t*)take(sizeof(uint16_t) * nt * kBigThreads);
@@ -112,6 +159,8 @@ BigWs big_layout(int64_t d, void* base) {
   w.tileoff = (double*)take(sizeof(double) * nt);
   w.prev_s = (double*)take(sizeof(double) * nt);
   w.next_s = (double*)take(sizeof(double) * nt);
+  w.prev_sl = (double*)take(sizeof(double) * nt);
+  w.next_sl = (double*)take(sizeof(double) * nt);
   w.fpos = (int32_t*)take(sizeof(int32_t) * nt);
   w.lpos = (int32_t*)take(sizeof(int32_t) * nt);
   w.fG = (double*)take(sizeof(double) * nt);
@@ -121,8 +170,50 @@ BigWs big_layout(int64_t d, void* base) {
   w.bytes = off;
   return w;
 }
+BigWs big_layout(const LongSetHost& hs, void* base) {
+  return big_layout(hs.elems, hs.nrt, hs.nt, (int64_t)hs.segs.size(), base);
+}
 
-size_t big_bytes(int64_t max_big) { return max_big > 0 ? big_layout(max_big, nullptr).bytes : 0; }
+// Workspace of one segment of length d (the segments of a plain call are solved one after another).
+size_t big_bytes(int64_t max_big) {
+  if (max_big <= 0) return 0;
+  return big_layout((max_big + 63) / 64 * 64, ceil_div(max_big, kRadixTile), ceil_div(max_big, kBigTile), 1,
+                    nullptr).bytes;
+}
+size_t set_bytes(const LongSetHost& hs) { return hs.segs.empty() ? 0 : big_layout(hs, nullptr).bytes; }
+
+// Launches of the merge levels done in LDS (k_big_merge): levels [lvl_lo, lvl_hi] with groups of
+// up to 2^lvl_hi tiles; the merge groups of each launch over the segments of a set (a segment
+// takes part while it has levels left, and a segment of one tile takes part in the first launch
+// only, to write its previous / next vertices).  Levels above kMergeLevelsInLds (segments of more
+// than 2^14 tiles) are done by k_big_merge_top.
+struct MergeLaunch {
+  int lvl_lo, lvl_hi, gmax;
+  std::vector<MergeGroup> groups;
+};
+std::vector<MergeLaunch> merge_launches(const LongSetHost& hs) {
+  std::vector<MergeLaunch> out;
+  const int top = std::min(std::max(hs.max_nlev, 1), kMergeLevelsInLds);
+  for (int lo = 1; lo <= top; lo += kMergeLevelsPerLaunch) {
+    MergeLaunch L;
+    L.lvl_lo = lo;
+    L.lvl_hi = std::min(lo + kMergeLevelsPerLaunch - 1, kMergeLevelsInLds);
+    int gmax = 1;
+    for (size_t si = 0; si < hs.segs.size(); ++si) {
+      const LongSeg& g = hs.segs[si];
+      if (lo > std::max(g.nlev, 1) || (g.nlev == 0 && lo > 1)) continue;
+      const int lh = std::min(L.lvl_hi, g.nlev);
+      const int G = 1 << lh;
+      gmax = std::max(gmax, G);
+      const int fin = lh == g.nlev ? 1 : 0;
+      for (int gb = 0; gb < g.nt; gb += G)
+        L.groups.push_back(MergeGroup{(int)si, g.tbase + gb, std::min(G, g.nt - gb), lh, fin});
+    }
+    L.gmax = gmax;
+    if (!L.groups.empty()) out.push_back(L);
+  }
+  return out;
+}
 
 int last_error() { return hipGetLastError() == hipSuccess ? WSR_OK : WSR_ERR_HIP; }
 
@@ -240,116 +331,178 @@ bool l1_args_ok(float beta, float rho) {
 // contiguous share of the tiles).
 int radix_grid(int ntiles, int maxg) { return (std::min(ntiles, maxg) + 7) / 8 * 8; }
 
-// Stable LSD radix sort of one long segment (up to 4 passes of 8 bits; a later pass whose digit
-// is the same for every key is skipped on the device): sorted keys end in b.keysA, the
-// permutation in perm_final; b.flags[0] gets the non-finite bit, b.flags[1] the varying key bits.
-void big_sort(const float* wseg, int64_t d, const BigWs& b, int32_t* perm_final, hipStream_t s) {
-  const int nrt = (int)ceil_div(d, kRadixTile);
+// Device tables of a set built once with a plan (segment records, tile -> segment maps, merge
+// groups per launch, the segments that need the top merge level).
+struct SetTables {
+  LongSet set{};
+  std::vector<MergeLaunch> launches;  // host copies; groups_dev[i] holds launches[i].groups
+  std::vector<MergeGroup*> groups_dev;
+  int32_t* top_dev = nullptr;
+  int ntop = 0;
+};
+
+// Launch context of one set: the set, its host description and (plans) its device tables.
+struct SetRun {
+  LongSet set;
+  const LongSetHost* hs;
+  const SetTables* tab;  // null: a single segment, groups computed in the kernels
+};
+
+// Stable LSD radix sort of every segment of the set (up to 4 passes of 8 bits; a later pass whose
+// digit is the same for every key of a segment is skipped for it on the device): sorted keys end
+// in b.keysA (at each segment's element base), the permutation in saved_perm (flat, segment
+// ranks) or in b.valsA; b.flags gets each segment's non-finite bit and varying key bits.  In the
+// first pass the input is w, or fmaf(-eta, grad, w) when grad is given.
+void big_sort(const SetRun& r, const float* w, const float* grad, float eta, const BigWs& b, int32_t* saved_perm,
+              hipStream_t s) {
+  const int nrt = r.set.nrt;
+  const int nsegs = r.set.nsegs;
   for (int pass = 0; pass < 4; ++pass) {
+    const dim3 hgrid(radix_grid(nrt, hist_grid())), sgrid(radix_grid(nrt, scatter_grid()));
     { WSR_TRACE("radix_hist", s);
-    hipLaunchKernelGGL(k_radix_hist, dim3(radix_grid(nrt, hist_grid())), dim3(kRadixThreads), 0, s, pass, wseg,
-                       b.keysA, b.keysB, b.valsA, b.valsB, perm_final, d, b.hist, nrt, b.tbad, b.tor, b.tand,
-                       b.flags); }
+    if (grad)
+      hipLaunchKernelGGL(k_radix_hist<true>, hgrid, dim3(kRadixThreads), 0, s, pass, r.set, w, grad, eta, b.keysA,
+                         b.keysB, b.valsA, b.valsB, saved_perm, b.hist, b.tbad, b.tor, b.tand, b.flags);
+    else
+      hipLaunchKernelGGL(k_radix_hist<false>, hgrid, dim3(kRadixThreads), 0, s, pass, r.set, w, grad, eta, b.keysA,
+                         b.keysB, b.valsA, b.valsB, saved_perm, b.hist, b.tbad, b.tor, b.tand, b.flags); }
     { WSR_TRACE("radix_rowscan", s);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(256), 0, s, pass, b.hist, nrt, b.totals, b.tbad, b.tor,
-                       b.tand, b.flags); }
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(256, nsegs), dim3(256), 0, s, pass, r.set, b.hist, b.totals, b.tbad,
+                       b.tor, b.tand, b.flags); }
     { WSR_TRACE("radix_scatter", s);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(radix_grid(nrt, scatter_grid())), dim3(kScatterThreads), 0, s, pass,
-                       wseg, b.keysA, b.keysB, b.valsA, b.valsB, perm_final, d, b.hist, b.totals, nrt, b.flags); }
+    if (grad)
+      hipLaunchKernelGGL(k_radix_scatter<true>, sgrid, dim3(kScatterThreads), 0, s, pass, r.set, w, grad, eta,
+                         b.keysA, b.keysB, b.valsA, b.valsB, saved_perm, b.hist, b.totals, b.flags);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<false>, sgrid, dim3(kScatterThreads), 0, s, pass, r.set, w, grad, eta,
+                         b.keysA, b.keysB, b.valsA, b.valsB, saved_perm, b.hist, b.totals, b.flags); }
   }
 }
 
-// Forward of one long segment [start, start + d).
-int big_forward(const float* w, float* out, int64_t start, int64_t d, const float* lam_arr, int seg_id,
-                float lam_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s,
-                const L1Opt& l1, int rounds = -1, uint32_t* status = nullptr) {
-  BigWs b = big_layout(d, ws);
-  const int nt = (int)ceil_div(d, kBigTile);
-  int32_t* perm_final = saved_perm ? saved_perm + start : b.valsA;
-  big_sort(w + start, d, b, perm_final, s);
-  { WSR_TRACE("big_tile_hull", s);
-  hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, lam_arr, seg_id,
-                     lam_scalar, b.vpos, b.vS, b.hcnt, b.tsum, b.hbits, rounds); }
-  { WSR_TRACE("big_tile_scan", s);
-#define WSR_LAUNCH_TILE_SCAN(CM)                                                                         \
-  hipLaunchKernelGGL(k_big_tile_scan<CM>, dim3(1), dim3(1024), 0, s, b.tsum, b.tileoff, b.hcnt, b.lo, b.hi, nt, \
-                     d, lam_arr, seg_id, lam_scalar)
-  if (nt <= 4 * 1024)
-    WSR_LAUNCH_TILE_SCAN(4);
-  else if (nt <= 8 * 1024)
-    WSR_LAUNCH_TILE_SCAN(8);
-  else
-    WSR_LAUNCH_TILE_SCAN(16);
-#undef WSR_LAUNCH_TILE_SCAN
-  }
-  int nlev = 0;
-  while ((1 << nlev) < nt) ++nlev;
-  int lvl_lo = 1;
-  do {
-    const int lvl_hi = std::min(lvl_lo + kMergeLevelsPerLaunch - 1, nlev);
-    const int G = 1 << lvl_hi;
-    const int groups = (int)ceil_div(nt, G);
-    const int fin = lvl_hi == nlev ? 1 : 0;
-    if (G > kMergeGroupMax) return WSR_ERR_UNSUPPORTED;
+// Tile scans hold CM tiles per thread.
+int scan_cm(int max_nt) { return max_nt <= 4 * 1024 ? 4 : max_nt <= 8 * 1024 ? 8 : max_nt <= 16 * 1024 ? 16 : 32; }
+
+// Merge levels of every segment of the set: the LDS levels, then the top level for segments of
+// more than 2^14 tiles.
+void big_merges(const SetRun& r, const BigWs& b, hipStream_t s) {
+  std::vector<MergeLaunch> local;
+  const std::vector<MergeLaunch>* launches = r.tab ? &r.tab->launches : &local;
+  if (!r.tab) local = merge_launches(*r.hs);
+  for (size_t i = 0; i < launches->size(); ++i) {
+    const MergeLaunch& L = (*launches)[i];
+    const MergeGroup* groups = r.tab ? r.tab->groups_dev[i] : nullptr;
+    const int grid = (int)L.groups.size();
     WSR_TRACE("big_merge", s);
-#define WSR_LAUNCH_MERGE(GM)                                                                             \
-  hipLaunchKernelGGL((k_big_merge<GM, kMergeRecMax>), dim3(groups), dim3(kMergeThreads), 0, s, lvl_lo, lvl_hi, \
-                     nt, b.vpos, b.vS, b.tileoff, b.lo, b.hi, fin, b.prev_pos, b.prev_s, b.next_pos, b.next_s)
-    if (G <= 16)
+#define WSR_LAUNCH_MERGE(GM)                                                                                \
+  hipLaunchKernelGGL((k_big_merge<GM, kMergeRecMax>), dim3(grid), dim3(kMergeThreads), 0, s, L.lvl_lo, L.lvl_hi, \
+                     r.set, groups, b.vpos, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s, b.next_pos, b.next_s, \
+                     b.prev_sl, b.next_sl)
+    if (L.gmax <= 16)
       WSR_LAUNCH_MERGE(16);
-    else if (G <= 256)
+    else if (L.gmax <= 256)
       WSR_LAUNCH_MERGE(256);
-    else if (G <= 4096)
+    else if (L.gmax <= 4096)
       WSR_LAUNCH_MERGE(4096);
     else
       WSR_LAUNCH_MERGE(16384);
 #undef WSR_LAUNCH_MERGE
-    lvl_lo = lvl_hi + 1;
-  } while (lvl_lo <= nlev);
+  }
+  int ntop = 0;
+  const int32_t* top = nullptr;
+  if (r.tab) {
+    ntop = r.tab->ntop;
+    top = r.tab->top_dev;
+  } else {
+    ntop = r.hs->segs[0].nlev > kMergeLevelsInLds ? 1 : 0;
+  }
+  if (ntop > 0) {
+    WSR_TRACE("big_merge_top", s);
+    hipLaunchKernelGGL(k_big_merge_top, dim3(ntop), dim3(kTopThreads), 0, s, r.set, top, b.vpos, b.vS, b.tileoff,
+                       b.lo, b.hi, b.prev_pos, b.prev_s, b.next_pos, b.next_s, b.prev_sl, b.next_sl);
+  }
+}
+
+// Forward of every segment of the set (in place allowed: every read of w and grad happens in the
+// sort's first pass, before any output is written).
+int big_forward(const SetRun& r, const float* w, const float* grad, float eta, float* out, LamArgs lam,
+                int32_t* saved_perm, uint32_t* saved_mask, void* ws, hipStream_t s, const L1Opt& l1,
+                int rounds = -1, uint32_t* status = nullptr) {
+  BigWs b = big_layout(*r.hs, ws);
+  big_sort(r, w, grad, eta, b, saved_perm, s);
+  const int nt = r.set.nt;
+  const int nsegs = r.set.nsegs;
+  { WSR_TRACE("big_tile_hull", s);
+  hipLaunchKernelGGL(k_big_tile_hull, dim3(nt), dim3(kBigThreads), 0, s, r.set, b.keysA, lam, b.vpos, b.vS, b.hcnt,
+                     b.tsum, b.hbits, rounds); }
+  { WSR_TRACE("big_tile_scan", s);
+#define WSR_LAUNCH_TILE_SCAN(CM)                                                                          \
+  hipLaunchKernelGGL(k_big_tile_scan<CM>, dim3(nsegs), dim3(1024), 0, s, r.set, b.tsum, b.tileoff, b.hcnt, b.lo, \
+                     b.hi, lam)
+  switch (scan_cm(r.hs->max_nt)) {
+    case 4: WSR_LAUNCH_TILE_SCAN(4); break;
+    case 8: WSR_LAUNCH_TILE_SCAN(8); break;
+    case 16: WSR_LAUNCH_TILE_SCAN(16); break;
+    default: WSR_LAUNCH_TILE_SCAN(32); break;
+  }
+#undef WSR_LAUNCH_TILE_SCAN
+  }
+  big_merges(r, b, s);
   { WSR_TRACE("big_apply", s);
-  hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, perm_final, d, lam_arr, seg_id,
-                     lam_scalar, b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s,
-                     b.next_pos, b.next_s, out, saved_mask, start, l1.beta, l1.rho, l1.kappa, l1.on, status); }
+  hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, r.set, b.keysA, saved_perm, b.valsA, lam,
+                     b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s, b.next_pos, b.next_s,
+                     b.prev_sl, b.next_sl, out, saved_mask, l1.beta, l1.rho, l1.kappa, l1.on, status); }
   return last_error();
 }
 
-int big_backward(const float* g, float* gw, int64_t start, int64_t d, const int32_t* perm,
-                 const uint32_t* mask, void* ws, hipStream_t s) {
-  BigWs b = big_layout(d, ws);
-  const int nt = (int)ceil_div(d, kBigTile);
+int big_backward(const SetRun& r, const float* g, float* gw, const int32_t* perm, const uint32_t* mask, void* ws,
+                 hipStream_t s) {
+  BigWs b = big_layout(*r.hs, ws);
+  const int nt = r.set.nt;
   float* gsorted = (float*)b.keysA;
   { WSR_TRACE("big_bwd_tile", s);
-  hipLaunchKernelGGL(k_big_bwd_tile, dim3(nt), dim3(kBigThreads), 0, s, g, perm + start, mask, d, start,
-                     gsorted, b.tsum, b.fpos, b.fG, b.lpos, b.lG); }
+  hipLaunchKernelGGL(k_big_bwd_tile, dim3(nt), dim3(kBigThreads), 0, s, r.set, g, perm, mask, gsorted, b.tsum,
+                     b.fpos, b.fG, b.lpos, b.lG); }
   { WSR_TRACE("big_bwd_scan", s);
-#define WSR_LAUNCH_BWD_SCAN(CM)                                                                          \
-  hipLaunchKernelGGL(k_big_bwd_scan<CM>, dim3(1), dim3(1024), 0, s, b.tsum, b.fpos, b.fG, b.lpos, b.lG, nt, d, \
-                     b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG)
-  if (nt <= 4 * 1024)
-    WSR_LAUNCH_BWD_SCAN(4);
-  else if (nt <= 8 * 1024)
-    WSR_LAUNCH_BWD_SCAN(8);
-  else
-    WSR_LAUNCH_BWD_SCAN(16);
+#define WSR_LAUNCH_BWD_SCAN(CM)                                                                           \
+  hipLaunchKernelGGL(k_big_bwd_scan<CM>, dim3(r.set.nsegs), dim3(1024), 0, s, r.set, b.tsum, b.fpos, b.fG, b.lpos, \
+                     b.lG, b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG)
+  switch (scan_cm(r.hs->max_nt)) {
+    case 4: WSR_LAUNCH_BWD_SCAN(4); break;
+    case 8: WSR_LAUNCH_BWD_SCAN(8); break;
+    case 16: WSR_LAUNCH_BWD_SCAN(16); break;
+    default: WSR_LAUNCH_BWD_SCAN(32); break;
+  }
 #undef WSR_LAUNCH_BWD_SCAN
   }
   { WSR_TRACE("big_bwd_apply", s);
-  hipLaunchKernelGGL(k_big_bwd_apply, dim3(nt), dim3(kBigThreads), 0, s, gsorted, perm + start, mask, d,
-                     start, b.tileoff, b.prev_pos, b.prevG, b.next_pos, b.nextG, gw); }
+  hipLaunchKernelGGL(k_big_bwd_apply, dim3(nt), dim3(kBigThreads), 0, s, r.set, gsorted, perm, mask, b.tileoff,
+                     b.prev_pos, b.prevG, b.next_pos, b.nextG, gw); }
   return last_error();
 }
 
-// Statistics of one long segment: the sort, then the tile partials and their fixed-order sum.
-int big_stats(const float* w, int64_t start, int64_t d, SegStats* out, void* ws, hipStream_t s) {
-  BigWs b = big_layout(d, ws);
-  const int nt = (int)ceil_div(d, kBigTile);
-  big_sort(w + start, d, b, b.valsA, s);
+// Statistics of every segment of the set: the sort, then the tile partials and their fixed-order
+// sum per segment (records at the segments' ids).
+int big_stats(const SetRun& r, const float* w, SegStats* out, void* ws, hipStream_t s) {
+  BigWs b = big_layout(*r.hs, ws);
+  big_sort(r, w, nullptr, 0.0f, b, nullptr, s);
   { WSR_TRACE("big_stats_tile", s);
-  hipLaunchKernelGGL(k_big_stats_tile, dim3(nt), dim3(kBigThreads), 0, s, b.keysA, d, b.tsum, b.hcnt, b.lo); }
+  hipLaunchKernelGGL(k_big_stats_tile, dim3(r.set.nt), dim3(kBigThreads), 0, s, r.set, b.keysA, b.tsum, b.hcnt,
+                     b.lo); }
   { WSR_TRACE("big_stats_final", s);
-  hipLaunchKernelGGL(k_big_stats_final, dim3(1), dim3(1024), 0, s, b.tsum, b.hcnt, b.lo, nt, d, b.flags, out); }
+  hipLaunchKernelGGL(k_big_stats_final, dim3(r.set.nsegs), dim3(1024), 0, s, r.set, b.tsum, b.hcnt, b.lo, b.flags,
+                     out); }
   return last_error();
 }
+
+// One long segment of a plain call, solved on its own.
+struct OneSeg {
+  LongSetHost hs;
+  SetRun run;
+  OneSeg(const int64_t* h_offsets, int32_t id) : hs(make_set(h_offsets, {id})) {
+    run = SetRun{single_set(hs), &hs, nullptr};
+  }
+  OneSeg(const OneSeg&) = delete;
+};
 
 void small_stats(int cls, int nblocks, const SegArgs& a, const float* w, SegStats* st, hipStream_t s) {
   switch (cls) {
@@ -371,7 +524,6 @@ static_assert(sizeof(SegStats) == sizeof(wsr_segment_stats_t), "stats layout");
 struct wsr_plan {
   int64_t n_seg = 0;
   int64_t total = 0;
-  int64_t max_big = 0;
   int device = 0;
   int64_t* d_offsets = nullptr;
   int32_t* d_sched = nullptr;                // all small schedules back to back
@@ -386,7 +538,64 @@ struct wsr_plan {
   int rounds[kNumSmall + 1] = {kIcaRounds, kIcaRounds, kIcaRounds, kIcaRounds};
   int small_route(int c) const { return rounds[c] >= 0 ? rounds[c] : kRouteEnd; }
   uint32_t* d_status = nullptr;  // sticky status word (kStatusNonFinite), read by wsr_read_status
+  // the long segments as one set, solved by one launch sequence; its device tables live in d_tables
+  LongSetHost longs;
+  SetTables tab;
+  void* d_tables = nullptr;
+  SetRun long_run() const { return SetRun{tab.set, &longs, &tab}; }
 };
+
+namespace {
+
+// Device tables of the plan's long segments (one allocation, at plan creation): the segment
+// records, the radix-tile and hull-tile -> segment maps, the merge groups of every launch and the
+// segments that need the top merge level.
+int build_set_tables(wsr_plan* p) {
+  const LongSetHost& hs = p->longs;
+  if (hs.segs.empty()) return WSR_OK;
+  SetTables& t = p->tab;
+  t.launches = merge_launches(hs);
+  std::vector<int32_t> rseg(hs.nrt), hseg(hs.nt), top;
+  for (size_t si = 0; si < hs.segs.size(); ++si) {
+    const LongSeg& g = hs.segs[si];
+    for (int i = 0; i < g.nrt; ++i) rseg[g.rbase + i] = (int32_t)si;
+    for (int i = 0; i < g.nt; ++i) hseg[g.tbase + i] = (int32_t)si;
+    if (g.nlev > kMergeLevelsInLds) top.push_back((int32_t)si);
+  }
+  // one buffer: segments, rseg, hseg, top list, then each launch's groups (256-byte aligned parts)
+  std::vector<size_t> parts = {sizeof(LongSeg) * hs.segs.size(), sizeof(int32_t) * rseg.size(),
+                               sizeof(int32_t) * hseg.size(), sizeof(int32_t) * std::max<size_t>(top.size(), 1)};
+  for (const MergeLaunch& L : t.launches) parts.push_back(sizeof(MergeGroup) * L.groups.size());
+  size_t total = 0;
+  std::vector<size_t> at;
+  for (size_t b : parts) {
+    at.push_back(total);
+    total += align_up(b);
+  }
+  std::vector<char> host(total, 0);
+  auto put = [&](int i, const void* src, size_t n) { if (n) std::memcpy(host.data() + at[i], src, n); };
+  put(0, hs.segs.data(), parts[0]);
+  put(1, rseg.data(), parts[1]);
+  put(2, hseg.data(), parts[2]);
+  put(3, top.data(), sizeof(int32_t) * top.size());
+  for (size_t i = 0; i < t.launches.size(); ++i) put(4 + (int)i, t.launches[i].groups.data(), parts[4 + i]);
+  if (hipMalloc(&p->d_tables, total) != hipSuccess) return WSR_ERR_HIP;
+  if (hipMemcpy(p->d_tables, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return WSR_ERR_HIP;
+  char* base = (char*)p->d_tables;
+  t.set = LongSet{};
+  t.set.segs = (const LongSeg*)(base + at[0]);
+  t.set.rseg = (const int32_t*)(base + at[1]);
+  t.set.hseg = (const int32_t*)(base + at[2]);
+  t.set.nsegs = (int)hs.segs.size();
+  t.set.nrt = hs.nrt;
+  t.set.nt = hs.nt;
+  t.top_dev = (int32_t*)(base + at[3]);
+  t.ntop = (int)top.size();
+  for (size_t i = 0; i < t.launches.size(); ++i) t.groups_dev.push_back((MergeGroup*)(base + at[4 + i]));
+  return WSR_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -437,7 +646,9 @@ int forward_impl(const float* w, float* out, const int64_t* h_offsets, int64_t n
     const int cls = size_class(d);
     if (cls == kSkip) continue;
     if (cls == kBig) {
-      rc = big_forward(w, out, start, d, nullptr, 0, lambda, saved_perm, saved_mask, ws, s, l1);
+      const OneSeg one(h_offsets, (int32_t)seg);
+      rc = big_forward(one.run, w, nullptr, 0.0f, out, LamArgs{nullptr, lambda, 1.0f}, saved_perm, saved_mask, ws, s,
+                       l1);
       if (rc) return rc;
       continue;
     }
@@ -454,7 +665,7 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
   if (!plan || !w || !out) return WSR_ERR_INVALID;
   if ((saved_perm == nullptr) != (saved_mask == nullptr)) return WSR_ERR_INVALID;
   if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
-  const size_t need = big_bytes(plan->max_big);
+  const size_t need = set_bytes(plan->longs);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (saved_mask && !plan->word_aligned) zero_words(saved_mask, ceil_div(plan->total, 32), s);
@@ -466,11 +677,9 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
     a.status = plan->d_status;
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
-  for (int32_t seg : plan->big_segs) {
-    const int64_t start = plan->h_offsets[seg];
-    const int64_t d = plan->h_offsets[seg + 1] - start;
-    const int rc = big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, saved_perm, saved_mask, ws, s, l1,
-                               plan->rounds[kNumSmall], plan->d_status);
+  if (!plan->longs.segs.empty()) {
+    const int rc = big_forward(plan->long_run(), w, nullptr, 0.0f, out, LamArgs{d_lambda, lambda_scalar, 1.0f},
+                               saved_perm, saved_mask, ws, s, l1, plan->rounds[kNumSmall], plan->d_status);
     if (rc) return rc;
   }
   return last_error();
@@ -495,7 +704,7 @@ int step_args_ok(const wsr_plan* plan, const float* w, const float* grad, float 
   if (flags & ~WSR_STEP_ETA_IN_DISPLACEMENT) return WSR_ERR_INVALID;
   if (!std::isfinite(eta) || eta < 0.0f || !l1_args_ok(beta, rho)) return WSR_ERR_INVALID;
   if (!d_alpha && (!std::isfinite(alpha_scalar) || alpha_scalar < 0.0f)) return WSR_ERR_INVALID;
-  const size_t need = big_bytes(plan->max_big);
+  const size_t need = set_bytes(plan->longs);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   return WSR_OK;
 }
@@ -508,29 +717,12 @@ void step_small(const wsr_plan* plan, int c, int nblocks, int route, const float
   small_fwd(c, nblocks, a, w, out, nullptr, nullptr, s);
 }
 
-// One long segment of the step: z = fmaf(-eta, grad, w) into out, then the device-wide path in place.
-int step_big(const wsr_plan* plan, int32_t seg, int rounds, const float* w, const float* grad, float eta, float* out,
+// The long segments of the step, as one set: the sort's first pass reads fmaf(-eta, grad, w), so
+// the gradient step costs no pass of its own; lambda = alpha_s * lam_mul on the device.
+int step_big(const wsr_plan* plan, int rounds, const float* w, const float* grad, float eta, float* out,
              const float* d_alpha, float alpha_scalar, const StepForm& f, void* ws, hipStream_t s) {
-  const int64_t start = plan->h_offsets[seg];
-  const int64_t d = plan->h_offsets[seg + 1] - start;
-  {
-    WSR_TRACE("grad_step", s);
-    const int64_t blocks = std::min<int64_t>(ceil_div(d, 256), 4 * (int64_t)cu_count());
-    hipLaunchKernelGGL(k_grad_step, dim3((unsigned)blocks), dim3(256), 0, s, out + start, w + start,
-                       grad + start, eta, d);
-  }
-  const float* lam_arr = d_alpha;
-  int lam_seg = seg;
-  const float lam_scalar = alpha_scalar * f.lam_mul;
-  if (d_alpha && f.lam_mul != 1.0f) {
-    BigWs b = big_layout(d, ws);
-    WSR_TRACE("scale_lambda", s);
-    hipLaunchKernelGGL(k_scale_lambda, dim3(1), dim3(64), 0, s, b.lamtmp, d_alpha, seg, alpha_scalar, f.lam_mul);
-    lam_arr = b.lamtmp;
-    lam_seg = 0;
-  }
-  return big_forward(out, out, start, d, lam_arr, lam_seg, lam_scalar, nullptr, nullptr, ws, s, f.l1, rounds,
-                     plan->d_status);
+  return big_forward(plan->long_run(), w, grad, eta, out, LamArgs{d_alpha, alpha_scalar, f.lam_mul}, nullptr, nullptr,
+                     ws, s, f.l1, rounds, plan->d_status);
 }
 
 int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, float eta, float* out,
@@ -546,8 +738,8 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
     step_small(plan, c, (int)plan->sched_cnt[c], plan->small_route(c), w, grad, eta, out, d_alpha, alpha_scalar, f,
                s);
   }
-  for (int32_t seg : plan->big_segs) {
-    rc = step_big(plan, seg, plan->rounds[kNumSmall], w, grad, eta, out, d_alpha, alpha_scalar, f, ws, s);
+  if (!plan->longs.segs.empty()) {
+    rc = step_big(plan, plan->rounds[kNumSmall], w, grad, eta, out, d_alpha, alpha_scalar, f, ws, s);
     if (rc) return rc;
   }
   return last_error();
@@ -556,9 +748,9 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
 // Autotuner core: for every short size class, times the batched launch of the class alone under
 // each candidate route and keeps the fastest; EndCollisions is a candidate only when a probe over
 // the class's first segments (one workgroup per CU pair) shows it no slower than 1.5x the default
-// route there.  Long segments: the caps {0, kIcaRounds, 16}, timed on the longest one.
+// route there.  Long segments: the caps {0, kIcaRounds, 16}, timed on all of them together.
 //   small(c, nblocks, route): launches class c over its first nblocks segments
-//   big(seg, rounds): runs long segment seg, returns a status
+//   big(rounds): runs the plan's long segments (one set), returns a status
 template <class SmallFn, class BigFn>
 int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
   hipEvent_t e0, e1;
@@ -602,17 +794,14 @@ int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
       }
     }
   }
-  if (rc == WSR_OK && !plan->big_segs.empty()) {
-    int32_t seg = plan->big_segs[0];
-    for (int32_t q : plan->big_segs)
-      if (plan->h_offsets[q + 1] - plan->h_offsets[q] > plan->h_offsets[seg + 1] - plan->h_offsets[seg]) seg = q;
+  if (rc == WSR_OK && !plan->longs.segs.empty()) {
     float best = 0.0f;
     bool first = true;
     for (int r : {0, kIcaRounds, 16}) {
       float ms = 0.0f;
       int lrc = WSR_OK;
       rc = time_it([&] {
-        const int e = big(seg, r);
+        const int e = big(r);
         if (e) lrc = e;
       }, kReps, &ms);
       if (!rc) rc = lrc;
@@ -704,7 +893,8 @@ int wsr_segment_stats(const float* w, const int64_t* h_offsets, int64_t n_seg, w
     const int cls = size_class(d);
     if (cls == kSkip) continue;
     if (cls == kBig) {
-      rc = big_stats(w, start, d, st + seg, ws, s);
+      const OneSeg one(h_offsets, (int32_t)seg);
+      rc = big_stats(one.run, w, st, ws, s);
       if (rc) return rc;
       continue;
     }
@@ -731,7 +921,8 @@ int wsr_prox_backward(const float* grad_out, float* grad_w, const int64_t* h_off
     const int cls = size_class(d);
     if (cls == kSkip) continue;
     if (cls == kBig) {
-      rc = big_backward(grad_out, grad_w, start, d, saved_perm, saved_mask, ws, s);
+      const OneSeg one(h_offsets, (int32_t)seg);
+      rc = big_backward(one.run, grad_out, grad_w, saved_perm, saved_mask, ws, s);
       if (rc) return rc;
       continue;
     }
@@ -752,7 +943,6 @@ int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan
   wsr_plan* p = new wsr_plan();
   p->n_seg = n_seg;
   p->total = h_offsets[n_seg];
-  p->max_big = mb;
   p->h_offsets.assign(h_offsets, h_offsets + n_seg + 1);
   p->word_aligned = offsets_word_aligned(h_offsets, n_seg);
   if (flags & WSR_PLAN_MERGE_HULL)
@@ -800,12 +990,14 @@ int wsr_plan_create(const int64_t* h_offsets, int64_t n_seg, int flags, wsr_plan
     if (hipMalloc(&p->d_sched, sizeof(int32_t) * sched.size()) != hipSuccess ||
         hipMemcpy(p->d_sched, sched.data(), sizeof(int32_t) * sched.size(), hipMemcpyHostToDevice) !=
             hipSuccess) {
-      (void)hipFree(p->d_offsets);
-      (void)hipFree(p->d_status);
-      if (p->d_sched) (void)hipFree(p->d_sched);
-      delete p;
+      (void)wsr_plan_destroy(p);
       return WSR_ERR_HIP;
     }
+  }
+  p->longs = make_set(h_offsets, p->big_segs);
+  if (build_set_tables(p) != WSR_OK) {
+    (void)wsr_plan_destroy(p);
+    return WSR_ERR_HIP;
   }
   *plan = p;
   return WSR_OK;
@@ -816,6 +1008,7 @@ int wsr_plan_destroy(wsr_plan* plan) {
   if (plan->d_offsets) (void)hipFree(plan->d_offsets);
   if (plan->d_sched) (void)hipFree(plan->d_sched);
   if (plan->d_status) (void)hipFree(plan->d_status);
+  if (plan->d_tables) (void)hipFree(plan->d_tables);
   delete plan;
   return WSR_OK;
 }
@@ -838,7 +1031,7 @@ int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear, void* stre
 
 int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes) {
   if (!plan || !bytes) return WSR_ERR_INVALID;
-  *bytes = big_bytes(plan->max_big);
+  *bytes = set_bytes(plan->longs);
   return WSR_OK;
 }
 
@@ -861,7 +1054,7 @@ int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d
   (void)hipGetLastError();  // report only errors of this call
   if (!plan || !w || !out || out == w) return WSR_ERR_INVALID;
   if (!d_lambda && (!std::isfinite(lambda_scalar) || lambda_scalar < 0.0f)) return WSR_ERR_INVALID;
-  const size_t need = big_bytes(plan->max_big);
+  const size_t need = set_bytes(plan->longs);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   return autotune_impl(
@@ -871,10 +1064,9 @@ int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d
         a.merge_rounds = route;
         small_fwd(c, nblocks, a, w, out, nullptr, nullptr, s);
       },
-      [&](int32_t seg, int rounds) {
-        const int64_t start = plan->h_offsets[seg];
-        const int64_t d = plan->h_offsets[seg + 1] - start;
-        return big_forward(w, out, start, d, d_lambda, seg, lambda_scalar, nullptr, nullptr, ws, s, L1Opt{}, rounds);
+      [&](int rounds) {
+        return big_forward(plan->long_run(), w, nullptr, 0.0f, out, LamArgs{d_lambda, lambda_scalar, 1.0f}, nullptr,
+                           nullptr, ws, s, L1Opt{}, rounds);
       },
       s);
 }
@@ -893,9 +1085,7 @@ int wsr_plan_autotune_step(wsr_plan* plan, const float* w, const float* grad, fl
       [&](int c, int nblocks, int route) {
         step_small(plan, c, nblocks, route, w, grad, eta, scratch, d_alpha, alpha_scalar, f, s);
       },
-      [&](int32_t seg, int rounds) {
-        return step_big(plan, seg, rounds, w, grad, eta, scratch, d_alpha, alpha_scalar, f, ws, s);
-      },
+      [&](int rounds) { return step_big(plan, rounds, w, grad, eta, scratch, d_alpha, alpha_scalar, f, ws, s); },
       s);
 }
 
@@ -925,7 +1115,7 @@ int wsr_segment_stats_batched(const wsr_plan* plan, const float* w, wsr_segment_
                               size_t ws_bytes, void* stream) {
   (void)hipGetLastError();  // report only errors of this call
   if (!plan || !w || !d_stats) return WSR_ERR_INVALID;
-  const size_t need = big_bytes(plan->max_big);
+  const size_t need = set_bytes(plan->longs);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   SegStats* st = reinterpret_cast<SegStats*>(d_stats);
@@ -935,10 +1125,8 @@ int wsr_segment_stats_batched(const wsr_plan* plan, const float* w, wsr_segment_
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], nullptr, 0.0f, 0, 0, 0};
     small_stats(c, (int)plan->sched_cnt[c], a, w, st, s);
   }
-  for (int32_t seg : plan->big_segs) {
-    const int64_t start = plan->h_offsets[seg];
-    const int64_t d = plan->h_offsets[seg + 1] - start;
-    const int rc = big_stats(w, start, d, st + seg, ws, s);
+  if (!plan->longs.segs.empty()) {
+    const int rc = big_stats(plan->long_run(), w, st, ws, s);
     if (rc) return rc;
   }
   return last_error();
@@ -949,7 +1137,7 @@ int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float
                               void* stream) {
   (void)hipGetLastError();  // report only errors of this call
   if (!plan || !grad_out || !grad_w || !saved_perm || !saved_mask || grad_out == grad_w) return WSR_ERR_INVALID;
-  const size_t need = big_bytes(plan->max_big);
+  const size_t need = set_bytes(plan->longs);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   for (int c = 0; c < kNumSmall; ++c) {
@@ -957,10 +1145,8 @@ int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], nullptr, 0.0f, 0, 0, 0};
     small_bwd(c, (int)plan->sched_cnt[c], a, grad_out, grad_w, saved_perm, saved_mask, s);
   }
-  for (int32_t seg : plan->big_segs) {
-    const int64_t start = plan->h_offsets[seg];
-    const int64_t d = plan->h_offsets[seg + 1] - start;
-    const int rc = big_backward(grad_out, grad_w, start, d, saved_perm, saved_mask, ws, s);
+  if (!plan->longs.segs.empty()) {
+    const int rc = big_backward(plan->long_run(), grad_out, grad_w, saved_perm, saved_mask, ws, s);
     if (rc) return rc;
   }
   return last_error();

@@ -1,4 +1,10 @@
 // wsr_big.h -- geometry and kernels of the long-segment (device-wide) path.
+//
+// The long segments of a call form a set that one launch sequence solves: every kernel covers
+// the tiles of all segments of the set, each tile knowing its segment from a tile -> segment
+// table (a single segment is passed by value, without tables).  Workspace arrays hold the
+// segments back to back: element arrays at the segment's element base, radix-tile and hull-tile
+// arrays at its tile bases, small per-segment records at its index.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -10,8 +16,9 @@ namespace wsr {
 constexpr int kRadixThreads = 256;   // histogram workgroup; the scatter's digit scan uses
                                      // one thread per digit
 constexpr int kRadixTile = 8192;     // keys per radix tile (digit runs average 32 keys)
-constexpr int kMaxRadixTiles = (1 << 26) / kRadixTile;  // radix tiles of the longest segment
-constexpr int kHistPerCu = 4;         // resident workgroups per CU of the persistent histogram
+constexpr int64_t kMaxLong = (int64_t)1 << 27;            // longest segment
+constexpr int kMaxRadixTiles = (int)(kMaxLong / kRadixTile);  // radix tiles of the longest segment
+constexpr int kHistPerCu = 3;         // resident workgroups per CU of the persistent histogram
 constexpr int kScatterThreads = 512;  // scatter workgroup (16 keys per thread)
 constexpr int kBigThreads = 256;
 constexpr int kBigE = 16;
@@ -20,57 +27,103 @@ constexpr int kApplySparseMax = 256;  // surviving hull vertices up to which a t
                                       // are read from the hull rather than recomputed
 constexpr int kMergeThreads = 512;  // one wave per merge
 constexpr int kMergeLevelsPerLaunch = 4;
-constexpr int kMergeGroupMax = 1 << 14;                         // tiles of the longest segment
+constexpr int kMergeGroupMax = 1 << 14;                         // tiles of one merge group in LDS
 constexpr int kMergeRecMax = 1 << (kMergeLevelsPerLaunch - 1);  // merges at a launch's first level
-static_assert((int64_t)kMergeGroupMax * kBigTile >= ((int64_t)1 << 26), "top merge group too small");
+constexpr int kMergeLevelsInLds = 14;                           // levels done by k_big_merge
+constexpr int kMaxHullTiles = (int)(kMaxLong / kBigTile);       // hull tiles of the longest segment
+constexpr int kTopThreads = 1024;                               // top merge level (k_big_merge_top)
+static_assert(kMergeGroupMax == 1 << kMergeLevelsInLds, "merge group of the LDS levels");
+static_assert(kMaxHullTiles == 2 * kMergeGroupMax, "one top level above the LDS merge groups");
 static_assert(kRadixThreads == 256, "one histogram bin per thread");
-static_assert(kMergeGroupMax / 1024 <= 16, "tile scans hold at most 16 tiles per thread");
+static_assert(kMaxHullTiles / 1024 <= 32, "tile scans hold at most 32 tiles per thread");
 static_assert(kScatterThreads >= 256, "digit scan assumes one digit per thread");
 
-__global__ void k_radix_hist(int pass, const float* wsrc, uint32_t* kA, uint32_t* kB, int32_t* vA, int32_t* vB,
-                             int32_t* vfinal, int64_t n, uint32_t* hist, int ntiles, uint32_t* tbad, uint32_t* tor,
-                             uint32_t* tand, const uint32_t* flags);
-__global__ void k_radix_rowscan(int pass, uint32_t* hist, int ntiles, uint32_t* totals, const uint32_t* tbad,
-                                const uint32_t* tor, const uint32_t* tand, uint32_t* flags);
-__global__ void k_radix_scatter(int pass, const float* w, uint32_t* kA, uint32_t* kB, int32_t* vA, int32_t* vB,
-                                int32_t* vfinal, int64_t n, const uint32_t* hist, const uint32_t* totals,
-                                int ntiles, const uint32_t* flags);
-__global__ void k_big_tile_hull(const uint32_t* skeys, int64_t d, const float* lam_arr, int seg_id,
-                                float lam_scalar, int32_t* vpos, double* vS, int32_t* hcnt,
-                                double* tsum, uint16_t* hbits, int rounds);
-template <int CM>
-__global__ void k_big_tile_scan(const double* tsum, double* tileoff, const int32_t* hcnt,
-                                int32_t* lo, int32_t* hi, int ntiles, int64_t d,
-                                const float* lam_arr, int seg_id, float lam_scalar);
-template <int GMAX, int RMAX>
-__global__ void k_big_merge(int lvl_lo, int lvl_hi, int ntiles, const int32_t* vpos,
-                            const double* vS, const double* tileoff, int32_t* lo_g, int32_t* hi_g,
-                            int finalize, int32_t* prev_pos, double* prev_s, int32_t* next_pos,
-                            double* next_s);
-__global__ void k_big_apply(const uint32_t* skeys, const int32_t* perm, int64_t d,
-                            const float* lam_arr, int seg_id, float lam_scalar,
-                            const uint32_t* flags, const uint16_t* hbits, const int32_t* hcnt,
-                            const double* vS, const double* tileoff, const int32_t* lo_g,
-                            const int32_t* hi_g,
-                            const int32_t* prev_pos, const double* prev_s, const int32_t* next_pos,
-                            const double* next_s, float* out, uint32_t* mask_out,
-                            int64_t seg_start, float beta, float rho, float kappa, int l1,
-                            uint32_t* status);
-__global__ void k_big_bwd_tile(const float* g, const int32_t* perm, const uint32_t* mask,
-                               int64_t d, int64_t seg_start, float* gsorted, double* tsum,
-                               int32_t* fpos, double* fG, int32_t* lpos, double* lG);
-template <int CM>
-__global__ void k_big_bwd_scan(const double* tsum, const int32_t* fpos, const double* fG,
-                               const int32_t* lpos, const double* lG, int ntiles, int64_t d,
-                               double* tileoff, int32_t* prevp, double* prevG, int32_t* nextp,
-                               double* nextG);
-__global__ void k_big_bwd_apply(const float* gsorted, const int32_t* perm, const uint32_t* mask,
-                                int64_t d, int64_t seg_start, const double* tileoff,
-                                const int32_t* prevp, const double* prevG, const int32_t* nextp,
-                                const double* nextG, float* gout);
+// One long segment of a set.
+struct LongSeg {
+  int64_t start;   // flat offset of the segment in w / out / grad / saved perm
+  int64_t d;       // length
+  int64_t ebase;   // offset of its elements in the workspace element arrays
+  int rbase, nrt;  // its radix tiles [rbase, rbase + nrt) of the set
+  int tbase, nt;   // its hull tiles [tbase, tbase + nt) of the set
+  int seg_id;      // index of the segment in per-segment lambda / statistics arrays
+  int nlev;        // merge levels: ceil(log2(nt))
+};
 
-__global__ void k_big_stats_tile(const uint32_t* skeys, int64_t d, double* tsum, int32_t* tnz, int32_t* tnd);
-__global__ void k_big_stats_final(const double* tsum, const int32_t* tnz, const int32_t* tnd, int ntiles,
-                                  int64_t d, const uint32_t* flags, SegStats* out);
+// The long segments of one launch sequence.  One segment travels by value (segs == nullptr);
+// several come from device tables built with a plan.
+struct LongSet {
+  const LongSeg* segs;
+  const int32_t* rseg;  // radix tile -> segment
+  const int32_t* hseg;  // hull tile -> segment
+  LongSeg one;
+  int nsegs;
+  int nrt, nt;  // radix / hull tiles of the whole set
+  __device__ __forceinline__ const LongSeg& seg(int s) const { return segs ? segs[s] : one; }
+  __device__ __forceinline__ int seg_of_rtile(int t) const { return rseg ? rseg[t] : 0; }
+  __device__ __forceinline__ int seg_of_htile(int t) const { return hseg ? hseg[t] : 0; }
+};
+
+// Lambda of a segment: (arr ? arr[seg_id] : scalar) * mul in FP32 (mul = eta for the
+// proximal-gradient step's standard form, else 1).
+struct LamArgs {
+  const float* arr;
+  float scalar;
+  float mul;
+  __device__ __forceinline__ float of(int seg_id) const { return (arr ? arr[seg_id] : scalar) * mul; }
+};
+
+// One merge group of a launch of k_big_merge: tiles [gbase, gbase + gn) of segment s, levels up to
+// lvl_hi; fin: the launch holds the segment's last level (write the previous / next surviving
+// vertex of every tile).
+struct MergeGroup {
+  int s, gbase, gn, lvl_hi, fin;
+};
+
+// Per-segment records in the workspace (flags): [0] a non-finite input, [1] the key bits that
+// vary over the segment.
+constexpr int kSegFlagWords = 4;
+
+template <bool GRAD>
+__global__ void k_radix_hist(int pass, LongSet set, const float* w, const float* grad, float eta, uint32_t* kA,
+                             uint32_t* kB, int32_t* vA, int32_t* vB, int32_t* saved_perm, uint32_t* hist,
+                             uint32_t* tbad, uint32_t* tor, uint32_t* tand, const uint32_t* flags);
+__global__ void k_radix_rowscan(int pass, LongSet set, uint32_t* hist, uint32_t* totals, const uint32_t* tbad,
+                                const uint32_t* tor, const uint32_t* tand, uint32_t* flags);
+template <bool GRAD>
+__global__ void k_radix_scatter(int pass, LongSet set, const float* w, const float* grad, float eta, uint32_t* kA,
+                                uint32_t* kB, int32_t* vA, int32_t* vB, int32_t* saved_perm, const uint32_t* hist,
+                                const uint32_t* totals, const uint32_t* flags);
+__global__ void k_big_tile_hull(LongSet set, const uint32_t* keys, LamArgs lam, int32_t* vpos, double* vS,
+                                int32_t* hcnt, double* tsum, uint16_t* hbits, int rounds);
+template <int CM>
+__global__ void k_big_tile_scan(LongSet set, const double* tsum, double* tileoff, const int32_t* hcnt,
+                                int32_t* lo, int32_t* hi, LamArgs lam);
+template <int GMAX, int RMAX>
+__global__ void k_big_merge(int lvl_lo, int lvl_hi, LongSet set, const MergeGroup* groups, const int32_t* vpos,
+                            const double* vS, const double* tileoff, int32_t* lo_g, int32_t* hi_g,
+                            int32_t* prev_pos, double* prev_s, int32_t* next_pos, double* next_s, double* prev_sl,
+                            double* next_sl);
+__global__ void k_big_merge_top(LongSet set, const int32_t* top_segs, const int32_t* vpos, const double* vS,
+                                const double* tileoff, int32_t* lo_g, int32_t* hi_g, int32_t* prev_pos,
+                                double* prev_s, int32_t* next_pos, double* next_s, double* prev_sl, double* next_sl);
+__global__ void k_big_apply(LongSet set, const uint32_t* keys, const int32_t* saved_perm, const int32_t* perm_ws,
+                            LamArgs lam, const uint32_t* flags, const uint16_t* hbits, const int32_t* hcnt,
+                            const double* vS, const double* tileoff, const int32_t* lo_g, const int32_t* hi_g,
+                            const int32_t* prev_pos, const double* prev_s, const int32_t* next_pos,
+                            const double* next_s, const double* prev_sl, const double* next_sl, float* out,
+                            uint32_t* mask_out, float beta, float rho, float kappa, int l1, uint32_t* status);
+__global__ void k_big_bwd_tile(LongSet set, const float* g, const int32_t* perm, const uint32_t* mask, float* gsorted,
+                               double* tsum, int32_t* fpos, double* fG, int32_t* lpos, double* lG);
+template <int CM>
+__global__ void k_big_bwd_scan(LongSet set, const double* tsum, const int32_t* fpos, const double* fG,
+                               const int32_t* lpos, const double* lG, double* tileoff, int32_t* prevp, double* prevG,
+                               int32_t* nextp, double* nextG);
+__global__ void k_big_bwd_apply(LongSet set, const float* gsorted, const int32_t* perm, const uint32_t* mask,
+                                const double* tileoff, const int32_t* prevp, const double* prevG,
+                                const int32_t* nextp, const double* nextG, float* gout);
+
+__global__ void k_big_stats_tile(LongSet set, const uint32_t* keys, double* tsum, int32_t* tnz, int32_t* tnd);
+__global__ void k_big_stats_final(LongSet set, const double* tsum, const int32_t* tnz, const int32_t* tnd,
+                                  const uint32_t* flags, SegStats* out);
 
 }  // namespace wsr

@@ -72,27 +72,41 @@ __device__ __forceinline__ RadixBufs radix_bufs(int pass, uint32_t varying, uint
   return b;
 }
 
-// Per-tile histogram of one 8-bit digit, written digit-major (hist[digit * ntiles + tile]; the
-// tiles in flight on one XCD are neighbours, so their counts of a digit fill whole cache lines).
-// Source: the FP32 weights (first pass: keys made on the fly, non-finite values flagged, and the
-// OR and AND of the tile's keys kept for the varying-bits mask) or the keys the previous pass
-// wrote.  Persistent: each workgroup has its next tile's keys in flight while it counts the
-// current one, so the loads of one tile overlap the LDS atomics of another.
-__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(int pass, const float* wsrc, uint32_t* kA, uint32_t* kB,
-                                                             int32_t* vA, int32_t* vB, int32_t* vfinal, int64_t n,
-                                                             uint32_t* hist, int ntiles, uint32_t* tbad,
+// Sort buffers of segment sg for pass `pass` (the segment's slices of the workspace arrays; the
+// final permutation goes to the caller's saved perm when there is one).
+__device__ __forceinline__ RadixBufs seg_radix_bufs(int pass, const LongSeg& sg, uint32_t varying, uint32_t* kA,
+                                                    uint32_t* kB, int32_t* vA, int32_t* vB, int32_t* saved_perm) {
+  int32_t* vfinal = saved_perm ? saved_perm + sg.start : vA + sg.ebase;
+  return radix_bufs(pass, varying, kA + sg.ebase, kB + sg.ebase, vA + sg.ebase, vB + sg.ebase, vfinal);
+}
+
+// First-pass input word of element i of a segment: the FP32 weight's bits, or (GRAD) those of
+// the proximal-gradient step fmaf(-eta, grad, w) (one rounding).
+template <bool GRAD>
+__device__ __forceinline__ uint32_t input_bits(const float* w, const float* grad, float eta, uint32_t i) {
+  const float x = *at_u32(w, i);
+  if constexpr (GRAD) return __float_as_uint(__builtin_fmaf(-eta, *at_u32(grad, i), x));
+  return __float_as_uint(x);
+}
+
+// Per-tile histogram of one 8-bit digit, written digit-major (hist[digit * nrt + tile], over the
+// radix tiles of the whole set; the tiles in flight on one XCD are neighbours, so their counts of
+// a digit fill whole cache lines).  Source: the FP32 weights or step inputs (first pass: keys made
+// on the fly, non-finite values flagged, and the OR and AND of the tile's keys kept for the
+// varying-bits mask) or the keys the previous pass wrote.  Persistent: each workgroup has its
+// next tile's words in flight while it counts the current one, so the loads of one tile overlap
+// the LDS atomics of another.
+template <bool GRAD>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(int pass, LongSet set, const float* w,
+                                                             const float* grad, float eta, uint32_t* kA,
+                                                             uint32_t* kB, int32_t* vA, int32_t* vB,
+                                                             int32_t* saved_perm, uint32_t* hist, uint32_t* tbad,
                                                              uint32_t* tor, uint32_t* tand, const uint32_t* flags) {
   constexpr int IPT = kRadixTile / kRadixThreads;
   constexpr int NW = kRadixThreads / kWave;
   constexpr int kHistLanes = 16;
   constexpr int kSub = kWave / kHistLanes;  // sub-histograms per wave
   const int shift = 8 * pass;
-  const uint32_t* ksrc = nullptr;
-  if (pass > 0) {
-    const RadixBufs b = radix_bufs(pass, flags[1], kA, kB, vA, vB, vfinal);
-    if (!b.run) return;
-    ksrc = b.ksrc;
-  }
   const bool first = pass == 0;
   // one pad word per sub-histogram: the same digit in different lane groups falls on different
   // LDS banks
@@ -102,111 +116,145 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(int pass, const fl
   const int lane = lane_id();
   const int wv = tid / kWave;
   for (int j = lane; j < 256 * kSub; j += kWave) h[wv * kSub + j / 256][j % 256] = 0u;
-  // raw 32-bit words of a tile (weights or keys), all in flight at once: uniform tile base,
+  // the tile's segment, its element count and whether this pass runs for it
+  auto tile_info = [&](int tile, const uint32_t** src, uint32_t* nt) -> bool {
+    const LongSeg& sg = set.seg(set.seg_of_rtile(tile));
+    const int64_t base = (int64_t)(tile - sg.rbase) * kRadixTile;
+    *nt = (uint32_t)min((int64_t)kRadixTile, sg.d - base);
+    if (first) {
+      *src = nullptr;
+      return true;
+    }
+    const RadixBufs b = seg_radix_bufs(pass, sg, flags[kSegFlagWords * set.seg_of_rtile(tile) + 1], kA, kB, vA,
+                                       vB, saved_perm);
+    *src = b.ksrc + base;
+    return b.run;
+  };
+  // raw 32-bit words of a tile (input bits or keys), all in flight at once: uniform tile base,
   // 32-bit offsets; words past the end of the segment are never counted
-  const uint32_t* src = first ? reinterpret_cast<const uint32_t*>(wsrc) : ksrc;
-  auto load = [&](int tile, uint32_t (&w)[IPT]) {
-    const int64_t base = (int64_t)tile * kRadixTile;
-    const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
-    const uint32_t* st = src + base;
+  auto load = [&](int tile, uint32_t (&wd)[IPT]) {
+    const uint32_t* st;
+    uint32_t nt;
+    if (!tile_info(tile, &st, &nt)) return;
+    if (first) {
+      const LongSeg& sg = set.seg(set.seg_of_rtile(tile));
+      const uint32_t b0 = (uint32_t)((tile - sg.rbase) * kRadixTile);
+      const float* ws = w + sg.start;
+      const float* gs = GRAD ? grad + sg.start : nullptr;
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+        wd[r] = p < nt ? input_bits<GRAD>(ws, gs, eta, b0 + p) : 0u;
+      }
+      return;
+    }
     if (nt == (uint32_t)kRadixTile) {  // full tile: no bounds checks
 #pragma unroll
-      for (int r = 0; r < IPT; ++r) w[r] = st[r * kRadixThreads + tid];
+      for (int r = 0; r < IPT; ++r) wd[r] = st[r * kRadixThreads + tid];
     } else {
 #pragma unroll
       for (int r = 0; r < IPT; ++r) {
         const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
-        w[r] = p < nt ? st[p] : 0u;
+        wd[r] = p < nt ? st[p] : 0u;
       }
     }
   };
   int tile, tend, tstep;
-  xcd_tiles(ntiles, &tile, &tend, &tstep);
+  xcd_tiles(set.nrt, &tile, &tend, &tstep);
   uint32_t word[IPT];
   if (tile < tend) load(tile, word);
   for (; tile < tend; tile += tstep) {
-    const int64_t base = (int64_t)tile * kRadixTile;
-    const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
+    const uint32_t* unused;
+    uint32_t nt;
+    const bool run = tile_info(tile, &unused, &nt);
     uint32_t wn[IPT];
     const int next = tile + tstep;
     if (next < tend) load(next, wn);
-    int bad = 0;
-    uint32_t kor = 0u, kand = 0xFFFFFFFFu;
+    if (run) {  // uniform over the workgroup
+      int bad = 0;
+      uint32_t kor = 0u, kand = 0xFFFFFFFFu;
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
-      const bool in = p < nt;
-      uint32_t key = word[r];
-      if (first) {
-        const float f = __uint_as_float(key);
-        bad |= in && !isfinite(f);
-        key = float_to_key(f);
-        kor |= in ? key : 0u;
-        kand &= in ? key : 0xFFFFFFFFu;
-      }
-      // each group of kHistLanes lanes counts into its own sub-histogram, so a skewed digit
-      // (the top byte of most inputs, long runs in sorted data) puts at most kHistLanes lanes on
-      // one address; keys past the end of the segment count into the pad word (never read).
-      // No branch per key.
-      const uint32_t dg = in ? (key >> shift) & 255u : 256u;
-      atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
-    }
-    if (first) {
-      // first pass: every tile's non-finite flag and key OR / AND are written each call (no
-      // clearing launch)
-      kor = wave_or_u32(kor);
-      kand = wave_and_u32(kand);
-      if (lane == 0) {
-        red[0][wv] = kor;
-        red[1][wv] = kand;
-      }
-      const int any = __syncthreads_or(bad);
-      if (tid == 0) {
-        uint32_t o = 0u, a = 0xFFFFFFFFu;
-        for (int w = 0; w < NW; ++w) {
-          o |= red[0][w];
-          a &= red[1][w];
+      for (int r = 0; r < IPT; ++r) {
+        const uint32_t p = (uint32_t)(r * kRadixThreads + tid);
+        const bool in = p < nt;
+        uint32_t key = word[r];
+        if (first) {
+          const float f = __uint_as_float(key);
+          bad |= in && !isfinite(f);
+          key = float_to_key(f);
+          kor |= in ? key : 0u;
+          kand &= in ? key : 0xFFFFFFFFu;
         }
-        tbad[tile] = any ? 1u : 0u;
-        tor[tile] = o;
-        tand[tile] = a;
+        // each group of kHistLanes lanes counts into its own sub-histogram, so a skewed digit
+        // (the top byte of most inputs, long runs in sorted data) puts at most kHistLanes lanes
+        // on one address; keys past the end of the segment count into the pad word (never read).
+        // No branch per key.
+        const uint32_t dg = in ? (key >> shift) & 255u : 256u;
+        atomicAdd(&h[wv * kSub + lane / kHistLanes][dg], 1u);
       }
-    } else {
-      __syncthreads();
-    }
-    for (int j = tid; j < 256; j += kRadixThreads) {
-      uint32_t c = 0;
+      if (first) {
+        // first pass: every tile's non-finite flag and key OR / AND are written each call (no
+        // clearing launch)
+        kor = wave_or_u32(kor);
+        kand = wave_and_u32(kand);
+        if (lane == 0) {
+          red[0][wv] = kor;
+          red[1][wv] = kand;
+        }
+        const int any = __syncthreads_or(bad);
+        if (tid == 0) {
+          uint32_t o = 0u, a = 0xFFFFFFFFu;
+          for (int q = 0; q < NW; ++q) {
+            o |= red[0][q];
+            a &= red[1][q];
+          }
+          tbad[tile] = any ? 1u : 0u;
+          tor[tile] = o;
+          tand[tile] = a;
+        }
+      } else {
+        __syncthreads();
+      }
+      for (int j = tid; j < 256; j += kRadixThreads) {
+        uint32_t c = 0;
 #pragma unroll
-      for (int w = 0; w < NW * kSub; ++w) {
-        c += h[w][j];
-        h[w][j] = 0u;
+        for (int q = 0; q < NW * kSub; ++q) {
+          c += h[q][j];
+          h[q][j] = 0u;
+        }
+        hist[(int64_t)j * set.nrt + tile] = c;
       }
-      hist[(int64_t)j * ntiles + tile] = c;
+      __syncthreads();  // the sub-histograms are clear (and red is free) for the next tile
     }
-    __syncthreads();  // the sub-histograms are clear (and red is free) for the next tile
 #pragma unroll
     for (int r = 0; r < IPT; ++r) word[r] = wn[r];
   }
 }
 
-// Exclusive scan of one digit's row of tile counts (one workgroup per digit); row total out.
-// The row goes through LDS so global reads and writes are coalesced.  For the first pass
-// (pass == 0) workgroup 0 also folds the tiles' non-finite flags into flags[0] and their key OR /
-// AND into the varying-bits mask flags[1] (plain stores: every call writes them); a later pass
-// whose digit does not vary returns at once.
-__global__ __launch_bounds__(256) void k_radix_rowscan(int pass, uint32_t* hist, int ntiles, uint32_t* totals,
+// Exclusive scan of one digit's row of tile counts over one segment's tiles (workgroup (digit,
+// segment)); row total out.  The row goes through LDS so global reads and writes are coalesced.
+// For the first pass (pass == 0) the digit-0 workgroup of each segment also folds the tiles'
+// non-finite flags into the segment's flags[0] and their key OR / AND into its varying-bits mask
+// flags[1] (plain stores: every call writes them); a later pass whose digit does not vary over
+// the segment returns at once.
+__global__ __launch_bounds__(256) void k_radix_rowscan(int pass, LongSet set, uint32_t* hist, uint32_t* totals,
                                                        const uint32_t* tbad, const uint32_t* tor,
                                                        const uint32_t* tand, uint32_t* flags) {
   __shared__ uint32_t row_s[kMaxRadixTiles];
   __shared__ int sh[256 / kWave + 1];
   __shared__ uint32_t ored[2][256 / kWave];
-  if (pass > 0 && !radix_pass_runs(pass, flags[1])) return;
-  if (pass == 0 && blockIdx.x == 0) {
+  const int digit = blockIdx.x;
+  const int si = blockIdx.y;
+  const LongSeg& sg = set.seg(si);
+  uint32_t* sflags = flags + kSegFlagWords * si;
+  if (pass > 0 && !radix_pass_runs(pass, sflags[1])) return;
+  const int ntiles = sg.nrt;
+  if (pass == 0 && digit == 0) {
     uint32_t any = 0u, o = 0u, a = 0xFFFFFFFFu;
     for (int i = threadIdx.x; i < ntiles; i += 256) {
-      any |= tbad[i];
-      o |= tor[i];
-      a &= tand[i];
+      any |= tbad[sg.rbase + i];
+      o |= tor[sg.rbase + i];
+      a &= tand[sg.rbase + i];
     }
     o = wave_or_u32(o);
     a = wave_and_u32(a);
@@ -217,15 +265,15 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(int pass, uint32_t* hist,
     any = __syncthreads_or(any != 0u);
     if (threadIdx.x == 0) {
       uint32_t wo = 0u, wa = 0xFFFFFFFFu;
-      for (int w = 0; w < 256 / kWave; ++w) {
-        wo |= ored[0][w];
-        wa &= ored[1][w];
+      for (int q = 0; q < 256 / kWave; ++q) {
+        wo |= ored[0][q];
+        wa &= ored[1][q];
       }
-      flags[0] = any ? 1u : 0u;
-      flags[1] = wo ^ wa;
+      sflags[0] = any ? 1u : 0u;
+      sflags[1] = wo ^ wa;
     }
   }
-  uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  uint32_t* row = hist + (int64_t)digit * set.nrt + sg.rbase;
   for (int i = threadIdx.x; i < ntiles; i += 256) row_s[i] = row[i];
   __syncthreads();
   const int chunk = (ntiles + 255) / 256;
@@ -242,27 +290,27 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(int pass, uint32_t* hist,
   }
   __syncthreads();
   for (int i = threadIdx.x; i < ntiles; i += 256) row[i] = row_s[i];
-  if (threadIdx.x == 0) totals[blockIdx.x] = (uint32_t)total;
+  if (threadIdx.x == 0) totals[256 * si + digit] = (uint32_t)total;
 }
 
 // Items of one tile in wave-striped order (p = wave*64*IPT + r*64 + lane); keys past the end
-// of the segment are 0xFFFFFFFF (they sort last and are never written).  From FP32 weights the
-// raw bits are loaded (past the end: 0x7FFFFFFF, whose key is 0xFFFFFFFF) and made keys by
+// of the segment are 0xFFFFFFFF (they sort last and are never written).  In the first pass the
+// input bits are loaded (past the end: 0x7FFFFFFF, whose key is 0xFFFFFFFF) and made keys by
 // radix_raw_to_key when the tile is used, so a prefetch does not wait for its loads.
-template <int IPT>
-__device__ __forceinline__ void radix_load_tile(const float* wsrc, const uint32_t* ksrc, const int32_t* vsrc,
-                                                int64_t n, int tile, uint32_t (&k)[IPT], int32_t (&v)[IPT]) {
+template <int IPT, bool GRAD>
+__device__ __forceinline__ void radix_load_tile(const float* wsrc, const float* gsrc, float eta,
+                                                const uint32_t* ksrc, const int32_t* vsrc, int64_t n, int ltile,
+                                                uint32_t (&k)[IPT], int32_t (&v)[IPT]) {
   const uint32_t p0 = (threadIdx.x / kWave) * kWave * IPT + lane_id();
-  const int64_t base = (int64_t)tile * kRadixTile;
+  const int64_t base = (int64_t)ltile * kRadixTile;
   const uint32_t nt = (uint32_t)min((int64_t)kRadixTile, n - base);
   const bool full = nt == (uint32_t)kRadixTile;
   // tile base pointers are uniform; per-item offsets are 32-bit
   if (wsrc) {
-    const uint32_t* wt = reinterpret_cast<const uint32_t*>(wsrc) + base;
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       const uint32_t p = p0 + r * kWave;
-      k[r] = (full || p < nt) ? wt[p] : 0x7FFFFFFFu;
+      k[r] = (full || p < nt) ? input_bits<GRAD>(wsrc, gsrc, eta, (uint32_t)base + p) : 0x7FFFFFFFu;
       v[r] = (int32_t)(base + p);
     }
   } else {
@@ -278,140 +326,183 @@ __device__ __forceinline__ void radix_load_tile(const float* wsrc, const uint32_
 }
 
 template <int IPT>
-__device__ __forceinline__ void radix_raw_to_key(const float* wsrc, uint32_t (&k)[IPT]) {
-  if (wsrc) {
+__device__ __forceinline__ void radix_raw_to_key(bool raw, uint32_t (&k)[IPT]) {
+  if (raw) {
 #pragma unroll
     for (int r = 0; r < IPT; ++r) k[r] = float_to_key(__uint_as_float(k[r]));
   }
 }
 
-// Stable scatter by one digit, persistent over XCD-contiguous tiles; each workgroup loads its
-// next tile's items while it ranks and writes the current one.  Items are ranked in wave-striped
-// order, which is the tile's current order, so equal digits keep their relative order.  Writes go
-// out digit-run by digit-run.
-__global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(int pass, const float* w, uint32_t* kA,
+// Stable scatter by one digit, persistent over XCD-contiguous tiles of the set; each workgroup
+// loads its next tile's items while it ranks and writes the current one.  Items are ranked in
+// wave-striped order, which is the tile's current order, so equal digits keep their relative
+// order.  Writes go out digit-run by digit-run, inside the tile's segment.
+template <bool GRAD>
+__global__ __launch_bounds__(kScatterThreads, 4) void k_radix_scatter(int pass, LongSet set, const float* w,
+                                                                const float* grad, float eta, uint32_t* kA,
                                                                 uint32_t* kB, int32_t* vA, int32_t* vB,
-                                                                int32_t* vfinal, int64_t n,
-                                                                const uint32_t* hist, const uint32_t* totals,
-                                                                int ntiles, const uint32_t* flags) {
+                                                                int32_t* saved_perm, const uint32_t* hist,
+                                                                const uint32_t* totals, const uint32_t* flags) {
   constexpr int IPT = kRadixTile / kScatterThreads;
   constexpr int NW = kScatterThreads / kWave;
-  const RadixBufs bufs = radix_bufs(pass, flags[1], kA, kB, vA, vB, vfinal);
-  if (!bufs.run) return;
-  const float* wsrc = pass == 0 ? w : nullptr;
-  const uint32_t* ksrc = bufs.ksrc;
-  const int32_t* vsrc = bufs.vsrc;
-  uint32_t* kdst = bufs.kdst;
-  int32_t* vdst = bufs.vdst;
   const int shift = 8 * pass;
+  const bool first = pass == 0;
   __shared__ uint32_t skey[kRadixTile];
   __shared__ int32_t sval[kRadixTile];
   __shared__ uint32_t wcnt[NW][256];
-  __shared__ int delta[256];  // per digit: global position of the tile's first key of the digit
-                              // minus its position in the tile
+  __shared__ int delta[256];  // per digit: position of the tile's first key of the digit in the
+                              // segment minus its position in the tile
   __shared__ int ish[NW + 1];
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
   const int wbase = wv * kWave * IPT;
-  // digit bases over the whole segment (the same for every tile); thread tid < 256 owns digit tid
+  // thread tid < 256 owns digit tid
   const bool owner = tid < 256;
-  int gt;
-  const int rowbase = block_excl_scan<kScatterThreads, int>(owner ? (int)totals[tid] : 0, ish, &gt);
+  struct TileSrc {
+    RadixBufs b;
+    const float* ws;
+    const float* gs;
+    int64_t d;
+    int ltile;
+    int seg;
+  };
+  auto tile_src = [&](int tile) -> TileSrc {
+    TileSrc t;
+    t.seg = set.seg_of_rtile(tile);
+    const LongSeg& sg = set.seg(t.seg);
+    t.b = seg_radix_bufs(pass, sg, flags[kSegFlagWords * t.seg + 1], kA, kB, vA, vB, saved_perm);
+    t.ws = first ? w + sg.start : nullptr;
+    t.gs = first && GRAD ? grad + sg.start : nullptr;
+    t.d = sg.d;
+    t.ltile = tile - sg.rbase;
+    return t;
+  };
   uint32_t k[IPT];
   int32_t v[IPT];
   int tile, tend, tstep;
-  xcd_tiles(ntiles, &tile, &tend, &tstep);
+  xcd_tiles(set.nrt, &tile, &tend, &tstep);
+  int cur_seg = -1;
+  int rowbase = 0;  // digit base of the owner's digit in the segment: keys of all smaller digits
   if (tile < tend) {
-    radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, tile, k, v);
-    radix_raw_to_key<IPT>(wsrc, k);
+    const TileSrc t = tile_src(tile);
+    if (t.b.run) {
+      radix_load_tile<IPT, GRAD>(t.ws, t.gs, eta, t.b.ksrc, t.b.vsrc, t.d, t.ltile, k, v);
+      radix_raw_to_key<IPT>(first, k);
+    }
   }
   for (; tile < tend; tile += tstep) {
-    const int64_t base = (int64_t)tile * kRadixTile;
-    const int nt = (int)min((int64_t)kRadixTile, n - base);
-    const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
-    const uint32_t tile_pre = owner ? hist[(int64_t)tid * ntiles + tile] : 0u;
-    // the next tile's items are in flight while this one is ranked and written
+    const TileSrc t = tile_src(tile);
     uint32_t kn[IPT];
     int32_t vn[IPT];
     const int next = tile + tstep;
-    if (next < tend) radix_load_tile<IPT>(wsrc, ksrc, vsrc, n, next, kn, vn);
-    for (int j = lane; j < 256; j += kWave) wcnt[wv][j] = 0u;
-    uint16_t rk[IPT];
-#pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      if (r < nr) {
-        const uint32_t dg = (k[r] >> shift) & 255u;
-        const uint64_t peers = match_digit8(dg);
-        const uint32_t b = wcnt[wv][dg];
-        const int nbelow = popc_below(peers);
-        if (nbelow == 0) wcnt[wv][dg] = b + (uint32_t)__popcll(peers);
-        rk[r] = (uint16_t)(b + nbelow);
-      }
+    if (next < tend) {  // the next tile's items are in flight while this one is ranked and written
+      const TileSrc tn = tile_src(next);
+      if (tn.b.run) radix_load_tile<IPT, GRAD>(tn.ws, tn.gs, eta, tn.b.ksrc, tn.b.vsrc, tn.d, tn.ltile, kn, vn);
     }
-    __syncthreads();
-    // digit offsets inside the tile (thread tid < 256 owns digit tid)
-    uint32_t run = 0;
-    if (owner) {
-      for (int w = 0; w < NW; ++w) {
-        const uint32_t c = wcnt[w][tid];
-        wcnt[w][tid] = run;
-        run += c;
+    if (t.b.run) {  // uniform over the workgroup
+      if (t.seg != cur_seg) {  // digit bases of the segment (the same for all its tiles)
+        int gt;
+        rowbase = block_excl_scan<kScatterThreads, int>(owner ? (int)totals[256 * t.seg + tid] : 0, ish, &gt);
+        cur_seg = t.seg;
       }
-    }
-    int tot;
-    const int dstart = block_excl_scan<kScatterThreads, int>((int)run, ish, &tot);
-    if (owner) {
-      for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
-      // global base of this digit = all smaller digits + this digit in the tiles before this one
-      delta[tid] = rowbase + (int)tile_pre - dstart;
-    }
-    __syncthreads();
+      const int64_t base = (int64_t)t.ltile * kRadixTile;
+      const int nt = (int)min((int64_t)kRadixTile, t.d - base);
+      const int nr = min(IPT, max(0, (nt - wbase + kWave - 1) / kWave));
+      const uint32_t tile_pre = owner ? hist[(int64_t)tid * set.nrt + tile] : 0u;
+      uint32_t* const kdst = t.b.kdst;
+      int32_t* const vdst = t.b.vdst;
+      const uint32_t n = (uint32_t)t.d;
+      for (int j = lane; j < 256; j += kWave) wcnt[wv][j] = 0u;
+      uint16_t rk[IPT];
 #pragma unroll
-    for (int r = 0; r < IPT; ++r) {
-      if (r < nr) {
-        const uint32_t dg = (k[r] >> shift) & 255u;
-        const int np = (int)wcnt[wv][dg] + rk[r];
-        skey[np] = k[r];
-        sval[np] = v[r];
-      }
-    }
-    __syncthreads();
-    // write-out by digit runs, four ranks of the thread at a time (their LDS reads issued
-    // together); 32-bit byte offsets (n <= 2^26) from the uniform array bases
-    constexpr int WB = 4;
-    static_assert(IPT % WB == 0, "write-out batches");
-#pragma unroll 1
-    for (int h = 0; h < IPT; h += WB) {
-      uint32_t ko[WB], dso[WB];
-      int32_t vo[WB];
-#pragma unroll
-      for (int q = 0; q < WB; ++q) {
-        const int sp = tid + (h + q) * kScatterThreads;
-        ko[q] = skey[sp];
-        vo[q] = sval[sp];
-      }
-#pragma unroll
-      for (int q = 0; q < WB; ++q)
-        dso[q] = (uint32_t)(delta[(ko[q] >> shift) & 255u] + tid + (h + q) * kScatterThreads);
-#pragma unroll
-      for (int q = 0; q < WB; ++q) {
-        // dso < n always holds for consistent histograms; it guards the scatter
-        if (tid + (h + q) * kScatterThreads < nt && dso[q] < (uint32_t)n) {
-          *at_u32(kdst, dso[q]) = ko[q];
-          *at_u32(vdst, dso[q]) = vo[q];
+      for (int r = 0; r < IPT; ++r) {
+        if (r < nr) {
+          const uint32_t dg = (k[r] >> shift) & 255u;
+          const uint64_t peers = match_digit8(dg);
+          const uint32_t b = wcnt[wv][dg];
+          const int nbelow = popc_below(peers);
+          if (nbelow == 0) wcnt[wv][dg] = b + (uint32_t)__popcll(peers);
+          rk[r] = (uint16_t)(b + nbelow);
         }
       }
+      __syncthreads();
+      // digit offsets inside the tile (thread tid < 256 owns digit tid)
+      uint32_t run = 0;
+      if (owner) {
+        for (int w = 0; w < NW; ++w) {
+          const uint32_t c = wcnt[w][tid];
+          wcnt[w][tid] = run;
+          run += c;
+        }
+      }
+      int tot;
+      const int dstart = block_excl_scan<kScatterThreads, int>((int)run, ish, &tot);
+      if (owner) {
+        for (int w = 0; w < NW; ++w) wcnt[w][tid] += (uint32_t)dstart;
+        // global base of this digit = all smaller digits + this digit in the tiles before this one
+        delta[tid] = rowbase + (int)tile_pre - dstart;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < IPT; ++r) {
+        if (r < nr) {
+          const uint32_t dg = (k[r] >> shift) & 255u;
+          const int np = (int)wcnt[wv][dg] + rk[r];
+          skey[np] = k[r];
+          sval[np] = v[r];
+        }
+      }
+      __syncthreads();
+      // write-out by digit runs, four ranks of the thread at a time (their LDS reads issued
+      // together); 32-bit byte offsets (n <= 2^27) from the uniform array bases
+      constexpr int WB = 4;
+      static_assert(IPT % WB == 0, "write-out batches");
+#pragma unroll 1
+      for (int h = 0; h < IPT; h += WB) {
+        uint32_t ko[WB], dso[WB];
+        int32_t vo[WB];
+#pragma unroll
+        for (int q = 0; q < WB; ++q) {
+          const int sp = tid + (h + q) * kScatterThreads;
+          ko[q] = skey[sp];
+          vo[q] = sval[sp];
+        }
+#pragma unroll
+        for (int q = 0; q < WB; ++q)
+          dso[q] = (uint32_t)(delta[(ko[q] >> shift) & 255u] + tid + (h + q) * kScatterThreads);
+#pragma unroll
+        for (int q = 0; q < WB; ++q) {
+          // dso < n always holds for consistent histograms; it guards the scatter
+          if (tid + (h + q) * kScatterThreads < nt && dso[q] < (uint32_t)n) {
+            *at_u32(kdst, dso[q]) = ko[q];
+            *at_u32(vdst, dso[q]) = vo[q];
+          }
+        }
+      }
+      __syncthreads();  // LDS is reused by the next tile
     }
-    __syncthreads();  // LDS is reused by the next tile
 #pragma unroll
     for (int r = 0; r < IPT; ++r) {
       k[r] = kn[r];
       v[r] = vn[r];
     }
-    radix_raw_to_key<IPT>(wsrc, k);
+    radix_raw_to_key<IPT>(first, k);
   }
 }
+
+template __global__ void k_radix_hist<false>(int, LongSet, const float*, const float*, float, uint32_t*, uint32_t*,
+                                              int32_t*, int32_t*, int32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                              uint32_t*, const uint32_t*);
+template __global__ void k_radix_hist<true>(int, LongSet, const float*, const float*, float, uint32_t*, uint32_t*,
+                                             int32_t*, int32_t*, int32_t*, uint32_t*, uint32_t*, uint32_t*,
+                                             uint32_t*, const uint32_t*);
+template __global__ void k_radix_scatter<false>(int, LongSet, const float*, const float*, float, uint32_t*,
+                                                 uint32_t*, int32_t*, int32_t*, int32_t*, const uint32_t*,
+                                                 const uint32_t*, const uint32_t*);
+template __global__ void k_radix_scatter<true>(int, LongSet, const float*, const float*, float, uint32_t*, uint32_t*,
+                                                int32_t*, int32_t*, int32_t*, const uint32_t*, const uint32_t*,
+                                                const uint32_t*);
 
 // ------------------------------------------------------------------------------- tile hulls
 
@@ -427,9 +518,6 @@ struct TileSmem {
   double xtot;
 };
 
-__device__ __forceinline__ float seg_lambda(const float* lam_arr, int seg_id, float lam_scalar) {
-  return lam_arr ? lam_arr[seg_id] : lam_scalar;
-}
 
 // Local hull of tile t: points k0..k0+np (np = elements in the tile) with tile-relative sums
 //   S'_j = sum_{k0 <= i < k0+j} (x_i - c) + lam/(d-1) * [(k0+j)(d-k0-j) - k0(d-k0)]
@@ -437,18 +525,19 @@ __device__ __forceinline__ float seg_lambda(const float* lam_arr, int seg_id, fl
 // i.e. S_{k0+j} minus the tile's offset S_{k0}.  Adding that offset back does not change the
 // hull; keeping it out keeps S' small (|S'| ~ tile size) so cluster values inside a tile are
 // differences of small numbers even when the segment's global prefix sums are ~1e7.
-__global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* skeys, int64_t d,
-                                                               const float* lam_arr, int seg_id,
-                                                               float lam_scalar, int32_t* vpos,
-                                                               double* vS, int32_t* hcnt, double* tsum,
-                                                               uint16_t* hbits, int rounds) {
+__global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(LongSet set, const uint32_t* keys, LamArgs lamargs,
+                                                               int32_t* vpos, double* vS, int32_t* hcnt,
+                                                               double* tsum, uint16_t* hbits, int rounds) {
   __shared__ TileSmem sm;
   const int tid = threadIdx.x;
-  const int t = blockIdx.x;
-  const int64_t k0 = (int64_t)t * kBigTile;
+  const int t = blockIdx.x;  // hull tile of the set
+  const LongSeg& sg = set.seg(set.seg_of_htile(t));
+  const int64_t d = sg.d;
+  const uint32_t* skeys = keys + sg.ebase;
+  const int64_t k0 = (int64_t)(t - sg.tbase) * kBigTile;  // segment rank of the tile's first rank
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const double c = (double)key_to_float(skeys[d >> 1]);
-  const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
+  const float lam = lamargs.of(sg.seg_id);
   const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
   const int j0 = tid * kBigE;
   // the thread's kBigE consecutive sorted keys, straight from global memory as 16-byte words
@@ -535,16 +624,19 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(const uint32_t* s
 }
 
 // Tile offsets S_{k0} = (exclusive scan of tile sums of x - c) + lam k0 (d-k0)/(d-1), and the
-// initial own ranges [1, hcnt-1].
+// initial own ranges [1, hcnt-1]; one workgroup per segment of the set.
 template <int CM>
-__global__ __launch_bounds__(1024) void k_big_tile_scan(const double* __restrict__ tsum,
+__global__ __launch_bounds__(1024) void k_big_tile_scan(LongSet set, const double* __restrict__ tsum,
                                                         double* __restrict__ tileoff,
                                                         const int32_t* __restrict__ hcnt,
                                                         int32_t* __restrict__ lo, int32_t* __restrict__ hi,
-                                                        int ntiles, int64_t d, const float* lam_arr,
-                                                        int seg_id, float lam_scalar) {
-  // CM >= tiles per thread (ceil(ntiles / 1024)), chosen by the host
-  const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
+                                                        LamArgs lamargs) {
+  // CM >= tiles per thread (ceil(nt / 1024)), chosen by the host
+  const LongSeg& sg = set.seg(blockIdx.x);
+  const int64_t d = sg.d;
+  const int ntiles = sg.nt;
+  const int tb = sg.tbase;
+  const float lam = lamargs.of(sg.seg_id);
   const double lamd = lam > 0.0f ? (double)lam / (double)(d - 1) : 0.0;
   __shared__ double sh[1024 / kWave + 1];
   const int chunk = (ntiles + 1023) / 1024;
@@ -556,8 +648,8 @@ __global__ __launch_bounds__(1024) void k_big_tile_scan(const double* __restrict
   for (int c = 0; c < CM; ++c) {
     const int i = a + c;
     const bool ok = c < chunk && i < ntiles;
-    ts[c] = ok ? tsum[i] : 0.0;
-    hc[c] = ok ? hcnt[i] : 0;
+    ts[c] = ok ? tsum[tb + i] : 0.0;
+    hc[c] = ok ? hcnt[tb + i] : 0;
   }
   double s = 0.0;
 #pragma unroll
@@ -568,10 +660,10 @@ __global__ __launch_bounds__(1024) void k_big_tile_scan(const double* __restrict
     const int i = a + c;
     if (c < chunk && i < ntiles) {
       const double k0 = (double)i * (double)kBigTile;
-      tileoff[i] = run + lamd * k0 * ((double)d - k0);
+      tileoff[tb + i] = run + lamd * k0 * ((double)d - k0);
       run += ts[c];
-      lo[i] = 1;
-      hi[i] = hc[c] - 1;
+      lo[tb + i] = 1;
+      hi[tb + i] = hc[c] - 1;
     }
   }
 }
@@ -579,8 +671,10 @@ __global__ __launch_bounds__(1024) void k_big_tile_scan(const double* __restrict
 // ------------------------------------------------------------------------------- cross-tile merges
 
 // Chain of a node = its left end point, then the own ranges of its tiles.  State in LDS:
-// lo16[t], cnt16[t] (own range start / length) and pre[t] (exclusive prefix of cnt16) for the
-// tiles of this workgroup's group; vertex data in global memory.
+// lo16[t] (own range start) and the exclusive prefix pre[t] of the own-range lengths, for the
+// tiles of this workgroup's group; vertex data in global memory.  The prefix is either one int
+// per tile (pre) or, for the top level's 2^15 tiles, split into an int per 8 tiles plus a 16-bit
+// offset per tile (base[t / 8] + off16[t]; 8 own ranges hold at most 8 * 4097 vertices).
 struct MergeCtx {
   const uint16_t* lo16;
   const int* pre;
@@ -588,6 +682,9 @@ struct MergeCtx {
   const int32_t* vpos;
   const double* vS;
   const double* tileoff;
+  const int* base = nullptr;
+  const uint16_t* off16 = nullptr;
+  __device__ __forceinline__ int pre_at(int t) const { return pre ? pre[t] : base[t >> 3] + (int)off16[t]; }
 };
 
 // m-th vertex of the node covering group-relative tiles [t0, t1): tile and index in that tile.
@@ -597,17 +694,17 @@ __device__ __forceinline__ void node_vertex(const MergeCtx& C, int t0, int t1, i
     *idx = 0;
     return;
   }
-  const int mm = m - 1 + C.pre[t0];
+  const int mm = m - 1 + C.pre_at(t0);
   int lo = t0, hi = t1;  // pre[lo] <= mm < pre[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (C.pre[mid] <= mm)
+    if (C.pre_at(mid) <= mm)
       lo = mid;
     else
       hi = mid;
   }
   *tile = lo;
-  *idx = C.lo16[lo] + (mm - C.pre[lo]);
+  *idx = C.lo16[lo] + (mm - C.pre_at(lo));
 }
 
 // Wave-cooperative access to a node's chain: any lane may fetch any vertex.  Chain indices
@@ -655,7 +752,7 @@ struct WaveNode {
     }
     int tile, idx;
     node_vertex(*C, t0, t1, m, &tile, &idx);
-    const bool same = m > 0 && idx + 1 < (int)C->lo16[tile] + (C->pre[tile + 1] - C->pre[tile]);
+    const bool same = m > 0 && idx + 1 < (int)C->lo16[tile] + (C->pre_at(tile + 1) - C->pre_at(tile));
     int tile1 = tile, idx1 = idx + 1;
     if (!same) node_vertex(*C, t0, t1, m + 1, &tile1, &idx1);
     load(tile, idx, p0, s0);
@@ -829,12 +926,12 @@ __device__ void wave_bridge(const WaveNode& L, int p, const WaveNode& R, int q, 
 // When finalize != 0 (single group holding every tile, last launch), also writes the previous
 // and next surviving vertex of every tile.
 template <int GMAX, int RMAX>
-__global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl_hi, int ntiles,
-                                                             const int32_t* vpos, const double* vS,
-                                                             const double* tileoff, int32_t* lo_g,
-                                                             int32_t* hi_g, int finalize, int32_t* prev_pos,
+__global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl_hi_launch, LongSet set,
+                                                             const MergeGroup* groups, const int32_t* vpos,
+                                                             const double* vS, const double* tileoff,
+                                                             int32_t* lo_g, int32_t* hi_g, int32_t* prev_pos,
                                                              double* prev_s, int32_t* next_pos,
-                                                             double* next_s) {
+                                                             double* next_s, double* prev_sl, double* next_sl) {
   constexpr int NWV = kMergeThreads / kWave;
   __shared__ int pre[GMAX + 1];
   __shared__ int rec[5 * RMAX];
@@ -843,9 +940,21 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   __shared__ int ish[NWV + 1];
   __shared__ int win_p[NWV][2][kWave];  // per wave: the junction windows of L and R
   __shared__ double win_s[NWV][2][kWave];
-  const int G = 1 << lvl_hi;
-  const int gbase = blockIdx.x * G;
-  const int gn = min(G, ntiles - gbase);
+  // this workgroup's group: from the launch's table, or, for a single segment, group blockIdx.x
+  // of 2^lvl_hi tiles with lvl_hi the launch's top level capped at the segment's
+  MergeGroup gr;
+  if (groups) {
+    gr = groups[blockIdx.x];
+  } else {
+    const LongSeg& sg = set.seg(0);
+    const int lh = min(lvl_hi_launch, sg.nlev);
+    const int G = 1 << lh;
+    gr = MergeGroup{0, sg.tbase + (int)blockIdx.x * G, min(G, sg.nt - (int)blockIdx.x * G), lh, lh == sg.nlev ? 1 : 0};
+  }
+  const int lvl_hi = gr.lvl_hi;
+  const int gbase = gr.gbase;
+  const int gn = gr.gn;
+  const int finalize = gr.fin;
   const int tid = threadIdx.x;
   const int wv = tid / kWave;
   const int lane = lane_id();
@@ -968,39 +1077,224 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   if (!finalize) return;
   // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t
   const int nglob = 1 + pre[gn];
-  auto gvertex = [&](int m, int* p, double* s) {
+  // a vertex's global S (S' + the tile offset, as every tile forms it) and its S' in its own tile
+  auto gvertex = [&](int m, int* p, double* s, double* sl) {
     int tile, idx;
     node_vertex(C, 0, gn, m, &tile, &idx);
-    const int64_t at = (int64_t)tile * (kBigTile + 1) + idx;
+    const int64_t at = (int64_t)(gbase + tile) * (kBigTile + 1) + idx;
     *p = vpos[at];
-    *s = vS[at] + tileoff[tile];
+    *sl = vS[at];
+    *s = *sl + tileoff[gbase + tile];
   };
   for (int t = tid; t < gn; t += kMergeThreads) {
     int p;
-    double s;
-    gvertex(pre[t], &p, &s);
-    prev_pos[t] = p;
-    prev_s[t] = s;
+    double s, sl;
+    gvertex(pre[t], &p, &s, &sl);
+    prev_pos[gbase + t] = p;
+    prev_s[gbase + t] = s;
+    prev_sl[gbase + t] = sl;
     const int nx = pre[t + 1] + 1;
     if (nx < nglob) {
-      gvertex(nx, &p, &s);
-      next_pos[t] = p;
-      next_s[t] = s;
+      gvertex(nx, &p, &s, &sl);
+      next_pos[gbase + t] = p;
+      next_s[gbase + t] = s;
+      next_sl[gbase + t] = sl;
     } else {
-      next_pos[t] = -1;
-      next_s[t] = 0.0;
+      next_pos[gbase + t] = -1;
+      next_s[gbase + t] = 0.0;
+      next_sl[gbase + t] = 0.0;
     }
   }
 }
 
-#define WSR_INSTANTIATE_MERGE(GM)                                                                    \
-  template __global__ void k_big_merge<GM, kMergeRecMax>(int, int, int, const int32_t*, const double*, \
-                                                         const double*, int32_t*, int32_t*, int,        \
-                                                         int32_t*, double*, int32_t*, double*);
+#define WSR_INSTANTIATE_MERGE(GM)                                                                           \
+  template __global__ void k_big_merge<GM, kMergeRecMax>(int, int, LongSet, const MergeGroup*, const int32_t*, \
+                                                         const double*, const double*, int32_t*, int32_t*,     \
+                                                         int32_t*, double*, int32_t*, double*, double*, double*);
 WSR_INSTANTIATE_MERGE(16)
 WSR_INSTANTIATE_MERGE(256)
 WSR_INSTANTIATE_MERGE(4096)
 WSR_INSTANTIATE_MERGE(16384)
+
+// The top merge level of a segment of 2^14 < nt <= 2^15 hull tiles (2^26 < d <= 2^27): the two
+// halves (tiles [0, 2^14) and [2^14, nt)), each solved by k_big_merge, are bridged by one wave
+// exactly as one merge of k_big_merge, then every tile gets its previous / next surviving vertex.
+// One workgroup per such segment (top_segs: their indices in the set; null for a single
+// segment).  The prefix of own-range lengths is kept split (an int per 8 tiles, a 16-bit offset
+// per tile) so that it and the tiles' own-range starts fit in LDS; each thread holds 32 tiles'
+// lengths in registers.
+__global__ __launch_bounds__(kTopThreads) void k_big_merge_top(LongSet set, const int32_t* top_segs,
+                                                               const int32_t* vpos, const double* vS,
+                                                               const double* tileoff, int32_t* lo_g,
+                                                               int32_t* hi_g, int32_t* prev_pos, double* prev_s,
+                                                               int32_t* next_pos, double* next_s, double* prev_sl,
+                                                               double* next_sl) {
+  constexpr int TPT = kMaxHullTiles / kTopThreads;  // tiles per thread
+  constexpr int HALF = kMergeGroupMax;
+  __shared__ int base[kMaxHullTiles / 8 + 1];
+  __shared__ uint16_t off16[kMaxHullTiles + 1];
+  __shared__ uint16_t lo16[kMaxHullTiles];
+  __shared__ int ish[kTopThreads / kWave + 1];
+  __shared__ int rec[5];
+  __shared__ int win_p[2][kWave];
+  __shared__ double win_s[2][kWave];
+  const LongSeg& sg = set.seg(top_segs ? top_segs[blockIdx.x] : 0);
+  const int gbase = sg.tbase;
+  const int gn = sg.nt;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int t0 = tid * TPT;
+  int cnt[TPT];
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const int t = t0 + i;
+    int l = 0, h = -1;
+    if (t < gn) {
+      l = lo_g[gbase + t];
+      h = hi_g[gbase + t];
+      lo16[t] = (uint16_t)l;
+    }
+    cnt[i] = max(0, h - l + 1);
+  }
+  // split prefix of the lengths: base at every 8th tile, 16-bit offsets inside
+  auto build_prefix = [&]() {
+    int sum = 0;
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) sum += cnt[i];
+    int total;
+    int run = block_excl_scan<kTopThreads, int>(sum, ish, &total);
+    int b = run;
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int t = t0 + i;
+      if ((t & 7) == 0) {
+        b = run;
+        base[t >> 3] = run;
+      }
+      if (t <= gn) off16[t] = (uint16_t)(run - b);
+      run += cnt[i];
+    }
+    // pre(gn) for gn below kMaxHullTiles was written above (tiles past gn add nothing)
+    if (tid == 0 && gn == kMaxHullTiles) {
+      base[kMaxHullTiles / 8] = total;
+      off16[kMaxHullTiles] = 0;
+    }
+    __syncthreads();
+  };
+  build_prefix();
+  MergeCtx C{lo16, nullptr, gbase, vpos, vS, tileoff};
+  C.base = base;
+  C.off16 = off16;
+  if (tid < kWave) {  // one wave bridges the halves
+    const int tm = HALF, t1 = gn;
+    const int p = C.pre_at(tm) - C.pre_at(0);
+    const int q = C.pre_at(t1) - C.pre_at(tm);
+    const int wlo = max(0, p - (kWave - 1));
+    const int rhi = min(q, kWave - 1);
+    {
+      WaveNode Lg{&C, 0, tm};
+      WaveNode Rg{&C, tm, t1};
+      int vp;
+      double vs;
+      if (wlo + lane <= p) {
+        Lg.fetch_global(wlo + lane, &vp, &vs);
+        win_p[0][lane] = vp;
+        win_s[0][lane] = vs;
+      }
+      if (lane <= rhi) {
+        Rg.fetch_global(lane, &vp, &vs);
+        win_p[1][lane] = vp;
+        win_s[1][lane] = vs;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    WaveNode L{&C, 0, tm, (const lds_int*)win_p[0], (const lds_double*)win_s[0], wlo, p};
+    WaveNode R{&C, tm, t1, (const lds_int*)win_p[1], (const lds_double*)win_s[1], 0, rhi};
+    int istar, jstar;
+    wave_bridge(L, p, R, q, &istar, &jstar);
+    int r0 = 0, r1 = 0, r2 = 0, r3 = 0, r4 = 0;
+    if (!(istar == p && jstar == 1)) {
+      int ti = -1, ii = 0, tj, jj;
+      if (istar > 0) node_vertex(C, 0, tm, istar, &ti, &ii);
+      node_vertex(C, tm, t1, jstar, &tj, &jj);
+      r0 = 1;
+      r1 = ti;
+      r2 = ii;
+      r3 = tj;
+      r4 = jj;
+    }
+    if (lane == 0) {
+      rec[0] = r0;
+      rec[1] = r1;
+      rec[2] = r2;
+      rec[3] = r3;
+      rec[4] = r4;
+    }
+  }
+  __syncthreads();
+  if (rec[0]) {  // cut the own ranges at the bridge (uniform branch)
+#pragma unroll
+    for (int i = 0; i < TPT; ++i) {
+      const int t = t0 + i;
+      if (t >= gn) continue;
+      if (t < HALF) {
+        if (t > rec[1])
+          cnt[i] = 0;
+        else if (t == rec[1])
+          cnt[i] = rec[2] - (int)lo16[t] + 1;
+      } else {
+        if (t < rec[3]) {
+          cnt[i] = 0;
+        } else if (t == rec[3]) {
+          const int oldend = (int)lo16[t] + cnt[i];
+          cnt[i] = oldend - rec[4];
+          lo16[t] = (uint16_t)rec[4];
+        }
+      }
+    }
+  }
+  __syncthreads();  // every prefix read of the merge is done before the rebuild
+  build_prefix();
+#pragma unroll
+  for (int i = 0; i < TPT; ++i) {
+    const int t = t0 + i;
+    if (t < gn) {
+      lo_g[gbase + t] = lo16[t];
+      hi_g[gbase + t] = (int)lo16[t] + cnt[i] - 1;
+    }
+  }
+  // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t
+  const int nglob = 1 + C.pre_at(gn);
+  auto gvertex = [&](int m, int* p, double* s, double* sl) {
+    int tile, idx;
+    node_vertex(C, 0, gn, m, &tile, &idx);
+    const int64_t at = (int64_t)(gbase + tile) * (kBigTile + 1) + idx;
+    *p = vpos[at];
+    *sl = vS[at];
+    *s = *sl + tileoff[gbase + tile];
+  };
+  for (int t = tid; t < gn; t += kTopThreads) {
+    int p;
+    double s, sl;
+    gvertex(C.pre_at(t), &p, &s, &sl);
+    prev_pos[gbase + t] = p;
+    prev_s[gbase + t] = s;
+    prev_sl[gbase + t] = sl;
+    const int nx = C.pre_at(t + 1) + 1;
+    if (nx < nglob) {
+      gvertex(nx, &p, &s, &sl);
+      next_pos[gbase + t] = p;
+      next_s[gbase + t] = s;
+      next_sl[gbase + t] = sl;
+    } else {
+      next_pos[gbase + t] = -1;
+      next_s[gbase + t] = 0.0;
+      next_sl[gbase + t] = 0.0;
+    }
+  }
+}
 
 // ------------------------------------------------------------------------------- apply
 
@@ -1021,34 +1315,38 @@ struct ApplySmem {
 // then sweeps its ranks with the neighbouring starts from the other threads (carry exchange) or
 // from the merge (tile ends).  l1 != 0: each cluster's output goes through Alg. prox's l1 and
 // rewinding lines (beta, rho, rewinding-line scale kappa).
-__global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys, const int32_t* perm,
-                                                           int64_t d, const float* lam_arr, int seg_id,
-                                                           float lam_scalar, const uint32_t* flags,
-                                                           const uint16_t* hbits, const int32_t* hcnt,
-                                                           const double* vS, const double* tileoff,
-                                                           const int32_t* lo_g,
+__global__ __launch_bounds__(kBigThreads) void k_big_apply(LongSet set, const uint32_t* keys, const int32_t* saved_perm,
+                                                           const int32_t* perm_ws, LamArgs lamargs,
+                                                           const uint32_t* flags, const uint16_t* hbits,
+                                                           const int32_t* hcnt, const double* vS,
+                                                           const double* tileoff, const int32_t* lo_g,
                                                            const int32_t* hi_g, const int32_t* prev_pos,
                                                            const double* prev_s, const int32_t* next_pos,
-                                                           const double* next_s, float* out,
-                                                           uint32_t* mask_out, int64_t seg_start,
+                                                           const double* next_s, const double* prev_sl,
+                                                           const double* next_sl, float* out, uint32_t* mask_out,
                                                            float beta, float rho, float kappa, int l1,
                                                            uint32_t* status) {
   constexpr int R = kBigTile / kBigThreads;
   __shared__ ApplySmem sm;
   const int tid = threadIdx.x;
-  const int t = blockIdx.x;
-  const int64_t k0 = (int64_t)t * kBigTile;
+  const int t = blockIdx.x;  // hull tile of the set
+  const int si = set.seg_of_htile(t);
+  const LongSeg& sg = set.seg(si);
+  const int64_t d = sg.d;
+  const int64_t seg_start = sg.start;
+  const uint32_t* skeys = keys + sg.ebase;
+  const int64_t k0 = (int64_t)(t - sg.tbase) * kBigTile;  // segment rank of the tile's first rank
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int off = (int)((seg_start + k0) & 31);
   const int j0 = tid * kBigE;
   const int nmine = max(0, min(kBigE, np - j0));
-  const float lam = seg_lambda(lam_arr, seg_id, lam_scalar);
-  const bool nonfinite = (flags[0] & 1u) != 0;
+  const float lam = lamargs.of(sg.seg_id);
+  const bool nonfinite = (flags[kSegFlagWords * si] & 1u) != 0;
   const bool identity = nonfinite || !(lam > 0.0f);
-  if (nonfinite && t == 0 && tid == 0 && status) atomicOr(status, kStatusNonFinite);
-  // segment-relative 32-bit offsets (d <= 2^26) from a uniform base
+  if (nonfinite && t == sg.tbase && tid == 0 && status) atomicOr(status, kStatusNonFinite);
+  // segment-relative 32-bit offsets (d <= 2^27) from a uniform base
   float* const og = out + seg_start;
-  const int32_t* const pt = perm + k0;
+  const int32_t* const pt = (saved_perm ? saved_perm + seg_start : perm_ws + sg.ebase) + k0;
   const uint32_t* const kt = skeys + k0;
   // the permutation entries are needed only for the final scatter: loaded late (their latency
   // overlaps the last barrier), so they do not hold registers through the scans and passes
@@ -1109,6 +1407,10 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   const int npn = next_pos[t];
   const double nsn = next_s[t];
   const double endS = vS[vb + hc - 1];  // the tile's end point, as the tile kernel stored it
+  const double ps_loc = prev_sl[t];     // S' of the previous / next surviving vertex in its own tile
+  const double ns_loc = next_sl[t];
+  // the previous tile's end point (a cluster entering this tile from it)
+  const double endS_prev = t > sg.tbase ? vS[(int64_t)(t - 1) * (kBigTile + 1) + hcnt[t - 1] - 1] : 0.0;
   // surviving starts among the thread's ranks: hull-vertex bits whose vertex index is own (the
   // scan's barriers also order the key writes above before the reads below)
   const int vbase = block_excl_scan<kBigThreads, int>(__popc(hb), sm.ired, (int*)nullptr);
@@ -1166,15 +1468,22 @@ __global__ __launch_bounds__(kBigThreads) void k_big_apply(const uint32_t* skeys
   // after the tile's last start: its end point when that survives (S'), else the merge's next
   // surviving vertex (global S)
   if (rc.pos < 0) rc = hi == hc - 1 ? Cand{(int)(k0 + np), endS} : Cand{npn, nsn};
-  // a cluster inside the tile uses S' (small numbers); a cluster reaching outside the tile uses
-  // global S formed exactly as the merge kernel forms it (S' + tile offset), so every tile it
-  // touches computes the identical value.  Candidates inside [k0, k0 + np] carry S', others S.
+  // A cluster inside the tile uses S' (small numbers).  A cluster spanning this tile and one
+  // neighbour uses the two tiles' S' with the first tile's end point, (E - S'(pa)) + S'(pb): no
+  // global sums, and both tiles read the same stored values.  A longer cluster uses global S formed
+  // exactly as the merge kernel forms it (S' + tile offset).  So every tile a cluster touches
+  // computes the identical value.  Candidates inside [k0, k0 + np] carry S', others S.
   auto cval = [&](int pa, double sa, int pb, double sb) -> float {
     const bool ina = pa >= k0 && pa <= k0 + np;
     const bool inb = pb >= k0 && pb <= k0 + np;
     double dS;
     if (ina && inb) {
       dS = sb - sa;
+    } else if ((pb - 1) / kBigTile == pa / kBigTile + 1) {
+      const double sa_l = ina ? sa : (pa % kBigTile == 0 ? 0.0 : ps_loc);  // S'(pa) in its tile
+      const double e_a = ina ? endS : endS_prev;                          // that tile's end point
+      const double sb_l = inb ? sb : ns_loc;                               // S'(pb) in its tile
+      dS = (e_a - sa_l) + sb_l;
     } else {
       const double ga = ina ? (pa == k0 ? ps : sa + toff) : sa;
       const double gb = inb ? sb + toff : sb;
@@ -1262,19 +1571,22 @@ struct BwdTileSmem {
 
 // Gather the cotangent in rank order (kept for the apply pass), tile sums, first / last cluster
 // start of the tile with the local prefix at it.
-__global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, const int32_t* perm,
-                                                              const uint32_t* mask, int64_t d,
-                                                              int64_t seg_start, float* gsorted,
-                                                              double* tsum, int32_t* fpos, double* fG,
-                                                              int32_t* lpos, double* lG) {
+__global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(LongSet set, const float* g, const int32_t* perm,
+                                                              const uint32_t* mask, float* gsorted_ws, double* tsum,
+                                                              int32_t* fpos, double* fG, int32_t* lpos, double* lG) {
   constexpr int R = kBigTile / kBigThreads;
   constexpr int NW = kBigThreads / kWave;
   __shared__ BwdTileSmem sm;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wv = tid / kWave;
-  const int t = blockIdx.x;
-  const int64_t k0 = (int64_t)t * kBigTile;
+  const int t = blockIdx.x;  // hull tile of the set
+  const LongSeg& sg = set.seg(set.seg_of_htile(t));
+  const int64_t d = sg.d;
+  const int64_t seg_start = sg.start;
+  float* const gsorted = gsorted_ws + sg.ebase;
+  perm += seg_start;  // the segment's saved permutation (segment ranks)
+  const int64_t k0 = (int64_t)(t - sg.tbase) * kBigTile;  // segment rank of the tile's first rank
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int j0 = tid * kBigE;
   const int nmine = max(0, min(kBigE, np - j0));
@@ -1359,22 +1671,25 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_tile(const float* g, co
   }
 }
 
-// One workgroup: tile offsets of G, and for every tile the last cluster start before it and the
-// first cluster start after its last local start (with global G values).  The carries are
+// One workgroup per segment: tile offsets of G, and for every tile the last cluster start before it
+// and the first cluster start after its last local start (with global G values).  The carries are
 // "last valid" / "first valid" scans over per-thread chunk summaries (wave shuffles + LDS).
 template <int CM>
-__global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* __restrict__ tsum,
+__global__ __launch_bounds__(1024) void k_big_bwd_scan(LongSet set, const double* __restrict__ tsum,
                                                        const int32_t* __restrict__ fpos,
                                                        const double* __restrict__ fG,
                                                        const int32_t* __restrict__ lpos,
-                                                       const double* __restrict__ lG, int ntiles, int64_t d,
-                                                       double* __restrict__ tileoff, int32_t* __restrict__ prevp,
-                                                       double* __restrict__ prevG, int32_t* __restrict__ nextp,
-                                                       double* __restrict__ nextG) {
-  // CM >= tiles per thread (ceil(ntiles / 1024)), chosen by the host
+                                                       const double* __restrict__ lG, double* __restrict__ tileoff,
+                                                       int32_t* __restrict__ prevp, double* __restrict__ prevG,
+                                                       int32_t* __restrict__ nextp, double* __restrict__ nextG) {
+  // CM >= tiles per thread (ceil(nt / 1024)), chosen by the host
   __shared__ double sh[1024 / kWave + 1];
   __shared__ Cand shL[1024 / kWave], shR[1024 / kWave];
   __shared__ int shF[1024 / kWave];
+  const LongSeg& sg = set.seg(blockIdx.x);
+  const int64_t d = sg.d;
+  const int ntiles = sg.nt;
+  const int tb = sg.tbase;
   const int tid = threadIdx.x;
   const int chunk = (ntiles + 1023) / 1024;
   const int a = tid * chunk;
@@ -1385,11 +1700,11 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* __restrict_
   for (int c = 0; c < CM; ++c) {
     const int i = a + c;
     const bool ok = c < chunk && i < ntiles;
-    ts[c] = ok ? tsum[i] : 0.0;
-    lp[c] = ok ? lpos[i] : -1;
-    fp[c] = ok ? fpos[i] : -1;
-    lg[c] = ok ? lG[i] : 0.0;
-    fg[c] = ok ? fG[i] : 0.0;
+    ts[c] = ok ? tsum[tb + i] : 0.0;
+    lp[c] = ok ? lpos[tb + i] : -1;
+    fp[c] = ok ? fpos[tb + i] : -1;
+    lg[c] = ok ? lG[tb + i] : 0.0;
+    fg[c] = ok ? fG[tb + i] : 0.0;
   }
   double s = 0.0;
 #pragma unroll
@@ -1400,7 +1715,7 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* __restrict_
   const double run0 = run;
 #pragma unroll
   for (int c = 0; c < CM; ++c) {
-    if (c < chunk && a + c < ntiles) tileoff[a + c] = run;
+    if (c < chunk && a + c < ntiles) tileoff[tb + a + c] = run;
     if (lp[c] >= 0) mineL = Cand{lp[c], run + lg[c]};
     if (fp[c] >= 0 && mineR.pos < 0) mineR = Cand{fp[c], run + fg[c]};
     run += ts[c];
@@ -1415,8 +1730,8 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* __restrict_
 #pragma unroll
   for (int c = 0; c < CM; ++c) {
     if (c < chunk && a + c < ntiles) {
-      prevp[a + c] = lc.pos;
-      prevG[a + c] = lc.s;
+      prevp[tb + a + c] = lc.pos;
+      prevG[tb + a + c] = lc.s;
     }
     if (lp[c] >= 0) lc = Cand{lp[c], run + lg[c]};
     firsts[c] = Cand{fp[c], run + fg[c]};
@@ -1425,22 +1740,23 @@ __global__ __launch_bounds__(1024) void k_big_bwd_scan(const double* __restrict_
 #pragma unroll
   for (int c = CM - 1; c >= 0; --c) {
     if (c < chunk && a + c < ntiles) {
-      nextp[a + c] = rc.pos;
-      nextG[a + c] = rc.s;
+      nextp[tb + a + c] = rc.pos;
+      nextG[tb + a + c] = rc.s;
     }
     if (firsts[c].pos >= 0) rc = firsts[c];
   }
 }
 
-#define WSR_INSTANTIATE_SCANS(CM)                                                                   \
-  template __global__ void k_big_tile_scan<CM>(const double*, double*, const int32_t*, int32_t*,      \
-                                               int32_t*, int, int64_t, const float*, int, float);     \
-  template __global__ void k_big_bwd_scan<CM>(const double*, const int32_t*, const double*,          \
-                                              const int32_t*, const double*, int, int64_t, double*,  \
-                                              int32_t*, double*, int32_t*, double*);
+#define WSR_INSTANTIATE_SCANS(CM)                                                                         \
+  template __global__ void k_big_tile_scan<CM>(LongSet, const double*, double*, const int32_t*, int32_t*,    \
+                                               int32_t*, LamArgs);                                             \
+  template __global__ void k_big_bwd_scan<CM>(LongSet, const double*, const int32_t*, const double*,           \
+                                              const int32_t*, const double*, double*, int32_t*, double*,       \
+                                              int32_t*, double*);
 WSR_INSTANTIATE_SCANS(4)
 WSR_INSTANTIATE_SCANS(8)
 WSR_INSTANTIATE_SCANS(16)
+WSR_INSTANTIATE_SCANS(32)
 
 struct BwdApplySmem {
   float v[rpad_size(kBigTile)];  // cotangent in rank order, then the results (rank-padded)
@@ -1452,21 +1768,25 @@ struct BwdApplySmem {
 // Per rank: the mean cotangent of its cluster, scattered to the original order.  Each thread
 // holds G (global prefix) at its kBigE ranks; the start before its first start and after its last
 // one come from the other threads (carry exchange) or, at the tile ends, from the tile scan.
-__global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsorted, const int32_t* perm,
-                                                               const uint32_t* mask, int64_t d,
-                                                               int64_t seg_start, const double* tileoff,
-                                                               const int32_t* prevp, const double* prevG,
-                                                               const int32_t* nextp, const double* nextG,
-                                                               float* gout) {
+__global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(LongSet set, const float* gsorted_ws,
+                                                               const int32_t* perm, const uint32_t* mask,
+                                                               const double* tileoff, const int32_t* prevp,
+                                                               const double* prevG, const int32_t* nextp,
+                                                               const double* nextG, float* gout) {
   constexpr int R = kBigTile / kBigThreads;
   __shared__ BwdApplySmem sm;
   const int tid = threadIdx.x;
-  const int t = blockIdx.x;
-  const int64_t k0 = (int64_t)t * kBigTile;
+  const int t = blockIdx.x;  // hull tile of the set
+  const LongSeg& sg = set.seg(set.seg_of_htile(t));
+  const int64_t d = sg.d;
+  const int64_t seg_start = sg.start;
+  const float* const gsorted = gsorted_ws + sg.ebase;
+  perm += seg_start;  // the segment's saved permutation (segment ranks)
+  const int64_t k0 = (int64_t)(t - sg.tbase) * kBigTile;  // segment rank of the tile's first rank
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const int j0 = tid * kBigE;
   const int nmine = max(0, min(kBigE, np - j0));
-  // segment-relative 32-bit offsets (d <= 2^26) from a uniform base; every load is issued first
+  // segment-relative 32-bit offsets (d <= 2^27) from a uniform base; every load is issued first
   float* const og = gout + seg_start;
   const int32_t* const pt = perm + k0;
   const float* const gt = gsorted + k0;
@@ -1551,12 +1871,15 @@ __global__ __launch_bounds__(kBigThreads) void k_big_bwd_apply(const float* gsor
 // the counts of non-zero weights and of distinct non-zero values (a rank counts when its value
 // differs from the previous rank's, read across the tile edge); k_big_stats_final adds the
 // tiles in a fixed order.  Deterministic.
-__global__ __launch_bounds__(kBigThreads) void k_big_stats_tile(const uint32_t* skeys, int64_t d, double* tsum,
+__global__ __launch_bounds__(kBigThreads) void k_big_stats_tile(LongSet set, const uint32_t* keys, double* tsum,
                                                                 int32_t* tnz, int32_t* tnd) {
   __shared__ double dred[kBigThreads / kWave + 1];
   __shared__ long long lred[kBigThreads / kWave + 1];
   const int tid = threadIdx.x;
-  const int64_t k0 = (int64_t)blockIdx.x * kBigTile;
+  const LongSeg& sg = set.seg(set.seg_of_htile(blockIdx.x));
+  const int64_t d = sg.d;
+  const uint32_t* skeys = keys + sg.ebase;
+  const int64_t k0 = (int64_t)(blockIdx.x - sg.tbase) * kBigTile;
   const int np = (int)min((int64_t)kBigTile, d - k0);
   const double c = (double)key_to_float(skeys[d >> 1]);
   double lsum = 0.0;
@@ -1583,15 +1906,16 @@ __global__ __launch_bounds__(kBigThreads) void k_big_stats_tile(const uint32_t* 
   }
 }
 
-__global__ __launch_bounds__(1024) void k_big_stats_final(const double* tsum, const int32_t* tnz,
-                                                          const int32_t* tnd, int ntiles, int64_t d,
-                                                          const uint32_t* flags, SegStats* out) {
+__global__ __launch_bounds__(1024) void k_big_stats_final(LongSet set, const double* tsum, const int32_t* tnz,
+                                                          const int32_t* tnd, const uint32_t* flags, SegStats* out) {
   __shared__ double dred[1024 / kWave + 1];
   __shared__ long long zred[1024 / kWave + 1], nred[1024 / kWave + 1];
   const int tid = threadIdx.x;
+  const LongSeg& sg = set.seg(blockIdx.x);  // one workgroup per segment
+  const int64_t d = sg.d;
   double s = 0.0;
   long long nz = 0, nd = 0;
-  for (int t = tid; t < ntiles; t += 1024) {
+  for (int t = sg.tbase + tid; t < sg.tbase + sg.nt; t += 1024) {
     s += tsum[t];
     nz += tnz[t];
     nd += tnd[t];
@@ -1602,10 +1926,10 @@ __global__ __launch_bounds__(1024) void k_big_stats_final(const double* tsum, co
   (void)block_excl_scan<1024, long long, false>(nz, zred, &ztot);
   (void)block_excl_scan<1024, long long, false>(nd, nred, &ntot);
   if (tid == 0) {
-    if (flags[0] & 1u)
-      out[0] = SegStats{__builtin_nan(""), -1, -1};
+    if (flags[kSegFlagWords * blockIdx.x] & 1u)
+      out[sg.seg_id] = SegStats{__builtin_nan(""), -1, -1};
     else
-      out[0] = SegStats{total / (double)(d - 1), ntot, ztot};
+      out[sg.seg_id] = SegStats{total / (double)(d - 1), ntot, ztot};
   }
 }
 

@@ -57,7 +57,5 @@ template <int TMAX, int NT>
 __global__ void k_prox_bwd_small(SegArgs args, const float* gin, float* gout, const int32_t* perm_in,
                                  const uint32_t* mask_in);
 __global__ void k_zero_u32(uint32_t* p, int64_t n);
-__global__ void k_grad_step(float* out, const float* w, const float* grad, float eta, int64_t n);
-__global__ void k_scale_lambda(float* dst, const float* lam_arr, int seg_id, float lam_scalar, float mul);
 
 }  // namespace wsr

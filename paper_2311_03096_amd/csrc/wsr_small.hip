@@ -828,19 +828,6 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
   for (int64_t j = i; j < n; j += stride) p[j] = 0u;
 }
 
-// Gradient step of a proximal-gradient update: out = fmaf(-eta, grad, w), one FP32 rounding
-// (out may alias w or grad).
-__global__ void k_grad_step(float* out, const float* w, const float* grad, float eta, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t j = i; j < n; j += stride) out[j] = __builtin_fmaf(-eta, grad[j], w[j]);
-}
-
-// dst[0] = (lam_arr ? lam_arr[seg_id] : lam_scalar) * mul, one FP32 rounding (one thread).
-__global__ void k_scale_lambda(float* dst, const float* lam_arr, int seg_id, float lam_scalar, float mul) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) dst[0] = (lam_arr ? lam_arr[seg_id] : lam_scalar) * mul;
-}
-
 #define WSR_INSTANTIATE_SMALL(TM, NTH)                                                          \
   template __global__ void k_seg_stats_small<TM, NTH>(SegArgs, const float*, SegStats*);         \
   template __global__ void k_prox_fwd_small<TM, NTH, false>(SegArgs, const float*, float*,       \

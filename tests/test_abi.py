@@ -45,7 +45,7 @@ def test_workspace_sizes():
     assert 0 < a < b and b == c
     assert b >= (1 << 20) * 16  # two key and two index buffers at least
     with pytest.raises(wsr.WsrError) as e:
-        wsr.wsr_workspace_bytes([0, (1 << 26) + 1])
+        wsr.wsr_workspace_bytes([0, (1 << 27) + 1])
     assert e.value.status == wsr.WSR_ERR_UNSUPPORTED
 
 
@@ -69,7 +69,7 @@ def test_forward_argument_errors():
     assert _fwd([0, 1 << 20]) == wsr.WSR_ERR_WORKSPACE  # long segment needs workspace
     need = wsr.wsr_workspace_bytes([0, 1 << 20])
     assert _fwd([0, 1 << 20], ws=FAKE, ws_bytes=need - 1) == wsr.WSR_ERR_WORKSPACE
-    assert _fwd([0, (1 << 26) + 1]) == wsr.WSR_ERR_UNSUPPORTED
+    assert _fwd([0, (1 << 27) + 1]) == wsr.WSR_ERR_UNSUPPORTED
     off = np.array([0, 4], np.int64)
     assert wsr.load().wsr_prox_forward(FAKE, FAKE, None, 1, ctypes.c_float(0.1), None, None, None, 0,
                                        None) == E
@@ -318,7 +318,7 @@ def test_noalloc_limits_on_host():
     assert wsr.wsr_workspace_bytes([0, wsr.WSR_NOALLOC_MAX_SEGMENT]) <= wsr.WSR_NOALLOC_SCRATCH_BYTES
     assert wsr.wsr_workspace_bytes([0, 4 * wsr.WSR_NOALLOC_MAX_SEGMENT]) > wsr.WSR_NOALLOC_SCRATCH_BYTES
     lib = wsr.load()
-    for d, want in ((4 * wsr.WSR_NOALLOC_MAX_SEGMENT, wsr.WSR_ERR_WORKSPACE), ((1 << 26) + 1, wsr.WSR_ERR_UNSUPPORTED)):
+    for d, want in ((4 * wsr.WSR_NOALLOC_MAX_SEGMENT, wsr.WSR_ERR_WORKSPACE), ((1 << 27) + 1, wsr.WSR_ERR_UNSUPPORTED)):
         off = np.array([0, d], np.int64)
         assert lib.wsr_prox_forward_noalloc(FAKE, FAKE, off.ctypes.data_as(ctypes.c_void_p), 1, ctypes.c_float(0.1),
                                             None, None, None) == want

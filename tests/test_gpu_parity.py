@@ -363,3 +363,71 @@ def test_graph_capture_replays():
         assert torch.equal(out, ref), "replay %d differs" % i
         _ = (w * 2).sum().item()  # eager work between replays
     bp.close()
+
+
+# ------------------------------------------------------------------------------- paper-scale layers
+
+def test_layer_1e8_normal_fan_in():
+    """One segment of 10^8 weights N(0, 1/fan_in) (a weight matrix of the paper's largest layer
+    size, R applied per layer): past 2^26, so the merge takes its top level above the LDS groups;
+    forward against the oracle with every check, and the backward on the GPU's partition."""
+    d = 100_000_000
+    rng = np.random.default_rng(90)
+    w = (rng.standard_normal(d) / np.sqrt(3072.0)).astype(np.float32)
+    case = dict(name="layer_1e8", w=w, offsets=np.array([0, d], np.int64), lam=float(np.float32(1e-3)))
+    g, _, st = _check(case)
+    assert st["clusters"] > 1000
+    gr = rng.standard_normal(d).astype(np.float32)
+    gw = gpu_backward(gr, case["offsets"], g["perm"], g["start"])
+    vjp_check(gr, case["offsets"], g, gw)
+
+
+def test_layer_1e8_chain():
+    """The collision chain at 10^8 weights: one final cluster, every output the mean."""
+    d = 100_000_000
+    case = workloads.chain(d, 0.7)
+    g, _, st = _check(case)
+    assert st["clusters"] == 1
+    assert np.all(g["out"] == g["out"][0])
+
+
+def test_max_segment_2p27_batched_with_rows():
+    """A plan holding a segment of exactly 2^27 weights (the longest supported: 2^15 hull tiles, all
+    merge levels including the top one) next to rows and a second long segment, in one sweep.
+    Checked without the oracle (a sort of 2^27 values on one host thread): the batched result is
+    bit-identical to the plain entry point's, and passes the optimality certificate (App. A.1 eq.
+    prox_opt with Sec. 2 eq. subdiff_R) and the momentum invariant (sum of each segment kept)."""
+    import pins
+    lens = [4096, 1 << 27, 3000, 70000]
+    case = workloads.random_segments(lens, "laplace", 0.05, seed=91)
+    w, off, lam = case["w"], case["offsets"], case["lam"]
+    gb = gpu_forward(w, off, lam, batched=True)
+    gp = gpu_forward(w, off, lam, batched=False)
+    for k in ("out", "perm", "start"):
+        assert np.array_equal(gb[k], gp[k]), k
+    cert = pins.kkt_certificate_segments(w, off, gb["out"], lam, tol_rel=1e-6, perm=gb["perm"], start=gb["start"])
+    _say("  2^27 certificate", cert, "clusters", int(gb["start"].sum()))
+    assert cert["ok"]
+    sw = np.add.reduceat(w.astype(np.float64), off[:-1])
+    su = np.add.reduceat(gb["out"].astype(np.float64), off[:-1])
+    assert np.all(np.abs(sw - su) <= 1e-6 * np.abs(w).max() * np.diff(off) ** 0.5 + 1e-3)
+
+
+def test_many_long_segments_one_sweep():
+    """Dozens of long segments of uneven lengths (one tile up to several thousand, both sides of
+    every merge-launch boundary) with short ones between them, batched (one launch sequence for
+    all long segments) against the plain entry point (one segment at a time) and the oracle,
+    forward and backward, per-segment lambdas."""
+    rng = np.random.default_rng(92)
+    lens = []
+    for i in range(40):
+        lens.append(int(rng.choice([8193, 9000, 4096 * 16 + 1, 4096 * 17, 4096 * 256 + 5, 300000, 2049])))
+        lens.append(int(rng.integers(1, 5000)))
+    case = workloads.random_segments(lens, "mixed", 0.05, seed=93)
+    lam_arr = (10.0 ** rng.uniform(-3, 0, len(lens))).astype(np.float32)
+    g1, _, _ = _check(case, batched=True, lam_arr=lam_arr)
+    g2 = gpu_forward(case["w"], case["offsets"], case["lam"], batched=False)
+    g3 = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
+    for k in ("out", "perm", "start"):
+        assert np.array_equal(g2[k], g3[k]), k
+    _check_backward(case, batched=True)
