@@ -167,7 +167,8 @@ typedef struct wsr_plan wsr_plan; /* opaque, owned by the library */
  *   only (Sec. 4.3 search collisions on hulls), without the ImminentCollisions rounds
  *   (Sec. 4.1) that the default route tries first; results are identical, only the time
  *   differs (for comparing the two routes).
- * On success *plan receives a new plan; free it with wsr_plan_destroy.
+ * On success *plan receives a new plan; free it with wsr_plan_destroy (which returns
+ * WSR_ERR_INVALID for a NULL plan).
  */
 #define WSR_PLAN_MERGE_HULL 2
 /* WSR_PLAN_MERGE_END: short segments merge by EndCollisions (Sec. 4.2, Alg. end_collisions: the
