@@ -597,9 +597,46 @@ def merge_route_figures(steps, warmup):
                 if route == "autotuned":
                     wsr.wsr_plan_autotune(plan, w, out, None, case["lam"], ws)
                     row["autotuned_rounds"] = wsr.wsr_plan_merge_rounds(plan)
+                    row["autotuned_sort"] = wsr.wsr_plan_sort_routes(plan)
                 fn = lambda: wsr.wsr_prox_forward_batched(plan, w, out, None, case["lam"], None, None, ws)
                 reps = 5 if route == "end_collisions" and name == "mlp_rows" else MED_REPS  # ~0.1 s a call
                 row["ms_" + route] = round(median_ms(fn, reps, 2 if reps < MED_REPS else MED_WARMUP), 4)
+            finally:
+                wsr.wsr_plan_destroy(plan)
+        res[name] = row
+    return res
+
+
+def sort_route_figures():
+    """The short classes' sort routes side by side (inference forward, batched, default merge
+    route): the bucket-rank sort (the radix sort when a bucket overflows), the radix sort alone,
+    and the autotuned choice, on the MLP rows and on the same rows quantised to 1/64 of the
+    weights' scale (a few hundred distinct values per row: many equal weights, as in weights that
+    are already shared)."""
+    import torch
+    import paper_2311_03096_amd as wsr
+    from paper_2311_03096_amd import workloads
+    base = workloads.mlp_rows()
+    scale = np.sqrt(3072.0) * 64.0
+    quant = (np.round(base["w"].astype(np.float64) * scale) / scale).astype(np.float32)
+    res = {}
+    for name, w_np in (("mlp_rows", base["w"]), ("mlp_rows_quantised_1_64", quant)):
+        w = torch.from_numpy(w_np).cuda()
+        out = torch.empty_like(w)
+        row = dict(distinct_values_first_row=int(np.unique(w_np[:3072]).shape[0]))
+        for route in ("bucket", "radix", "autotuned"):
+            plan = wsr.wsr_plan_create(base["offsets"])
+            try:
+                nb = wsr.wsr_plan_workspace_bytes(plan)
+                ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+                if route == "autotuned":
+                    wsr.wsr_plan_autotune(plan, w, out, None, base["lam"], ws)
+                    row["autotuned_sort"] = wsr.wsr_plan_sort_routes(plan)
+                    row["autotuned_rounds"] = wsr.wsr_plan_merge_rounds(plan)
+                else:
+                    wsr.wsr_plan_set_sort_routes(plan, [wsr.WSR_SORT_RADIX if route == "radix" else wsr.WSR_SORT_BUCKET] * 3)
+                fn = lambda: wsr.wsr_prox_forward_batched(plan, w, out, None, base["lam"], None, None, ws)
+                row["ms_" + route] = round(median_ms(fn), 4)
             finally:
                 wsr.wsr_plan_destroy(plan)
         res[name] = row
@@ -702,6 +739,8 @@ def main():
         log("lds probe", extra["lds_probe"])
         extra["merge_routes"] = merge_route_figures(max(5, args.steps), args.warmup)
         log("merge routes", extra["merge_routes"])
+        extra["sort_routes"] = sort_route_figures()
+        log("sort routes", extra["sort_routes"])
         lay = workloads.mlp_layers()
         st = Step(lay, batched=True)
         ms_l = median_ms(st)

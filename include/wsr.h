@@ -217,6 +217,23 @@ WSR_API int wsr_plan_merge_rounds(const wsr_plan* plan, int32_t* rounds);
 WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
 
 /*
+ * Sort route per short size class (2048, 4096, 8192), the sort step of Alg. prox for segments
+ * that fit one workgroup: WSR_SORT_BUCKET (default) sorts by value buckets and ranks inside each
+ * bucket, taking the LDS radix sort only when a bucket overflows; WSR_SORT_RADIX takes the LDS
+ * radix sort at once.  Both give the same sorted order (by value, then index), so results are
+ * identical; the bucket sort is faster on spread-out weights, the radix sort on rows with many
+ * equal weights (quantised or already shared).  wsr_plan_autotune and wsr_plan_autotune_step time
+ * the radix route against the bucket route with each class's chosen merge route and keep the
+ * faster.  wsr_plan_sort_routes writes 3 values; wsr_plan_set_sort_routes sets them (host only;
+ * WSR_ERR_INVALID for another value).  The batched forward, l1 forward, step and statistics use
+ * them; the per-segment entry points use the bucket route.
+ */
+#define WSR_SORT_BUCKET 0
+#define WSR_SORT_RADIX 1
+WSR_API int wsr_plan_sort_routes(const wsr_plan* plan, int32_t* routes);
+WSR_API int wsr_plan_set_sort_routes(wsr_plan* plan, const int32_t* routes);
+
+/*
  * Sticky status of a plan's batched calls (forward, l1 forward, step): bit WSR_STATUS_NONFINITE
  * is set on the device when any segment held a NaN or +-Inf input weight (that segment's
  * outputs are NaN, as documented above) and stays set until read with clear != 0.  Enqueues the
@@ -228,8 +245,9 @@ WSR_API int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds);
 WSR_API int wsr_read_status(const wsr_plan* plan, uint32_t* flags, int clear, void* stream);
 
 /* A plan may be used by calls on any stream, but calls that overlap in time must not share a
- * workspace; wsr_plan_autotune and wsr_plan_set_merge_rounds change the plan and must not run
- * while other calls with the same plan are being issued from another host thread. */
+ * workspace; wsr_plan_autotune(_step), wsr_plan_set_merge_rounds and wsr_plan_set_sort_routes
+ * change the plan and must not run while other calls with the same plan are being issued from
+ * another host thread. */
 
 /* Workspace bytes needed by the batched calls of this plan. */
 WSR_API int wsr_plan_workspace_bytes(const wsr_plan* plan, size_t* bytes);

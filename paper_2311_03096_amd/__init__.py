@@ -7,7 +7,8 @@ is its ctypes binding (same names) plus torch wrappers for autograd and batched 
 from ._lib import (Plan, WSR_ERR_HIP, WSR_ERR_INVALID, WSR_ERR_UNSUPPORTED, WSR_ERR_WORKSPACE,
                    WSR_MAX_SEGMENT, WSR_OK, WSR_PLAN_MERGE_END, WSR_PLAN_MERGE_HULL, WsrError, load,
                    wsr_plan_autotune, wsr_plan_autotune_step, wsr_plan_create, wsr_plan_destroy, wsr_plan_merge_rounds,
-                   wsr_plan_set_merge_rounds, wsr_read_status, WSR_STATUS_NONFINITE,
+                   wsr_plan_set_merge_rounds, wsr_plan_sort_routes, wsr_plan_set_sort_routes, WSR_SORT_BUCKET,
+                   WSR_SORT_RADIX, wsr_read_status, WSR_STATUS_NONFINITE,
                    wsr_plan_workspace_bytes,
                    wsr_prox_backward, wsr_prox_backward_batched, wsr_prox_forward, wsr_prox_forward_noalloc,
                    WSR_NOALLOC_MAX_SEGMENT, WSR_NOALLOC_SCRATCH_BYTES,
@@ -28,5 +29,6 @@ __all__ = [
     "WSR_OK", "WSR_ERR_INVALID", "WSR_ERR_WORKSPACE", "WSR_ERR_HIP", "WSR_ERR_UNSUPPORTED",
     "WSR_PLAN_MERGE_HULL", "WSR_PLAN_MERGE_END", "WSR_MAX_SEGMENT", "wsr_plan_autotune", "wsr_plan_autotune_step",
     "wsr_plan_merge_rounds", "Plan",
-    "wsr_plan_set_merge_rounds", "wsr_read_status", "WSR_STATUS_NONFINITE",
+    "wsr_plan_set_merge_rounds", "wsr_plan_sort_routes", "wsr_plan_set_sort_routes", "WSR_SORT_BUCKET",
+    "WSR_SORT_RADIX", "wsr_read_status", "WSR_STATUS_NONFINITE",
 ]

@@ -31,6 +31,7 @@ EXPORTED = (
     "wsr_prox_l1_forward", "wsr_prox_l1_forward_batched", "wsr_prox_step_batched",
     "wsr_segment_stats", "wsr_segment_stats_batched", "wsr_plan_autotune", "wsr_plan_merge_rounds",
     "wsr_plan_set_merge_rounds", "wsr_read_status", "wsr_plan_autotune_step", "wsr_prox_forward_noalloc",
+    "wsr_plan_sort_routes", "wsr_plan_set_sort_routes",
 )
 
 
@@ -68,6 +69,8 @@ def load():
         "wsr_plan_autotune": ([p, p, p, p, f32, p, sz, p], i32),
         "wsr_plan_merge_rounds": ([p, p], i32),
         "wsr_plan_set_merge_rounds": ([p, p], i32),
+        "wsr_plan_sort_routes": ([p, p], i32),
+        "wsr_plan_set_sort_routes": ([p, p], i32),
         "wsr_read_status": ([p, ctypes.POINTER(ctypes.c_uint32), i32, p], i32),
         "wsr_plan_autotune_step": ([p, p, p, f32, p, p, f32, f32, f32, i32, p, sz, p], i32),
         "wsr_segment_stats_batched": ([p, p, p, p, sz, p], i32),
@@ -346,6 +349,23 @@ def wsr_plan_merge_rounds(plan):
 def wsr_plan_set_merge_rounds(plan, rounds):
     r = (ctypes.c_int32 * 4)(*[int(x) for x in rounds])
     _check("wsr_plan_set_merge_rounds", load().wsr_plan_set_merge_rounds(_plan(plan), ctypes.cast(r, ctypes.c_void_p)))
+
+
+WSR_SORT_BUCKET = 0
+WSR_SORT_RADIX = 1
+
+
+def wsr_plan_sort_routes(plan):
+    """The plan's sort route per short size class (2048, 4096, 8192): WSR_SORT_BUCKET or
+    WSR_SORT_RADIX."""
+    r = (ctypes.c_int32 * 3)()
+    _check("wsr_plan_sort_routes", load().wsr_plan_sort_routes(_plan(plan), ctypes.cast(r, ctypes.c_void_p)))
+    return list(r)
+
+
+def wsr_plan_set_sort_routes(plan, routes):
+    r = (ctypes.c_int32 * 3)(*[int(x) for x in routes])
+    _check("wsr_plan_set_sort_routes", load().wsr_plan_set_sort_routes(_plan(plan), ctypes.cast(r, ctypes.c_void_p)))
 
 
 def wsr_read_status(plan, clear=True, stream=None):

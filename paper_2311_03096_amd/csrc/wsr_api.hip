@@ -537,6 +537,8 @@ struct wsr_plan {
   // (short classes only)
   int rounds[kNumSmall + 1] = {kIcaRounds, kIcaRounds, kIcaRounds, kIcaRounds};
   int small_route(int c) const { return rounds[c] >= 0 ? rounds[c] : kRouteEnd; }
+  // sort route per short size class (kSortBucket or kSortRadix)
+  int sort[kNumSmall] = {kSortBucket, kSortBucket, kSortBucket};
   uint32_t* d_status = nullptr;  // sticky status word (kStatusNonFinite), read by wsr_read_status
   // the long segments as one set, solved by one launch sequence; its device tables live in d_tables
   LongSetHost longs;
@@ -675,6 +677,7 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
               l1.beta, l1.rho, l1.on, l1.kappa};
     a.merge_rounds = plan->small_route(c);
     a.status = plan->d_status;
+    a.sort_route = plan->sort[c];
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
   if (!plan->longs.segs.empty()) {
@@ -709,11 +712,12 @@ int step_args_ok(const wsr_plan* plan, const float* w, const float* grad, float 
   return WSR_OK;
 }
 
-// The fused launch of size class c over its first nblocks segments with merge route `route`.
-void step_small(const wsr_plan* plan, int c, int nblocks, int route, const float* w, const float* grad, float eta,
-                float* out, const float* d_alpha, float alpha_scalar, const StepForm& f, hipStream_t s) {
+// The fused launch of size class c over its first nblocks segments with merge route `route` and
+// sort route `sort`.
+void step_small(const wsr_plan* plan, int c, int nblocks, int route, int sort, const float* w, const float* grad,
+                float eta, float* out, const float* d_alpha, float alpha_scalar, const StepForm& f, hipStream_t s) {
   SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_alpha, alpha_scalar, 0, 0, 0,
-            f.l1.beta, f.l1.rho, f.l1.on, f.l1.kappa, grad, eta, f.lam_mul, route, plan->d_status};
+            f.l1.beta, f.l1.rho, f.l1.on, f.l1.kappa, grad, eta, f.lam_mul, route, plan->d_status, sort};
   small_fwd(c, nblocks, a, w, out, nullptr, nullptr, s);
 }
 
@@ -735,8 +739,8 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
   hipStream_t s = (hipStream_t)stream;
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
-    step_small(plan, c, (int)plan->sched_cnt[c], plan->small_route(c), w, grad, eta, out, d_alpha, alpha_scalar, f,
-               s);
+    step_small(plan, c, (int)plan->sched_cnt[c], plan->small_route(c), plan->sort[c], w, grad, eta, out, d_alpha,
+               alpha_scalar, f, s);
   }
   if (!plan->longs.segs.empty()) {
     rc = step_big(plan, plan->rounds[kNumSmall], w, grad, eta, out, d_alpha, alpha_scalar, f, ws, s);
@@ -746,10 +750,13 @@ int step_batched_impl(const wsr_plan* plan, const float* w, const float* grad, f
 }
 
 // Autotuner core: for every short size class, times the batched launch of the class alone under
-// each candidate route and keeps the fastest; EndCollisions is a candidate only when a probe over
-// the class's first segments (one workgroup per CU pair) shows it no slower than 1.5x the default
-// route there.  Long segments: the caps {0, kIcaRounds, 16}, timed on all of them together.
-//   small(c, nblocks, route): launches class c over its first nblocks segments
+// each candidate merge route and keeps the fastest; EndCollisions is a candidate only when a probe
+// over the class's first segments (one workgroup per CU pair) shows it no slower than 1.5x the
+// default route there.  Then, with that merge route, the radix-only sort route against the
+// bucket-rank sort (the radix sort wins on rows with many equal weights, where the bucket sort
+// takes its tie path or overflows).  Long segments: the caps {0, kIcaRounds, 16}, timed on all of
+// them together.
+//   small(c, nblocks, route, sort): launches class c over its first nblocks segments
 //   big(rounds): runs the plan's long segments (one set), returns a status
 template <class SmallFn, class BigFn>
 int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
@@ -777,22 +784,29 @@ int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
     {
       const int np = std::min(cnt, 2 * cu_count());
       float t_def = 0.0f, t_end = 0.0f;
-      rc = time_it([&] { small(c, np, kIcaRounds); }, 1, &t_def);
+      rc = time_it([&] { small(c, np, kIcaRounds, kSortBucket); }, 1, &t_def);
       if (rc) break;
-      rc = time_it([&] { small(c, np, kRouteEnd); }, 1, &t_end);
+      rc = time_it([&] { small(c, np, kRouteEnd, kSortBucket); }, 1, &t_end);
       if (rc) break;
       if (t_end <= 1.5f * t_def) cand.push_back(kRouteEnd);
     }
     float best = 0.0f;
+    int best_route = kIcaRounds;
     for (size_t i = 0; i < cand.size(); ++i) {
       float ms = 0.0f;
-      rc = time_it([&] { small(c, cnt, cand[i]); }, kReps, &ms);
+      rc = time_it([&] { small(c, cnt, cand[i], kSortBucket); }, kReps, &ms);
       if (rc) break;
       if (i == 0 || ms < best) {
         best = ms;
-        plan->rounds[c] = cand[i] == kRouteEnd ? -1 : cand[i];
+        best_route = cand[i];
       }
     }
+    if (rc) break;
+    plan->rounds[c] = best_route == kRouteEnd ? -1 : best_route;
+    float t_radix = 0.0f;
+    rc = time_it([&] { small(c, cnt, best_route, kSortRadix); }, kReps, &t_radix);
+    if (rc) break;
+    plan->sort[c] = t_radix < best ? kSortRadix : kSortBucket;
   }
   if (rc == WSR_OK && !plan->longs.segs.empty()) {
     float best = 0.0f;
@@ -826,6 +840,7 @@ int autotune_impl(wsr_plan* plan, SmallFn&& small, BigFn&& big, hipStream_t s) {
 // hipGetSymbolAddress returns for the current device, looked up once per device.
 constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
 static_assert(kNoAllocScratchBytes == WSR_NOALLOC_SCRATCH_BYTES, "scratch size as declared in the header");
+static_assert(kSortBucket == WSR_SORT_BUCKET && kSortRadix == WSR_SORT_RADIX, "sort routes as declared in the header");
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 int noalloc_scratch(void** out) {
@@ -1049,6 +1064,20 @@ int wsr_plan_set_merge_rounds(wsr_plan* plan, const int32_t* rounds) {
   return WSR_OK;
 }
 
+int wsr_plan_sort_routes(const wsr_plan* plan, int32_t* routes) {
+  if (!plan || !routes) return WSR_ERR_INVALID;
+  for (int c = 0; c < kNumSmall; ++c) routes[c] = plan->sort[c];
+  return WSR_OK;
+}
+
+int wsr_plan_set_sort_routes(wsr_plan* plan, const int32_t* routes) {
+  if (!plan || !routes) return WSR_ERR_INVALID;
+  for (int c = 0; c < kNumSmall; ++c)
+    if (routes[c] != kSortBucket && routes[c] != kSortRadix) return WSR_ERR_INVALID;
+  for (int c = 0; c < kNumSmall; ++c) plan->sort[c] = routes[c];
+  return WSR_OK;
+}
+
 int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d_lambda, float lambda_scalar,
                       void* ws, size_t ws_bytes, void* stream) {
   (void)hipGetLastError();  // report only errors of this call
@@ -1059,9 +1088,10 @@ int wsr_plan_autotune(wsr_plan* plan, const float* w, float* out, const float* d
   hipStream_t s = (hipStream_t)stream;
   return autotune_impl(
       plan,
-      [&](int c, int nblocks, int route) {
+      [&](int c, int nblocks, int route, int sort) {
         SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0};
         a.merge_rounds = route;
+        a.sort_route = sort;
         small_fwd(c, nblocks, a, w, out, nullptr, nullptr, s);
       },
       [&](int rounds) {
@@ -1082,8 +1112,8 @@ int wsr_plan_autotune_step(wsr_plan* plan, const float* w, const float* grad, fl
   hipStream_t s = (hipStream_t)stream;
   return autotune_impl(
       plan,
-      [&](int c, int nblocks, int route) {
-        step_small(plan, c, nblocks, route, w, grad, eta, scratch, d_alpha, alpha_scalar, f, s);
+      [&](int c, int nblocks, int route, int sort) {
+        step_small(plan, c, nblocks, route, sort, w, grad, eta, scratch, d_alpha, alpha_scalar, f, s);
       },
       [&](int rounds) { return step_big(plan, rounds, w, grad, eta, scratch, d_alpha, alpha_scalar, f, ws, s); },
       s);
@@ -1123,6 +1153,7 @@ int wsr_segment_stats_batched(const wsr_plan* plan, const float* w, wsr_segment_
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], nullptr, 0.0f, 0, 0, 0};
+    a.sort_route = plan->sort[c];
     small_stats(c, (int)plan->sched_cnt[c], a, w, st, s);
   }
   if (!plan->longs.segs.empty()) {

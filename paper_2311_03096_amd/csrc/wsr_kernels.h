@@ -35,7 +35,13 @@ struct SegArgs {
   int merge_rounds = -1;  // cap on ImminentCollisions rounds before the hull merge (-1: default,
                           // 0: hull merge only), or kRouteEnd: EndCollisions
   uint32_t* status = nullptr;  // sticky status word: bit 0 is OR-ed in for a non-finite segment
+  int sort_route = 0;  // kSortBucket: bucket-rank sort (the radix sort when a bucket overflows),
+                       // kSortRadix: the LDS radix sort only
 };
+
+// Sort routes of the short-segment kernels.
+constexpr int kSortBucket = 0;
+constexpr int kSortRadix = 1;
 
 // Bits of the sticky status word of a plan.
 constexpr uint32_t kStatusNonFinite = 1u;

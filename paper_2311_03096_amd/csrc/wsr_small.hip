@@ -562,7 +562,8 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     return;
   }
 
-  if (!block_bucket_sort<TMAX, NT>(sm, k, ix, d)) block_radix_sort<TMAX, NT>(sm, k, ix, d);
+  if (args.sort_route == kSortRadix || !block_bucket_sort<TMAX, NT>(sm, k, ix, d))
+    block_radix_sort<TMAX, NT>(sm, k, ix, d);
 
   // centred FP64 prefix sums S_k (blocked: thread t owns ranks [tE, tE+E)); S overwrites the
   // sorted keys, so every key is read before the block scan's barriers
@@ -700,7 +701,8 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_seg_stats_smal
     if (tid == 0) stats[sid] = SegStats{__builtin_nan(""), -1, -1};
     return;
   }
-  if (!block_bucket_sort<TMAX, NT>(sm, k, ix, d)) block_radix_sort<TMAX, NT>(sm, k, ix, d);
+  if (args.sort_route == kSortRadix || !block_bucket_sort<TMAX, NT>(sm, k, ix, d))
+    block_radix_sort<TMAX, NT>(sm, k, ix, d);
   const uint32_t* skey = sm.c.bs.key;
   const double c = (double)key_to_float(skey[d >> 1]);
   const int k0 = tid * E;

@@ -57,9 +57,11 @@ def tuning_key(offsets, arch, flags=0, kind="forward"):
 
 
 class TuningCache:
-    """Merge routes found by the autotuner, persisted as JSON {key: [4 routes]} and keyed by
-    ``tuning_key`` so that a later run with the same architecture and segment layout reuses them
-    without timing again.  Writes are atomic (temporary file + rename)."""
+    """Routes found by the autotuner, persisted as JSON {key: {"rounds": [4 merge routes],
+    "sort": [3 sort routes]}} and keyed by ``tuning_key`` so that a later run with the same
+    architecture and segment layout reuses them without timing again (an entry of the older form,
+    the 4 merge routes alone, reads with the bucket sort route).  Writes are atomic (temporary
+    file + rename)."""
 
     def __init__(self, path=None):
         self.path = path or os.environ.get("WSR_TUNING_CACHE") or os.path.join(
@@ -74,16 +76,23 @@ class TuningCache:
         except (OSError, ValueError):
             return {}
 
+    @staticmethod
+    def _ints(v, n):
+        return isinstance(v, list) and len(v) == n and all(isinstance(x, int) for x in v)
+
     def get(self, key):
+        """{"rounds": [4], "sort": [3]} stored under key, or None."""
         r = self._read().get(key)
-        if isinstance(r, list) and len(r) == 4 and all(isinstance(x, int) for x in r):
-            return r
+        if self._ints(r, 4):
+            return {"rounds": r, "sort": [0, 0, 0]}
+        if isinstance(r, dict) and self._ints(r.get("rounds"), 4) and self._ints(r.get("sort"), 3):
+            return {"rounds": r["rounds"], "sort": r["sort"]}
         return None
 
-    def put(self, key, rounds):
+    def put(self, key, rounds, sort=(0, 0, 0)):
         with self._lock:
             data = self._read()
-            data[key] = [int(x) for x in rounds]
+            data[key] = {"rounds": [int(x) for x in rounds], "sort": [int(x) for x in sort]}
             d = os.path.dirname(self.path)
             if d:
                 os.makedirs(d, exist_ok=True)
@@ -101,7 +110,7 @@ class BatchedProx:
     ``forward(w, out, lam)`` runs the batched prox; with ``save=True`` the saved permutation and
     cluster-start bits for ``backward`` are kept in this object.  ``capture()`` records one
     forward into a HIP graph (torch.cuda.CUDAGraph) for replay with ``replay()``.
-    ``autotune=True`` times the merge routes on the first call's inputs (wsr_plan_autotune, or
+    ``autotune=True`` times the merge and sort routes on the first call's inputs (wsr_plan_autotune, or
     wsr_plan_autotune_step for ``step``), into a scratch buffer; with ``tuning_cache`` (a
     ``TuningCache`` or a path) a stored tuning for the same architecture and segment layout is
     reused and a new one stored.  ``hull_only=True`` merges by the hull merge alone (for
@@ -140,15 +149,19 @@ class BatchedProx:
         key = tuning_key(self.offsets, device_arch(self.device), self.flags, kind) if self.tuning_cache else None
         cached = self.tuning_cache.get(key) if key else None
         if cached is not None:
-            _lib.wsr_plan_set_merge_rounds(self.plan, cached)
+            _lib.wsr_plan_set_merge_rounds(self.plan, cached["rounds"])
+            _lib.wsr_plan_set_sort_routes(self.plan, cached["sort"])
         else:
             run()
             if key:
-                self.tuning_cache.put(key, _lib.wsr_plan_merge_rounds(self.plan))
+                self.tuning_cache.put(key, _lib.wsr_plan_merge_rounds(self.plan), _lib.wsr_plan_sort_routes(self.plan))
         self.tune_pending = False
 
     def merge_rounds(self):
         return _lib.wsr_plan_merge_rounds(self.plan)
+
+    def sort_routes(self):
+        return _lib.wsr_plan_sort_routes(self.plan)
 
     def forward(self, w, out, lam=None, lam_scalar=0.0, save=True):
         scratch = None

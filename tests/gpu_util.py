@@ -60,7 +60,8 @@ def seg_start_of_rank(offsets):
     return np.repeat(offsets[:-1], lens)
 
 
-def gpu_forward(w, offsets, lam, save=True, batched=False, lam_arr=None, plan_flags=0, autotune=False):
+def gpu_forward(w, offsets, lam, save=True, batched=False, lam_arr=None, plan_flags=0, autotune=False,
+                sort_routes=None):
     wt = dev(w)
     out = torch.empty_like(wt)
     n = w.shape[0]
@@ -72,6 +73,8 @@ def gpu_forward(w, offsets, lam, save=True, batched=False, lam_arr=None, plan_fl
             nb = wsr.wsr_plan_workspace_bytes(plan)
             ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
             la = dev(np.asarray(lam_arr, np.float32)) if lam_arr is not None else None
+            if sort_routes is not None:
+                wsr.wsr_plan_set_sort_routes(plan, sort_routes)
             if autotune:
                 wsr.wsr_plan_autotune(plan, wt, out, la, lam, ws)
             wsr.wsr_prox_forward_batched(plan, wt, out, la, lam, perm, mask, ws)

@@ -94,6 +94,8 @@ int main() {
   int32_t rounds[4] = {0};
   expect(wsr_plan_merge_rounds(nullptr, rounds), WSR_ERR_INVALID, "plan_merge_rounds(null)");
   expect(wsr_plan_set_merge_rounds(nullptr, rounds), WSR_ERR_INVALID, "plan_set_merge_rounds(null)");
+  expect(wsr_plan_sort_routes(nullptr, rounds), WSR_ERR_INVALID, "plan_sort_routes(null)");
+  expect(wsr_plan_set_sort_routes(nullptr, rounds), WSR_ERR_INVALID, "plan_set_sort_routes(null)");
   uint32_t flags = 0;
   expect(wsr_read_status(nullptr, &flags, 0, nullptr), WSR_ERR_INVALID, "read_status(null)");
   expect(wsr_prox_forward_batched(nullptr, buf, buf, nullptr, 0.1f, nullptr, nullptr, ws, sizeof ws, nullptr),

@@ -22,7 +22,7 @@ def _declared_symbols():
 
 def test_header_matches_exports():
     declared = _declared_symbols()
-    assert len(declared) == 23
+    assert len(declared) == 25
     lib = wsr.load()
     for name in declared:
         assert hasattr(lib, name), name
@@ -164,6 +164,8 @@ def test_plan_argument_errors():
     assert lib.wsr_plan_autotune(None, FAKE, FAKE, None, ctypes.c_float(0.1), None, 0, None) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_plan_set_merge_rounds(None, FAKE) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_plan_sort_routes(None, FAKE) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_plan_set_sort_routes(None, FAKE) == wsr.WSR_ERR_INVALID
     assert lib.wsr_read_status(None, None, 0, None) == wsr.WSR_ERR_INVALID
     f = ctypes.c_float
     assert lib.wsr_plan_autotune_step(None, FAKE, FAKE, f(0.1), ctypes.c_void_p(512), None, f(0.1), f(0.0), f(0.0), 0,
@@ -303,10 +305,18 @@ def test_tuning_key_and_cache(tmp_path):
     assert tuning_key(off[:-1], "gfx950", 0, "forward") != k
     cache = TuningCache(str(tmp_path / "sub" / "tuning.json"))
     assert cache.get(k) is None
-    cache.put(k, [6, 64, -1, 16])
-    assert TuningCache(cache.path).get(k) == [6, 64, -1, 16]
+    cache.put(k, [6, 64, -1, 16], [0, 1, 0])
+    assert TuningCache(cache.path).get(k) == {"rounds": [6, 64, -1, 16], "sort": [0, 1, 0]}
     cache.put("other", [0, 0, 0, 0])
-    assert cache.get(k) == [6, 64, -1, 16] and cache.get("other") == [0, 0, 0, 0]
+    assert cache.get(k)["rounds"] == [6, 64, -1, 16] and cache.get("other") == {"rounds": [0, 0, 0, 0],
+                                                                                "sort": [0, 0, 0]}
+    import json
+    with open(cache.path) as f:
+        data = json.load(f)
+    data["old"] = [2, 2, 2, 0]  # the older form: merge routes alone
+    with open(cache.path, "w") as f:
+        json.dump(data, f)
+    assert cache.get("old") == {"rounds": [2, 2, 2, 0], "sort": [0, 0, 0]}
     with open(cache.path, "w") as f:
         f.write("not json")
     assert cache.get(k) is None  # a damaged file is ignored, not fatal

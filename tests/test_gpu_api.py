@@ -119,17 +119,39 @@ def test_tuning_cache_round_trip(tmp_path):
     a.forward(w, out1, lam_scalar=case["lam"])
     key = ops.tuning_key(off, ops.device_arch(), 0, "forward")
     stored = ops.TuningCache(path).get(key)
-    assert stored == a.merge_rounds()
+    assert stored == {"rounds": a.merge_rounds(), "sort": a.sort_routes()}
     # a different stored tuning is applied as is, with no timing (the plan's routes become it)
-    forced = [6, 0, 16, 0]
-    ops.TuningCache(path).put(key, forced)
+    forced, forced_sort = [6, 0, 16, 0], [1, 1, 0]
+    ops.TuningCache(path).put(key, forced, forced_sort)
     b = ops.BatchedProx(off, autotune=True, tuning_cache=path)
     b.forward(w, out2, lam_scalar=case["lam"])
-    assert b.merge_rounds() == forced and not b.tune_pending
+    assert b.merge_rounds() == forced and b.sort_routes() == forced_sort and not b.tune_pending
     torch.cuda.synchronize()
     assert torch.equal(out1, out2)  # every route gives the same result
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("dist", ["normal", "quantised", "ties"])
+def test_sort_routes_give_the_same_bits(dist):
+    """The short classes' two sort routes (the bucket-rank sort, with the radix sort when a bucket
+    overflows; the radix sort alone) give identical outputs, permutations and cluster starts (both
+    order by value, then index) on spread-out, quantised and tie-heavy rows of every size class,
+    matching the oracle; the autotuned routes give the same bits again."""
+    lens = [17, 1, 2049] + [2048] * 30 + [3072] * 30 + [4096] * 30 + [6000] * 10 + [8192] * 6
+    case = workloads.random_segments(lens, "ties" if dist == "ties" else "normal", 1e-3, seed=66)
+    w = case["w"]
+    if dist == "quantised":  # 1/64 steps: a few equal weights per value
+        w = (np.round(w.astype(np.float64) * 64) / 64).astype(np.float32)
+    off, lam = case["offsets"], case["lam"]
+    a = gpu_forward(w, off, lam, batched=True, sort_routes=[wsr.WSR_SORT_BUCKET] * 3)
+    b = gpu_forward(w, off, lam, batched=True, sort_routes=[wsr.WSR_SORT_RADIX] * 3)
+    c = gpu_forward(w, off, lam, batched=True, autotune=True)
+    for k in ("out", "perm", "start"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+    _say("sort routes", dist, "clusters", int(a["start"].sum()))
+    compare(w, off, a, oracle_forward(w, off, lam), lam=lam)
 
 
 def test_read_status_on_its_stream():
