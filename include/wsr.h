@@ -183,7 +183,8 @@ WSR_API int wsr_plan_destroy(wsr_plan* plan);
  * Autotuner: times the merge routes of every size class of the plan on the caller's weights
  * (the batched forward of that class alone, without saved state: a warm-up launch and three
  * timed ones per route) and keeps the fastest route of each class in the plan for every later
- * batched call.  Routes of the short classes: a cap of 0 (hull merge only), 2, 6, 16 or 64
+ * batched call; then, for each short class, the radix sort route against the bucket sort route
+ * with that merge route (see wsr_plan_sort_routes).  Routes of the short classes: a cap of 0 (hull merge only), 2, 6, 16 or 64
  * ImminentCollisions rounds before the hull merge, and EndCollisions (Sec. 4.2) when a probe over
  * the class's first segments finds it no slower than 1.5x the default route there; long
  * segments: a cap of 0, 6 or 16, timed on the longest one.  Synchronises the stream; not for use

@@ -154,6 +154,42 @@ def test_sort_routes_give_the_same_bits(dist):
     compare(w, off, a, oracle_forward(w, off, lam), lam=lam)
 
 
+def test_sort_routes_l1_step_and_stats():
+    """The batched l1 forward, proximal-gradient step and segment statistics give the same bits
+    under both sort routes, on tie-heavy rows (where the routes differ most in time)."""
+    lens = [2048] * 20 + [4096] * 20 + [7000] * 5 + [3]
+    case = workloads.random_segments(lens, "normal", 1e-3, seed=67)
+    w_np = (np.round(case["w"].astype(np.float64) * 32) / 32).astype(np.float32)
+    off = case["offsets"]
+    g_np = np.random.default_rng(68).standard_normal(w_np.shape[0]).astype(np.float32)
+    w, g = dev(w_np), dev(g_np)
+    res = []
+    for route in (wsr.WSR_SORT_BUCKET, wsr.WSR_SORT_RADIX):
+        plan = wsr.wsr_plan_create(off)
+        try:
+            wsr.wsr_plan_set_sort_routes(plan, [route] * 3)
+            assert wsr.wsr_plan_sort_routes(plan) == [route] * 3
+            nb = wsr.wsr_plan_workspace_bytes(plan)
+            ws = torch.empty(nb, dtype=torch.uint8, device="cuda") if nb else None
+            o1, o2 = torch.empty_like(w), torch.empty_like(w)
+            wsr.wsr_prox_l1_forward_batched(plan, w, o1, None, 0.05, 0.01, 0.5, ws)
+            wsr.wsr_prox_step_batched(plan, w, g, 0.1, o2, None, 1e-2, 0.01, 0.98, 0, ws)
+            st = torch.full((len(lens), 3), -7, dtype=torch.int64, device="cuda")  # every record written
+            wsr.wsr_segment_stats_batched(plan, w, st, ws)
+            torch.cuda.synchronize()
+            res.append((o1.cpu().numpy(), o2.cpu().numpy(), st.cpu().numpy()))
+        finally:
+            wsr.wsr_plan_destroy(plan)
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    with pytest.raises(wsr.WsrError):
+        plan = wsr.wsr_plan_create(off)
+        try:
+            wsr.wsr_plan_set_sort_routes(plan, [0, 2, 0])
+        finally:
+            wsr.wsr_plan_destroy(plan)
+
+
 def test_read_status_on_its_stream():
     """The status read synchronises only the stream it is given: work on that stream is covered."""
     case = workloads.random_segments([3000, 20000], "normal", 0.05, seed=66)
