@@ -607,6 +607,12 @@ def merge_route_figures(steps, warmup):
     return res
 
 
+def quantised_rows(w):
+    """The MLP rows' weights rounded to 1/64 of their scale (1/sqrt(3072))."""
+    scale = np.sqrt(3072.0) * 64.0
+    return (np.round(w.astype(np.float64) * scale) / scale).astype(np.float32)
+
+
 def sort_route_figures():
     """The short classes' sort routes side by side (inference forward, batched, default merge
     route): the bucket-rank sort (the radix sort when a bucket overflows), the radix sort alone,
@@ -617,8 +623,7 @@ def sort_route_figures():
     import paper_2311_03096_amd as wsr
     from paper_2311_03096_amd import workloads
     base = workloads.mlp_rows()
-    scale = np.sqrt(3072.0) * 64.0
-    quant = (np.round(base["w"].astype(np.float64) * scale) / scale).astype(np.float32)
+    quant = quantised_rows(base["w"])
     res = {}
     for name, w_np in (("mlp_rows", base["w"]), ("mlp_rows_quantised_1_64", quant)):
         w = torch.from_numpy(w_np).cuda()
@@ -640,6 +645,88 @@ def sort_route_figures():
             finally:
                 wsr.wsr_plan_destroy(plan)
         res[name] = row
+    return res
+
+
+PHASES = ("load_and_key", "sort", "prefix_sums", "collisions_and_values", "stores")
+
+
+def phase_clock_figures():
+    """Where the short-segment forward spends its time: the measurement build libwsr_phases.so
+    (the same kernels, with one thread of each workgroup reading the device wall clock after the
+    barrier that closes each phase) on the MLP rows and on the same rows quantised to 1/64, under
+    both sort routes (inference forward, batched, default merge route).  Per phase: the mean and
+    median over workgroups of its duration and its share of a workgroup's lifetime; per launch:
+    the span from the first start to the last end and the mean number of workgroups in flight per
+    CU; and the launch time of the regular build next to the timestamped one."""
+    import ctypes
+    import torch
+    from paper_2311_03096_amd import workloads
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2311_03096_amd", "libwsr_phases.so"))
+    p, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.wsr_plan_create.argtypes = [p, i64, ctypes.c_int, ctypes.POINTER(p)]
+    lib.wsr_plan_destroy.argtypes = [p]
+    lib.wsr_plan_set_sort_routes.argtypes = [p, p]
+    lib.wsr_prox_forward_batched.argtypes = [p, p, p, p, ctypes.c_float, p, p, p, ctypes.c_size_t, p]
+    lib.wsr_phase_clock_buffer.argtypes = [p, i64]
+    lib.wsr_phase_clock_rate_khz.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    lib.wsr_phase_occupancy.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    slots = lib.wsr_phase_clock_slots()
+    occ = ctypes.c_int()
+    if lib.wsr_phase_occupancy(1, ctypes.byref(occ)) != 0:
+        raise RuntimeError("wsr_phase_occupancy failed")
+    khz = ctypes.c_int()
+    if lib.wsr_phase_clock_rate_khz(ctypes.byref(khz)) != 0 or khz.value <= 0:
+        raise RuntimeError("no wall-clock rate")
+    base = workloads.mlp_rows()
+    off = np.ascontiguousarray(base["offsets"], dtype=np.int64)
+    nseg = off.shape[0] - 1
+    clocks = torch.zeros(nseg * slots, dtype=torch.int64, device="cuda")
+    stream = p(torch.cuda.current_stream().cuda_stream)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res = dict(workload="mlp_rows, lam=1e-3, forward batched", workgroups=nseg, clock_mhz=khz.value / 1e3,
+               occupancy_limit_per_cu=occ.value)
+    for name, w_np in (("mlp_rows", base["w"]), ("mlp_rows_quantised_1_64", quantised_rows(base["w"]))):
+        w = torch.from_numpy(w_np).cuda()
+        out = torch.empty_like(w)
+        for route, rname in ((0, "bucket"), (1, "radix")):
+            plan = p()
+            if lib.wsr_plan_create(off.ctypes.data, nseg, 0, ctypes.byref(plan)) != 0:
+                raise RuntimeError("wsr_plan_create failed")
+            try:
+                if lib.wsr_plan_set_sort_routes(plan, (ctypes.c_int32 * 3)(route, route, route)) != 0:
+                    raise RuntimeError("wsr_plan_set_sort_routes failed")
+
+                def fn():
+                    rc = lib.wsr_prox_forward_batched(plan, p(w.data_ptr()), p(out.data_ptr()), None, base["lam"],
+                                                      None, None, None, 0, stream)
+                    if rc != 0:
+                        raise RuntimeError("wsr_prox_forward_batched: %d" % rc)
+                lib.wsr_phase_clock_buffer(None, 0)
+                ms_plain = median_ms(fn, 20, 5)
+                clocks.zero_()
+                if lib.wsr_phase_clock_buffer(p(clocks.data_ptr()), nseg) != 0:
+                    raise RuntimeError("wsr_phase_clock_buffer failed")
+                ms_clocked = median_ms(fn, 20, 5)  # the last call's timestamps stay in the buffer
+                torch.cuda.synchronize()
+                lib.wsr_phase_clock_buffer(None, 0)
+                t = clocks.view(nseg, slots)[:, :len(PHASES) + 1].cpu().numpy().astype(np.float64)
+            finally:
+                lib.wsr_plan_destroy(plan)
+            t = t[t[:, -1] > 0] / (khz.value * 1e-3)  # ticks -> us
+            dur = np.diff(t, axis=1)
+            life = t[:, -1] - t[:, 0]
+            span = t[:, -1].max() - t[:, 0].min()
+            ev = np.concatenate([np.stack([t[:, 0], np.ones(len(t))], 1), np.stack([t[:, -1], -np.ones(len(t))], 1)])
+            ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]  # at equal times, ends before starts
+            row = dict(ms_regular_build=round(ms_plain, 4), ms_timestamped=round(ms_clocked, 4),
+                       span_us=round(span, 1), workgroup_us_mean=round(life.mean(), 2),
+                       in_flight_per_cu=round(life.sum() / span / cus, 2),
+                       in_flight_max_per_cu=round(np.cumsum(ev[:, 1]).max() / cus, 2))
+            for i, ph in enumerate(PHASES):
+                row[ph] = dict(us_mean=round(dur[:, i].mean(), 2), us_median=round(float(np.median(dur[:, i])), 2),
+                               share=round(dur[:, i].sum() / life.sum(), 3))
+            res[name + "_" + rname] = row
     return res
 
 
@@ -741,6 +828,11 @@ def main():
         log("merge routes", extra["merge_routes"])
         extra["sort_routes"] = sort_route_figures()
         log("sort routes", extra["sort_routes"])
+        try:
+            extra["phase_clocks"] = phase_clock_figures()
+        except Exception as e:  # noqa: BLE001
+            extra["phase_clocks"] = dict(error=str(e))
+        log("phase clocks", extra["phase_clocks"])
         lay = workloads.mlp_layers()
         st = Step(lay, batched=True)
         ms_l = median_ms(st)

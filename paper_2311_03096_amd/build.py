@@ -19,25 +19,42 @@ FLAGS = [
 
 PROBE_LIB = os.path.join(HERE, "libwsr_probe.so")  # LDS throughput probes (measurement only)
 PROBE_SOURCES = ["wsr_lds_probe.hip"]
+# the same sources with phase timestamps in the short-segment forward (measurement only)
+PHASE_LIB = os.path.join(HERE, "libwsr_phases.so")
 
 
-def _hipcc(sources, lib, verbose):
+def _hipcc(sources, lib, verbose, defines=()):
+    """Start hipcc on `sources` into `lib`; returns a function that waits for it and installs it."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = lib + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + [os.path.join(CSRC, s) for s in sources] + ["-o", tmp]
+    cmd = [hipcc] + FLAGS + ["-D" + m for m in defines] + [os.path.join(CSRC, s) for s in sources] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    err = "\n".join(l for l in res.stderr.splitlines() if "packed-fp32-ops" not in l)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + err)
-    os.replace(tmp, lib)
-    return lib
+    proc = subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+    def finish():
+        _, stderr = proc.communicate()
+        err = "\n".join(l for l in stderr.splitlines() if "packed-fp32-ops" not in l)
+        if proc.returncode != 0:
+            raise RuntimeError("hipcc failed:\n" + err)
+        os.replace(tmp, lib)
+        return lib
+    return finish
 
 
 def build(verbose: bool = False) -> str:
-    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
-    return _hipcc(SOURCES, LIB, verbose)
+    """Compile the three libraries side by side (each hipcc run is single-threaded)."""
+    jobs = [_hipcc(SOURCES, LIB, verbose), _hipcc(PROBE_SOURCES, PROBE_LIB, verbose),
+            _hipcc(SOURCES, PHASE_LIB, verbose, defines=("WSR_PHASE_CLOCKS",))]
+    errors = []
+    for finish in jobs:  # wait for every job before reporting, so no compiler is left running
+        try:
+            finish()
+        except RuntimeError as e:
+            errors.append(str(e))
+    if errors:
+        raise RuntimeError("\n".join(errors))
+    return LIB
 
 
 if __name__ == "__main__":

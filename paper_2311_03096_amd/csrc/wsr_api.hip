@@ -660,6 +660,13 @@ int forward_impl(const float* w, float* out, const int64_t* h_offsets, int64_t n
   return last_error();
 }
 
+#ifdef WSR_PHASE_CLOCKS
+// Measurement build: where the short-segment forward writes its phase timestamps (kPhaseSlots per
+// workgroup, the size classes of one call one after another), and for how many workgroups.
+unsigned long long* g_phase_clocks = nullptr;
+int64_t g_phase_blocks = 0;
+#endif
+
 int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const float* d_lambda,
                          float lambda_scalar, int32_t* saved_perm, uint32_t* saved_mask, void* ws,
                          size_t ws_bytes, void* stream, const L1Opt& l1) {
@@ -671,6 +678,9 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   if (saved_mask && !plan->word_aligned) zero_words(saved_mask, ceil_div(plan->total, 32), s);
+#ifdef WSR_PHASE_CLOCKS
+  int64_t clock_base = 0;
+#endif
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], d_lambda, lambda_scalar, 0, 0, 0,
@@ -678,6 +688,11 @@ int forward_batched_impl(const wsr_plan* plan, const float* w, float* out, const
     a.merge_rounds = plan->small_route(c);
     a.status = plan->d_status;
     a.sort_route = plan->sort[c];
+#ifdef WSR_PHASE_CLOCKS
+    if (g_phase_clocks && clock_base + plan->sched_cnt[c] <= g_phase_blocks)
+      a.clocks = g_phase_clocks + clock_base * kPhaseSlots;
+    clock_base += plan->sched_cnt[c];
+#endif
     small_fwd(c, (int)plan->sched_cnt[c], a, w, out, saved_perm, saved_mask, s);
   }
   if (!plan->longs.segs.empty()) {
@@ -1230,5 +1245,37 @@ int wsr_trace_collect(int max_entries, char* names, int64_t* counts, double* tot
   *n_out = n;
   return rc;
 }
+
+#ifdef WSR_PHASE_CLOCKS
+// Measurement build only (not declared in the public header): the buffer of kPhaseSlots
+// timestamps per workgroup that later batched forwards fill (null: none), and the device's
+// wall-clock rate in kHz.
+__attribute__((visibility("default"))) int wsr_phase_clock_buffer(void* clocks, int64_t n_blocks) {
+  if (n_blocks < 0 || (clocks == nullptr) != (n_blocks == 0)) return WSR_ERR_INVALID;
+  g_phase_clocks = (unsigned long long*)clocks;
+  g_phase_blocks = n_blocks;
+  return WSR_OK;
+}
+__attribute__((visibility("default"))) int wsr_phase_clock_rate_khz(int* khz) {
+  int dev = 0;
+  if (!khz || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+    return WSR_ERR_HIP;
+  return WSR_OK;
+}
+__attribute__((visibility("default"))) int wsr_phase_clock_slots(void) { return kPhaseSlots; }
+// Resident workgroups per CU of the short-segment forward of size class cls (default merge route)
+// by the runtime's occupancy calculator.
+__attribute__((visibility("default"))) int wsr_phase_occupancy(int cls, int* blocks_per_cu) {
+  if (!blocks_per_cu || cls < 0 || cls >= kNumSmall) return WSR_ERR_INVALID;
+  hipError_t e;
+  switch (cls) {
+    case kC2048: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_prox_fwd_small<2048, 256, false>, 256, 0); break;
+    case kC4096: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_prox_fwd_small<4096, 512, false>, 512, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_prox_fwd_small<8192, 1024, false>, 1024, 0); break;
+  }
+  return e == hipSuccess ? WSR_OK : WSR_ERR_HIP;
+}
+#endif
 
 }  // extern "C"

@@ -37,7 +37,27 @@ struct SegArgs {
   uint32_t* status = nullptr;  // sticky status word: bit 0 is OR-ed in for a non-finite segment
   int sort_route = 0;  // kSortBucket: bucket-rank sort (the radix sort when a bucket overflows),
                        // kSortRadix: the LDS radix sort only
+#ifdef WSR_PHASE_CLOCKS
+  unsigned long long* clocks = nullptr;  // phase timestamps (measurement build only, see below)
+#endif
 };
+
+// Measurement build (WSR_PHASE_CLOCKS): thread 0 of each workgroup of the short-segment forward
+// records the device wall clock right after the barrier that closes each phase, at
+// clocks[block * kPhaseSlots + mark]: 0 start, 1 weights loaded and keyed, 2 sorted, 3 prefix
+// sums, 4 collisions and cluster values, 5 stores issued.  The regular build has no such code.
+constexpr int kPhaseSlots = 8;
+#ifdef WSR_PHASE_CLOCKS
+#define WSR_PHASE_MARK(args, m)                                                              \
+  do {                                                                                       \
+    if (threadIdx.x == 0 && (args).clocks)                                                   \
+      (args).clocks[(int64_t)blockIdx.x * kPhaseSlots + (m)] = wall_clock64();               \
+  } while (0)
+#else
+#define WSR_PHASE_MARK(args, m) \
+  do {                          \
+  } while (0)
+#endif
 
 // Sort routes of the short-segment kernels.
 constexpr int kSortBucket = 0;

@@ -25,7 +25,9 @@ constexpr int kRankPad = 64;
 
 // LDS of the forward kernel, sized so that three workgroups of the 4096 class share a CU.  The
 // prefix sums use the transposed rank layout; the other arrays indexed by rank are flat (a
-// thread's E = 8 consecutive ranks are read as 16-byte words).
+// thread's E = 8 consecutive ranks are read as 16-byte words).  Arrays whose lifetimes do not
+// overlap share storage: the bucket sort's scratch, the collision rounds' exchange slots and the
+// hull merge's scratch are live one after another, with a barrier between each two.
 template <int TMAX, int NT>
 struct FwdSmem {
   static constexpr int E = TMAX / NT;
@@ -52,7 +54,8 @@ struct FwdSmem {
       int16_t cnt[NT];
       int16_t mres[NT];
     } h;                  // hull merge (collision rounds not converged)
-    uint16_t tidx[TMAX];  // bucket sort: indices in bucket order
+    uint16_t tidx[TMAX];     // bucket sort: indices in bucket order
+    WaveBound wb[2 * NW];    // collision rounds: wave exchange slots, two sets
   } d;
   uint32_t lmask[TMAX / 32 + 2];
   union {
@@ -62,14 +65,13 @@ struct FwdSmem {
   int tiecnt;  // bucket sort: sum over keys of the smaller keys in their bucket
   int ired[NW + 1];
   uint32_t ured[2 * NW];
-  WaveBound wb[2 * NW];  // collision exchange slots, two sets
   int flag[4];  // one slot per radix pass: "every key has the same digit"
 };
 
-// LDS is allocated in 512-byte granules: three 4096-key forward workgroups share a CU (160 KB)
-// only while the rounded size stays at or below a third of it.
-static_assert(3 * ((sizeof(FwdSmem<4096, 512>) + 511) / 512 * 512) <= 160 * 1024,
-              "three 4096-key forward workgroups per CU");
+// gfx950 allocates LDS to workgroups in granules of 1280 bytes (128 per CU): three 4096-key
+// forward workgroups share a CU only while the rounded size is at most 42 granules.  At 43 the
+// timestamps of the measurement build show at most two resident per CU.
+static_assert(3 * ((sizeof(FwdSmem<4096, 512>) + 1279) / 1280) <= 128, "three 4096-key forward workgroups per CU");
 
 struct SegView {
   int64_t start;
@@ -513,6 +515,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   const int wv = tid / kWave;
   const int wbase = wv * kWave * IPT;
   const int off = (int)(start & 31);
+  WSR_PHASE_MARK(args, 0);
 
   for (int j = tid; j < TMAX / 32 + 2; j += NT) sm.lmask[j] = 0u;
   uint32_t k[IPT];
@@ -543,6 +546,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   }
   bucket_sort_prologue<TMAX, NT>(sm, k, d);  // shares the barrier below
   const bool nonfinite = __syncthreads_or(bad) != 0;
+  WSR_PHASE_MARK(args, 1);
   if (nonfinite && tid == 0 && args.status) atomicOr(args.status, kStatusNonFinite);
   if (nonfinite || d == 1 || !(lam > 0.0f)) {
     // identity (or NaN) segment: every weight its own cluster, perm = identity
@@ -564,6 +568,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
 
   if (args.sort_route == kSortRadix || !block_bucket_sort<TMAX, NT>(sm, k, ix, d))
     block_radix_sort<TMAX, NT>(sm, k, ix, d);
+  WSR_PHASE_MARK(args, 2);
 
   // centred FP64 prefix sums S_k (blocked: thread t owns ranks [tE, tE+E)); S overwrites the
   // sorted keys, so every key is read before the block scan's barriers
@@ -594,6 +599,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   }
   if (tid == NT - 1 && d == TMAX) sm.c.S[SL::at(TMAX)] = sv[E];  // X_d (the shift term vanishes at k = d)
   __syncthreads();
+  WSR_PHASE_MARK(args, 3);
 
   // collisions: ImminentCollisions rounds (converge in a few rounds on typical weights), else
   // the bounded-depth hull merge; or, in the END instantiation (a route the caller chooses),
@@ -603,7 +609,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   bool staged = true;
   if (!END &&
       ica_rounds<NT, E, SL>(sm.c.S, sv, d, args.merge_rounds < 0 ? kIcaRounds : args.merge_rounds, &bm, &lc, &rc,
-                            sm.wb)) {
+                            sm.d.wb)) {
     if (bm) {
       const int b0 = k0 + off;
       const uint64_t wide = (uint64_t)bm << (b0 & 31);
@@ -622,6 +628,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     if constexpr (END) {
       nv = end_collisions<NT, E, SL>(sm.c.S, sv, d, sm.d.h.vert, sm.ired);
     } else {
+      __syncthreads();  // the rounds' last reads of the exchange slots, which the hull overwrites
       tile_hull<NT, E, SL, int16_t>(sm.c.S, d, sm.d.h.vert, sm.d.h.cnt, sm.d.h.mres);
       nv = sm.d.h.cnt[0];
     }
@@ -639,6 +646,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     staged = false;
   }
   __syncthreads();
+  WSR_PHASE_MARK(args, 4);
   // fixed trip count (TMAX / NT) so every LDS read is issued before the stores wait on them
   float* const og = out + start;
   if (staged) {
@@ -657,6 +665,7 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
     }
   }
   if (mask_out) store_mask_words<NT>(mask_out, start, d, sm.lmask);
+  WSR_PHASE_MARK(args, 5);
 }
 
 // Statistics of one segment from its sorted order (App. B): R(w) = 1/(d-1) sum_k (2k-d+1) x_k,

@@ -190,6 +190,55 @@ def test_sort_routes_l1_step_and_stats():
             wsr.wsr_plan_destroy(plan)
 
 
+def test_phase_clock_build():
+    """The measurement build libwsr_phases.so gives the regular library's bits, and its phase
+    timestamps are written for every short segment, in order, at the slots of its workgroup."""
+    import ctypes
+    import os
+    lens = [2048] * 30 + [1] + [4096] * 30 + [7000] * 10 + [30000]
+    case = workloads.random_segments(lens, "normal", 0.05, seed=69)
+    off = np.ascontiguousarray(case["offsets"], dtype=np.int64)
+    w = dev(case["w"])
+    ref = torch.empty_like(w)
+    plan = wsr.wsr_plan_create(off)
+    try:
+        nb = wsr.wsr_plan_workspace_bytes(plan)
+        ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        wsr.wsr_prox_forward_batched(plan, w, ref, None, case["lam"], None, None, ws)
+    finally:
+        wsr.wsr_plan_destroy(plan)
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(wsr.__file__), "libwsr_phases.so"))
+    p, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.wsr_plan_create.argtypes = [p, i64, ctypes.c_int, ctypes.POINTER(p)]
+    lib.wsr_plan_destroy.argtypes = [p]
+    lib.wsr_prox_forward_batched.argtypes = [p, p, p, p, ctypes.c_float, p, p, p, ctypes.c_size_t, p]
+    lib.wsr_phase_clock_buffer.argtypes = [p, i64]
+    slots = lib.wsr_phase_clock_slots()
+    n_short = len(lens) - 1
+    clocks = torch.zeros(n_short * slots, dtype=torch.int64, device="cuda")
+    out = torch.empty_like(w)
+    stream = p(torch.cuda.current_stream().cuda_stream)
+    assert lib.wsr_phase_clock_buffer(None, 5) == wsr.WSR_ERR_INVALID
+    assert lib.wsr_phase_clock_buffer(p(clocks.data_ptr()), n_short) == 0
+    h = p()
+    assert lib.wsr_plan_create(off.ctypes.data, len(lens), 0, ctypes.byref(h)) == 0
+    try:
+        rc = lib.wsr_prox_forward_batched(h, p(w.data_ptr()), p(out.data_ptr()), None, case["lam"], None, None,
+                                          p(ws.data_ptr()), nb, stream)
+        assert rc == 0
+        torch.cuda.synchronize()
+    finally:
+        lib.wsr_phase_clock_buffer(None, 0)
+        lib.wsr_plan_destroy(h)
+    assert torch.equal(out.view(torch.int32), ref.view(torch.int32))
+    t = clocks.view(n_short, slots).cpu().numpy()
+    done = t[:, 5] > 0
+    assert done.sum() == n_short - 1  # the d = 1 segment leaves before the sort
+    assert np.all(t[~done, :2] > 0) and np.all(t[~done, 2:] == 0)
+    assert np.all(np.diff(t[done, :6], axis=1) >= 0)
+    assert np.all(t[:, 6:] == 0)
+
+
 def test_read_status_on_its_stream():
     """The status read synchronises only the stream it is given: work on that stream is covered."""
     case = workloads.random_segments([3000, 20000], "normal", 0.05, seed=66)
