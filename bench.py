@@ -649,16 +649,39 @@ def sort_route_figures():
 
 
 PHASES = ("load_and_key", "sort", "prefix_sums", "collisions_and_values", "stores")
+BWD_PHASES = ("load_and_stage", "gather_and_scan", "cluster_values", "stores")
+
+
+def phase_summary(t, names, tick_us, cus):
+    """Per-phase mean / median duration and share of the workgroups' lifetimes, the launch span
+    and the resident workgroups per CU (mean and maximum) from one launch's timestamps
+    (t[workgroup, mark], ticks; workgroups that did not reach the last mark are left out)."""
+    k = len(names) + 1
+    t = t[:, :k]
+    t = t[t[:, -1] > 0] * tick_us
+    dur = np.diff(t, axis=1)
+    life = t[:, -1] - t[:, 0]
+    span = t[:, -1].max() - t[:, 0].min()
+    ev = np.concatenate([np.stack([t[:, 0], np.ones(len(t))], 1), np.stack([t[:, -1], -np.ones(len(t))], 1)])
+    ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]  # at equal times, ends before starts
+    row = dict(span_us=round(float(span), 1), workgroup_us_mean=round(float(life.mean()), 2),
+               in_flight_per_cu=round(float(life.sum() / span / cus), 2),
+               in_flight_max_per_cu=round(float(np.cumsum(ev[:, 1]).max() / cus), 2))
+    for i, ph in enumerate(names):
+        row[ph] = dict(us_mean=round(float(dur[:, i].mean()), 2), us_median=round(float(np.median(dur[:, i])), 2),
+                       share=round(float(dur[:, i].sum() / life.sum()), 3))
+    return row
 
 
 def phase_clock_figures():
-    """Where the short-segment forward spends its time: the measurement build libwsr_phases.so
+    """Where the short-segment kernels spend their time: the measurement build libwsr_phases.so
     (the same kernels, with one thread of each workgroup reading the device wall clock after the
-    barrier that closes each phase) on the MLP rows and on the same rows quantised to 1/64, under
-    both sort routes (inference forward, batched, default merge route).  Per phase: the mean and
-    median over workgroups of its duration and its share of a workgroup's lifetime; per launch:
-    the span from the first start to the last end and the mean number of workgroups in flight per
-    CU; and the launch time of the regular build next to the timestamped one."""
+    barrier that closes each phase) on the MLP rows and on the same rows quantised to 1/64: the
+    forward under both sort routes, and the backward (inference forward / backward, batched,
+    default merge route).  Per phase: the mean and median over workgroups of its duration and its
+    share of a workgroup's lifetime; per launch: the span from the first start to the last end
+    and the mean and maximum number of workgroups resident per CU; and the launch time of the
+    regular build next to the timestamped one."""
     import ctypes
     import torch
     from paper_2311_03096_amd import workloads
@@ -668,6 +691,7 @@ def phase_clock_figures():
     lib.wsr_plan_destroy.argtypes = [p]
     lib.wsr_plan_set_sort_routes.argtypes = [p, p]
     lib.wsr_prox_forward_batched.argtypes = [p, p, p, p, ctypes.c_float, p, p, p, ctypes.c_size_t, p]
+    lib.wsr_prox_backward_batched.argtypes = [p, p, p, p, p, p, ctypes.c_size_t, p]
     lib.wsr_phase_clock_buffer.argtypes = [p, i64]
     lib.wsr_phase_clock_rate_khz.argtypes = [ctypes.POINTER(ctypes.c_int)]
     lib.wsr_phase_occupancy.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -678,55 +702,138 @@ def phase_clock_figures():
     khz = ctypes.c_int()
     if lib.wsr_phase_clock_rate_khz(ctypes.byref(khz)) != 0 or khz.value <= 0:
         raise RuntimeError("no wall-clock rate")
+    tick_us = 1e3 / khz.value
     base = workloads.mlp_rows()
     off = np.ascontiguousarray(base["offsets"], dtype=np.int64)
     nseg = off.shape[0] - 1
     clocks = torch.zeros(nseg * slots, dtype=torch.int64, device="cuda")
     stream = p(torch.cuda.current_stream().cuda_stream)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    res = dict(workload="mlp_rows, lam=1e-3, forward batched", workgroups=nseg, clock_mhz=khz.value / 1e3,
+    res = dict(workload="mlp_rows, lam=1e-3, batched", workgroups=nseg, clock_mhz=khz.value / 1e3,
                occupancy_limit_per_cu=occ.value)
+
+    def check(rc, what):
+        if rc != 0:
+            raise RuntimeError("%s: %d" % (what, rc))
+
+    def timed(fn):
+        """(ms of the regular launch, ms with timestamps, the last launch's timestamps)."""
+        lib.wsr_phase_clock_buffer(None, 0)
+        ms_plain = median_ms(fn, 20, 5)
+        clocks.zero_()
+        check(lib.wsr_phase_clock_buffer(p(clocks.data_ptr()), nseg), "wsr_phase_clock_buffer")
+        ms_clocked = median_ms(fn, 20, 5)  # the last call's timestamps stay in the buffer
+        torch.cuda.synchronize()
+        lib.wsr_phase_clock_buffer(None, 0)
+        t = clocks.view(nseg, slots).cpu().numpy().astype(np.float64)
+        return ms_plain, ms_clocked, t
+
+    g = torch.from_numpy(np.random.default_rng(3).standard_normal(off[-1]).astype(np.float32)).cuda()
+    gw = torch.empty_like(g)
+    perm = torch.empty(off[-1], dtype=torch.int32, device="cuda")
+    mask = torch.empty((int(off[-1]) + 31) // 32 + 1, dtype=torch.int32, device="cuda")
     for name, w_np in (("mlp_rows", base["w"]), ("mlp_rows_quantised_1_64", quantised_rows(base["w"]))):
         w = torch.from_numpy(w_np).cuda()
         out = torch.empty_like(w)
         for route, rname in ((0, "bucket"), (1, "radix")):
             plan = p()
-            if lib.wsr_plan_create(off.ctypes.data, nseg, 0, ctypes.byref(plan)) != 0:
-                raise RuntimeError("wsr_plan_create failed")
+            check(lib.wsr_plan_create(off.ctypes.data, nseg, 0, ctypes.byref(plan)), "wsr_plan_create")
             try:
-                if lib.wsr_plan_set_sort_routes(plan, (ctypes.c_int32 * 3)(route, route, route)) != 0:
-                    raise RuntimeError("wsr_plan_set_sort_routes failed")
-
-                def fn():
-                    rc = lib.wsr_prox_forward_batched(plan, p(w.data_ptr()), p(out.data_ptr()), None, base["lam"],
-                                                      None, None, None, 0, stream)
-                    if rc != 0:
-                        raise RuntimeError("wsr_prox_forward_batched: %d" % rc)
-                lib.wsr_phase_clock_buffer(None, 0)
-                ms_plain = median_ms(fn, 20, 5)
-                clocks.zero_()
-                if lib.wsr_phase_clock_buffer(p(clocks.data_ptr()), nseg) != 0:
-                    raise RuntimeError("wsr_phase_clock_buffer failed")
-                ms_clocked = median_ms(fn, 20, 5)  # the last call's timestamps stay in the buffer
-                torch.cuda.synchronize()
-                lib.wsr_phase_clock_buffer(None, 0)
-                t = clocks.view(nseg, slots)[:, :len(PHASES) + 1].cpu().numpy().astype(np.float64)
+                check(lib.wsr_plan_set_sort_routes(plan, (ctypes.c_int32 * 3)(route, route, route)),
+                      "wsr_plan_set_sort_routes")
+                fwd = lambda: check(lib.wsr_prox_forward_batched(plan, p(w.data_ptr()), p(out.data_ptr()), None,
+                                                                 base["lam"], None, None, None, 0, stream), "forward")
+                ms_plain, ms_clocked, t = timed(fwd)
+                row = dict(ms_regular_build=round(ms_plain, 4), ms_timestamped=round(ms_clocked, 4))
+                row.update(phase_summary(t, PHASES, tick_us, cus))
+                res[name + "_" + rname] = row
+                if name == "mlp_rows" and route == 0:  # the backward on this forward's saved state
+                    check(lib.wsr_prox_forward_batched(plan, p(w.data_ptr()), p(out.data_ptr()), None, base["lam"],
+                                                       p(perm.data_ptr()), p(mask.data_ptr()), None, 0, stream),
+                          "forward with saved state")
+                    bwd = lambda: check(lib.wsr_prox_backward_batched(plan, p(g.data_ptr()), p(gw.data_ptr()),
+                                                                      p(perm.data_ptr()), p(mask.data_ptr()), None, 0,
+                                                                      stream), "backward")
+                    ms_plain, ms_clocked, t = timed(bwd)
+                    row = dict(ms_regular_build=round(ms_plain, 4), ms_timestamped=round(ms_clocked, 4))
+                    row.update(phase_summary(t, BWD_PHASES, tick_us, cus))
+                    res["mlp_rows_backward"] = row
             finally:
                 lib.wsr_plan_destroy(plan)
-            t = t[t[:, -1] > 0] / (khz.value * 1e-3)  # ticks -> us
-            dur = np.diff(t, axis=1)
-            life = t[:, -1] - t[:, 0]
-            span = t[:, -1].max() - t[:, 0].min()
-            ev = np.concatenate([np.stack([t[:, 0], np.ones(len(t))], 1), np.stack([t[:, -1], -np.ones(len(t))], 1)])
-            ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]  # at equal times, ends before starts
-            row = dict(ms_regular_build=round(ms_plain, 4), ms_timestamped=round(ms_clocked, 4),
-                       span_us=round(span, 1), workgroup_us_mean=round(life.mean(), 2),
-                       in_flight_per_cu=round(life.sum() / span / cus, 2),
-                       in_flight_max_per_cu=round(np.cumsum(ev[:, 1]).max() / cus, 2))
-            for i, ph in enumerate(PHASES):
-                row[ph] = dict(us_mean=round(dur[:, i].mean(), 2), us_median=round(float(np.median(dur[:, i])), 2),
-                               share=round(dur[:, i].sum() / life.sum(), 3))
-            res[name + "_" + rname] = row
+    return res
+
+
+def merge_clock_figures():
+    """The tile merge tree of one long segment (d = 2^24: 4096 hull tiles, 12 levels in three
+    launches of 4), timed inside the kernels by the measurement build libwsr_phases.so, on the
+    chain and on N(0,1) weights: per launch and level the span to the level's end, the longest
+    bridge search among its merges, the mean time per level spent before the searches (junction
+    windows) and after them (range updates and prefix rebuild), and the end of the launch's
+    work (the last launch also writes every tile's neighbouring surviving vertices)."""
+    import ctypes
+    import torch
+    from paper_2311_03096_amd import workloads
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2311_03096_amd", "libwsr_phases.so"))
+    p, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.wsr_prox_forward.argtypes = [p, p, p, i64, ctypes.c_float, p, p, p, sz, p]
+    lib.wsr_workspace_bytes.argtypes = [p, i64, ctypes.POINTER(sz)]
+    lib.wsr_phase_merge_clock_buffer.argtypes = [p]
+    lib.wsr_phase_clock_rate_khz.argtypes = [ctypes.POINTER(ctypes.c_int)]
+    khz = ctypes.c_int()
+    if lib.wsr_phase_clock_rate_khz(ctypes.byref(khz)) != 0 or khz.value <= 0:
+        raise RuntimeError("no wall-clock rate")
+    tick_us = 1e3 / khz.value
+    nl, ng, ns = 4, 4096, 16  # launches, workgroups, words per workgroup (the build's layout)
+    clk = torch.zeros(nl * ng * ns, dtype=torch.int64, device="cuda")
+    res = {}
+    for name, case in (("chain_d2p24", workloads.chain(1 << 24, 0.7)),
+                       ("typical_d2p24", workloads.plain(1 << 24, 0.1, seed=1))):
+        off = np.ascontiguousarray(case["offsets"], dtype=np.int64)
+        n = off.shape[0] - 1
+        nb = sz()
+        if lib.wsr_workspace_bytes(off.ctypes.data, n, ctypes.byref(nb)) != 0:
+            raise RuntimeError("wsr_workspace_bytes failed")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        w = torch.from_numpy(case["w"]).cuda()
+        out = torch.empty_like(w)
+        stream = p(torch.cuda.current_stream().cuda_stream)
+
+        def fwd():
+            rc = lib.wsr_prox_forward(p(w.data_ptr()), p(out.data_ptr()), off.ctypes.data, n, float(case["lam"]),
+                                      None, None, p(ws.data_ptr()), nb.value, stream)
+            if rc != 0:
+                raise RuntimeError("wsr_prox_forward: %d" % rc)
+        for _ in range(3):
+            fwd()
+        clk.zero_()
+        if lib.wsr_phase_merge_clock_buffer(p(clk.data_ptr())) != 0:
+            raise RuntimeError("wsr_phase_merge_clock_buffer failed")
+        try:
+            fwd()
+            torch.cuda.synchronize()
+        finally:
+            lib.wsr_phase_merge_clock_buffer(None)
+        t = clk.view(nl, ng, ns).cpu().numpy().astype(np.float64)
+        row = {}
+        for li in range(nl):
+            a = t[li]
+            a = a[a[:, 0] > 0]
+            if len(a) == 0:
+                continue
+            t0 = a[:, 0].min()
+            lv = []
+            for l in range(4):
+                if not (a[:, 1 + l] > 0).any():
+                    break
+                lv.append(dict(end_us=round(float((a[:, 1 + l].max() - t0) * tick_us), 2),
+                               bridge_max_us=round(float(a[:, 5 + l].max() * tick_us), 2)))
+            row["launch%d" % li] = dict(workgroups=len(a), levels=lv,
+                                        before_searches_us_per_level=round(float(a[:, 15].mean() * tick_us / len(lv)), 2),
+                                        after_searches_us_per_level=round(float(a[:, 14].mean() * tick_us / len(lv)), 2),
+                                        end_of_work_us=round(float((a[:, 13].max() - t0) * tick_us), 2))
+        res[name] = row
+        del ws, w, out
+        torch.cuda.empty_cache()
     return res
 
 
@@ -833,6 +940,11 @@ def main():
         except Exception as e:  # noqa: BLE001
             extra["phase_clocks"] = dict(error=str(e))
         log("phase clocks", extra["phase_clocks"])
+        try:
+            extra["merge_clocks"] = merge_clock_figures()
+        except Exception as e:  # noqa: BLE001
+            extra["merge_clocks"] = dict(error=str(e))
+        log("merge clocks", extra["merge_clocks"])
         lay = workloads.mlp_layers()
         st = Step(lay, batched=True)
         ms_l = median_ms(st)

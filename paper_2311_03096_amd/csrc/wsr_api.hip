@@ -1186,9 +1186,17 @@ int wsr_prox_backward_batched(const wsr_plan* plan, const float* grad_out, float
   const size_t need = set_bytes(plan->longs);
   if (need > 0 && (ws == nullptr || ws_bytes < need)) return WSR_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
+#ifdef WSR_PHASE_CLOCKS
+  int64_t clock_base = 0;
+#endif
   for (int c = 0; c < kNumSmall; ++c) {
     if (plan->sched_cnt[c] == 0) continue;
     SegArgs a{plan->d_offsets, plan->d_sched + plan->sched_off[c], nullptr, 0.0f, 0, 0, 0};
+#ifdef WSR_PHASE_CLOCKS
+    if (g_phase_clocks && clock_base + plan->sched_cnt[c] <= g_phase_blocks)
+      a.clocks = g_phase_clocks + clock_base * kPhaseSlots;
+    clock_base += plan->sched_cnt[c];
+#endif
     small_bwd(c, (int)plan->sched_cnt[c], a, grad_out, grad_w, saved_perm, saved_mask, s);
   }
   if (!plan->longs.segs.empty()) {
@@ -1248,8 +1256,8 @@ int wsr_trace_collect(int max_entries, char* names, int64_t* counts, double* tot
 
 #ifdef WSR_PHASE_CLOCKS
 // Measurement build only (not declared in the public header): the buffer of kPhaseSlots
-// timestamps per workgroup that later batched forwards fill (null: none), and the device's
-// wall-clock rate in kHz.
+// timestamps per workgroup that later batched forwards and backwards of short segments fill
+// (null: none), and the device's wall-clock rate in kHz.
 __attribute__((visibility("default"))) int wsr_phase_clock_buffer(void* clocks, int64_t n_blocks) {
   if (n_blocks < 0 || (clocks == nullptr) != (n_blocks == 0)) return WSR_ERR_INVALID;
   g_phase_clocks = (unsigned long long*)clocks;
@@ -1264,6 +1272,11 @@ __attribute__((visibility("default"))) int wsr_phase_clock_rate_khz(int* khz) {
   return WSR_OK;
 }
 __attribute__((visibility("default"))) int wsr_phase_clock_slots(void) { return kPhaseSlots; }
+// The buffer of the tile merge launches' timestamps (kMergeClockLaunches x kMergeClockGroups x
+// kMergeClockSlots words; null: none).
+__attribute__((visibility("default"))) int wsr_phase_merge_clock_buffer(void* clocks) {
+  return set_merge_clock_buffer(clocks) == 0 ? WSR_OK : WSR_ERR_HIP;
+}
 // Resident workgroups per CU of the short-segment forward of size class cls (default merge route)
 // by the runtime's occupancy calculator.
 __attribute__((visibility("default"))) int wsr_phase_occupancy(int cls, int* blocks_per_cu) {

@@ -122,6 +122,20 @@ __global__ void k_big_bwd_apply(LongSet set, const float* gsorted, const int32_t
                                 const double* tileoff, const int32_t* prevp, const double* prevG,
                                 const int32_t* nextp, const double* nextG, float* gout);
 
+#ifdef WSR_PHASE_CLOCKS
+// Measurement build: where the tile merge launches record their timestamps (null: nowhere).
+// Per launch (slot (lvl_lo - 1) / kMergeLevelsPerLaunch, below kMergeClockLaunches) and
+// workgroup (below kMergeClockGroups), kMergeClockSlots words: 0 the start of the first level,
+// 1 + l the end of level l of the launch, 5 + l the longest and 9 + l the summed bridge search
+// of the level's merges, 13 the end of the launch's work, 14 the summed bookkeeping after the
+// levels' searches (thread 0), 15 the summed time from each level's start to wave 0's bridge
+// search (wall-clock ticks).
+constexpr int kMergeClockLaunches = 4;
+constexpr int kMergeClockGroups = 4096;
+constexpr int kMergeClockSlots = 16;
+int set_merge_clock_buffer(void* clocks);
+#endif
+
 __global__ void k_big_stats_tile(LongSet set, const uint32_t* keys, double* tsum, int32_t* tnz, int32_t* tnd);
 __global__ void k_big_stats_final(LongSet set, const double* tsum, const int32_t* tnz, const int32_t* tnd,
                                   const uint32_t* flags, SegStats* out);

@@ -918,6 +918,13 @@ __device__ void wave_bridge(const WaveNode& L, int p, const WaveNode& R, int q, 
   *jstar = jhi;
 }
 
+#ifdef WSR_PHASE_CLOCKS
+__device__ unsigned long long* g_merge_clocks = nullptr;
+int set_merge_clock_buffer(void* clocks) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_merge_clocks), &clocks, sizeof(clocks)) == hipSuccess ? 0 : -1;
+}
+#endif
+
 // Levels [lvl_lo, lvl_hi] of the tile merge tree; workgroup g owns tiles [g*2^lvl_hi, ...).
 // LDS (static, sized for the largest group GMAX): pre[G+1], rec[5 * (G >> lvl_lo)], lo16[G],
 // cnt16[G] with G = 2^lvl_hi <= GMAX and G >> lvl_lo <= RMAX.  One wave per merge.
@@ -958,18 +965,35 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   const int tid = threadIdx.x;
   const int wv = tid / kWave;
   const int lane = lane_id();
+#ifdef WSR_PHASE_CLOCKS
+  __shared__ unsigned long long mclk[2][kMergeLevelsPerLaunch];  // longest and summed bridge search
+  const int mlaunch = (lvl_lo - 1) / kMergeLevelsPerLaunch;
+  unsigned long long* const mc =
+      g_merge_clocks && mlaunch < kMergeClockLaunches && blockIdx.x < kMergeClockGroups
+          ? g_merge_clocks + ((int64_t)mlaunch * kMergeClockGroups + blockIdx.x) * kMergeClockSlots
+          : nullptr;
+  if (tid < 2 * kMergeLevelsPerLaunch) mclk[tid / kMergeLevelsPerLaunch][tid % kMergeLevelsPerLaunch] = 0ull;
+#endif
 
+  // the exclusive prefix pre[] of the own-range lengths: thread t sums a chunk of consecutive
+  // tiles held in registers (all its LDS reads issued at once), one block scan, then writes
+  constexpr int kChunkMax = (GMAX + kMergeThreads - 1) / kMergeThreads;
   auto rebuild_prefix = [&]() {
     const int chunk = (gn + kMergeThreads - 1) / kMergeThreads;
     const int a = tid * chunk;
-    const int b = min(a + chunk, gn);
+    int c[kChunkMax];
     int s = 0;
-    for (int i = a; i < b; ++i) s += cnt16[i];
+#pragma unroll
+    for (int j = 0; j < kChunkMax; ++j) {
+      c[j] = j < chunk && a + j < gn ? (int)cnt16[a + j] : 0;
+      s += c[j];
+    }
     int total;
     int run = block_excl_scan<kMergeThreads, int>(s, ish, &total);
-    for (int i = a; i < b; ++i) {
-      pre[i] = run;
-      run += cnt16[i];
+#pragma unroll
+    for (int j = 0; j < kChunkMax; ++j) {
+      if (j < chunk && a + j < gn) pre[a + j] = run;
+      run += c[j];
     }
     if (tid == 0) pre[gn] = total;
     __syncthreads();
@@ -984,11 +1008,20 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   __syncthreads();
   rebuild_prefix();
   MergeCtx C{lo16, pre, gbase, vpos, vS, tileoff};
+#ifdef WSR_PHASE_CLOCKS
+  if (mc && tid == 0) mc[0] = wall_clock64();
+#endif
 
+#ifdef WSR_PHASE_CLOCKS
+  unsigned long long t_books = 0ull, t_pre = 0ull;  // bookkeeping (thread 0), pre-bridge (wave 0)
+#endif
   for (int lvl = lvl_lo; lvl <= lvl_hi; ++lvl) {
     const int size = 1 << lvl;
     const int half = size >> 1;
     const int nm = min((gn + size - 1) >> lvl, RMAX);
+#ifdef WSR_PHASE_CLOCKS
+    const unsigned long long tl0 = wall_clock64();
+#endif
     for (int m = wv; m < nm; m += NWV) {
       const int t0 = m << lvl;
       const int tm = t0 + half;
@@ -1024,7 +1057,18 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
         WaveNode L{&C, t0, tm, (const lds_int*)win_p[wv][0], (const lds_double*)win_s[wv][0], wlo, p};
         WaveNode R{&C, tm, t1, (const lds_int*)win_p[wv][1], (const lds_double*)win_s[wv][1], 0, rhi};
         int istar, jstar;
+#ifdef WSR_PHASE_CLOCKS
+        const unsigned long long tb0 = wall_clock64();
+        if (m == wv && wv == 0) t_pre += tb0 - tl0;
+#endif
         wave_bridge(L, p, R, q, &istar, &jstar);
+#ifdef WSR_PHASE_CLOCKS
+        if (mc && lane == 0 && lvl - lvl_lo < kMergeLevelsPerLaunch) {
+          const unsigned long long tb = wall_clock64() - tb0;
+          atomicMax(&mclk[0][lvl - lvl_lo], tb);
+          atomicAdd(&mclk[1][lvl - lvl_lo], tb);
+        }
+#endif
         if (!(istar == p && jstar == 1)) {
           int ti = t0 - 1, ii = 0, tj, jj;
           if (istar > 0) node_vertex(C, t0, tm, istar, &ti, &ii);
@@ -1046,9 +1090,14 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
       }
     }
     __syncthreads();
-    for (int i = tid; i < gn; i += kMergeThreads) {
+#ifdef WSR_PHASE_CLOCKS
+    const unsigned long long tk0 = wall_clock64();
+#endif
+#pragma unroll
+    for (int k = 0; k < kChunkMax; ++k) {  // tiles tid, tid + NT, ...: their LDS reads overlap
+      const int i = tid + k * kMergeThreads;
       const int m = i >> lvl;
-      if (m >= nm) continue;
+      if (i >= gn || m >= nm) continue;
       const int* r = rec + 5 * m;
       if (!r[0]) continue;
       const int tm = (m << lvl) + half;
@@ -1069,11 +1118,26 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
     }
     __syncthreads();
     rebuild_prefix();
+#ifdef WSR_PHASE_CLOCKS
+    if (tid == 0) t_books += wall_clock64() - tk0;
+    if (mc && tid == 0 && lvl - lvl_lo < kMergeLevelsPerLaunch) {
+      mc[1 + lvl - lvl_lo] = wall_clock64();
+      mc[5 + lvl - lvl_lo] = mclk[0][lvl - lvl_lo];
+      mc[9 + lvl - lvl_lo] = mclk[1][lvl - lvl_lo];
+    }
+#endif
   }
   for (int i = tid; i < gn; i += kMergeThreads) {
     lo_g[gbase + i] = lo16[i];
     hi_g[gbase + i] = (int)lo16[i] + (int)cnt16[i] - 1;
   }
+#ifdef WSR_PHASE_CLOCKS
+  if (mc && tid == 0) {
+    mc[14] = t_books;
+    mc[15] = t_pre;
+  }
+  if (mc && !finalize && tid == 0) mc[13] = wall_clock64();
+#endif
   if (!finalize) return;
   // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t
   const int nglob = 1 + pre[gn];
@@ -1105,6 +1169,10 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
       next_sl[gbase + t] = 0.0;
     }
   }
+#ifdef WSR_PHASE_CLOCKS
+  __syncthreads();
+  if (mc && tid == 0) mc[13] = wall_clock64();
+#endif
 }
 
 #define WSR_INSTANTIATE_MERGE(GM)                                                                           \

@@ -45,7 +45,9 @@ struct SegArgs {
 // Measurement build (WSR_PHASE_CLOCKS): thread 0 of each workgroup of the short-segment forward
 // records the device wall clock right after the barrier that closes each phase, at
 // clocks[block * kPhaseSlots + mark]: 0 start, 1 weights loaded and keyed, 2 sorted, 3 prefix
-// sums, 4 collisions and cluster values, 5 stores issued.  The regular build has no such code.
+// sums, 4 collisions and cluster values, 5 stores issued; the backward: 0 start, 1 cotangent,
+// perm and mask staged, 2 gathered and scanned, 3 cluster values, 4 stores issued.  The regular
+// build has no such code.
 constexpr int kPhaseSlots = 8;
 #ifdef WSR_PHASE_CLOCKS
 #define WSR_PHASE_MARK(args, m)                                                              \

@@ -764,6 +764,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   const int off = (int)(start & 31);
   const int nwords = (off + d + 31) >> 5;
   const int64_t g0 = start >> 5;
+  WSR_PHASE_MARK(args, 0);
   // every load of the thread in flight before the LDS stores (fixed trip count TMAX / NT)
   {
     const float* const gg = gin + start;
@@ -787,6 +788,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   }
   for (int j = tid; j < nwords; j += NT) sm.lmask[j] = mask_in[g0 + j];
   __syncthreads();
+  WSR_PHASE_MARK(args, 1);
   // cotangent in rank order, cluster starts of the thread's ranks, FP64 prefix sums G (registers)
   const int k0 = tid * E;
   uint16_t ixr[E];
@@ -807,6 +809,7 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   }
   double total;
   double G = block_excl_scan<NT, double, false>(lsum, sm.dred, &total);
+  WSR_PHASE_MARK(args, 2);
   double sv[E + 1];
   Cand mineL{-1, 0.0}, mineR{-1, 0.0};
 #pragma unroll
@@ -824,12 +827,14 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   carry_exchange<NT>(mineL, mineR, false, Cand{d, total}, sm.shL, sm.shR, sm.shF, &lc, &rc);
   walk_values<E>(bm, sv, lc, rc, d, 0.0, ixr, sm.g);  // every gather above is done (block scan)
   __syncthreads();
+  WSR_PHASE_MARK(args, 3);
   float* const og = gout + start;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = tid + r * NT;
     if (i < d) og[i] = sm.g[i];
   }
+  WSR_PHASE_MARK(args, 4);
 }
 
 // Zero a word array (used for the saved cluster-start mask before OR-ing boundary words).
