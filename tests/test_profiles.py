@@ -46,3 +46,26 @@ def test_counter_summary_parses():
         assert kv["workload"] == "mlp_rows" and len(kv["src"]) == 16
         assert float(kv["valu"]) > 0 and float(kv["waves"]) > 0
     assert "rocprofv3 --pmc SQ_INSTS_VALU" in open(f).read()
+
+
+def test_phase_summary_reduces_timestamps():
+    """The bench's reduction of phase timestamps: durations, shares, span and resident workgroups
+    on a hand-checked example (workgroups that never reached the last mark are left out)."""
+    import numpy as np
+    import bench
+    t = np.array([[0, 10, 30, 40, 70, 80, 0, 0],
+                  [40, 50, 60, 70, 80, 100, 0, 0],
+                  [90, 100, 110, 120, 130, 140, 0, 0],
+                  [5, 6, 0, 0, 0, 0, 0, 0]], dtype=np.float64)
+    names = ("a", "b", "c", "d", "e")
+    r = bench.phase_summary(t, names, 0.01, 1)
+    assert r["span_us"] == 1.4
+    assert r["workgroup_us_mean"] == round((0.8 + 0.6 + 0.5) / 3, 2)
+    assert r["in_flight_max_per_cu"] == 2.0  # [0, 80] and [40, 100] overlap, [90, 140] with the second
+    assert r["in_flight_per_cu"] == round((80 + 60 + 50) / 140, 2)
+    assert r["a"]["us_mean"] == 0.1 and r["a"]["share"] == round(30 / 190, 3)
+    assert r["d"]["us_mean"] == round((0.3 + 0.1 + 0.1) / 3, 2)
+    assert abs(sum(r[n]["share"] for n in names) - 1.0) < 5e-3
+    # a workgroup that ends exactly where another starts does not count as overlapping it
+    r2 = bench.phase_summary(np.array([[0, 1, 2, 3, 4, 5], [5, 6, 7, 8, 9, 10]], dtype=np.float64), names, 1.0, 1)
+    assert r2["in_flight_max_per_cu"] == 1.0
