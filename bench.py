@@ -860,7 +860,8 @@ def config_table(copy_gbs):
                                                   cpu_threads=nproc())
     log("backward rows", rows["backward_rows_1024x8192"])
     prec = workloads.precision(1 << 26, 1e-4)
-    rows["precision_d2p26"] = config_line("precision_d2p26", prec, copy_gbs, long_sort=True, oracle_check=True)
+    rows["precision_d2p26"] = config_line("precision_d2p26", prec, copy_gbs, long_sort=True, oracle_check=True,
+                                          cpu_threads=1)
     rows["precision_d2p26"]["fp32_prefix_sum_control"] = fp32_prefix_control(prec)
     log("precision", rows["precision_d2p26"])
     return rows

@@ -239,6 +239,82 @@ def test_phase_clock_build():
     assert np.all(t[:, 6:] == 0)
 
 
+def test_phase_clock_build_merge_and_backward():
+    """The measurement build's long-segment forward gives the regular bits and writes the merge
+    launches' timestamps in order; its batched backward gives the regular bits and writes the
+    backward's phase timestamps in order."""
+    import ctypes
+    import os
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(wsr.__file__), "libwsr_phases.so"))
+    p, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    lib.wsr_prox_forward.argtypes = [p, p, p, i64, ctypes.c_float, p, p, p, sz, p]
+    lib.wsr_workspace_bytes.argtypes = [p, i64, ctypes.POINTER(sz)]
+    lib.wsr_phase_merge_clock_buffer.argtypes = [p]
+    lib.wsr_phase_clock_buffer.argtypes = [p, i64]
+    lib.wsr_plan_create.argtypes = [p, i64, ctypes.c_int, ctypes.POINTER(p)]
+    lib.wsr_plan_destroy.argtypes = [p]
+    lib.wsr_prox_forward_batched.argtypes = [p, p, p, p, ctypes.c_float, p, p, p, ctypes.c_size_t, p]
+    lib.wsr_prox_backward_batched.argtypes = [p, p, p, p, p, p, ctypes.c_size_t, p]
+    stream = p(torch.cuda.current_stream().cuda_stream)
+    # one long segment of 2^20 + 777 weights: 257 hull tiles, levels in three merge launches
+    case = workloads.plain((1 << 20) + 777, 0.05, seed=70)
+    off = np.ascontiguousarray(case["offsets"], dtype=np.int64)
+    w = dev(case["w"])
+    ref = torch.empty_like(w)
+    out = torch.empty_like(w)
+    nb = sz()
+    assert lib.wsr_workspace_bytes(off.ctypes.data, 1, ctypes.byref(nb)) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    wsr.wsr_prox_forward(w, ref, off, case["lam"], None, None, ws)
+    clk = torch.zeros(4 * 4096 * 16, dtype=torch.int64, device="cuda")
+    assert lib.wsr_phase_merge_clock_buffer(p(clk.data_ptr())) == 0
+    try:
+        assert lib.wsr_prox_forward(p(w.data_ptr()), p(out.data_ptr()), off.ctypes.data, 1, case["lam"], None, None,
+                                    p(ws.data_ptr()), nb.value, stream) == 0
+        torch.cuda.synchronize()
+    finally:
+        lib.wsr_phase_merge_clock_buffer(None)
+    assert torch.equal(out.view(torch.int32), ref.view(torch.int32))
+    t = clk.view(4, 4096, 16).cpu().numpy()
+    launches = [li for li in range(4) if (t[li, :, 0] > 0).any()]
+    assert launches == [0, 1, 2]  # 257 tiles: levels 1-4, 5-8, 9
+    for li in launches:
+        a = t[li][t[li, :, 0] > 0]
+        nlev = int((a[0, 1:5] > 0).sum())
+        assert nlev >= 1 and np.all(a[:, 1:1 + nlev] > 0)
+        assert np.all(np.diff(a[:, :1 + nlev], axis=1) >= 0)
+        assert np.all(a[:, 13] >= a[:, nlev])
+    # the batched backward of short rows
+    lens = [4096] * 40 + [3000] * 20
+    case = workloads.random_segments(lens, "normal", 1e-3, seed=71)
+    off = np.ascontiguousarray(case["offsets"], dtype=np.int64)
+    w = dev(case["w"])
+    g = dev(np.random.default_rng(72).standard_normal(off[-1]).astype(np.float32))
+    out = torch.empty_like(w)
+    perm = torch.empty(off[-1], dtype=torch.int32, device="cuda")
+    mask = torch.empty((int(off[-1]) + 31) // 32, dtype=torch.int32, device="cuda")
+    gw_ref, gw = torch.empty_like(g), torch.empty_like(g)
+    h = p()
+    assert lib.wsr_plan_create(off.ctypes.data, len(lens), 0, ctypes.byref(h)) == 0
+    slots = lib.wsr_phase_clock_slots()
+    clocks = torch.zeros(len(lens) * slots, dtype=torch.int64, device="cuda")
+    try:
+        assert lib.wsr_prox_forward_batched(h, p(w.data_ptr()), p(out.data_ptr()), None, case["lam"],
+                                            p(perm.data_ptr()), p(mask.data_ptr()), None, 0, stream) == 0
+        assert lib.wsr_prox_backward_batched(h, p(g.data_ptr()), p(gw_ref.data_ptr()), p(perm.data_ptr()),
+                                             p(mask.data_ptr()), None, 0, stream) == 0
+        assert lib.wsr_phase_clock_buffer(p(clocks.data_ptr()), len(lens)) == 0
+        assert lib.wsr_prox_backward_batched(h, p(g.data_ptr()), p(gw.data_ptr()), p(perm.data_ptr()),
+                                             p(mask.data_ptr()), None, 0, stream) == 0
+        torch.cuda.synchronize()
+    finally:
+        lib.wsr_phase_clock_buffer(None, 0)
+        lib.wsr_plan_destroy(h)
+    assert torch.equal(gw.view(torch.int32), gw_ref.view(torch.int32))
+    tb = clocks.view(len(lens), slots).cpu().numpy()
+    assert np.all(tb[:, :5] > 0) and np.all(np.diff(tb[:, :5], axis=1) >= 0) and np.all(tb[:, 5:] == 0)
+
+
 def test_read_status_on_its_stream():
     """The status read synchronises only the stream it is given: work on that stream is covered."""
     case = workloads.random_segments([3000, 20000], "normal", 0.05, seed=66)
