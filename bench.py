@@ -310,13 +310,13 @@ def accuracy(case, step, u, perm, start, vg=None):
 
 
 def config_line(name, case, copy_gbs, kind="fwd_bwd", batched=False, long_sort=False, oracle_check=False,
-                cpu_threads=0):
+                cpu_threads=0, cpu_runs=5):
     """One row of the per-workload table: the median step time (>= 50 reps after >= 10 warm-ups),
     elements/s, the whole step's fraction of HBM peak under the algorithmic bytes (24.25 B/el for
     forward with saved state + backward, 12.125 B/el for the backward alone; plus the sort's
     16 B/el round trip for a segment too long for on-chip memory), and the dominant kernel with its
     own fraction.  ``oracle_check``: errors against the FP64 oracle; ``cpu_threads`` > 0: the
-    oracle's forward + VJP timed on that many host threads (median of >= 5 runs)."""
+    oracle's forward + VJP timed on that many host threads (median of ``cpu_runs`` runs)."""
     import torch
     import oracle
     step = Step(case, batched=batched)
@@ -352,15 +352,16 @@ def config_line(name, case, copy_gbs, kind="fwd_bwd", batched=False, long_sort=F
         g = step.g.cpu().numpy().astype(np.float64)
         nthr = cpu_threads or 1
         times = []
-        for _ in range(5 if cpu_threads else 1):
+        for _ in range(cpu_runs if cpu_threads else 1):
             t0 = time.perf_counter()
             u, perm, start = oracle.prox_segments(w, lam, off, n_threads=nthr)
             vg = oracle.vjp(g, perm, start, off)
             times.append(time.perf_counter() - t0)
         if cpu_threads:
             t = float(np.median(times))
+            what = "median of %d fwd+vjp runs" % len(times) if len(times) > 1 else "one fwd+vjp run"
             res["cpu_oracle"] = dict(value=n / t, unit="elements/s", cores=nthr, kind="oracle",
-                                     sample="median of 5 fwd+vjp runs over the whole workload, %.3f s each" % t)
+                                     sample="%s over the whole workload, %.3f s each" % (what, t))
         if kind != "bwd":
             step()  # results of one whole step for the accuracy check
         torch.cuda.synchronize()
@@ -861,7 +862,7 @@ def config_table(copy_gbs):
     log("backward rows", rows["backward_rows_1024x8192"])
     prec = workloads.precision(1 << 26, 1e-4)
     rows["precision_d2p26"] = config_line("precision_d2p26", prec, copy_gbs, long_sort=True, oracle_check=True,
-                                          cpu_threads=1)
+                                          cpu_threads=1, cpu_runs=1)  # ~10 s a run
     rows["precision_d2p26"]["fp32_prefix_sum_control"] = fp32_prefix_control(prec)
     log("precision", rows["precision_d2p26"])
     return rows
