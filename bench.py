@@ -359,9 +359,9 @@ def config_line(name, case, copy_gbs, kind="fwd_bwd", batched=False, long_sort=F
             times.append(time.perf_counter() - t0)
         if cpu_threads:
             t = float(np.median(times))
-            what = "median of %d fwd+vjp runs" % len(times) if len(times) > 1 else "one fwd+vjp run"
-            res["cpu_oracle"] = dict(value=n / t, unit="elements/s", cores=nthr, kind="oracle",
-                                     sample="%s over the whole workload, %.3f s each" % (what, t))
+            what = ("median of %d fwd+vjp runs over the whole workload, %.3f s each" % (len(times), t)
+                    if len(times) > 1 else "one fwd+vjp run over the whole workload, %.3f s" % t)
+            res["cpu_oracle"] = dict(value=n / t, unit="elements/s", cores=nthr, kind="oracle", sample=what)
         if kind != "bwd":
             step()  # results of one whole step for the accuracy check
         torch.cuda.synchronize()
