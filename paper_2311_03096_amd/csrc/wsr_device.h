@@ -161,6 +161,32 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sh, T* total) {
   return base + exc;
 }
 
+// block_excl_scan of doubles (no closing barrier, as TRAIL = false) for kernels short of
+// registers: the cross-wave sums come from one LDS read per lane and lane reads instead of one
+// LDS read per wave held in registers; the summation order is the same, so are the bits.
+template <int NT>
+__device__ __forceinline__ double block_excl_scan_lean(double v, double* sh, double* total) {
+  constexpr int NW = NT / kWave;
+  const int lane = lane_id();
+  const int wv = threadIdx.x / kWave;
+  const double inc = wave_incl_scan(v);
+  const double exc = wave_shift_up(inc, 0.0);
+  if (lane == kWave - 1) sh[wv] = inc;
+  __syncthreads();
+  const long long mb = __double_as_longlong(lane < NW ? sh[lane] : 0.0);
+  double base = 0.0, tot = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const int lo = __builtin_amdgcn_readlane((int)(mb & 0xFFFFFFFFll), w);
+    const int hi = __builtin_amdgcn_readlane((int)(mb >> 32), w);
+    const double t = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned int)lo);
+    if (w < wv) base += t;
+    tot += t;
+  }
+  if (total) *total = tot;
+  return base + exc;
+}
+
 // Layouts of LDS arrays indexed by rank (prefix sums S): rank-padded (blocks of 16 ranks per
 // thread spread over the banks) or transposed.
 struct RankPadded {

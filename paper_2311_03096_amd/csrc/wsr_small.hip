@@ -750,8 +750,10 @@ struct BwdSmem {
   int shF[NW];
 };
 
+// Eight waves per SIMD (64 VGPRs): the kernel waits mostly for its loads, so as many segments
+// as the registers allow are in flight (four 4096-class or two 8192-class workgroups per CU).
 template <int TMAX, int NT>
-__global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float* gin, float* gout,
+__global__ __launch_bounds__(NT, 8) void k_prox_bwd_small(SegArgs args, const float* gin, float* gout,
                                                        const int32_t* perm_in, const uint32_t* mask_in) {
   constexpr int E = TMAX / NT;
   __shared__ BwdSmem<TMAX, NT> sm;
@@ -791,24 +793,28 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   WSR_PHASE_MARK(args, 1);
   // cotangent in rank order, cluster starts of the thread's ranks, FP64 prefix sums G (registers)
   const int k0 = tid * E;
-  uint16_t ixr[E];
-  load_u16_block<E>(sm.idx, k0, ixr);  // ranks past d hold stale entries, not used
   float gk[E];
   double lsum = 0.0;
   uint32_t bm = 0;
+  {
+    uint16_t ixr[E];
+    load_u16_block<E>(sm.idx, k0, ixr);  // ranks past d hold stale entries, not used
+    // the start bits of ranks k0 .. k0+E-1 lie in two mask words (words past the segment's end
+    // hold stale bits, masked below)
+    const int b0 = k0 + off;
+    const uint64_t mw = (uint64_t)sm.lmask[b0 >> 5] | ((uint64_t)sm.lmask[(b0 >> 5) + 1] << 32);
 #pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int kk = k0 + i;
-    const int kc = min(kk, d - 1);
-    const float gv = sm.g[kk < d ? ixr[i] : 0];  // unconditional gather
-    const int b = kc + off;
-    const uint32_t st = (kk == 0) | ((sm.lmask[b >> 5] >> (b & 31)) & 1u);
-    gk[i] = kk < d ? gv : 0.0f;
-    lsum += (double)gk[i];
-    bm |= (kk < d ? st : 0u) << i;
+    for (int i = 0; i < E; ++i) {
+      const int kk = k0 + i;
+      const float gv = sm.g[kk < d ? ixr[i] : 0];  // unconditional gather
+      const uint32_t st = (kk == 0) | (uint32_t)((mw >> ((b0 & 31) + i)) & 1u);
+      gk[i] = kk < d ? gv : 0.0f;
+      lsum += (double)gk[i];
+      bm |= (kk < d ? st : 0u) << i;
+    }
   }
   double total;
-  double G = block_excl_scan<NT, double, false>(lsum, sm.dred, &total);
+  double G = block_excl_scan_lean<NT>(lsum, sm.dred, &total);
   WSR_PHASE_MARK(args, 2);
   double sv[E + 1];
   Cand mineL{-1, 0.0}, mineR{-1, 0.0};
@@ -825,7 +831,9 @@ __global__ __launch_bounds__(NT) void k_prox_bwd_small(SegArgs args, const float
   }
   Cand lc, rc;
   carry_exchange<NT>(mineL, mineR, false, Cand{d, total}, sm.shL, sm.shR, sm.shF, &lc, &rc);
-  walk_values<E>(bm, sv, lc, rc, d, 0.0, ixr, sm.g);  // every gather above is done (block scan)
+  uint16_t ixw[E];  // read again here rather than held through the scans
+  load_u16_block<E>(sm.idx, k0, ixw);
+  walk_values<E>(bm, sv, lc, rc, d, 0.0, ixw, sm.g);  // every gather above is done (block scan)
   __syncthreads();
   WSR_PHASE_MARK(args, 3);
   float* const og = gout + start;
