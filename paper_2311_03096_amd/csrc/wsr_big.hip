@@ -1382,8 +1382,10 @@ struct ApplySmem {
 // recomputed from the sorted keys by the tile kernel's own operations (dense tiles); each thread
 // then sweeps its ranks with the neighbouring starts from the other threads (carry exchange) or
 // from the merge (tile ends).  l1 != 0: each cluster's output goes through Alg. prox's l1 and
-// rewinding lines (beta, rho, rewinding-line scale kappa).
-__global__ __launch_bounds__(kBigThreads) void k_big_apply(LongSet set, const uint32_t* keys, const int32_t* saved_perm,
+// rewinding lines (beta, rho, rewinding-line scale kappa).  Held to eight waves per SIMD (eight
+// workgroups per CU): on unsorted weights its scattered stores through the permutation want as
+// many tiles in flight as possible.
+__global__ __launch_bounds__(kBigThreads, 8) void k_big_apply(LongSet set, const uint32_t* keys, const int32_t* saved_perm,
                                                            const int32_t* perm_ws, LamArgs lamargs,
                                                            const uint32_t* flags, const uint16_t* hbits,
                                                            const int32_t* hcnt, const double* vS,
