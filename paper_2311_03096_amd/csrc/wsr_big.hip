@@ -507,8 +507,8 @@ template __global__ void k_radix_scatter<true>(int, LongSet, const float*, const
 // ------------------------------------------------------------------------------- tile hulls
 
 struct TileSmem {
-  double S[rpad_size(kBigTile + 1)];  // tile-relative prefix sums (rank-padded)
-  uint16_t vert[kBigThreads * (kBigE + 1)];
+  double S[rpad_size(kBigTile + 1)];  // tile-relative prefix sums (rank-padded), then hull S'
+  uint16_t vert[kBigThreads * (kBigE + 1)];  // hull scratch, or the hull's tile-local ranks
   int cnt[kBigThreads];
   int mres[kBigThreads];
   double dred[kBigThreads / kWave + 1];
@@ -517,6 +517,8 @@ struct TileSmem {
   uint32_t hb[kBigThreads];  // fallback path: hull-vertex bits of each thread's ranks
   double xtot;
 };
+static_assert(kBigTile - 1 + ((kBigTile - 1) >> 4) < kBigThreads * (kBigE + 1),
+              "the hull's tile-local ranks (rank-padded) fit the hull scratch");
 
 
 // Local hull of tile t: points k0..k0+np (np = elements in the tile) with tile-relative sums
@@ -586,21 +588,29 @@ __global__ __launch_bounds__(kBigThreads) void k_big_tile_hull(LongSet set, cons
   Cand lc, rc;
   if (ica_rounds<kBigThreads, kBigE, RankPadded>(sm.S, sv, np, rounds < 0 ? kIcaRounds : rounds, &bm, &lc, &rc,
                                                   sm.wb)) {
-    // hull vertices = surviving candidates in rank order, then the tile's end point
+    // hull vertices = surviving candidates in rank order, then the tile's end point.  The
+    // records go through LDS (S' over the dead prefix sums, tile-local ranks in the hull scratch,
+    // both rank-padded) so that the global stores are lane-consecutive.
+    const double endS = sm.S[rpad(np)];  // read before the scan's barrier: S is overwritten below
     int nv;
     int at = block_excl_scan<kBigThreads, int>(__popc(bm), sm.ired, &nv);
     hbits[(int64_t)t * kBigThreads + tid] = (uint16_t)bm;
 #pragma unroll
     for (int i = 0; i < kBigE; ++i) {
       if ((bm >> i) & 1u) {
-        vpos[vb + at] = (int32_t)(k0 + j0 + i);
-        vS[vb + at] = sv[i];
+        sm.S[rpad(at)] = sv[i];
+        sm.vert[rpad(at)] = (uint16_t)(j0 + i);
         ++at;
       }
     }
+    __syncthreads();
+    for (int i = tid; i < nv; i += kBigThreads) {
+      vpos[vb + i] = (int32_t)(k0 + sm.vert[rpad(i)]);
+      vS[vb + i] = sm.S[rpad(i)];
+    }
     if (tid == 0) {
       vpos[vb + nv] = (int32_t)(k0 + np);
-      vS[vb + nv] = sm.S[rpad(np)];
+      vS[vb + nv] = endS;
       hcnt[t] = nv + 1;
       tsum[t] = sm.xtot;
     }
