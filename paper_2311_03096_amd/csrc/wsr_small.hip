@@ -398,13 +398,12 @@ __device__ bool block_bucket_sort(FwdSmem<TMAX, NT>& sm, const uint32_t (&k)[TMA
   return true;
 }
 
-// Given the hull vertices vert[0..ncl] (ranks, vert[ncl] == d) of S, write every rank k < d of
-// the thread's blocked range the output fin(offset + (S_b - S_a)/(b - a), a, b) of its cluster
-// [a, b) at out[idx[k]].
+// Given the hull vertices vert[0..ncl] (ranks, vert[ncl] == d) of S, the output
+// fin(offset + (S_b - S_a)/(b - a), a, b) of the cluster [a, b) of every rank of the thread's
+// blocked range, into val[i] for rank k0 + i < d (the caller stages them by original index).
 template <int NT, int E, typename SL, typename Fin>
-__device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int ncl, const double* S,
-                                                       double offset, const uint16_t* idx, float* out, int d,
-                                                       Fin fin) {
+__device__ __forceinline__ void cluster_values(const uint16_t* vert, int ncl, const double* S, double offset, int d,
+                                               Fin fin, float (&val)[E]) {
   const int k0 = threadIdx.x * E;
   if (k0 >= d) return;
   // cluster of k0: last i with vert[i] <= k0
@@ -419,15 +418,18 @@ __device__ __forceinline__ void scatter_cluster_values(const uint16_t* vert, int
   int a = vert[lo];
   int b = vert[lo + 1];
   float v = fin(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a), a, b);
-  const int k1 = min(k0 + E, d);
-  for (int k = k0; k < k1; ++k) {
-    while (k >= b) {
-      ++lo;
-      a = b;
-      b = vert[lo + 1];
-      v = fin(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a), a, b);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = k0 + i;
+    if (k < d) {
+      while (k >= b) {
+        ++lo;
+        a = b;
+        b = vert[lo + 1];
+        v = fin(offset + (S[SL::at(b)] - S[SL::at(a)]) / (double)(b - a), a, b);
+      }
+      val[i] = v;
     }
-    out[idx[k]] = v;
   }
 }
 
@@ -606,7 +608,6 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
   // EndCollisions
   uint32_t bm;
   Cand lc, rc;
-  bool staged = true;
   if (!END &&
       ica_rounds<NT, E, SL>(sm.c.S, sv, d, args.merge_rounds < 0 ? kIcaRounds : args.merge_rounds, &bm, &lc, &rc,
                             sm.d.wb)) {
@@ -637,24 +638,29 @@ __global__ __launch_bounds__(NT, fwd_waves_per_simd(TMAX)) void k_prox_fwd_small
       const int a = vert[i];
       atomicOr(&sm.lmask[(a + off) >> 5], 1u << ((a + off) & 31));
     }
-    // values straight to their original positions (S still holds the sums)
+    // values in registers while S holds the sums, then by original index into LDS over S (the
+    // stores below are lane-consecutive)
+    float val[E];
     if (args.l1)
-      scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d,
-                                        L1Value{L1Rewind(args.beta, args.rho, args.kappa), lamd, d});
+      cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, d, L1Value{L1Rewind(args.beta, args.rho, args.kappa), lamd, d},
+                                val);
     else
-      scatter_cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, sm.idx, out + start, d, PlainValue());
-    staged = false;
+      cluster_values<NT, E, SL>(vert, nv - 1, sm.c.S, c, d, PlainValue(), val);
+    __syncthreads();  // every read of S is done
+    uint16_t ixr[E];
+    load_u16_block<E>(sm.idx, k0, ixr);
+#pragma unroll
+    for (int i = 0; i < E; ++i)
+      if (k0 + i < d) sm.c.outv[ixr[i]] = val[i];
   }
   __syncthreads();
   WSR_PHASE_MARK(args, 4);
   // fixed trip count (TMAX / NT) so every LDS read is issued before the stores wait on them
   float* const og = out + start;
-  if (staged) {
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int i = tid + r * NT;
-      if (i < d) og[i] = sm.c.outv[i];
-    }
+  for (int r = 0; r < E; ++r) {
+    const int i = tid + r * NT;
+    if (i < d) og[i] = sm.c.outv[i];
   }
   if (perm_out) {
     int32_t* const pg = perm_out + start;
