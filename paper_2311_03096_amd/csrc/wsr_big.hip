@@ -1149,35 +1149,107 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   if (mc && !finalize && tid == 0) mc[13] = wall_clock64();
 #endif
   if (!finalize) return;
-  // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t
-  const int nglob = 1 + pre[gn];
-  // a vertex's global S (S' + the tile offset, as every tile forms it) and its S' in its own tile
-  auto gvertex = [&](int m, int* p, double* s, double* sl) {
-    int tile, idx;
-    node_vertex(C, 0, gn, m, &tile, &idx);
-    const int64_t at = (int64_t)(gbase + tile) * (kBigTile + 1) + idx;
-    *p = vpos[at];
-    *sl = vS[at];
-    *s = *sl + tileoff[gbase + tile];
-  };
-  for (int t = tid; t < gn; t += kMergeThreads) {
-    int p;
-    double s, sl;
-    gvertex(pre[t], &p, &s, &sl);
-    prev_pos[gbase + t] = p;
-    prev_s[gbase + t] = s;
-    prev_sl[gbase + t] = sl;
-    const int nx = pre[t + 1] + 1;
-    if (nx < nglob) {
-      gvertex(nx, &p, &s, &sl);
-      next_pos[gbase + t] = p;
-      next_s[gbase + t] = s;
-      next_sl[gbase + t] = sl;
-    } else {
-      next_pos[gbase + t] = -1;
-      next_s[gbase + t] = 0.0;
-      next_sl[gbase + t] = 0.0;
+  // Every tile's previous and next surviving vertex on the group's chain (P_0 = tile 0, index 0,
+  // then the tiles' own ranges in order): the last own vertex of the last tile before it that
+  // keeps any (else P_0) and the first own vertex of the first tile after it that keeps any (else
+  // none).  Those tiles come from a max-scan and a reversed min-scan over the threads' chunks of
+  // consecutive tiles, packed per tile into pre[] (no longer needed); then each thread takes
+  // tiles tid, tid + NT, ... with all their vertex loads in flight and coalesced stores.
+  __shared__ int fin_w[NWV];
+  __shared__ int fin_r[kMergeThreads];
+  {
+    constexpr int kNone = 0x7FFFFFFF;
+    const int chunk = (gn + kMergeThreads - 1) / kMergeThreads;
+    const int a0 = tid * chunk;
+    int myl = -1, myf = kNone;  // last / first tile of the chunk keeping vertices
+#pragma unroll
+    for (int j = 0; j < kChunkMax; ++j) {
+      const int i = a0 + j;
+      if (j < chunk && i < gn && cnt16[i] > 0) {
+        myl = i;
+        myf = min(myf, i);
+      }
     }
+    auto imax = [](int x, int y) { return x > y ? x : y; };
+    auto imin = [](int x, int y) { return x < y ? x : y; };
+    // last keeping tile before the chunk: exclusive max-scan in thread order
+    int lbefore;
+    {
+      const int inc = wave_incl_scan_op(myl, -1, imax);
+      const int exc = wave_shift_up(inc, -1);
+      if (lane == kWave - 1) fin_w[wv] = inc;
+      __syncthreads();
+      int b = -1;
+      for (int w = 0; w < wv; ++w) b = max(b, fin_w[w]);
+      lbefore = max(b, exc);
+      __syncthreads();
+    }
+    // first keeping tile after the chunk: the same scan with min over the reversed thread order
+    int fafter;
+    {
+      fin_r[kMergeThreads - 1 - tid] = myf;
+      __syncthreads();
+      const int inc = wave_incl_scan_op(fin_r[tid], kNone, imin);
+      const int exc = wave_shift_up(inc, kNone);
+      if (lane == kWave - 1) fin_w[wv] = inc;
+      __syncthreads();
+      int b = kNone;
+      for (int w = 0; w < wv; ++w) b = min(b, fin_w[w]);
+      const int res = min(b, exc);
+      __syncthreads();
+      fin_r[kMergeThreads - 1 - tid] = res;
+      __syncthreads();
+      fafter = fin_r[tid];
+    }
+    // walk the chunk both ways; pre[i] = (previous keeping tile + 1) | (next keeping tile + 1) << 16
+    int nexts[kChunkMax];
+    {
+      int nx = fafter;
+#pragma unroll
+      for (int j = kChunkMax - 1; j >= 0; --j) {
+        const int i = a0 + j;
+        nexts[j] = nx;
+        if (j < chunk && i < gn && cnt16[i] > 0) nx = i;
+      }
+      int pv = lbefore;
+#pragma unroll
+      for (int j = 0; j < kChunkMax; ++j) {
+        const int i = a0 + j;
+        if (j < chunk && i < gn) {
+          pre[i] = (pv + 1) | ((nexts[j] == kNone ? 0 : nexts[j] + 1) << 16);
+          if (cnt16[i] > 0) pv = i;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // a vertex's global S (S' + the tile offset, as every tile forms it) and its S' in its own tile
+#pragma unroll
+  for (int k = 0; k < kChunkMax; ++k) {
+    const int t = tid + k * kMergeThreads;
+    if (t >= gn) continue;
+    const int pk = pre[t];
+    const int pt = (pk & 0xFFFF) - 1, nt = (pk >> 16) - 1;
+    const int ptile = pt < 0 ? 0 : pt;
+    const int pidx = pt < 0 ? 0 : (int)lo16[pt] + (int)cnt16[pt] - 1;
+    const int64_t pat = (int64_t)(gbase + ptile) * (kBigTile + 1) + pidx;
+    const int pp = vpos[pat];
+    const double psl = vS[pat];
+    const double poff = tileoff[gbase + ptile];
+    int np_ = -1;
+    double nsl = 0.0, noff = 0.0;
+    if (nt >= 0) {
+      const int64_t nat = (int64_t)(gbase + nt) * (kBigTile + 1) + (int)lo16[nt];
+      np_ = vpos[nat];
+      nsl = vS[nat];
+      noff = tileoff[gbase + nt];
+    }
+    prev_pos[gbase + t] = pp;
+    prev_s[gbase + t] = psl + poff;
+    prev_sl[gbase + t] = psl;
+    next_pos[gbase + t] = np_;
+    next_s[gbase + t] = nt >= 0 ? nsl + noff : 0.0;
+    next_sl[gbase + t] = nsl;
   }
 #ifdef WSR_PHASE_CLOCKS
   __syncthreads();
