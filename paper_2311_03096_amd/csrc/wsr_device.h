@@ -528,6 +528,7 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
   if (wk0 > 0 && wk0 <= d) wl = Cand{wk0 - 1, S[SI::at(wk0 - 1)]};
   if (wk0 + kWave * E < d) wr = Cand{wk0 + kWave * E, S[SI::at(wk0 + kWave * E)]};
   Cand l{-1, 0.0}, r = dflt, mineL{-1, 0.0}, mineR{-1, 0.0};
+  bool lout = true, rout = true;  // the lane's l / r came from outside the wave in the last sweep
   for (int round = 0; round < max_rounds; ++round) {
     // 2. sweeps inside the wave
     int overflow = 0;
@@ -549,8 +550,10 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
       l.s = __shfl(mineL.s, src_l, kWave);
       r.pos = __shfl(mineR.pos, src_r, kWave);
       r.s = __shfl(mineR.s, src_r, kWave);
-      if (!lower) l = wl;
-      if (!upper) r = wr;
+      lout = !lower;
+      rout = !upper;
+      if (lout) l = wl;
+      if (rout) r = wr;
       if (b) {
         if (l.pos != lprev) todo |= b & (0u - b);
         if (r.pos != rprev) todo |= 1u << (31 - __clz(b));
@@ -618,6 +621,12 @@ __device__ bool ica_rounds(const double* S, const double (&sv)[E + 1], int d, in
     wr = Cand{__shfl(exr.pos, wv, kWave), __shfl(exr.s, wv, kWave)};
     if (ovf) break;
     if (!wrong) {
+      // the check above covers the waves holding candidates; a wave holding none may have swept
+      // with stale outside neighbours (a lower wave's last candidate removed in this round), and
+      // its lanes' values use them: every lane whose neighbour lies outside its wave takes the
+      // exact one just exchanged
+      if (lout) l = wl;
+      if (rout) r = wr;
       *bm = b;
       *lc = l;
       *rc = r;

@@ -229,7 +229,7 @@ def test_long_segment_repeatable():
                 assert np.array_equal(first[k], g[k]), "run %d differs in %s" % (run, k)
 
 
-@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("seed", range(12))
 def test_random_layouts(seed):
     """Seeded random layouts: 1-40 segments with lengths from 1 to ~150k (both size classes and
     the long path, ragged tails), every weight distribution, lambda over five decades; plain and
@@ -244,6 +244,35 @@ def test_random_layouts(seed):
     case = workloads.random_segments(lens, dist, lam, seed=seed)
     _check(case, batched=bool(seed % 2))
     _check_backward(case, batched=bool(seed % 2))
+
+
+def test_converged_rounds_use_exact_outside_neighbours():
+    """A 4428-weight row (8192 class, 16 waves) whose collision rounds converge in a round that
+    removes the last candidate of wave 0 while the waves above hold none: every wave must take
+    the exchanged outside neighbours for its cluster values, so the one cluster has one value
+    (the row of seed 10 of the random layouts, taken alone; plain, batched and by every merge
+    route against the oracle)."""
+    import paper_2311_03096_amd as wsr
+    rng = np.random.default_rng(1010)
+    nseg = int(rng.integers(1, 41))
+    kinds = rng.choice(["tiny", "short", "long"], nseg, p=[0.3, 0.5, 0.2])
+    lens = [int(rng.integers(0, 40)) if k == "tiny" else int(rng.integers(40, 8193)) if k == "short"
+            else int(rng.integers(8193, 150000)) for k in kinds]
+    lam = float(10.0 ** rng.uniform(-4, 1))
+    full = workloads.random_segments(lens, "normal", lam, seed=10)
+    s0, s1 = int(full["offsets"][13]), int(full["offsets"][14])
+    w = np.ascontiguousarray(full["w"][s0:s1])
+    off = np.array([0, w.shape[0]], dtype=np.int64)
+    case = dict(name="seed10_row13", w=w, offsets=off, lam=lam)
+    o = oracle_forward(w, off, lam)
+    assert o["start"].sum() == 1  # one cluster
+    _check(case, batched=False)
+    _check(case, batched=True)
+    for flags in (wsr.WSR_PLAN_MERGE_HULL, wsr.WSR_PLAN_MERGE_END):
+        g = gpu_forward(w, off, lam, batched=True, plan_flags=flags)
+        assert np.unique(g["out"]).shape[0] == 1
+    g = gpu_forward(w, off, lam, batched=True)
+    assert np.unique(g["out"]).shape[0] == 1
 
 
 def test_determinism():
