@@ -454,9 +454,20 @@ def compare_l1(w, offsets, out, o_l1, o_plain, g_plain, beta, rho, lam, rel_tol=
     bad = err > rel_tol * sc + 2 * ulp
     assert not bad.any(), "value mismatch at %s: gpu %r oracle %r" % (
         np.nonzero(bad)[0][:5], out[bad][:5], o_l1[bad][:5])
-    zeros_g = (out == 0.0) & finite & ~skip
+    # the soft threshold zeroes a cluster when |u| < beta (both sides decide it the same way on
+    # their FP64 u; the near-threshold band is skipped above): those outputs are exactly zero on
+    # both sides.  Any other exact zero comes from the rewinding line's cancellation (u - rho v of
+    # a cluster whose weights are all zero is zero in exact arithmetic), which the GPU's FP64
+    # prefix-sum form leaves as a rounding residue: there the other side must be zero up to FP64
+    # rounding of the segment's scale.
+    thr = finite & ~skip & (np.abs(u) < float(np.float32(beta)))
+    assert np.all(out[thr] == 0.0) and np.all(o_l1[thr] == 0.0), "thresholded weights are not zero"
+    rest = finite & ~skip & ~thr
+    cancel = 1e-11 * sc
+    zo, zg = rest & (o_l1 == 0.0), rest & (out == 0.0)
+    assert np.all(np.abs(out[zo]) <= cancel[zo]) and np.all(np.abs(o_l1[zg]) <= cancel[zg]), \
+        "zeroed weights differ beyond the rewinding's rounding"
     zeros_o = (o_l1 == 0.0) & finite & ~skip
-    assert np.array_equal(zeros_g, zeros_o), "zeroed weights differ"
     lam_el = _per_segment(lam, lens.shape[0])[seg_of]
     extra = 8 * 2.0 ** -53 * (np.abs(u) + np.abs(lam_el) + abs(float(beta)))
     est = element_check(w, offsets, out, u, lam, same & ~near_zero_test, csize, sc, o_plain["perm"],

@@ -263,7 +263,7 @@ def _random_layout(seed):
     return case, beta, rho, rng
 
 
-@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("seed", list(range(5)) + [28, 32])  # 28, 32: beta = 0, rho = 1, clusters of zeros
 def test_l1_and_step_random_layouts(seed):
     """Seeded random layouts (1-40 segments, 1 to ~150k weights each, every distribution):
     Alg. prox in full through the plain and batched entry points, and one proximal-gradient step
