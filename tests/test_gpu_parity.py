@@ -275,6 +275,22 @@ def test_converged_rounds_use_exact_outside_neighbours():
     assert np.unique(g["out"]).shape[0] == 1
 
 
+@pytest.mark.parametrize("seed", [0, 2, 6, 9, 12, 15])
+def test_rows_large_lambda(seed):
+    """200 rows of 500-8192 weights with per-row lambda over [0.05, 20] (few, large clusters:
+    the collision rounds often converge with whole waves holding no candidate), batched, and
+    for some seeds plain, against the oracle (seeds 2, 6, 9, 12 and 15 failed with stale outside
+    neighbours in converged rounds)."""
+    rng = np.random.default_rng(7000 + seed)
+    lens = [int(x) for x in rng.integers(500, 8193, 200)]
+    dist = ["normal", "laplace", "sorted", "mixed", "ties"][seed % 5]
+    case = workloads.random_segments(lens, dist, 1.0, seed=seed)
+    lam_arr = (10.0 ** rng.uniform(np.log10(0.05), np.log10(20.0), len(lens))).astype(np.float32)
+    _check(case, batched=True, lam_arr=lam_arr)
+    if seed % 4 == 0:
+        _check(case, batched=False)
+
+
 def test_determinism():
     case = workloads.random_segments([3000, 4096, 8192, 100000], "normal", 0.05, seed=9)
     a = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
