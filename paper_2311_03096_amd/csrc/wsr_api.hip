@@ -121,10 +121,11 @@ struct BigWs {
   int32_t* vpos;
   double* vS;
   uint16_t* hbits;  // per tile and thread: hull-vertex bits of the thread's ranks
-  int32_t *hcnt, *lo, *hi, *prev_pos, *next_pos;
-  double *tsum, *tileoff, *prev_s, *next_s, *prev_sl, *next_sl;
+  int32_t *hcnt, *lo, *hi;
+  int64_t *prev_ref, *next_ref;  // per tile: its previous / next surviving vertex (index into vpos, vS)
+  double *tsum, *tileoff;
   // backward
-  int32_t *fpos, *lpos;
+  int32_t *fpos, *lpos, *prev_pos, *next_pos;
   double *fG, *lG, *prevG, *nextG;
   size_t bytes;
 };
@@ -153,16 +154,14 @@ BigWs big_layout(int64_t elems, int64_t nrt, int64_t nt, int64_t nsegs, void* ba
   w.hcnt = (int32_t*)take(sizeof(int32_t) * nt);
   w.lo = (int32_t*)take(sizeof(int32_t) * nt);
   w.hi = (int32_t*)take(sizeof(int32_t) * nt);
-  w.prev_pos = (int32_t*)take(sizeof(int32_t) * nt);
-  w.next_pos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.prev_ref = (int64_t*)take(sizeof(int64_t) * nt);
+  w.next_ref = (int64_t*)take(sizeof(int64_t) * nt);
   w.tsum = (double*)take(sizeof(double) * nt);
   w.tileoff = (double*)take(sizeof(double) * nt);
-  w.prev_s = (double*)take(sizeof(double) * nt);
-  w.next_s = (double*)take(sizeof(double) * nt);
-  w.prev_sl = (double*)take(sizeof(double) * nt);
-  w.next_sl = (double*)take(sizeof(double) * nt);
   w.fpos = (int32_t*)take(sizeof(int32_t) * nt);
   w.lpos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.prev_pos = (int32_t*)take(sizeof(int32_t) * nt);
+  w.next_pos = (int32_t*)take(sizeof(int32_t) * nt);
   w.fG = (double*)take(sizeof(double) * nt);
   w.lG = (double*)take(sizeof(double) * nt);
   w.prevG = (double*)take(sizeof(double) * nt);
@@ -395,8 +394,7 @@ void big_merges(const SetRun& r, const BigWs& b, hipStream_t s) {
     WSR_TRACE("big_merge", s);
 #define WSR_LAUNCH_MERGE(GM)                                                                                \
   hipLaunchKernelGGL((k_big_merge<GM, kMergeRecMax>), dim3(grid), dim3(kMergeThreads), 0, s, L.lvl_lo, L.lvl_hi, \
-                     r.set, groups, b.vpos, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s, b.next_pos, b.next_s, \
-                     b.prev_sl, b.next_sl)
+                     r.set, groups, b.vpos, b.vS, b.tileoff, b.lo, b.hi, b.prev_ref, b.next_ref)
     if (L.gmax <= 16)
       WSR_LAUNCH_MERGE(16);
     else if (L.gmax <= 256)
@@ -418,7 +416,7 @@ void big_merges(const SetRun& r, const BigWs& b, hipStream_t s) {
   if (ntop > 0) {
     WSR_TRACE("big_merge_top", s);
     hipLaunchKernelGGL(k_big_merge_top, dim3(ntop), dim3(kTopThreads), 0, s, r.set, top, b.vpos, b.vS, b.tileoff,
-                       b.lo, b.hi, b.prev_pos, b.prev_s, b.next_pos, b.next_s, b.prev_sl, b.next_sl);
+                       b.lo, b.hi, b.prev_ref, b.next_ref);
   }
 }
 
@@ -449,8 +447,8 @@ int big_forward(const SetRun& r, const float* w, const float* grad, float eta, f
   big_merges(r, b, s);
   { WSR_TRACE("big_apply", s);
   hipLaunchKernelGGL(k_big_apply, dim3(nt), dim3(kBigThreads), 0, s, r.set, b.keysA, saved_perm, b.valsA, lam,
-                     b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.prev_pos, b.prev_s, b.next_pos, b.next_s,
-                     b.prev_sl, b.next_sl, out, saved_mask, l1.beta, l1.rho, l1.kappa, l1.on, status); }
+                     b.flags, b.hbits, b.hcnt, b.vS, b.tileoff, b.lo, b.hi, b.vpos, b.prev_ref, b.next_ref, out,
+                     saved_mask, l1.beta, l1.rho, l1.kappa, l1.on, status); }
   return last_error();
 }
 

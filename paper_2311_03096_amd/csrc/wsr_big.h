@@ -101,16 +101,14 @@ __global__ void k_big_tile_scan(LongSet set, const double* tsum, double* tileoff
 template <int GMAX, int RMAX>
 __global__ void k_big_merge(int lvl_lo, int lvl_hi, LongSet set, const MergeGroup* groups, const int32_t* vpos,
                             const double* vS, const double* tileoff, int32_t* lo_g, int32_t* hi_g,
-                            int32_t* prev_pos, double* prev_s, int32_t* next_pos, double* next_s, double* prev_sl,
-                            double* next_sl);
+                            int64_t* prev_ref, int64_t* next_ref);
 __global__ void k_big_merge_top(LongSet set, const int32_t* top_segs, const int32_t* vpos, const double* vS,
-                                const double* tileoff, int32_t* lo_g, int32_t* hi_g, int32_t* prev_pos,
-                                double* prev_s, int32_t* next_pos, double* next_s, double* prev_sl, double* next_sl);
+                                const double* tileoff, int32_t* lo_g, int32_t* hi_g, int64_t* prev_ref,
+                                int64_t* next_ref);
 __global__ void k_big_apply(LongSet set, const uint32_t* keys, const int32_t* saved_perm, const int32_t* perm_ws,
                             LamArgs lam, const uint32_t* flags, const uint16_t* hbits, const int32_t* hcnt,
                             const double* vS, const double* tileoff, const int32_t* lo_g, const int32_t* hi_g,
-                            const int32_t* prev_pos, const double* prev_s, const int32_t* next_pos,
-                            const double* next_s, const double* prev_sl, const double* next_sl, float* out,
+                            const int32_t* vpos, const int64_t* prev_ref, const int64_t* next_ref, float* out,
                             uint32_t* mask_out, float beta, float rho, float kappa, int l1, uint32_t* status);
 __global__ void k_big_bwd_tile(LongSet set, const float* g, const int32_t* perm, const uint32_t* mask, float* gsorted,
                                double* tsum, int32_t* fpos, double* fG, int32_t* lpos, double* lG);

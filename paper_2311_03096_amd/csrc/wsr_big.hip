@@ -940,15 +940,14 @@ int set_merge_clock_buffer(void* clocks) {
 // cnt16[G] with G = 2^lvl_hi <= GMAX and G >> lvl_lo <= RMAX.  One wave per merge.
 // A merge record is {bridged, last left tile keeping vertices (t0-1: none), its last kept
 // index, first right tile keeping vertices, its first kept index}.
-// When finalize != 0 (single group holding every tile, last launch), also writes the previous
-// and next surviving vertex of every tile.
+// When finalize != 0 (single group holding every tile, last launch), also writes references to
+// the previous and next surviving vertex of every tile.
 template <int GMAX, int RMAX>
 __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl_hi_launch, LongSet set,
                                                              const MergeGroup* groups, const int32_t* vpos,
                                                              const double* vS, const double* tileoff,
-                                                             int32_t* lo_g, int32_t* hi_g, int32_t* prev_pos,
-                                                             double* prev_s, int32_t* next_pos,
-                                                             double* next_s, double* prev_sl, double* next_sl) {
+                                                             int32_t* lo_g, int32_t* hi_g, int64_t* prev_ref,
+                                                             int64_t* next_ref) {
   constexpr int NWV = kMergeThreads / kWave;
   __shared__ int pre[GMAX + 1];
   __shared__ int rec[5 * RMAX];
@@ -1153,8 +1152,9 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
   // then the tiles' own ranges in order): the last own vertex of the last tile before it that
   // keeps any (else P_0) and the first own vertex of the first tile after it that keeps any (else
   // none).  Those tiles come from a max-scan and a reversed min-scan over the threads' chunks of
-  // consecutive tiles, packed per tile into pre[] (no longer needed); then each thread takes
-  // tiles tid, tid + NT, ... with all their vertex loads in flight and coalesced stores.
+  // consecutive tiles, packed per tile into pre[] (no longer needed); then the references to the
+  // two vertices are stored, tile by tile, lane-consecutive (the apply's workgroups load the
+  // vertices themselves, spread over the device).
   __shared__ int fin_w[NWV];
   __shared__ int fin_r[kMergeThreads];
   {
@@ -1223,7 +1223,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
     }
   }
   __syncthreads();
-  // a vertex's global S (S' + the tile offset, as every tile forms it) and its S' in its own tile
+  // the records: each vertex's flat index in the hull arrays (the apply reads the vertex itself)
 #pragma unroll
   for (int k = 0; k < kChunkMax; ++k) {
     const int t = tid + k * kMergeThreads;
@@ -1232,24 +1232,8 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
     const int pt = (pk & 0xFFFF) - 1, nt = (pk >> 16) - 1;
     const int ptile = pt < 0 ? 0 : pt;
     const int pidx = pt < 0 ? 0 : (int)lo16[pt] + (int)cnt16[pt] - 1;
-    const int64_t pat = (int64_t)(gbase + ptile) * (kBigTile + 1) + pidx;
-    const int pp = vpos[pat];
-    const double psl = vS[pat];
-    const double poff = tileoff[gbase + ptile];
-    int np_ = -1;
-    double nsl = 0.0, noff = 0.0;
-    if (nt >= 0) {
-      const int64_t nat = (int64_t)(gbase + nt) * (kBigTile + 1) + (int)lo16[nt];
-      np_ = vpos[nat];
-      nsl = vS[nat];
-      noff = tileoff[gbase + nt];
-    }
-    prev_pos[gbase + t] = pp;
-    prev_s[gbase + t] = psl + poff;
-    prev_sl[gbase + t] = psl;
-    next_pos[gbase + t] = np_;
-    next_s[gbase + t] = nt >= 0 ? nsl + noff : 0.0;
-    next_sl[gbase + t] = nsl;
+    prev_ref[gbase + t] = (int64_t)(gbase + ptile) * (kBigTile + 1) + pidx;
+    next_ref[gbase + t] = nt >= 0 ? (int64_t)(gbase + nt) * (kBigTile + 1) + (int)lo16[nt] : (int64_t)-1;
   }
 #ifdef WSR_PHASE_CLOCKS
   __syncthreads();
@@ -1260,7 +1244,7 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
 #define WSR_INSTANTIATE_MERGE(GM)                                                                           \
   template __global__ void k_big_merge<GM, kMergeRecMax>(int, int, LongSet, const MergeGroup*, const int32_t*, \
                                                          const double*, const double*, int32_t*, int32_t*,     \
-                                                         int32_t*, double*, int32_t*, double*, double*, double*);
+                                                         int64_t*, int64_t*);
 WSR_INSTANTIATE_MERGE(16)
 WSR_INSTANTIATE_MERGE(256)
 WSR_INSTANTIATE_MERGE(4096)
@@ -1276,9 +1260,7 @@ WSR_INSTANTIATE_MERGE(16384)
 __global__ __launch_bounds__(kTopThreads) void k_big_merge_top(LongSet set, const int32_t* top_segs,
                                                                const int32_t* vpos, const double* vS,
                                                                const double* tileoff, int32_t* lo_g,
-                                                               int32_t* hi_g, int32_t* prev_pos, double* prev_s,
-                                                               int32_t* next_pos, double* next_s, double* prev_sl,
-                                                               double* next_sl) {
+                                                               int32_t* hi_g, int64_t* prev_ref, int64_t* next_ref) {
   constexpr int TPT = kMaxHullTiles / kTopThreads;  // tiles per thread
   constexpr int HALF = kMergeGroupMax;
   __shared__ int base[kMaxHullTiles / 8 + 1];
@@ -1415,34 +1397,18 @@ __global__ __launch_bounds__(kTopThreads) void k_big_merge_top(LongSet set, cons
       hi_g[gbase + t] = (int)lo16[t] + cnt[i] - 1;
     }
   }
-  // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t
+  // global chain: gv[0] = P_0 (tile 0, index 0); gv[1 + pre[t] + i] = own vertex i of tile t;
+  // each tile's previous and next surviving vertex, as references into the hull arrays
   const int nglob = 1 + C.pre_at(gn);
-  auto gvertex = [&](int m, int* p, double* s, double* sl) {
+  auto gref = [&](int m) -> int64_t {
     int tile, idx;
     node_vertex(C, 0, gn, m, &tile, &idx);
-    const int64_t at = (int64_t)(gbase + tile) * (kBigTile + 1) + idx;
-    *p = vpos[at];
-    *sl = vS[at];
-    *s = *sl + tileoff[gbase + tile];
+    return (int64_t)(gbase + tile) * (kBigTile + 1) + idx;
   };
   for (int t = tid; t < gn; t += kTopThreads) {
-    int p;
-    double s, sl;
-    gvertex(C.pre_at(t), &p, &s, &sl);
-    prev_pos[gbase + t] = p;
-    prev_s[gbase + t] = s;
-    prev_sl[gbase + t] = sl;
+    prev_ref[gbase + t] = gref(C.pre_at(t));
     const int nx = C.pre_at(t + 1) + 1;
-    if (nx < nglob) {
-      gvertex(nx, &p, &s, &sl);
-      next_pos[gbase + t] = p;
-      next_s[gbase + t] = s;
-      next_sl[gbase + t] = sl;
-    } else {
-      next_pos[gbase + t] = -1;
-      next_s[gbase + t] = 0.0;
-      next_sl[gbase + t] = 0.0;
-    }
+    next_ref[gbase + t] = nx < nglob ? gref(nx) : (int64_t)-1;
   }
 }
 
@@ -1472,10 +1438,9 @@ __global__ __launch_bounds__(kBigThreads, 8) void k_big_apply(LongSet set, const
                                                            const uint32_t* flags, const uint16_t* hbits,
                                                            const int32_t* hcnt, const double* vS,
                                                            const double* tileoff, const int32_t* lo_g,
-                                                           const int32_t* hi_g, const int32_t* prev_pos,
-                                                           const double* prev_s, const int32_t* next_pos,
-                                                           const double* next_s, const double* prev_sl,
-                                                           const double* next_sl, float* out, uint32_t* mask_out,
+                                                           const int32_t* hi_g, const int32_t* vpos,
+                                                           const int64_t* prev_ref, const int64_t* next_ref,
+                                                           float* out, uint32_t* mask_out,
                                                            float beta, float rho, float kappa, int l1,
                                                            uint32_t* status) {
   constexpr int R = kBigTile / kBigThreads;
@@ -1554,13 +1519,17 @@ __global__ __launch_bounds__(kBigThreads, 8) void k_big_apply(LongSet set, const
   const double lamd = (double)lam / (double)(d - 1);
   const L1Rewind l1f(beta, rho, kappa);
   const double toff = tileoff[t];
-  const int ppos = prev_pos[t];
-  const double ps = prev_s[t];
-  const int npn = next_pos[t];
-  const double nsn = next_s[t];
+  // the previous / next surviving vertex on the segment's chain, from the references the merge
+  // left: its position, its global S (S' + its tile's offset, as every tile forms it) and its S'
+  // in its own tile
+  const int64_t pref = prev_ref[t], nref = next_ref[t];
+  const int ppos = vpos[pref];
+  const double ps_loc = vS[pref];
+  const double ps = ps_loc + tileoff[pref / (kBigTile + 1)];
+  const int npn = nref >= 0 ? vpos[nref] : -1;
+  const double ns_loc = nref >= 0 ? vS[nref] : 0.0;
+  const double nsn = nref >= 0 ? ns_loc + tileoff[nref / (kBigTile + 1)] : 0.0;
   const double endS = vS[vb + hc - 1];  // the tile's end point, as the tile kernel stored it
-  const double ps_loc = prev_sl[t];     // S' of the previous / next surviving vertex in its own tile
-  const double ns_loc = next_sl[t];
   // the previous tile's end point (a cluster entering this tile from it)
   const double endS_prev = t > sg.tbase ? vS[(int64_t)(t - 1) * (kBigTile + 1) + hcnt[t - 1] - 1] : 0.0;
   // surviving starts among the thread's ranks: hull-vertex bits whose vertex index is own (the
