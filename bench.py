@@ -770,7 +770,7 @@ def merge_clock_figures():
     chain and on N(0,1) weights: per launch and level the span to the level's end, the longest
     bridge search among its merges, the mean time per level spent before the searches (junction
     windows) and after them (range updates and prefix rebuild), and the end of the launch's
-    work (the last launch also writes every tile's neighbouring surviving vertices)."""
+    work (the last launch also writes references to every tile's neighbouring surviving vertices)."""
     import ctypes
     import torch
     from paper_2311_03096_amd import workloads
