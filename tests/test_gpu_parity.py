@@ -291,6 +291,21 @@ def test_rows_large_lambda(seed):
         _check(case, batched=False)
 
 
+@pytest.mark.parametrize("seed", [0, 3, 7])
+def test_many_tile_random_layouts(seed):
+    """One to three long segments of 2^20 to 3*2^20 random weights (256-768 hull tiles, so the
+    tile merge tree takes three launches and its last launch writes the neighbour references for
+    groups of up to 4096 tiles) beside one short row, forward and backward against the oracle."""
+    rng = np.random.default_rng(13000 + seed)
+    n = int(rng.integers(1, 4))
+    lens = [int(x) for x in rng.integers(1 << 20, 3 << 20, n)] + [int(rng.integers(40, 8193))]
+    dist = ["normal", "laplace", "sorted", "mixed", "ties"][seed % 5]
+    lam = float(10.0 ** rng.uniform(-3, 1))
+    case = workloads.random_segments(lens, dist, lam, seed=seed)
+    _check(case, batched=bool(seed % 2))
+    _check_backward(case, batched=bool(seed % 2))
+
+
 def test_determinism():
     case = workloads.random_segments([3000, 4096, 8192, 100000], "normal", 0.05, seed=9)
     a = gpu_forward(case["w"], case["offsets"], case["lam"], batched=True)
