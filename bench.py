@@ -851,14 +851,14 @@ def config_table(copy_gbs):
     rows["plain_d4096"] = config_line("plain_d4096", workloads.plain(4096, 0.1), copy_gbs, oracle_check=True,
                                       cpu_threads=1)
     log("plain d=4096", rows["plain_d4096"])
-    rows["chain_d2p24_shuffled"] = config_line("chain_shuffled_d2p24", workloads.chain(d, 0.7, shuffle=True),
+    rows["chain_d2p24_shuffled"] = config_line("chain_d2p24_shuffled", workloads.chain(d, 0.7, shuffle=True),
                                                copy_gbs, long_sort=True)
     log("shuffled chain", rows["chain_d2p24_shuffled"])
     rows["typical_d2p24"] = config_line("typical_d2p24", workloads.plain(d, 0.1, seed=1), copy_gbs, long_sort=True)
     log("typical", rows["typical_d2p24"])
-    rows["backward_rows_1024x8192"] = config_line("backward_rows", workloads.backward_rows(1024, 8192, 0.05),
-                                                  copy_gbs, kind="bwd", batched=True, oracle_check=True,
-                                                  cpu_threads=nproc())
+    rows["backward_rows_1024x8192"] = config_line("backward_rows_1024x8192",
+                                                  workloads.backward_rows(1024, 8192, 0.05), copy_gbs, kind="bwd",
+                                                  batched=True, oracle_check=True, cpu_threads=nproc())
     log("backward rows", rows["backward_rows_1024x8192"])
     prec = workloads.precision(1 << 26, 1e-4)
     rows["precision_d2p26"] = config_line("precision_d2p26", prec, copy_gbs, long_sort=True, oracle_check=True,
@@ -898,10 +898,10 @@ def main():
     if args.workload in ("shuffled", "backward", "precision"):  # one workload's row (for profiling)
         copy_gbs = copy_bandwidth()
         if args.workload == "shuffled":
-            res = config_line("chain_shuffled_d2p24", workloads.chain(d, 0.7, shuffle=True), copy_gbs, long_sort=True)
+            res = config_line("chain_d2p24_shuffled", workloads.chain(d, 0.7, shuffle=True), copy_gbs, long_sort=True)
         elif args.workload == "backward":
-            res = config_line("backward_rows", workloads.backward_rows(1024, 8192, 0.05), copy_gbs, kind="bwd",
-                              batched=True)
+            res = config_line("backward_rows_1024x8192", workloads.backward_rows(1024, 8192, 0.05), copy_gbs,
+                              kind="bwd", batched=True)
         else:
             res = config_line("precision_d2p26", workloads.precision(1 << 26, 1e-4), copy_gbs, long_sort=True)
         print(json.dumps(res), flush=True)
