@@ -249,12 +249,27 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(int pass, LongSet set, ui
   uint32_t* sflags = flags + kSegFlagWords * si;
   if (pass > 0 && !radix_pass_runs(pass, sflags[1])) return;
   const int ntiles = sg.nrt;
+  // global reads in batches of U per thread, all in flight together (a plain strided loop waits
+  // for each load before the next); indexes past the row end read its last entry again, so every
+  // load is unconditional and in bounds
+  constexpr int U = 8;
   if (pass == 0 && digit == 0) {
     uint32_t any = 0u, o = 0u, a = 0xFFFFFFFFu;
-    for (int i = threadIdx.x; i < ntiles; i += 256) {
-      any |= tbad[sg.rbase + i];
-      o |= tor[sg.rbase + i];
-      a &= tand[sg.rbase + i];
+    for (int i0 = threadIdx.x; i0 < ntiles; i0 += 256 * U) {
+      uint32_t fb[U], fo[U], fa[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int i = sg.rbase + min(i0 + u * 256, ntiles - 1);  // OR / AND: a repeat changes nothing
+        fb[u] = tbad[i];
+        fo[u] = tor[i];
+        fa[u] = tand[i];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        any |= fb[u];
+        o |= fo[u];
+        a &= fa[u];
+      }
     }
     o = wave_or_u32(o);
     a = wave_and_u32(a);
@@ -274,7 +289,16 @@ __global__ __launch_bounds__(256) void k_radix_rowscan(int pass, LongSet set, ui
     }
   }
   uint32_t* row = hist + (int64_t)digit * set.nrt + sg.rbase;
-  for (int i = threadIdx.x; i < ntiles; i += 256) row_s[i] = row[i];
+  for (int i0 = threadIdx.x; i0 < ntiles; i0 += 256 * U) {
+    uint32_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = row[min(i0 + u * 256, ntiles - 1)];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = i0 + u * 256;
+      if (i < ntiles) row_s[i] = v[u];
+    }
+  }
   __syncthreads();
   const int chunk = (ntiles + 255) / 256;
   const int lo = threadIdx.x * chunk;
@@ -1008,11 +1032,25 @@ __global__ __launch_bounds__(kMergeThreads) void k_big_merge(int lvl_lo, int lvl
     __syncthreads();
   };
 
-  for (int i = tid; i < gn; i += kMergeThreads) {
-    const int l = lo_g[gbase + i];
-    const int h = hi_g[gbase + i];
-    lo16[i] = (uint16_t)l;
-    cnt16[i] = (uint16_t)max(0, h - l + 1);
+  // the group's own ranges, up to 8 tiles per thread with all their loads in flight (indexes
+  // past the group's end read its last tile again and store nothing)
+  constexpr int UL = kChunkMax < 8 ? kChunkMax : 8;
+  for (int i0 = tid; i0 < gn; i0 += kMergeThreads * UL) {
+    int l[UL], h[UL];
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int i = gbase + min(i0 + u * kMergeThreads, gn - 1);
+      l[u] = lo_g[i];
+      h[u] = hi_g[i];
+    }
+#pragma unroll
+    for (int u = 0; u < UL; ++u) {
+      const int i = i0 + u * kMergeThreads;
+      if (i < gn) {
+        lo16[i] = (uint16_t)l[u];
+        cnt16[i] = (uint16_t)max(0, h[u] - l[u] + 1);
+      }
+    }
   }
   __syncthreads();
   rebuild_prefix();
